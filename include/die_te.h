@@ -1,0 +1,162 @@
+/*
+ * die_te.h -- C ABI of the MI355X (gfx950) solver for 2-D TE scattering by the
+ * domain-integral-equation method of Zouros & Budko.
+ *
+ * Problem statement (Section 2 and Section 4 of the paper): an x3-invariant
+ * object with relative permittivity eps_r(x) in a homogeneous background
+ * (eps_b = mu_b = 1, no magnetic contrast) is illuminated by an incident
+ * in-plane electric field E_in; the total field E = (E1, E2) solves
+ *
+ *     E_in = E - (k_b^2 + grad div) g * (chi E),  chi = eps_r - 1,
+ *     g = (i/4) H0^(1)(k_b |x|)       (eqs. MatrixSolutionTE, GreenFunction)
+ *
+ * discretised by collocation with the midpoint rule on a uniform grid of square
+ * cells (Section 4, eq. A11 and the element formulas that follow it):
+ * A u = b with A = I - T X, X = diag(chi), T the Green tensor sampled at cell
+ * separations (self cell integrated over the disc of equal area).
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im): complex128 = 2 doubles,
+ *     complex64 = 2 floats (the layout of PyTorch complex tensors).
+ *   - Field arrays are laid out [nrhs][2][ny][nx] (component 0 = E1 = E_x),
+ *     x fastest.  Cell (ix, iy) is centred at (x0 + (ix + 1/2) h, y0 + (iy + 1/2) h);
+ *     only h enters the operator (it is translation invariant).
+ *   - Units: lambda_b = 1 unless k_b says otherwise.
+ *   - Pointers named "device" must point to GPU memory of the current device;
+ *     the caller owns them and keeps them alive for the duration of the call
+ *     (for asynchronous calls: until the stream reaches the call).  The
+ *     library never frees or retains a caller pointer.
+ *   - `stream` is a hipStream_t (NULL = the default stream).
+ *   - Return codes: 0 = DIE_OK; > 0 = warning, outputs valid; < 0 = error,
+ *     outputs unspecified, die_te_last_error() holds a message.  No entry point
+ *     throws, aborts or exits.
+ *   - A context is not thread safe: serialise calls that use it.
+ */
+#ifndef DIE_TE_H
+#define DIE_TE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct die_te_ctx die_te_ctx;
+
+enum {
+  DIE_OK = 0,
+  DIE_NOT_CONVERGED = 1, /* solve: tolerance not reached; the best iterate is returned */
+  DIE_E_INVALID = -1,    /* bad argument (sizes, pointers, options) */
+  DIE_E_SINGULAR = -2,   /* eps_r == 0 in some cell: existence condition eq. ExistenceTE fails */
+  DIE_E_NOMEM = -3,      /* device or host allocation failed */
+  DIE_E_HIP = -4,        /* a HIP runtime call failed */
+  DIE_E_BREAKDOWN = -5   /* NaN/Inf met inside the Krylov iteration */
+};
+
+enum { DIE_C128 = 0, DIE_C64 = 1 }; /* precision of x and y for the operator products */
+
+typedef struct {
+  int nx, ny;   /* cells along x and y, each in [1, 2048] */
+  double h;     /* cell side, > 0 */
+  double k_b;   /* background wavenumber; 0 selects 2*pi (lambda_b = 1) */
+  int px, py;   /* padded FFT grid; 0 selects the smallest power of two >= 2n-1
+                   (any power of two >= 2n-1 and <= 4096 is accepted and gives
+                   the same product: the linear convolution fits without wrap) */
+} die_te_grid;
+
+typedef struct {
+  int regularize;          /* 1: solve A_R A u = A_R b with A_R = A(chi'), chi' = 1/eps_r - 1
+                              (Section 3, eqs. InverseSymbol, Regularization; Section 5) */
+  int deflate_k;           /* r >= 0: deflate the r largest-magnitude eigenvalues of the
+                              solved operator (A_R A, or A) with the right preconditioner
+                              P^-1 = I + V (T^-1 - I) V^*, T = V^* M V (Section 4,
+                              eq. DeflatingPrecondtioner); 0 = no deflation */
+  double eigs_tol;         /* Ritz pair accepted when ||M v - theta v|| <= eigs_tol |theta|; 0 -> 1e-4 */
+  int eigs_krylov;         /* Krylov dimension of the eigensolver; 0 -> max(2r + 8, 24) */
+  int eigs_max_restarts;   /* 0 -> 300 */
+  unsigned long long seed; /* start vector of the eigensolver */
+} die_te_setup_opts;
+
+typedef struct {
+  int restart;       /* GMRES restart length m (>= 1, <= 512) */
+  int max_iters;     /* cap on the total number of inner GMRES iterations (>= 1) */
+  double tol;        /* stop when ||b - A u||_2 <= tol ||b||_2, checked in FP64 on the
+                        original (unregularized) operator; 0 -> 1e-8 */
+  int mixed;         /* 0: FP64 throughout; 1: complex64 Krylov basis and operator products
+                        inside an FP64 refinement loop (true residual, Hessenberg, Givens
+                        and the deflation basis stay FP64) */
+  int x0_given;      /* 1: e_tot holds the initial guess on entry; 0: start from zero */
+  double reg_margin; /* regularized runs end a cycle when the regularized residual estimate
+                        reaches reg_margin * (the target scaled to the cycle); 0 -> 0.1 */
+} die_te_solve_opts;
+
+typedef struct {
+  int status;          /* DIE_OK or DIE_NOT_CONVERGED for this right-hand side */
+  int iters;           /* inner GMRES iterations (each one applies the solved operator once) */
+  int products_A;      /* applications of A (the FFT product), including residuals */
+  int products_AR;     /* applications of A_R */
+  int cycles;          /* GMRES cycles = FP64 residual refinements */
+  double rel_res_true; /* final ||b - A u|| / ||b|| evaluated in FP64 */
+} die_te_solve_info;
+
+/* Build a context for one object: copies eps_r, evaluates the Green tensor on all
+ * (2nx-1)(2ny-1) cell separations in FP64 on the host, embeds it circulantly in the
+ * px x py grid, transforms it on the GPU once (the "symbol", shared by A and A_R,
+ * as the paper notes for the regularizer) and, when deflate_k > 0, runs the
+ * offline eigensolver.  eps_r: device, complex128 [ny][nx].  opts may be NULL
+ * (defaults: no regularizer, no deflation).  Synchronises `stream`.
+ * Returns DIE_E_SINGULAR if some eps_r is exactly 0. */
+int die_te_setup(die_te_ctx **ctx, const die_te_grid *grid, const void *eps_r,
+                 const die_te_setup_opts *opts, void *stream);
+
+/* y = A x for nrhs fields (Section 4, eq. A11 family, realised by FFT convolution).
+ * x, y: device, [nrhs][2][ny][nx] in the precision `prec` (DIE_C128 or DIE_C64);
+ * x and y must not overlap.  Asynchronous on `stream`. */
+int die_te_matvec(die_te_ctx *ctx, const void *x, void *y, int nrhs, int prec, void *stream);
+
+/* y = A_R x = A(chi') x: the same operator with the regularizer contrast
+ * chi' = 1/eps_r - 1 (Section 3, eq. InverseSymbol; Section 5).  Same arguments
+ * and semantics as die_te_matvec. */
+int die_te_regularize(die_te_ctx *ctx, const void *x, void *y, int nrhs, int prec, void *stream);
+
+/* Solve A u = b for nrhs incident fields with restarted GMRES (Section 4) on
+ * M P^-1 v = A_R r  (M = A_R A when regularized, else A; P^-1 the deflation
+ * preconditioner when the context has one; u += P^-1 v), each cycle restarted
+ * from the FP64 true residual r = b - A u.  All right-hand sides advance
+ * together in batched kernels; each stops on its own.
+ * e_in:  device, complex128 [nrhs][2][ny][nx], the sampled incident field b.
+ * e_tot: device, complex128, same shape: the total field u (initial guess on
+ *        entry when opts->x0_given).
+ * info:  host array of nrhs records (may be NULL).
+ * Returns DIE_OK when every RHS converged, DIE_NOT_CONVERGED when some did not
+ * (their best iterate is returned), < 0 on error.  Synchronises `stream`. */
+int die_te_solve(die_te_ctx *ctx, const void *e_in, void *e_tot, int nrhs,
+                 const die_te_solve_opts *opts, die_te_solve_info *info, void *stream);
+
+/* P^-1 x = x + V ((T^-1 - I) (V^* x)) for nrhs complex128 vectors of length 2 nx ny
+ * (Section 4, eq. DeflatingPrecondtioner).  x, y: device; may alias.
+ * DIE_E_INVALID if the context has no deflation basis.  Asynchronous. */
+int die_te_apply_deflation(die_te_ctx *ctx, const void *x, void *y, int nrhs, void *stream);
+
+/* Read back the deflation data: r (host int), the r Ritz values of largest
+ * magnitude (host complex128 [r], may be NULL), the orthonormal basis V
+ * (device complex128 [r][2][ny][nx], may be NULL) and C = T^-1 - I (host
+ * complex128 [r][r] row-major, may be NULL).  Synchronises `stream`. */
+int die_te_deflation_info(die_te_ctx *ctx, int *r, void *ritz_values, void *V, void *C,
+                          void *stream);
+
+/* Diagnostic: in-place unnormalised forward (inverse = 0) or backward
+ * (inverse = 1, also unnormalised) 2-D FFT of `batch` complex arrays
+ * [batch][py][px] with the library's own FFT kernels; px, py powers of two in
+ * [2, 4096].  data: device, complex128 (prec = DIE_C128) or complex64.
+ * Synchronises `stream`. */
+int die_te_fft2(void *data, int px, int py, int batch, int inverse, int prec, void *stream);
+
+/* Release everything the context owns. */
+int die_te_destroy(die_te_ctx *ctx);
+
+/* Message for the most recent error return in the calling thread ("" if none). */
+const char *die_te_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIE_TE_H */

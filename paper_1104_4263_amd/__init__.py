@@ -1,0 +1,21 @@
+"""MI355X (gfx950) solver for 2-D TE scattering by the domain-integral-equation
+method of Zouros & Budko: FFT-speed products with the discretised operator A and
+its regularizer A_R, and restarted GMRES (optionally regularized and deflated)
+driving them.  Every step runs in the HIP library libdie_te.so; this module
+only marshals PyTorch device tensors into its C ABI (include/die_te.h).
+"""
+from __future__ import annotations
+
+from .api import (  # noqa: F401
+    Solver,
+    die_te_setup,
+    die_te_matvec,
+    die_te_regularize,
+    die_te_solve,
+    die_te_apply_deflation,
+    die_te_deflation_info,
+    die_te_fft2,
+    die_te_destroy,
+    die_te_last_error,
+)
+from ._lib import DieTeError, load  # noqa: F401

@@ -1,0 +1,93 @@
+"""ctypes declarations of the C ABI in include/die_te.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdie_te.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "die_te.h")
+
+DIE_OK = 0
+DIE_NOT_CONVERGED = 1
+DIE_E_INVALID = -1
+DIE_E_SINGULAR = -2
+DIE_E_NOMEM = -3
+DIE_E_HIP = -4
+DIE_E_BREAKDOWN = -5
+DIE_C128 = 0
+DIE_C64 = 1
+
+
+class DieTeGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("h", ctypes.c_double), ("k_b", ctypes.c_double),
+                ("px", ctypes.c_int), ("py", ctypes.c_int)]
+
+
+class DieTeSetupOpts(ctypes.Structure):
+    _fields_ = [("regularize", ctypes.c_int), ("deflate_k", ctypes.c_int), ("eigs_tol", ctypes.c_double),
+                ("eigs_krylov", ctypes.c_int), ("eigs_max_restarts", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
+
+
+class DieTeSolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("tol", ctypes.c_double),
+                ("mixed", ctypes.c_int), ("x0_given", ctypes.c_int), ("reg_margin", ctypes.c_double)]
+
+
+class DieTeSolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("products_A", ctypes.c_int),
+                ("products_AR", ctypes.c_int), ("cycles", ctypes.c_int), ("rel_res_true", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class DieTeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"die_te error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libdie_te.so built in-tree; raise loudly when it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1104_4263_amd.build` "
+                           "(the solver has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, i = ctypes.c_void_p, ctypes.c_int, ctypes.c_int
+    lib.die_te_setup.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(DieTeGrid), vp, ctypes.POINTER(DieTeSetupOpts), vp]
+    lib.die_te_matvec.argtypes = [vp, vp, vp, i, i, vp]
+    lib.die_te_regularize.argtypes = [vp, vp, vp, i, i, vp]
+    lib.die_te_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(DieTeSolveOpts), ctypes.POINTER(DieTeSolveInfo), vp]
+    lib.die_te_apply_deflation.argtypes = [vp, vp, vp, i, vp]
+    lib.die_te_deflation_info.argtypes = [vp, ctypes.POINTER(ip), vp, vp, vp, vp]
+    lib.die_te_fft2.argtypes = [vp, i, i, i, i, i, vp]
+    lib.die_te_destroy.argtypes = [vp]
+    lib.die_te_last_error.argtypes = []
+    lib.die_te_last_error.restype = ctypes.c_char_p
+    for name in ("die_te_setup", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_apply_deflation",
+                 "die_te_deflation_info", "die_te_fft2", "die_te_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/die_te.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(die_te_\w+)\s*\(", text, re.M)))
+
+
+def check(code: int, allow_warning: bool = False) -> int:
+    if code < 0 or (code > 0 and not allow_warning):
+        msg = load().die_te_last_error().decode(errors="replace")
+        raise DieTeError(code, msg)
+    return code

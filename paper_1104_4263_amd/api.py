@@ -1,0 +1,167 @@
+"""Python binding of the C ABI, one function per entry point, plus a small
+convenience class.  Tensors must be contiguous CUDA (HIP) tensors of the dtype
+the entry point expects; the current torch stream is passed to the library."""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from ._lib import (DIE_C128, DIE_C64, DieTeGrid, DieTeSetupOpts, DieTeSolveInfo, DieTeSolveOpts, check, load)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtypes, name: str) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(t: torch.Tensor) -> int:
+    return DIE_C128 if t.dtype == torch.complex128 else DIE_C64
+
+
+def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0, py: int = 0,
+                 regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
+                 eigs_max_restarts: int = 0, seed: int = 0) -> ctypes.c_void_p:
+    lib = load()
+    g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
+    o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
+                       int(eigs_max_restarts), int(seed))
+    ctx = ctypes.c_void_p()
+    check(lib.die_te_setup(ctypes.byref(ctx), ctypes.byref(g), _dev(eps_r, (torch.complex128,), "eps_r"),
+                           ctypes.byref(o), _stream()))
+    return ctx
+
+
+def die_te_matvec(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
+    check(load().die_te_matvec(ctx, _dev(x, (torch.complex128, torch.complex64), "x"),
+                               _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))
+
+
+def die_te_regularize(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
+    check(load().die_te_regularize(ctx, _dev(x, (torch.complex128, torch.complex64), "x"),
+                                   _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))
+
+
+def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, restart: int = 30,
+                 max_iters: int = 100_000, tol: float = 1e-8, mixed: bool = False, x0_given: bool = False,
+                 reg_margin: float = 0.0) -> tuple[int, list[dict]]:
+    o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(bool(mixed)), int(bool(x0_given)),
+                       float(reg_margin))
+    info = (DieTeSolveInfo * nrhs)()
+    rc = load().die_te_solve(ctx, _dev(e_in, (torch.complex128,), "e_in"), _dev(e_tot, (torch.complex128,), "e_tot"),
+                             nrhs, ctypes.byref(o), info, _stream())
+    check(rc, allow_warning=True)
+    return rc, [info[i].as_dict() for i in range(nrhs)]
+
+
+def die_te_apply_deflation(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
+    check(load().die_te_apply_deflation(ctx, _dev(x, (torch.complex128,), "x"), _dev(y, (torch.complex128,), "y"),
+                                        nrhs, _stream()))
+
+
+def die_te_deflation_info(ctx, nvec: int, device=None):
+    """Returns (ritz values [r] complex128 numpy-like list, V [r, nvec] tensor, C [r, r] tensor on CPU)."""
+    lib = load()
+    r = ctypes.c_int(0)
+    check(lib.die_te_deflation_info(ctx, ctypes.byref(r), None, None, None, _stream()))
+    n = r.value
+    if n == 0:
+        return torch.zeros(0, dtype=torch.complex128), None, None
+    ritz = torch.zeros(n, dtype=torch.complex128)
+    C = torch.zeros(n, n, dtype=torch.complex128)
+    V = torch.zeros(n, nvec, dtype=torch.complex128, device=device or "cuda")
+    check(lib.die_te_deflation_info(ctx, ctypes.byref(r), ctypes.c_void_p(ritz.data_ptr()),
+                                    _dev(V, (torch.complex128,), "V"), ctypes.c_void_p(C.data_ptr()), _stream()))
+    return ritz, V, C
+
+
+def die_te_fft2(data: torch.Tensor, inverse: bool = False) -> None:
+    """In-place unnormalised 2-D FFT over the last two axes of a [batch, py, px] tensor."""
+    if data.dim() != 3:
+        raise ValueError("data must be [batch, py, px]")
+    b, py, px = data.shape
+    check(load().die_te_fft2(_dev(data, (torch.complex128, torch.complex64), "data"), px, py, b, int(bool(inverse)),
+                             _prec(data), _stream()))
+
+
+def die_te_destroy(ctx) -> None:
+    if ctx:
+        check(load().die_te_destroy(ctx))
+
+
+def die_te_last_error() -> str:
+    return load().die_te_last_error().decode(errors="replace")
+
+
+class Solver:
+    """One scatterer on one grid: owns a library context."""
+
+    def __init__(self, nx: int, ny: int, h: float, eps_r, *, k_b: float = 2.0 * math.pi, px: int = 0, py: int = 0,
+                 regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
+                 eigs_max_restarts: int = 0, seed: int = 0, device: str = "cuda"):
+        eps = torch.as_tensor(eps_r, dtype=torch.complex128).to(device).contiguous()
+        if tuple(eps.shape) != (ny, nx):
+            raise ValueError(f"eps_r must have shape ({ny}, {nx})")
+        self.nx, self.ny, self.h, self.k_b = nx, ny, h, k_b
+        self.nvec = 2 * nx * ny
+        self.device = device
+        self.regularized = bool(regularize)
+        self.ctx = die_te_setup(nx, ny, h, eps, k_b=k_b, px=px, py=py, regularize=regularize, deflate_k=deflate_k,
+                                eigs_tol=eigs_tol, eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts,
+                                seed=seed)
+
+    @classmethod
+    def from_grid(cls, grid, eps_r, **kw):
+        return cls(grid.nx, grid.ny, grid.h, eps_r, k_b=grid.k, **kw)
+
+    def _shape(self, x: torch.Tensor) -> int:
+        if x.shape[-3:] != (2, self.ny, self.nx):
+            raise ValueError(f"fields must be [..., 2, {self.ny}, {self.nx}]")
+        return 1 if x.dim() == 3 else int(x.shape[0])
+
+    def matvec(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        die_te_matvec(self.ctx, x.contiguous(), y, self._shape(x))
+        return y
+
+    def regularize(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        die_te_regularize(self.ctx, x.contiguous(), y, self._shape(x))
+        return y
+
+    def solve(self, e_in: torch.Tensor, x0: torch.Tensor | None = None, **kw):
+        nrhs = self._shape(e_in)
+        out = x0.clone().contiguous() if x0 is not None else torch.empty_like(e_in)
+        rc, info = die_te_solve(self.ctx, e_in.contiguous(), out, nrhs, x0_given=x0 is not None, **kw)
+        return out, rc, info
+
+    def apply_deflation(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        nrhs = x.numel() // self.nvec
+        die_te_apply_deflation(self.ctx, x.contiguous(), y, nrhs)
+        return y
+
+    def deflation_info(self):
+        return die_te_deflation_info(self.ctx, self.nvec, device=self.device)
+
+    def close(self):
+        if self.ctx:
+            die_te_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

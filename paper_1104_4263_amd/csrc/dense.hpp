@@ -1,0 +1,234 @@
+// Small dense complex linear algebra on the host (FP64) for the offline
+// eigensolver: Householder reduction to Hessenberg form, the shifted QR
+// algorithm to complex Schur form, reordering of the Schur form, eigenvectors
+// of a triangular matrix, and an LU inverse.  Matrices are column-major.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+namespace die {
+namespace la {
+
+using cd = std::complex<double>;
+
+struct Mat {
+  int n = 0, m = 0;  // rows, cols
+  std::vector<cd> a;
+  Mat() = default;
+  Mat(int rows, int cols) : n(rows), m(cols), a((size_t)rows * cols, cd(0.0, 0.0)) {}
+  cd& operator()(int i, int j) { return a[(size_t)j * n + i]; }
+  const cd& operator()(int i, int j) const { return a[(size_t)j * n + i]; }
+  static Mat eye(int k) {
+    Mat e(k, k);
+    for (int i = 0; i < k; ++i) e(i, i) = 1.0;
+    return e;
+  }
+};
+
+// Rotation G = [[c, s], [-conj(s), c]] with G [a; b] = [r; 0].
+inline void givens(cd a, cd b, double* c, cd* s, cd* r) {
+  const double aa = std::abs(a), bb = std::abs(b);
+  if (bb == 0.0) { *c = 1.0; *s = 0.0; *r = a; return; }
+  if (aa == 0.0) { *c = 0.0; *s = std::conj(b) / bb; *r = bb; return; }
+  const double rho = std::hypot(aa, bb);
+  *c = aa / rho;
+  *s = (a / aa) * std::conj(b) / rho;
+  *r = (a / aa) * rho;
+}
+
+// rows k, k+1 of H (columns j0..j1-1) <- G rows
+inline void rot_rows(Mat& H, int k, double c, cd s, int j0, int j1) {
+  for (int j = j0; j < j1; ++j) {
+    const cd t1 = H(k, j), t2 = H(k + 1, j);
+    H(k, j) = c * t1 + s * t2;
+    H(k + 1, j) = -std::conj(s) * t1 + c * t2;
+  }
+}
+// columns k, k+1 of H (rows i0..i1-1) <- times G^H
+inline void rot_cols(Mat& H, int k, double c, cd s, int i0, int i1) {
+  for (int i = i0; i < i1; ++i) {
+    const cd t1 = H(i, k), t2 = H(i, k + 1);
+    H(i, k) = c * t1 + std::conj(s) * t2;
+    H(i, k + 1) = -s * t1 + c * t2;
+  }
+}
+
+// A (n x n) -> Q H Q^H with H upper Hessenberg (Householder); Q accumulated into Z (Z <- Z Q).
+inline void hessenberg(Mat& A, Mat& Z) {
+  const int n = A.n;
+  std::vector<cd> v(n);
+  for (int k = 0; k + 2 < n + 0 && k < n - 2; ++k) {
+    double alpha2 = 0.0;
+    for (int i = k + 1; i < n; ++i) alpha2 += std::norm(A(i, k));
+    const double anorm = std::sqrt(alpha2);
+    if (anorm == 0.0) continue;
+    const cd x0 = A(k + 1, k);
+    const cd ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cd(1.0, 0.0);
+    // v = x + ph * |x| e1, H = I - 2 v v^H / (v^H v)
+    for (int i = 0; i < n; ++i) v[i] = 0.0;
+    for (int i = k + 1; i < n; ++i) v[i] = A(i, k);
+    v[k + 1] += ph * anorm;
+    double vn = 0.0;
+    for (int i = k + 1; i < n; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    const double tau = 2.0 / vn;
+    // A <- H A
+    for (int j = 0; j < n; ++j) {
+      cd s = 0.0;
+      for (int i = k + 1; i < n; ++i) s += std::conj(v[i]) * A(i, j);
+      s *= tau;
+      for (int i = k + 1; i < n; ++i) A(i, j) -= v[i] * s;
+    }
+    // A <- A H, Z <- Z H
+    for (int i = 0; i < n; ++i) {
+      cd s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += A(i, j) * v[j];
+      s *= tau;
+      for (int j = k + 1; j < n; ++j) A(i, j) -= s * std::conj(v[j]);
+    }
+    for (int i = 0; i < Z.n; ++i) {
+      cd s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += Z(i, j) * v[j];
+      s *= tau;
+      for (int j = k + 1; j < n; ++j) Z(i, j) -= s * std::conj(v[j]);
+    }
+    for (int i = k + 2; i < n; ++i) A(i, k) = 0.0;
+  }
+}
+
+// Hessenberg H -> upper triangular T = Z^H H Z by single-shift QR with Wilkinson
+// shifts (and an exceptional shift when a block stalls).  Z <- Z * (rotations).
+// Returns false if it did not converge within 60 n sweeps.
+inline bool schur(Mat& H, Mat& Z) {
+  const int n = H.n;
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1;
+  int iter = 0, since = 0;
+  const int maxit = 60 * std::max(n, 1);
+  while (hi > 0) {
+    if (iter++ > maxit) return false;
+    int l = hi;
+    while (l > 0) {
+      const double s = std::abs(H(l, l)) + std::abs(H(l - 1, l - 1));
+      if (std::abs(H(l, l - 1)) <= eps * (s > 0 ? s : 1.0)) { H(l, l - 1) = 0.0; break; }
+      --l;
+    }
+    if (l == hi) { --hi; since = 0; continue; }
+    ++since;
+    cd mu;
+    if (since % 11 == 10) {
+      mu = H(hi, hi) + 0.75 * std::abs(H(hi, hi - 1));
+    } else {
+      const cd a = H(hi - 1, hi - 1), b = H(hi - 1, hi), c = H(hi, hi - 1), d = H(hi, hi);
+      const cd tr = a + d, det = a * d - b * c;
+      const cd disc = std::sqrt(tr * tr / 4.0 - det);
+      const cd e1 = tr / 2.0 + disc, e2 = tr / 2.0 - disc;
+      mu = std::abs(e1 - d) < std::abs(e2 - d) ? e1 : e2;
+    }
+    cd x = H(l, l) - mu, y = H(l + 1, l);
+    for (int k = l; k < hi; ++k) {
+      double c; cd s, r;
+      givens(x, y, &c, &s, &r);
+      rot_rows(H, k, c, s, k > l ? k - 1 : l, n);
+      rot_cols(H, k, c, s, 0, std::min(k + 3, hi + 1));
+      rot_cols(Z, k, c, s, 0, Z.n);
+      if (k > l) H(k + 1, k - 1) = 0.0;
+      if (k + 1 < hi) { x = H(k + 1, k); y = H(k + 2, k); }
+    }
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 1; i < n; ++i) H(i, j) = 0.0;
+  return true;
+}
+
+// Swap the adjacent diagonal entries T(i,i), T(i+1,i+1) of the upper triangular T.
+inline void schur_swap(Mat& T, Mat& Z, int i) {
+  const int n = T.n;
+  const cd a = T(i, i), b = T(i + 1, i + 1), t = T(i, i + 1);
+  double c; cd s, r;
+  givens(t, b - a, &c, &s, &r);  // G [t; b - a] = [r; 0]: the eigenvector of b goes first
+  rot_rows(T, i, c, s, i, n);
+  rot_cols(T, i, c, s, 0, i + 2);
+  rot_cols(Z, i, c, s, 0, Z.n);
+  T(i + 1, i) = 0.0;
+  T(i, i) = b;
+  T(i + 1, i + 1) = a;
+}
+
+// Move the entries flagged in `want` (by current diagonal position) to the leading
+// positions, keeping their relative order.
+inline void reorder(Mat& T, Mat& Z, std::vector<char> want) {
+  int dest = 0;
+  for (int k = 0; k < T.n; ++k) {
+    if (!want[k]) continue;
+    for (int p = k; p > dest; --p) {
+      schur_swap(T, Z, p - 1);
+      std::swap(want[p], want[p - 1]);
+    }
+    ++dest;
+  }
+}
+
+// Eigenvector y_k of upper triangular T for T(k,k): y_k(k) = 1, zero below k; columns of Y.
+inline Mat tri_eigvecs(const Mat& T) {
+  const int n = T.n;
+  Mat Y(n, n);
+  double tn = 0.0;
+  for (auto& v : T.a) tn = std::max(tn, std::abs(v));
+  const double small = 1e-14 * (tn > 0 ? tn : 1.0);
+  for (int k = 0; k < n; ++k) {
+    const cd lam = T(k, k);
+    Y(k, k) = 1.0;
+    for (int i = k - 1; i >= 0; --i) {
+      cd s = 0.0;
+      for (int j = i + 1; j <= k; ++j) s += T(i, j) * Y(j, k);
+      cd d = T(i, i) - lam;
+      if (std::abs(d) < small) d = small;
+      Y(i, k) = -s / d;
+    }
+    double nrm = 0.0;
+    for (int i = 0; i <= k; ++i) nrm += std::norm(Y(i, k));
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i <= k; ++i) Y(i, k) /= nrm;
+  }
+  return Y;
+}
+
+// Inverse by LU with partial pivoting; false if singular.
+inline bool inverse(const Mat& A, Mat& Ainv) {
+  const int n = A.n;
+  Mat L = A;
+  std::vector<int> piv(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::abs(L(k, k));
+    for (int i = k + 1; i < n; ++i)
+      if (std::abs(L(i, k)) > best) { best = std::abs(L(i, k)); p = i; }
+    if (best == 0.0) return false;
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(L(k, j), L(p, j));
+    for (int i = k + 1; i < n; ++i) {
+      L(i, k) /= L(k, k);
+      for (int j = k + 1; j < n; ++j) L(i, j) -= L(i, k) * L(k, j);
+    }
+  }
+  Ainv = Mat::eye(n);
+  for (int k = 0; k < n; ++k)
+    if (piv[k] != k)
+      for (int j = 0; j < n; ++j) std::swap(Ainv(k, j), Ainv(piv[k], j));
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i)
+      for (int l = 0; l < i; ++l) Ainv(i, j) -= L(i, l) * Ainv(l, j);
+    for (int i = n - 1; i >= 0; --i) {
+      for (int l = i + 1; l < n; ++l) Ainv(i, j) -= L(i, l) * Ainv(l, j);
+      Ainv(i, j) /= L(i, i);
+    }
+  }
+  return true;
+}
+
+}  // namespace la
+}  // namespace die

@@ -1,0 +1,776 @@
+// Host runtime of the TE DIE solver: the C ABI declared in include/die_te.h.
+//
+// Everything numerical runs in the HIP kernels of kernels_fft.hip and
+// kernels_krylov.hip; this file owns device memory, validates arguments,
+// evaluates the Green tensor once on the host (FP64) and orchestrates the
+// Krylov methods (restarted GMRES, Section 4; Arnoldi/Krylov-Schur eigensolver
+// for the deflation basis, Section 4 eq. DeflatingPrecondtioner).
+#include "die_te.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "dense.hpp"
+#include "green.hpp"
+#include "ops.hpp"
+
+using die::c2;
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define DIE_HIP(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return fail(DIE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define DIE_TRY(expr)          \
+  do {                         \
+    int _rc = (expr);          \
+    if (_rc < 0) return _rc;   \
+  } while (0)
+
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  int alloc(size_t b) {
+    if (b <= bytes && p) return DIE_OK;
+    release();
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(e == hipErrorOutOfMemory ? DIE_E_NOMEM : DIE_E_HIP,
+                  "hipMalloc(" + std::to_string(b) + " bytes): " + hipGetErrorString(e));
+    }
+    bytes = b;
+    return DIE_OK;
+  }
+  template <class X> X* as() const { return static_cast<X*>(p); }
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+int auto_pad(int n) {
+  int p = 2;
+  while (p < 2 * n - 1) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+struct die_te_ctx {
+  int dev = 0;
+  int nx = 0, ny = 0, px = 0, py = 0, lpx = 0, lpy = 0;
+  double h = 0, k = 0;
+  size_t ncell = 0, nvec = 0;
+  DBuf chi64, chir64, chi32, chir32, sym64, sym32;
+  DBuf work;  // FFT intermediate [nrhs][2][px][ny]
+  int regularize = 0;
+  // deflation
+  int r = 0;
+  DBuf V;     // [r][nvec] complex128, orthonormal
+  DBuf Cdev;  // [r][r] row-major complex128, C = T^-1 - I
+  std::vector<cd> Chost, ritz;
+  int eigs_restarts = 0, eigs_converged = 0;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ operator products
+template <class T> const c2<T>* chi_of(const die_te_ctx* c, bool reg);
+template <> const double2* chi_of<double>(const die_te_ctx* c, bool reg) {
+  return reg ? c->chir64.as<double2>() : c->chi64.as<double2>();
+}
+template <> const float2* chi_of<float>(const die_te_ctx* c, bool reg) {
+  return reg ? c->chir32.as<float2>() : c->chi32.as<float2>();
+}
+template <class T> const c2<T>* sym_of(const die_te_ctx* c);
+template <> const double2* sym_of<double>(const die_te_ctx* c) { return c->sym64.as<double2>(); }
+template <> const float2* sym_of<float>(const die_te_ctx* c) { return c->sym32.as<float2>(); }
+
+int ensure_work(die_te_ctx* c, size_t bytes, hipStream_t st) {
+  if (c->work.p && c->work.bytes >= bytes) return DIE_OK;
+  if (c->work.p) DIE_HIP(hipStreamSynchronize(st));
+  return c->work.alloc(bytes);
+}
+
+// y = A(chi) x (reg = false) or A(chi') x (reg = true) for nrhs fields.
+template <class T>
+int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const int* live, hipStream_t st) {
+  DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * sizeof(c2<T>), st));
+  c2<T>* W = c->work.as<c2<T>>();
+  DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi_of<T>(c, reg), W, c->nx, c->ny, 2 * nrhs, 2, live, st)));
+  DIE_HIP((die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, nrhs, live, st)));
+  DIE_HIP((die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, 2 * nrhs, 2, live, st)));
+  return DIE_OK;
+}
+
+// Solved operator M = A_R A (regularized) or A: out = M in, tmp is a scratch field set.
+template <class T>
+int apply_M(die_te_ctx* c, bool reg, const c2<T>* in, c2<T>* tmp, c2<T>* out, int nrhs, const int* live,
+            hipStream_t st) {
+  if (reg) {
+    DIE_TRY(apply_op<T>(c, in, tmp, nrhs, false, live, st));
+    DIE_TRY(apply_op<T>(c, tmp, out, nrhs, true, live, st));
+  } else {
+    DIE_TRY(apply_op<T>(c, in, out, nrhs, false, live, st));
+  }
+  return DIE_OK;
+}
+
+// Deflation projector y = P^-1 x = x + V (C (V^* x)) on basis-precision vectors (V in FP64).
+template <class T>
+int apply_pinv(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, double2* part, double2* coef, const int* live,
+               hipStream_t st) {
+  const size_t n = c->nvec;
+  const int nblk = die::blas_blocks(n);
+  DIE_HIP((die::launch_mdot<double, T>(c->V.as<double2>(), n, 0, c->r, nullptr, x, n, n, nrhs, part, live, st)));
+  DIE_HIP(die::launch_reduce(part, c->r, nblk, nrhs, 1.0, c->Cdev.as<double2>(), coef, live, st));
+  DIE_HIP((die::launch_maxpy<double, T, T>(0, c->V.as<double2>(), n, 0, c->r, nullptr, coef, c->r, x, n, 1.0, y, n,
+                                           0.0, n, nrhs, nullptr, nullptr, live, st)));
+  return DIE_OK;
+}
+
+// One CGS2 Arnoldi step on w against Q[0..nq) (Q[i] of rhs r at Q + (i * nrhs + r) n):
+// leaves w orthogonalised, h1neg/h2neg = -(projection coefficients) ([r * ldh + i]),
+// partn = partial ||w||^2.
+template <class T>
+int cgs2(const c2<T>* Q, int nq, int nrhs, size_t n, c2<T>* w, double2* part, double2* h1neg, double2* h2neg,
+         int ldh, double* partn, const int* live, hipStream_t st) {
+  const int nblk = die::blas_blocks(n);
+  const size_t vs = (size_t)nrhs * n;
+  DIE_HIP((die::launch_mdot<T, T>(Q, vs, n, nq, nullptr, w, n, n, nrhs, part, live, st)));
+  DIE_HIP(die::launch_reduce(part, nq, nblk, nrhs, -1.0, nullptr, h1neg, live, st));
+  // the reduce writes [r * nq + i]; ldh must equal nq for the coefficient reads below
+  (void)ldh;
+  DIE_HIP((die::launch_maxpy<T, T, T>(1, Q, vs, n, nq, nullptr, h1neg, nq, w, n, 1.0, w, n, 0.0, n, nrhs, part,
+                                      nullptr, live, st)));
+  DIE_HIP(die::launch_reduce(part, nq, nblk, nrhs, -1.0, nullptr, h2neg, live, st));
+  DIE_HIP((die::launch_maxpy<T, T, T>(2, Q, vs, n, nq, nullptr, h2neg, nq, w, n, 1.0, w, n, 0.0, n, nrhs, nullptr,
+                                      partn, live, st)));
+  return DIE_OK;
+}
+
+// ------------------------------------------------------------------ eigensolver
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int run_eigs(die_te_ctx* c, int r, double tol, int mk, int maxrst, unsigned long long seed, hipStream_t st) {
+  const size_t n = c->nvec;
+  const bool reg = c->regularize != 0;
+  const int nblk = die::blas_blocks(n);
+  if (mk <= 0) mk = std::max(2 * r + 8, 24);
+  if ((size_t)mk > n - 1) mk = (int)(n - 1);
+  if (mk < r + 1) return fail(DIE_E_INVALID, "deflate_k too large for the Krylov dimension");
+  if (maxrst <= 0) maxrst = 300;
+  if (tol <= 0) tol = 1e-4;
+  DBuf Q, Qn, Tm, Wv, part, partn, hA, hB, nrm, Zd;
+  DIE_TRY(Q.alloc((size_t)(mk + 1) * n * sizeof(double2)));
+  DIE_TRY(Qn.alloc((size_t)mk * n * sizeof(double2)));
+  DIE_TRY(Tm.alloc(n * sizeof(double2)));
+  DIE_TRY(part.alloc((size_t)(mk + 1) * nblk * sizeof(double2)));
+  DIE_TRY(partn.alloc((size_t)nblk * sizeof(double)));
+  DIE_TRY(hA.alloc((size_t)(mk + 1) * sizeof(double2)));
+  DIE_TRY(hB.alloc((size_t)(mk + 1) * sizeof(double2)));
+  DIE_TRY(nrm.alloc(sizeof(double)));
+  DIE_TRY(Zd.alloc((size_t)mk * mk * sizeof(double2)));
+  double2* q = Q.as<double2>();
+  // seeded start vector
+  {
+    std::vector<double2> v(n);
+    uint64_t s = seed ^ 0x5DEECE66Dull;
+    for (size_t e = 0; e < n; ++e) {
+      const double a = (double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+      const double b = (double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+      v[e] = make_double2(a, b);
+    }
+    DIE_HIP(hipMemcpyAsync(q, v.data(), n * sizeof(double2), hipMemcpyHostToDevice, st));
+    DIE_HIP((die::launch_norm2<double>(q, n, n, 1, partn.as<double>(), nullptr, st)));
+    DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, 1, nrm.as<double>(), nullptr, st));
+    double nn = 0;
+    DIE_HIP(hipMemcpyAsync(&nn, nrm.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    std::vector<double> sc(1, 1.0 / std::sqrt(nn));
+    DBuf scd;
+    DIE_TRY(scd.alloc(sizeof(double)));
+    DIE_HIP(hipMemcpyAsync(scd.p, sc.data(), sizeof(double), hipMemcpyHostToDevice, st));
+    DIE_HIP((die::launch_scale<double, double>(q, n, q, n, scd.as<double>(), 1, n, 1, nullptr, st)));
+    DIE_HIP(hipStreamSynchronize(st));
+  }
+  die::la::Mat H(mk + 1, mk);
+  int k0 = 0, mk_eff = mk;
+  die::la::Mat S, Z;
+  std::vector<double> resid;
+  int rst = 0;
+  bool converged = false;
+  DBuf scd;
+  DIE_TRY(scd.alloc(sizeof(double)));
+  for (rst = 0; rst <= maxrst; ++rst) {
+    mk_eff = mk;
+    for (int j = k0; j < mk; ++j) {
+      double2* w = q + (size_t)(j + 1) * n;
+      DIE_TRY(apply_M<double>(c, reg, q + (size_t)j * n, Tm.as<double2>(), w, 1, nullptr, st));
+      DIE_TRY(cgs2<double>(q, j + 1, 1, n, w, part.as<double2>(), hA.as<double2>(), hB.as<double2>(), j + 1,
+                           partn.as<double>(), nullptr, st));
+      DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, 1, nrm.as<double>(), nullptr, st));
+      std::vector<double2> ha(j + 1), hb(j + 1);
+      double nn = 0;
+      DIE_HIP(hipMemcpyAsync(ha.data(), hA.p, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+      DIE_HIP(hipMemcpyAsync(hb.data(), hB.p, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+      DIE_HIP(hipMemcpyAsync(&nn, nrm.p, sizeof(double), hipMemcpyDeviceToHost, st));
+      DIE_HIP(hipStreamSynchronize(st));
+      double hn = 0;
+      for (int i = 0; i <= j; ++i) {
+        H(i, j) = -cd(ha[i].x + hb[i].x, ha[i].y + hb[i].y);
+        hn += std::norm(H(i, j));
+      }
+      const double beta = std::sqrt(nn);
+      if (!std::isfinite(beta)) return fail(DIE_E_BREAKDOWN, "eigensolver: non-finite Arnoldi coefficient");
+      H(j + 1, j) = beta;
+      if (beta <= 1e-13 * std::sqrt(hn)) {  // invariant subspace: the Ritz values are exact
+        mk_eff = j + 1;
+        break;
+      }
+      const double inv = 1.0 / beta;
+      DIE_HIP(hipMemcpyAsync(scd.p, &inv, sizeof(double), hipMemcpyHostToDevice, st));
+      DIE_HIP((die::launch_scale<double, double>(w, n, w, n, scd.as<double>(), 1, n, 1, nullptr, st)));
+      DIE_HIP(hipStreamSynchronize(st));
+    }
+    // Schur form of the projected matrix, wanted (largest |theta|) first
+    S = die::la::Mat(mk_eff, mk_eff);
+    for (int j = 0; j < mk_eff; ++j)
+      for (int i = 0; i < mk_eff; ++i) S(i, j) = H(i, j);
+    Z = die::la::Mat::eye(mk_eff);
+    die::la::hessenberg(S, Z);
+    if (!die::la::schur(S, Z)) return fail(DIE_E_BREAKDOWN, "eigensolver: QR iteration did not converge");
+    std::vector<int> idx(mk_eff);
+    for (int i = 0; i < mk_eff; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return std::abs(S(a, a)) > std::abs(S(b, b)); });
+    const int rr = std::min(r, mk_eff);
+    std::vector<char> want(mk_eff, 0);
+    for (int i = 0; i < rr; ++i) want[idx[i]] = 1;
+    die::la::reorder(S, Z, want);
+    const cd beta_last = H(mk_eff, mk_eff - 1);
+    std::vector<cd> b(mk_eff);
+    for (int l = 0; l < mk_eff; ++l) b[l] = beta_last * Z(mk_eff - 1, l);
+    die::la::Mat Y = die::la::tri_eigvecs(S);
+    resid.assign(rr, 0.0);
+    int nconv = 0;
+    for (int i = 0; i < rr; ++i) {
+      cd s = 0;
+      for (int l = 0; l <= i; ++l) s += b[l] * Y(l, i);
+      resid[i] = std::abs(s);
+      if (resid[i] <= tol * std::abs(S(i, i))) ++nconv;
+    }
+    c->eigs_converged = nconv;
+    if (nconv >= rr || mk_eff < mk || rst == maxrst) {
+      converged = nconv >= rr;
+      break;
+    }
+    // Krylov-Schur restart: keep kk leading Schur vectors
+    const int kk = std::min(mk - 1, r + (mk - r) / 2);
+    std::vector<double2> zh((size_t)mk_eff * kk);
+    for (int l = 0; l < kk; ++l)
+      for (int i = 0; i < mk_eff; ++i) zh[(size_t)l * mk_eff + i] = make_double2(Z(i, l).real(), Z(i, l).imag());
+    DIE_HIP(hipMemcpyAsync(Zd.p, zh.data(), zh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    DIE_HIP((die::launch_maxpy<double, double, double>(0, q, n, 0, mk_eff, nullptr, Zd.as<double2>(), mk_eff,
+                                                       (const double2*)nullptr, 0, 0.0, Qn.as<double2>(), n, 0.0,
+                                                       n, kk, nullptr, nullptr, nullptr, st)));
+    DIE_HIP(hipMemcpyAsync(q, Qn.p, (size_t)kk * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    DIE_HIP(hipMemcpyAsync(q + (size_t)kk * n, q + (size_t)mk_eff * n, n * sizeof(double2), hipMemcpyDeviceToDevice,
+                           st));
+    DIE_HIP(hipStreamSynchronize(st));
+    die::la::Mat Hn(mk + 1, mk);
+    for (int j = 0; j < kk; ++j) {
+      for (int i = 0; i <= j; ++i) Hn(i, j) = S(i, j);
+      Hn(kk, j) = b[j];
+    }
+    H = Hn;
+    k0 = kk;
+  }
+  c->eigs_restarts = rst;
+  const int rr = std::min(r, mk_eff);
+  // deflation basis V = Q Z[:, :rr]
+  DIE_TRY(c->V.alloc((size_t)rr * n * sizeof(double2)));
+  {
+    std::vector<double2> zh((size_t)mk_eff * rr);
+    for (int l = 0; l < rr; ++l)
+      for (int i = 0; i < mk_eff; ++i) zh[(size_t)l * mk_eff + i] = make_double2(Z(i, l).real(), Z(i, l).imag());
+    DIE_HIP(hipMemcpyAsync(Zd.p, zh.data(), zh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    DIE_HIP((die::launch_maxpy<double, double, double>(0, q, n, 0, mk_eff, nullptr, Zd.as<double2>(), mk_eff,
+                                                       (const double2*)nullptr, 0, 0.0, c->V.as<double2>(), n, 0.0,
+                                                       n, rr, nullptr, nullptr, nullptr, st)));
+  }
+  // T = V^* M V from rr products of M (batched), C = T^-1 - I
+  DBuf MV, MT, partT, Td;
+  DIE_TRY(MV.alloc((size_t)rr * n * sizeof(double2)));
+  DIE_TRY(MT.alloc((size_t)rr * n * sizeof(double2)));
+  DIE_TRY(partT.alloc((size_t)rr * rr * nblk * sizeof(double2)));
+  DIE_TRY(Td.alloc((size_t)rr * rr * sizeof(double2)));
+  DIE_TRY(apply_M<double>(c, reg, c->V.as<double2>(), MT.as<double2>(), MV.as<double2>(), rr, nullptr, st));
+  DIE_HIP((die::launch_mdot<double, double>(c->V.as<double2>(), n, 0, rr, nullptr, MV.as<double2>(), n, n, rr,
+                                            partT.as<double2>(), nullptr, st)));
+  DIE_HIP(die::launch_reduce(partT.as<double2>(), rr, nblk, rr, 1.0, nullptr, Td.as<double2>(), nullptr, st));
+  std::vector<double2> th((size_t)rr * rr);
+  DIE_HIP(hipMemcpyAsync(th.data(), Td.p, th.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+  DIE_HIP(hipStreamSynchronize(st));
+  die::la::Mat T(rr, rr), Ti;
+  for (int l = 0; l < rr; ++l)
+    for (int i = 0; i < rr; ++i) T(i, l) = cd(th[(size_t)l * rr + i].x, th[(size_t)l * rr + i].y);
+  if (!die::la::inverse(T, Ti)) return fail(DIE_E_BREAKDOWN, "deflation: T = V^* M V is singular");
+  c->Chost.assign((size_t)rr * rr, cd(0, 0));
+  std::vector<double2> ch((size_t)rr * rr);
+  for (int i = 0; i < rr; ++i)
+    for (int l = 0; l < rr; ++l) {
+      cd v = Ti(i, l) - (i == l ? 1.0 : 0.0);
+      c->Chost[(size_t)i * rr + l] = v;
+      ch[(size_t)i * rr + l] = make_double2(v.real(), v.imag());
+    }
+  DIE_TRY(c->Cdev.alloc(ch.size() * sizeof(double2)));
+  DIE_HIP(hipMemcpyAsync(c->Cdev.p, ch.data(), ch.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  c->ritz.resize(rr);
+  for (int i = 0; i < rr; ++i) c->ritz[i] = S(i, i);
+  c->r = rr;
+  DIE_HIP(hipStreamSynchronize(st));
+  (void)converged;
+  return DIE_OK;
+}
+
+// ------------------------------------------------------------------ GMRES
+template <class T>
+int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
+                die_te_solve_info* info, hipStream_t st) {
+  const size_t n = c->nvec;
+  const int m = o.restart;
+  const int nblk = die::blas_blocks(n);
+  const bool reg = c->regularize != 0;
+  const bool defl = c->r > 0;
+  const double tol = o.tol > 0 ? o.tol : 1e-8;
+  const double margin = reg ? (o.reg_margin > 0 ? o.reg_margin : 0.1) : 1.0;
+  const double floor_eta = std::is_same<T, float>::value ? 2e-6 : 0.0;
+  const size_t vbytes = (size_t)nrhs * n * sizeof(c2<T>);
+  const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
+  const int nvmax = std::max(m + 1, c->r);
+  DBuf Q, Zb, Tb, Wb, Rs, Sd, part, partn, h1, h2, hd, Rm, cs, sn, g, y, state, live, active, nrm;
+  DIE_TRY(Q.alloc((size_t)(m + 1) * vbytes));
+  if (defl) DIE_TRY(Zb.alloc(vbytes));
+  if (reg) DIE_TRY(Tb.alloc(vbytes));
+  DIE_TRY(Wb.alloc(vbytes));
+  DIE_TRY(Rs.alloc(dbytes));
+  if (reg) DIE_TRY(Sd.alloc(dbytes));
+  DIE_TRY(part.alloc((size_t)nrhs * nvmax * nblk * sizeof(double2)));
+  DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
+  DIE_TRY(h1.alloc((size_t)nrhs * (m + 1) * sizeof(double2)));
+  DIE_TRY(h2.alloc((size_t)nrhs * (m + 1) * sizeof(double2)));
+  DIE_TRY(hd.alloc((size_t)nrhs * std::max(c->r, 1) * sizeof(double2)));
+  DIE_TRY(Rm.alloc((size_t)nrhs * (m + 1) * m * sizeof(double2)));
+  DIE_TRY(cs.alloc((size_t)nrhs * m * sizeof(double)));
+  DIE_TRY(sn.alloc((size_t)nrhs * m * sizeof(double2)));
+  DIE_TRY(g.alloc((size_t)nrhs * (m + 1) * sizeof(double2)));
+  DIE_TRY(y.alloc((size_t)nrhs * m * sizeof(double2)));
+  DIE_TRY(state.alloc((size_t)nrhs * sizeof(die::GmresState)));
+  DIE_TRY(live.alloc((size_t)nrhs * sizeof(int)));
+  DIE_TRY(active.alloc((size_t)nrhs * sizeof(int)));
+  DIE_TRY(nrm.alloc((size_t)nrhs * sizeof(double)));
+  DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * std::max(sizeof(c2<T>), sizeof(double2)), st));
+
+  c2<T>* q = Q.as<c2<T>>();
+  const size_t vs = (size_t)nrhs * n;  // stride between basis vectors j
+  double2* res = Rs.as<double2>();
+  std::vector<double> bnorm(nrhs), rnorm(nrhs), hn(nrhs);
+  std::vector<int> act(nrhs, 1), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0),
+      brk(nrhs, 0);
+  std::vector<double> relres(nrhs, 1.0);
+
+  if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
+  DIE_HIP((die::launch_norm2<double>(b, n, n, nrhs, partn.as<double>(), nullptr, st)));
+  DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), nullptr, st));
+  DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  DIE_HIP(hipStreamSynchronize(st));
+  for (int r = 0; r < nrhs; ++r) {
+    bnorm[r] = std::sqrt(hn[r]);
+    if (!std::isfinite(bnorm[r])) return fail(DIE_E_INVALID, "e_in contains non-finite values");
+  }
+
+  std::vector<die::GmresState> hst(nrhs);
+  std::vector<double2> hg((size_t)nrhs * (m + 1));
+  std::vector<double> inv0(nrhs);
+  DBuf sc;
+  DIE_TRY(sc.alloc((size_t)nrhs * sizeof(double)));
+  for (;;) {
+    // ---- FP64 true residual res = b - A u
+    DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    const int* dact = active.as<int>();
+    DIE_TRY(apply_op<double>(c, u, res, nrhs, false, dact, st));
+    DIE_HIP((die::launch_maxpy<double, double, double>(2, (const double2*)nullptr, 0, 0, 0, nullptr, nullptr, 0, b, n,
+                                                       1.0, res, n, -1.0, n, nrhs, nullptr, partn.as<double>(), dact,
+                                                       st)));
+    DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), dact, st));
+    DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    int nact = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!act[r]) continue;
+      pa[r] += 1;
+      rnorm[r] = std::sqrt(hn[r]);
+      relres[r] = bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0;
+      if (!std::isfinite(rnorm[r])) {
+        brk[r] = 1;
+        act[r] = 0;
+      } else if (relres[r] <= tol || bnorm[r] == 0.0) {
+        conv[r] = 1;
+        act[r] = 0;
+      } else if (iters[r] >= o.max_iters) {
+        act[r] = 0;
+      } else {
+        ++nact;
+      }
+    }
+    if (nact == 0) break;
+    DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    // ---- cycle right-hand side s = A_R res (or res), beta0, q0 = s / beta0
+    const double2* s = res;
+    if (reg) {
+      DIE_TRY(apply_op<double>(c, res, Sd.as<double2>(), nrhs, true, dact, st));
+      s = Sd.as<double2>();
+      for (int r = 0; r < nrhs; ++r) par[r] += act[r];
+    }
+    DIE_HIP((die::launch_norm2<double>(s, n, n, nrhs, partn.as<double>(), dact, st)));
+    DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), dact, st));
+    DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    std::fill(hg.begin(), hg.end(), make_double2(0.0, 0.0));
+    for (int r = 0; r < nrhs; ++r) {
+      die::GmresState S{};
+      S.j = 0;
+      S.done = act[r] ? 0 : 1;
+      const double beta0 = std::sqrt(hn[r]);
+      S.beta0 = beta0;
+      double eta = act[r] ? tol * bnorm[r] / rnorm[r] * margin : 1.0;
+      eta = std::min(1.0, std::max(eta, floor_eta));
+      S.target = eta * beta0;
+      hst[r] = S;
+      hg[(size_t)r * (m + 1)] = make_double2(beta0, 0.0);
+      inv0[r] = beta0 > 0 ? 1.0 / beta0 : 0.0;
+      if (act[r] && !(beta0 > 0 && std::isfinite(beta0))) {
+        // regularized residual vanished or is non-finite: nothing this cycle can do
+        act[r] = 0;
+        if (!std::isfinite(beta0)) brk[r] = 1;
+      }
+    }
+    DIE_HIP(hipMemcpyAsync(state.p, hst.data(), nrhs * sizeof(die::GmresState), hipMemcpyHostToDevice, st));
+    DIE_HIP(hipMemcpyAsync(g.p, hg.data(), hg.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    DIE_HIP(hipMemcpyAsync(sc.p, inv0.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    DIE_HIP(hipMemcpyAsync(live.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    int* dlive = live.as<int>();
+    DIE_HIP((die::launch_scale<double, T>(s, n, q, n, sc.as<double>(), 1, n, nrhs, dact, st)));
+    // ---- Arnoldi / GMRES iterations of this cycle
+    for (int j = 0; j < m; ++j) {
+      const c2<T>* qj = q + (size_t)j * vs;
+      const c2<T>* z = qj;
+      if (defl) {
+        DIE_TRY(apply_pinv<T>(c, qj, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dlive, st));
+        z = Zb.as<c2<T>>();
+      }
+      c2<T>* w = q + (size_t)(j + 1) * vs;
+      DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st));
+      DIE_TRY(cgs2<T>(q, j + 1, nrhs, n, w, part.as<double2>(), h1.as<double2>(), h2.as<double2>(), j + 1,
+                      partn.as<double>(), dlive, st));
+      DIE_HIP(die::launch_givens(h1.as<double2>(), h2.as<double2>(), j + 1, -1.0, partn.as<double>(), nblk,
+                                 state.as<die::GmresState>(), Rm.as<double2>(), cs.as<double>(), sn.as<double2>(),
+                                 g.as<double2>(), y.as<double2>(), m, nrhs, dlive, dact, st));
+      DIE_HIP((die::launch_scale<T, T>(w, n, w, n, &state.as<die::GmresState>()->invbeta,
+                                       (int)(sizeof(die::GmresState) / sizeof(double)), n, nrhs, dlive, st)));
+    }
+    // ---- u += P^-1 (Q y)
+    DIE_HIP(hipMemcpyAsync(hst.data(), state.p, nrhs * sizeof(die::GmresState), hipMemcpyDeviceToHost, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    std::vector<int> jn(nrhs);
+    for (int r = 0; r < nrhs; ++r) jn[r] = act[r] ? hst[r].j : 0;
+    DBuf jd;
+    DIE_TRY(jd.alloc(nrhs * sizeof(int)));
+    DIE_HIP(hipMemcpyAsync(jd.p, jn.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    c2<T>* t = Wb.as<c2<T>>();
+    DIE_HIP((die::launch_maxpy<T, T, T>(0, q, vs, n, m, jd.as<int>(), y.as<double2>(), m, (const c2<T>*)nullptr, 0,
+                                        0.0, t, n, 0.0, n, nrhs, nullptr, nullptr, dact, st)));
+    if (defl) {
+      DIE_HIP((die::launch_mdot<double, T>(c->V.as<double2>(), n, 0, c->r, nullptr, t, n, n, nrhs, part.as<double2>(),
+                                           dact, st)));
+      DIE_HIP(die::launch_reduce(part.as<double2>(), c->r, nblk, nrhs, 1.0, c->Cdev.as<double2>(), hd.as<double2>(),
+                                 dact, st));
+      DIE_HIP((die::launch_maxpy<double, T, double>(0, c->V.as<double2>(), n, 0, c->r, nullptr, hd.as<double2>(), c->r,
+                                                    t, n, 1.0, u, n, 1.0, n, nrhs, nullptr, nullptr, dact, st)));
+    } else {
+      DIE_HIP((die::launch_maxpy<double, T, double>(0, (const double2*)nullptr, 0, 0, 0, nullptr, nullptr, 0, t, n, 1.0,
+                                                    u, n, 1.0, n, nrhs, nullptr, nullptr, dact, st)));
+    }
+    for (int r = 0; r < nrhs; ++r) {
+      if (!act[r]) continue;
+      iters[r] += hst[r].j;
+      cycles[r] += 1;
+      pa[r] += hst[r].j;
+      if (reg) par[r] += hst[r].j;
+      if (hst[r].breakdown) {
+        brk[r] = 1;
+        act[r] = 0;
+      }
+    }
+  }
+  int rc = DIE_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    if (brk[r]) rc = std::min(rc, (int)DIE_E_BREAKDOWN);
+    else if (!conv[r] && rc == DIE_OK) rc = DIE_NOT_CONVERGED;
+    if (info) {
+      info[r].status = brk[r] ? DIE_E_BREAKDOWN : (conv[r] ? DIE_OK : DIE_NOT_CONVERGED);
+      info[r].iters = iters[r];
+      info[r].products_A = pa[r];
+      info[r].products_AR = par[r];
+      info[r].cycles = cycles[r];
+      info[r].rel_res_true = relres[r];
+    }
+  }
+  if (rc == DIE_E_BREAKDOWN) return fail(DIE_E_BREAKDOWN, "GMRES met a non-finite value");
+  return rc;
+}
+
+int check_ctx(const die_te_ctx* c) {
+  if (!c) return fail(DIE_E_INVALID, "null context");
+  return DIE_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* die_te_last_error(void) { return g_err.c_str(); }
+
+int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, const die_te_setup_opts* opts,
+                 void* stream) {
+  g_err.clear();
+  if (!out || !gr || !eps_r) return fail(DIE_E_INVALID, "null argument");
+  *out = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  if (gr->nx < 1 || gr->ny < 1 || gr->nx > 2048 || gr->ny > 2048)
+    return fail(DIE_E_INVALID, "nx, ny must be in [1, 2048]");
+  if (!(gr->h > 0) || !std::isfinite(gr->h)) return fail(DIE_E_INVALID, "h must be positive and finite");
+  const double k = gr->k_b == 0 ? 2.0 * M_PI : gr->k_b;
+  if (!(k > 0) || !std::isfinite(k)) return fail(DIE_E_INVALID, "k_b must be positive and finite");
+  const int px = gr->px ? gr->px : auto_pad(gr->nx);
+  const int py = gr->py ? gr->py : auto_pad(gr->ny);
+  if (!is_pow2(px) || !is_pow2(py) || px < 2 || py < 2 || px > 4096 || py > 4096 || px < 2 * gr->nx - 1 ||
+      py < 2 * gr->ny - 1)
+    return fail(DIE_E_INVALID, "px, py must be powers of two in [max(2, 2n-1), 4096]");
+  die_te_setup_opts o{};
+  if (opts) o = *opts;
+  if (o.deflate_k < 0) return fail(DIE_E_INVALID, "deflate_k must be >= 0");
+
+  auto* c = new (std::nothrow) die_te_ctx();
+  if (!c) return fail(DIE_E_NOMEM, "host allocation failed");
+  auto guard = [&](int rc) {
+    if (rc < 0) delete c;
+    return rc;
+  };
+  if (hipGetDevice(&c->dev) != hipSuccess) return guard(fail(DIE_E_HIP, "hipGetDevice failed"));
+  c->nx = gr->nx; c->ny = gr->ny; c->px = px; c->py = py;
+  c->lpx = ilog2(px); c->lpy = ilog2(py);
+  c->h = gr->h; c->k = k;
+  c->ncell = (size_t)gr->nx * gr->ny;
+  c->nvec = 2 * c->ncell;
+  c->regularize = o.regularize ? 1 : 0;
+
+  // contrast (eq. ElectricContrast) and regularizer contrast (eq. InverseSymbol)
+  std::vector<double2> eps(c->ncell);
+  if (hipMemcpyAsync(eps.data(), eps_r, c->ncell * sizeof(double2), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return guard(fail(DIE_E_HIP, "reading eps_r failed (is it a device pointer?)"));
+  std::vector<double2> chi(c->ncell), chir(c->ncell);
+  std::vector<float2> chi32(c->ncell), chir32(c->ncell);
+  for (size_t e = 0; e < c->ncell; ++e) {
+    const cd ev(eps[e].x, eps[e].y);
+    if (!std::isfinite(ev.real()) || !std::isfinite(ev.imag()))
+      return guard(fail(DIE_E_INVALID, "eps_r contains non-finite values"));
+    if (ev == cd(0.0, 0.0))
+      return guard(fail(DIE_E_SINGULAR, "eps_r == 0 at cell " + std::to_string(e) + ": no solution exists"));
+    const cd x = ev - 1.0, xr = 1.0 / ev - 1.0;
+    chi[e] = make_double2(x.real(), x.imag());
+    chir[e] = make_double2(xr.real(), xr.imag());
+    chi32[e] = make_float2((float)x.real(), (float)x.imag());
+    chir32[e] = make_float2((float)xr.real(), (float)xr.imag());
+  }
+  int rc;
+  if ((rc = c->chi64.alloc(c->ncell * sizeof(double2))) < 0 || (rc = c->chir64.alloc(c->ncell * sizeof(double2))) < 0 ||
+      (rc = c->chi32.alloc(c->ncell * sizeof(float2))) < 0 || (rc = c->chir32.alloc(c->ncell * sizeof(float2))) < 0)
+    return guard(rc);
+  if (hipMemcpyAsync(c->chi64.p, chi.data(), c->ncell * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->chir64.p, chir.data(), c->ncell * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->chi32.p, chi32.data(), c->ncell * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->chir32.p, chir32.data(), c->ncell * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess)
+    return guard(fail(DIE_E_HIP, "uploading the contrast failed"));
+
+  // Green tensor, circulant embedding, symbol = FFT2 / (px py) on the GPU
+  {
+    std::vector<cd> planes;
+    die::green::embed(c->nx, c->ny, px, py, c->h, c->k, planes);
+    const size_t plane = (size_t)px * py;
+    DBuf E, W;
+    if ((rc = E.alloc(3 * plane * sizeof(double2))) < 0 || (rc = W.alloc(3 * plane * sizeof(double2))) < 0)
+      return guard(rc);
+    if (hipMemcpyAsync(E.p, planes.data(), 3 * plane * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess)
+      return guard(fail(DIE_E_HIP, "uploading the Green tensor failed"));
+    if ((rc = c->sym64.alloc(3 * plane * sizeof(double2))) < 0 || (rc = c->sym32.alloc(3 * plane * sizeof(float2))) < 0)
+      return guard(rc);
+    hipError_t e1 = die::launch_rows_fwd<double, double>(c->lpx, false, E.as<double2>(), nullptr, W.as<double2>(), px,
+                                                         py, 3, 1, nullptr, st);
+    hipError_t e2 = die::launch_cols_plain<double>(c->lpy, false, W.as<double2>(), px, 3, st);
+    hipError_t e3 = die::launch_pack_symbol(W.as<double2>(), c->sym64.as<double2>(), c->sym32.as<float2>(), px, py,
+                                            1.0 / ((double)px * (double)py), st);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      return guard(fail(DIE_E_HIP, "symbol transform failed"));
+  }
+  if (o.deflate_k > 0) {
+    if ((size_t)o.deflate_k >= c->nvec) return guard(fail(DIE_E_INVALID, "deflate_k must be < 2 nx ny"));
+    rc = run_eigs(c, o.deflate_k, o.eigs_tol, o.eigs_krylov, o.eigs_max_restarts, o.seed, st);
+    if (rc < 0) return guard(rc);
+  }
+  *out = c;
+  return DIE_OK;
+}
+
+static int product(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream, bool reg) {
+  g_err.clear();
+  DIE_TRY(check_ctx(c));
+  if (!x || !y || nrhs < 1) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
+  if (x == y) return fail(DIE_E_INVALID, "x and y must not overlap");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == DIE_C128) return apply_op<double>(c, (const double2*)x, (double2*)y, nrhs, reg, nullptr, st);
+  if (prec == DIE_C64) return apply_op<float>(c, (const float2*)x, (float2*)y, nrhs, reg, nullptr, st);
+  return fail(DIE_E_INVALID, "prec must be DIE_C128 or DIE_C64");
+}
+
+int die_te_matvec(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream) {
+  return product(c, x, y, nrhs, prec, stream, false);
+}
+
+int die_te_regularize(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream) {
+  return product(c, x, y, nrhs, prec, stream, true);
+}
+
+int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const die_te_solve_opts* opts,
+                 die_te_solve_info* info, void* stream) {
+  g_err.clear();
+  DIE_TRY(check_ctx(c));
+  if (!e_in || !e_tot || nrhs < 1 || !opts) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
+  if (e_in == e_tot) return fail(DIE_E_INVALID, "e_in and e_tot must not overlap");
+  die_te_solve_opts o = *opts;
+  if (o.restart < 1 || o.restart > 512) return fail(DIE_E_INVALID, "restart must be in [1, 512]");
+  if (o.max_iters < 1) return fail(DIE_E_INVALID, "max_iters must be >= 1");
+  if (o.tol < 0 || !std::isfinite(o.tol)) return fail(DIE_E_INVALID, "tol must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  if (o.mixed) return gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+  return gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+}
+
+int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void* stream) {
+  g_err.clear();
+  DIE_TRY(check_ctx(c));
+  if (c->r <= 0) return fail(DIE_E_INVALID, "the context has no deflation basis");
+  if (!x || !y || nrhs < 1) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = c->nvec;
+  const int nblk = die::blas_blocks(n);
+  DBuf part, coef;
+  DIE_TRY(part.alloc((size_t)nrhs * c->r * nblk * sizeof(double2)));
+  DIE_TRY(coef.alloc((size_t)nrhs * c->r * sizeof(double2)));
+  DIE_TRY(apply_pinv<double>(c, (const double2*)x, (double2*)y, nrhs, part.as<double2>(), coef.as<double2>(), nullptr,
+                             st));
+  DIE_HIP(hipStreamSynchronize(st));  // part/coef are freed on return
+  return DIE_OK;
+}
+
+int die_te_deflation_info(die_te_ctx* c, int* r, void* ritz, void* V, void* C, void* stream) {
+  g_err.clear();
+  DIE_TRY(check_ctx(c));
+  if (!r) return fail(DIE_E_INVALID, "null r");
+  *r = c->r;
+  hipStream_t st = (hipStream_t)stream;
+  if (ritz && c->r > 0) std::memcpy(ritz, c->ritz.data(), c->r * sizeof(cd));
+  if (C && c->r > 0) std::memcpy(C, c->Chost.data(), (size_t)c->r * c->r * sizeof(cd));
+  if (V && c->r > 0) {
+    DIE_HIP(hipMemcpyAsync(V, c->V.p, (size_t)c->r * c->nvec * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    DIE_HIP(hipStreamSynchronize(st));
+  }
+  return DIE_OK;
+}
+
+int die_te_fft2(void* data, int px, int py, int batch, int inverse, int prec, void* stream) {
+  g_err.clear();
+  if (!data || batch < 1) return fail(DIE_E_INVALID, "null data or batch < 1");
+  if (!is_pow2(px) || !is_pow2(py) || px < 2 || py < 2 || px > 4096 || py > 4096)
+    return fail(DIE_E_INVALID, "px, py must be powers of two in [2, 4096]");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t plane = (size_t)px * py;
+  const bool inv = inverse != 0;
+  DBuf W;
+  if (prec == DIE_C128) {
+    DIE_TRY(W.alloc(batch * plane * sizeof(double2)));
+    DIE_HIP((die::launch_rows_fwd<double, double>(ilog2(px), inv, (const double2*)data, nullptr, W.as<double2>(), px,
+                                                  py, batch, 1, nullptr, st)));
+    DIE_HIP(die::launch_cols_plain<double>(ilog2(py), inv, W.as<double2>(), px, batch, st));
+    DIE_HIP(die::launch_transpose<double>(W.as<double2>(), (double2*)data, px, py, batch, st));
+  } else if (prec == DIE_C64) {
+    DIE_TRY(W.alloc(batch * plane * sizeof(float2)));
+    DIE_HIP((die::launch_rows_fwd<float, float>(ilog2(px), inv, (const float2*)data, nullptr, W.as<float2>(), px, py,
+                                                batch, 1, nullptr, st)));
+    DIE_HIP(die::launch_cols_plain<float>(ilog2(py), inv, W.as<float2>(), px, batch, st));
+    DIE_HIP(die::launch_transpose<float>(W.as<float2>(), (float2*)data, px, py, batch, st));
+  } else {
+    return fail(DIE_E_INVALID, "prec must be DIE_C128 or DIE_C64");
+  }
+  DIE_HIP(hipStreamSynchronize(st));
+  return DIE_OK;
+}
+
+int die_te_destroy(die_te_ctx* c) {
+  g_err.clear();
+  if (!c) return DIE_OK;
+  (void)hipDeviceSynchronize();
+  delete c;
+  return DIE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,463 @@
+// Krylov kernels: multi-dot / multi-axpy for classical Gram-Schmidt with one
+// re-orthogonalisation (CGS2) in the Arnoldi process of restarted GMRES, the
+// deflation projector x + V (C (V^* x)), norms, scaling, and the FP64 Givens
+// least-squares update of the GMRES Hessenberg column.  All reductions are
+// two-stage (per-block partials, then a fixed-order sum), so results are
+// deterministic run to run.
+#include "ops.hpp"
+
+#include <cmath>
+
+namespace die {
+
+namespace {
+
+constexpr int NT = kBlasThreads;
+constexpr int EPT = kBlasEpt;
+constexpr int NW = NT / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  `red` holds NW entries.
+__device__ __forceinline__ double2 block_sum(double2 v, double2* red) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) { s.x += red[k].x; s.y += red[k].y; }
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double block_sum1(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[k];
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zcmul(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- multi-dot
+template <class SA, class SB>
+__global__ void __launch_bounds__(NT)
+k_mdot(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const int* __restrict__ nv_dev,
+       const c2<SB>* __restrict__ B, size_t b_rs, size_t n, double2* __restrict__ part,
+       const int* __restrict__ live) {
+  const int r = blockIdx.y;
+  if (live && !live[r]) return;
+  __shared__ double2 red[NW];
+  const int nblk = gridDim.x;
+  const int nvr = nv_dev ? min(nv_dev[r], nv) : nv;
+  const size_t e0 = (size_t)blockIdx.x * NT * EPT + threadIdx.x;
+  const c2<SB>* Br = B + (size_t)r * b_rs;
+  double2 b[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = e0 + (size_t)k * NT;
+    b[k] = e < n ? ld<double, SB>(Br + e) : make_double2(0.0, 0.0);
+  }
+  for (int i = 0; i < nv; ++i) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (i < nvr) {
+      const c2<SA>* Ai = A + (size_t)i * a_vs + (size_t)r * a_rs;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const size_t e = e0 + (size_t)k * NT;
+        if (e < n) {
+          const double2 a = ld<double, SA>(Ai + e);
+          const double2 p = zcmul(a, b[k]);
+          acc.x += p.x;
+          acc.y += p.y;
+        }
+      }
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[((size_t)r * nv + i) * nblk + blockIdx.x] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- reduce
+constexpr int kMaxReduceNv = 1024;
+
+__global__ void __launch_bounds__(NT)
+k_reduce(const double2* __restrict__ part, int nv, int nblk, double sign, const double2* __restrict__ C,
+         double2* __restrict__ out, const int* __restrict__ live) {
+  const int r = blockIdx.x;
+  if (live && !live[r]) return;
+  __shared__ double2 tmp[kMaxReduceNv];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = w; i < nv; i += NW) {
+    const double2* p = part + ((size_t)r * nv + i) * nblk;
+    double sx = 0.0, sy = 0.0;
+    for (int b = lane; b < nblk; b += 64) { sx += p[b].x; sy += p[b].y; }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if (lane == 0) tmp[i] = make_double2(sign * sx, sign * sy);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += NT) {
+    double2 v;
+    if (C) {
+      v = make_double2(0.0, 0.0);
+      for (int l = 0; l < nv; ++l) {
+        const double2 p = zmul(C[(size_t)i * nv + l], tmp[l]);
+        v.x += p.x;
+        v.y += p.y;
+      }
+    } else {
+      v = tmp[i];
+    }
+    out[(size_t)r * nv + i] = v;
+  }
+}
+
+// ---------------------------------------------------------------- multi-axpy
+template <class SA, class SX, class SY, int MODE>
+__global__ void __launch_bounds__(NT)
+k_maxpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const int* __restrict__ nv_dev,
+        const double2* __restrict__ coef, int ldc, const c2<SX>* X, size_t x_rs, double alpha, c2<SY>* Y,
+        size_t y_rs, double beta, size_t n, double2* __restrict__ part, double* __restrict__ partn,
+        const int* __restrict__ live) {
+  const int r = blockIdx.y;
+  if (live && !live[r]) return;
+  __shared__ double2 red[NW];
+  __shared__ double red1[NW];
+  const int nblk = gridDim.x;
+  const int nvr = nv_dev ? min(nv_dev[r], nv) : nv;
+  const size_t e0 = (size_t)blockIdx.x * NT * EPT + threadIdx.x;
+  c2<SY>* Yr = Y + (size_t)r * y_rs;
+  const c2<SX>* Xr = X ? X + (size_t)r * x_rs : nullptr;
+  double2 y[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = e0 + (size_t)k * NT;
+    double2 v = make_double2(0.0, 0.0);
+    if (e < n) {
+      if (beta != 0.0) {
+        const double2 yo = ld<double, SY>(Yr + e);
+        v.x = beta * yo.x;
+        v.y = beta * yo.y;
+      }
+      if (Xr) {
+        const double2 xv = ld<double, SX>(Xr + e);
+        v.x += alpha * xv.x;
+        v.y += alpha * xv.y;
+      }
+    }
+    y[k] = v;
+  }
+  for (int i = 0; i < nvr; ++i) {
+    const double2 c = coef[(size_t)r * ldc + i];
+    const c2<SA>* Ai = A + (size_t)i * a_vs + (size_t)r * a_rs;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const size_t e = e0 + (size_t)k * NT;
+      if (e < n) {
+        const double2 p = zmul(c, ld<double, SA>(Ai + e));
+        y[k].x += p.x;
+        y[k].y += p.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = e0 + (size_t)k * NT;
+    if (e < n) {
+      st<SY, double>(Yr + e, y[k]);
+      y[k] = ld<double, SY>(Yr + e);  // continue with the stored (rounded) value
+    }
+  }
+  if constexpr (MODE == 1) {
+    for (int i = 0; i < nv; ++i) {
+      double2 acc = make_double2(0.0, 0.0);
+      if (i < nvr) {
+        const c2<SA>* Ai = A + (size_t)i * a_vs + (size_t)r * a_rs;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const size_t e = e0 + (size_t)k * NT;
+          if (e < n) {
+            const double2 p = zcmul(ld<double, SA>(Ai + e), y[k]);
+            acc.x += p.x;
+            acc.y += p.y;
+          }
+        }
+      }
+      acc = block_sum(acc, red);
+      if (threadIdx.x == 0) part[((size_t)r * nv + i) * nblk + blockIdx.x] = acc;
+    }
+  } else if constexpr (MODE == 2) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) s += y[k].x * y[k].x + y[k].y * y[k].y;
+    s = block_sum1(s, red1);
+    if (threadIdx.x == 0) partn[(size_t)r * nblk + blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------- norms, scaling
+template <class S>
+__global__ void __launch_bounds__(NT)
+k_norm2(const c2<S>* __restrict__ X, size_t x_rs, size_t n, double* __restrict__ partn,
+        const int* __restrict__ live) {
+  const int r = blockIdx.y;
+  if (live && !live[r]) return;
+  __shared__ double red1[NW];
+  const size_t e0 = (size_t)blockIdx.x * NT * EPT + threadIdx.x;
+  const c2<S>* Xr = X + (size_t)r * x_rs;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = e0 + (size_t)k * NT;
+    if (e < n) {
+      const double2 v = ld<double, S>(Xr + e);
+      s += v.x * v.x + v.y * v.y;
+    }
+  }
+  s = block_sum1(s, red1);
+  if (threadIdx.x == 0) partn[(size_t)r * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(64)
+k_reduce_norm(const double* __restrict__ partn, int nblk, double* __restrict__ out, const int* __restrict__ live) {
+  const int r = blockIdx.x;
+  if (live && !live[r]) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += partn[(size_t)r * nblk + b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[r] = s;
+}
+
+template <class SX, class SY>
+__global__ void __launch_bounds__(NT)
+k_scale(const c2<SX>* X, size_t x_rs, c2<SY>* Y, size_t y_rs, const double* __restrict__ scale, int sstride,
+        size_t n, const int* __restrict__ live) {
+  const int r = blockIdx.y;
+  if (live && !live[r]) return;
+  const double s = scale[(size_t)r * sstride];
+  const size_t e0 = (size_t)blockIdx.x * NT * EPT + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = e0 + (size_t)k * NT;
+    if (e < n) {
+      const double2 v = ld<double, SX>(X + (size_t)r * x_rs + e);
+      st<SY, double>(Y + (size_t)r * y_rs + e, make_double2(s * v.x, s * v.y));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Givens / least squares
+__global__ void __launch_bounds__(64)
+k_givens(const double2* __restrict__ h1, const double2* __restrict__ h2, int ldh, double hsign,
+         const double* __restrict__ partn,
+         int nblk, GmresState* __restrict__ state, double2* __restrict__ Rm, double* __restrict__ cs,
+         double2* __restrict__ sn, double2* __restrict__ g, double2* __restrict__ y, int m, int* __restrict__ live,
+         const int* __restrict__ active) {
+  const int r = blockIdx.x;
+  if (!live[r] || (active && !active[r])) return;
+  double s2 = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) s2 += partn[(size_t)r * nblk + b];
+  s2 = wave_sum(s2);
+  if (threadIdx.x != 0) return;
+  GmresState S = state[r];
+  if (S.done) return;
+  const int j = S.j;
+  const int ld = m + 1;
+  double2* R = Rm + (size_t)r * ld * m;
+  double2* gr = g + (size_t)r * ld;
+  double* csr = cs + (size_t)r * m;
+  double2* snr = sn + (size_t)r * m;
+  const double beta = sqrt(s2);
+  for (int i = 0; i <= j; ++i) {
+    const double2 a = h1[(size_t)r * ldh + i];
+    const double2 b = h2 ? h2[(size_t)r * ldh + i] : make_double2(0.0, 0.0);
+    R[i + (size_t)j * ld] = make_double2(hsign * (a.x + b.x), hsign * (a.y + b.y));
+  }
+  for (int i = 0; i < j; ++i) {
+    const double c = csr[i];
+    const double2 s = snr[i];
+    const double2 a = R[i + (size_t)j * ld], b = R[i + 1 + (size_t)j * ld];
+    const double2 sb = zmul(s, b);
+    const double2 sa = zcmul(s, a);  // conj(s) * a
+    R[i + (size_t)j * ld] = make_double2(c * a.x + sb.x, c * a.y + sb.y);
+    R[i + 1 + (size_t)j * ld] = make_double2(c * b.x - sa.x, c * b.y - sa.y);
+  }
+  const double2 a = R[j + (size_t)j * ld];
+  const double absa = hypot(a.x, a.y);
+  const double rho = hypot(absa, beta);
+  double c;
+  double2 s;
+  if (absa > 0.0) {
+    c = absa / rho;
+    s = make_double2(a.x / absa * beta / rho, a.y / absa * beta / rho);
+    R[j + (size_t)j * ld] = make_double2(a.x / absa * rho, a.y / absa * rho);
+  } else {
+    c = 0.0;
+    s = make_double2(1.0, 0.0);
+    R[j + (size_t)j * ld] = make_double2(beta, 0.0);
+  }
+  csr[j] = c;
+  snr[j] = s;
+  const double2 gj = gr[j];
+  gr[j] = make_double2(c * gj.x, c * gj.y);
+  const double2 sg = zcmul(s, gj);  // conj(s) * g_j
+  gr[j + 1] = make_double2(-sg.x, -sg.y);
+  const double resid = hypot(gr[j + 1].x, gr[j + 1].y);
+  const int j1 = j + 1;
+  const bool fin = isfinite(resid) && isfinite(rho) && rho > 0.0;
+  S.j = j1;
+  S.resid = resid;
+  S.invbeta = (beta > 0.0 && fin) ? 1.0 / beta : 0.0;
+  if (!fin) S.breakdown = 1;
+  if (!fin || resid <= S.target || j1 >= m) {
+    S.done = 1;
+    live[r] = 0;
+    double2* yr = y + (size_t)r * m;
+    if (fin) {
+      for (int i = j1 - 1; i >= 0; --i) {
+        double2 acc = gr[i];
+        for (int l = i + 1; l < j1; ++l) {
+          const double2 p = zmul(R[i + (size_t)l * ld], yr[l]);
+          acc.x -= p.x;
+          acc.y -= p.y;
+        }
+        const double2 d = R[i + (size_t)i * ld];
+        const double dd = d.x * d.x + d.y * d.y;
+        yr[i] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+      }
+    } else {
+      for (int i = 0; i < j1; ++i) yr[i] = make_double2(0.0, 0.0);
+    }
+  }
+  state[r] = S;
+}
+
+// ---------------------------------------------------------------- launchers
+template <class SA, class SB>
+hipError_t launch_mdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const int* nv_dev, const c2<SB>* B,
+                       size_t b_rs, size_t n, int nrhs, double2* part, const int* live, hipStream_t st) {
+  if (nrhs <= 0 || nv <= 0) return hipSuccess;
+  dim3 grid(blas_blocks(n), nrhs);
+  hipLaunchKernelGGL((k_mdot<SA, SB>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, nv_dev, B, b_rs, n, part, live);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double2* part, int nv, int nblk, int nrhs, double sign, const double2* C,
+                         double2* out, const int* live, hipStream_t st) {
+  if (nrhs <= 0 || nv <= 0) return hipSuccess;
+  if (nv > kMaxReduceNv) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce, dim3(nrhs), dim3(NT), 0, st, part, nv, nblk, sign, C, out, live);
+  return hipGetLastError();
+}
+
+template <class SA, class SX, class SY>
+hipError_t launch_maxpy(int mode, const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const int* nv_dev,
+                        const double2* coef, int ldc, const c2<SX>* X, size_t x_rs, double alpha, c2<SY>* Y,
+                        size_t y_rs, double beta, size_t n, int nrhs, double2* part, double* partn,
+                        const int* live, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  dim3 grid(blas_blocks(n), nrhs);
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL((k_maxpy<SA, SX, SY, 0>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, nv_dev, coef, ldc, X,
+                         x_rs, alpha, Y, y_rs, beta, n, part, partn, live);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_maxpy<SA, SX, SY, 1>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, nv_dev, coef, ldc, X,
+                         x_rs, alpha, Y, y_rs, beta, n, part, partn, live);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_maxpy<SA, SX, SY, 2>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, nv_dev, coef, ldc, X,
+                         x_rs, alpha, Y, y_rs, beta, n, part, partn, live);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_norm2(const c2<S>* X, size_t x_rs, size_t n, int nrhs, double* partn, const int* live,
+                        hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  dim3 grid(blas_blocks(n), nrhs);
+  hipLaunchKernelGGL((k_norm2<S>), grid, dim3(NT), 0, st, X, x_rs, n, partn, live);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_norm(const double* partn, int nblk, int nrhs, double* out, const int* live,
+                              hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_norm, dim3(nrhs), dim3(64), 0, st, partn, nblk, out, live);
+  return hipGetLastError();
+}
+
+template <class SX, class SY>
+hipError_t launch_scale(const c2<SX>* X, size_t x_rs, c2<SY>* Y, size_t y_rs, const double* scale, int sstride,
+                        size_t n, int nrhs, const int* live, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  dim3 grid(blas_blocks(n), nrhs);
+  hipLaunchKernelGGL((k_scale<SX, SY>), grid, dim3(NT), 0, st, X, x_rs, Y, y_rs, scale, sstride, n, live);
+  return hipGetLastError();
+}
+
+hipError_t launch_givens(const double2* h1, const double2* h2, int ldh, double hsign, const double* partn,
+                         int nblk, GmresState* state, double2* R, double* cs, double2* sn, double2* g, double2* y, int m,
+                         int nrhs, int* live, const int* active, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_givens, dim3(nrhs), dim3(64), 0, st, h1, h2, ldh, hsign, partn, nblk, state, R, cs, sn, g, y, m,
+                     live, active);
+  return hipGetLastError();
+}
+
+// explicit instantiations (basis / vector precisions used by the solver)
+#define DIE_INST_MDOT(SA, SB)                                                                              \
+  template hipError_t launch_mdot<SA, SB>(const c2<SA>*, size_t, size_t, int, const int*, const c2<SB>*,   \
+                                          size_t, size_t, int, double2*, const int*, hipStream_t);
+DIE_INST_MDOT(double, double)
+DIE_INST_MDOT(float, float)
+DIE_INST_MDOT(double, float)
+#define DIE_INST_MAXPY(SA, SX, SY)                                                                          \
+  template hipError_t launch_maxpy<SA, SX, SY>(int, const c2<SA>*, size_t, size_t, int, const int*,          \
+                                               const double2*, int, const c2<SX>*, size_t, double, c2<SY>*,  \
+                                               size_t, double, size_t, int, double2*, double*, const int*,   \
+                                               hipStream_t);
+DIE_INST_MAXPY(double, double, double)
+DIE_INST_MAXPY(float, float, float)
+DIE_INST_MAXPY(double, float, float)
+DIE_INST_MAXPY(double, float, double)
+DIE_INST_MAXPY(float, float, double)
+template hipError_t launch_norm2<double>(const double2*, size_t, size_t, int, double*, const int*, hipStream_t);
+template hipError_t launch_norm2<float>(const float2*, size_t, size_t, int, double*, const int*, hipStream_t);
+#define DIE_INST_SCALE(SX, SY)                                                                              \
+  template hipError_t launch_scale<SX, SY>(const c2<SX>*, size_t, c2<SY>*, size_t, const double*, int,       \
+                                           size_t, int, const int*, hipStream_t);
+DIE_INST_SCALE(double, double)
+DIE_INST_SCALE(float, float)
+DIE_INST_SCALE(double, float)
+DIE_INST_SCALE(float, double)
+
+}  // namespace die

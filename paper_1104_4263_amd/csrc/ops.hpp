@@ -1,0 +1,106 @@
+// Internal launch interface between the host runtime and the HIP kernels.
+#pragma once
+#include "common.hpp"
+
+namespace die {
+
+// ---------------------------------------------------------------- FFT passes
+// Twiddle tables exp(-2 pi i j / 4096) for the current device (created on first use).
+hipError_t fft_tables(const double2** tw64, const float2** tw32);
+
+// Pass 1.  For every set s (s = rhs * sets_per_rhs + component) and row y < nrows:
+// W[s][x][y] = FFT_N( pad_N( chi[y][:] * x_in[s][y][:] ) )[x], x < N = 2^logn
+// (chi may be NULL).  x_in rows have nx <= N entries; W is transposed ([N][nrows]).
+template <class T, class S>
+hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x_in, const c2<T>* chi, c2<T>* W,
+                           int nx, int nrows, int nsets, int sets_per_rhs, const int* live,
+                           hipStream_t st);
+
+// Pass 2.  For every rhs r and column x < ncols of W[r][c][x][0:nrows] (c = 0, 1):
+// FFT_N over y (zero padded), 2x2 multiply by sym[x][ky][{11,12,22}], inverse FFT_N,
+// keep y < nrows; in place.
+template <class T>
+hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
+                              const int* live, hipStream_t st);
+
+// Pass 3.  y_out[s][y][x] = u[s][y][x] - IFFT_N(W[s][:][y])[x] for x < nx.
+template <class T, class S>
+hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y_out, int nx,
+                               int nrows, int nsets, int sets_per_rhs, const int* live,
+                               hipStream_t st);
+
+// Full-length FFT along the contiguous axis of W[nsets][ncols][N], in place.
+template <class T>
+hipError_t launch_cols_plain(int logn, bool inverse, c2<T>* W, int ncols, int nsets, hipStream_t st);
+
+// out[b][j][i] = in[b][i][j] for in of shape [nb][rows][cols].
+template <class T>
+hipError_t launch_transpose(const c2<T>* in, c2<T>* out, int rows, int cols, int nb, hipStream_t st);
+
+// sym64[(x * py + ky) * 3 + a] = scale * W[a][x][ky]; sym32 the rounded copy.
+hipError_t launch_pack_symbol(const double2* W, double2* sym64, float2* sym32, int px, int py,
+                              double scale, hipStream_t st);
+
+// ------------------------------------------------------------- Krylov BLAS-1
+constexpr int kBlasThreads = 256;
+constexpr int kBlasEpt = 4;
+inline int blas_blocks(size_t n) {
+  return (int)((n + (size_t)kBlasThreads * kBlasEpt - 1) / ((size_t)kBlasThreads * kBlasEpt));
+}
+
+// part[(r * nv + i) * nblk + b] = sum over block b of conj(A_i,r[e]) * B_r[e],
+// A_i,r = A + i * a_vs + r * a_rs, B_r = B + r * b_rs, e < n.  nv_r = nv_dev ? nv_dev[r] : nv.
+template <class SA, class SB>
+hipError_t launch_mdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const int* nv_dev,
+                       const c2<SB>* B, size_t b_rs, size_t n, int nrhs, double2* part,
+                       const int* live, hipStream_t st);
+
+// out[r * nv + i] = sign * sum_b part[(r * nv + i) * nblk + b]; if C (nv x nv, row-major,
+// shared by all r) is given, out[r] is replaced by C * out[r].
+hipError_t launch_reduce(const double2* part, int nv, int nblk, int nrhs, double sign,
+                         const double2* C, double2* out, const int* live, hipStream_t st);
+
+// Y_r = beta * Y_r + alpha * X_r + sum_{i < nv_r} coef[r * ldc + i] * A_i,r   (X may be NULL,
+// X may alias Y).  MODE 0: nothing else; 1: also part = partial dots conj(A_i) . Y_new (CGS2
+// second pass, nv_r vectors); 2: also partn[r * nblk + b] = partial ||Y_new||^2.
+template <class SA, class SX, class SY>
+hipError_t launch_maxpy(int mode, const c2<SA>* A, size_t a_vs, size_t a_rs, int nv,
+                        const int* nv_dev, const double2* coef, int ldc, const c2<SX>* X,
+                        size_t x_rs, double alpha, c2<SY>* Y, size_t y_rs, double beta, size_t n,
+                        int nrhs, double2* part, double* partn, const int* live, hipStream_t st);
+
+// partn[r * nblk + b] = partial ||X_r||^2.
+template <class S>
+hipError_t launch_norm2(const c2<S>* X, size_t x_rs, size_t n, int nrhs, double* partn,
+                        const int* live, hipStream_t st);
+
+// out[r] = sum_b partn[r * nblk + b]
+hipError_t launch_reduce_norm(const double* partn, int nblk, int nrhs, double* out,
+                              const int* live, hipStream_t st);
+
+// Y_r = s_r * X_r with s_r = scale[r * sstride] (double), converting precision.  X may alias Y.
+template <class SX, class SY>
+hipError_t launch_scale(const c2<SX>* X, size_t x_rs, c2<SY>* Y, size_t y_rs, const double* scale,
+                        int sstride, size_t n, int nrhs, const int* live, hipStream_t st);
+
+// ----------------------------------------------------------------- GMRES state
+struct GmresState {
+  int j;         // iterations done in the current cycle
+  int done;      // cycle finished (target reached, m iterations, breakdown)
+  int breakdown; // 1: non-finite value met
+  int pad;
+  double beta0;  // norm of the cycle's starting residual
+  double target; // cycle stops when |g_{j}| <= target
+  double resid;  // current residual estimate |g_j|
+  double invbeta;// 1 / h_{j+1,j} of the last column (0 if breakdown)
+};
+
+// One Arnoldi column per live rhs: h = hsign (h1 + h2) (two CGS passes, [r * ldh + i], i <= j),
+// beta = sqrt(sum_b partn[r * nblk + b]); Givens update of the (m+1) x m least-squares
+// problem kept in R (column-major, [r][m * (m + 1)]), cs, sn, g; when the cycle ends,
+// y = R^-1 g is written to y[r * m + i].  Clears live[r] when the cycle ends.
+hipError_t launch_givens(const double2* h1, const double2* h2, int ldh, double hsign, const double* partn,
+                         int nblk, GmresState* state, double2* R, double* cs, double2* sn, double2* g,
+                         double2* y, int m, int nrhs, int* live, const int* active, hipStream_t st);
+
+}  // namespace die

@@ -1,0 +1,31 @@
+"""CPU checks of the built library: it loads and exports every entry point
+declared in include/die_te.h (no compute call is made without a GPU)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1104_4263_amd import _lib
+
+
+def test_header_declares_the_boundary():
+    names = _lib.header_symbols()
+    for n in ("die_te_setup", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_destroy",
+              "die_te_last_error", "die_te_apply_deflation", "die_te_deflation_info", "die_te_fft2"):
+        assert n in names
+
+
+def test_library_loads_and_exports_every_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libdie_te.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in _lib.header_symbols():
+        assert hasattr(lib, n), n
+
+
+def test_last_error_without_gpu_calls():
+    lib = _lib.load()
+    assert lib.die_te_last_error() == b""
+    # a null context is rejected before any HIP call
+    assert lib.die_te_matvec(None, None, None, 1, 0, None) == _lib.DIE_E_INVALID
+    assert b"context" in lib.die_te_last_error()
