@@ -128,7 +128,7 @@ template <class T>
 int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const int* live, hipStream_t st) {
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * sizeof(c2<T>), st));
   c2<T>* W = c->work.as<c2<T>>();
-  DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi_of<T>(c, reg), W, c->nx, c->ny, 2 * nrhs, 2, live, st)));
+  DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi_of<T>(c, reg), W, c->nx, c->ny, nrhs, 2, 0, live, st)));
   DIE_HIP((die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, nrhs, live, st)));
   DIE_HIP((die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, 2 * nrhs, 2, live, st)));
   return DIE_OK;
@@ -655,7 +655,7 @@ int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, con
     if ((rc = c->sym64.alloc(3 * plane * sizeof(double2))) < 0 || (rc = c->sym32.alloc(3 * plane * sizeof(float2))) < 0)
       return guard(rc);
     hipError_t e1 = die::launch_rows_fwd<double, double>(c->lpx, false, E.as<double2>(), nullptr, W.as<double2>(), px,
-                                                         py, 3, 1, nullptr, st);
+                                                         py, 3, 1, 0, nullptr, st);
     hipError_t e2 = die::launch_cols_plain<double>(c->lpy, false, W.as<double2>(), px, 3, st);
     hipError_t e3 = die::launch_pack_symbol(W.as<double2>(), c->sym64.as<double2>(), c->sym32.as<float2>(), px, py,
                                             1.0 / ((double)px * (double)py), st);
@@ -749,13 +749,13 @@ int die_te_fft2(void* data, int px, int py, int batch, int inverse, int prec, vo
   if (prec == DIE_C128) {
     DIE_TRY(W.alloc(batch * plane * sizeof(double2)));
     DIE_HIP((die::launch_rows_fwd<double, double>(ilog2(px), inv, (const double2*)data, nullptr, W.as<double2>(), px,
-                                                  py, batch, 1, nullptr, st)));
+                                                  py, batch, 1, 0, nullptr, st)));
     DIE_HIP(die::launch_cols_plain<double>(ilog2(py), inv, W.as<double2>(), px, batch, st));
     DIE_HIP(die::launch_transpose<double>(W.as<double2>(), (double2*)data, px, py, batch, st));
   } else if (prec == DIE_C64) {
     DIE_TRY(W.alloc(batch * plane * sizeof(float2)));
     DIE_HIP((die::launch_rows_fwd<float, float>(ilog2(px), inv, (const float2*)data, nullptr, W.as<float2>(), px, py,
-                                                batch, 1, nullptr, st)));
+                                                batch, 1, 0, nullptr, st)));
     DIE_HIP(die::launch_cols_plain<float>(ilog2(py), inv, W.as<float2>(), px, batch, st));
     DIE_HIP(die::launch_transpose<float>(W.as<float2>(), (float2*)data, px, py, batch, st));
   } else {

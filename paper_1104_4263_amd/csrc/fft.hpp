@@ -1,30 +1,40 @@
-// LDS-resident Stockham FFT for power-of-two lengths up to 4096 (gfx950).
+// Register-resident Stockham FFT for power-of-two lengths up to 4096 (gfx950).
 //
-// A block holds NB transforms of length N = 2^LOGN in LDS (transform b starts
-// at buf + b * stride).  Every stage is a Stockham autosort step of radix
-// R = 2^LOGR: butterfly i of a transform reads x[i + q N/R] (q < R), multiplies
-// by w^(q k), k = i mod p (p = product of the radices already applied,
-// w = exp(-+2 pi i / (p R))), runs an in-register DFT of size R and writes
-// y[(i - k) R + k + q p].  The output is in natural order.  Stages are radix 8
-// (the first stage takes the remaining 1 or 2 bits), so a 4096-point transform
-// needs 4 LDS round trips.  Each thread owns E = 8 values per stage.
+// A block transforms NB arrays of length N = 2^LOGN (times NP arrays held in
+// lock step by the same threads, e.g. the two field components).  Each of the
+// NT = NB N / E threads owns E values.  A stage of radix R = 2^LR maps each
+// butterfly (b, i), i < N / R, to a thread; the butterfly reads x[b][i + q N/R]
+// (q < R), multiplies by w^(q k) with k = i mod p (p = product of the radices
+// already applied, w = exp(-+2 pi i / (p R))), does an in-register DFT of size
+// R and writes y[b][(i - k) R + k + q p].  The output is in natural order for
+// any sequence of radices.
+//
+// The first stage takes its inputs from registers (the caller loads them from
+// global memory) and the last stage leaves its outputs in registers, so a
+// transform costs only (stages - 1) exchanges through LDS.  Which thread owns
+// which butterfly is chosen per stage: "position fast" (consecutive lanes,
+// consecutive i of one array) or "array fast" (consecutive lanes, the same i of
+// consecutive arrays).  Switching between the two inside the transform turns a
+// row-major load into a transposed store (and back) at no extra LDS cost.
+// LDS rows are padded by one element per 256 bytes (gfx950 LDS: 64 banks of 4 bytes)
+// plus five elements per array, which spreads the stride-R accesses of the early
+// stages and the array-fast accesses over the banks.
 #pragma once
 #include "common.hpp"
 
 namespace die {
 
-__device__ __forceinline__ double2 twiddle_ld(const double2* t, int j) { return t[j]; }
-__device__ __forceinline__ float2 twiddle_ld(const float2* t, int j) { return t[j]; }
-
+// ------------------------------------------------------------------ small DFTs
 template <class T, bool INV> __device__ __forceinline__ void dft2(c2<T>* v) {
-  c2<T> a = v[0];
+  const c2<T> a = v[0];
   v[0] = cadd<T>(a, v[1]);
   v[1] = csub<T>(a, v[1]);
 }
 
 template <class T, bool INV> __device__ __forceinline__ void dft4(c2<T>* v) {
-  c2<T> a0 = cadd<T>(v[0], v[2]), a1 = csub<T>(v[0], v[2]);
-  c2<T> b0 = cadd<T>(v[1], v[3]), b1 = csub<T>(v[1], v[3]);
+  const c2<T> a0 = cadd<T>(v[0], v[2]), a1 = csub<T>(v[0], v[2]);
+  const c2<T> b0 = cadd<T>(v[1], v[3]);
+  c2<T> b1 = csub<T>(v[1], v[3]);
   b1 = INV ? mul_pi<T>(b1) : mul_mi<T>(b1);
   v[0] = cadd<T>(a0, b0);
   v[2] = csub<T>(a0, b0);
@@ -32,91 +42,187 @@ template <class T, bool INV> __device__ __forceinline__ void dft4(c2<T>* v) {
   v[3] = csub<T>(a1, b1);
 }
 
+// exp(-+2 pi i m / 16) for m < 16
+template <class T, bool INV> __device__ __forceinline__ c2<T> w16(int m) {
+  constexpr double C[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0,
+                            -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                            -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173, 0.0,
+                            0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  constexpr double S[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613, 1.0,
+                            0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0,
+                            -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                            -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+  return mk<T>((T)C[m], INV ? (T)S[m] : (T)-S[m]);
+}
+
 template <class T, bool INV> __device__ __forceinline__ void dft8(c2<T>* v) {
   c2<T> e[4] = {v[0], v[2], v[4], v[6]};
   c2<T> o[4] = {v[1], v[3], v[5], v[7]};
   dft4<T, INV>(e);
   dft4<T, INV>(o);
-  const T c = (T)0.70710678118654752440084436210485;
-  c2<T> t1 = INV ? mk<T>(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
-                 : mk<T>(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
-  c2<T> t2 = INV ? mul_pi<T>(o[2]) : mul_mi<T>(o[2]);
-  c2<T> t3 = INV ? mk<T>(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
-                 : mk<T>(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
-  v[0] = cadd<T>(e[0], o[0]);
-  v[4] = csub<T>(e[0], o[0]);
-  v[1] = cadd<T>(e[1], t1);
-  v[5] = csub<T>(e[1], t1);
-  v[2] = cadd<T>(e[2], t2);
-  v[6] = csub<T>(e[2], t2);
-  v[3] = cadd<T>(e[3], t3);
-  v[7] = csub<T>(e[3], t3);
-}
-
-template <class T, int LOGR, bool INV> __device__ __forceinline__ void dftR(c2<T>* v) {
-  if constexpr (LOGR == 1) dft2<T, INV>(v);
-  else if constexpr (LOGR == 2) dft4<T, INV>(v);
-  else dft8<T, INV>(v);
-}
-
-__host__ __device__ constexpr int fft_elems(int logn) { return logn >= 3 ? 8 : (1 << logn); }
-
-// One Stockham stage on all NB transforms of the block.  nthr threads each own
-// E/R butterflies.  `tw` is the exp(-2 pi i j / 4096) table.
-template <class T, int LOGN, int LOGR, int LOGP, int E, bool INV>
-__device__ __forceinline__ void fft_stage(c2<T>* buf, int stride, const c2<T>* __restrict__ tw,
-                                          int tid, int nthr) {
-  constexpr int R = 1 << LOGR;
-  constexpr int NR = 1 << (LOGN - LOGR);
-  constexpr int P = 1 << LOGP;
-  constexpr int NBF = E / R;  // butterflies per thread
-  c2<T> v[NBF][R];
-  int base[NBF], ii[NBF];
 #pragma unroll
-  for (int u = 0; u < NBF; ++u) {
-    const int t = tid + u * nthr;
-    base[u] = (t >> (LOGN - LOGR)) * stride;
-    ii[u] = t & (NR - 1);
-#pragma unroll
-    for (int q = 0; q < R; ++q) v[u][q] = buf[base[u] + ii[u] + q * NR];
+  for (int k = 0; k < 4; ++k) {
+    const c2<T> t = k == 0 ? o[0] : cmul<T>(o[k], w16<T, INV>(2 * k));
+    v[k] = cadd<T>(e[k], t);
+    v[k + 4] = csub<T>(e[k], t);
   }
-  __syncthreads();
+}
+
+template <class T, bool INV> __device__ __forceinline__ void dft16(c2<T>* v) {
+  c2<T> a[4][4];
 #pragma unroll
-  for (int u = 0; u < NBF; ++u) {
-    const int i = ii[u];
-    const int k = i & (P - 1);
-    if constexpr (LOGP > 0) {
+  for (int n2 = 0; n2 < 4; ++n2) {
+    c2<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+    dft4<T, INV>(t);
 #pragma unroll
-      for (int q = 1; q < R; ++q) {
-        c2<T> w = twiddle_ld(tw, (q * k) << (kLogTw - LOGP - LOGR));
-        if (INV) w.y = -w.y;
-        v[u][q] = cmul<T>(v[u][q], w);
+    for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = (n2 == 0 || k1 == 0) ? t[k1] : cmul<T>(t[k1], w16<T, INV>(n2 * k1));
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    c2<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4<T, INV>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+  }
+}
+
+template <class T, int LR, bool INV> __device__ __forceinline__ void dftR(c2<T>* v) {
+  if constexpr (LR == 1) dft2<T, INV>(v);
+  else if constexpr (LR == 2) dft4<T, INV>(v);
+  else if constexpr (LR == 3) dft8<T, INV>(v);
+  else dft16<T, INV>(v);
+}
+
+// Multiply v[q] (q = 1 .. R-1) by w^q, w = tw[base] (^* for INV), forming the powers
+// from the table entries w, w^2, w^4, w^8 with at most three products each.
+template <class T, int LR, bool INV>
+__device__ __forceinline__ void twiddle(c2<T>* v, const c2<T>* __restrict__ tw, int base) {
+  constexpr int R = 1 << LR;
+  c2<T> p[R];
+  p[1] = tw[base];
+  if constexpr (R > 2) p[2] = tw[(2 * base) & (kTw - 1)];
+  if constexpr (R > 4) p[4] = tw[(4 * base) & (kTw - 1)];
+  if constexpr (R > 8) p[8] = tw[(8 * base) & (kTw - 1)];
+#pragma unroll
+  for (int q = 3; q < R; ++q) {
+    if (q == 4 || q == 8) continue;
+    const int hi = q >= 8 ? 8 : (q >= 4 ? 4 : 2);
+    p[q] = cmul<T>(p[hi], p[q - hi]);
+  }
+#pragma unroll
+  for (int q = 1; q < R; ++q) {
+    c2<T> w = p[q];
+    if (INV) w.y = -w.y;
+    v[q] = cmul<T>(v[q], w);
+  }
+}
+
+enum : int { kPosFast = 0, kArrFast = 1 };
+
+__host__ __device__ constexpr int fft_pad_shift(int elem_bytes) { return elem_bytes == 8 ? 5 : 4; }
+__host__ __device__ constexpr int fft_row_stride(int n, int elem_bytes) {
+  return n + (n >> fft_pad_shift(elem_bytes)) + 5;
+}
+
+template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int MAPR> struct RegFft {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int LE = LOGE < LOGN ? LOGE : LOGN;
+  static constexpr int E = 1 << LE;
+  static constexpr int NT = NB * N / E;
+  static constexpr int REM = LOGN % LE;
+  static constexpr int NS = LOGN / LE + (REM ? 1 : 0);
+  static constexpr int ES = (int)sizeof(c2<T>);
+  static constexpr int PS = fft_pad_shift(ES);
+  static constexpr int LDB = fft_row_stride(N, ES);
+  static constexpr int LDS_ELEMS = NP * NB * LDB;
+
+  static constexpr int lr(int s) { return (REM && (REV ? s == NS - 1 : s == 0)) ? REM : LE; }
+  static constexpr int lp(int s) { return s == 0 ? 0 : lp(s - 1) + lr(s - 1); }
+  static constexpr int map(int s) { return s == 0 ? MAP0 : MAPR; }
+  static __device__ __forceinline__ int f(int j) { return j + (j >> PS); }
+
+  // butterfly (array b, index i) of thread t, slot u, in stage S
+  template <int S> static __device__ __forceinline__ void bi(int t, int u, int& b, int& i) {
+    constexpr int NR = N >> lr(S);
+    const int g = t + u * NT;
+    if constexpr (map(S) == kArrFast) {
+      b = g % NB;
+      i = g / NB;
+    } else {
+      b = g / NR;
+      i = g % NR;
+    }
+  }
+  // element position held in v[u * R + q] before stage 0 (inputs) / after the last stage (outputs)
+  static constexpr int R0 = 1 << lr(0);
+  static constexpr int RL = 1 << lr(NS - 1);
+  static __device__ __forceinline__ void in_pos(int t, int u, int q, int& b, int& pos) {
+    int i;
+    bi<0>(t, u, b, i);
+    pos = i + q * (N / R0);
+  }
+  static __device__ __forceinline__ void out_pos(int t, int u, int q, int& b, int& pos) {
+    int i;
+    bi<NS - 1>(t, u, b, i);
+    pos = i + q * (N / RL);
+  }
+
+  template <int S, bool INV>
+  static __device__ __forceinline__ void stage(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t) {
+    constexpr int LR = lr(S), R = 1 << LR, NR = N >> LR, LP = lp(S), P = 1 << LP, NU = E / R;
+    if constexpr (S > 0) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        int b, i;
+        bi<S>(t, u, b, i);
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int q = 0; q < R; ++q) v[p][u * R + q] = lds[(p * NB + b) * LDB + f(i + q * NR)];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      int b, i;
+      bi<S>(t, u, b, i);
+      const int k = i & (P - 1);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if constexpr (LP > 0) twiddle<T, LR, INV>(&v[p][u * R], tw, k << (kLogTw - LP - LR));
+        dftR<T, LR, INV>(&v[p][u * R]);
+      }
+      if constexpr (S < NS - 1) {
+        const int j = ((i - k) << LR) + k;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int q = 0; q < R; ++q) lds[(p * NB + b) * LDB + f(j + q * P)] = v[p][u * R + q];
       }
     }
-    dftR<T, LOGR, INV>(v[u]);
-    const int j = ((i - k) << LOGR) + k;
-#pragma unroll
-    for (int q = 0; q < R; ++q) buf[base[u] + j + q * P] = v[u][q];
+    if constexpr (S < NS - 1) __syncthreads();
   }
-  __syncthreads();
-}
 
-template <class T, int LOGN, int E, bool INV, int S, int LOGP> struct FftStages {
-  static __device__ __forceinline__ void run(c2<T>* buf, int stride, const c2<T>* __restrict__ tw,
-                                             int tid, int nthr) {
-    constexpr int REM = LOGN % 3;
-    constexpr int LOGR = (S == 0 && REM != 0) ? REM : 3;
-    fft_stage<T, LOGN, LOGR, LOGP, E, INV>(buf, stride, tw, tid, nthr);
-    if constexpr (LOGP + LOGR < LOGN)
-      FftStages<T, LOGN, E, INV, S + 1, LOGP + LOGR>::run(buf, stride, tw, tid, nthr);
+  template <int S, bool INV>
+  static __device__ __forceinline__ void stages(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t) {
+    stage<S, INV>(v, lds, tw, t);
+    if constexpr (S + 1 < NS) stages<S + 1, INV>(v, lds, tw, t);
+  }
+
+  // v holds the stage-0 inputs; on return it holds the outputs (see out_pos).
+  // LDS may be reused by the caller right after the call returns.
+  template <bool INV>
+  static __device__ __forceinline__ void run(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t) {
+    stages<0, INV>(v, lds, tw, t);
   }
 };
 
-// In-place FFT of all transforms of the block; buf must be filled and synchronised.
-template <class T, int LOGN, bool INV>
-__device__ __forceinline__ void lds_fft(c2<T>* buf, int stride, const c2<T>* __restrict__ tw, int tid,
-                                        int nthr) {
-  FftStages<T, LOGN, fft_elems(LOGN), INV, 0, 0>::run(buf, stride, tw, tid, nthr);
+// Physical block id -> logical block id such that each of the 8 XCDs (which
+// receive blocks round robin) processes a contiguous range of logical blocks.
+__device__ __forceinline__ int xcd_remap(int b, int total) {
+  const int q = total >> 3;
+  if (b >= (q << 3)) return b;
+  return (b & 7) * q + (b >> 3);
 }
 
 }  // namespace die

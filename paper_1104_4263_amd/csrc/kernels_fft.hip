@@ -13,144 +13,227 @@
 #include "fft.hpp"
 #include "ops.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <vector>
 
 namespace die {
 
+// Per-thread element count: radix 16 in FP32, radix 8 in FP64 (register budget of the
+// paired column pass).  Tile sizes keep the LDS exchange buffer near 72 KB so that two
+// blocks share a CU.
+template <class T> __host__ __device__ constexpr int fft_loge() { return sizeof(c2<T>) == 8 ? 4 : 3; }
+constexpr int kLdsBudget = 76000;
+template <class T> __host__ __device__ constexpr int fft_e(int logn) {
+  return 1 << (fft_loge<T>() < logn ? fft_loge<T>() : logn);
+}
 template <class T> __host__ __device__ constexpr int rows_ty(int logn) {
-  int n = 1 << logn, e = fft_elems(logn), ty = 16;
-  while (ty > 1 && (ty * (n + 1) * (int)sizeof(c2<T>) > 66000 || ty * n / e > 1024)) ty >>= 1;
+  int n = 1 << logn, es = (int)sizeof(c2<T>), ty = 16;
+  while (ty > 1 && (ty * fft_row_stride(n, es) * es > kLdsBudget || ty * n / fft_e<T>(logn) > 1024)) ty >>= 1;
   return ty;
 }
 template <class T> __host__ __device__ constexpr int rows_threads(int logn) {
-  return rows_ty<T>(logn) * (1 << logn) / fft_elems(logn);
+  return rows_ty<T>(logn) * (1 << logn) / fft_e<T>(logn);
 }
 template <class T> __host__ __device__ constexpr int cols_cx(int logn) {
-  int n = 1 << logn, e = fft_elems(logn), cx = 8;
-  while (cx > 1 && (2 * cx * (n + 1) * (int)sizeof(c2<T>) > 66000 || 2 * cx * n / e > 1024)) cx >>= 1;
+  int n = 1 << logn, es = (int)sizeof(c2<T>), cx = 16;
+  while (cx > 1 && (2 * cx * fft_row_stride(n, es) * es > kLdsBudget || cx * n / fft_e<T>(logn) > 1024)) cx >>= 1;
   return cx;
 }
 template <class T> __host__ __device__ constexpr int cols_threads(int logn) {
-  return 2 * cols_cx<T>(logn) * (1 << logn) / fft_elems(logn);
+  return cols_cx<T>(logn) * (1 << logn) / fft_e<T>(logn);
 }
 
 // ------------------------------------------------------------------ pass 1
+// Block: TY consecutive rows of the sets of `rb` right-hand sides (spr sets each).
+// Loads rows position-fast (coalesced), stores W[s][x][y] array-fast (TY-contiguous).
 template <class T, class S, int LOGN, bool INV>
 __global__ void __launch_bounds__(rows_threads<T>(LOGN))
 k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi, c2<T>* __restrict__ W,
-           const c2<T>* __restrict__ tw, int nx, int nrows, int sets_per_rhs,
+           const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr, int rb,
            const int* __restrict__ live) {
-  constexpr int N = 1 << LOGN, TY = rows_ty<T>(LOGN), NT = rows_threads<T>(LOGN), LD = N + 1;
-  __shared__ c2<T> buf[TY * LD];
-  const int s = blockIdx.y;
-  if (live && !live[s / sets_per_rhs]) return;
-  const int y0 = blockIdx.x * TY;
-  const c2<S>* xs = x + (size_t)s * nrows * nx;
-  for (int e = threadIdx.x; e < TY * N; e += NT) {
-    const int row = e >> LOGN, ix = e & (N - 1), yy = y0 + row;
-    c2<T> v = mk<T>(0, 0);
-    if (ix < nx && yy < nrows) {
-      v = ld<T, S>(xs + (size_t)yy * nx + ix);
-      if (chi) v = cmul<T>(v, chi[(size_t)yy * nx + ix]);
+  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(), 1, false, kPosFast, kArrFast>;
+  constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN);
+  __shared__ c2<T> lds[F::LDS_ELEMS];
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = L % ntiles, grp = L / ntiles;
+  const int y0 = tile * TY;
+  const int r1 = min(nrhs, (grp + 1) * rb);
+  for (int r = grp * rb; r < r1; ++r) {
+    if (live && !live[r]) continue;
+    for (int c = 0; c < spr; ++c) {
+      const size_t s = (size_t)r * spr + c;
+      const c2<S>* xs = x + s * nrows * nx;
+      // keep per-element address arithmetic inside the loop (hoisting it costs ~100 VGPRs)
+      int t = threadIdx.x;
+      asm volatile("" : "+v"(t));
+      c2<T> v[1][E];
+#pragma unroll
+      for (int u = 0; u < E / F::R0; ++u)
+#pragma unroll
+        for (int q = 0; q < F::R0; ++q) {
+          int b, pos;
+          F::in_pos(t, u, q, b, pos);
+          const int yy = y0 + b;
+          c2<T> a = mk<T>(0, 0);
+          if (pos < nx && yy < nrows) {
+            a = ld<T, S>(xs + (size_t)yy * nx + pos);
+            if (chi) a = cmul<T>(a, chi[(size_t)yy * nx + pos]);
+          }
+          v[0][u * F::R0 + q] = a;
+        }
+      F::template run<INV>(v, lds, tw, t);
+      c2<T>* Ws = W + s * N * nrows;
+#pragma unroll
+      for (int u = 0; u < E / F::RL; ++u)
+#pragma unroll
+        for (int q = 0; q < F::RL; ++q) {
+          int b, pos;
+          F::out_pos(t, u, q, b, pos);
+          const int yy = y0 + b;
+          if (yy < nrows) Ws[(size_t)pos * nrows + yy] = v[0][u * F::RL + q];
+        }
     }
-    buf[row * LD + ix] = v;
-  }
-  __syncthreads();
-  lds_fft<T, LOGN, INV>(buf, LD, tw, threadIdx.x, NT);
-  c2<T>* Ws = W + (size_t)s * N * nrows;
-  for (int e = threadIdx.x; e < TY * N; e += NT) {
-    const int row = e % TY, ix = e / TY, yy = y0 + row;
-    if (yy < nrows) Ws[(size_t)ix * nrows + yy] = buf[row * LD + ix];
   }
 }
 
 // ------------------------------------------------------------------ pass 2
+// Block: CX columns of one right-hand side, both components held by the same threads,
+// so the 2x2 symbol multiply runs in registers between the forward and the inverse
+// transform.  Logical blocks are ordered rhs-fastest: blocks sharing symbol columns run
+// on the same XCD at the same time.
 template <class T, int LOGN>
 __global__ void __launch_bounds__(cols_threads<T>(LOGN))
-k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>* __restrict__ tw,
-              int ncols, int nrows, const int* __restrict__ live) {
-  constexpr int N = 1 << LOGN, CX = cols_cx<T>(LOGN), NT = cols_threads<T>(LOGN), LD = N + 1;
-  __shared__ c2<T> buf[2 * CX * LD];
-  const int r = blockIdx.y;
+k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>* __restrict__ tw, int ncols,
+              int nrows, int nrhs, const int* __restrict__ live) {
+  constexpr int CX = cols_cx<T>(LOGN);
+  using F = RegFft<T, LOGN, CX, fft_loge<T>(), 2, false, kPosFast, kPosFast>;
+  using G = RegFft<T, LOGN, CX, fft_loge<T>(), 2, true, kPosFast, kPosFast>;
+  static_assert(G::R0 == F::RL, "inverse must start with the forward's last radix");
+  constexpr int N = F::N, E = F::E;
+  __shared__ c2<T> lds[F::LDS_ELEMS];
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = L % nrhs, x0 = (L / nrhs) * CX;
+  int t = threadIdx.x;
   if (live && !live[r]) return;
-  const int x0 = blockIdx.x * CX;
   c2<T>* Wr = W + (size_t)r * 2 * ncols * nrows;
-  // transform t = c * CX + cx holds column x0 + cx of component c
-  for (int e = threadIdx.x; e < 2 * CX * N; e += NT) {
-    const int t = e >> LOGN, ky = e & (N - 1), c = t / CX, xx = x0 + t % CX;
-    c2<T> v = mk<T>(0, 0);
-    if (ky < nrows && xx < ncols) v = Wr[((size_t)c * ncols + xx) * nrows + ky];
-    buf[t * LD + ky] = v;
-  }
-  __syncthreads();
-  lds_fft<T, LOGN, false>(buf, LD, tw, threadIdx.x, NT);
-  for (int e = threadIdx.x; e < CX * N; e += NT) {
-    const int cx = e >> LOGN, ky = e & (N - 1), xx = x0 + cx;
-    if (xx < ncols) {
-      const c2<T>* sp = sym + ((size_t)xx * N + ky) * 3;
-      const c2<T> s11 = sp[0], s12 = sp[1], s22 = sp[2];
-      const c2<T> a = buf[cx * LD + ky], b = buf[(CX + cx) * LD + ky];
-      buf[cx * LD + ky] = cadd<T>(cmul<T>(s11, a), cmul<T>(s12, b));
-      buf[(CX + cx) * LD + ky] = cadd<T>(cmul<T>(s12, a), cmul<T>(s22, b));
+  c2<T> v[2][E];
+#pragma unroll
+  for (int u = 0; u < E / F::R0; ++u)
+#pragma unroll
+    for (int q = 0; q < F::R0; ++q) {
+      int b, pos;
+      F::in_pos(t, u, q, b, pos);
+      const int xx = x0 + b, e = u * F::R0 + q;
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        v[c][e] = (xx < ncols && pos < nrows) ? Wr[((size_t)c * ncols + xx) * nrows + pos] : mk<T>(0, 0);
     }
-  }
-  __syncthreads();
-  lds_fft<T, LOGN, true>(buf, LD, tw, threadIdx.x, NT);
-  for (int e = threadIdx.x; e < 2 * CX * N; e += NT) {
-    const int t = e >> LOGN, ky = e & (N - 1), c = t / CX, xx = x0 + t % CX;
-    if (ky < nrows && xx < ncols) Wr[((size_t)c * ncols + xx) * nrows + ky] = buf[t * LD + ky];
-  }
+  F::template run<false>(v, lds, tw, t);
+  asm volatile("" : "+v"(t));  // per-phase address arithmetic (hoisting it costs VGPRs)
+#pragma unroll
+  for (int u = 0; u < E / F::RL; ++u)
+#pragma unroll
+    for (int q = 0; q < F::RL; ++q) {
+      int b, pos;
+      F::out_pos(t, u, q, b, pos);
+      const int xx = x0 + b, e = u * F::RL + q;
+      if (xx < ncols) {
+        const c2<T>* sp = sym + ((size_t)xx * N + pos) * 3;
+        const c2<T> s11 = sp[0], s12 = sp[1], s22 = sp[2];
+        const c2<T> a = v[0][e], bb = v[1][e];
+        v[0][e] = cadd<T>(cmul<T>(s11, a), cmul<T>(s12, bb));
+        v[1][e] = cadd<T>(cmul<T>(s12, a), cmul<T>(s22, bb));
+      }
+    }
+  G::template run<true>(v, lds, tw, t);
+  asm volatile("" : "+v"(t));
+#pragma unroll
+  for (int u = 0; u < E / G::RL; ++u)
+#pragma unroll
+    for (int q = 0; q < G::RL; ++q) {
+      int b, pos;
+      G::out_pos(t, u, q, b, pos);
+      const int xx = x0 + b, e = u * G::RL + q;
+      if (xx < ncols && pos < nrows) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) Wr[((size_t)c * ncols + xx) * nrows + pos] = v[c][e];
+      }
+    }
 }
 
-// Full-length transforms along the contiguous axis of W[set][col][0:N] (setup and diagnostics).
+// Full-length transforms along the contiguous axis of W[set][col][0:N], in place
+// (symbol setup and diagnostics).
 template <class T, int LOGN, bool INV>
 __global__ void __launch_bounds__(cols_threads<T>(LOGN))
-k_cols_plain(c2<T>* __restrict__ W, const c2<T>* __restrict__ tw, int ncols) {
-  constexpr int N = 1 << LOGN, NTR = 2 * cols_cx<T>(LOGN), NT = cols_threads<T>(LOGN), LD = N + 1;
-  __shared__ c2<T> buf[NTR * LD];
-  const int s = blockIdx.y;
-  const int x0 = blockIdx.x * NTR;
+k_cols_plain(c2<T>* __restrict__ W, const c2<T>* __restrict__ tw, int ncols, int ntiles) {
+  constexpr int NB = cols_cx<T>(LOGN);
+  using F = RegFft<T, LOGN, NB, fft_loge<T>(), 1, false, kPosFast, kPosFast>;
+  constexpr int N = F::N, E = F::E;
+  __shared__ c2<T> lds[F::LDS_ELEMS];
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = L / ntiles, x0 = (L % ntiles) * NB, t = threadIdx.x;
   c2<T>* Ws = W + (size_t)s * ncols * N;
-  for (int e = threadIdx.x; e < NTR * N; e += NT) {
-    const int t = e >> LOGN, ky = e & (N - 1), xx = x0 + t;
-    buf[t * LD + ky] = xx < ncols ? Ws[(size_t)xx * N + ky] : mk<T>(0, 0);
-  }
-  __syncthreads();
-  lds_fft<T, LOGN, INV>(buf, LD, tw, threadIdx.x, NT);
-  for (int e = threadIdx.x; e < NTR * N; e += NT) {
-    const int t = e >> LOGN, ky = e & (N - 1), xx = x0 + t;
-    if (xx < ncols) Ws[(size_t)xx * N + ky] = buf[t * LD + ky];
-  }
+  c2<T> v[1][E];
+#pragma unroll
+  for (int u = 0; u < E / F::R0; ++u)
+#pragma unroll
+    for (int q = 0; q < F::R0; ++q) {
+      int b, pos;
+      F::in_pos(t, u, q, b, pos);
+      v[0][u * F::R0 + q] = (x0 + b < ncols) ? Ws[(size_t)(x0 + b) * N + pos] : mk<T>(0, 0);
+    }
+  F::template run<INV>(v, lds, tw, t);
+#pragma unroll
+  for (int u = 0; u < E / F::RL; ++u)
+#pragma unroll
+    for (int q = 0; q < F::RL; ++q) {
+      int b, pos;
+      F::out_pos(t, u, q, b, pos);
+      if (x0 + b < ncols) Ws[(size_t)(x0 + b) * N + pos] = v[0][u * F::RL + q];
+    }
 }
 
 // ------------------------------------------------------------------ pass 3
+// Block: TY rows of one set.  Loads W[s][x][y] array-fast (TY-contiguous), stores
+// y = u - crop(IFFT) position-fast (coalesced).
 template <class T, class S, int LOGN>
 __global__ void __launch_bounds__(rows_threads<T>(LOGN))
 k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* __restrict__ y,
-               const c2<T>* __restrict__ tw, int nx, int nrows, int sets_per_rhs,
-               const int* __restrict__ live) {
-  constexpr int N = 1 << LOGN, TY = rows_ty<T>(LOGN), NT = rows_threads<T>(LOGN), LD = N + 1;
-  __shared__ c2<T> buf[TY * LD];
-  const int s = blockIdx.y;
-  if (live && !live[s / sets_per_rhs]) return;
-  const int y0 = blockIdx.x * TY;
+               const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int spr, const int* __restrict__ live) {
+  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(), 1, false, kArrFast, kPosFast>;
+  constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN);
+  __shared__ c2<T> lds[F::LDS_ELEMS];
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = L % ntiles, s = L / ntiles, t = threadIdx.x;
+  if (live && !live[s / spr]) return;
+  const int y0 = tile * TY;
   const c2<T>* Ws = W + (size_t)s * N * nrows;
-  for (int e = threadIdx.x; e < TY * N; e += NT) {
-    const int row = e % TY, ix = e / TY, yy = y0 + row;
-    buf[row * LD + ix] = yy < nrows ? Ws[(size_t)ix * nrows + yy] : mk<T>(0, 0);
-  }
-  __syncthreads();
-  lds_fft<T, LOGN, true>(buf, LD, tw, threadIdx.x, NT);
-  const size_t so = (size_t)s * nrows * nx;
-  for (int e = threadIdx.x; e < TY * N; e += NT) {
-    const int row = e >> LOGN, ix = e & (N - 1), yy = y0 + row;
-    if (ix < nx && yy < nrows) {
-      const size_t o = so + (size_t)yy * nx + ix;
-      st<S, T>(y + o, csub<T>(ld<T, S>(u + o), buf[row * LD + ix]));
+  c2<T> v[1][E];
+#pragma unroll
+  for (int uu = 0; uu < E / F::R0; ++uu)
+#pragma unroll
+    for (int q = 0; q < F::R0; ++q) {
+      int b, pos;
+      F::in_pos(t, uu, q, b, pos);
+      const int yy = y0 + b;
+      v[0][uu * F::R0 + q] = yy < nrows ? Ws[(size_t)pos * nrows + yy] : mk<T>(0, 0);
     }
-  }
+  F::template run<true>(v, lds, tw, t);
+  const size_t so = (size_t)s * nrows * nx;
+#pragma unroll
+  for (int uu = 0; uu < E / F::RL; ++uu)
+#pragma unroll
+    for (int q = 0; q < F::RL; ++q) {
+      int b, pos;
+      F::out_pos(t, uu, q, b, pos);
+      const int yy = y0 + b;
+      if (pos < nx && yy < nrows) {
+        const size_t o = so + (size_t)yy * nx + pos;
+        st<S, T>(y + o, csub<T>(ld<T, S>(u + o), v[0][uu * F::RL + q]));
+      }
+    }
 }
 
 // ------------------------------------------------------------------ helpers
@@ -244,22 +327,25 @@ template <> const float2* table_for<float>() {
 #define DIE_LOGN_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 
 template <class T, class S>
-hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* chi, c2<T>* W, int nx,
-                           int nrows, int nsets, int sets_per_rhs, const int* live, hipStream_t st) {
+hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* chi, c2<T>* W, int nx, int nrows,
+                           int nrhs, int spr, int rb, const int* live, hipStream_t st) {
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
-  if (nsets <= 0 || nrows <= 0) return hipSuccess;
+  if (nrhs <= 0 || nrows <= 0) return hipSuccess;
   switch (logn) {
-#define CASE(L)                                                                                    \
-  case L: {                                                                                        \
-    dim3 grid((nrows + rows_ty<T>(L) - 1) / rows_ty<T>(L), nsets);                                 \
-    if (inverse)                                                                                   \
-      hipLaunchKernelGGL((k_rows_fwd<T, S, L, true>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
-                         nx, nrows, sets_per_rhs, live);                                           \
-    else                                                                                           \
-      hipLaunchKernelGGL((k_rows_fwd<T, S, L, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
-                         nx, nrows, sets_per_rhs, live);                                           \
-    break;                                                                                         \
+#define CASE(L)                                                                                         \
+  case L: {                                                                                             \
+    const int ntiles = (nrows + rows_ty<T>(L) - 1) / rows_ty<T>(L);                                     \
+    if (rb <= 0) rb = std::max(1, std::min(nrhs, ntiles * nrhs / 2048));                                \
+    const int ngroups = (nrhs + rb - 1) / rb;                                                           \
+    dim3 grid((unsigned)(ntiles * ngroups));                                                            \
+    if (inverse)                                                                                        \
+      hipLaunchKernelGGL((k_rows_fwd<T, S, L, true>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, nx, \
+                         nrows, ntiles, nrhs, spr, rb, live);                                           \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_rows_fwd<T, S, L, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, nx, \
+                         nrows, ntiles, nrhs, spr, rb, live);                                           \
+    break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
 #undef CASE
@@ -276,12 +362,12 @@ hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, i
   if (!tw) return hipErrorNotInitialized;
   if (nrhs <= 0) return hipSuccess;
   switch (logn) {
-#define CASE(L)                                                                                    \
-  case L: {                                                                                        \
-    dim3 grid((ncols + cols_cx<T>(L) - 1) / cols_cx<T>(L), nrhs);                                  \
-    hipLaunchKernelGGL((k_cols_symbol<T, L>), grid, dim3(cols_threads<T>(L)), 0, st, W, sym, tw, ncols, \
-                       nrows, live);                                                               \
-    break;                                                                                         \
+#define CASE(L)                                                                                         \
+  case L: {                                                                                             \
+    dim3 grid((unsigned)(((ncols + cols_cx<T>(L) - 1) / cols_cx<T>(L)) * nrhs));                        \
+    hipLaunchKernelGGL((k_cols_symbol<T, L>), grid, dim3(cols_threads<T>(L)), 0, st, W, sym, tw, ncols, nrows, \
+                       nrhs, live);                                                                     \
+    break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
 #undef CASE
@@ -292,18 +378,19 @@ hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, i
 }
 
 template <class T, class S>
-hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y, int nx, int nrows,
-                               int nsets, int sets_per_rhs, const int* live, hipStream_t st) {
+hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y, int nx, int nrows, int nsets,
+                               int spr, const int* live, hipStream_t st) {
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nsets <= 0 || nrows <= 0) return hipSuccess;
   switch (logn) {
-#define CASE(L)                                                                                    \
-  case L: {                                                                                        \
-    dim3 grid((nrows + rows_ty<T>(L) - 1) / rows_ty<T>(L), nsets);                                 \
-    hipLaunchKernelGGL((k_rows_inv_sub<T, S, L>), grid, dim3(rows_threads<T>(L)), 0, st, W, u, y, tw, nx, \
-                       nrows, sets_per_rhs, live);                                                 \
-    break;                                                                                         \
+#define CASE(L)                                                                                         \
+  case L: {                                                                                             \
+    const int ntiles = (nrows + rows_ty<T>(L) - 1) / rows_ty<T>(L);                                     \
+    dim3 grid((unsigned)(ntiles * nsets));                                                              \
+    hipLaunchKernelGGL((k_rows_inv_sub<T, S, L>), grid, dim3(rows_threads<T>(L)), 0, st, W, u, y, tw, nx, nrows, \
+                       ntiles, spr, live);                                                              \
+    break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
 #undef CASE
@@ -319,15 +406,15 @@ hipError_t launch_cols_plain(int logn, bool inverse, c2<T>* W, int ncols, int ns
   if (!tw) return hipErrorNotInitialized;
   if (nsets <= 0 || ncols <= 0) return hipSuccess;
   switch (logn) {
-#define CASE(L)                                                                                    \
-  case L: {                                                                                        \
-    const int ntr = 2 * cols_cx<T>(L);                                                             \
-    dim3 grid((ncols + ntr - 1) / ntr, nsets);                                                     \
-    if (inverse)                                                                                   \
-      hipLaunchKernelGGL((k_cols_plain<T, L, true>), grid, dim3(cols_threads<T>(L)), 0, st, W, tw, ncols); \
-    else                                                                                           \
-      hipLaunchKernelGGL((k_cols_plain<T, L, false>), grid, dim3(cols_threads<T>(L)), 0, st, W, tw, ncols); \
-    break;                                                                                         \
+#define CASE(L)                                                                                         \
+  case L: {                                                                                             \
+    const int ntiles = (ncols + cols_cx<T>(L) - 1) / cols_cx<T>(L);                                     \
+    dim3 grid((unsigned)(ntiles * nsets));                                                              \
+    if (inverse)                                                                                        \
+      hipLaunchKernelGGL((k_cols_plain<T, L, true>), grid, dim3(cols_threads<T>(L)), 0, st, W, tw, ncols, ntiles); \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_cols_plain<T, L, false>), grid, dim3(cols_threads<T>(L)), 0, st, W, tw, ncols, ntiles); \
+    break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
 #undef CASE
@@ -355,9 +442,9 @@ hipError_t launch_pack_symbol(const double2* W, double2* s64, float2* s32, int p
 
 // explicit instantiations
 template hipError_t launch_rows_fwd<double, double>(int, bool, const double2*, const double2*, double2*, int,
-                                                    int, int, int, const int*, hipStream_t);
+                                                    int, int, int, int, const int*, hipStream_t);
 template hipError_t launch_rows_fwd<float, float>(int, bool, const float2*, const float2*, float2*, int, int,
-                                                  int, int, const int*, hipStream_t);
+                                                  int, int, int, const int*, hipStream_t);
 template hipError_t launch_cols_symbol<double>(int, double2*, const double2*, int, int, int, const int*,
                                                hipStream_t);
 template hipError_t launch_cols_symbol<float>(int, float2*, const float2*, int, int, int, const int*,

@@ -8,12 +8,13 @@ namespace die {
 // Twiddle tables exp(-2 pi i j / 4096) for the current device (created on first use).
 hipError_t fft_tables(const double2** tw64, const float2** tw32);
 
-// Pass 1.  For every set s (s = rhs * sets_per_rhs + component) and row y < nrows:
-// W[s][x][y] = FFT_N( pad_N( chi[y][:] * x_in[s][y][:] ) )[x], x < N = 2^logn
-// (chi may be NULL).  x_in rows have nx <= N entries; W is transposed ([N][nrows]).
+// Pass 1.  For every set s = r * spr + c (r < nrhs right-hand sides, c < spr components)
+// and row y < nrows: W[s][x][y] = FFT_N( pad_N( chi[y][:] * x_in[s][y][:] ) )[x],
+// x < N = 2^logn (chi may be NULL).  x_in rows have nx <= N entries; W is transposed
+// ([N][nrows]).  A block handles the spr sets of rb right-hand sides (chi loaded once).
 template <class T, class S>
 hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x_in, const c2<T>* chi, c2<T>* W,
-                           int nx, int nrows, int nsets, int sets_per_rhs, const int* live,
+                           int nx, int nrows, int nrhs, int spr, int rb, const int* live,
                            hipStream_t st);
 
 // Pass 2.  For every rhs r and column x < ncols of W[r][c][x][0:nrows] (c = 0, 1):
