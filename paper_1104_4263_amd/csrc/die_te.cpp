@@ -148,13 +148,13 @@ int apply_M(die_te_ctx* c, bool reg, const c2<T>* in, c2<T>* tmp, c2<T>* out, in
 }
 
 // Deflation projector y = P^-1 x = x + V (C (V^* x)) on basis-precision vectors (V in FP64).
+// counter: nrhs zeroed ints (left zeroed).
 template <class T>
-int apply_pinv(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, double2* part, double2* coef, const int* live,
-               hipStream_t st) {
+int apply_pinv(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, double2* part, double2* coef, int* counter,
+               const int* live, hipStream_t st) {
   const size_t n = c->nvec;
-  const int nblk = die::blas_blocks(n);
-  DIE_HIP((die::launch_mdot<double, T>(c->V.as<double2>(), n, 0, c->r, nullptr, x, n, n, nrhs, part, live, st)));
-  DIE_HIP(die::launch_reduce(part, c->r, nblk, nrhs, 1.0, c->Cdev.as<double2>(), coef, live, st));
+  DIE_HIP((die::launch_fdot<double, T>(c->V.as<double2>(), n, 0, c->r, x, n, n, nrhs, part, 1.0,
+                                       c->Cdev.as<double2>(), coef, counter, live, st)));
   DIE_HIP((die::launch_maxpy<double, T, T>(0, c->V.as<double2>(), n, 0, c->r, nullptr, coef, c->r, x, n, 1.0, y, n,
                                            0.0, n, nrhs, nullptr, nullptr, live, st)));
   return DIE_OK;
@@ -384,14 +384,15 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   const size_t vbytes = (size_t)nrhs * n * sizeof(c2<T>);
   const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
   const int nvmax = std::max(m + 1, c->r);
-  DBuf Q, Zb, Tb, Wb, Rs, Sd, part, partn, h1, h2, hd, Rm, cs, sn, g, y, state, live, active, nrm;
+  DBuf Q, Zb, Tb, Wb, Rs, Sd, part, partn, h1, h2, hd, Rm, cs, sn, g, y, state, live, active, nrm, cnt;
   DIE_TRY(Q.alloc((size_t)(m + 1) * vbytes));
   if (defl) DIE_TRY(Zb.alloc(vbytes));
   if (reg) DIE_TRY(Tb.alloc(vbytes));
   DIE_TRY(Wb.alloc(vbytes));
   DIE_TRY(Rs.alloc(dbytes));
   if (reg) DIE_TRY(Sd.alloc(dbytes));
-  DIE_TRY(part.alloc((size_t)nrhs * nvmax * nblk * sizeof(double2)));
+  DIE_TRY(part.alloc((size_t)nrhs * std::max((size_t)nvmax * nblk, die::gmres_part_elems(n, nvmax)) *
+                     sizeof(double2)));
   DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
   DIE_TRY(h1.alloc((size_t)nrhs * (m + 1) * sizeof(double2)));
   DIE_TRY(h2.alloc((size_t)nrhs * (m + 1) * sizeof(double2)));
@@ -405,6 +406,9 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   DIE_TRY(live.alloc((size_t)nrhs * sizeof(int)));
   DIE_TRY(active.alloc((size_t)nrhs * sizeof(int)));
   DIE_TRY(nrm.alloc((size_t)nrhs * sizeof(double)));
+  DIE_TRY(cnt.alloc((size_t)nrhs * sizeof(int)));
+  DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * sizeof(int), st));
+  int* dcnt = cnt.as<int>();
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * std::max(sizeof(c2<T>), sizeof(double2)), st));
 
   c2<T>* q = Q.as<c2<T>>();
@@ -426,6 +430,9 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   }
 
   std::vector<die::GmresState> hst(nrhs);
+  std::vector<int> jn(nrhs);
+  DBuf jd;
+  DIE_TRY(jd.alloc(nrhs * sizeof(int)));
   std::vector<double2> hg((size_t)nrhs * (m + 1));
   std::vector<double> inv0(nrhs);
   DBuf sc;
@@ -503,35 +510,37 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
       const c2<T>* qj = q + (size_t)j * vs;
       const c2<T>* z = qj;
       if (defl) {
-        DIE_TRY(apply_pinv<T>(c, qj, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dlive, st));
+        DIE_TRY(apply_pinv<T>(c, qj, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st));
         z = Zb.as<c2<T>>();
       }
       c2<T>* w = q + (size_t)(j + 1) * vs;
       DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st));
-      DIE_TRY(cgs2<T>(q, j + 1, nrhs, n, w, part.as<double2>(), h1.as<double2>(), h2.as<double2>(), j + 1,
-                      partn.as<double>(), dlive, st));
-      DIE_HIP(die::launch_givens(h1.as<double2>(), h2.as<double2>(), j + 1, -1.0, partn.as<double>(), nblk,
-                                 state.as<die::GmresState>(), Rm.as<double2>(), cs.as<double>(), sn.as<double2>(),
-                                 g.as<double2>(), y.as<double2>(), m, nrhs, dlive, dact, st));
+      // CGS2 against Q[0..j], FP64 Givens update, normalisation
+      const int nq = j + 1;
+      DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
+                                      h1.as<double2>(), dcnt, dlive, st)));
+      DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, nq, h1.as<double2>(), w, n, n, nrhs, dlive, st)));
+      DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
+                                      h2.as<double2>(), dcnt, dlive, st)));
+      DIE_HIP((die::launch_faxpy_givens<T, T>(q, vs, n, nq, h2.as<double2>(), h1.as<double2>(), w, n, n, nrhs,
+                                              part.as<double2>(), dcnt, state.as<die::GmresState>(), Rm.as<double2>(),
+                                              cs.as<double>(), sn.as<double2>(), g.as<double2>(), m, dlive, st)));
       DIE_HIP((die::launch_scale<T, T>(w, n, w, n, &state.as<die::GmresState>()->invbeta,
                                        (int)(sizeof(die::GmresState) / sizeof(double)), n, nrhs, dlive, st)));
     }
-    // ---- u += P^-1 (Q y)
+    // ---- least squares y = R^-1 g, then u += P^-1 (Q y)
+    DIE_HIP(die::launch_lsq(state.as<die::GmresState>(), Rm.as<double2>(), g.as<double2>(), y.as<double2>(), m, nrhs,
+                            dact, st));
     DIE_HIP(hipMemcpyAsync(hst.data(), state.p, nrhs * sizeof(die::GmresState), hipMemcpyDeviceToHost, st));
     DIE_HIP(hipStreamSynchronize(st));
-    std::vector<int> jn(nrhs);
     for (int r = 0; r < nrhs; ++r) jn[r] = act[r] ? hst[r].j : 0;
-    DBuf jd;
-    DIE_TRY(jd.alloc(nrhs * sizeof(int)));
     DIE_HIP(hipMemcpyAsync(jd.p, jn.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     c2<T>* t = Wb.as<c2<T>>();
     DIE_HIP((die::launch_maxpy<T, T, T>(0, q, vs, n, m, jd.as<int>(), y.as<double2>(), m, (const c2<T>*)nullptr, 0,
                                         0.0, t, n, 0.0, n, nrhs, nullptr, nullptr, dact, st)));
     if (defl) {
-      DIE_HIP((die::launch_mdot<double, T>(c->V.as<double2>(), n, 0, c->r, nullptr, t, n, n, nrhs, part.as<double2>(),
-                                           dact, st)));
-      DIE_HIP(die::launch_reduce(part.as<double2>(), c->r, nblk, nrhs, 1.0, c->Cdev.as<double2>(), hd.as<double2>(),
-                                 dact, st));
+      DIE_HIP((die::launch_fdot<double, T>(c->V.as<double2>(), n, 0, c->r, t, n, n, nrhs, part.as<double2>(), 1.0,
+                                           c->Cdev.as<double2>(), hd.as<double2>(), dcnt, dact, st)));
       DIE_HIP((die::launch_maxpy<double, T, double>(0, c->V.as<double2>(), n, 0, c->r, nullptr, hd.as<double2>(), c->r,
                                                     t, n, 1.0, u, n, 1.0, n, nrhs, nullptr, nullptr, dact, st)));
     } else {
@@ -713,11 +722,14 @@ int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void
   hipStream_t st = (hipStream_t)stream;
   const size_t n = c->nvec;
   const int nblk = die::blas_blocks(n);
-  DBuf part, coef;
-  DIE_TRY(part.alloc((size_t)nrhs * c->r * nblk * sizeof(double2)));
+  DBuf part, coef, cnt;
+  DIE_TRY(part.alloc((size_t)nrhs * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
+                     sizeof(double2)));
   DIE_TRY(coef.alloc((size_t)nrhs * c->r * sizeof(double2)));
-  DIE_TRY(apply_pinv<double>(c, (const double2*)x, (double2*)y, nrhs, part.as<double2>(), coef.as<double2>(), nullptr,
-                             st));
+  DIE_TRY(cnt.alloc((size_t)nrhs * sizeof(int)));
+  DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * sizeof(int), st));
+  DIE_TRY(apply_pinv<double>(c, (const double2*)x, (double2*)y, nrhs, part.as<double2>(), coef.as<double2>(),
+                             cnt.as<int>(), nullptr, st));
   DIE_HIP(hipStreamSynchronize(st));  // part/coef are freed on return
   return DIE_OK;
 }

@@ -6,6 +6,7 @@
 // deterministic run to run.
 #include "ops.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace die {
@@ -50,6 +51,22 @@ __device__ __forceinline__ double block_sum1(double v, double* red) {
   }
   __syncthreads();
   return s;
+}
+
+// Cross-block partial sums: the partials are written and read with agent-scope atomic
+// accesses, which are coherent across the XCDs' L2 caches without a cache write-back;
+// waiting for the stores to complete (vmcnt 0) orders them before the counter update.
+__device__ __forceinline__ void st_agent(double2* p, double2 v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 ld_agent(const double2* p) {
+  return make_double2(__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ bool arrive_last(int* counter, int total) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  return __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == total - 1;
 }
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
@@ -459,5 +476,304 @@ DIE_INST_SCALE(double, double)
 DIE_INST_SCALE(float, float)
 DIE_INST_SCALE(double, float)
 DIE_INST_SCALE(float, double)
+
+}  // namespace die
+
+// =====================================================================================
+// Fused Arnoldi kernels for the GMRES inner loop.  Each kernel reduces its own partial
+// sums: every block writes its partials, and the last block to finish (counted with a
+// device-scope atomic) sums them in a fixed order, so results stay deterministic.
+// =====================================================================================
+namespace die {
+namespace {
+
+constexpr int kFusedMaxNv = 512;
+
+}  // namespace
+
+// Dot products out[r][i] = sign * conj(A_i,r) . B_r (optionally times C), GEMV style:
+// one block per (chunk of kDotChunk elements, vector i, rhs r), one block reduction
+// each, so the reductions of different vectors run in parallel; the last block of a
+// rhs sums the chunk partials in a fixed order.
+constexpr int kDotEpt = 8;
+constexpr int kDotChunk = NT * kDotEpt;
+static_assert(kDotChunk == kDotChunkElems, "partial-buffer sizing assumes this chunk");
+
+template <class SA, class SB>
+__global__ void __launch_bounds__(NT)
+k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* __restrict__ B, size_t b_rs,
+       size_t n, double2* __restrict__ part, double sign, const double2* __restrict__ C, double2* __restrict__ out,
+       int* __restrict__ counter, const int* __restrict__ live) {
+  const int r = blockIdx.z;
+  if (live && !live[r]) return;
+  __shared__ double2 red[NW];
+  __shared__ double2 tmp[kFusedMaxNv];
+  __shared__ int s_last;
+  const int nchunk = gridDim.x, i = blockIdx.y, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const size_t base = (size_t)blockIdx.x * kDotChunk + t;
+  const c2<SA>* Ai = A + (size_t)i * a_vs + (size_t)r * a_rs;
+  const c2<SB>* Br = B + (size_t)r * b_rs;
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int k = 0; k < kDotEpt; ++k) {
+    const size_t e = base + (size_t)k * NT;
+    if (e < n) {
+      const double2 a = ld<double, SA>(Ai + e), b = ld<double, SB>(Br + e);
+      sx += a.x * b.x + a.y * b.y;
+      sy += a.x * b.y - a.y * b.x;
+    }
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  if (lane == 0) red[w] = make_double2(sx, sy);
+  __syncthreads();
+  if (t == 0) {
+    double2 s = red[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) { s.x += red[k].x; s.y += red[k].y; }
+    st_agent(part + ((size_t)r * nv + i) * nchunk + blockIdx.x, s);
+    s_last = arrive_last(&counter[r], nchunk * nv);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  for (int ii = w; ii < nv; ii += NW) {
+    const double2* p = part + ((size_t)r * nv + ii) * nchunk;
+    double ax = 0.0, ay = 0.0;
+    for (int c = lane; c < nchunk; c += 64) {
+      const double2 v = ld_agent(p + c);
+      ax += v.x;
+      ay += v.y;
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (lane == 0) tmp[ii] = make_double2(ax, ay);
+  }
+  __syncthreads();
+  for (int ii = t; ii < nv; ii += NT) {
+    double2 v = make_double2(sign * tmp[ii].x, sign * tmp[ii].y);
+    if (C) {
+      v = make_double2(0.0, 0.0);
+      for (int l = 0; l < nv; ++l) {
+        const double2 p = zmul(C[(size_t)ii * nv + l], tmp[l]);
+        v.x += sign * p.x;
+        v.y += sign * p.y;
+      }
+    }
+    out[(size_t)r * nv + ii] = v;
+  }
+  if (t == 0) counter[r] = 0;
+}
+
+// W_r += sum_i coef[r * nv + i] A_i,r (element parallel).  GIVENS: also beta = ||W_r||
+// (last block) and the Givens update of column j = nv - 1 with h = -(h1neg + coef).
+template <class SA, class SW, bool GIVENS>
+__global__ void __launch_bounds__(NT)
+k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const double2* __restrict__ coef,
+       c2<SW>* __restrict__ W, size_t w_rs, size_t n, int ept, double2* __restrict__ part, int* __restrict__ counter,
+       const int* __restrict__ live_in, const double2* __restrict__ h1, GmresState* __restrict__ state,
+       double2* __restrict__ Rm, double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g, int m,
+       int* __restrict__ live_out) {
+  const int r = blockIdx.y;
+  if (live_in && !live_in[r]) return;
+  __shared__ double red1[NW];
+  __shared__ int s_last;
+  const int nblk = gridDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  c2<SW>* Wr = W + (size_t)r * w_rs;
+  double s2 = 0.0;
+  for (int k = 0; k < ept; ++k) {
+    const size_t e = ((size_t)blockIdx.x * ept + k) * NT + t;
+    if (e >= n) break;
+    double2 y = ld<double, SW>(Wr + e);
+    for (int i = 0; i < nv; ++i) {
+      const double2 p = zmul(coef[(size_t)r * nv + i], ld<double, SA>(A + (size_t)i * a_vs + (size_t)r * a_rs + e));
+      y.x += p.x;
+      y.y += p.y;
+    }
+    st<SW, double>(Wr + e, y);
+    if constexpr (GIVENS) {
+      y = ld<double, SW>(Wr + e);
+      s2 += y.x * y.x + y.y * y.y;
+    }
+  }
+  if constexpr (GIVENS) {
+    s2 = wave_sum(s2);
+    if (lane == 0) red1[w] = s2;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) s += red1[k];
+      st_agent(part + (size_t)r * nblk + blockIdx.x, make_double2(s, 0.0));
+      s_last = arrive_last(&counter[r], nblk);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __shared__ double2 col[kFusedMaxNv + 1];
+    __shared__ double s_beta;
+    __shared__ GmresState S;
+    if (w == 0) {
+      double bs = 0.0;
+      for (int c = lane; c < nblk; c += 64) bs += ld_agent(part + (size_t)r * nblk + c).x;
+      bs = wave_sum(bs);
+      if (lane == 0) {
+        s_beta = sqrt(bs);
+        S = state[r];
+        counter[r] = 0;
+      }
+    }
+    __syncthreads();
+    if (S.done) return;
+    const int j = S.j, ld = m + 1;
+    double2* R = Rm + (size_t)r * ld * m;
+    double2* gr = g + (size_t)r * ld;
+    double* csr = cs + (size_t)r * m;
+    double2* snr = sn + (size_t)r * m;
+    for (int i = t; i <= j; i += NT) {
+      const double2 a = h1[(size_t)r * nv + i], b = coef[(size_t)r * nv + i];
+      col[i] = make_double2(-(a.x + b.x), -(a.y + b.y));
+    }
+    __syncthreads();
+    if (t == 0) {
+      // apply the previous rotations to the new column, then the new rotation
+      const double beta = s_beta;
+      for (int i = 0; i < j; ++i) {
+        const double c = csr[i];
+        const double2 sv = snr[i];
+        const double2 a = col[i], b = col[i + 1];
+        const double2 sb = zmul(sv, b), sa = zcmul(sv, a);
+        col[i] = make_double2(c * a.x + sb.x, c * a.y + sb.y);
+        col[i + 1] = make_double2(c * b.x - sa.x, c * b.y - sa.y);
+      }
+      const double2 a = col[j];
+      const double absa = hypot(a.x, a.y), rho = hypot(absa, beta);
+      double c;
+      double2 sv;
+      if (absa > 0.0) {
+        c = absa / rho;
+        sv = make_double2(a.x / absa * beta / rho, a.y / absa * beta / rho);
+        col[j] = make_double2(a.x / absa * rho, a.y / absa * rho);
+      } else {
+        c = 0.0;
+        sv = make_double2(1.0, 0.0);
+        col[j] = make_double2(beta, 0.0);
+      }
+      csr[j] = c;
+      snr[j] = sv;
+      const double2 gj = gr[j];
+      gr[j] = make_double2(c * gj.x, c * gj.y);
+      const double2 sgj = zcmul(sv, gj);
+      gr[j + 1] = make_double2(-sgj.x, -sgj.y);
+      const double resid = hypot(sgj.x, sgj.y);
+      const bool fin = isfinite(resid) && isfinite(rho) && rho > 0.0;
+      GmresState Sn = S;
+      Sn.j = j + 1;
+      Sn.resid = resid;
+      Sn.invbeta = (beta > 0.0 && fin) ? 1.0 / beta : 0.0;
+      if (!fin) Sn.breakdown = 1;
+      if (!fin || resid <= Sn.target || j + 1 >= m) {
+        Sn.done = 1;
+        live_out[r] = 0;
+      }
+      state[r] = Sn;
+    }
+    __syncthreads();
+    for (int i = t; i <= j; i += NT) R[i + (size_t)j * ld] = col[i];
+  }
+}
+
+// y_r = R_r^-1 g_r for the j_r leading columns (cycle end), one wave per rhs, column
+// oriented so each step is a parallel update.
+__global__ void __launch_bounds__(64)
+k_lsq(const GmresState* __restrict__ state, const double2* __restrict__ Rm, const double2* __restrict__ g,
+      double2* __restrict__ y, int m, const int* __restrict__ active) {
+  const int r = blockIdx.x;
+  if (active && !active[r]) return;
+  const GmresState S = state[r];
+  const int jj = S.j, ld = m + 1, lane = threadIdx.x;
+  const double2* R = Rm + (size_t)r * ld * m;
+  double2* yr = y + (size_t)r * m;
+  __shared__ double2 rhs[kFusedMaxNv];
+  for (int i = lane; i < jj; i += 64) rhs[i] = g[(size_t)r * ld + i];
+  __syncthreads();
+  for (int i = jj - 1; i >= 0; --i) {
+    const double2 d = R[i + (size_t)i * ld];
+    const double dd = d.x * d.x + d.y * d.y;
+    const double2 a = rhs[i];
+    const double2 yi = S.breakdown ? make_double2(0.0, 0.0)
+                                   : make_double2((a.x * d.x + a.y * d.y) / dd, (a.y * d.x - a.x * d.y) / dd);
+    if (lane == 0) yr[i] = yi;
+    for (int l = lane; l < i; l += 64) {
+      const double2 p = zmul(R[l + (size_t)i * ld], yi);
+      rhs[l].x -= p.x;
+      rhs[l].y -= p.y;
+    }
+    __syncthreads();
+  }
+}
+
+inline int axpy_ept(size_t n) {
+  size_t e = n / ((size_t)NT * 1024);
+  return (int)std::min<size_t>(16, std::max<size_t>(1, e));
+}
+
+template <class SA, class SB>
+hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* B, size_t b_rs, size_t n,
+                       int nrhs, double2* part, double sign, const double2* C, double2* out, int* counter,
+                       const int* live, hipStream_t st) {
+  if (nrhs <= 0 || nv <= 0) return hipSuccess;
+  if (nv > kFusedMaxNv) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((n + kDotChunk - 1) / kDotChunk), nv, nrhs);
+  hipLaunchKernelGGL((k_dots<SA, SB>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, B, b_rs, n, part, sign, C, out,
+                     counter, live);
+  return hipGetLastError();
+}
+
+template <class SA, class SW>
+hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, c2<SW>* W,
+                        size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st) {
+  if (nrhs <= 0 || nv <= 0) return hipSuccess;
+  const int ept = axpy_ept(n);
+  dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
+  hipLaunchKernelGGL((k_axpy<SA, SW, false>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, coef, W, w_rs, n, ept,
+                     nullptr, nullptr, live, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+  return hipGetLastError();
+}
+
+template <class SA, class SW>
+hipError_t launch_faxpy_givens(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* h2neg,
+                               const double2* h1neg, c2<SW>* W, size_t w_rs, size_t n, int nrhs, double2* part,
+                               int* counter, GmresState* state, double2* R, double* cs, double2* sn, double2* g,
+                               int m, int* live, hipStream_t st) {
+  if (nrhs <= 0 || nv <= 0) return hipSuccess;
+  const int ept = axpy_ept(n);
+  dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
+  hipLaunchKernelGGL((k_axpy<SA, SW, true>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, h2neg, W, w_rs, n, ept, part,
+                     counter, live, h1neg, state, R, cs, sn, g, m, live);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsq(const GmresState* state, const double2* R, const double2* g, double2* y, int m, int nrhs,
+                      const int* active, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  if (m > kFusedMaxNv) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lsq, dim3(nrhs), dim3(64), 0, st, state, R, g, y, m, active);
+  return hipGetLastError();
+}
+
+#define DIE_INST_FUSED(SA, SB)                                                                                    \
+  template hipError_t launch_fdot<SA, SB>(const c2<SA>*, size_t, size_t, int, const c2<SB>*, size_t, size_t, int, \
+                                          double2*, double, const double2*, double2*, int*, const int*, hipStream_t);
+DIE_INST_FUSED(double, double)
+DIE_INST_FUSED(float, float)
+DIE_INST_FUSED(double, float)
+#define DIE_INST_FAXPY(SA, SW)                                                                                     \
+  template hipError_t launch_faxpy<SA, SW>(const c2<SA>*, size_t, size_t, int, const double2*, c2<SW>*, size_t,     \
+                                           size_t, int, const int*, hipStream_t);                                   \
+  template hipError_t launch_faxpy_givens<SA, SW>(const c2<SA>*, size_t, size_t, int, const double2*,              \
+                                                  const double2*, c2<SW>*, size_t, size_t, int, double2*, int*,     \
+                                                  GmresState*, double2*, double*, double2*, double2*, int, int*,    \
+                                                  hipStream_t);
+DIE_INST_FAXPY(double, double)
+DIE_INST_FAXPY(float, float)
 
 }  // namespace die

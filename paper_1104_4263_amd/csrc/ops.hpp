@@ -104,4 +104,33 @@ hipError_t launch_givens(const double2* h1, const double2* h2, int ldh, double h
                          int nblk, GmresState* state, double2* R, double* cs, double2* sn, double2* g,
                          double2* y, int m, int nrhs, int* live, const int* active, hipStream_t st);
 
+// ---- Arnoldi kernels for the GMRES inner loop (reductions finished by the last block)
+// counter: nrhs ints, zero on entry, left zero on exit.  part: nrhs * max(nv * dot_chunks(n),
+// axpy blocks) partials.
+constexpr int kDotChunkElems = 2048;
+inline size_t gmres_part_elems(size_t n, int nv) {
+  const size_t dots = (size_t)nv * ((n + kDotChunkElems - 1) / kDotChunkElems);
+  const size_t axpy = (n + 255) / 256;
+  return dots > axpy ? dots : axpy;
+}
+// out[r * nv + i] = sign * sum_e conj(A_i,r[e]) B_r[e]   (times C when given).
+template <class SA, class SB>
+hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* B, size_t b_rs, size_t n,
+                       int nrhs, double2* part, double sign, const double2* C, double2* out, int* counter,
+                       const int* live, hipStream_t st);
+// W_r += sum_i coef[r * nv + i] A_i,r.
+template <class SA, class SW>
+hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, c2<SW>* W,
+                        size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st);
+// W_r += sum_i h2neg[r * nv + i] A_i,r; beta = ||W_r||; Givens update of column j = nv - 1 with
+// h = -(h1neg + h2neg); clears live[r] when the cycle of rhs r ends.
+template <class SA, class SW>
+hipError_t launch_faxpy_givens(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* h2neg,
+                               const double2* h1neg, c2<SW>* W, size_t w_rs, size_t n, int nrhs, double2* part,
+                               int* counter, GmresState* state, double2* R, double* cs, double2* sn, double2* g,
+                               int m, int* live, hipStream_t st);
+// y_r = R_r^-1 g_r over the j_r columns of the cycle.
+hipError_t launch_lsq(const GmresState* state, const double2* R, const double2* g, double2* y, int m, int nrhs,
+                      const int* active, hipStream_t st);
+
 }  // namespace die
