@@ -150,6 +150,19 @@ int die_te_deflation_info(die_te_ctx *ctx, int *r, void *ritz_values, void *V, v
  * Synchronises `stream`. */
 int die_te_fft2(void *data, int px, int py, int batch, int inverse, int prec, void *stream);
 
+/* Diagnostic timing.  die_te_profile(ctx, s) with s >= 1 clears the counters and starts
+ * bracketing, with hipEvents on the stream each launch is issued on, one in every s
+ * launches of each kind: operator products (the three FFT passes of one application of
+ * A or A_R: kind DIE_PROF_PRODUCT), Arnoldi dot-product kernels (DIE_PROF_DOTS) and
+ * Arnoldi multi-axpy kernels (DIE_PROF_AXPY) issued through the context;
+ * die_te_profile(ctx, 0) stops.
+ * die_te_profile_read returns the number of bracketed launches of `kind`, the number of
+ * launches of that kind issued while profiling was on (`seen`, may be NULL) and the total
+ * elapsed milliseconds of the bracketed ones (synchronises on the recorded events). */
+enum { DIE_PROF_PRODUCT = 0, DIE_PROF_DOTS = 1, DIE_PROF_AXPY = 2 };
+int die_te_profile(die_te_ctx *ctx, int enable);
+int die_te_profile_read(die_te_ctx *ctx, int kind, long long *launches, long long *seen, double *total_ms);
+
 /* Release everything the context owns. */
 int die_te_destroy(die_te_ctx *ctx);
 

@@ -16,6 +16,8 @@ from .api import (  # noqa: F401
     die_te_deflation_info,
     die_te_fft2,
     die_te_destroy,
+    die_te_profile,
+    die_te_profile_read,
     die_te_last_error,
 )
 from ._lib import DieTeError, load  # noqa: F401

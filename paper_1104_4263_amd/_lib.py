@@ -18,6 +18,9 @@ DIE_E_HIP = -4
 DIE_E_BREAKDOWN = -5
 DIE_C128 = 0
 DIE_C64 = 1
+DIE_PROF_PRODUCT = 0
+DIE_PROF_DOTS = 1
+DIE_PROF_AXPY = 2
 
 
 class DieTeGrid(ctypes.Structure):
@@ -70,10 +73,14 @@ def load() -> ctypes.CDLL:
     lib.die_te_deflation_info.argtypes = [vp, ctypes.POINTER(ip), vp, vp, vp, vp]
     lib.die_te_fft2.argtypes = [vp, i, i, i, i, i, vp]
     lib.die_te_destroy.argtypes = [vp]
+    lib.die_te_profile.argtypes = [vp, i]
+    lib.die_te_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                                        ctypes.POINTER(ctypes.c_double)]
     lib.die_te_last_error.argtypes = []
     lib.die_te_last_error.restype = ctypes.c_char_p
     for name in ("die_te_setup", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_apply_deflation",
-                 "die_te_deflation_info", "die_te_fft2", "die_te_destroy"):
+                 "die_te_deflation_info", "die_te_fft2", "die_te_destroy", "die_te_profile",
+                 "die_te_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

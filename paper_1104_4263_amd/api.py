@@ -95,6 +95,20 @@ def die_te_fft2(data: torch.Tensor, inverse: bool = False) -> None:
                              _prec(data), _stream()))
 
 
+def die_te_profile(ctx, every: int) -> None:
+    """every >= 1: bracket one launch in `every` of each kind with events; 0: stop."""
+    check(load().die_te_profile(ctx, int(every)))
+
+
+def die_te_profile_read(ctx, kind: int) -> tuple[int, int, float]:
+    """(bracketed launches, launches seen, total ms of the bracketed launches)."""
+    n = ctypes.c_longlong(0)
+    seen = ctypes.c_longlong(0)
+    ms = ctypes.c_double(0.0)
+    check(load().die_te_profile_read(ctx, int(kind), ctypes.byref(n), ctypes.byref(seen), ctypes.byref(ms)))
+    return int(n.value), int(seen.value), float(ms.value)
+
+
 def die_te_destroy(ctx) -> None:
     if ctx:
         check(load().die_te_destroy(ctx))
@@ -154,6 +168,12 @@ class Solver:
 
     def deflation_info(self):
         return die_te_deflation_info(self.ctx, self.nvec, device=self.device)
+
+    def profile(self, every: int) -> None:
+        die_te_profile(self.ctx, every)
+
+    def profile_read(self, kind: int) -> tuple[int, int, float]:
+        return die_te_profile_read(self.ctx, kind)
 
     def close(self):
         if self.ctx:

@@ -101,9 +101,48 @@ struct die_te_ctx {
   DBuf Cdev;  // [r][r] row-major complex128, C = T^-1 - I
   std::vector<cd> Chost, ritz;
   int eigs_restarts = 0, eigs_converged = 0;
+  // diagnostic timing: event pairs recorded around launches of each kind
+  bool prof_on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[3];
+  size_t prof_used[3] = {0, 0, 0};
+  unsigned long long prof_seen[3] = {0, 0, 0};
+  int prof_every = 1;
+  ~die_te_ctx() {
+    for (auto& v : prof_ev)
+      for (auto& pr : v) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+  }
 };
 
 namespace {
+
+// Brackets the launches of one kind with events on the launch stream while profiling is on.
+struct ProfScope {
+  die_te_ctx* c;
+  int kind;
+  hipStream_t st;
+  hipEvent_t end = nullptr;
+  ProfScope(die_te_ctx* cc, int k, hipStream_t s) : c(cc), kind(k), st(s) {
+    if (!c->prof_on) return;
+    if (c->prof_seen[kind]++ % c->prof_every) return;  // sample one launch in prof_every
+    auto& v = c->prof_ev[kind];
+    size_t& u = c->prof_used[kind];
+    if (u == v.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+      v.emplace_back(a, b);
+    }
+    (void)hipEventRecord(v[u].first, st);
+    end = v[u].second;
+    ++u;
+  }
+  ~ProfScope() {
+    if (end) (void)hipEventRecord(end, st);
+  }
+};
 
 // ------------------------------------------------------------------ operator products
 template <class T> const c2<T>* chi_of(const die_te_ctx* c, bool reg);
@@ -128,6 +167,7 @@ template <class T>
 int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const int* live, hipStream_t st) {
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * sizeof(c2<T>), st));
   c2<T>* W = c->work.as<c2<T>>();
+  ProfScope prof(c, DIE_PROF_PRODUCT, st);
   DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi_of<T>(c, reg), W, c->nx, c->ny, nrhs, 2, 0, live, st)));
   DIE_HIP((die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, nrhs, live, st)));
   DIE_HIP((die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, 2 * nrhs, 2, live, st)));
@@ -155,8 +195,7 @@ int apply_pinv(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, double2* part,
   const size_t n = c->nvec;
   DIE_HIP((die::launch_fdot<double, T>(c->V.as<double2>(), n, 0, c->r, x, n, n, nrhs, part, 1.0,
                                        c->Cdev.as<double2>(), coef, counter, live, st)));
-  DIE_HIP((die::launch_maxpy<double, T, T>(0, c->V.as<double2>(), n, 0, c->r, nullptr, coef, c->r, x, n, 1.0, y, n,
-                                           0.0, n, nrhs, nullptr, nullptr, live, st)));
+  DIE_HIP((die::launch_faxpy<double, T>(c->V.as<double2>(), n, 0, c->r, coef, x, y, n, n, nrhs, live, st)));
   return DIE_OK;
 }
 
@@ -406,8 +445,8 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   DIE_TRY(live.alloc((size_t)nrhs * sizeof(int)));
   DIE_TRY(active.alloc((size_t)nrhs * sizeof(int)));
   DIE_TRY(nrm.alloc((size_t)nrhs * sizeof(double)));
-  DIE_TRY(cnt.alloc((size_t)nrhs * sizeof(int)));
-  DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * sizeof(int), st));
+  DIE_TRY(cnt.alloc((size_t)nrhs * die::kCounterStride * sizeof(int)));
+  DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * die::kCounterStride * sizeof(int), st));
   int* dcnt = cnt.as<int>();
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * std::max(sizeof(c2<T>), sizeof(double2)), st));
 
@@ -517,14 +556,28 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
       DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st));
       // CGS2 against Q[0..j], FP64 Givens update, normalisation
       const int nq = j + 1;
-      DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
-                                      h1.as<double2>(), dcnt, dlive, st)));
-      DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, nq, h1.as<double2>(), w, n, n, nrhs, dlive, st)));
-      DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
-                                      h2.as<double2>(), dcnt, dlive, st)));
-      DIE_HIP((die::launch_faxpy_givens<T, T>(q, vs, n, nq, h2.as<double2>(), h1.as<double2>(), w, n, n, nrhs,
-                                              part.as<double2>(), dcnt, state.as<die::GmresState>(), Rm.as<double2>(),
-                                              cs.as<double>(), sn.as<double2>(), g.as<double2>(), m, dlive, st)));
+      {
+        ProfScope prof(c, DIE_PROF_DOTS, st);
+        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
+                                        h1.as<double2>(), dcnt, dlive, st)));
+      }
+      {
+        ProfScope prof(c, DIE_PROF_AXPY, st);
+        DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, nq, h1.as<double2>(), (const c2<T>*)nullptr, w, n, n, nrhs, dlive,
+                                         st)));
+      }
+      {
+        ProfScope prof(c, DIE_PROF_DOTS, st);
+        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
+                                        h2.as<double2>(), dcnt, dlive, st)));
+      }
+      {
+        ProfScope prof(c, DIE_PROF_AXPY, st);
+        DIE_HIP((die::launch_faxpy_givens<T, T>(q, vs, n, nq, h2.as<double2>(), h1.as<double2>(), w, n, n, nrhs,
+                                                part.as<double2>(), dcnt, state.as<die::GmresState>(),
+                                                Rm.as<double2>(), cs.as<double>(), sn.as<double2>(), g.as<double2>(),
+                                                m, dlive, st)));
+      }
       DIE_HIP((die::launch_scale<T, T>(w, n, w, n, &state.as<die::GmresState>()->invbeta,
                                        (int)(sizeof(die::GmresState) / sizeof(double)), n, nrhs, dlive, st)));
     }
@@ -726,8 +779,8 @@ int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void
   DIE_TRY(part.alloc((size_t)nrhs * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
                      sizeof(double2)));
   DIE_TRY(coef.alloc((size_t)nrhs * c->r * sizeof(double2)));
-  DIE_TRY(cnt.alloc((size_t)nrhs * sizeof(int)));
-  DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * sizeof(int), st));
+  DIE_TRY(cnt.alloc((size_t)nrhs * die::kCounterStride * sizeof(int)));
+  DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * die::kCounterStride * sizeof(int), st));
   DIE_TRY(apply_pinv<double>(c, (const double2*)x, (double2*)y, nrhs, part.as<double2>(), coef.as<double2>(),
                              cnt.as<int>(), nullptr, st));
   DIE_HIP(hipStreamSynchronize(st));  // part/coef are freed on return
@@ -774,6 +827,37 @@ int die_te_fft2(void* data, int px, int py, int batch, int inverse, int prec, vo
     return fail(DIE_E_INVALID, "prec must be DIE_C128 or DIE_C64");
   }
   DIE_HIP(hipStreamSynchronize(st));
+  return DIE_OK;
+}
+
+int die_te_profile(die_te_ctx* c, int enable) {
+  g_err.clear();
+  DIE_TRY(check_ctx(c));
+  c->prof_on = enable > 0;
+  if (enable > 0) {
+    c->prof_every = enable;
+    for (size_t& u : c->prof_used) u = 0;
+    for (auto& sn : c->prof_seen) sn = 0;
+  }
+  return DIE_OK;
+}
+
+int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long* seen, double* total_ms) {
+  g_err.clear();
+  DIE_TRY(check_ctx(c));
+  if (kind < 0 || kind > 2 || !launches || !total_ms) return fail(DIE_E_INVALID, "bad profile kind or null output");
+  if (seen) *seen = (long long)c->prof_seen[kind];
+  double tot = 0.0;
+  const size_t u = c->prof_used[kind];
+  for (size_t i = 0; i < u; ++i) {
+    auto& pr = c->prof_ev[kind][i];
+    DIE_HIP(hipEventSynchronize(pr.second));
+    float ms = 0.0f;
+    DIE_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  *launches = (long long)u;
+  *total_ms = tot;
   return DIE_OK;
 }
 

@@ -492,52 +492,76 @@ constexpr int kFusedMaxNv = 512;
 }  // namespace
 
 // Dot products out[r][i] = sign * conj(A_i,r) . B_r (optionally times C), GEMV style:
-// one block per (chunk of kDotChunk elements, vector i, rhs r), one block reduction
-// each, so the reductions of different vectors run in parallel; the last block of a
-// rhs sums the chunk partials in a fixed order.
+// one block per (chunk of kDotChunk elements, group of kDotG vectors, rhs r) with one
+// block reduction per vector.  Completion is counted per (rhs, vector group) and then
+// per rhs, so no counter sees more than max(chunks, groups) atomic increments; the
+// last block of a group sums its vectors' chunk partials in a fixed order, and when C
+// is given the last group applies it.  counter: [nrhs][kCounterStride] zeroed ints.
 constexpr int kDotEpt = 8;
 constexpr int kDotChunk = NT * kDotEpt;
+constexpr int kDotG = 4;
+constexpr int kNormGroup = 64;
 static_assert(kDotChunk == kDotChunkElems, "partial-buffer sizing assumes this chunk");
 
 template <class SA, class SB>
 __global__ void __launch_bounds__(NT)
 k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* __restrict__ B, size_t b_rs,
-       size_t n, double2* __restrict__ part, double sign, const double2* __restrict__ C, double2* __restrict__ out,
-       int* __restrict__ counter, const int* __restrict__ live) {
+       size_t n, double2* __restrict__ part, double sign, const double2* __restrict__ C, double2* __restrict__ raw,
+       double2* __restrict__ out, int* __restrict__ counter, const int* __restrict__ live) {
   const int r = blockIdx.z;
   if (live && !live[r]) return;
-  __shared__ double2 red[NW];
-  __shared__ double2 tmp[kFusedMaxNv];
+  __shared__ double2 red[NW][kDotG];
   __shared__ int s_last;
-  const int nchunk = gridDim.x, i = blockIdx.y, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int nchunk = gridDim.x, ngrp = gridDim.y, grp = blockIdx.y, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int i0 = grp * kDotG, gn = min(kDotG, nv - i0);
   const size_t base = (size_t)blockIdx.x * kDotChunk + t;
-  const c2<SA>* Ai = A + (size_t)i * a_vs + (size_t)r * a_rs;
   const c2<SB>* Br = B + (size_t)r * b_rs;
-  double sx = 0.0, sy = 0.0;
+  double2 b[kDotEpt];
 #pragma unroll
   for (int k = 0; k < kDotEpt; ++k) {
     const size_t e = base + (size_t)k * NT;
-    if (e < n) {
-      const double2 a = ld<double, SA>(Ai + e), b = ld<double, SB>(Br + e);
-      sx += a.x * b.x + a.y * b.y;
-      sy += a.x * b.y - a.y * b.x;
+    b[k] = e < n ? ld<double, SB>(Br + e) : make_double2(0.0, 0.0);
+  }
+  double sx[kDotG], sy[kDotG];
+#pragma unroll
+  for (int g = 0; g < kDotG; ++g) {
+    sx[g] = sy[g] = 0.0;
+    if (g < gn) {
+      const c2<SA>* Ai = A + (size_t)(i0 + g) * a_vs + (size_t)r * a_rs;
+#pragma unroll
+      for (int k = 0; k < kDotEpt; ++k) {
+        const size_t e = base + (size_t)k * NT;
+        if (e < n) {
+          const double2 a = ld<double, SA>(Ai + e);
+          sx[g] += a.x * b[k].x + a.y * b[k].y;
+          sy[g] += a.x * b[k].y - a.y * b[k].x;
+        }
+      }
     }
   }
-  sx = wave_sum(sx);
-  sy = wave_sum(sy);
-  if (lane == 0) red[w] = make_double2(sx, sy);
-  __syncthreads();
-  if (t == 0) {
-    double2 s = red[0];
 #pragma unroll
-    for (int k = 1; k < NW; ++k) { s.x += red[k].x; s.y += red[k].y; }
-    st_agent(part + ((size_t)r * nv + i) * nchunk + blockIdx.x, s);
-    s_last = arrive_last(&counter[r], nchunk * nv);
+  for (int g = 0; g < kDotG; ++g) {
+    sx[g] = wave_sum(sx[g]);
+    sy[g] = wave_sum(sy[g]);
   }
+  if (lane == 0)
+#pragma unroll
+    for (int g = 0; g < kDotG; ++g) red[w][g] = make_double2(sx[g], sy[g]);
+  __syncthreads();
+  int* cnt = counter + (size_t)r * kCounterStride;
+  if (t < gn) {
+    double2 s = red[0][t];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) { s.x += red[k][t].x; s.y += red[k][t].y; }
+    st_agent(part + ((size_t)r * nv + i0 + t) * nchunk + blockIdx.x, s);
+  }
+  if (t == 0) s_last = arrive_last(cnt + 1 + grp, nchunk);
   __syncthreads();
   if (!s_last) return;
-  for (int ii = w; ii < nv; ii += NW) {
-    const double2* p = part + ((size_t)r * nv + ii) * nchunk;
+  // last block of this vector group: sum the chunk partials of its vectors
+  double2* dst = C ? raw : out;
+  for (int g = w; g < gn; g += NW) {
+    const double2* p = part + ((size_t)r * nv + i0 + g) * nchunk;
     double ax = 0.0, ay = 0.0;
     for (int c = lane; c < nchunk; c += 64) {
       const double2 v = ld_agent(p + c);
@@ -546,22 +570,29 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<
     }
     ax = wave_sum(ax);
     ay = wave_sum(ay);
-    if (lane == 0) tmp[ii] = make_double2(ax, ay);
+    if (lane == 0) {
+      const double2 v = make_double2(sign * ax, sign * ay);
+      if (C) st_agent(dst + (size_t)r * nv + i0 + g, v);
+      else dst[(size_t)r * nv + i0 + g] = v;
+    }
   }
+  if (t == 0) cnt[1 + grp] = 0;
+  if (!C) return;
   __syncthreads();
+  if (t == 0) s_last = arrive_last(cnt, ngrp);
+  __syncthreads();
+  if (!s_last) return;
+  // last group: out = C raw
   for (int ii = t; ii < nv; ii += NT) {
-    double2 v = make_double2(sign * tmp[ii].x, sign * tmp[ii].y);
-    if (C) {
-      v = make_double2(0.0, 0.0);
-      for (int l = 0; l < nv; ++l) {
-        const double2 p = zmul(C[(size_t)ii * nv + l], tmp[l]);
-        v.x += sign * p.x;
-        v.y += sign * p.y;
-      }
+    double2 v = make_double2(0.0, 0.0);
+    for (int l = 0; l < nv; ++l) {
+      const double2 p = zmul(C[(size_t)ii * nv + l], ld_agent(raw + (size_t)r * nv + l));
+      v.x += p.x;
+      v.y += p.y;
     }
     out[(size_t)r * nv + ii] = v;
   }
-  if (t == 0) counter[r] = 0;
+  if (t == 0) cnt[0] = 0;
 }
 
 // W_r += sum_i coef[r * nv + i] A_i,r (element parallel).  GIVENS: also beta = ||W_r||
@@ -569,7 +600,7 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<
 template <class SA, class SW, bool GIVENS>
 __global__ void __launch_bounds__(NT)
 k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const double2* __restrict__ coef,
-       c2<SW>* __restrict__ W, size_t w_rs, size_t n, int ept, double2* __restrict__ part, int* __restrict__ counter,
+       const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, int ept, double2* __restrict__ part, int* __restrict__ counter,
        const int* __restrict__ live_in, const double2* __restrict__ h1, GmresState* __restrict__ state,
        double2* __restrict__ Rm, double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g, int m,
        int* __restrict__ live_out) {
@@ -579,11 +610,12 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const dou
   __shared__ int s_last;
   const int nblk = gridDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   c2<SW>* Wr = W + (size_t)r * w_rs;
+  const c2<SW>* Xr = X ? X + (size_t)r * w_rs : Wr;
   double s2 = 0.0;
   for (int k = 0; k < ept; ++k) {
     const size_t e = ((size_t)blockIdx.x * ept + k) * NT + t;
     if (e >= n) break;
-    double2 y = ld<double, SW>(Wr + e);
+    double2 y = ld<double, SW>(Xr + e);
     for (int i = 0; i < nv; ++i) {
       const double2 p = zmul(coef[(size_t)r * nv + i], ld<double, SA>(A + (size_t)i * a_vs + (size_t)r * a_rs + e));
       y.x += p.x;
@@ -604,7 +636,25 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const dou
 #pragma unroll
       for (int k = 0; k < NW; ++k) s += red1[k];
       st_agent(part + (size_t)r * nblk + blockIdx.x, make_double2(s, 0.0));
-      s_last = arrive_last(&counter[r], nblk);
+    }
+    // two-level completion count: groups of kNormGroup blocks, then the groups
+    int* cnt = counter + (size_t)r * kCounterStride;
+    const int grp = blockIdx.x / kNormGroup, ngrp = (nblk + kNormGroup - 1) / kNormGroup;
+    const int gsize = min(kNormGroup, nblk - grp * kNormGroup);
+    if (t == 0) s_last = arrive_last(cnt + 1 + grp, gsize);
+    __syncthreads();
+    if (!s_last) return;
+    double2* gpart = part + (size_t)gridDim.y * nblk;  // group sums after the block partials
+    if (w == 0) {
+      double gs = 0.0;
+      for (int c = grp * kNormGroup + lane; c < grp * kNormGroup + gsize; c += 64)
+        gs += ld_agent(part + (size_t)r * nblk + c).x;
+      gs = wave_sum(gs);
+      if (lane == 0) {
+        st_agent(gpart + (size_t)r * ngrp + grp, make_double2(gs, 0.0));
+        cnt[1 + grp] = 0;
+        s_last = arrive_last(cnt, ngrp);
+      }
     }
     __syncthreads();
     if (!s_last) return;
@@ -613,12 +663,12 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const dou
     __shared__ GmresState S;
     if (w == 0) {
       double bs = 0.0;
-      for (int c = lane; c < nblk; c += 64) bs += ld_agent(part + (size_t)r * nblk + c).x;
+      for (int c = lane; c < ngrp; c += 64) bs += ld_agent(gpart + (size_t)r * ngrp + c).x;
       bs = wave_sum(bs);
       if (lane == 0) {
         s_beta = sqrt(bs);
         S = state[r];
-        counter[r] = 0;
+        cnt[0] = 0;
       }
     }
     __syncthreads();
@@ -722,19 +772,21 @@ hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const 
                        const int* live, hipStream_t st) {
   if (nrhs <= 0 || nv <= 0) return hipSuccess;
   if (nv > kFusedMaxNv) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((n + kDotChunk - 1) / kDotChunk), nv, nrhs);
-  hipLaunchKernelGGL((k_dots<SA, SB>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, B, b_rs, n, part, sign, C, out,
+  const unsigned nchunk = (unsigned)((n + kDotChunk - 1) / kDotChunk);
+  dim3 grid(nchunk, (nv + kDotG - 1) / kDotG, nrhs);
+  double2* raw = part + (size_t)nrhs * nv * nchunk;  // C-path scratch after the partials
+  hipLaunchKernelGGL((k_dots<SA, SB>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, B, b_rs, n, part, sign, C, raw, out,
                      counter, live);
   return hipGetLastError();
 }
 
 template <class SA, class SW>
-hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, c2<SW>* W,
-                        size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st) {
-  if (nrhs <= 0 || nv <= 0) return hipSuccess;
+hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, const c2<SW>* X,
+                        c2<SW>* W, size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
   const int ept = axpy_ept(n);
   dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
-  hipLaunchKernelGGL((k_axpy<SA, SW, false>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, coef, W, w_rs, n, ept,
+  hipLaunchKernelGGL((k_axpy<SA, SW, false>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, coef, X, W, w_rs, n, ept,
                      nullptr, nullptr, live, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
   return hipGetLastError();
 }
@@ -747,8 +799,8 @@ hipError_t launch_faxpy_givens(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv
   if (nrhs <= 0 || nv <= 0) return hipSuccess;
   const int ept = axpy_ept(n);
   dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
-  hipLaunchKernelGGL((k_axpy<SA, SW, true>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, h2neg, W, w_rs, n, ept, part,
-                     counter, live, h1neg, state, R, cs, sn, g, m, live);
+  hipLaunchKernelGGL((k_axpy<SA, SW, true>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, h2neg, (const c2<SW>*)nullptr,
+                     W, w_rs, n, ept, part, counter, live, h1neg, state, R, cs, sn, g, m, live);
   return hipGetLastError();
 }
 
@@ -767,13 +819,15 @@ DIE_INST_FUSED(double, double)
 DIE_INST_FUSED(float, float)
 DIE_INST_FUSED(double, float)
 #define DIE_INST_FAXPY(SA, SW)                                                                                     \
-  template hipError_t launch_faxpy<SA, SW>(const c2<SA>*, size_t, size_t, int, const double2*, c2<SW>*, size_t,     \
-                                           size_t, int, const int*, hipStream_t);                                   \
+  template hipError_t launch_faxpy<SA, SW>(const c2<SA>*, size_t, size_t, int, const double2*, const c2<SW>*,      \
+                                           c2<SW>*, size_t, size_t, int, const int*, hipStream_t);                  \
   template hipError_t launch_faxpy_givens<SA, SW>(const c2<SA>*, size_t, size_t, int, const double2*,              \
                                                   const double2*, c2<SW>*, size_t, size_t, int, double2*, int*,     \
                                                   GmresState*, double2*, double*, double2*, double2*, int, int*,    \
                                                   hipStream_t);
 DIE_INST_FAXPY(double, double)
 DIE_INST_FAXPY(float, float)
+template hipError_t launch_faxpy<double, float>(const double2*, size_t, size_t, int, const double2*, const float2*,
+                                                float2*, size_t, size_t, int, const int*, hipStream_t);
 
 }  // namespace die

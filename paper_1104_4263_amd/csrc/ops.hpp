@@ -105,12 +105,13 @@ hipError_t launch_givens(const double2* h1, const double2* h2, int ldh, double h
                          double2* y, int m, int nrhs, int* live, const int* active, hipStream_t st);
 
 // ---- Arnoldi kernels for the GMRES inner loop (reductions finished by the last block)
-// counter: nrhs ints, zero on entry, left zero on exit.  part: nrhs * max(nv * dot_chunks(n),
-// axpy blocks) partials.
+// counter: nrhs * kCounterStride ints, zero on entry, left zero on exit.
+// part: nrhs * gmres_part_elems(n, nv) partials.
 constexpr int kDotChunkElems = 2048;
+constexpr int kCounterStride = 1024;
 inline size_t gmres_part_elems(size_t n, int nv) {
-  const size_t dots = (size_t)nv * ((n + kDotChunkElems - 1) / kDotChunkElems);
-  const size_t axpy = (n + 255) / 256;
+  const size_t dots = (size_t)nv * ((n + kDotChunkElems - 1) / kDotChunkElems) + (size_t)nv;
+  const size_t axpy = 2 * ((n + 255) / 256);
   return dots > axpy ? dots : axpy;
 }
 // out[r * nv + i] = sign * sum_e conj(A_i,r[e]) B_r[e]   (times C when given).
@@ -118,10 +119,10 @@ template <class SA, class SB>
 hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* B, size_t b_rs, size_t n,
                        int nrhs, double2* part, double sign, const double2* C, double2* out, int* counter,
                        const int* live, hipStream_t st);
-// W_r += sum_i coef[r * nv + i] A_i,r.
+// W_r = X_r + sum_i coef[r * nv + i] A_i,r  (X NULL: W_r += ...).
 template <class SA, class SW>
-hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, c2<SW>* W,
-                        size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st);
+hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, const c2<SW>* X,
+                        c2<SW>* W, size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st);
 // W_r += sum_i h2neg[r * nv + i] A_i,r; beta = ||W_r||; Givens update of column j = nv - 1 with
 // h = -(h1neg + h2neg); clears live[r] when the cycle of rhs r ends.
 template <class SA, class SW>
