@@ -107,6 +107,18 @@ typedef struct {
 int die_te_setup(die_te_ctx **ctx, const die_te_grid *grid, const void *eps_r,
                  const die_te_setup_opts *opts, void *stream);
 
+/* A context for nobj objects (1 <= nobj <= 65536) on one grid: the batched
+ * many-object / many-incidence regime of the paper's learning experiments
+ * (Section 6), where every object shares the grid, hence the symbol, and keeps
+ * its own contrasts and, when deflate_k > 0, its own deflation data (one offline
+ * eigensolve per object; Section 4, eq. DeflatingPrecondtioner).
+ * eps_r: device, complex128 [nobj][ny][nx].  Every entry point that takes nrhs
+ * then requires nrhs to be a multiple of nobj and maps right-hand side r to
+ * object r / (nrhs / nobj): fields are grouped object by object.  die_te_setup is
+ * this call with nobj = 1.  Same return codes as die_te_setup. */
+int die_te_setup_multi(die_te_ctx **ctx, const die_te_grid *grid, int nobj, const void *eps_r,
+                       const die_te_setup_opts *opts, void *stream);
+
 /* y = A x for nrhs fields (Section 4, eq. A11 family, realised by FFT convolution).
  * x, y: device, [nrhs][2][ny][nx] in the precision `prec` (DIE_C128 or DIE_C64);
  * x and y must not overlap.  Asynchronous on `stream`. */
@@ -137,9 +149,11 @@ int die_te_solve(die_te_ctx *ctx, const void *e_in, void *e_tot, int nrhs,
 int die_te_apply_deflation(die_te_ctx *ctx, const void *x, void *y, int nrhs, void *stream);
 
 /* Read back the deflation data: r (host int), the r Ritz values of largest
- * magnitude (host complex128 [r], may be NULL), the orthonormal basis V
- * (device complex128 [r][2][ny][nx], may be NULL) and C = T^-1 - I (host
- * complex128 [r][r] row-major, may be NULL).  Synchronises `stream`. */
+ * magnitude (host complex128 [nobj][r], may be NULL), the orthonormal bases V
+ * (device complex128 [nobj][r][2][ny][nx], may be NULL) and C = T^-1 - I (host
+ * complex128 [nobj][r][r] row-major, may be NULL).  An object whose Krylov space
+ * closes before r vectors has zero rows in V and C past its last vector, which
+ * leaves its P^-1 unchanged there.  Synchronises `stream`. */
 int die_te_deflation_info(die_te_ctx *ctx, int *r, void *ritz_values, void *V, void *C,
                           void *stream);
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 from .api import (  # noqa: F401
     Solver,
     die_te_setup,
+    die_te_setup_multi,
     die_te_matvec,
     die_te_regularize,
     die_te_solve,

@@ -66,6 +66,8 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     vp, ip, i = ctypes.c_void_p, ctypes.c_int, ctypes.c_int
     lib.die_te_setup.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(DieTeGrid), vp, ctypes.POINTER(DieTeSetupOpts), vp]
+    lib.die_te_setup_multi.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(DieTeGrid), i, vp,
+                                       ctypes.POINTER(DieTeSetupOpts), vp]
     lib.die_te_matvec.argtypes = [vp, vp, vp, i, i, vp]
     lib.die_te_regularize.argtypes = [vp, vp, vp, i, i, vp]
     lib.die_te_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(DieTeSolveOpts), ctypes.POINTER(DieTeSolveInfo), vp]
@@ -78,7 +80,7 @@ def load() -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.c_double)]
     lib.die_te_last_error.argtypes = []
     lib.die_te_last_error.restype = ctypes.c_char_p
-    for name in ("die_te_setup", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_apply_deflation",
+    for name in ("die_te_setup", "die_te_setup_multi", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_apply_deflation",
                  "die_te_deflation_info", "die_te_fft2", "die_te_destroy", "die_te_profile",
                  "die_te_profile_read"):
         getattr(lib, name).restype = ctypes.c_int

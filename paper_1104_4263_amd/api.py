@@ -43,6 +43,19 @@ def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float 
     return ctx
 
 
+def die_te_setup_multi(nx: int, ny: int, h: float, nobj: int, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0,
+                       py: int = 0, regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4,
+                       eigs_krylov: int = 0, eigs_max_restarts: int = 0, seed: int = 0) -> ctypes.c_void_p:
+    lib = load()
+    g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
+    o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
+                       int(eigs_max_restarts), int(seed))
+    ctx = ctypes.c_void_p()
+    check(lib.die_te_setup_multi(ctypes.byref(ctx), ctypes.byref(g), int(nobj),
+                                 _dev(eps_r, (torch.complex128,), "eps_r"), ctypes.byref(o), _stream()))
+    return ctx
+
+
 def die_te_matvec(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
     check(load().die_te_matvec(ctx, _dev(x, (torch.complex128, torch.complex64), "x"),
                                _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))
@@ -70,17 +83,17 @@ def die_te_apply_deflation(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> 
                                         nrhs, _stream()))
 
 
-def die_te_deflation_info(ctx, nvec: int, device=None):
-    """Returns (ritz values [r] complex128 numpy-like list, V [r, nvec] tensor, C [r, r] tensor on CPU)."""
+def die_te_deflation_info(ctx, nvec: int, device=None, nobj: int = 1):
+    """Returns (Ritz values [nobj, r] on CPU, V [nobj, r, nvec] on the device, C [nobj, r, r] on CPU)."""
     lib = load()
     r = ctypes.c_int(0)
     check(lib.die_te_deflation_info(ctx, ctypes.byref(r), None, None, None, _stream()))
     n = r.value
     if n == 0:
-        return torch.zeros(0, dtype=torch.complex128), None, None
-    ritz = torch.zeros(n, dtype=torch.complex128)
-    C = torch.zeros(n, n, dtype=torch.complex128)
-    V = torch.zeros(n, nvec, dtype=torch.complex128, device=device or "cuda")
+        return torch.zeros(nobj, 0, dtype=torch.complex128), None, None
+    ritz = torch.zeros(nobj, n, dtype=torch.complex128)
+    C = torch.zeros(nobj, n, n, dtype=torch.complex128)
+    V = torch.zeros(nobj, n, nvec, dtype=torch.complex128, device=device or "cuda")
     check(lib.die_te_deflation_info(ctx, ctypes.byref(r), ctypes.c_void_p(ritz.data_ptr()),
                                     _dev(V, (torch.complex128,), "V"), ctypes.c_void_p(C.data_ptr()), _stream()))
     return ritz, V, C
@@ -119,21 +132,27 @@ def die_te_last_error() -> str:
 
 
 class Solver:
-    """One scatterer on one grid: owns a library context."""
+    """Scatterers on one grid, owning a library context: eps_r of shape [ny, nx]
+    (one object) or [nobj, ny, nx] (nobj objects; batches of fields are then
+    grouped object by object, nrhs a multiple of nobj)."""
 
     def __init__(self, nx: int, ny: int, h: float, eps_r, *, k_b: float = 2.0 * math.pi, px: int = 0, py: int = 0,
                  regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
                  eigs_max_restarts: int = 0, seed: int = 0, device: str = "cuda"):
         eps = torch.as_tensor(eps_r, dtype=torch.complex128).to(device).contiguous()
-        if tuple(eps.shape) != (ny, nx):
-            raise ValueError(f"eps_r must have shape ({ny}, {nx})")
+        if tuple(eps.shape[-2:]) != (ny, nx) or eps.dim() not in (2, 3):
+            raise ValueError(f"eps_r must have shape ({ny}, {nx}) or (nobj, {ny}, {nx})")
+        self.nobj = 1 if eps.dim() == 2 else int(eps.shape[0])
         self.nx, self.ny, self.h, self.k_b = nx, ny, h, k_b
         self.nvec = 2 * nx * ny
         self.device = device
         self.regularized = bool(regularize)
-        self.ctx = die_te_setup(nx, ny, h, eps, k_b=k_b, px=px, py=py, regularize=regularize, deflate_k=deflate_k,
-                                eigs_tol=eigs_tol, eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts,
-                                seed=seed)
+        kw = dict(k_b=k_b, px=px, py=py, regularize=regularize, deflate_k=deflate_k, eigs_tol=eigs_tol,
+                  eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts, seed=seed)
+        if eps.dim() == 2:
+            self.ctx = die_te_setup(nx, ny, h, eps, **kw)
+        else:
+            self.ctx = die_te_setup_multi(nx, ny, h, self.nobj, eps, **kw)
 
     @classmethod
     def from_grid(cls, grid, eps_r, **kw):
@@ -167,7 +186,12 @@ class Solver:
         return y
 
     def deflation_info(self):
-        return die_te_deflation_info(self.ctx, self.nvec, device=self.device)
+        """(Ritz values, V, C): shapes [r], [r, nvec], [r, r] for one object, with a
+        leading [nobj] axis for several."""
+        ritz, V, C = die_te_deflation_info(self.ctx, self.nvec, device=self.device, nobj=self.nobj)
+        if self.nobj == 1:
+            return ritz[0], (None if V is None else V[0]), (None if C is None else C[0])
+        return ritz, V, C
 
     def profile(self, every: int) -> None:
         die_te_profile(self.ctx, every)

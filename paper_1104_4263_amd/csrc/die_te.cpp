@@ -92,14 +92,15 @@ struct die_te_ctx {
   int nx = 0, ny = 0, px = 0, py = 0, lpx = 0, lpy = 0;
   double h = 0, k = 0;
   size_t ncell = 0, nvec = 0;
+  int nobj = 1;  // objects sharing this grid (and therefore the symbol)
   DBuf chi64, chir64, chi32, chir32, sym64, sym32;
   DBuf work;  // FFT intermediate [nrhs][2][px][ny]
   int regularize = 0;
   // deflation
   int r = 0;
-  DBuf V;     // [r][nvec] complex128, orthonormal
-  DBuf Cdev;  // [r][r] row-major complex128, C = T^-1 - I
-  std::vector<cd> Chost, ritz;
+  DBuf V;     // [nobj][r][nvec] complex128, orthonormal per object
+  DBuf Cdev;  // [nobj][r][r] row-major complex128, C = T^-1 - I
+  std::vector<cd> Chost, ritz;  // [nobj][r][r], [nobj][r]
   int eigs_restarts = 0, eigs_converged = 0;
   // diagnostic timing: event pairs recorded around launches of each kind
   bool prof_on = false;
@@ -163,12 +164,15 @@ int ensure_work(die_te_ctx* c, size_t bytes, hipStream_t st) {
 }
 
 // y = A(chi) x (reg = false) or A(chi') x (reg = true) for nrhs fields.
+// Right-hand side r uses object obj0 + r / rpo (rpo = 0: every right-hand side uses object obj0).
 template <class T>
-int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const int* live, hipStream_t st) {
+int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const int* live, hipStream_t st,
+             int rpo, int obj0 = 0) {
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * sizeof(c2<T>), st));
   c2<T>* W = c->work.as<c2<T>>();
   ProfScope prof(c, DIE_PROF_PRODUCT, st);
-  DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi_of<T>(c, reg), W, c->nx, c->ny, nrhs, 2, 0, live, st)));
+  const c2<T>* chi = chi_of<T>(c, reg) + (size_t)obj0 * c->ncell;
+  DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi, W, c->nx, c->ny, nrhs, 2, 0, rpo, live, st)));
   DIE_HIP((die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, nrhs, live, st)));
   DIE_HIP((die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, 2 * nrhs, 2, live, st)));
   return DIE_OK;
@@ -177,25 +181,27 @@ int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const 
 // Solved operator M = A_R A (regularized) or A: out = M in, tmp is a scratch field set.
 template <class T>
 int apply_M(die_te_ctx* c, bool reg, const c2<T>* in, c2<T>* tmp, c2<T>* out, int nrhs, const int* live,
-            hipStream_t st) {
+            hipStream_t st, int rpo, int obj0 = 0) {
   if (reg) {
-    DIE_TRY(apply_op<T>(c, in, tmp, nrhs, false, live, st));
-    DIE_TRY(apply_op<T>(c, tmp, out, nrhs, true, live, st));
+    DIE_TRY(apply_op<T>(c, in, tmp, nrhs, false, live, st, rpo, obj0));
+    DIE_TRY(apply_op<T>(c, tmp, out, nrhs, true, live, st, rpo, obj0));
   } else {
-    DIE_TRY(apply_op<T>(c, in, out, nrhs, false, live, st));
+    DIE_TRY(apply_op<T>(c, in, out, nrhs, false, live, st, rpo, obj0));
   }
   return DIE_OK;
 }
 
 // Deflation projector y = P^-1 x = x + V (C (V^* x)) on basis-precision vectors (V in FP64).
 // counter: nrhs zeroed ints (left zeroed).
+// (rpo right-hand sides per object: each uses its object's V and C)
 template <class T>
 int apply_pinv(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, double2* part, double2* coef, int* counter,
-               const int* live, hipStream_t st) {
+               const int* live, hipStream_t st, int rpo) {
   const size_t n = c->nvec;
-  DIE_HIP((die::launch_fdot<double, T>(c->V.as<double2>(), n, 0, c->r, x, n, n, nrhs, part, 1.0,
-                                       c->Cdev.as<double2>(), coef, counter, live, st)));
-  DIE_HIP((die::launch_faxpy<double, T>(c->V.as<double2>(), n, 0, c->r, coef, x, y, n, n, nrhs, live, st)));
+  const size_t vstride = (size_t)c->r * n, cstride = (size_t)c->r * c->r;
+  DIE_HIP((die::launch_fdot<double, T>(c->V.as<double2>(), n, vstride, rpo, c->r, x, n, n, nrhs, part, 1.0,
+                                       c->Cdev.as<double2>(), cstride, coef, counter, live, st)));
+  DIE_HIP((die::launch_faxpy<double, T>(c->V.as<double2>(), n, vstride, rpo, c->r, coef, x, y, n, n, nrhs, live, st)));
   return DIE_OK;
 }
 
@@ -227,7 +233,10 @@ uint64_t splitmix(uint64_t& s) {
   return z ^ (z >> 31);
 }
 
-int run_eigs(die_te_ctx* c, int r, double tol, int mk, int maxrst, unsigned long long seed, hipStream_t st) {
+// Deflation data of object `obj` into the slots of c->V / c->Cdev / c->Chost / c->ritz (sized for
+// c->r vectors per object; an object whose Krylov space closes early fills fewer and the rest of
+// its slots stay zero, which leaves P^-1 unchanged).
+int run_eigs(die_te_ctx* c, int obj, int r, double tol, int mk, int maxrst, unsigned long long seed, hipStream_t st) {
   const size_t n = c->nvec;
   const bool reg = c->regularize != 0;
   const int nblk = die::blas_blocks(n);
@@ -281,7 +290,7 @@ int run_eigs(die_te_ctx* c, int r, double tol, int mk, int maxrst, unsigned long
     mk_eff = mk;
     for (int j = k0; j < mk; ++j) {
       double2* w = q + (size_t)(j + 1) * n;
-      DIE_TRY(apply_M<double>(c, reg, q + (size_t)j * n, Tm.as<double2>(), w, 1, nullptr, st));
+      DIE_TRY(apply_M<double>(c, reg, q + (size_t)j * n, Tm.as<double2>(), w, 1, nullptr, st, 0, obj));
       DIE_TRY(cgs2<double>(q, j + 1, 1, n, w, part.as<double2>(), hA.as<double2>(), hB.as<double2>(), j + 1,
                            partn.as<double>(), nullptr, st));
       DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, 1, nrm.as<double>(), nullptr, st));
@@ -363,14 +372,14 @@ int run_eigs(die_te_ctx* c, int r, double tol, int mk, int maxrst, unsigned long
   c->eigs_restarts = rst;
   const int rr = std::min(r, mk_eff);
   // deflation basis V = Q Z[:, :rr]
-  DIE_TRY(c->V.alloc((size_t)rr * n * sizeof(double2)));
+  double2* Vo = c->V.as<double2>() + (size_t)obj * r * n;
   {
     std::vector<double2> zh((size_t)mk_eff * rr);
     for (int l = 0; l < rr; ++l)
       for (int i = 0; i < mk_eff; ++i) zh[(size_t)l * mk_eff + i] = make_double2(Z(i, l).real(), Z(i, l).imag());
     DIE_HIP(hipMemcpyAsync(Zd.p, zh.data(), zh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
     DIE_HIP((die::launch_maxpy<double, double, double>(0, q, n, 0, mk_eff, nullptr, Zd.as<double2>(), mk_eff,
-                                                       (const double2*)nullptr, 0, 0.0, c->V.as<double2>(), n, 0.0,
+                                                       (const double2*)nullptr, 0, 0.0, Vo, n, 0.0,
                                                        n, rr, nullptr, nullptr, nullptr, st)));
   }
   // T = V^* M V from rr products of M (batched), C = T^-1 - I
@@ -379,8 +388,8 @@ int run_eigs(die_te_ctx* c, int r, double tol, int mk, int maxrst, unsigned long
   DIE_TRY(MT.alloc((size_t)rr * n * sizeof(double2)));
   DIE_TRY(partT.alloc((size_t)rr * rr * nblk * sizeof(double2)));
   DIE_TRY(Td.alloc((size_t)rr * rr * sizeof(double2)));
-  DIE_TRY(apply_M<double>(c, reg, c->V.as<double2>(), MT.as<double2>(), MV.as<double2>(), rr, nullptr, st));
-  DIE_HIP((die::launch_mdot<double, double>(c->V.as<double2>(), n, 0, rr, nullptr, MV.as<double2>(), n, n, rr,
+  DIE_TRY(apply_M<double>(c, reg, Vo, MT.as<double2>(), MV.as<double2>(), rr, nullptr, st, 0, obj));
+  DIE_HIP((die::launch_mdot<double, double>(Vo, n, 0, rr, nullptr, MV.as<double2>(), n, n, rr,
                                             partT.as<double2>(), nullptr, st)));
   DIE_HIP(die::launch_reduce(partT.as<double2>(), rr, nblk, rr, 1.0, nullptr, Td.as<double2>(), nullptr, st));
   std::vector<double2> th((size_t)rr * rr);
@@ -390,19 +399,17 @@ int run_eigs(die_te_ctx* c, int r, double tol, int mk, int maxrst, unsigned long
   for (int l = 0; l < rr; ++l)
     for (int i = 0; i < rr; ++i) T(i, l) = cd(th[(size_t)l * rr + i].x, th[(size_t)l * rr + i].y);
   if (!die::la::inverse(T, Ti)) return fail(DIE_E_BREAKDOWN, "deflation: T = V^* M V is singular");
-  c->Chost.assign((size_t)rr * rr, cd(0, 0));
-  std::vector<double2> ch((size_t)rr * rr);
+  std::vector<double2> ch((size_t)r * r, make_double2(0.0, 0.0));
+  cd* Ch = c->Chost.data() + (size_t)obj * r * r;
   for (int i = 0; i < rr; ++i)
     for (int l = 0; l < rr; ++l) {
       cd v = Ti(i, l) - (i == l ? 1.0 : 0.0);
-      c->Chost[(size_t)i * rr + l] = v;
-      ch[(size_t)i * rr + l] = make_double2(v.real(), v.imag());
+      Ch[(size_t)i * r + l] = v;
+      ch[(size_t)i * r + l] = make_double2(v.real(), v.imag());
     }
-  DIE_TRY(c->Cdev.alloc(ch.size() * sizeof(double2)));
-  DIE_HIP(hipMemcpyAsync(c->Cdev.p, ch.data(), ch.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-  c->ritz.resize(rr);
-  for (int i = 0; i < rr; ++i) c->ritz[i] = S(i, i);
-  c->r = rr;
+  DIE_HIP(hipMemcpyAsync(c->Cdev.as<double2>() + (size_t)obj * r * r, ch.data(), ch.size() * sizeof(double2),
+                         hipMemcpyHostToDevice, st));
+  for (int i = 0; i < rr; ++i) c->ritz[(size_t)obj * r + i] = S(i, i);
   DIE_HIP(hipStreamSynchronize(st));
   (void)converged;
   return DIE_OK;
@@ -417,6 +424,7 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   const int nblk = die::blas_blocks(n);
   const bool reg = c->regularize != 0;
   const bool defl = c->r > 0;
+  const int rpo = nrhs / c->nobj;  // right-hand sides per object (validated by the caller)
   const double tol = o.tol > 0 ? o.tol : 1e-8;
   const double margin = reg ? (o.reg_margin > 0 ? o.reg_margin : 0.1) : 1.0;
   const double floor_eta = std::is_same<T, float>::value ? 2e-6 : 0.0;
@@ -480,7 +488,7 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     // ---- FP64 true residual res = b - A u
     DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     const int* dact = active.as<int>();
-    DIE_TRY(apply_op<double>(c, u, res, nrhs, false, dact, st));
+    DIE_TRY(apply_op<double>(c, u, res, nrhs, false, dact, st, rpo));
     DIE_HIP((die::launch_maxpy<double, double, double>(2, (const double2*)nullptr, 0, 0, 0, nullptr, nullptr, 0, b, n,
                                                        1.0, res, n, -1.0, n, nrhs, nullptr, partn.as<double>(), dact,
                                                        st)));
@@ -510,7 +518,7 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     // ---- cycle right-hand side s = A_R res (or res), beta0, q0 = s / beta0
     const double2* s = res;
     if (reg) {
-      DIE_TRY(apply_op<double>(c, res, Sd.as<double2>(), nrhs, true, dact, st));
+      DIE_TRY(apply_op<double>(c, res, Sd.as<double2>(), nrhs, true, dact, st, rpo));
       s = Sd.as<double2>();
       for (int r = 0; r < nrhs; ++r) par[r] += act[r];
     }
@@ -549,26 +557,26 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
       const c2<T>* qj = q + (size_t)j * vs;
       const c2<T>* z = qj;
       if (defl) {
-        DIE_TRY(apply_pinv<T>(c, qj, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st));
+        DIE_TRY(apply_pinv<T>(c, qj, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st, rpo));
         z = Zb.as<c2<T>>();
       }
       c2<T>* w = q + (size_t)(j + 1) * vs;
-      DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st));
+      DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
       // CGS2 against Q[0..j], FP64 Givens update, normalisation
       const int nq = j + 1;
       {
         ProfScope prof(c, DIE_PROF_DOTS, st);
-        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
+        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
                                         h1.as<double2>(), dcnt, dlive, st)));
       }
       {
         ProfScope prof(c, DIE_PROF_AXPY, st);
-        DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, nq, h1.as<double2>(), (const c2<T>*)nullptr, w, n, n, nrhs, dlive,
-                                         st)));
+        DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, 1, nq, h1.as<double2>(), (const c2<T>*)nullptr, w, n, n, nrhs,
+                                         dlive, st)));
       }
       {
         ProfScope prof(c, DIE_PROF_DOTS, st);
-        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr,
+        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
                                         h2.as<double2>(), dcnt, dlive, st)));
       }
       {
@@ -592,11 +600,10 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     DIE_HIP((die::launch_maxpy<T, T, T>(0, q, vs, n, m, jd.as<int>(), y.as<double2>(), m, (const c2<T>*)nullptr, 0,
                                         0.0, t, n, 0.0, n, nrhs, nullptr, nullptr, dact, st)));
     if (defl) {
-      DIE_HIP((die::launch_fdot<double, T>(c->V.as<double2>(), n, 0, c->r, t, n, n, nrhs, part.as<double2>(), 1.0,
-                                           c->Cdev.as<double2>(), hd.as<double2>(), dcnt, dact, st)));
-      DIE_HIP((die::launch_maxpy<double, T, double>(0, c->V.as<double2>(), n, 0, c->r, nullptr, hd.as<double2>(), c->r,
-                                                    t, n, 1.0, u, n, 1.0, n, nrhs, nullptr, nullptr, dact, st)));
-    } else {
+      // t += V (C (V^* t)) with each object's V and C, then u += t below
+      DIE_TRY(apply_pinv<T>(c, t, t, nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dact, st, rpo));
+    }
+    {
       DIE_HIP((die::launch_maxpy<double, T, double>(0, (const double2*)nullptr, 0, 0, 0, nullptr, nullptr, 0, t, n, 1.0,
                                                     u, n, 1.0, n, nrhs, nullptr, nullptr, dact, st)));
     }
@@ -641,10 +648,11 @@ extern "C" {
 
 const char* die_te_last_error(void) { return g_err.c_str(); }
 
-int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, const die_te_setup_opts* opts,
-                 void* stream) {
+int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const void* eps_r,
+                       const die_te_setup_opts* opts, void* stream) {
   g_err.clear();
   if (!out || !gr || !eps_r) return fail(DIE_E_INVALID, "null argument");
+  if (nobj < 1 || nobj > 65536) return fail(DIE_E_INVALID, "nobj must be in [1, 65536]");
   *out = nullptr;
   hipStream_t st = (hipStream_t)stream;
   if (gr->nx < 1 || gr->ny < 1 || gr->nx > 2048 || gr->ny > 2048)
@@ -673,21 +681,24 @@ int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, con
   c->h = gr->h; c->k = k;
   c->ncell = (size_t)gr->nx * gr->ny;
   c->nvec = 2 * c->ncell;
+  c->nobj = nobj;
   c->regularize = o.regularize ? 1 : 0;
+  const size_t ncells = c->ncell * (size_t)nobj;
 
   // contrast (eq. ElectricContrast) and regularizer contrast (eq. InverseSymbol)
-  std::vector<double2> eps(c->ncell);
-  if (hipMemcpyAsync(eps.data(), eps_r, c->ncell * sizeof(double2), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  std::vector<double2> eps(ncells);
+  if (hipMemcpyAsync(eps.data(), eps_r, ncells * sizeof(double2), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return guard(fail(DIE_E_HIP, "reading eps_r failed (is it a device pointer?)"));
-  std::vector<double2> chi(c->ncell), chir(c->ncell);
-  std::vector<float2> chi32(c->ncell), chir32(c->ncell);
-  for (size_t e = 0; e < c->ncell; ++e) {
+  std::vector<double2> chi(ncells), chir(ncells);
+  std::vector<float2> chi32(ncells), chir32(ncells);
+  for (size_t e = 0; e < ncells; ++e) {
     const cd ev(eps[e].x, eps[e].y);
     if (!std::isfinite(ev.real()) || !std::isfinite(ev.imag()))
       return guard(fail(DIE_E_INVALID, "eps_r contains non-finite values"));
     if (ev == cd(0.0, 0.0))
-      return guard(fail(DIE_E_SINGULAR, "eps_r == 0 at cell " + std::to_string(e) + ": no solution exists"));
+      return guard(fail(DIE_E_SINGULAR, "eps_r == 0 at cell " + std::to_string(e % c->ncell) + " of object " +
+                                            std::to_string(e / c->ncell) + ": no solution exists"));
     const cd x = ev - 1.0, xr = 1.0 / ev - 1.0;
     chi[e] = make_double2(x.real(), x.imag());
     chir[e] = make_double2(xr.real(), xr.imag());
@@ -695,13 +706,13 @@ int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, con
     chir32[e] = make_float2((float)xr.real(), (float)xr.imag());
   }
   int rc;
-  if ((rc = c->chi64.alloc(c->ncell * sizeof(double2))) < 0 || (rc = c->chir64.alloc(c->ncell * sizeof(double2))) < 0 ||
-      (rc = c->chi32.alloc(c->ncell * sizeof(float2))) < 0 || (rc = c->chir32.alloc(c->ncell * sizeof(float2))) < 0)
+  if ((rc = c->chi64.alloc(ncells * sizeof(double2))) < 0 || (rc = c->chir64.alloc(ncells * sizeof(double2))) < 0 ||
+      (rc = c->chi32.alloc(ncells * sizeof(float2))) < 0 || (rc = c->chir32.alloc(ncells * sizeof(float2))) < 0)
     return guard(rc);
-  if (hipMemcpyAsync(c->chi64.p, chi.data(), c->ncell * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(c->chir64.p, chir.data(), c->ncell * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(c->chi32.p, chi32.data(), c->ncell * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(c->chir32.p, chir32.data(), c->ncell * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess)
+  if (hipMemcpyAsync(c->chi64.p, chi.data(), ncells * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->chir64.p, chir.data(), ncells * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->chi32.p, chi32.data(), ncells * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->chir32.p, chir32.data(), ncells * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess)
     return guard(fail(DIE_E_HIP, "uploading the contrast failed"));
 
   // Green tensor, circulant embedding, symbol = FFT2 / (px py) on the GPU
@@ -717,7 +728,7 @@ int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, con
     if ((rc = c->sym64.alloc(3 * plane * sizeof(double2))) < 0 || (rc = c->sym32.alloc(3 * plane * sizeof(float2))) < 0)
       return guard(rc);
     hipError_t e1 = die::launch_rows_fwd<double, double>(c->lpx, false, E.as<double2>(), nullptr, W.as<double2>(), px,
-                                                         py, 3, 1, 0, nullptr, st);
+                                                         py, 3, 1, 0, 0, nullptr, st);
     hipError_t e2 = die::launch_cols_plain<double>(c->lpy, false, W.as<double2>(), px, 3, st);
     hipError_t e3 = die::launch_pack_symbol(W.as<double2>(), c->sym64.as<double2>(), c->sym32.as<float2>(), px, py,
                                             1.0 / ((double)px * (double)py), st);
@@ -726,11 +737,31 @@ int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, con
   }
   if (o.deflate_k > 0) {
     if ((size_t)o.deflate_k >= c->nvec) return guard(fail(DIE_E_INVALID, "deflate_k must be < 2 nx ny"));
-    rc = run_eigs(c, o.deflate_k, o.eigs_tol, o.eigs_krylov, o.eigs_max_restarts, o.seed, st);
-    if (rc < 0) return guard(rc);
+    const int r = o.deflate_k;
+    if ((rc = c->V.alloc((size_t)nobj * r * c->nvec * sizeof(double2))) < 0 ||
+        (rc = c->Cdev.alloc((size_t)nobj * r * r * sizeof(double2))) < 0)
+      return guard(rc);
+    if (hipMemsetAsync(c->V.p, 0, (size_t)nobj * r * c->nvec * sizeof(double2), st) != hipSuccess ||
+        hipMemsetAsync(c->Cdev.p, 0, (size_t)nobj * r * r * sizeof(double2), st) != hipSuccess)
+      return guard(fail(DIE_E_HIP, "clearing the deflation data failed"));
+    c->Chost.assign((size_t)nobj * r * r, cd(0, 0));
+    c->ritz.assign((size_t)nobj * r, cd(0, 0));
+    c->r = r;
+    int conv = r;
+    for (int ob = 0; ob < nobj; ++ob) {
+      rc = run_eigs(c, ob, r, o.eigs_tol, o.eigs_krylov, o.eigs_max_restarts, o.seed, st);
+      if (rc < 0) return guard(rc);
+      conv = std::min(conv, c->eigs_converged);
+    }
+    c->eigs_converged = conv;
   }
   *out = c;
   return DIE_OK;
+}
+
+int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, const die_te_setup_opts* opts,
+                 void* stream) {
+  return die_te_setup_multi(out, gr, 1, eps_r, opts, stream);
 }
 
 static int product(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream, bool reg) {
@@ -738,9 +769,11 @@ static int product(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, vo
   DIE_TRY(check_ctx(c));
   if (!x || !y || nrhs < 1) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
   if (x == y) return fail(DIE_E_INVALID, "x and y must not overlap");
+  if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
   hipStream_t st = (hipStream_t)stream;
-  if (prec == DIE_C128) return apply_op<double>(c, (const double2*)x, (double2*)y, nrhs, reg, nullptr, st);
-  if (prec == DIE_C64) return apply_op<float>(c, (const float2*)x, (float2*)y, nrhs, reg, nullptr, st);
+  const int rpo = nrhs / c->nobj;
+  if (prec == DIE_C128) return apply_op<double>(c, (const double2*)x, (double2*)y, nrhs, reg, nullptr, st, rpo);
+  if (prec == DIE_C64) return apply_op<float>(c, (const float2*)x, (float2*)y, nrhs, reg, nullptr, st, rpo);
   return fail(DIE_E_INVALID, "prec must be DIE_C128 or DIE_C64");
 }
 
@@ -758,6 +791,7 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   DIE_TRY(check_ctx(c));
   if (!e_in || !e_tot || nrhs < 1 || !opts) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
   if (e_in == e_tot) return fail(DIE_E_INVALID, "e_in and e_tot must not overlap");
+  if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
   die_te_solve_opts o = *opts;
   if (o.restart < 1 || o.restart > 512) return fail(DIE_E_INVALID, "restart must be in [1, 512]");
   if (o.max_iters < 1) return fail(DIE_E_INVALID, "max_iters must be >= 1");
@@ -772,6 +806,7 @@ int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void
   DIE_TRY(check_ctx(c));
   if (c->r <= 0) return fail(DIE_E_INVALID, "the context has no deflation basis");
   if (!x || !y || nrhs < 1) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
+  if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
   hipStream_t st = (hipStream_t)stream;
   const size_t n = c->nvec;
   const int nblk = die::blas_blocks(n);
@@ -782,7 +817,7 @@ int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void
   DIE_TRY(cnt.alloc((size_t)nrhs * die::kCounterStride * sizeof(int)));
   DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * die::kCounterStride * sizeof(int), st));
   DIE_TRY(apply_pinv<double>(c, (const double2*)x, (double2*)y, nrhs, part.as<double2>(), coef.as<double2>(),
-                             cnt.as<int>(), nullptr, st));
+                             cnt.as<int>(), nullptr, st, nrhs / c->nobj));
   DIE_HIP(hipStreamSynchronize(st));  // part/coef are freed on return
   return DIE_OK;
 }
@@ -793,10 +828,11 @@ int die_te_deflation_info(die_te_ctx* c, int* r, void* ritz, void* V, void* C, v
   if (!r) return fail(DIE_E_INVALID, "null r");
   *r = c->r;
   hipStream_t st = (hipStream_t)stream;
-  if (ritz && c->r > 0) std::memcpy(ritz, c->ritz.data(), c->r * sizeof(cd));
-  if (C && c->r > 0) std::memcpy(C, c->Chost.data(), (size_t)c->r * c->r * sizeof(cd));
+  const size_t no = (size_t)c->nobj;
+  if (ritz && c->r > 0) std::memcpy(ritz, c->ritz.data(), no * c->r * sizeof(cd));
+  if (C && c->r > 0) std::memcpy(C, c->Chost.data(), no * c->r * c->r * sizeof(cd));
   if (V && c->r > 0) {
-    DIE_HIP(hipMemcpyAsync(V, c->V.p, (size_t)c->r * c->nvec * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    DIE_HIP(hipMemcpyAsync(V, c->V.p, no * c->r * c->nvec * sizeof(double2), hipMemcpyDeviceToDevice, st));
     DIE_HIP(hipStreamSynchronize(st));
   }
   return DIE_OK;
@@ -814,13 +850,13 @@ int die_te_fft2(void* data, int px, int py, int batch, int inverse, int prec, vo
   if (prec == DIE_C128) {
     DIE_TRY(W.alloc(batch * plane * sizeof(double2)));
     DIE_HIP((die::launch_rows_fwd<double, double>(ilog2(px), inv, (const double2*)data, nullptr, W.as<double2>(), px,
-                                                  py, batch, 1, 0, nullptr, st)));
+                                                  py, batch, 1, 0, 0, nullptr, st)));
     DIE_HIP(die::launch_cols_plain<double>(ilog2(py), inv, W.as<double2>(), px, batch, st));
     DIE_HIP(die::launch_transpose<double>(W.as<double2>(), (double2*)data, px, py, batch, st));
   } else if (prec == DIE_C64) {
     DIE_TRY(W.alloc(batch * plane * sizeof(float2)));
     DIE_HIP((die::launch_rows_fwd<float, float>(ilog2(px), inv, (const float2*)data, nullptr, W.as<float2>(), px, py,
-                                                batch, 1, 0, nullptr, st)));
+                                                batch, 1, 0, 0, nullptr, st)));
     DIE_HIP(die::launch_cols_plain<float>(ilog2(py), inv, W.as<float2>(), px, batch, st));
     DIE_HIP(die::launch_transpose<float>(W.as<float2>(), (float2*)data, px, py, batch, st));
   } else {

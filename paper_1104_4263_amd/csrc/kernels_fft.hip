@@ -50,8 +50,8 @@ template <class T> __host__ __device__ constexpr int cols_threads(int logn) {
 // Loads rows position-fast (coalesced), stores W[s][x][y] array-fast (TY-contiguous).
 template <class T, class S, int LOGN, bool INV>
 __global__ void __launch_bounds__(rows_threads<T>(LOGN))
-k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi, c2<T>* __restrict__ W,
-           const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr, int rb,
+k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* __restrict__ W,
+           const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr, int rb, int rpo,
            const int* __restrict__ live) {
   using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(), 1, false, kPosFast, kArrFast>;
   constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN);
@@ -62,6 +62,8 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi, c2<T>* __
   const int r1 = min(nrhs, (grp + 1) * rb);
   for (int r = grp * rb; r < r1; ++r) {
     if (live && !live[r]) continue;
+    // right-hand side r belongs to object r / rpo (rpo = 0: a single object)
+    const c2<T>* chi = chi0 ? chi0 + (rpo > 0 ? (size_t)(r / rpo) * nrows * nx : 0) : nullptr;
     for (int c = 0; c < spr; ++c) {
       const size_t s = (size_t)r * spr + c;
       const c2<S>* xs = x + s * nrows * nx;
@@ -328,7 +330,7 @@ template <> const float2* table_for<float>() {
 
 template <class T, class S>
 hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* chi, c2<T>* W, int nx, int nrows,
-                           int nrhs, int spr, int rb, const int* live, hipStream_t st) {
+                           int nrhs, int spr, int rb, int rpo, const int* live, hipStream_t st) {
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nrhs <= 0 || nrows <= 0) return hipSuccess;
@@ -341,10 +343,10 @@ hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* 
     dim3 grid((unsigned)(ntiles * ngroups));                                                            \
     if (inverse)                                                                                        \
       hipLaunchKernelGGL((k_rows_fwd<T, S, L, true>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, nx, \
-                         nrows, ntiles, nrhs, spr, rb, live);                                           \
+                         nrows, ntiles, nrhs, spr, rb, rpo, live);                                      \
     else                                                                                                \
       hipLaunchKernelGGL((k_rows_fwd<T, S, L, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, nx, \
-                         nrows, ntiles, nrhs, spr, rb, live);                                           \
+                         nrows, ntiles, nrhs, spr, rb, rpo, live);                                      \
     break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
@@ -442,9 +444,9 @@ hipError_t launch_pack_symbol(const double2* W, double2* s64, float2* s32, int p
 
 // explicit instantiations
 template hipError_t launch_rows_fwd<double, double>(int, bool, const double2*, const double2*, double2*, int,
-                                                    int, int, int, int, const int*, hipStream_t);
+                                                    int, int, int, int, int, const int*, hipStream_t);
 template hipError_t launch_rows_fwd<float, float>(int, bool, const float2*, const float2*, float2*, int, int,
-                                                  int, int, int, const int*, hipStream_t);
+                                                  int, int, int, int, const int*, hipStream_t);
 template hipError_t launch_cols_symbol<double>(int, double2*, const double2*, int, int, int, const int*,
                                                hipStream_t);
 template hipError_t launch_cols_symbol<float>(int, float2*, const float2*, int, int, int, const int*,

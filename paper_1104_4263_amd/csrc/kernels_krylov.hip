@@ -505,9 +505,9 @@ static_assert(kDotChunk == kDotChunkElems, "partial-buffer sizing assumes this c
 
 template <class SA, class SB>
 __global__ void __launch_bounds__(NT)
-k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* __restrict__ B, size_t b_rs,
-       size_t n, double2* __restrict__ part, double sign, const double2* __restrict__ C, double2* __restrict__ raw,
-       double2* __restrict__ out, int* __restrict__ counter, const int* __restrict__ live) {
+k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const c2<SB>* __restrict__ B,
+       size_t b_rs, size_t n, double2* __restrict__ part, double sign, const double2* __restrict__ C0, size_t c_stride,
+       double2* __restrict__ raw, double2* __restrict__ out, int* __restrict__ counter, const int* __restrict__ live) {
   const int r = blockIdx.z;
   if (live && !live[r]) return;
   __shared__ double2 red[NW][kDotG];
@@ -515,6 +515,8 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<
   const int nchunk = gridDim.x, ngrp = gridDim.y, grp = blockIdx.y, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int i0 = grp * kDotG, gn = min(kDotG, nv - i0);
   const size_t base = (size_t)blockIdx.x * kDotChunk + t;
+  const size_t aoff = (size_t)(r / a_rpo) * a_rs;
+  const double2* C = C0 ? C0 + (size_t)(r / a_rpo) * c_stride : nullptr;
   const c2<SB>* Br = B + (size_t)r * b_rs;
   double2 b[kDotEpt];
 #pragma unroll
@@ -527,7 +529,7 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<
   for (int g = 0; g < kDotG; ++g) {
     sx[g] = sy[g] = 0.0;
     if (g < gn) {
-      const c2<SA>* Ai = A + (size_t)(i0 + g) * a_vs + (size_t)r * a_rs;
+      const c2<SA>* Ai = A + (size_t)(i0 + g) * a_vs + aoff;
 #pragma unroll
       for (int k = 0; k < kDotEpt; ++k) {
         const size_t e = base + (size_t)k * NT;
@@ -599,7 +601,7 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const c2<
 // (last block) and the Givens update of column j = nv - 1 with h = -(h1neg + coef).
 template <class SA, class SW, bool GIVENS>
 __global__ void __launch_bounds__(NT)
-k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const double2* __restrict__ coef,
+k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const double2* __restrict__ coef,
        const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, int ept, double2* __restrict__ part, int* __restrict__ counter,
        const int* __restrict__ live_in, const double2* __restrict__ h1, GmresState* __restrict__ state,
        double2* __restrict__ Rm, double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g, int m,
@@ -617,7 +619,8 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int nv, const dou
     if (e >= n) break;
     double2 y = ld<double, SW>(Xr + e);
     for (int i = 0; i < nv; ++i) {
-      const double2 p = zmul(coef[(size_t)r * nv + i], ld<double, SA>(A + (size_t)i * a_vs + (size_t)r * a_rs + e));
+      const double2 p =
+          zmul(coef[(size_t)r * nv + i], ld<double, SA>(A + (size_t)i * a_vs + (size_t)(r / a_rpo) * a_rs + e));
       y.x += p.x;
       y.y += p.y;
     }
@@ -767,27 +770,30 @@ inline int axpy_ept(size_t n) {
 }
 
 template <class SA, class SB>
-hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* B, size_t b_rs, size_t n,
-                       int nrhs, double2* part, double sign, const double2* C, double2* out, int* counter,
-                       const int* live, hipStream_t st) {
+hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const c2<SB>* B, size_t b_rs,
+                       size_t n, int nrhs, double2* part, double sign, const double2* C, size_t c_stride,
+                       double2* out, int* counter, const int* live, hipStream_t st) {
   if (nrhs <= 0 || nv <= 0) return hipSuccess;
   if (nv > kFusedMaxNv) return hipErrorInvalidValue;
   const unsigned nchunk = (unsigned)((n + kDotChunk - 1) / kDotChunk);
   dim3 grid(nchunk, (nv + kDotG - 1) / kDotG, nrhs);
   double2* raw = part + (size_t)nrhs * nv * nchunk;  // C-path scratch after the partials
-  hipLaunchKernelGGL((k_dots<SA, SB>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, B, b_rs, n, part, sign, C, raw, out,
-                     counter, live);
+  if (a_rpo < 1) a_rpo = 1;
+  hipLaunchKernelGGL((k_dots<SA, SB>), grid, dim3(NT), 0, st, A, a_vs, a_rs, a_rpo, nv, B, b_rs, n, part, sign, C,
+                     c_stride, raw, out, counter, live);
   return hipGetLastError();
 }
 
 template <class SA, class SW>
-hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, const c2<SW>* X,
-                        c2<SW>* W, size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st) {
+hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const double2* coef,
+                        const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, int nrhs, const int* live,
+                        hipStream_t st) {
   if (nrhs <= 0) return hipSuccess;
   const int ept = axpy_ept(n);
   dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
-  hipLaunchKernelGGL((k_axpy<SA, SW, false>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, coef, X, W, w_rs, n, ept,
-                     nullptr, nullptr, live, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+  if (a_rpo < 1) a_rpo = 1;
+  hipLaunchKernelGGL((k_axpy<SA, SW, false>), grid, dim3(NT), 0, st, A, a_vs, a_rs, a_rpo, nv, coef, X, W, w_rs, n,
+                     ept, nullptr, nullptr, live, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -799,8 +805,8 @@ hipError_t launch_faxpy_givens(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv
   if (nrhs <= 0 || nv <= 0) return hipSuccess;
   const int ept = axpy_ept(n);
   dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
-  hipLaunchKernelGGL((k_axpy<SA, SW, true>), grid, dim3(NT), 0, st, A, a_vs, a_rs, nv, h2neg, (const c2<SW>*)nullptr,
-                     W, w_rs, n, ept, part, counter, live, h1neg, state, R, cs, sn, g, m, live);
+  hipLaunchKernelGGL((k_axpy<SA, SW, true>), grid, dim3(NT), 0, st, A, a_vs, a_rs, 1, nv, h2neg,
+                     (const c2<SW>*)nullptr, W, w_rs, n, ept, part, counter, live, h1neg, state, R, cs, sn, g, m, live);
   return hipGetLastError();
 }
 
@@ -813,21 +819,22 @@ hipError_t launch_lsq(const GmresState* state, const double2* R, const double2* 
 }
 
 #define DIE_INST_FUSED(SA, SB)                                                                                    \
-  template hipError_t launch_fdot<SA, SB>(const c2<SA>*, size_t, size_t, int, const c2<SB>*, size_t, size_t, int, \
-                                          double2*, double, const double2*, double2*, int*, const int*, hipStream_t);
+  template hipError_t launch_fdot<SA, SB>(const c2<SA>*, size_t, size_t, int, int, const c2<SB>*, size_t, size_t, \
+                                          int, double2*, double, const double2*, size_t, double2*, int*, const int*, \
+                                          hipStream_t);
 DIE_INST_FUSED(double, double)
 DIE_INST_FUSED(float, float)
 DIE_INST_FUSED(double, float)
 #define DIE_INST_FAXPY(SA, SW)                                                                                     \
-  template hipError_t launch_faxpy<SA, SW>(const c2<SA>*, size_t, size_t, int, const double2*, const c2<SW>*,      \
-                                           c2<SW>*, size_t, size_t, int, const int*, hipStream_t);                  \
+  template hipError_t launch_faxpy<SA, SW>(const c2<SA>*, size_t, size_t, int, int, const double2*,              \
+                                           const c2<SW>*, c2<SW>*, size_t, size_t, int, const int*, hipStream_t);   \
   template hipError_t launch_faxpy_givens<SA, SW>(const c2<SA>*, size_t, size_t, int, const double2*,              \
                                                   const double2*, c2<SW>*, size_t, size_t, int, double2*, int*,     \
                                                   GmresState*, double2*, double*, double2*, double2*, int, int*,    \
                                                   hipStream_t);
 DIE_INST_FAXPY(double, double)
 DIE_INST_FAXPY(float, float)
-template hipError_t launch_faxpy<double, float>(const double2*, size_t, size_t, int, const double2*, const float2*,
-                                                float2*, size_t, size_t, int, const int*, hipStream_t);
+template hipError_t launch_faxpy<double, float>(const double2*, size_t, size_t, int, int, const double2*,
+                                                const float2*, float2*, size_t, size_t, int, const int*, hipStream_t);
 
 }  // namespace die

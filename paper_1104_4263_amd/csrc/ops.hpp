@@ -11,10 +11,12 @@ hipError_t fft_tables(const double2** tw64, const float2** tw32);
 // Pass 1.  For every set s = r * spr + c (r < nrhs right-hand sides, c < spr components)
 // and row y < nrows: W[s][x][y] = FFT_N( pad_N( chi[y][:] * x_in[s][y][:] ) )[x],
 // x < N = 2^logn (chi may be NULL).  x_in rows have nx <= N entries; W is transposed
-// ([N][nrows]).  A block handles the spr sets of rb right-hand sides (chi loaded once).
+// ([N][nrows]).  A block handles the spr sets of rb right-hand sides (rb = 0: automatic).
+// chi holds one [nrows][nx] plane per object; right-hand side r uses plane r / rpo
+// (rpo = 0: every right-hand side uses the first plane).
 template <class T, class S>
 hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x_in, const c2<T>* chi, c2<T>* W,
-                           int nx, int nrows, int nrhs, int spr, int rb, const int* live,
+                           int nx, int nrows, int nrhs, int spr, int rb, int rpo, const int* live,
                            hipStream_t st);
 
 // Pass 2.  For every rhs r and column x < ncols of W[r][c][x][0:nrows] (c = 0, 1):
@@ -114,15 +116,19 @@ inline size_t gmres_part_elems(size_t n, int nv) {
   const size_t axpy = 2 * ((n + 255) / 256);
   return dots > axpy ? dots : axpy;
 }
-// out[r * nv + i] = sign * sum_e conj(A_i,r[e]) B_r[e]   (times C when given).
+// In the two kernels below the operand of right-hand side r is A + i * a_vs + (r / a_rpo) * a_rs
+// (a_rpo right-hand sides share one set of vectors, e.g. the deflation basis of an object).
+// out[r * nv + i] = sign * sum_e conj(A_i,r[e]) B_r[e]   (times C_(r / a_rpo) = C + (r / a_rpo) *
+// c_stride when C is given).
 template <class SA, class SB>
-hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const c2<SB>* B, size_t b_rs, size_t n,
-                       int nrhs, double2* part, double sign, const double2* C, double2* out, int* counter,
-                       const int* live, hipStream_t st);
+hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const c2<SB>* B, size_t b_rs,
+                       size_t n, int nrhs, double2* part, double sign, const double2* C, size_t c_stride,
+                       double2* out, int* counter, const int* live, hipStream_t st);
 // W_r = X_r + sum_i coef[r * nv + i] A_i,r  (X NULL: W_r += ...).
 template <class SA, class SW>
-hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv, const double2* coef, const c2<SW>* X,
-                        c2<SW>* W, size_t w_rs, size_t n, int nrhs, const int* live, hipStream_t st);
+hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const double2* coef,
+                        const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, int nrhs, const int* live,
+                        hipStream_t st);
 // W_r += sum_i h2neg[r * nv + i] A_i,r; beta = ||W_r||; Givens update of column j = nv - 1 with
 // h = -(h1neg + h2neg); clears live[r] when the cycle of rhs r ends.
 template <class SA, class SW>

@@ -10,7 +10,7 @@ from paper_1104_4263_amd import _lib
 
 def test_header_declares_the_boundary():
     names = _lib.header_symbols()
-    for n in ("die_te_setup", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_destroy",
+    for n in ("die_te_setup", "die_te_setup_multi", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_destroy",
               "die_te_last_error", "die_te_apply_deflation", "die_te_deflation_info", "die_te_fft2"):
         assert n in names
 
@@ -29,3 +29,15 @@ def test_last_error_without_gpu_calls():
     # a null context is rejected before any HIP call
     assert lib.die_te_matvec(None, None, None, 1, 0, None) == _lib.DIE_E_INVALID
     assert b"context" in lib.die_te_last_error()
+
+
+def test_setup_multi_validates_before_any_gpu_call():
+    lib = _lib.load()
+    ctx = ctypes.c_void_p()
+    g = _lib.DieTeGrid(8, 8, 0.05, 0.0, 0, 0)
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the object count is checked first
+    assert lib.die_te_setup_multi(ctypes.byref(ctx), ctypes.byref(g), 0, dummy, None, None) == _lib.DIE_E_INVALID
+    assert b"nobj" in lib.die_te_last_error()
+    g.nx = 0
+    assert lib.die_te_setup_multi(ctypes.byref(ctx), ctypes.byref(g), 2, dummy, None, None) == _lib.DIE_E_INVALID
+    assert not ctx.value
