@@ -171,11 +171,17 @@ int die_te_fft2(void *data, int px, int py, int batch, int inverse, int prec, vo
  * Arnoldi multi-axpy kernels (DIE_PROF_AXPY) issued through the context;
  * die_te_profile(ctx, 0) stops.
  * die_te_profile_read returns the number of bracketed launches of `kind`, the number of
- * launches of that kind issued while profiling was on (`seen`, may be NULL) and the total
- * elapsed milliseconds of the bracketed ones (synchronises on the recorded events). */
+ * launches of that kind issued while profiling was on (`seen`, may be NULL), the total
+ * elapsed milliseconds of the bracketed ones (synchronises on the recorded events) and
+ * (`bytes`, may be NULL) the sum of their algorithmic HBM bytes: the compulsory reads and
+ * writes of each launch's operands for the right-hand sides live when it was issued
+ * (inside a solve: those active at the start of the GMRES cycle).  Products:
+ * es (2RN + n_obj N + 8R ny px + 3 px py + 4RN) with es the bytes per complex value;
+ * dots over j basis vectors: R (j + 1) 2N es; multi-axpys: R (j + 2) 2N es. */
 enum { DIE_PROF_PRODUCT = 0, DIE_PROF_DOTS = 1, DIE_PROF_AXPY = 2 };
 int die_te_profile(die_te_ctx *ctx, int enable);
-int die_te_profile_read(die_te_ctx *ctx, int kind, long long *launches, long long *seen, double *total_ms);
+int die_te_profile_read(die_te_ctx *ctx, int kind, long long *launches, long long *seen, double *total_ms,
+                        double *bytes);
 
 /* Release everything the context owns. */
 int die_te_destroy(die_te_ctx *ctx);

@@ -77,7 +77,7 @@ def load() -> ctypes.CDLL:
     lib.die_te_destroy.argtypes = [vp]
     lib.die_te_profile.argtypes = [vp, i]
     lib.die_te_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
-                                        ctypes.POINTER(ctypes.c_double)]
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.die_te_last_error.argtypes = []
     lib.die_te_last_error.restype = ctypes.c_char_p
     for name in ("die_te_setup", "die_te_setup_multi", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_apply_deflation",

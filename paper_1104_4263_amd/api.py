@@ -113,13 +113,16 @@ def die_te_profile(ctx, every: int) -> None:
     check(load().die_te_profile(ctx, int(every)))
 
 
-def die_te_profile_read(ctx, kind: int) -> tuple[int, int, float]:
-    """(bracketed launches, launches seen, total ms of the bracketed launches)."""
+def die_te_profile_read(ctx, kind: int) -> tuple[int, int, float, float]:
+    """(bracketed launches, launches seen, total ms and total algorithmic bytes of the
+    bracketed launches)."""
     n = ctypes.c_longlong(0)
     seen = ctypes.c_longlong(0)
     ms = ctypes.c_double(0.0)
-    check(load().die_te_profile_read(ctx, int(kind), ctypes.byref(n), ctypes.byref(seen), ctypes.byref(ms)))
-    return int(n.value), int(seen.value), float(ms.value)
+    nb = ctypes.c_double(0.0)
+    check(load().die_te_profile_read(ctx, int(kind), ctypes.byref(n), ctypes.byref(seen), ctypes.byref(ms),
+                                     ctypes.byref(nb)))
+    return int(n.value), int(seen.value), float(ms.value), float(nb.value)
 
 
 def die_te_destroy(ctx) -> None:
@@ -196,7 +199,7 @@ class Solver:
     def profile(self, every: int) -> None:
         die_te_profile(self.ctx, every)
 
-    def profile_read(self, kind: int) -> tuple[int, int, float]:
+    def profile_read(self, kind: int) -> tuple[int, int, float, float]:
         return die_te_profile_read(self.ctx, kind)
 
     def close(self):

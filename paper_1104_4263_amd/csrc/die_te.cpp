@@ -107,7 +107,9 @@ struct die_te_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[3];
   size_t prof_used[3] = {0, 0, 0};
   unsigned long long prof_seen[3] = {0, 0, 0};
+  double prof_bytes[3] = {0, 0, 0};  // algorithmic bytes of the bracketed launches
   int prof_every = 1;
+  int prof_nlive = -1;  // right-hand sides live in the current launches (-1: all of them)
   ~die_te_ctx() {
     for (auto& v : prof_ev)
       for (auto& pr : v) {
@@ -125,7 +127,9 @@ struct ProfScope {
   int kind;
   hipStream_t st;
   hipEvent_t end = nullptr;
-  ProfScope(die_te_ctx* cc, int k, hipStream_t s) : c(cc), kind(k), st(s) {
+  // bytes: the algorithmic HBM bytes of the bracketed launch (the compulsory reads and writes
+  // of its operands), credited to the kind only when the launch is bracketed.
+  ProfScope(die_te_ctx* cc, int k, hipStream_t s, double bytes) : c(cc), kind(k), st(s) {
     if (!c->prof_on) return;
     if (c->prof_seen[kind]++ % c->prof_every) return;  // sample one launch in prof_every
     auto& v = c->prof_ev[kind];
@@ -139,11 +143,24 @@ struct ProfScope {
     (void)hipEventRecord(v[u].first, st);
     end = v[u].second;
     ++u;
+    c->prof_bytes[kind] += bytes;
   }
   ~ProfScope() {
     if (end) (void)hipEventRecord(end, st);
   }
 };
+
+int live_count(const die_te_ctx* c, int nrhs) { return c->prof_nlive >= 0 ? std::min(c->prof_nlive, nrhs) : nrhs; }
+
+// Algorithmic bytes of one product on R live right-hand sides (the three passes):
+// pass 1 reads u (2RN) and chi, writes the row transforms (2R ny px);
+// pass 2 reads them and the symbol (3 px py), writes the column products (2R ny px);
+// pass 3 reads those and u, writes y (2RN).
+double product_bytes(const die_te_ctx* c, int R, int nchi, size_t es) {
+  const double N = (double)c->ncell, rows = (double)c->ny * c->px, P = (double)c->px * c->py;
+  return es * (2.0 * R * N + nchi * N + 2.0 * R * rows + 2.0 * R * rows + 3.0 * P + 2.0 * R * rows +
+               2.0 * R * rows + 2.0 * R * N + 2.0 * R * N);
+}
 
 // ------------------------------------------------------------------ operator products
 template <class T> const c2<T>* chi_of(const die_te_ctx* c, bool reg);
@@ -170,7 +187,8 @@ int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const 
              int rpo, int obj0 = 0) {
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * sizeof(c2<T>), st));
   c2<T>* W = c->work.as<c2<T>>();
-  ProfScope prof(c, DIE_PROF_PRODUCT, st);
+  const int nchi = rpo > 0 ? (nrhs + rpo - 1) / rpo : 1;
+  ProfScope prof(c, DIE_PROF_PRODUCT, st, product_bytes(c, live_count(c, nrhs), nchi, sizeof(c2<T>)));
   const c2<T>* chi = chi_of<T>(c, reg) + (size_t)obj0 * c->ncell;
   DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi, W, c->nx, c->ny, nrhs, 2, 0, rpo, live, st)));
   DIE_HIP((die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, nrhs, live, st)));
@@ -484,8 +502,18 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   std::vector<double> inv0(nrhs);
   DBuf sc;
   DIE_TRY(sc.alloc((size_t)nrhs * sizeof(double)));
+  struct LiveReset {
+    die_te_ctx* c;
+    ~LiveReset() { c->prof_nlive = -1; }
+  } live_reset{c};
+  auto nlive = [&]() {
+    int k = 0;
+    for (int r = 0; r < nrhs; ++r) k += act[r] != 0;
+    return k;
+  };
   for (;;) {
     // ---- FP64 true residual res = b - A u
+    c->prof_nlive = nlive();
     DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     const int* dact = active.as<int>();
     DIE_TRY(apply_op<double>(c, u, res, nrhs, false, dact, st, rpo));
@@ -545,6 +573,7 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
         if (!std::isfinite(beta0)) brk[r] = 1;
       }
     }
+    c->prof_nlive = nlive();
     DIE_HIP(hipMemcpyAsync(state.p, hst.data(), nrhs * sizeof(die::GmresState), hipMemcpyHostToDevice, st));
     DIE_HIP(hipMemcpyAsync(g.p, hg.data(), hg.size() * sizeof(double2), hipMemcpyHostToDevice, st));
     DIE_HIP(hipMemcpyAsync(sc.p, inv0.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
@@ -564,23 +593,25 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
       DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
       // CGS2 against Q[0..j], FP64 Givens update, normalisation
       const int nq = j + 1;
+      // per live right-hand side: dots read nq basis vectors and w; the multi-axpys also write w
+      const double vb = (double)live_count(c, nrhs) * n * sizeof(c2<T>);
       {
-        ProfScope prof(c, DIE_PROF_DOTS, st);
+        ProfScope prof(c, DIE_PROF_DOTS, st, vb * (nq + 1));
         DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
                                         h1.as<double2>(), dcnt, dlive, st)));
       }
       {
-        ProfScope prof(c, DIE_PROF_AXPY, st);
+        ProfScope prof(c, DIE_PROF_AXPY, st, vb * (nq + 2));
         DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, 1, nq, h1.as<double2>(), (const c2<T>*)nullptr, w, n, n, nrhs,
                                          dlive, st)));
       }
       {
-        ProfScope prof(c, DIE_PROF_DOTS, st);
+        ProfScope prof(c, DIE_PROF_DOTS, st, vb * (nq + 1));
         DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
                                         h2.as<double2>(), dcnt, dlive, st)));
       }
       {
-        ProfScope prof(c, DIE_PROF_AXPY, st);
+        ProfScope prof(c, DIE_PROF_AXPY, st, vb * (nq + 2));
         DIE_HIP((die::launch_faxpy_givens<T, T>(q, vs, n, nq, h2.as<double2>(), h1.as<double2>(), w, n, n, nrhs,
                                                 part.as<double2>(), dcnt, state.as<die::GmresState>(),
                                                 Rm.as<double2>(), cs.as<double>(), sn.as<double2>(), g.as<double2>(),
@@ -874,15 +905,18 @@ int die_te_profile(die_te_ctx* c, int enable) {
     c->prof_every = enable;
     for (size_t& u : c->prof_used) u = 0;
     for (auto& sn : c->prof_seen) sn = 0;
+    for (double& b : c->prof_bytes) b = 0;
   }
   return DIE_OK;
 }
 
-int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long* seen, double* total_ms) {
+int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long* seen, double* total_ms,
+                        double* bytes) {
   g_err.clear();
   DIE_TRY(check_ctx(c));
   if (kind < 0 || kind > 2 || !launches || !total_ms) return fail(DIE_E_INVALID, "bad profile kind or null output");
   if (seen) *seen = (long long)c->prof_seen[kind];
+  if (bytes) *bytes = c->prof_bytes[kind];
   double tot = 0.0;
   const size_t u = c->prof_used[kind];
   for (size_t i = 0; i < u; ++i) {
