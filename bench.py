@@ -63,22 +63,24 @@ def source_hash(*names):
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_tag, src_hash):
-    """HBM bytes per dispatch from a committed rocprofv3 --pmc summary, if it was taken on
-    the current kernel source (else None)."""
+def read_traffic(kernel_tag, src_hash, algorithmic_bytes):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary: its measured ratio of
+    HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel) to algorithmic bytes,
+    applied to this run's algorithmic bytes per launch.  None unless the summary was taken
+    on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
     with open(path) as f:
         for line in f:
-            if ":" in line:
+            if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != src_hash:
         return None
     try:
-        return float(vals["hbm_bytes_per_dispatch"])
+        return float(vals["hbm_over_algorithmic"]) * algorithmic_bytes
     except (KeyError, ValueError):
         return None
 
@@ -198,7 +200,8 @@ def main():
     src = source_hash("kernels_fft.hip" if dom == "product" else "kernels_krylov.hip")
     kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "cgs_dots_c64_256_batched",
                   "axpy": "cgs_axpy_c64_256_batched"}[dom]
-    traffic = read_traffic(kernel_tag, src)
+    traffic = read_traffic(kernel_tag, src, bytes_per_launch)
+    traffic = None if traffic is None else int(traffic)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_launch_us": round(1000.0 * avg_ms, 2),
