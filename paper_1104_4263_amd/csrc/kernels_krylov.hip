@@ -491,31 +491,65 @@ constexpr int kFusedMaxNv = 512;
 
 }  // namespace
 
-// Dot products out[r][i] = sign * conj(A_i,r) . B_r (optionally times C), GEMV style:
-// one block per (chunk of kDotChunk elements, group of kDotG vectors, rhs r) with one
-// block reduction per vector.  Completion is counted per (rhs, vector group) and then
-// per rhs, so no counter sees more than max(chunks, groups) atomic increments; the
-// last block of a group sums its vectors' chunk partials in a fixed order, and when C
-// is given the last group applies it.  counter: [nrhs][kCounterStride] zeroed ints.
+// Dot products out[r][i] = sign * conj(A_i,r) . B_r (optionally times C), GEMV style,
+// one partial per (vector, chunk of kDotChunk elements) from one block reduction per
+// vector.  WALK: one block per (chunk, rhs) loads its chunk of B_r once and walks all
+// vectors in groups of kDotG (large batches).  Otherwise one block per (chunk, group of
+// kDotG vectors, rhs), for more blocks when the batch is small; completion is then counted
+// per (rhs, group) first.  The last block of rhs r (counted with agent-scope atomics)
+// sums each vector's chunk partials in a fixed order and, when C is given, applies it.
+// Both shapes compute the same partials and sums, so results do not depend on the shape.
+// counter: [nrhs][kCounterStride] zeroed ints (left zeroed).
 constexpr int kDotEpt = 8;
 constexpr int kDotChunk = NT * kDotEpt;
 constexpr int kDotG = 4;
 constexpr int kNormGroup = 64;
 static_assert(kDotChunk == kDotChunkElems, "partial-buffer sizing assumes this chunk");
 
-template <class SA, class SB>
+// Accumulate conj(A_i) . b over this thread's kDotEpt elements for kDotG vectors, FP64
+// fused multiply-adds on widened values.  FULL: the whole chunk is inside the vector.
+template <class SA, bool FULL>
+__device__ __forceinline__ void dots_group(const c2<SA>* __restrict__ Ar, size_t a_vs, int i0, int gn, size_t base,
+                                           size_t n, const double2 (&b)[kDotEpt], double (&v)[2 * kDotG]) {
+#pragma unroll
+  for (int g = 0; g < kDotG; ++g) {
+    double sx = 0.0, sy = 0.0;
+    if (g < gn) {
+      const c2<SA>* Ai = Ar + (size_t)(i0 + g) * a_vs + base;
+#pragma unroll
+      for (int k = 0; k < kDotEpt; ++k) {
+        if (FULL || base + (size_t)k * NT < n) {
+          const double2 a = ld<double, SA>(Ai + (size_t)k * NT);
+          sx = fma(a.x, b[k].x, sx);
+          sx = fma(a.y, b[k].y, sx);
+          sy = fma(a.x, b[k].y, sy);
+          sy = fma(-a.y, b[k].x, sy);
+        }
+      }
+    }
+    v[2 * g] = sx;
+    v[2 * g + 1] = sy;
+  }
+}
+
+template <class SA, class SB, bool WALK>
 __global__ void __launch_bounds__(NT)
 k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const c2<SB>* __restrict__ B,
-       size_t b_rs, size_t n, double2* __restrict__ part, double sign, const double2* __restrict__ C0, size_t c_stride,
-       double2* __restrict__ raw, double2* __restrict__ out, int* __restrict__ counter, const int* __restrict__ live) {
-  const int r = blockIdx.z;
+       size_t b_rs, size_t n, double2* __restrict__ part, double sign, const double2* __restrict__ C0,
+       size_t c_stride, double2* __restrict__ out, int* __restrict__ counter, const int* __restrict__ live) {
+  const int r = WALK ? blockIdx.y : blockIdx.z;
   if (live && !live[r]) return;
-  __shared__ double2 red[NW][kDotG];
+  // block reduction of the 2 kDotG values of every thread: transposed through LDS
+  // (value v of thread t at red[v][t]); a team of 32 lanes per value then sums entries
+  // l, l + 32, ..., l + 224 in lane l and finishes with a 32-lane butterfly.
+  __shared__ double red[2 * kDotG][NT];
+  __shared__ double2 acc[kFusedMaxNv];
   __shared__ int s_last;
-  const int nchunk = gridDim.x, ngrp = gridDim.y, grp = blockIdx.y, t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const int i0 = grp * kDotG, gn = min(kDotG, nv - i0);
+  static_assert(2 * kDotG * 32 == NT, "one 32-lane team per reduced value");
+  const int nchunk = gridDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const size_t base = (size_t)blockIdx.x * kDotChunk + t;
-  const size_t aoff = (size_t)(r / a_rpo) * a_rs;
+  const bool full = (size_t)(blockIdx.x + 1) * kDotChunk <= n;
+  const c2<SA>* Ar = A + (size_t)(r / a_rpo) * a_rs;
   const double2* C = C0 ? C0 + (size_t)(r / a_rpo) * c_stride : nullptr;
   const c2<SB>* Br = B + (size_t)r * b_rs;
   double2 b[kDotEpt];
@@ -524,46 +558,48 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
     const size_t e = base + (size_t)k * NT;
     b[k] = e < n ? ld<double, SB>(Br + e) : make_double2(0.0, 0.0);
   }
-  double sx[kDotG], sy[kDotG];
+  const int ifirst = WALK ? 0 : blockIdx.y * kDotG, iend = WALK ? nv : min(nv, ifirst + kDotG);
+  const int rv = t >> 5, rl = t & 31;  // reduced value and lane of this thread's team
+  for (int i0 = ifirst; i0 < iend; i0 += kDotG) {
+    const int gn = min(kDotG, nv - i0);
+    double v[2 * kDotG];
+    if (full) dots_group<SA, true>(Ar, a_vs, i0, gn, base, n, b, v);
+    else dots_group<SA, false>(Ar, a_vs, i0, gn, base, n, b, v);
 #pragma unroll
-  for (int g = 0; g < kDotG; ++g) {
-    sx[g] = sy[g] = 0.0;
-    if (g < gn) {
-      const c2<SA>* Ai = A + (size_t)(i0 + g) * a_vs + aoff;
+    for (int q = 0; q < 2 * kDotG; ++q) red[q][t] = v[q];
+    __syncthreads();
+    double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < kDotEpt; ++k) {
-        const size_t e = base + (size_t)k * NT;
-        if (e < n) {
-          const double2 a = ld<double, SA>(Ai + e);
-          sx[g] += a.x * b[k].x + a.y * b[k].y;
-          sy[g] += a.x * b[k].y - a.y * b[k].x;
-        }
-      }
+    for (int k = 0; k < NT / 32; ++k) s += red[rv][k * 32 + rl];
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+    if (rl == 0 && (rv >> 1) < gn) {
+      double* dst = reinterpret_cast<double*>(part + ((size_t)r * nv + i0 + (rv >> 1)) * nchunk + blockIdx.x);
+      __hip_atomic_store(dst + (rv & 1), s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
   }
-#pragma unroll
-  for (int g = 0; g < kDotG; ++g) {
-    sx[g] = wave_sum(sx[g]);
-    sy[g] = wave_sum(sy[g]);
-  }
-  if (lane == 0)
-#pragma unroll
-    for (int g = 0; g < kDotG; ++g) red[w][g] = make_double2(sx[g], sy[g]);
+  // the partials were stored by lanes of every wave: each wave waits for its own stores
+  // before the block's completion is counted
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   int* cnt = counter + (size_t)r * kCounterStride;
-  if (t < gn) {
-    double2 s = red[0][t];
-#pragma unroll
-    for (int k = 1; k < NW; ++k) { s.x += red[k][t].x; s.y += red[k][t].y; }
-    st_agent(part + ((size_t)r * nv + i0 + t) * nchunk + blockIdx.x, s);
+  if (!WALK) {  // first level: the chunks of this vector group
+    if (t == 0) s_last = arrive_last(cnt + 1 + blockIdx.y, nchunk);
+    __syncthreads();
+    if (!s_last) return;
+    if (t == 0) {
+      cnt[1 + blockIdx.y] = 0;
+      s_last = arrive_last(cnt, gridDim.y);
+    }
+  } else if (t == 0) {
+    s_last = arrive_last(cnt, nchunk);
   }
-  if (t == 0) s_last = arrive_last(cnt + 1 + grp, nchunk);
   __syncthreads();
   if (!s_last) return;
-  // last block of this vector group: sum the chunk partials of its vectors
-  double2* dst = C ? raw : out;
-  for (int g = w; g < gn; g += NW) {
-    const double2* p = part + ((size_t)r * nv + i0 + g) * nchunk;
+  // last block of rhs r: sum each vector's chunk partials in a fixed order
+  for (int g = w; g < nv; g += NW) {
+    const double2* p = part + ((size_t)r * nv + g) * nchunk;
     double ax = 0.0, ay = 0.0;
     for (int c = lane; c < nchunk; c += 64) {
       const double2 v = ld_agent(p + c);
@@ -574,84 +610,103 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
     ay = wave_sum(ay);
     if (lane == 0) {
       const double2 v = make_double2(sign * ax, sign * ay);
-      if (C) st_agent(dst + (size_t)r * nv + i0 + g, v);
-      else dst[(size_t)r * nv + i0 + g] = v;
+      if (C) acc[g] = v;
+      else out[(size_t)r * nv + g] = v;
     }
   }
-  if (t == 0) cnt[1 + grp] = 0;
+  if (t == 0) cnt[0] = 0;
   if (!C) return;
   __syncthreads();
-  if (t == 0) s_last = arrive_last(cnt, ngrp);
-  __syncthreads();
-  if (!s_last) return;
-  // last group: out = C raw
   for (int ii = t; ii < nv; ii += NT) {
     double2 v = make_double2(0.0, 0.0);
     for (int l = 0; l < nv; ++l) {
-      const double2 p = zmul(C[(size_t)ii * nv + l], ld_agent(raw + (size_t)r * nv + l));
-      v.x += p.x;
-      v.y += p.y;
+      const double2 q = zmul(C[(size_t)ii * nv + l], acc[l]);
+      v.x += q.x;
+      v.y += q.y;
     }
     out[(size_t)r * nv + ii] = v;
   }
-  if (t == 0) cnt[0] = 0;
 }
 
-// W_r += sum_i coef[r * nv + i] A_i,r (element parallel).  GIVENS: also beta = ||W_r||
+// W_r += sum_i coef[r * nv + i] A_i,r (element parallel, EPT elements per thread so that
+// EPT loads of each basis vector are in flight together).  GIVENS: also beta = ||W_r||
 // (last block) and the Givens update of column j = nv - 1 with h = -(h1neg + coef).
-template <class SA, class SW, bool GIVENS>
+template <class SA, class SW, bool GIVENS, int EPT>
 __global__ void __launch_bounds__(NT)
 k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const double2* __restrict__ coef,
-       const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, int ept, double2* __restrict__ part, int* __restrict__ counter,
+       const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, double2* __restrict__ part, int* __restrict__ counter,
        const int* __restrict__ live_in, const double2* __restrict__ h1, GmresState* __restrict__ state,
        double2* __restrict__ Rm, double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g, int m,
        int* __restrict__ live_out) {
   const int r = blockIdx.y;
   if (live_in && !live_in[r]) return;
-  __shared__ double red1[NW];
   __shared__ int s_last;
   const int nblk = gridDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   c2<SW>* Wr = W + (size_t)r * w_rs;
   const c2<SW>* Xr = X ? X + (size_t)r * w_rs : Wr;
-  double s2 = 0.0;
-  for (int k = 0; k < ept; ++k) {
-    const size_t e = ((size_t)blockIdx.x * ept + k) * NT + t;
-    if (e >= n) break;
-    double2 y = ld<double, SW>(Xr + e);
-    for (int i = 0; i < nv; ++i) {
-      const double2 p =
-          zmul(coef[(size_t)r * nv + i], ld<double, SA>(A + (size_t)i * a_vs + (size_t)(r / a_rpo) * a_rs + e));
-      y.x += p.x;
-      y.y += p.y;
+  const c2<SA>* Ar = A + (size_t)(r / a_rpo) * a_rs;
+  const size_t base = (size_t)blockIdx.x * (NT * EPT) + t;
+  double2 y[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = base + (size_t)k * NT;
+    y[k] = e < n ? ld<double, SW>(Xr + e) : make_double2(0.0, 0.0);
+  }
+  for (int i = 0; i < nv; ++i) {
+    const double2 cf = coef[(size_t)r * nv + i];
+    const c2<SA>* Ai = Ar + (size_t)i * a_vs;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const size_t e = base + (size_t)k * NT;
+      if (e < n) {
+        const double2 p = zmul(cf, ld<double, SA>(Ai + e));
+        y[k].x += p.x;
+        y[k].y += p.y;
+      }
     }
-    st<SW, double>(Wr + e, y);
-    if constexpr (GIVENS) {
-      y = ld<double, SW>(Wr + e);
-      s2 += y.x * y.x + y.y * y.y;
+  }
+  double s2[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = base + (size_t)k * NT;
+    s2[k] = 0.0;
+    if (e < n) {
+      const c2<SW> v = mk<SW>((SW)y[k].x, (SW)y[k].y);
+      Wr[e] = v;
+      if constexpr (GIVENS) s2[k] = (double)v.x * (double)v.x + (double)v.y * (double)v.y;  // of the stored value
     }
   }
   if constexpr (GIVENS) {
-    s2 = wave_sum(s2);
-    if (lane == 0) red1[w] = s2;
-    __syncthreads();
-    if (t == 0) {
-      double s = 0.0;
+    // one partial per 256 consecutive elements (whatever EPT is), so the sum of squares is
+    // associated the same way for every launch shape
+    __shared__ double red1[EPT][NW];
+    const int npart = nblk * EPT;
 #pragma unroll
-      for (int k = 0; k < NW; ++k) s += red1[k];
-      st_agent(part + (size_t)r * nblk + blockIdx.x, make_double2(s, 0.0));
+    for (int k = 0; k < EPT; ++k) {
+      const double v = wave_sum(s2[k]);
+      if (lane == 0) red1[k][w] = v;
     }
-    // two-level completion count: groups of kNormGroup blocks, then the groups
+    __syncthreads();
+    if (t < EPT) {  // wave 0 only: its vmcnt wait below orders these stores before the count
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) v += red1[t][k];
+      st_agent(part + (size_t)r * npart + (size_t)blockIdx.x * EPT + t, make_double2(v, 0.0));
+    }
+    // two-level completion count: groups of kNormGroup partials, then the groups
     int* cnt = counter + (size_t)r * kCounterStride;
-    const int grp = blockIdx.x / kNormGroup, ngrp = (nblk + kNormGroup - 1) / kNormGroup;
-    const int gsize = min(kNormGroup, nblk - grp * kNormGroup);
-    if (t == 0) s_last = arrive_last(cnt + 1 + grp, gsize);
+    constexpr int kBlocksPerGroup = kNormGroup / EPT;
+    const int grp = blockIdx.x / kBlocksPerGroup, ngrp = (nblk + kBlocksPerGroup - 1) / kBlocksPerGroup;
+    const int gblocks = min(kBlocksPerGroup, nblk - grp * kBlocksPerGroup);
+    if (t == 0) s_last = arrive_last(cnt + 1 + grp, gblocks);
     __syncthreads();
     if (!s_last) return;
-    double2* gpart = part + (size_t)gridDim.y * nblk;  // group sums after the block partials
+    double2* gpart = part + (size_t)gridDim.y * npart;  // group sums after the partials
+    const int gsize = gblocks * EPT;
     if (w == 0) {
       double gs = 0.0;
       for (int c = grp * kNormGroup + lane; c < grp * kNormGroup + gsize; c += 64)
-        gs += ld_agent(part + (size_t)r * nblk + c).x;
+        gs += ld_agent(part + (size_t)r * npart + c).x;
       gs = wave_sum(gs);
       if (lane == 0) {
         st_agent(gpart + (size_t)r * ngrp + grp, make_double2(gs, 0.0));
@@ -764,9 +819,35 @@ k_lsq(const GmresState* __restrict__ state, const double2* __restrict__ Rm, cons
   }
 }
 
-inline int axpy_ept(size_t n) {
-  size_t e = n / ((size_t)NT * 1024);
-  return (int)std::min<size_t>(16, std::max<size_t>(1, e));
+// Elements per thread of the multi-axpys: the largest power of two (up to 8) that still
+// leaves about 2048 blocks (8 per CU) in the launch.
+inline int blocks_split(size_t units, int nrhs) {
+  int e = 8;
+  while (e > 1 && ((units + e - 1) / e) * (size_t)nrhs < 2048) e >>= 1;
+  return e;
+}
+
+template <class SA, class SW, bool GIVENS>
+hipError_t launch_axpy_ept(const c2<SA>* A, size_t a_vs, size_t a_rs, int a_rpo, int nv, const double2* coef,
+                           const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, int nrhs, double2* part, int* counter,
+                           const int* live_in, const double2* h1, GmresState* state, double2* R, double* cs,
+                           double2* sn, double2* g, int m, int* live_out, hipStream_t st) {
+  const int ept = blocks_split((n + NT - 1) / NT, nrhs);
+  dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
+#define DIE_AXPY_CASE(E)                                                                                         \
+  case E:                                                                                                        \
+    hipLaunchKernelGGL((k_axpy<SA, SW, GIVENS, E>), grid, dim3(NT), 0, st, A, a_vs, a_rs, a_rpo, nv, coef, X, W, \
+                       w_rs, n, part, counter, live_in, h1, state, R, cs, sn, g, m, live_out);                   \
+    break;
+  switch (ept) {
+    DIE_AXPY_CASE(1)
+    DIE_AXPY_CASE(2)
+    DIE_AXPY_CASE(4)
+    DIE_AXPY_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef DIE_AXPY_CASE
+  return hipGetLastError();
 }
 
 template <class SA, class SB>
@@ -776,11 +857,15 @@ hipError_t launch_fdot(const c2<SA>* A, size_t a_vs, size_t a_rs, int a_rpo, int
   if (nrhs <= 0 || nv <= 0) return hipSuccess;
   if (nv > kFusedMaxNv) return hipErrorInvalidValue;
   const unsigned nchunk = (unsigned)((n + kDotChunk - 1) / kDotChunk);
-  dim3 grid(nchunk, (nv + kDotG - 1) / kDotG, nrhs);
-  double2* raw = part + (size_t)nrhs * nv * nchunk;  // C-path scratch after the partials
   if (a_rpo < 1) a_rpo = 1;
-  hipLaunchKernelGGL((k_dots<SA, SB>), grid, dim3(NT), 0, st, A, a_vs, a_rs, a_rpo, nv, B, b_rs, n, part, sign, C,
-                     c_stride, raw, out, counter, live);
+  if ((size_t)nchunk * nrhs >= 2048) {
+    hipLaunchKernelGGL((k_dots<SA, SB, true>), dim3(nchunk, nrhs), dim3(NT), 0, st, A, a_vs, a_rs, a_rpo, nv, B,
+                       b_rs, n, part, sign, C, c_stride, out, counter, live);
+  } else {
+    const unsigned ngrp = (unsigned)((nv + kDotG - 1) / kDotG);
+    hipLaunchKernelGGL((k_dots<SA, SB, false>), dim3(nchunk, ngrp, nrhs), dim3(NT), 0, st, A, a_vs, a_rs, a_rpo, nv,
+                       B, b_rs, n, part, sign, C, c_stride, out, counter, live);
+  }
   return hipGetLastError();
 }
 
@@ -789,12 +874,9 @@ hipError_t launch_faxpy(const c2<SA>* A, size_t a_vs, size_t a_rs, int a_rpo, in
                         const c2<SW>* X, c2<SW>* W, size_t w_rs, size_t n, int nrhs, const int* live,
                         hipStream_t st) {
   if (nrhs <= 0) return hipSuccess;
-  const int ept = axpy_ept(n);
-  dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
   if (a_rpo < 1) a_rpo = 1;
-  hipLaunchKernelGGL((k_axpy<SA, SW, false>), grid, dim3(NT), 0, st, A, a_vs, a_rs, a_rpo, nv, coef, X, W, w_rs, n,
-                     ept, nullptr, nullptr, live, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
-  return hipGetLastError();
+  return launch_axpy_ept<SA, SW, false>(A, a_vs, a_rs, a_rpo, nv, coef, X, W, w_rs, n, nrhs, nullptr, nullptr, live,
+                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr, st);
 }
 
 template <class SA, class SW>
@@ -803,11 +885,8 @@ hipError_t launch_faxpy_givens(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv
                                int* counter, GmresState* state, double2* R, double* cs, double2* sn, double2* g,
                                int m, int* live, hipStream_t st) {
   if (nrhs <= 0 || nv <= 0) return hipSuccess;
-  const int ept = axpy_ept(n);
-  dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
-  hipLaunchKernelGGL((k_axpy<SA, SW, true>), grid, dim3(NT), 0, st, A, a_vs, a_rs, 1, nv, h2neg,
-                     (const c2<SW>*)nullptr, W, w_rs, n, ept, part, counter, live, h1neg, state, R, cs, sn, g, m, live);
-  return hipGetLastError();
+  return launch_axpy_ept<SA, SW, true>(A, a_vs, a_rs, 1, nv, h2neg, (const c2<SW>*)nullptr, W, w_rs, n, nrhs, part,
+                                       counter, live, h1neg, state, R, cs, sn, g, m, live, st);
 }
 
 hipError_t launch_lsq(const GmresState* state, const double2* R, const double2* g, double2* y, int m, int nrhs,

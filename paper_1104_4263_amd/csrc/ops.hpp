@@ -113,7 +113,7 @@ constexpr int kDotChunkElems = 2048;
 constexpr int kCounterStride = 1024;
 inline size_t gmres_part_elems(size_t n, int nv) {
   const size_t dots = (size_t)nv * ((n + kDotChunkElems - 1) / kDotChunkElems) + (size_t)nv;
-  const size_t axpy = 2 * ((n + 255) / 256);
+  const size_t axpy = 2 * ((n + 255) / 256) + 16;  // per-256 partials (+ up to 7 past the end) and group sums
   return dots > axpy ? dots : axpy;
 }
 // In the two kernels below the operand of right-hand side r is A + i * a_vs + (r / a_rpo) * a_rs
