@@ -652,16 +652,18 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
     const size_t e = base + (size_t)k * NT;
     y[k] = e < n ? ld<double, SW>(Xr + e) : make_double2(0.0, 0.0);
   }
+  const bool full = (size_t)(blockIdx.x + 1) * (NT * EPT) <= n;
   for (int i = 0; i < nv; ++i) {
     const double2 cf = coef[(size_t)r * nv + i];
-    const c2<SA>* Ai = Ar + (size_t)i * a_vs;
+    const c2<SA>* Ai = Ar + (size_t)i * a_vs + base;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-      const size_t e = base + (size_t)k * NT;
-      if (e < n) {
-        const double2 p = zmul(cf, ld<double, SA>(Ai + e));
-        y[k].x += p.x;
-        y[k].y += p.y;
+      if (full || base + (size_t)k * NT < n) {
+        const double2 a = ld<double, SA>(Ai + (size_t)k * NT);
+        y[k].x = fma(cf.x, a.x, y[k].x);
+        y[k].x = fma(-cf.y, a.y, y[k].x);
+        y[k].y = fma(cf.x, a.y, y[k].y);
+        y[k].y = fma(cf.y, a.x, y[k].y);
       }
     }
   }
