@@ -21,6 +21,10 @@ Contents (each function cites the passage of Zouros & Budko it follows):
 * ``mie``        -- textbook Bessel/Hankel series of the TE (H-polarised) plane
                     wave on a homogeneous circular cylinder; the paper only names
                     it as its accuracy reference (Section 4, grid rule).
+* ``unet``       -- the learned warm start (not in the paper): the U-Net that
+                    proposes GMRES initial guesses, its loss gradient and the Adam
+                    update, in plain PyTorch CPU float64 with the library's
+                    bfloat16 rounding points.
 
 Every function is pinned by CPU tests against something other than itself
 (finite differences, quadrature, closed forms, brute force, exact invariants).
