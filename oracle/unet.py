@@ -162,7 +162,7 @@ def loss_and_grad(params, x, target, levels: int, base: int, bf16: bool = True):
     tgt = torch.as_tensor(np.asarray(target, np.float64))
     loss = ((out - tgt) ** 2).mean()
     loss.backward()
-    return float(loss), flat.grad.numpy().copy()
+    return float(loss.detach()), flat.grad.numpy().copy()
 
 
 def adam_step(w, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):

@@ -7,7 +7,8 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdie_te.so")
-HEADER = os.path.join(os.path.dirname(HERE), "include", "die_te.h")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+HEADERS = [os.path.join(INCLUDE, "die_te.h"), os.path.join(INCLUDE, "die_te_learn.h")]
 
 DIE_OK = 0
 DIE_NOT_CONVERGED = 1
@@ -80,19 +81,35 @@ def load() -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.die_te_last_error.argtypes = []
     lib.die_te_last_error.restype = ctypes.c_char_p
-    for name in ("die_te_setup", "die_te_setup_multi", "die_te_matvec", "die_te_regularize", "die_te_solve", "die_te_apply_deflation",
-                 "die_te_deflation_info", "die_te_fft2", "die_te_destroy", "die_te_profile",
-                 "die_te_profile_read"):
-        getattr(lib, name).restype = ctypes.c_int
+    fp, dp, ll, f, ull = (ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double), ctypes.c_longlong,
+                          ctypes.c_float, ctypes.c_ulonglong)
+    lib.die_te_unet_create.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, ull, vp]
+    lib.die_te_unet_num_params.argtypes = [vp, ctypes.POINTER(ll)]
+    lib.die_te_unet_get_params.argtypes = [vp, vp, vp]
+    lib.die_te_unet_set_params.argtypes = [vp, vp, vp]
+    lib.die_te_unet_get_grads.argtypes = [vp, vp, vp]
+    lib.die_te_unet_forward.argtypes = [vp, vp, vp, i, vp]
+    lib.die_te_unet_loss_grad.argtypes = [vp, vp, vp, i, dp, vp]
+    lib.die_te_unet_adam.argtypes = [vp, f, f, f, f, vp]
+    lib.die_te_unet_train_step.argtypes = [vp, vp, vp, i, f, dp, vp]
+    lib.die_te_unet_pack_inputs.argtypes = [vp, i, vp, vp, i, i, i, vp]
+    lib.die_te_unet_pack_targets.argtypes = [vp, vp, vp, i, i, i, vp]
+    lib.die_te_warm_start.argtypes = [vp, vp, vp, vp, i, vp]
+    lib.die_te_unet_destroy.argtypes = [vp]
+    for name in header_symbols():
+        if name != "die_te_last_error":
+            getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
 
 def header_symbols() -> list[str]:
-    """Names of the functions declared in include/die_te.h."""
-    with open(HEADER) as f:
-        text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(die_te_\w+)\s*\(", text, re.M)))
+    """Names of the functions declared in include/*.h."""
+    names = set()
+    for path in HEADERS:
+        with open(path) as f:
+            names.update(re.findall(r"^\s*(?:int|const char \*)\s*(die_te_\w+)\s*\(", f.read(), re.M))
+    return sorted(names)
 
 
 def check(code: int, allow_warning: bool = False) -> int:

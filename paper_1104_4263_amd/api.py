@@ -212,3 +212,152 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------- learned warm start
+def die_te_unet_create(levels: int, base: int, height: int, width: int, max_batch: int, seed: int = 0):
+    net = ctypes.c_void_p()
+    check(load().die_te_unet_create(ctypes.byref(net), int(levels), int(base), int(height), int(width),
+                                    int(max_batch), int(seed), _stream()))
+    return net
+
+
+def die_te_unet_num_params(net) -> int:
+    n = ctypes.c_longlong(0)
+    check(load().die_te_unet_num_params(net, ctypes.byref(n)))
+    return int(n.value)
+
+
+def _host_f32(t: torch.Tensor, name: str) -> ctypes.c_void_p:
+    if t.device.type != "cpu" or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous CPU float32 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def die_te_unet_get_params(net, params: torch.Tensor) -> None:
+    check(load().die_te_unet_get_params(net, _host_f32(params, "params"), _stream()))
+
+
+def die_te_unet_set_params(net, params: torch.Tensor) -> None:
+    check(load().die_te_unet_set_params(net, _host_f32(params, "params"), _stream()))
+
+
+def die_te_unet_get_grads(net, grads: torch.Tensor) -> None:
+    check(load().die_te_unet_get_grads(net, _host_f32(grads, "grads"), _stream()))
+
+
+def die_te_unet_forward(net, x: torch.Tensor, y: torch.Tensor, batch: int) -> None:
+    check(load().die_te_unet_forward(net, _dev(x, (torch.float32,), "x"), _dev(y, (torch.float32,), "y"), int(batch),
+                                     _stream()))
+
+
+def die_te_unet_loss_grad(net, x: torch.Tensor, target: torch.Tensor, batch: int) -> float:
+    loss = ctypes.c_double(0.0)
+    check(load().die_te_unet_loss_grad(net, _dev(x, (torch.float32,), "x"), _dev(target, (torch.float32,), "target"),
+                                       int(batch), ctypes.byref(loss), _stream()))
+    return float(loss.value)
+
+
+def die_te_unet_adam(net, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    check(load().die_te_unet_adam(net, float(lr), float(beta1), float(beta2), float(eps), _stream()))
+
+
+def die_te_unet_train_step(net, x: torch.Tensor, target: torch.Tensor, batch: int, lr: float) -> float:
+    loss = ctypes.c_double(0.0)
+    check(load().die_te_unet_train_step(net, _dev(x, (torch.float32,), "x"), _dev(target, (torch.float32,), "target"),
+                                        int(batch), float(lr), ctypes.byref(loss), _stream()))
+    return float(loss.value)
+
+
+def die_te_unet_pack_inputs(eps_r: torch.Tensor, nobj: int, e_in: torch.Tensor, x: torch.Tensor, batch: int, ny: int,
+                            nx: int) -> None:
+    check(load().die_te_unet_pack_inputs(_dev(eps_r, (torch.complex128,), "eps_r"), int(nobj),
+                                         _dev(e_in, (torch.complex128,), "e_in"), _dev(x, (torch.float32,), "x"),
+                                         int(batch), int(ny), int(nx), _stream()))
+
+
+def die_te_unet_pack_targets(e_tot: torch.Tensor, e_in: torch.Tensor, t: torch.Tensor, batch: int, ny: int,
+                             nx: int) -> None:
+    check(load().die_te_unet_pack_targets(_dev(e_tot, (torch.complex128,), "e_tot"),
+                                          _dev(e_in, (torch.complex128,), "e_in"), _dev(t, (torch.float32,), "t"),
+                                          int(batch), int(ny), int(nx), _stream()))
+
+
+def die_te_warm_start(ctx, net, e_in: torch.Tensor, x0: torch.Tensor, nrhs: int) -> None:
+    check(load().die_te_warm_start(ctx, net, _dev(e_in, (torch.complex128,), "e_in"),
+                                   _dev(x0, (torch.complex128,), "x0"), int(nrhs), _stream()))
+
+
+def die_te_unet_destroy(net) -> None:
+    if net:
+        check(load().die_te_unet_destroy(net))
+
+
+class UNet:
+    """The warm-start network: owns a library network object."""
+
+    def __init__(self, levels: int, base: int, height: int, width: int, max_batch: int, seed: int = 0):
+        self.levels, self.base, self.height, self.width, self.max_batch = levels, base, height, width, max_batch
+        self.net = die_te_unet_create(levels, base, height, width, max_batch, seed)
+        self.n_params = die_te_unet_num_params(self.net)
+
+    def get_params(self) -> torch.Tensor:
+        p = torch.empty(self.n_params, dtype=torch.float32)
+        die_te_unet_get_params(self.net, p)
+        return p
+
+    def set_params(self, p) -> None:
+        die_te_unet_set_params(self.net, torch.as_tensor(p, dtype=torch.float32).contiguous())
+
+    def get_grads(self) -> torch.Tensor:
+        g = torch.empty(self.n_params, dtype=torch.float32)
+        die_te_unet_get_grads(self.net, g)
+        return g
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        b = int(x.shape[0])
+        y = torch.empty(b, self.height, self.width, 4, dtype=torch.float32, device=x.device)
+        die_te_unet_forward(self.net, x.contiguous(), y, b)
+        return y
+
+    def loss_grad(self, x: torch.Tensor, target: torch.Tensor) -> float:
+        return die_te_unet_loss_grad(self.net, x.contiguous(), target.contiguous(), int(x.shape[0]))
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+        die_te_unet_adam(self.net, lr, beta1, beta2, eps)
+
+    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float) -> float:
+        return die_te_unet_train_step(self.net, x.contiguous(), target.contiguous(), int(x.shape[0]), lr)
+
+    @staticmethod
+    def pack_inputs(eps_r: torch.Tensor, e_in: torch.Tensor) -> torch.Tensor:
+        """eps_r [nobj, ny, nx], e_in [batch, 2, ny, nx] (complex128, device) -> [batch, ny, nx, 8]."""
+        b, _, ny, nx = e_in.shape
+        eps = eps_r if eps_r.dim() == 3 else eps_r[None]
+        x = torch.empty(b, ny, nx, 8, dtype=torch.float32, device=e_in.device)
+        die_te_unet_pack_inputs(eps.contiguous(), int(eps.shape[0]), e_in.contiguous(), x, b, ny, nx)
+        return x
+
+    @staticmethod
+    def pack_targets(e_tot: torch.Tensor, e_in: torch.Tensor) -> torch.Tensor:
+        b, _, ny, nx = e_in.shape
+        t = torch.empty(b, ny, nx, 4, dtype=torch.float32, device=e_in.device)
+        die_te_unet_pack_targets(e_tot.contiguous(), e_in.contiguous(), t, b, ny, nx)
+        return t
+
+    def warm_start(self, solver: "Solver", e_in: torch.Tensor) -> torch.Tensor:
+        x0 = torch.empty_like(e_in)
+        nrhs = 1 if e_in.dim() == 3 else int(e_in.shape[0])
+        die_te_warm_start(solver.ctx, self.net, e_in.contiguous(), x0, nrhs)
+        return x0
+
+    def close(self):
+        if self.net:
+            die_te_unet_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

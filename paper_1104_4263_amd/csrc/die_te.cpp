@@ -6,6 +6,7 @@
 // Krylov methods (restarted GMRES, Section 4; Arnoldi/Krylov-Schur eigensolver
 // for the deflation basis, Section 4 eq. DeflatingPrecondtioner).
 #include "die_te.h"
+#include "die_te_learn.h"
 
 #include <algorithm>
 #include <cmath>
@@ -18,60 +19,24 @@
 
 #include "dense.hpp"
 #include "green.hpp"
+#include "host.hpp"
 #include "ops.hpp"
+#include "unet_internal.hpp"
 
 using die::c2;
 using cd = std::complex<double>;
 
+namespace die_host {
+std::string& last_error() {
+  thread_local std::string msg;
+  return msg;
+}
+}  // namespace die_host
+
 namespace {
 
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-  g_err = msg;
-  return code;
-}
-
-#define DIE_HIP(expr)                                                                        \
-  do {                                                                                       \
-    hipError_t _e = (expr);                                                                  \
-    if (_e != hipSuccess) return fail(DIE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
-  } while (0)
-
-#define DIE_TRY(expr)          \
-  do {                         \
-    int _rc = (expr);          \
-    if (_rc < 0) return _rc;   \
-  } while (0)
-
-struct DBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  DBuf() = default;
-  DBuf(const DBuf&) = delete;
-  DBuf& operator=(const DBuf&) = delete;
-  ~DBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  int alloc(size_t b) {
-    if (b <= bytes && p) return DIE_OK;
-    release();
-    if (b == 0) b = 16;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      return fail(e == hipErrorOutOfMemory ? DIE_E_NOMEM : DIE_E_HIP,
-                  "hipMalloc(" + std::to_string(b) + " bytes): " + hipGetErrorString(e));
-    }
-    bytes = b;
-    return DIE_OK;
-  }
-  template <class X> X* as() const { return static_cast<X*>(p); }
-};
+using die_host::DBuf;
+using die_host::fail;
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int v) {
@@ -677,11 +642,11 @@ int check_ctx(const die_te_ctx* c) {
 // ====================================================================== C ABI
 extern "C" {
 
-const char* die_te_last_error(void) { return g_err.c_str(); }
+const char* die_te_last_error(void) { return die_host::last_error().c_str(); }
 
 int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const void* eps_r,
                        const die_te_setup_opts* opts, void* stream) {
-  g_err.clear();
+  die_host::last_error().clear();
   if (!out || !gr || !eps_r) return fail(DIE_E_INVALID, "null argument");
   if (nobj < 1 || nobj > 65536) return fail(DIE_E_INVALID, "nobj must be in [1, 65536]");
   *out = nullptr;
@@ -796,7 +761,7 @@ int die_te_setup(die_te_ctx** out, const die_te_grid* gr, const void* eps_r, con
 }
 
 static int product(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream, bool reg) {
-  g_err.clear();
+  die_host::last_error().clear();
   DIE_TRY(check_ctx(c));
   if (!x || !y || nrhs < 1) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
   if (x == y) return fail(DIE_E_INVALID, "x and y must not overlap");
@@ -818,7 +783,7 @@ int die_te_regularize(die_te_ctx* c, const void* x, void* y, int nrhs, int prec,
 
 int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const die_te_solve_opts* opts,
                  die_te_solve_info* info, void* stream) {
-  g_err.clear();
+  die_host::last_error().clear();
   DIE_TRY(check_ctx(c));
   if (!e_in || !e_tot || nrhs < 1 || !opts) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
   if (e_in == e_tot) return fail(DIE_E_INVALID, "e_in and e_tot must not overlap");
@@ -833,7 +798,7 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
 }
 
 int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void* stream) {
-  g_err.clear();
+  die_host::last_error().clear();
   DIE_TRY(check_ctx(c));
   if (c->r <= 0) return fail(DIE_E_INVALID, "the context has no deflation basis");
   if (!x || !y || nrhs < 1) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
@@ -854,7 +819,7 @@ int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void
 }
 
 int die_te_deflation_info(die_te_ctx* c, int* r, void* ritz, void* V, void* C, void* stream) {
-  g_err.clear();
+  die_host::last_error().clear();
   DIE_TRY(check_ctx(c));
   if (!r) return fail(DIE_E_INVALID, "null r");
   *r = c->r;
@@ -870,7 +835,7 @@ int die_te_deflation_info(die_te_ctx* c, int* r, void* ritz, void* V, void* C, v
 }
 
 int die_te_fft2(void* data, int px, int py, int batch, int inverse, int prec, void* stream) {
-  g_err.clear();
+  die_host::last_error().clear();
   if (!data || batch < 1) return fail(DIE_E_INVALID, "null data or batch < 1");
   if (!is_pow2(px) || !is_pow2(py) || px < 2 || py < 2 || px > 4096 || py > 4096)
     return fail(DIE_E_INVALID, "px, py must be powers of two in [2, 4096]");
@@ -898,7 +863,7 @@ int die_te_fft2(void* data, int px, int py, int batch, int inverse, int prec, vo
 }
 
 int die_te_profile(die_te_ctx* c, int enable) {
-  g_err.clear();
+  die_host::last_error().clear();
   DIE_TRY(check_ctx(c));
   c->prof_on = enable > 0;
   if (enable > 0) {
@@ -912,7 +877,7 @@ int die_te_profile(die_te_ctx* c, int enable) {
 
 int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long* seen, double* total_ms,
                         double* bytes) {
-  g_err.clear();
+  die_host::last_error().clear();
   DIE_TRY(check_ctx(c));
   if (kind < 0 || kind > 2 || !launches || !total_ms) return fail(DIE_E_INVALID, "bad profile kind or null output");
   if (seen) *seen = (long long)c->prof_seen[kind];
@@ -931,8 +896,18 @@ int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long*
   return DIE_OK;
 }
 
+int die_te_warm_start(die_te_ctx* c, die_te_unet* net, const void* e_in, void* x0, int nrhs, void* stream) {
+  die_host::last_error().clear();
+  DIE_TRY(check_ctx(c));
+  if (!net || !e_in || !x0 || nrhs < 1) return fail(DIE_E_INVALID, "null argument or nrhs < 1");
+  if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
+  if (e_in == x0) return fail(DIE_E_INVALID, "e_in and x0 must not overlap");
+  return die_host::unet_guess(net, c->chi64.as<double2>(), nrhs / c->nobj, (const double2*)e_in, (double2*)x0, nrhs,
+                              c->ny, c->nx, (hipStream_t)stream);
+}
+
 int die_te_destroy(die_te_ctx* c) {
-  g_err.clear();
+  die_host::last_error().clear();
   if (!c) return DIE_OK;
   (void)hipDeviceSynchronize();
   delete c;

@@ -41,3 +41,15 @@ def test_setup_multi_validates_before_any_gpu_call():
     g.nx = 0
     assert lib.die_te_setup_multi(ctypes.byref(ctx), ctypes.byref(g), 2, dummy, None, None) == _lib.DIE_E_INVALID
     assert not ctx.value
+
+
+def test_unet_create_validates_before_any_gpu_call():
+    lib = _lib.load()
+    net = ctypes.c_void_p()
+    # the coarsest level of a 3-level network on 16 x 16 would be 4 wide (needs 8)
+    assert lib.die_te_unet_create(ctypes.byref(net), 3, 8, 16, 16, 1, 0, None) == _lib.DIE_E_INVALID
+    assert b"multiples" in lib.die_te_last_error()
+    assert lib.die_te_unet_create(ctypes.byref(net), 2, 12, 16, 16, 1, 0, None) == _lib.DIE_E_INVALID
+    assert lib.die_te_unet_create(ctypes.byref(net), 2, 8, 16, 16, 0, 0, None) == _lib.DIE_E_INVALID
+    assert not net.value
+    assert lib.die_te_unet_forward(None, None, None, 1, None) == _lib.DIE_E_INVALID
