@@ -106,6 +106,71 @@ def cpu_baseline(g, eps, products_per_solve):
                       f"the mean {products_per_solve:.0f} operator applications per solve of the batched run"}
 
 
+def learned_run(ntrain, g, eps, B, nsolve, value_batched, iters_batched):
+    """Learned warm start on the headline batch: train the configured U-Net on ntrain solves
+    of fresh random-field objects (one random angle each, solved by the batched solver), then
+    time network guesses + the batched solve from them."""
+    import numpy as np
+    import torch
+    from synth import plane_wave, random_field_object
+    from paper_1104_4263_amd import Solver, UNet
+    rng = np.random.default_rng(100_000)
+    X, T = [], []
+    t0 = time.perf_counter()
+    for c0 in range(0, ntrain, 256):
+        objs = [random_field_object(256, seed=100_000 + i) for i in range(c0, min(ntrain, c0 + 256))]
+        ps = 2 * math.pi * rng.random(len(objs))
+        e = np.stack([o[1] for o in objs])
+        b = torch.from_numpy(np.stack([plane_wave(g, p) for p in ps])).cuda()
+        sv = Solver.from_grid(g, e)
+        u, rc, _ = sv.solve(b, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=True)
+        X.append(UNet.pack_inputs(torch.from_numpy(e).cuda(), b))
+        T.append(UNet.pack_targets(u, b))
+        sv.close()
+        log(f"learned: generated {c0 + len(objs)} / {ntrain} training solves")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    X, T = torch.cat(X), torch.cat(T)
+    bsz, epochs = 16, 12
+    net = UNet(4, 32, 256, 256, max_batch=bsz, seed=1)
+    order = np.arange(ntrain)
+    t0 = time.perf_counter()
+    losses = []
+    steps = 0
+    for ep in range(epochs):
+        rng.shuffle(order)
+        for k in range(0, ntrain - bsz + 1, bsz):
+            idx = torch.from_numpy(order[k:k + bsz]).cuda()
+            losses.append(net.train_step(X[idx], T[idx], 5e-4))
+            steps += 1
+        log(f"learned: epoch {ep} loss {np.mean(losses[-(ntrain // bsz):]):.4f}")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    flops_step = 3 * 21.3e9 * bsz  # forward + two backward GEMMs per layer, 21.3 GFLOP per sample forward
+    # the headline batch from the network's guesses, network inference inside the timed region
+    s = Solver.from_grid(g, eps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x0 = net.warm_start(s, B)
+    torch.cuda.synchronize()
+    inf_s = time.perf_counter() - t0
+    _, rc, info = s.solve(B, x0=x0, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = np.array([x["iters"] for x in info])
+    ok = rc == 0 and all(x["rel_res_true"] <= TOL for x in info)
+    res = {"value": round(nsolve / dt, 3) if ok else 0.0, "unit": "solves/s", "train_solves": ntrain,
+           "generate_s": round(gen_s, 1), "train_s": round(train_s, 1), "epochs": epochs, "batch": bsz,
+           "train_loss_first_last": [round(losses[0], 4), round(float(np.mean(losses[-(ntrain // bsz):])), 4)],
+           "train_TFLOPs": round(flops_step * steps / train_s / 1e12, 2), "inference_s": round(inf_s, 3),
+           "iters_mean": round(float(it.mean()), 1), "iters_mean_zero_guess": round(float(iters_batched.mean()), 1),
+           "vs_batched": round((nsolve / dt) / value_batched, 3) if ok and value_batched > 0 else None}
+    log(f"learned: {res}")
+    s.close()
+    net.close()
+    return res
+
+
 def time_matvec(s, x, reps):
     """Average ms of one product call, timed with events on the stream the library launches on."""
     import torch
@@ -130,6 +195,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--orth", type=int, default=1, choices=(0, 1),
+                    help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
+    ap.add_argument("--learned", type=int, default=0, metavar="NTRAIN",
+                    help="train the warm-start U-Net (4 levels, 32 channels) on NTRAIN method-generated 256^2 "
+                         "solves, then time the batch from its guesses (several minutes)")
     ap.add_argument("--configured-deflation", action="store_true",
                     help="also run the batch with the configured k=16 deflation (about 40 s)")
     args = ap.parse_args()
@@ -161,7 +231,7 @@ def main():
     log(f"setup of {nobj} objects on {g.nx}x{g.ny}: {setup_s:.3f} s")
 
     def batch_solve():
-        return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=True)
+        return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=True, orth=args.orth)
 
     for i in range(args.warmup):
         _, rc, info = batch_solve()
@@ -236,7 +306,8 @@ def main():
         its, ok = [], True
         t0 = time.perf_counter()
         for o, j in sample:
-            _, rc, inf = singles[o].solve(B[o * N_ANGLES + j], restart=RESTART, max_iters=MAX_ITERS, tol=TOL)
+            _, rc, inf = singles[o].solve(B[o * N_ANGLES + j], restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
+                                          orth=args.orth)
             its.append(inf[0]["iters"])
             ok = ok and rc == 0
         torch.cuda.synchronize()
@@ -313,6 +384,9 @@ def main():
             log(f"cylinder variant {name}: {variants[name]}")
             sv.close()
         out["cylinder_variants"] = variants
+
+    if args.learned > 0:
+        out["learned"] = learned_run(args.learned, g, eps, B, nsolve, value, iters)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (one direct-sum product at 256^2) ...")

@@ -76,7 +76,7 @@ typedef struct {
 } die_te_setup_opts;
 
 typedef struct {
-  int restart;       /* GMRES restart length m (>= 1, <= 512) */
+  int restart;       /* GMRES restart length m (>= 1, <= 510) */
   int max_iters;     /* cap on the total number of inner GMRES iterations (>= 1) */
   double tol;        /* stop when ||b - A u||_2 <= tol ||b||_2, checked in FP64 on the
                         original (unregularized) operator; 0 -> 1e-8 */
@@ -86,6 +86,10 @@ typedef struct {
   int x0_given;      /* 1: e_tot holds the initial guess on entry; 0: start from zero */
   double reg_margin; /* regularized runs end a cycle when the regularized residual estimate
                         reaches reg_margin * (the target scaled to the cycle); 0 -> 0.1 */
+  int orth;          /* Arnoldi orthogonalisation: 0 = CGS2 (two projections per step, four
+                        passes over the basis); 1 = CGS2 with the second projection of each
+                        vector delayed to the next step (one block reduction and two passes
+                        over the basis per step; equal in exact arithmetic) */
 } die_te_solve_opts;
 
 typedef struct {

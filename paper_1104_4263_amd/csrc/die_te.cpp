@@ -440,6 +440,17 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * die::kCounterStride * sizeof(int), st));
   int* dcnt = cnt.as<int>();
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * std::max(sizeof(c2<T>), sizeof(double2)), st));
+  // one-reduction Arnoldi: raw dots, unrotated Hessenberg, first projections, axpy coefficients
+  const bool dcgs = o.orth == 1;
+  const int dstride = 2 * (m + 2);
+  DBuf Dd, Hu, cprev, coef, part2;
+  if (dcgs) {
+    DIE_TRY(Dd.alloc((size_t)nrhs * dstride * sizeof(double2)));
+    DIE_TRY(Hu.alloc((size_t)nrhs * (m + 1) * m * sizeof(double2)));
+    DIE_TRY(cprev.alloc((size_t)nrhs * (m + 1) * sizeof(double2)));
+    DIE_TRY(coef.alloc((size_t)nrhs * 2 * (m + 1) * sizeof(double2)));
+    DIE_TRY(part2.alloc((size_t)nrhs * die::gmres_part_elems(n, 2 * (m + 2)) * sizeof(double2)));
+  }
 
   c2<T>* q = Q.as<c2<T>>();
   const size_t vs = (size_t)nrhs * n;  // stride between basis vectors j
@@ -547,7 +558,36 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     int* dlive = live.as<int>();
     DIE_HIP((die::launch_scale<double, T>(s, n, q, n, sc.as<double>(), 1, n, nrhs, dact, st)));
     // ---- Arnoldi / GMRES iterations of this cycle
-    for (int j = 0; j < m; ++j) {
+    for (int j = 0; dcgs && j <= m; ++j) {
+      // one-reduction step j: product on the slot-j vector, one dots pass, scalar update,
+      // one pass writing q_j and the next vector
+      c2<T>* v = q + (size_t)j * vs;
+      c2<T>* w = j < m ? q + (size_t)(j + 1) * vs : nullptr;
+      if (w) {
+        const c2<T>* zin = v;
+        if (defl) {
+          DIE_TRY(apply_pinv<T>(c, v, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st,
+                                rpo));
+          zin = Zb.as<c2<T>>();
+        }
+        DIE_TRY(apply_M<T>(c, reg, zin, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
+      }
+      const double vb = (double)live_count(c, nrhs) * n * sizeof(c2<T>);
+      {
+        ProfScope prof(c, DIE_PROF_DOTS, st, vb * (j + 1 + (w ? 1 : 0)));
+        DIE_HIP((die::launch_dots2<T>(q, vs, j, v, w, n, n, nrhs, part2.as<double2>(), Dd.as<double2>(), dstride, dcnt,
+                                      dlive, st)));
+      }
+      DIE_HIP(die::launch_dcgs_update(Dd.as<double2>(), dstride, j, m, nrhs, state.as<die::GmresState>(),
+                                      Hu.as<double2>(), Rm.as<double2>(), cs.as<double>(), sn.as<double2>(),
+                                      g.as<double2>(), cprev.as<double2>(), coef.as<double2>(), dlive, st));
+      if (j < m) {
+        ProfScope prof(c, DIE_PROF_AXPY, st, vb * (j + 4));
+        DIE_HIP((die::launch_dcgs_axpy<T>(q, vs, j, n, n, nrhs, coef.as<double2>(), m + 1,
+                                          state.as<die::GmresState>(), dlive, st)));
+      }
+    }
+    for (int j = 0; !dcgs && j < m; ++j) {
       const c2<T>* qj = q + (size_t)j * vs;
       const c2<T>* z = qj;
       if (defl) {
@@ -607,8 +647,10 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
       if (!act[r]) continue;
       iters[r] += hst[r].j;
       cycles[r] += 1;
-      pa[r] += hst[r].j;
-      if (reg) par[r] += hst[r].j;
+      // the one-reduction step that detects the end has already applied its product
+      const int prods = dcgs ? std::min(hst[r].j + 1, m) : hst[r].j;
+      pa[r] += prods;
+      if (reg) par[r] += prods;
       if (hst[r].breakdown) {
         brk[r] = 1;
         act[r] = 0;
@@ -789,7 +831,8 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   if (e_in == e_tot) return fail(DIE_E_INVALID, "e_in and e_tot must not overlap");
   if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
   die_te_solve_opts o = *opts;
-  if (o.restart < 1 || o.restart > 512) return fail(DIE_E_INVALID, "restart must be in [1, 512]");
+  if (o.restart < 1 || o.restart > 510) return fail(DIE_E_INVALID, "restart must be in [1, 510]");
+  if (o.orth != 0 && o.orth != 1) return fail(DIE_E_INVALID, "orth must be 0 (CGS2) or 1 (one-reduction CGS2)");
   if (o.max_iters < 1) return fail(DIE_E_INVALID, "max_iters must be >= 1");
   if (o.tol < 0 || !std::isfinite(o.tol)) return fail(DIE_E_INVALID, "tol must be >= 0");
   hipStream_t st = (hipStream_t)stream;

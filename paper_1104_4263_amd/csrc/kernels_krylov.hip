@@ -823,6 +823,345 @@ k_lsq(const GmresState* __restrict__ state, const double2* __restrict__ Rm, cons
 
 // Elements per thread of the multi-axpys: the largest power of two (up to 8) that still
 // leaves about 2048 blocks (8 per CU) in the launch.
+// ==================================================================== one-reduction Arnoldi
+// CGS2 with the second projection of each new vector delayed to the next step (one
+// block reduction and one pass of multi-axpys over the basis per step).  At step j of a
+// cycle the basis holds q_0..q_{j-1} (final), the slot j holds v (the new vector after
+// one projection, not yet normalised) and the slot j+1 holds w = M P^-1 v.
+//   s = Q^H v, alpha = v^H v, z = Q^H w, beta = v^H w          (k_dots2, one pass)
+//   nu = sqrt(alpha - |s|^2),  q_j = (v - Q s) / nu,
+//   column j-1 of H = c_{j-1} + s with subdiagonal nu            (k_dcgs_update)
+//   t = H s,  h_j = [(z - t_{<j}) / nu ; ((beta - s^H z) / nu - t_j) / nu],
+//   d = t + nu h_j,  v_{j+1} = (w - Q d_{<j} - q_j d_j) / nu      (k_dcgs_axpy, one pass)
+// using the Arnoldi relation M P^-1 Q = Q H to turn w into M P^-1 q_j without a product.
+// c_j = h_j is the first projection of the next column.
+
+constexpr int kDots2G = 2;  // vectors per group: 2 vectors x 2 targets x (re, im) = 8 values
+
+template <class S, bool FULL>
+__device__ __forceinline__ void dots2_group(const c2<S>* __restrict__ Qr, size_t q_vs, const c2<S>* __restrict__ Vr,
+                                            int nq, int i0, int gn, size_t base, size_t n,
+                                            const double2 (&b0)[kDotEpt], const double2 (&b1)[kDotEpt],
+                                            double (&v)[8]) {
+#pragma unroll
+  for (int g = 0; g < kDots2G; ++g) {
+    double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
+    if (g < gn) {
+      const int i = i0 + g;
+      const c2<S>* Ai = (i < nq ? Qr + (size_t)i * q_vs : Vr) + base;
+#pragma unroll
+      for (int k = 0; k < kDotEpt; ++k) {
+        if (FULL || base + (size_t)k * NT < n) {
+          const double2 a = ld<double, S>(Ai + (size_t)k * NT);
+          s0x = fma(a.x, b0[k].x, s0x);
+          s0x = fma(a.y, b0[k].y, s0x);
+          s0y = fma(a.x, b0[k].y, s0y);
+          s0y = fma(-a.y, b0[k].x, s0y);
+          s1x = fma(a.x, b1[k].x, s1x);
+          s1x = fma(a.y, b1[k].y, s1x);
+          s1y = fma(a.x, b1[k].y, s1y);
+          s1y = fma(-a.y, b1[k].x, s1y);
+        }
+      }
+    }
+    v[4 * g + 0] = s0x;
+    v[4 * g + 1] = s0y;
+    v[4 * g + 2] = s1x;
+    v[4 * g + 3] = s1y;
+  }
+}
+
+// out[r ostride + 2 i + t] = conj(A_i,r) . T_t,r for A_0..A_{nq-1} = Q, A_nq = V, T_0 = V,
+// T_1 = W (W null: T_1 = 0).  Same shapes and fixed-order sums as k_dots.
+template <class S, bool WALK>
+__global__ void __launch_bounds__(NT)
+k_dots2(const c2<S>* __restrict__ Q, size_t q_vs, int nq, const c2<S>* __restrict__ V, const c2<S>* __restrict__ Wt,
+        size_t rs, size_t n, double2* __restrict__ part, double2* __restrict__ out, int ostride,
+        int* __restrict__ counter, const int* __restrict__ live) {
+  const int r = WALK ? blockIdx.y : blockIdx.z;
+  if (live && !live[r]) return;
+  __shared__ double red[8][NT];
+  __shared__ int s_last;
+  const int nA = nq + 1, nchunk = gridDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const size_t base = (size_t)blockIdx.x * kDotChunk + t;
+  const bool full = (size_t)(blockIdx.x + 1) * kDotChunk <= n;
+  const c2<S>* Qr = Q + (size_t)r * rs;
+  const c2<S>* Vr = V + (size_t)r * rs;
+  const c2<S>* Wr = Wt ? Wt + (size_t)r * rs : nullptr;
+  double2 b0[kDotEpt], b1[kDotEpt];
+#pragma unroll
+  for (int k = 0; k < kDotEpt; ++k) {
+    const size_t e = base + (size_t)k * NT;
+    b0[k] = e < n ? ld<double, S>(Vr + e) : make_double2(0.0, 0.0);
+    b1[k] = (Wr && e < n) ? ld<double, S>(Wr + e) : make_double2(0.0, 0.0);
+  }
+  const int ifirst = WALK ? 0 : blockIdx.y * kDots2G, iend = WALK ? nA : min(nA, ifirst + kDots2G);
+  const int rv = t >> 5, rl = t & 31;
+  for (int i0 = ifirst; i0 < iend; i0 += kDots2G) {
+    const int gn = min(kDots2G, nA - i0);
+    double v[8];
+    if (full) dots2_group<S, true>(Qr, q_vs, Vr, nq, i0, gn, base, n, b0, b1, v);
+    else dots2_group<S, false>(Qr, q_vs, Vr, nq, i0, gn, base, n, b0, b1, v);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][t] = v[q];
+    __syncthreads();
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 32; ++k) sum += red[rv][k * 32 + rl];
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 32);
+    const int gv = rv >> 2, tg = (rv >> 1) & 1, comp = rv & 1;
+    if (rl == 0 && gv < gn) {
+      double* dst =
+          reinterpret_cast<double*>(part + (((size_t)r * nA + i0 + gv) * 2 + tg) * nchunk + blockIdx.x);
+      __hip_atomic_store(dst + comp, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  int* cnt = counter + (size_t)r * kCounterStride;
+  if (!WALK) {
+    if (t == 0) s_last = arrive_last(cnt + 1 + blockIdx.y, nchunk);
+    __syncthreads();
+    if (!s_last) return;
+    if (t == 0) {
+      cnt[1 + blockIdx.y] = 0;
+      s_last = arrive_last(cnt, gridDim.y);
+    }
+  } else if (t == 0) {
+    s_last = arrive_last(cnt, nchunk);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  for (int g = w; g < 2 * nA; g += NW) {
+    const double2* p = part + ((size_t)r * nA * 2 + g) * nchunk;
+    double ax = 0.0, ay = 0.0;
+    for (int c = lane; c < nchunk; c += 64) {
+      const double2 u = ld_agent(p + c);
+      ax += u.x;
+      ay += u.y;
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (lane == 0) out[(size_t)r * ostride + g] = make_double2(ax, ay);
+  }
+  if (t == 0) cnt[0] = 0;
+}
+
+// Scalar work of step j for one right-hand side (one block of 64 threads per rhs): the
+// delayed correction and Givens rotation of column j-1, the stopping test, and the
+// coefficients of k_dcgs_axpy.  D: [nrhs][dstride] from k_dots2; Hu: unrotated H
+// [nrhs][(m+1) m]; c: [nrhs][m+1] first projection of the last column; coef: [nrhs][2(m+1)]
+// (s at 0..j-1, d at m+1 .. m+1+j).
+__global__ void __launch_bounds__(64)
+k_dcgs_update(const double2* __restrict__ D, int dstride, int j, int m, GmresState* __restrict__ state,
+              double2* __restrict__ Hu, double2* __restrict__ Rm, double* __restrict__ cs, double2* __restrict__ sn,
+              double2* __restrict__ g, double2* __restrict__ c, double2* __restrict__ coef, int* __restrict__ live) {
+  const int r = blockIdx.x, lane = threadIdx.x;
+  if (!live[r]) return;
+  __shared__ double2 col[kFusedMaxNv + 1], tt[kFusedMaxNv + 1];
+  __shared__ double s_nu;
+  __shared__ int s_stop;
+  const int ld = m + 1;
+  const double2* Dr = D + (size_t)r * dstride;  // Dr[2 i + 0] = q_i^H v, Dr[2 i + 1] = q_i^H w
+  double2* Hr = Hu + (size_t)r * ld * m;
+  double2* cr = c + (size_t)r * ld;
+  double2* kr = coef + (size_t)r * 2 * ld;
+  double s2 = 0.0;
+  for (int i = lane; i < j; i += 64) {
+    const double2 si = Dr[2 * i];
+    s2 += si.x * si.x + si.y * si.y;
+  }
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    const double alpha = Dr[2 * j].x;
+    const double nu2 = alpha - s2;
+    GmresState S = state[r];
+    // nu2 <= 0 (up to rounding) means v lies in span(Q): a lucky breakdown, nu = 0
+    const bool ok = isfinite(nu2);
+    const double nu = ok ? sqrt(fmax(nu2, 0.0)) : 0.0;
+    s_nu = nu;
+    int stop = 0;
+    if (!ok) {
+      S.breakdown = 1;
+      stop = 1;
+    } else if (j == 0) {
+      const double2 g0 = g[(size_t)r * ld];  // q_0 = v / nu, so the start residual is beta0 nu q_0
+      g[(size_t)r * ld] = make_double2(g0.x * nu, g0.y * nu);
+      if (!(nu > 0.0)) {
+        S.breakdown = 1;
+        stop = 1;
+      }
+    }
+    S.invbeta = nu > 0.0 ? 1.0 / nu : 0.0;
+    s_stop = stop;
+    state[r] = S;
+  }
+  __syncthreads();
+  const double nu = s_nu;
+  if (j >= 1 && !s_stop) {
+    // column j-1 of H: c_{j-1} + s, subdiagonal nu
+    for (int i = lane; i < j; i += 64) {
+      const double2 a = cr[i], si = Dr[2 * i];
+      col[i] = make_double2(a.x + si.x, a.y + si.y);
+      Hr[i + (size_t)(j - 1) * ld] = col[i];
+    }
+    if (lane == 0) {
+      col[j] = make_double2(nu, 0.0);
+      Hr[j + (size_t)(j - 1) * ld] = col[j];
+    }
+    __syncthreads();
+    if (lane == 0) {
+      GmresState S = state[r];
+      const int jc = j - 1;  // the column being rotated
+      double* csr = cs + (size_t)r * m;
+      double2* snr = sn + (size_t)r * m;
+      double2* gr = g + (size_t)r * ld;
+      for (int i = 0; i < jc; ++i) {
+        const double cc = csr[i];
+        const double2 sv = snr[i];
+        const double2 a = col[i], b = col[i + 1];
+        const double2 sb = zmul(sv, b), sa = zcmul(sv, a);
+        col[i] = make_double2(cc * a.x + sb.x, cc * a.y + sb.y);
+        col[i + 1] = make_double2(cc * b.x - sa.x, cc * b.y - sa.y);
+      }
+      const double2 a = col[jc];
+      const double absa = hypot(a.x, a.y), rho = hypot(absa, nu);
+      double cc;
+      double2 sv;
+      if (absa > 0.0) {
+        cc = absa / rho;
+        sv = make_double2(a.x / absa * nu / rho, a.y / absa * nu / rho);
+        col[jc] = make_double2(a.x / absa * rho, a.y / absa * rho);
+      } else {
+        cc = 0.0;
+        sv = make_double2(1.0, 0.0);
+        col[jc] = make_double2(nu, 0.0);
+      }
+      csr[jc] = cc;
+      snr[jc] = sv;
+      const double2 gj = gr[jc];
+      gr[jc] = make_double2(cc * gj.x, cc * gj.y);
+      const double2 sgj = zcmul(sv, gj);
+      gr[jc + 1] = make_double2(-sgj.x, -sgj.y);
+      const double resid = hypot(sgj.x, sgj.y);
+      const bool fin = isfinite(resid) && isfinite(rho) && rho > 0.0;
+      S.j = j;
+      S.resid = resid;
+      if (!fin) S.breakdown = 1;
+      if (!fin || resid <= S.target || j >= m || !(nu > 0.0)) s_stop = 1;
+      state[r] = S;
+    }
+    __syncthreads();
+    for (int i = lane; i <= j - 1; i += 64) Rm[(size_t)r * ld * m + i + (size_t)(j - 1) * ld] = col[i];
+  }
+  __syncthreads();
+  if (s_stop || j >= m) {
+    if (lane == 0) {
+      GmresState S = state[r];
+      S.done = 1;
+      S.j = j;
+      state[r] = S;
+      live[r] = 0;
+    }
+    return;
+  }
+  // t = H s over the finalised columns 0..j-1 (rows 0..j), then h_j and d
+  for (int i = lane; i <= j; i += 64) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) {
+      const double2 p = zmul(Hr[i + (size_t)l * ld], Dr[2 * l]);
+      acc.x += p.x;
+      acc.y += p.y;
+    }
+    tt[i] = acc;
+  }
+  double2 sz = make_double2(0.0, 0.0);
+  for (int i = lane; i < j; i += 64) {
+    const double2 p = zcmul(Dr[2 * i], Dr[2 * i + 1]);
+    sz.x += p.x;
+    sz.y += p.y;
+  }
+  sz.x = wave_sum(sz.x);
+  sz.y = wave_sum(sz.y);
+  __syncthreads();
+  const double inu = 1.0 / nu;
+  for (int i = lane; i <= j; i += 64) {
+    double2 h;
+    if (i < j) {
+      const double2 zi = Dr[2 * i + 1];
+      h = make_double2((zi.x - tt[i].x) * inu, (zi.y - tt[i].y) * inu);
+      kr[i] = Dr[2 * i];  // s_i
+    } else {
+      const double2 beta = Dr[2 * j + 1];
+      h = make_double2(((beta.x - sz.x) * inu - tt[i].x) * inu, ((beta.y - sz.y) * inu - tt[i].y) * inu);
+    }
+    cr[i] = h;
+    kr[ld + i] = make_double2(tt[i].x + nu * h.x, tt[i].y + nu * h.y);  // d_i
+  }
+}
+
+// q_j = (v - Q s) / nu into slot j and v_{j+1} = (w - Q d_{<j} - q_j d_j) / nu into slot
+// j+1, one pass over Q_0..Q_{j-1} (EPT elements per thread).
+template <class S, int EPT>
+__global__ void __launch_bounds__(NT)
+k_dcgs_axpy(c2<S>* __restrict__ Q, size_t q_vs, int j, size_t rs, size_t n, const double2* __restrict__ coef,
+            int cld, const GmresState* __restrict__ state, const int* __restrict__ live) {
+  const int r = blockIdx.y;
+  if (!live[r]) return;
+  const double inu = state[r].invbeta;
+  c2<S>* Qr = Q + (size_t)r * rs;
+  c2<S>* V = Qr + (size_t)j * q_vs;
+  c2<S>* Wv = Qr + (size_t)(j + 1) * q_vs;
+  const double2* sr = coef + (size_t)r * 2 * cld;
+  const double2* dr = sr + cld;
+  const size_t base = (size_t)blockIdx.x * (NT * EPT) + threadIdx.x;
+  const bool full = (size_t)(blockIdx.x + 1) * (NT * EPT) <= n;
+  double2 aq[EPT], aw[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = base + (size_t)k * NT;
+    const bool in = full || e < n;
+    aq[k] = in ? ld<double, S>(V + e) : make_double2(0.0, 0.0);
+    aw[k] = in ? ld<double, S>(Wv + e) : make_double2(0.0, 0.0);
+  }
+  for (int i = 0; i < j; ++i) {
+    const double2 si = sr[i], di = dr[i];
+    const c2<S>* Ai = Qr + (size_t)i * q_vs + base;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      if (full || base + (size_t)k * NT < n) {
+        const double2 a = ld<double, S>(Ai + (size_t)k * NT);
+        aq[k].x = fma(-si.x, a.x, aq[k].x);
+        aq[k].x = fma(si.y, a.y, aq[k].x);
+        aq[k].y = fma(-si.x, a.y, aq[k].y);
+        aq[k].y = fma(-si.y, a.x, aq[k].y);
+        aw[k].x = fma(-di.x, a.x, aw[k].x);
+        aw[k].x = fma(di.y, a.y, aw[k].x);
+        aw[k].y = fma(-di.x, a.y, aw[k].y);
+        aw[k].y = fma(-di.y, a.x, aw[k].y);
+      }
+    }
+  }
+  const double2 dj = dr[j];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const size_t e = base + (size_t)k * NT;
+    if (full || e < n) {
+      const c2<S> q = mk<S>((S)(aq[k].x * inu), (S)(aq[k].y * inu));
+      V[e] = q;
+      const double2 qd = make_double2((double)q.x, (double)q.y);  // the stored (rounded) q_j
+      double2 y = aw[k];
+      y.x = fma(-dj.x, qd.x, y.x);
+      y.x = fma(dj.y, qd.y, y.x);
+      y.y = fma(-dj.x, qd.y, y.y);
+      y.y = fma(-dj.y, qd.x, y.y);
+      Wv[e] = mk<S>((S)(y.x * inu), (S)(y.y * inu));
+    }
+  }
+}
+
 inline int blocks_split(size_t units, int nrhs) {
   int e = 8;
   while (e > 1 && ((units + e - 1) / e) * (size_t)nrhs < 2048) e >>= 1;
@@ -898,6 +1237,64 @@ hipError_t launch_lsq(const GmresState* state, const double2* R, const double2* 
   hipLaunchKernelGGL(k_lsq, dim3(nrhs), dim3(64), 0, st, state, R, g, y, m, active);
   return hipGetLastError();
 }
+
+template <class S>
+hipError_t launch_dots2(const c2<S>* Q, size_t q_vs, int nq, const c2<S>* V, const c2<S>* W, size_t rs, size_t n,
+                        int nrhs, double2* part, double2* out, int ostride, int* counter, const int* live,
+                        hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  if (nq < 0 || nq + 1 > kFusedMaxNv || ostride < 2 * (nq + 1)) return hipErrorInvalidValue;
+  const unsigned nchunk = (unsigned)((n + kDotChunk - 1) / kDotChunk);
+  if ((size_t)nchunk * nrhs >= 2048) {
+    hipLaunchKernelGGL((k_dots2<S, true>), dim3(nchunk, nrhs), dim3(NT), 0, st, Q, q_vs, nq, V, W, rs, n, part, out,
+                       ostride, counter, live);
+  } else {
+    const unsigned ngrp = (unsigned)((nq + 1 + kDots2G - 1) / kDots2G);
+    hipLaunchKernelGGL((k_dots2<S, false>), dim3(nchunk, ngrp, nrhs), dim3(NT), 0, st, Q, q_vs, nq, V, W, rs, n,
+                       part, out, ostride, counter, live);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dcgs_update(const double2* D, int dstride, int j, int m, int nrhs, GmresState* state, double2* Hu,
+                              double2* R, double* cs, double2* sn, double2* g, double2* c, double2* coef, int* live,
+                              hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  if (m > kFusedMaxNv || j > m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dcgs_update, dim3(nrhs), dim3(64), 0, st, D, dstride, j, m, state, Hu, R, cs, sn, g, c, coef,
+                     live);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_dcgs_axpy(c2<S>* Q, size_t q_vs, int j, size_t rs, size_t n, int nrhs, const double2* coef, int ld,
+                            const GmresState* state, const int* live, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  const int ept = blocks_split((n + NT - 1) / NT, nrhs);
+  dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
+#define DIE_DCGS_CASE(E)                                                                                         \
+  case E:                                                                                                        \
+    hipLaunchKernelGGL((k_dcgs_axpy<S, E>), grid, dim3(NT), 0, st, Q, q_vs, j, rs, n, coef, ld, state, live); \
+    break;
+  switch (ept) {
+    DIE_DCGS_CASE(1)
+    DIE_DCGS_CASE(2)
+    DIE_DCGS_CASE(4)
+    DIE_DCGS_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef DIE_DCGS_CASE
+  return hipGetLastError();
+}
+
+template hipError_t launch_dots2<double>(const double2*, size_t, int, const double2*, const double2*, size_t, size_t,
+                                         int, double2*, double2*, int, int*, const int*, hipStream_t);
+template hipError_t launch_dots2<float>(const float2*, size_t, int, const float2*, const float2*, size_t, size_t, int,
+                                        double2*, double2*, int, int*, const int*, hipStream_t);
+template hipError_t launch_dcgs_axpy<double>(double2*, size_t, int, size_t, size_t, int, const double2*, int,
+                                             const GmresState*, const int*, hipStream_t);
+template hipError_t launch_dcgs_axpy<float>(float2*, size_t, int, size_t, size_t, int, const double2*, int,
+                                            const GmresState*, const int*, hipStream_t);
 
 #define DIE_INST_FUSED(SA, SB)                                                                                    \
   template hipError_t launch_fdot<SA, SB>(const c2<SA>*, size_t, size_t, int, int, const c2<SB>*, size_t, size_t, \
