@@ -268,8 +268,8 @@ def main():
     bytes_per_launch = p["bytes"] / max(p["timed"], 1)
     achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
     src = source_hash("kernels_fft.hip" if dom == "product" else "kernels_krylov.hip")
-    kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "cgs_dots_c64_256_batched",
-                  "axpy": "cgs_axpy_c64_256_batched"}[dom]
+    kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "arnoldi_dots_c64_256_batched",
+                  "axpy": "arnoldi_axpy_c64_256_batched"}[dom]
     traffic = read_traffic(kernel_tag, src, bytes_per_launch)
     traffic = None if traffic is None else int(traffic)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
