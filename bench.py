@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--orth", type=int, default=1, choices=(0, 1),
                     help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
+    ap.add_argument("--basis", type=int, default=16, choices=(16, 32),
+                    help="bits per real part of the stored Krylov basis in the batched run (16 needs --orth 1)")
     ap.add_argument("--learned", type=int, default=0, metavar="NTRAIN",
                     help="train the warm-start U-Net (4 levels, 32 channels) on NTRAIN method-generated 256^2 "
                          "solves, then time the batch from its guesses (several minutes)")
@@ -231,7 +233,8 @@ def main():
     log(f"setup of {nobj} objects on {g.nx}x{g.ny}: {setup_s:.3f} s")
 
     def batch_solve():
-        return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=True, orth=args.orth)
+        return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=2 if args.basis == 16 else 1,
+                       orth=args.orth)
 
     for i in range(args.warmup):
         _, rc, info = batch_solve()
@@ -287,11 +290,13 @@ def main():
         "metric": "TE solves/s to rel-res 1e-8 (plain vs mixed/batched/learned); matvec % HBM peak",
         "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 products and basis, f64 refinement", "data": "synthetic",
+        "dtype": f"f32 products, {'f16' if args.basis == 16 else 'f32'} basis storage, f64 dots/Givens/refinement",
+        "data": "synthetic",
         "config": {"workload": f"random-field objects, 256x256 cells (h = lambda/48), {nobj} objects x "
                                f"{N_ANGLES} TE incidence angles = {nsolve} solves per step",
-                   "method": f"batched GMRES({RESTART}) on A, FP32 products/basis, FP64 true-residual "
-                             f"refinement per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call",
+                   "method": f"batched GMRES({RESTART}) on A, FP32 products, {args.basis}-bit basis storage, "
+                             f"{'one-reduction' if args.orth else 'two-pass'} CGS2, FP64 true-residual refinement "
+                             f"per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call",
                    "iters_mean": round(float(iters.mean()), 1), "iters_max": int(iters.max()),
                    "products_mean": round(float(prods.mean()), 1),
                    "rel_res_true_max": max(x["rel_res_true"] for x in last), "setup_s": round(setup_s, 3)},

@@ -82,7 +82,9 @@ typedef struct {
                         original (unregularized) operator; 0 -> 1e-8 */
   int mixed;         /* 0: FP64 throughout; 1: complex64 Krylov basis and operator products
                         inside an FP64 refinement loop (true residual, Hessenberg, Givens
-                        and the deflation basis stay FP64) */
+                        and the deflation basis stay FP64); 2: as 1 with the Krylov basis
+                        stored as complex binary16 (half the basis traffic; dots, Hessenberg
+                        and Givens still FP64; needs orth = 1) */
   int x0_given;      /* 1: e_tot holds the initial guess on entry; 0: start from zero */
   double reg_margin; /* regularized runs end a cycle when the regularized residual estimate
                         reaches reg_margin * (the target scaled to the cycle); 0 -> 0.1 */

@@ -67,9 +67,11 @@ def die_te_regularize(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
 
 
 def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, restart: int = 30,
-                 max_iters: int = 100_000, tol: float = 1e-8, mixed: bool = False, x0_given: bool = False,
+                 max_iters: int = 100_000, tol: float = 1e-8, mixed: int = 0, x0_given: bool = False,
                  reg_margin: float = 0.0, orth: int = 0) -> tuple[int, list[dict]]:
-    o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(bool(mixed)), int(bool(x0_given)),
+    """mixed: 0 FP64, 1 (or True) complex64 products and basis, 2 complex64 products with a
+    binary16 basis (orth=1)."""
+    o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
                        float(reg_margin), int(orth))
     info = (DieTeSolveInfo * nrhs)()
     rc = load().die_te_solve(ctx, _dev(e_in, (torch.complex128,), "e_in"), _dev(e_tot, (torch.complex128,), "e_tot"),

@@ -9,6 +9,11 @@ namespace die {
 template <class T> struct c2t;
 template <> struct c2t<double> { using type = double2; };
 template <> struct c2t<float> { using type = float2; };
+// complex with IEEE binary16 parts: the storage type of the compressed Krylov basis
+struct alignas(4) half2c {
+  _Float16 x, y;
+};
+template <> struct c2t<_Float16> { using type = half2c; };
 template <class T> using c2 = typename c2t<T>::type;
 
 template <class T> __host__ __device__ __forceinline__ c2<T> mk(T re, T im) {

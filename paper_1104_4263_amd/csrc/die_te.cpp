@@ -399,7 +399,9 @@ int run_eigs(die_te_ctx* c, int obj, int r, double tol, int mk, int maxrst, unsi
 }
 
 // ------------------------------------------------------------------ GMRES
-template <class T>
+// T: precision of the cycle's products and vectors; TB: storage of the Krylov basis in the
+// one-reduction path (T, or binary16 for the compressed basis).
+template <class T, class TB = T>
 int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
                 die_te_solve_info* info, hipStream_t st) {
   const size_t n = c->nvec;
@@ -415,7 +417,15 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
   const int nvmax = std::max(m + 1, c->r);
   DBuf Q, Zb, Tb, Wb, Rs, Sd, part, partn, h1, h2, hd, Rm, cs, sn, g, y, state, live, active, nrm, cnt;
-  DIE_TRY(Q.alloc((size_t)(m + 1) * vbytes));
+  DBuf Qb, Vf, Wf;  // one-reduction path: basis q_0..q_{m-1} (TB), current v and w (T)
+  const bool dcgs = o.orth == 1;
+  if (dcgs) {
+    DIE_TRY(Qb.alloc((size_t)m * nrhs * n * sizeof(c2<TB>)));
+    DIE_TRY(Vf.alloc(vbytes));
+    DIE_TRY(Wf.alloc(vbytes));
+  } else {
+    DIE_TRY(Q.alloc((size_t)(m + 1) * vbytes));
+  }
   if (defl) DIE_TRY(Zb.alloc(vbytes));
   if (reg) DIE_TRY(Tb.alloc(vbytes));
   DIE_TRY(Wb.alloc(vbytes));
@@ -441,7 +451,6 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   int* dcnt = cnt.as<int>();
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * std::max(sizeof(c2<T>), sizeof(double2)), st));
   // one-reduction Arnoldi: raw dots, unrotated Hessenberg, first projections, axpy coefficients
-  const bool dcgs = o.orth == 1;
   const int dstride = 2 * (m + 2);
   DBuf Dd, Hu, cprev, coef, part2;
   if (dcgs) {
@@ -453,6 +462,9 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   }
 
   c2<T>* q = Q.as<c2<T>>();
+  c2<TB>* qb = Qb.as<c2<TB>>();
+  c2<T>* vf = Vf.as<c2<T>>();
+  c2<T>* wf = Wf.as<c2<T>>();
   const size_t vs = (size_t)nrhs * n;  // stride between basis vectors j
   double2* res = Rs.as<double2>();
   std::vector<double> bnorm(nrhs), rnorm(nrhs), hn(nrhs);
@@ -556,13 +568,13 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     DIE_HIP(hipMemcpyAsync(live.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     int* dlive = live.as<int>();
-    DIE_HIP((die::launch_scale<double, T>(s, n, q, n, sc.as<double>(), 1, n, nrhs, dact, st)));
+    DIE_HIP((die::launch_scale<double, T>(s, n, dcgs ? vf : q, n, sc.as<double>(), 1, n, nrhs, dact, st)));
     // ---- Arnoldi / GMRES iterations of this cycle
     for (int j = 0; dcgs && j <= m; ++j) {
-      // one-reduction step j: product on the slot-j vector, one dots pass, scalar update,
-      // one pass writing q_j and the next vector
-      c2<T>* v = q + (size_t)j * vs;
-      c2<T>* w = j < m ? q + (size_t)(j + 1) * vs : nullptr;
+      // one-reduction step j: product on v, one dots pass, scalar update, one pass writing
+      // q_j into the basis and the next v
+      c2<T>* v = vf;
+      c2<T>* w = j < m ? wf : nullptr;
       if (w) {
         const c2<T>* zin = v;
         if (defl) {
@@ -572,19 +584,21 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
         }
         DIE_TRY(apply_M<T>(c, reg, zin, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
       }
-      const double vb = (double)live_count(c, nrhs) * n * sizeof(c2<T>);
+      // algorithmic bytes: j basis vectors in TB, v and w in T
+      const double nl = (double)live_count(c, nrhs) * n;
+      const double bb = nl * sizeof(c2<TB>), vb = nl * sizeof(c2<T>);
       {
-        ProfScope prof(c, DIE_PROF_DOTS, st, vb * (j + 1 + (w ? 1 : 0)));
-        DIE_HIP((die::launch_dots2<T>(q, vs, j, v, w, n, n, nrhs, part2.as<double2>(), Dd.as<double2>(), dstride, dcnt,
-                                      dlive, st)));
+        ProfScope prof(c, DIE_PROF_DOTS, st, bb * j + vb * (w ? 2 : 1));
+        DIE_HIP((die::launch_dots2<TB, T>(qb, vs, j, v, w, n, n, nrhs, part2.as<double2>(), Dd.as<double2>(), dstride,
+                                          dcnt, dlive, st)));
       }
       DIE_HIP(die::launch_dcgs_update(Dd.as<double2>(), dstride, j, m, nrhs, state.as<die::GmresState>(),
                                       Hu.as<double2>(), Rm.as<double2>(), cs.as<double>(), sn.as<double2>(),
                                       g.as<double2>(), cprev.as<double2>(), coef.as<double2>(), dlive, st));
       if (j < m) {
-        ProfScope prof(c, DIE_PROF_AXPY, st, vb * (j + 4));
-        DIE_HIP((die::launch_dcgs_axpy<T>(q, vs, j, n, n, nrhs, coef.as<double2>(), m + 1,
-                                          state.as<die::GmresState>(), dlive, st)));
+        ProfScope prof(c, DIE_PROF_AXPY, st, bb * (j + 1) + vb * 3);
+        DIE_HIP((die::launch_dcgs_axpy<TB, T>(qb, vs, j, vf, wf, n, n, nrhs, coef.as<double2>(), m + 1,
+                                              state.as<die::GmresState>(), dlive, st)));
       }
     }
     for (int j = 0; !dcgs && j < m; ++j) {
@@ -633,8 +647,12 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     for (int r = 0; r < nrhs; ++r) jn[r] = act[r] ? hst[r].j : 0;
     DIE_HIP(hipMemcpyAsync(jd.p, jn.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     c2<T>* t = Wb.as<c2<T>>();
-    DIE_HIP((die::launch_maxpy<T, T, T>(0, q, vs, n, m, jd.as<int>(), y.as<double2>(), m, (const c2<T>*)nullptr, 0,
-                                        0.0, t, n, 0.0, n, nrhs, nullptr, nullptr, dact, st)));
+    if (dcgs)
+      DIE_HIP((die::launch_maxpy<TB, T, T>(0, qb, vs, n, m, jd.as<int>(), y.as<double2>(), m, (const c2<T>*)nullptr,
+                                           0, 0.0, t, n, 0.0, n, nrhs, nullptr, nullptr, dact, st)));
+    else
+      DIE_HIP((die::launch_maxpy<T, T, T>(0, q, vs, n, m, jd.as<int>(), y.as<double2>(), m, (const c2<T>*)nullptr, 0,
+                                          0.0, t, n, 0.0, n, nrhs, nullptr, nullptr, dact, st)));
     if (defl) {
       // t += V (C (V^* t)) with each object's V and C, then u += t below
       DIE_TRY(apply_pinv<T>(c, t, t, nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dact, st, rpo));
@@ -836,6 +854,10 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   if (o.max_iters < 1) return fail(DIE_E_INVALID, "max_iters must be >= 1");
   if (o.tol < 0 || !std::isfinite(o.tol)) return fail(DIE_E_INVALID, "tol must be >= 0");
   hipStream_t st = (hipStream_t)stream;
+  if (o.mixed < 0 || o.mixed > 2) return fail(DIE_E_INVALID, "mixed must be 0, 1 or 2");
+  if (o.mixed == 2 && o.orth != 1) return fail(DIE_E_INVALID, "mixed = 2 (binary16 basis) needs orth = 1");
+  if (o.mixed == 2)
+    return gmres_solve<float, _Float16>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
   if (o.mixed) return gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
   return gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
 }

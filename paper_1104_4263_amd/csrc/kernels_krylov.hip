@@ -838,19 +838,19 @@ k_lsq(const GmresState* __restrict__ state, const double2* __restrict__ Rm, cons
 
 constexpr int kDots2G = 2;  // vectors per group: 2 vectors x 2 targets x (re, im) = 8 values
 
-template <class S, bool FULL>
-__device__ __forceinline__ void dots2_group(const c2<S>* __restrict__ Qr, size_t q_vs, int i0, int gn, size_t base,
+template <class SQ, bool FULL>
+__device__ __forceinline__ void dots2_group(const c2<SQ>* __restrict__ Qr, size_t q_vs, int i0, int gn, size_t base,
                                             size_t n, const double2 (&b0)[kDotEpt], const double2 (&b1)[kDotEpt],
                                             double (&v)[8]) {
 #pragma unroll
   for (int g = 0; g < kDots2G; ++g) {
     double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
     if (g < gn) {
-      const c2<S>* Ai = Qr + (size_t)(i0 + g) * q_vs + base;
+      const c2<SQ>* Ai = Qr + (size_t)(i0 + g) * q_vs + base;
 #pragma unroll
       for (int k = 0; k < kDotEpt; ++k) {
         if (FULL || base + (size_t)k * NT < n) {
-          const double2 a = ld<double, S>(Ai + (size_t)k * NT);
+          const double2 a = ld<double, SQ>(Ai + (size_t)k * NT);
           s0x = fma(a.x, b0[k].x, s0x);
           s0x = fma(a.y, b0[k].y, s0x);
           s0y = fma(a.x, b0[k].y, s0y);
@@ -870,12 +870,13 @@ __device__ __forceinline__ void dots2_group(const c2<S>* __restrict__ Qr, size_t
 }
 
 // out[r ostride + 2 i + t] = conj(A_i,r) . T_t,r for A_0..A_{nq-1} = Q, A_nq = V, T_0 = V,
-// T_1 = W (W null: T_1 = 0).  Same shapes and fixed-order sums as k_dots.
-template <class S, bool WALK>
+// T_1 = W (W null: T_1 = 0).  Same shapes and fixed-order sums as k_dots.  The basis Q is
+// stored in SQ, V and W in SV.
+template <class SQ, class SV, bool WALK>
 __global__ void __launch_bounds__(NT)
-k_dots2(const c2<S>* __restrict__ Q, size_t q_vs, int nq, const c2<S>* __restrict__ V, const c2<S>* __restrict__ Wt,
-        size_t rs, size_t n, double2* __restrict__ part, double2* __restrict__ out, int ostride,
-        int* __restrict__ counter, const int* __restrict__ live) {
+k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restrict__ V,
+        const c2<SV>* __restrict__ Wt, size_t rs, size_t n, double2* __restrict__ part, double2* __restrict__ out,
+        int ostride, int* __restrict__ counter, const int* __restrict__ live) {
   const int r = WALK ? blockIdx.y : blockIdx.z;
   if (live && !live[r]) return;
   __shared__ double red[8][NT];
@@ -883,15 +884,15 @@ k_dots2(const c2<S>* __restrict__ Q, size_t q_vs, int nq, const c2<S>* __restric
   const int nA = nq + 1, nchunk = gridDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const size_t base = (size_t)blockIdx.x * kDotChunk + t;
   const bool full = (size_t)(blockIdx.x + 1) * kDotChunk <= n;
-  const c2<S>* Qr = Q + (size_t)r * rs;
-  const c2<S>* Vr = V + (size_t)r * rs;
-  const c2<S>* Wr = Wt ? Wt + (size_t)r * rs : nullptr;
+  const c2<SQ>* Qr = Q + (size_t)r * rs;
+  const c2<SV>* Vr = V + (size_t)r * rs;
+  const c2<SV>* Wr = Wt ? Wt + (size_t)r * rs : nullptr;
   double2 b0[kDotEpt], b1[kDotEpt];
 #pragma unroll
   for (int k = 0; k < kDotEpt; ++k) {
     const size_t e = base + (size_t)k * NT;
-    b0[k] = e < n ? ld<double, S>(Vr + e) : make_double2(0.0, 0.0);
-    b1[k] = (Wr && e < n) ? ld<double, S>(Wr + e) : make_double2(0.0, 0.0);
+    b0[k] = e < n ? ld<double, SV>(Vr + e) : make_double2(0.0, 0.0);
+    b1[k] = (Wr && e < n) ? ld<double, SV>(Wr + e) : make_double2(0.0, 0.0);
   }
   const int ifirst = WALK ? 0 : blockIdx.y * kDots2G, iend = WALK ? nA : min(nA, ifirst + kDots2G);
   const int rv = t >> 5, rl = t & 31;
@@ -917,8 +918,8 @@ k_dots2(const c2<S>* __restrict__ Q, size_t q_vs, int nq, const c2<S>* __restric
   for (int i0 = ifirst; i0 < min(iend, nq); i0 += kDots2G) {
     const int gn = min(kDots2G, nq - i0);
     double v[8];
-    if (full) dots2_group<S, true>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
-    else dots2_group<S, false>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
+    if (full) dots2_group<SQ, true>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
+    else dots2_group<SQ, false>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
     reduce_store(v, i0, gn);
   }
   // A_nq = V: v^H v and v^H w from the target values already in registers
@@ -1121,18 +1122,21 @@ k_dcgs_update(const double2* __restrict__ D, int dstride, int j, int m, GmresSta
   }
 }
 
-// q_j = (v - Q s) / nu into slot j and v_{j+1} = (w - Q d_{<j} - q_j d_j) / nu into slot
-// j+1, one pass over Q_0..Q_{j-1} (EPT elements per thread).
-template <class S, int EPT>
+// q_j = (v - Q s) / nu into basis slot j and v_{j+1} = (w - Q d_{<j} - q_j d_j) / nu into V
+// (in place), one pass over Q_0..Q_{j-1} (EPT elements per thread).  Basis in SQ, V and W
+// in SV; d_j multiplies the stored (rounded) q_j.
+template <class SQ, class SV, int EPT>
 __global__ void __launch_bounds__(NT)
-k_dcgs_axpy(c2<S>* __restrict__ Q, size_t q_vs, int j, size_t rs, size_t n, const double2* __restrict__ coef,
-            int cld, const GmresState* __restrict__ state, const int* __restrict__ live) {
+k_dcgs_axpy(c2<SQ>* __restrict__ Q, size_t q_vs, int j, c2<SV>* __restrict__ V, const c2<SV>* __restrict__ Wt,
+            size_t rs, size_t n, const double2* __restrict__ coef, int cld, const GmresState* __restrict__ state,
+            const int* __restrict__ live) {
   const int r = blockIdx.y;
   if (!live[r]) return;
   const double inu = state[r].invbeta;
-  c2<S>* Qr = Q + (size_t)r * rs;
-  c2<S>* V = Qr + (size_t)j * q_vs;
-  c2<S>* Wv = Qr + (size_t)(j + 1) * q_vs;
+  c2<SQ>* Qr = Q + (size_t)r * rs;
+  c2<SQ>* Qj = Qr + (size_t)j * q_vs;
+  c2<SV>* Vr = V + (size_t)r * rs;
+  const c2<SV>* Wr = Wt + (size_t)r * rs;
   const double2* sr = coef + (size_t)r * 2 * cld;
   const double2* dr = sr + cld;
   const size_t base = (size_t)blockIdx.x * (NT * EPT) + threadIdx.x;
@@ -1142,16 +1146,16 @@ k_dcgs_axpy(c2<S>* __restrict__ Q, size_t q_vs, int j, size_t rs, size_t n, cons
   for (int k = 0; k < EPT; ++k) {
     const size_t e = base + (size_t)k * NT;
     const bool in = full || e < n;
-    aq[k] = in ? ld<double, S>(V + e) : make_double2(0.0, 0.0);
-    aw[k] = in ? ld<double, S>(Wv + e) : make_double2(0.0, 0.0);
+    aq[k] = in ? ld<double, SV>(Vr + e) : make_double2(0.0, 0.0);
+    aw[k] = in ? ld<double, SV>(Wr + e) : make_double2(0.0, 0.0);
   }
   for (int i = 0; i < j; ++i) {
     const double2 si = sr[i], di = dr[i];
-    const c2<S>* Ai = Qr + (size_t)i * q_vs + base;
+    const c2<SQ>* Ai = Qr + (size_t)i * q_vs + base;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       if (full || base + (size_t)k * NT < n) {
-        const double2 a = ld<double, S>(Ai + (size_t)k * NT);
+        const double2 a = ld<double, SQ>(Ai + (size_t)k * NT);
         aq[k].x = fma(-si.x, a.x, aq[k].x);
         aq[k].x = fma(si.y, a.y, aq[k].x);
         aq[k].y = fma(-si.x, a.y, aq[k].y);
@@ -1168,15 +1172,15 @@ k_dcgs_axpy(c2<S>* __restrict__ Q, size_t q_vs, int j, size_t rs, size_t n, cons
   for (int k = 0; k < EPT; ++k) {
     const size_t e = base + (size_t)k * NT;
     if (full || e < n) {
-      const c2<S> q = mk<S>((S)(aq[k].x * inu), (S)(aq[k].y * inu));
-      V[e] = q;
+      const c2<SQ> q = mk<SQ>((SQ)(aq[k].x * inu), (SQ)(aq[k].y * inu));
+      Qj[e] = q;
       const double2 qd = make_double2((double)q.x, (double)q.y);  // the stored (rounded) q_j
       double2 y = aw[k];
       y.x = fma(-dj.x, qd.x, y.x);
       y.x = fma(dj.y, qd.y, y.x);
       y.y = fma(-dj.x, qd.y, y.y);
       y.y = fma(-dj.y, qd.x, y.y);
-      Wv[e] = mk<S>((S)(y.x * inu), (S)(y.y * inu));
+      Vr[e] = mk<SV>((SV)(y.x * inu), (SV)(y.y * inu));
     }
   }
 }
@@ -1257,20 +1261,20 @@ hipError_t launch_lsq(const GmresState* state, const double2* R, const double2* 
   return hipGetLastError();
 }
 
-template <class S>
-hipError_t launch_dots2(const c2<S>* Q, size_t q_vs, int nq, const c2<S>* V, const c2<S>* W, size_t rs, size_t n,
+template <class SQ, class SV>
+hipError_t launch_dots2(const c2<SQ>* Q, size_t q_vs, int nq, const c2<SV>* V, const c2<SV>* W, size_t rs, size_t n,
                         int nrhs, double2* part, double2* out, int ostride, int* counter, const int* live,
                         hipStream_t st) {
   if (nrhs <= 0) return hipSuccess;
   if (nq < 0 || nq + 1 > kFusedMaxNv || ostride < 2 * (nq + 1)) return hipErrorInvalidValue;
   const unsigned nchunk = (unsigned)((n + kDotChunk - 1) / kDotChunk);
   if ((size_t)nchunk * nrhs >= 2048) {
-    hipLaunchKernelGGL((k_dots2<S, true>), dim3(nchunk, nrhs), dim3(NT), 0, st, Q, q_vs, nq, V, W, rs, n, part, out,
-                       ostride, counter, live);
+    hipLaunchKernelGGL((k_dots2<SQ, SV, true>), dim3(nchunk, nrhs), dim3(NT), 0, st, Q, q_vs, nq, V, W, rs, n, part,
+                       out, ostride, counter, live);
   } else {
     const unsigned ngrp = (unsigned)((nq + 1 + kDots2G - 1) / kDots2G);
-    hipLaunchKernelGGL((k_dots2<S, false>), dim3(nchunk, ngrp, nrhs), dim3(NT), 0, st, Q, q_vs, nq, V, W, rs, n,
-                       part, out, ostride, counter, live);
+    hipLaunchKernelGGL((k_dots2<SQ, SV, false>), dim3(nchunk, ngrp, nrhs), dim3(NT), 0, st, Q, q_vs, nq, V, W, rs,
+                       n, part, out, ostride, counter, live);
   }
   return hipGetLastError();
 }
@@ -1285,36 +1289,40 @@ hipError_t launch_dcgs_update(const double2* D, int dstride, int j, int m, int n
   return hipGetLastError();
 }
 
-template <class S>
-hipError_t launch_dcgs_axpy(c2<S>* Q, size_t q_vs, int j, size_t rs, size_t n, int nrhs, const double2* coef, int ld,
-                            const GmresState* state, const int* live, hipStream_t st) {
+template <class SQ, class SV>
+hipError_t launch_dcgs_axpy(c2<SQ>* Q, size_t q_vs, int j, c2<SV>* V, const c2<SV>* W, size_t rs, size_t n, int nrhs,
+                            const double2* coef, int ld, const GmresState* state, const int* live, hipStream_t st) {
   if (nrhs <= 0) return hipSuccess;
   // at most 4 elements per thread: 8 needs 84 VGPRs and measured 4.4 against 5.3 TB/s
   const int ept = std::min(4, blocks_split((n + NT - 1) / NT, nrhs));
   dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
-#define DIE_DCGS_CASE(E)                                                                                         \
-  case E:                                                                                                        \
-    hipLaunchKernelGGL((k_dcgs_axpy<S, E>), grid, dim3(NT), 0, st, Q, q_vs, j, rs, n, coef, ld, state, live); \
+#define DIE_DCGS_CASE(E)                                                                                       \
+  case E:                                                                                                      \
+    hipLaunchKernelGGL((k_dcgs_axpy<SQ, SV, E>), grid, dim3(NT), 0, st, Q, q_vs, j, V, W, rs, n, coef, ld, state, \
+                       live);                                                                                  \
     break;
   switch (ept) {
     DIE_DCGS_CASE(1)
     DIE_DCGS_CASE(2)
     DIE_DCGS_CASE(4)
-    DIE_DCGS_CASE(8)
     default: return hipErrorInvalidValue;
   }
 #undef DIE_DCGS_CASE
   return hipGetLastError();
 }
 
-template hipError_t launch_dots2<double>(const double2*, size_t, int, const double2*, const double2*, size_t, size_t,
-                                         int, double2*, double2*, int, int*, const int*, hipStream_t);
-template hipError_t launch_dots2<float>(const float2*, size_t, int, const float2*, const float2*, size_t, size_t, int,
-                                        double2*, double2*, int, int*, const int*, hipStream_t);
-template hipError_t launch_dcgs_axpy<double>(double2*, size_t, int, size_t, size_t, int, const double2*, int,
-                                             const GmresState*, const int*, hipStream_t);
-template hipError_t launch_dcgs_axpy<float>(float2*, size_t, int, size_t, size_t, int, const double2*, int,
-                                            const GmresState*, const int*, hipStream_t);
+#define DIE_INST_DCGS(SQ, SV)                                                                                      \
+  template hipError_t launch_dots2<SQ, SV>(const c2<SQ>*, size_t, int, const c2<SV>*, const c2<SV>*, size_t,       \
+                                           size_t, int, double2*, double2*, int, int*, const int*, hipStream_t);   \
+  template hipError_t launch_dcgs_axpy<SQ, SV>(c2<SQ>*, size_t, int, c2<SV>*, const c2<SV>*, size_t, size_t, int,  \
+                                               const double2*, int, const GmresState*, const int*, hipStream_t);
+DIE_INST_DCGS(double, double)
+DIE_INST_DCGS(float, float)
+DIE_INST_DCGS(_Float16, float)
+template hipError_t launch_maxpy<_Float16, float, float>(int, const half2c*, size_t, size_t, int, const int*,
+                                                         const double2*, int, const float2*, size_t, double, float2*,
+                                                         size_t, double, size_t, int, double2*, double*, const int*,
+                                                         hipStream_t);
 
 #define DIE_INST_FUSED(SA, SB)                                                                                    \
   template hipError_t launch_fdot<SA, SB>(const c2<SA>*, size_t, size_t, int, int, const c2<SB>*, size_t, size_t, \

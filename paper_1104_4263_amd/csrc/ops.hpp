@@ -141,16 +141,17 @@ hipError_t launch_faxpy_givens(const c2<SA>* A, size_t a_vs, size_t a_rs, int nv
 // Q_0..Q_{nq-1} and V against V and W (W null: zero second target), out[r ostride + 2 i + t]; the per-rhs scalar update of step j (delayed column j-1,
 // Givens, stopping, coefficients); the pass that writes q_j and v_{j+1}.
 // part: nrhs * gmres_part_elems(n, 2 (nq + 1)); counter as for launch_fdot.
-template <class S>
-hipError_t launch_dots2(const c2<S>* Q, size_t q_vs, int nq, const c2<S>* V, const c2<S>* W, size_t rs, size_t n,
+template <class SQ, class SV>
+hipError_t launch_dots2(const c2<SQ>* Q, size_t q_vs, int nq, const c2<SV>* V, const c2<SV>* W, size_t rs, size_t n,
                         int nrhs, double2* part, double2* out, int ostride, int* counter, const int* live,
                         hipStream_t st);
 hipError_t launch_dcgs_update(const double2* D, int dstride, int j, int m, int nrhs, GmresState* state, double2* Hu,
                               double2* R, double* cs, double2* sn, double2* g, double2* c, double2* coef, int* live,
                               hipStream_t st);
-template <class S>
-hipError_t launch_dcgs_axpy(c2<S>* Q, size_t q_vs, int j, size_t rs, size_t n, int nrhs, const double2* coef, int ld,
-                            const GmresState* state, const int* live, hipStream_t st);
+// q_j into basis slot j (Q), v_{j+1} into V in place, reading w from W.
+template <class SQ, class SV>
+hipError_t launch_dcgs_axpy(c2<SQ>* Q, size_t q_vs, int j, c2<SV>* V, const c2<SV>* W, size_t rs, size_t n, int nrhs,
+                            const double2* coef, int ld, const GmresState* state, const int* live, hipStream_t st);
 hipError_t launch_lsq(const GmresState* state, const double2* R, const double2* g, double2* y, int m, int nrhs,
                       const int* active, hipStream_t st);
 

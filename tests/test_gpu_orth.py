@@ -50,14 +50,14 @@ def test_one_reduction_batched_random_fields():
     psis = [0.0, 1.3, 2.6]
     b = np.concatenate([np.stack([plane_wave(g, p) for p in psis])] * len(objs))
     s = api.Solver.from_grid(g, eps)
-    for mixed in (False, True):
+    for mixed in (0, 1, 2):
         u1, rc1, i1 = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=mixed, orth=1)
-        u0, rc0, i0 = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=mixed, orth=0)
+        u0, rc0, i0 = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=min(mixed, 1), orth=0)
         assert rc1 == 0 and rc0 == 0
         it1 = np.array([x["iters"] for x in i1])
         it0 = np.array([x["iters"] for x in i0])
         say(f"  mixed={mixed}: iters orth1 {it1.tolist()} orth0 {it0.tolist()}")
-        assert it1.sum() <= 1.05 * it0.sum() + 5
+        assert it1.sum() <= (1.05 if mixed < 2 else 1.3) * it0.sum() + 5
         assert rel(host(u1), host(u0)) < 1e-6
         for o in range(len(objs)):
             sl = slice(3 * o, 3 * o + 3)
@@ -67,3 +67,31 @@ def test_one_reduction_batched_random_fields():
     u, rc, info = one.solve(dev(b[1]), restart=30, max_iters=20000, tol=1e-8, orth=1)
     _, _, ib = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, orth=1)
     assert info[0]["iters"] == ib[1]["iters"]
+
+
+@pytest.mark.parametrize("eps_obj,reg,defl", [(4.0 + 0j, False, 0), (-2.5 + 0.2j, True, 8), (16.0 + 0j, False, 6)])
+def test_binary16_basis_matches_lu(eps_obj, reg, defl):
+    """mixed=2 stores the Krylov basis as complex binary16: the FP64 refinement still
+    brings every solution to 1e-8; the iteration count may grow a little."""
+    say(f"binary16 basis eps={eps_obj} reg={reg} defl={defl}")
+    g = centred_grid(24, 1.0, ny=20)
+    eps = cylinder(g, 0.35, eps_obj)
+    b = np.stack([plane_wave(g, 0.3), plane_wave(g, 2.1)])
+    u_lu = op.solve_dense(g, eps, b)
+    s = api.Solver.from_grid(g, eps, regularize=reg, deflate_k=defl, seed=3)
+    u2, rc2, i2 = s.solve(dev(b), restart=20, max_iters=40000, tol=1e-8, mixed=2, orth=1)
+    _, rc1, i1 = s.solve(dev(b), restart=20, max_iters=40000, tol=1e-8, mixed=1, orth=1)
+    assert rc2 == 0 and rc1 == 0
+    uh = host(u2)
+    for r in range(2):
+        assert i2[r]["rel_res_true"] <= 1e-8
+        assert op.relative_residual(g, eps, uh[r], b[r]) <= 1.02e-8
+        assert rel(uh[r], u_lu[r]) < 2e-5
+        say(f"  rhs {r}: iters binary16 {i2[r]['iters']} complex64 {i1[r]['iters']}")
+
+
+def test_binary16_basis_needs_one_reduction():
+    g = centred_grid(16, 1.0)
+    s = api.Solver.from_grid(g, cylinder(g, 0.3, 4.0 + 0j))
+    with pytest.raises(Exception):
+        s.solve(dev(plane_wave(g, 0.0)), mixed=2, orth=0)
