@@ -4,10 +4,12 @@ Headline workload: the 256 x 256 size class of the batched random-field workload
 four objects (seeds 1004..1007: Re eps = 1 + 9U, Im eps = 0.5 U2, correlation length
 lambda/2, masked to a random ellipse; h = lambda/48, so 5.33 wavelengths across) lit
 by 64 equispaced TE plane waves each: 256 solves.  A step solves all 256 in one call
-of the batched solver: FP32 (complex64) operator products and Arnoldi basis inside
-restarted GMRES(30), every cycle restarted from the FP64 true residual, tol 1e-8 on
-that residual, zero initial guess.  Inputs are resident in HBM before the timed region;
-the per-object setup (symbol) is done once, outside it.
+of the batched solver: FP32 (complex64) operator products inside restarted GMRES(30)
+with the one-reduction Arnoldi and the Krylov basis stored as complex binary16 (dots,
+Hessenberg and Givens in FP64; --basis 32 / --orth 0 select the complex64 basis and the
+two-pass CGS2), every cycle restarted from the FP64 true residual, tol 1e-8 on that
+residual, zero initial guess.  Inputs are resident in HBM before the timed region; the
+per-object setup (symbol) is done once, outside it.
 
 The configured deflation (k = 16 largest-magnitude eigenvalues) is not applied in the
 headline: on these objects GMRES(30) on A P^-1 stagnates near 3e-2 for many angles (an
@@ -15,8 +17,8 @@ independent scipy GMRES(30) with ARPACK eigenvectors stagnates at the same value
 deflation is measured as a variant (--configured-deflation) and the headline and the
 plain baseline both solve the undeflated system A.
 
-Reported next to it: the plain solver (FP64, one right-hand side per call, same method,
-a sample of 16 of the 256 solves), the product throughput at the batched shape and at
+Reported next to it: the plain solver (FP64 products and basis, one right-hand side per
+call, the same GMRES(30) and orthogonalisation, a sample of 16 of the 256 solves), the product throughput at the batched shape and at
 the 1024^2 class (64 fields), the hard-cylinder variants (regularizer, deflation,
 mixed precision) and the FP64 oracle on the host.
 
