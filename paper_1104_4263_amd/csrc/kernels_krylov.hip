@@ -838,6 +838,25 @@ k_lsq(const GmresState* __restrict__ state, const double2* __restrict__ Rm, cons
 
 constexpr int kDots2G = 2;  // vectors per group: 2 vectors x 2 targets x (re, im) = 8 values
 
+// Two consecutive complex values in one access (8 bytes for binary16 parts, 16 for float,
+// 32 for double).  The one-reduction kernels give each thread pairs (2t, 2t + 1) of every
+// 2 NT elements; vector lengths are even (two field components), so a pair is either whole
+// inside a vector or whole outside.
+template <class S> struct alignas(2 * sizeof(c2<S>)) cpair {
+  c2<S> a, b;
+};
+template <class S> __device__ __forceinline__ void ld_pair(const c2<S>* p, double2& x, double2& y) {
+  const cpair<S> v = *reinterpret_cast<const cpair<S>*>(p);
+  x = make_double2((double)v.a.x, (double)v.a.y);
+  y = make_double2((double)v.b.x, (double)v.b.y);
+}
+template <class S> __device__ __forceinline__ cpair<S> mk_pair(double2 x, double2 y) {
+  cpair<S> v;
+  v.a = mk<S>((S)x.x, (S)x.y);
+  v.b = mk<S>((S)y.x, (S)y.y);
+  return v;
+}
+
 template <class SQ, bool FULL>
 __device__ __forceinline__ void dots2_group(const c2<SQ>* __restrict__ Qr, size_t q_vs, int i0, int gn, size_t base,
                                             size_t n, const double2 (&b0)[kDotEpt], const double2 (&b1)[kDotEpt],
@@ -847,10 +866,21 @@ __device__ __forceinline__ void dots2_group(const c2<SQ>* __restrict__ Qr, size_
     double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
     if (g < gn) {
       const c2<SQ>* Ai = Qr + (size_t)(i0 + g) * q_vs + base;
+      cpair<SQ> raw[kDotEpt / 2];  // kept in storage precision until used
+#pragma unroll
+      for (int p = 0; p < kDotEpt / 2; ++p) {
+        if (FULL || base + (size_t)p * 2 * NT < n) {
+          raw[p] = *reinterpret_cast<const cpair<SQ>*>(Ai + (size_t)p * 2 * NT);
+        } else {
+          raw[p].a = mk<SQ>((SQ)0, (SQ)0);
+          raw[p].b = raw[p].a;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < kDotEpt; ++k) {
-        if (FULL || base + (size_t)k * NT < n) {
-          const double2 a = ld<double, SQ>(Ai + (size_t)k * NT);
+        {
+          const c2<SQ> ak = (k & 1) ? raw[k / 2].b : raw[k / 2].a;
+          const double2 a = make_double2((double)ak.x, (double)ak.y);
           s0x = fma(a.x, b0[k].x, s0x);
           s0x = fma(a.y, b0[k].y, s0x);
           s0y = fma(a.x, b0[k].y, s0y);
@@ -882,17 +912,20 @@ k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restr
   __shared__ double red[8][NT];
   __shared__ int s_last;
   const int nA = nq + 1, nchunk = gridDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const size_t base = (size_t)blockIdx.x * kDotChunk + t;
+  const size_t base = (size_t)blockIdx.x * kDotChunk + 2 * t;  // pairs (base + 2 p NT, + 1)
   const bool full = (size_t)(blockIdx.x + 1) * kDotChunk <= n;
   const c2<SQ>* Qr = Q + (size_t)r * rs;
   const c2<SV>* Vr = V + (size_t)r * rs;
   const c2<SV>* Wr = Wt ? Wt + (size_t)r * rs : nullptr;
   double2 b0[kDotEpt], b1[kDotEpt];
 #pragma unroll
-  for (int k = 0; k < kDotEpt; ++k) {
-    const size_t e = base + (size_t)k * NT;
-    b0[k] = e < n ? ld<double, SV>(Vr + e) : make_double2(0.0, 0.0);
-    b1[k] = (Wr && e < n) ? ld<double, SV>(Wr + e) : make_double2(0.0, 0.0);
+  for (int p = 0; p < kDotEpt / 2; ++p) {
+    const size_t e = base + (size_t)p * 2 * NT;
+    b0[2 * p] = b0[2 * p + 1] = b1[2 * p] = b1[2 * p + 1] = make_double2(0.0, 0.0);
+    if (e < n) {
+      ld_pair<SV>(Vr + e, b0[2 * p], b0[2 * p + 1]);
+      if (Wr) ld_pair<SV>(Wr + e, b1[2 * p], b1[2 * p + 1]);
+    }
   }
   const int ifirst = WALK ? 0 : blockIdx.y * kDots2G, iend = WALK ? nA : min(nA, ifirst + kDots2G);
   const int rv = t >> 5, rl = t & 31;
@@ -1139,48 +1172,65 @@ k_dcgs_axpy(c2<SQ>* __restrict__ Q, size_t q_vs, int j, c2<SV>* __restrict__ V, 
   const c2<SV>* Wr = Wt + (size_t)r * rs;
   const double2* sr = coef + (size_t)r * 2 * cld;
   const double2* dr = sr + cld;
-  const size_t base = (size_t)blockIdx.x * (NT * EPT) + threadIdx.x;
+  static_assert(EPT % 2 == 0, "pairs of elements");
+  constexpr int NPR = EPT / 2;
+  const size_t base = (size_t)blockIdx.x * (NT * EPT) + 2 * threadIdx.x;  // pairs (base + 2 p NT, + 1)
   const bool full = (size_t)(blockIdx.x + 1) * (NT * EPT) <= n;
   double2 aq[EPT], aw[EPT];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const size_t e = base + (size_t)k * NT;
-    const bool in = full || e < n;
-    aq[k] = in ? ld<double, SV>(Vr + e) : make_double2(0.0, 0.0);
-    aw[k] = in ? ld<double, SV>(Wr + e) : make_double2(0.0, 0.0);
+  for (int p = 0; p < NPR; ++p) {
+    const size_t e = base + (size_t)p * 2 * NT;
+    aq[2 * p] = aq[2 * p + 1] = aw[2 * p] = aw[2 * p + 1] = make_double2(0.0, 0.0);
+    if (full || e < n) {
+      ld_pair<SV>(Vr + e, aq[2 * p], aq[2 * p + 1]);
+      ld_pair<SV>(Wr + e, aw[2 * p], aw[2 * p + 1]);
+    }
   }
   for (int i = 0; i < j; ++i) {
     const double2 si = sr[i], di = dr[i];
     const c2<SQ>* Ai = Qr + (size_t)i * q_vs + base;
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      if (full || base + (size_t)k * NT < n) {
-        const double2 a = ld<double, SQ>(Ai + (size_t)k * NT);
-        aq[k].x = fma(-si.x, a.x, aq[k].x);
-        aq[k].x = fma(si.y, a.y, aq[k].x);
-        aq[k].y = fma(-si.x, a.y, aq[k].y);
-        aq[k].y = fma(-si.y, a.x, aq[k].y);
-        aw[k].x = fma(-di.x, a.x, aw[k].x);
-        aw[k].x = fma(di.y, a.y, aw[k].x);
-        aw[k].y = fma(-di.x, a.y, aw[k].y);
-        aw[k].y = fma(-di.y, a.x, aw[k].y);
+    for (int p = 0; p < NPR; ++p) {
+      if (full || base + (size_t)p * 2 * NT < n) {
+        double2 a2[2];
+        ld_pair<SQ>(Ai + (size_t)p * 2 * NT, a2[0], a2[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = 2 * p + h;
+          const double2 a = a2[h];
+          aq[k].x = fma(-si.x, a.x, aq[k].x);
+          aq[k].x = fma(si.y, a.y, aq[k].x);
+          aq[k].y = fma(-si.x, a.y, aq[k].y);
+          aq[k].y = fma(-si.y, a.x, aq[k].y);
+          aw[k].x = fma(-di.x, a.x, aw[k].x);
+          aw[k].x = fma(di.y, a.y, aw[k].x);
+          aw[k].y = fma(-di.x, a.y, aw[k].y);
+          aw[k].y = fma(-di.y, a.x, aw[k].y);
+        }
       }
     }
   }
   const double2 dj = dr[j];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const size_t e = base + (size_t)k * NT;
+  for (int p = 0; p < NPR; ++p) {
+    const size_t e = base + (size_t)p * 2 * NT;
     if (full || e < n) {
-      const c2<SQ> q = mk<SQ>((SQ)(aq[k].x * inu), (SQ)(aq[k].y * inu));
-      Qj[e] = q;
-      const double2 qd = make_double2((double)q.x, (double)q.y);  // the stored (rounded) q_j
-      double2 y = aw[k];
-      y.x = fma(-dj.x, qd.x, y.x);
-      y.x = fma(dj.y, qd.y, y.x);
-      y.y = fma(-dj.x, qd.y, y.y);
-      y.y = fma(-dj.y, qd.x, y.y);
-      Vr[e] = mk<SV>((SV)(y.x * inu), (SV)(y.y * inu));
+      const cpair<SQ> q = mk_pair<SQ>(make_double2(aq[2 * p].x * inu, aq[2 * p].y * inu),
+                                      make_double2(aq[2 * p + 1].x * inu, aq[2 * p + 1].y * inu));
+      *reinterpret_cast<cpair<SQ>*>(Qj + e) = q;
+      double2 y[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const c2<SQ> qh = h ? q.b : q.a;
+        const double2 qd = make_double2((double)qh.x, (double)qh.y);  // the stored (rounded) q_j
+        double2 yy = aw[2 * p + h];
+        yy.x = fma(-dj.x, qd.x, yy.x);
+        yy.x = fma(dj.y, qd.y, yy.x);
+        yy.y = fma(-dj.x, qd.y, yy.y);
+        yy.y = fma(-dj.y, qd.x, yy.y);
+        y[h] = make_double2(yy.x * inu, yy.y * inu);
+      }
+      *reinterpret_cast<cpair<SV>*>(Vr + e) = mk_pair<SV>(y[0], y[1]);
     }
   }
 }
@@ -1266,7 +1316,7 @@ hipError_t launch_dots2(const c2<SQ>* Q, size_t q_vs, int nq, const c2<SV>* V, c
                         int nrhs, double2* part, double2* out, int ostride, int* counter, const int* live,
                         hipStream_t st) {
   if (nrhs <= 0) return hipSuccess;
-  if (nq < 0 || nq + 1 > kFusedMaxNv || ostride < 2 * (nq + 1)) return hipErrorInvalidValue;
+  if (nq < 0 || nq + 1 > kFusedMaxNv || ostride < 2 * (nq + 1) || n % 2) return hipErrorInvalidValue;
   const unsigned nchunk = (unsigned)((n + kDotChunk - 1) / kDotChunk);
   if ((size_t)nchunk * nrhs >= 2048) {
     hipLaunchKernelGGL((k_dots2<SQ, SV, true>), dim3(nchunk, nrhs), dim3(NT), 0, st, Q, q_vs, nq, V, W, rs, n, part,
@@ -1294,7 +1344,8 @@ hipError_t launch_dcgs_axpy(c2<SQ>* Q, size_t q_vs, int j, c2<SV>* V, const c2<S
                             const double2* coef, int ld, const GmresState* state, const int* live, hipStream_t st) {
   if (nrhs <= 0) return hipSuccess;
   // at most 4 elements per thread: 8 needs 84 VGPRs and measured 4.4 against 5.3 TB/s
-  const int ept = std::min(4, blocks_split((n + NT - 1) / NT, nrhs));
+  if (n % 2) return hipErrorInvalidValue;  // pairs of elements
+  const int ept = std::max(2, std::min(4, blocks_split((n + NT - 1) / NT, nrhs)));
   dim3 grid((unsigned)((n + (size_t)NT * ept - 1) / ((size_t)NT * ept)), nrhs);
 #define DIE_DCGS_CASE(E)                                                                                       \
   case E:                                                                                                      \
@@ -1302,7 +1353,6 @@ hipError_t launch_dcgs_axpy(c2<SQ>* Q, size_t q_vs, int j, c2<SV>* V, const c2<S
                        live);                                                                                  \
     break;
   switch (ept) {
-    DIE_DCGS_CASE(1)
     DIE_DCGS_CASE(2)
     DIE_DCGS_CASE(4)
     default: return hipErrorInvalidValue;
