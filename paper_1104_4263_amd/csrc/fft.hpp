@@ -134,7 +134,7 @@ template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int M
   static constexpr int ES = (int)sizeof(c2<T>);
   static constexpr int PS = fft_pad_shift(ES);
   static constexpr int LDB = fft_row_stride(N, ES);
-  static constexpr int LDS_ELEMS = NP * NB * LDB;
+  static constexpr int LDS_ELEMS = NB * LDB;  // one array set at a time (see stage)
 
   static constexpr int lr(int s) { return (REM && (REV ? s == NS - 1 : s == 0)) ? REM : LE; }
   static constexpr int lp(int s) { return s == 0 ? 0 : lp(s - 1) + lr(s - 1); }
@@ -167,21 +167,12 @@ template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int M
     pos = i + q * (N / RL);
   }
 
+  // Stage S on registers, then (except after the last stage) the exchange into the layout of
+  // stage S+1 through LDS.  The NP arrays held in lock step go through one LDS buffer in
+  // turn, so the buffer is NP times smaller than all the data (more blocks per CU).
   template <int S, bool INV>
   static __device__ __forceinline__ void stage(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t) {
-    constexpr int LR = lr(S), R = 1 << LR, NR = N >> LR, LP = lp(S), P = 1 << LP, NU = E / R;
-    if constexpr (S > 0) {
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        int b, i;
-        bi<S>(t, u, b, i);
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-          for (int q = 0; q < R; ++q) v[p][u * R + q] = lds[(p * NB + b) * LDB + f(i + q * NR)];
-      }
-      __syncthreads();
-    }
+    constexpr int LR = lr(S), R = 1 << LR, LP = lp(S), P = 1 << LP, NU = E / R;
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       int b, i;
@@ -192,15 +183,31 @@ template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int M
         if constexpr (LP > 0) twiddle<T, LR, INV>(&v[p][u * R], tw, k << (kLogTw - LP - LR));
         dftR<T, LR, INV>(&v[p][u * R]);
       }
-      if constexpr (S < NS - 1) {
-        const int j = ((i - k) << LR) + k;
+    }
+    if constexpr (S < NS - 1) {
+      constexpr int LR1 = lr(S + 1), R1 = 1 << LR1, NR1 = N >> LR1, NU1 = E / R1;
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+      for (int p = 0; p < NP; ++p) {
 #pragma unroll
-          for (int q = 0; q < R; ++q) lds[(p * NB + b) * LDB + f(j + q * P)] = v[p][u * R + q];
+        for (int u = 0; u < NU; ++u) {
+          int b, i;
+          bi<S>(t, u, b, i);
+          const int k = i & (P - 1);
+          const int j = ((i - k) << LR) + k;
+#pragma unroll
+          for (int q = 0; q < R; ++q) lds[b * LDB + f(j + q * P)] = v[p][u * R + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NU1; ++u) {
+          int b, i;
+          bi<S + 1>(t, u, b, i);
+#pragma unroll
+          for (int q = 0; q < R1; ++q) v[p][u * R1 + q] = lds[b * LDB + f(i + q * NR1)];
+        }
+        __syncthreads();
       }
     }
-    if constexpr (S < NS - 1) __syncthreads();
   }
 
   template <int S, bool INV>

@@ -48,7 +48,9 @@ template <class T> __host__ __device__ constexpr int cols_threads(int logn) {
 // ------------------------------------------------------------------ pass 1
 // Block: TY consecutive rows of the sets of `rb` right-hand sides (spr sets each).
 // Loads rows position-fast (coalesced), stores W[s][x][y] array-fast (TY-contiguous).
-template <class T, class S, int LOGN, bool INV>
+// HALF: the rows hold at most N/2 values (nx <= N/2, the zero-padded product), so inputs in
+// the upper half are known zeros at compile time and the first stage folds them away.
+template <class T, class S, int LOGN, bool INV, bool HALF>
 __global__ void __launch_bounds__(rows_threads<T>(LOGN))
 k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* __restrict__ W,
            const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr, int rb, int rpo,
@@ -79,7 +81,7 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* _
           F::in_pos(t, u, q, b, pos);
           const int yy = y0 + b;
           c2<T> a = mk<T>(0, 0);
-          if (pos < nx && yy < nrows) {
+          if ((!HALF || q * (N / F::R0) < N / 2) && pos < nx && yy < nrows) {
             a = ld<T, S>(xs + (size_t)yy * nx + pos);
             if (chi) a = cmul<T>(a, chi[(size_t)yy * nx + pos]);
           }
@@ -128,9 +130,11 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       int b, pos;
       F::in_pos(t, u, q, b, pos);
       const int xx = x0 + b, e = u * F::R0 + q;
+      // nrows <= N/2 (zero padding to at least 2 nrows - 1): the upper half is known zero
+      const bool lower = q * (N / F::R0) < N / 2;
 #pragma unroll
       for (int c = 0; c < 2; ++c)
-        v[c][e] = (xx < ncols && pos < nrows) ? Wr[((size_t)c * ncols + xx) * nrows + pos] : mk<T>(0, 0);
+        v[c][e] = (lower && xx < ncols && pos < nrows) ? Wr[((size_t)c * ncols + xx) * nrows + pos] : mk<T>(0, 0);
     }
   F::template run<false>(v, lds, tw, t);
   asm volatile("" : "+v"(t));  // per-phase address arithmetic (hoisting it costs VGPRs)
@@ -158,7 +162,7 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       int b, pos;
       G::out_pos(t, u, q, b, pos);
       const int xx = x0 + b, e = u * G::RL + q;
-      if (xx < ncols && pos < nrows) {
+      if (q * (N / G::RL) < N / 2 && xx < ncols && pos < nrows) {  // only rows < nrows <= N/2 are kept
 #pragma unroll
         for (int c = 0; c < 2; ++c) Wr[((size_t)c * ncols + xx) * nrows + pos] = v[c][e];
       }
@@ -231,7 +235,7 @@ k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* 
       int b, pos;
       F::out_pos(t, uu, q, b, pos);
       const int yy = y0 + b;
-      if (pos < nx && yy < nrows) {
+      if (q * (N / F::RL) < N / 2 && pos < nx && yy < nrows) {  // only columns < nx <= N/2 are kept
         const size_t o = so + (size_t)yy * nx + pos;
         st<S, T>(y + o, csub<T>(ld<T, S>(u + o), v[0][uu * F::RL + q]));
       }
@@ -342,11 +346,14 @@ hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* 
     const int ngroups = (nrhs + rb - 1) / rb;                                                           \
     dim3 grid((unsigned)(ntiles * ngroups));                                                            \
     if (inverse)                                                                                        \
-      hipLaunchKernelGGL((k_rows_fwd<T, S, L, true>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, nx, \
-                         nrows, ntiles, nrhs, spr, rb, rpo, live);                                      \
+      hipLaunchKernelGGL((k_rows_fwd<T, S, L, true, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
+                         nx, nrows, ntiles, nrhs, spr, rb, rpo, live);                                  \
+    else if (2 * nx <= (1 << L))                                                                        \
+      hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, true>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
+                         nx, nrows, ntiles, nrhs, spr, rb, rpo, live);                                  \
     else                                                                                                \
-      hipLaunchKernelGGL((k_rows_fwd<T, S, L, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, nx, \
-                         nrows, ntiles, nrhs, spr, rb, rpo, live);                                      \
+      hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
+                         nx, nrows, ntiles, nrhs, spr, rb, rpo, live);                                  \
     break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
@@ -363,6 +370,7 @@ hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, i
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nrhs <= 0) return hipSuccess;
+  if (2 * nrows > (1 << logn)) return hipErrorInvalidValue;  // the upper half must be padding
   switch (logn) {
 #define CASE(L)                                                                                         \
   case L: {                                                                                             \
@@ -385,6 +393,7 @@ hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* 
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nsets <= 0 || nrows <= 0) return hipSuccess;
+  if (2 * nx > (1 << logn)) return hipErrorInvalidValue;  // the upper half must be padding
   switch (logn) {
 #define CASE(L)                                                                                         \
   case L: {                                                                                             \
