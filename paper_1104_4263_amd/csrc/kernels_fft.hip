@@ -20,13 +20,16 @@
 
 namespace die {
 
-// Per-thread element count: radix 16 in FP32, radix 8 in FP64 (register budget of the
-// paired column pass).  Tile sizes keep the LDS exchange buffer near 72 KB so that two
-// blocks share a CU.
-template <class T> __host__ __device__ constexpr int fft_loge() { return sizeof(c2<T>) == 8 ? 4 : 3; }
+// Per-thread element count (the radix of the register stages): radix 8 in FP64 (register
+// budget of the paired column pass); in FP32 radix 8 where log2 N is a multiple of 3 (the
+// same stage count as radix 16 with lighter butterflies and more resident waves), else
+// radix 16 (one stage fewer).  Tile sizes keep the LDS exchange buffer near 72 KB.
+template <class T> __host__ __device__ constexpr int fft_loge(int logn) {
+  return (sizeof(c2<T>) == 8 && logn % 3 != 0) ? 4 : 3;
+}
 constexpr int kLdsBudget = 76000;
 template <class T> __host__ __device__ constexpr int fft_e(int logn) {
-  return 1 << (fft_loge<T>() < logn ? fft_loge<T>() : logn);
+  return 1 << (fft_loge<T>(logn) < logn ? fft_loge<T>(logn) : logn);
 }
 template <class T> __host__ __device__ constexpr int rows_ty(int logn) {
   int n = 1 << logn, es = (int)sizeof(c2<T>), ty = 16;
@@ -55,7 +58,7 @@ __global__ void __launch_bounds__(rows_threads<T>(LOGN))
 k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* __restrict__ W,
            const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr, int rb, int rpo,
            const int* __restrict__ live) {
-  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(), 1, false, kPosFast, kArrFast>;
+  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(LOGN), 1, false, kPosFast, kArrFast>;
   constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN);
   __shared__ c2<T> lds[F::LDS_ELEMS];
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -112,8 +115,8 @@ __global__ void __launch_bounds__(cols_threads<T>(LOGN))
 k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>* __restrict__ tw, int ncols,
               int nrows, int nrhs, const int* __restrict__ live) {
   constexpr int CX = cols_cx<T>(LOGN);
-  using F = RegFft<T, LOGN, CX, fft_loge<T>(), 2, false, kPosFast, kPosFast>;
-  using G = RegFft<T, LOGN, CX, fft_loge<T>(), 2, true, kPosFast, kPosFast>;
+  using F = RegFft<T, LOGN, CX, fft_loge<T>(LOGN), 2, false, kPosFast, kPosFast>;
+  using G = RegFft<T, LOGN, CX, fft_loge<T>(LOGN), 2, true, kPosFast, kPosFast>;
   static_assert(G::R0 == F::RL, "inverse must start with the forward's last radix");
   constexpr int N = F::N, E = F::E;
   __shared__ c2<T> lds[F::LDS_ELEMS];
@@ -175,7 +178,7 @@ template <class T, int LOGN, bool INV>
 __global__ void __launch_bounds__(cols_threads<T>(LOGN))
 k_cols_plain(c2<T>* __restrict__ W, const c2<T>* __restrict__ tw, int ncols, int ntiles) {
   constexpr int NB = cols_cx<T>(LOGN);
-  using F = RegFft<T, LOGN, NB, fft_loge<T>(), 1, false, kPosFast, kPosFast>;
+  using F = RegFft<T, LOGN, NB, fft_loge<T>(LOGN), 1, false, kPosFast, kPosFast>;
   constexpr int N = F::N, E = F::E;
   __shared__ c2<T> lds[F::LDS_ELEMS];
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -208,7 +211,7 @@ template <class T, class S, int LOGN>
 __global__ void __launch_bounds__(rows_threads<T>(LOGN))
 k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* __restrict__ y,
                const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int spr, const int* __restrict__ live) {
-  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(), 1, false, kArrFast, kPosFast>;
+  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(LOGN), 1, false, kArrFast, kPosFast>;
   constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN);
   __shared__ c2<T> lds[F::LDS_ELEMS];
   const int L = xcd_remap(blockIdx.x, gridDim.x);
