@@ -845,25 +845,35 @@ constexpr int kDots2G = 2;  // vectors per group: 2 vectors x 2 targets x (re, i
 template <class S> struct alignas(2 * sizeof(c2<S>)) cpair {
   c2<S> a, b;
 };
-template <class S> __device__ __forceinline__ void ld_pair(const c2<S>* p, double2& x, double2& y) {
+template <class A, class S> __device__ __forceinline__ void ld_pair(const c2<S>* p, c2<A>& x, c2<A>& y) {
   const cpair<S> v = *reinterpret_cast<const cpair<S>*>(p);
-  x = make_double2((double)v.a.x, (double)v.a.y);
-  y = make_double2((double)v.b.x, (double)v.b.y);
+  x = mk<A>((A)v.a.x, (A)v.a.y);
+  y = mk<A>((A)v.b.x, (A)v.b.y);
 }
-template <class S> __device__ __forceinline__ cpair<S> mk_pair(double2 x, double2 y) {
+template <class S, class A> __device__ __forceinline__ cpair<S> mk_pair(c2<A> x, c2<A> y) {
   cpair<S> v;
   v.a = mk<S>((S)x.x, (S)x.y);
   v.b = mk<S>((S)y.x, (S)y.y);
   return v;
 }
 
-template <class SQ, bool FULL>
+// Arithmetic inside a thread of the one-reduction kernels: FP64 for FP64 and FP32 bases;
+// FP32 for the binary16 basis, whose storage rounding (2^-11) is far above FP32 rounding
+// (2^-24), and where the binary16 operand widens inside the fused multiply-add
+// (v_fma_mix_f32) instead of through two conversions.  Sums across threads and blocks,
+// and every coefficient the scalar step computes, stay FP64.
+template <class SQ> struct arn_acc { using type = double; };
+template <> struct arn_acc<_Float16> { using type = float; };
+__device__ __forceinline__ float afma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double afma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <class SQ, class A, bool FULL>
 __device__ __forceinline__ void dots2_group(const c2<SQ>* __restrict__ Qr, size_t q_vs, int i0, int gn, size_t base,
-                                            size_t n, const double2 (&b0)[kDotEpt], const double2 (&b1)[kDotEpt],
+                                            size_t n, const c2<A> (&b0)[kDotEpt], const c2<A> (&b1)[kDotEpt],
                                             double (&v)[8]) {
 #pragma unroll
   for (int g = 0; g < kDots2G; ++g) {
-    double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
+    A s0x = 0, s0y = 0, s1x = 0, s1y = 0;
     if (g < gn) {
       const c2<SQ>* Ai = Qr + (size_t)(i0 + g) * q_vs + base;
       cpair<SQ> raw[kDotEpt / 2];  // kept in storage precision until used
@@ -880,22 +890,22 @@ __device__ __forceinline__ void dots2_group(const c2<SQ>* __restrict__ Qr, size_
       for (int k = 0; k < kDotEpt; ++k) {
         {
           const c2<SQ> ak = (k & 1) ? raw[k / 2].b : raw[k / 2].a;
-          const double2 a = make_double2((double)ak.x, (double)ak.y);
-          s0x = fma(a.x, b0[k].x, s0x);
-          s0x = fma(a.y, b0[k].y, s0x);
-          s0y = fma(a.x, b0[k].y, s0y);
-          s0y = fma(-a.y, b0[k].x, s0y);
-          s1x = fma(a.x, b1[k].x, s1x);
-          s1x = fma(a.y, b1[k].y, s1x);
-          s1y = fma(a.x, b1[k].y, s1y);
-          s1y = fma(-a.y, b1[k].x, s1y);
+          const A ax = (A)ak.x, ay = (A)ak.y;
+          s0x = afma(ax, b0[k].x, s0x);
+          s0x = afma(ay, b0[k].y, s0x);
+          s0y = afma(ax, b0[k].y, s0y);
+          s0y = afma(-ay, b0[k].x, s0y);
+          s1x = afma(ax, b1[k].x, s1x);
+          s1x = afma(ay, b1[k].y, s1x);
+          s1y = afma(ax, b1[k].y, s1y);
+          s1y = afma(-ay, b1[k].x, s1y);
         }
       }
     }
-    v[4 * g + 0] = s0x;
-    v[4 * g + 1] = s0y;
-    v[4 * g + 2] = s1x;
-    v[4 * g + 3] = s1y;
+    v[4 * g + 0] = (double)s0x;
+    v[4 * g + 1] = (double)s0y;
+    v[4 * g + 2] = (double)s1x;
+    v[4 * g + 3] = (double)s1y;
   }
 }
 
@@ -917,14 +927,15 @@ k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restr
   const c2<SQ>* Qr = Q + (size_t)r * rs;
   const c2<SV>* Vr = V + (size_t)r * rs;
   const c2<SV>* Wr = Wt ? Wt + (size_t)r * rs : nullptr;
-  double2 b0[kDotEpt], b1[kDotEpt];
+  using A = typename arn_acc<SQ>::type;
+  c2<A> b0[kDotEpt], b1[kDotEpt];
 #pragma unroll
   for (int p = 0; p < kDotEpt / 2; ++p) {
     const size_t e = base + (size_t)p * 2 * NT;
-    b0[2 * p] = b0[2 * p + 1] = b1[2 * p] = b1[2 * p + 1] = make_double2(0.0, 0.0);
+    b0[2 * p] = b0[2 * p + 1] = b1[2 * p] = b1[2 * p + 1] = mk<A>((A)0, (A)0);
     if (e < n) {
-      ld_pair<SV>(Vr + e, b0[2 * p], b0[2 * p + 1]);
-      if (Wr) ld_pair<SV>(Wr + e, b1[2 * p], b1[2 * p + 1]);
+      ld_pair<A, SV>(Vr + e, b0[2 * p], b0[2 * p + 1]);
+      if (Wr) ld_pair<A, SV>(Wr + e, b1[2 * p], b1[2 * p + 1]);
     }
   }
   const int ifirst = WALK ? 0 : blockIdx.y * kDots2G, iend = WALK ? nA : min(nA, ifirst + kDots2G);
@@ -951,24 +962,25 @@ k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restr
   for (int i0 = ifirst; i0 < min(iend, nq); i0 += kDots2G) {
     const int gn = min(kDots2G, nq - i0);
     double v[8];
-    if (full) dots2_group<SQ, true>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
-    else dots2_group<SQ, false>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
+    if (full) dots2_group<SQ, A, true>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
+    else dots2_group<SQ, A, false>(Qr, q_vs, i0, gn, base, n, b0, b1, v);
     reduce_store(v, i0, gn);
   }
   // A_nq = V: v^H v and v^H w from the target values already in registers
   if (ifirst <= nq && nq < iend) {
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = 0.0;
+    A a[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < kDotEpt; ++k) {
-      v[0] = fma(b0[k].x, b0[k].x, v[0]);
-      v[0] = fma(b0[k].y, b0[k].y, v[0]);
-      v[2] = fma(b0[k].x, b1[k].x, v[2]);
-      v[2] = fma(b0[k].y, b1[k].y, v[2]);
-      v[3] = fma(b0[k].x, b1[k].y, v[3]);
-      v[3] = fma(-b0[k].y, b1[k].x, v[3]);
+      a[0] = afma(b0[k].x, b0[k].x, a[0]);
+      a[0] = afma(b0[k].y, b0[k].y, a[0]);
+      a[2] = afma(b0[k].x, b1[k].x, a[2]);
+      a[2] = afma(b0[k].y, b1[k].y, a[2]);
+      a[3] = afma(b0[k].x, b1[k].y, a[3]);
+      a[3] = afma(-b0[k].y, b1[k].x, a[3]);
     }
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = q < 4 ? (double)a[q] : 0.0;
     reduce_store(v, nq, 1);
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1165,7 +1177,8 @@ k_dcgs_axpy(c2<SQ>* __restrict__ Q, size_t q_vs, int j, c2<SV>* __restrict__ V, 
             const int* __restrict__ live) {
   const int r = blockIdx.y;
   if (!live[r]) return;
-  const double inu = state[r].invbeta;
+  using A = typename arn_acc<SQ>::type;
+  const A inu = (A)state[r].invbeta;
   c2<SQ>* Qr = Q + (size_t)r * rs;
   c2<SQ>* Qj = Qr + (size_t)j * q_vs;
   c2<SV>* Vr = V + (size_t)r * rs;
@@ -1176,61 +1189,61 @@ k_dcgs_axpy(c2<SQ>* __restrict__ Q, size_t q_vs, int j, c2<SV>* __restrict__ V, 
   constexpr int NPR = EPT / 2;
   const size_t base = (size_t)blockIdx.x * (NT * EPT) + 2 * threadIdx.x;  // pairs (base + 2 p NT, + 1)
   const bool full = (size_t)(blockIdx.x + 1) * (NT * EPT) <= n;
-  double2 aq[EPT], aw[EPT];
+  c2<A> aq[EPT], aw[EPT];
 #pragma unroll
   for (int p = 0; p < NPR; ++p) {
     const size_t e = base + (size_t)p * 2 * NT;
-    aq[2 * p] = aq[2 * p + 1] = aw[2 * p] = aw[2 * p + 1] = make_double2(0.0, 0.0);
+    aq[2 * p] = aq[2 * p + 1] = aw[2 * p] = aw[2 * p + 1] = mk<A>((A)0, (A)0);
     if (full || e < n) {
-      ld_pair<SV>(Vr + e, aq[2 * p], aq[2 * p + 1]);
-      ld_pair<SV>(Wr + e, aw[2 * p], aw[2 * p + 1]);
+      ld_pair<A, SV>(Vr + e, aq[2 * p], aq[2 * p + 1]);
+      ld_pair<A, SV>(Wr + e, aw[2 * p], aw[2 * p + 1]);
     }
   }
   for (int i = 0; i < j; ++i) {
-    const double2 si = sr[i], di = dr[i];
+    const c2<A> si = mk<A>((A)sr[i].x, (A)sr[i].y), di = mk<A>((A)dr[i].x, (A)dr[i].y);
     const c2<SQ>* Ai = Qr + (size_t)i * q_vs + base;
 #pragma unroll
     for (int p = 0; p < NPR; ++p) {
       if (full || base + (size_t)p * 2 * NT < n) {
-        double2 a2[2];
-        ld_pair<SQ>(Ai + (size_t)p * 2 * NT, a2[0], a2[1]);
+        const cpair<SQ> raw = *reinterpret_cast<const cpair<SQ>*>(Ai + (size_t)p * 2 * NT);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int k = 2 * p + h;
-          const double2 a = a2[h];
-          aq[k].x = fma(-si.x, a.x, aq[k].x);
-          aq[k].x = fma(si.y, a.y, aq[k].x);
-          aq[k].y = fma(-si.x, a.y, aq[k].y);
-          aq[k].y = fma(-si.y, a.x, aq[k].y);
-          aw[k].x = fma(-di.x, a.x, aw[k].x);
-          aw[k].x = fma(di.y, a.y, aw[k].x);
-          aw[k].y = fma(-di.x, a.y, aw[k].y);
-          aw[k].y = fma(-di.y, a.x, aw[k].y);
+          const c2<SQ> a = h ? raw.b : raw.a;
+          const A ax = (A)a.x, ay = (A)a.y;
+          aq[k].x = afma(-si.x, ax, aq[k].x);
+          aq[k].x = afma(si.y, ay, aq[k].x);
+          aq[k].y = afma(-si.x, ay, aq[k].y);
+          aq[k].y = afma(-si.y, ax, aq[k].y);
+          aw[k].x = afma(-di.x, ax, aw[k].x);
+          aw[k].x = afma(di.y, ay, aw[k].x);
+          aw[k].y = afma(-di.x, ay, aw[k].y);
+          aw[k].y = afma(-di.y, ax, aw[k].y);
         }
       }
     }
   }
-  const double2 dj = dr[j];
+  const c2<A> dj = mk<A>((A)dr[j].x, (A)dr[j].y);
 #pragma unroll
   for (int p = 0; p < NPR; ++p) {
     const size_t e = base + (size_t)p * 2 * NT;
     if (full || e < n) {
-      const cpair<SQ> q = mk_pair<SQ>(make_double2(aq[2 * p].x * inu, aq[2 * p].y * inu),
-                                      make_double2(aq[2 * p + 1].x * inu, aq[2 * p + 1].y * inu));
+      const cpair<SQ> q = mk_pair<SQ, A>(mk<A>(aq[2 * p].x * inu, aq[2 * p].y * inu),
+                                         mk<A>(aq[2 * p + 1].x * inu, aq[2 * p + 1].y * inu));
       *reinterpret_cast<cpair<SQ>*>(Qj + e) = q;
-      double2 y[2];
+      c2<A> y[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const c2<SQ> qh = h ? q.b : q.a;
-        const double2 qd = make_double2((double)qh.x, (double)qh.y);  // the stored (rounded) q_j
-        double2 yy = aw[2 * p + h];
-        yy.x = fma(-dj.x, qd.x, yy.x);
-        yy.x = fma(dj.y, qd.y, yy.x);
-        yy.y = fma(-dj.x, qd.y, yy.y);
-        yy.y = fma(-dj.y, qd.x, yy.y);
-        y[h] = make_double2(yy.x * inu, yy.y * inu);
+        const A qx = (A)qh.x, qy = (A)qh.y;  // the stored (rounded) q_j
+        c2<A> yy = aw[2 * p + h];
+        yy.x = afma(-dj.x, qx, yy.x);
+        yy.x = afma(dj.y, qy, yy.x);
+        yy.y = afma(-dj.x, qy, yy.y);
+        yy.y = afma(-dj.y, qx, yy.y);
+        y[h] = mk<A>(yy.x * inu, yy.y * inu);
       }
-      *reinterpret_cast<cpair<SV>*>(Vr + e) = mk_pair<SV>(y[0], y[1]);
+      *reinterpret_cast<cpair<SV>*>(Vr + e) = mk_pair<SV, A>(y[0], y[1]);
     }
   }
 }
