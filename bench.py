@@ -272,7 +272,9 @@ def main():
     avg_ms = p["ms"] / max(p["timed"], 1)
     bytes_per_launch = p["bytes"] / max(p["timed"], 1)
     achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
-    src = source_hash("kernels_fft.hip" if dom == "product" else "kernels_krylov.hip")
+    # the kernel file and every header it includes (a traffic summary is only valid for this code)
+    src = source_hash(*(("kernels_fft.hip", "fft.hpp", "ops.hpp", "common.hpp") if dom == "product" else
+                        ("kernels_krylov.hip", "ops.hpp", "common.hpp")))
     kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "arnoldi_dots_c64_256_batched",
                   "axpy": "arnoldi_axpy_c64_256_batched"}[dom]
     traffic = read_traffic(kernel_tag, src, bytes_per_launch)

@@ -55,16 +55,34 @@ template <class T, bool INV> __device__ __forceinline__ c2<T> w16(int m) {
   return mk<T>((T)C[m], INV ? (T)S[m] : (T)-S[m]);
 }
 
+// a * exp(-+2 pi i M / 16) with the trivial and the eighth-turn factors written out
+// (no multiplications by 0 or 1).
+template <class T, bool INV, int M> __device__ __forceinline__ c2<T> mulw16(c2<T> a) {
+  constexpr int m = M & 15;
+  if constexpr (m == 0) return a;
+  else if constexpr (m == 8) return mk<T>(-a.x, -a.y);
+  else if constexpr (m == 4) return INV ? mul_pi<T>(a) : mul_mi<T>(a);
+  else if constexpr (m == 12) return INV ? mul_mi<T>(a) : mul_pi<T>(a);
+  else if constexpr (m % 4 == 2) {
+    // exp(-+i pi / 4) a, then the remaining quarter turns
+    constexpr T c = (T)0.70710678118654752440;
+    const c2<T> e = INV ? mk<T>((a.x - a.y) * c, (a.x + a.y) * c) : mk<T>((a.x + a.y) * c, (a.y - a.x) * c);
+    return mulw16<T, INV, m - 2>(e);
+  } else {
+    return cmul<T>(a, w16<T, INV>(m));
+  }
+}
+
 template <class T, bool INV> __device__ __forceinline__ void dft8(c2<T>* v) {
   c2<T> e[4] = {v[0], v[2], v[4], v[6]};
   c2<T> o[4] = {v[1], v[3], v[5], v[7]};
   dft4<T, INV>(e);
   dft4<T, INV>(o);
+  const c2<T> t[4] = {o[0], mulw16<T, INV, 2>(o[1]), mulw16<T, INV, 4>(o[2]), mulw16<T, INV, 6>(o[3])};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const c2<T> t = k == 0 ? o[0] : cmul<T>(o[k], w16<T, INV>(2 * k));
-    v[k] = cadd<T>(e[k], t);
-    v[k + 4] = csub<T>(e[k], t);
+    v[k] = cadd<T>(e[k], t[k]);
+    v[k + 4] = csub<T>(e[k], t[k]);
   }
 }
 
@@ -74,8 +92,16 @@ template <class T, bool INV> __device__ __forceinline__ void dft16(c2<T>* v) {
   for (int n2 = 0; n2 < 4; ++n2) {
     c2<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
     dft4<T, INV>(t);
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = (n2 == 0 || k1 == 0) ? t[k1] : cmul<T>(t[k1], w16<T, INV>(n2 * k1));
+    a[n2][0] = t[0];
+    if (n2 == 0) {
+      a[0][1] = t[1], a[0][2] = t[2], a[0][3] = t[3];
+    } else if (n2 == 1) {
+      a[1][1] = mulw16<T, INV, 1>(t[1]), a[1][2] = mulw16<T, INV, 2>(t[2]), a[1][3] = mulw16<T, INV, 3>(t[3]);
+    } else if (n2 == 2) {
+      a[2][1] = mulw16<T, INV, 2>(t[1]), a[2][2] = mulw16<T, INV, 4>(t[2]), a[2][3] = mulw16<T, INV, 6>(t[3]);
+    } else {
+      a[3][1] = mulw16<T, INV, 3>(t[1]), a[3][2] = mulw16<T, INV, 6>(t[2]), a[3][3] = mulw16<T, INV, 9>(t[3]);
+    }
   }
 #pragma unroll
   for (int k1 = 0; k1 < 4; ++k1) {
