@@ -173,6 +173,44 @@ def learned_run(ntrain, g, eps, B, nsolve, value_batched, iters_batched):
     return res
 
 
+SIZE_CLASSES = (128, 256, 512, 1024)  # object o of the batched workload has size class o // 4, seed 1000 + o
+
+
+def uneven_run(sizes, args):
+    """Several size classes of the batched workload (4 objects x 64 angles each) solved in one
+    die_te_solve_batch call, one context per grid size."""
+    import numpy as np
+    import torch
+    from synth import plane_wave, random_field_object
+    from paper_1104_4263_amd import Solver
+    solvers, Bs = [], []
+    for n in sizes:
+        c = SIZE_CLASSES.index(n)
+        objs = [random_field_object(n, seed=1000 + 4 * c + i) for i in range(4)]
+        gn = objs[0][0]
+        solvers.append(Solver.from_grid(gn, np.stack([e for _, e in objs])))
+        b1 = np.stack([plane_wave(gn, 2.0 * math.pi * j / N_ANGLES) for j in range(N_ANGLES)])
+        Bs.append(torch.from_numpy(np.concatenate([b1] * 4)).cuda())
+    kw = dict(restart=RESTART, tol=TOL, mixed=2 if args.basis == 16 else 1, orth=args.orth)
+    Solver.solve_batch(solvers, Bs, max_iters=RESTART, **kw)  # allocates every context's buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, rc = Solver.solve_batch(solvers, Bs, max_iters=MAX_ITERS, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nsol = sum(b.shape[0] for b in Bs)
+    ok = rc == 0 and all(x["rel_res_true"] <= TOL for _, inf in res for x in inf)
+    per = {f"{n}x{n}": {"iters_mean": round(float(np.mean([x["iters"] for x in inf])), 1),
+                        "iters_max": int(max(x["iters"] for x in inf))} for n, (_, inf) in zip(sizes, res)}
+    out = {"workload": f"size classes {sizes} of the batched random-field workload, 4 objects x {N_ANGLES} "
+                       f"angles each, one die_te_solve_batch call", "solves": nsol, "s": round(dt, 3),
+           "solves_per_s": round(nsol / dt, 3) if ok else 0.0, "classes": per}
+    log(f"uneven: {out}")
+    for sv in solvers:
+        sv.close()
+    return out
+
+
 def time_matvec(s, x, reps):
     """Average ms of one product call, timed with events on the stream the library launches on."""
     import torch
@@ -206,6 +244,9 @@ def main():
                          "solves, then time the batch from its guesses (several minutes)")
     ap.add_argument("--configured-deflation", action="store_true",
                     help="also run the batch with the configured k=16 deflation (about 40 s)")
+    ap.add_argument("--uneven", type=str, default="", metavar="SIZES",
+                    help="also solve size classes of the batched workload on grids of different sizes in one "
+                         "call (e.g. 128,256,512: 4 objects x 64 angles per class, seeds 1000 + object index)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
@@ -393,6 +434,9 @@ def main():
             log(f"cylinder variant {name}: {variants[name]}")
             sv.close()
         out["cylinder_variants"] = variants
+
+    if args.uneven:
+        out["uneven"] = uneven_run([int(v) for v in args.uneven.split(",")], args)
 
     if args.learned > 0:
         out["learned"] = learned_run(args.learned, g, eps, B, nsolve, value, iters)

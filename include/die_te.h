@@ -149,6 +149,19 @@ int die_te_regularize(die_te_ctx *ctx, const void *x, void *y, int nrhs, int pre
 int die_te_solve(die_te_ctx *ctx, const void *e_in, void *e_tot, int nrhs,
                  const die_te_solve_opts *opts, die_te_solve_info *info, void *stream);
 
+/* Objects on grids of different sizes in one call (the same solver as die_te_solve,
+ * Section 4): context i (one grid size, one or more objects) solves nrhs[i] incident
+ * fields e_in[i] -> e_tot[i] (each laid out as in die_te_solve for that context) with the
+ * shared options; info[i] receives nrhs[i] records (info, or any info[i], may be NULL).
+ * Work queued on `stream` before the call completes first; the contexts then advance
+ * concurrently, each on a stream of its own that the call creates (default priority) and
+ * destroys, and the call returns when all have finished.  The contexts must be distinct.
+ * Returns the first error (< 0, in context order; die_te_last_error() names the context),
+ * else DIE_NOT_CONVERGED if any right-hand side did not converge, else DIE_OK. */
+int die_te_solve_batch(die_te_ctx *const *ctx, int nctx, const void *const *e_in, void *const *e_tot,
+                       const int *nrhs, const die_te_solve_opts *opts, die_te_solve_info *const *info,
+                       void *stream);
+
 /* P^-1 x = x + V ((T^-1 - I) (V^* x)) for nrhs complex128 vectors of length 2 nx ny
  * (Section 4, eq. DeflatingPrecondtioner).  x, y: device; may alias.
  * DIE_E_INVALID if the context has no deflation basis.  Asynchronous. */

@@ -73,6 +73,9 @@ def load() -> ctypes.CDLL:
     lib.die_te_matvec.argtypes = [vp, vp, vp, i, i, vp]
     lib.die_te_regularize.argtypes = [vp, vp, vp, i, i, vp]
     lib.die_te_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(DieTeSolveOpts), ctypes.POINTER(DieTeSolveInfo), vp]
+    lib.die_te_solve_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(DieTeSolveOpts),
+                                       ctypes.POINTER(vp), vp]
     lib.die_te_apply_deflation.argtypes = [vp, vp, vp, i, vp]
     lib.die_te_deflation_info.argtypes = [vp, ctypes.POINTER(ip), vp, vp, vp, vp]
     lib.die_te_fft2.argtypes = [vp, i, i, i, i, i, vp]

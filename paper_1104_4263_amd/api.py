@@ -80,6 +80,27 @@ def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, res
     return rc, [info[i].as_dict() for i in range(nrhs)]
 
 
+def die_te_solve_batch(ctxs, e_ins, e_tots, nrhs, *, restart: int = 30, max_iters: int = 100_000, tol: float = 1e-8,
+                       mixed: int = 0, x0_given: bool = False, reg_margin: float = 0.0,
+                       orth: int = 0) -> tuple[int, list[list[dict]]]:
+    """Several contexts (grid sizes) in one call; returns (code, per-context info lists)."""
+    n = len(ctxs)
+    if not (len(e_ins) == len(e_tots) == len(nrhs) == n):
+        raise ValueError("ctxs, e_ins, e_tots and nrhs must have the same length")
+    o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
+                       float(reg_margin), int(orth))
+    vp = ctypes.c_void_p
+    c_arr = (vp * n)(*[vp(c.value if isinstance(c, vp) else c) for c in ctxs])
+    i_arr = (vp * n)(*[_dev(t, (torch.complex128,), "e_in") for t in e_ins])
+    o_arr = (vp * n)(*[_dev(t, (torch.complex128,), "e_tot") for t in e_tots])
+    r_arr = (ctypes.c_int * n)(*[int(r) for r in nrhs])
+    infos = [(DieTeSolveInfo * int(r))() for r in nrhs]
+    f_arr = (vp * n)(*[ctypes.cast(x, vp) for x in infos])
+    rc = load().die_te_solve_batch(c_arr, n, i_arr, o_arr, r_arr, ctypes.byref(o), f_arr, _stream())
+    check(rc, allow_warning=True)
+    return rc, [[x[k].as_dict() for k in range(int(r))] for x, r in zip(infos, nrhs)]
+
+
 def die_te_apply_deflation(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
     check(load().die_te_apply_deflation(ctx, _dev(x, (torch.complex128,), "x"), _dev(y, (torch.complex128,), "y"),
                                         nrhs, _stream()))
@@ -183,6 +204,18 @@ class Solver:
         out = x0.clone().contiguous() if x0 is not None else torch.empty_like(e_in)
         rc, info = die_te_solve(self.ctx, e_in.contiguous(), out, nrhs, x0_given=x0 is not None, **kw)
         return out, rc, info
+
+    @staticmethod
+    def solve_batch(solvers, e_ins, x0s=None, **kw):
+        """Solvers on different grids in one call: returns [(u, info)] per solver and the code."""
+        nrhs = [s._shape(e) for s, e in zip(solvers, e_ins)]
+        if x0s is not None and any(x0 is None for x0 in x0s):
+            raise ValueError("x0s must give an initial guess for every solver (or be None)")
+        outs = [(x0.clone().contiguous() if x0 is not None else torch.empty_like(e))
+                for e, x0 in zip(e_ins, x0s or [None] * len(e_ins))]
+        rc, infos = die_te_solve_batch([s.ctx for s in solvers], [e.contiguous() for e in e_ins], outs, nrhs,
+                                       x0_given=x0s is not None, **kw)
+        return [(u, inf) for u, inf in zip(outs, infos)], rc
 
     def apply_deflation(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)

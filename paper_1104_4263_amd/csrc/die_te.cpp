@@ -15,6 +15,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dense.hpp"
@@ -860,6 +861,45 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
     return gmres_solve<float, _Float16>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
   if (o.mixed) return gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
   return gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+}
+
+int die_te_solve_batch(die_te_ctx* const* ctx, int nctx, const void* const* e_in, void* const* e_tot,
+                       const int* nrhs, const die_te_solve_opts* opts, die_te_solve_info* const* info,
+                       void* stream) {
+  die_host::last_error().clear();
+  if (!ctx || !e_in || !e_tot || !nrhs || !opts || nctx < 1)
+    return fail(DIE_E_INVALID, "null pointer or nctx < 1");
+  for (int i = 0; i < nctx; ++i) {
+    if (!ctx[i]) return fail(DIE_E_INVALID, "context " + std::to_string(i) + " is null");
+    for (int k = 0; k < i; ++k)
+      if (ctx[k] == ctx[i]) return fail(DIE_E_INVALID, "context " + std::to_string(i) + " is listed twice");
+  }
+  DIE_HIP(hipStreamSynchronize((hipStream_t)stream));  // the caller's queued work (inputs) is complete
+  struct Result {
+    int rc = DIE_OK;
+    std::string msg;
+  };
+  std::vector<Result> res(nctx);
+  auto run = [&](int i) {
+    die_te_ctx* c = ctx[i];
+    hipStream_t s = nullptr;
+    if (hipSetDevice(c->dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      res[i] = {DIE_E_HIP, "stream creation failed"};
+      return;
+    }
+    res[i].rc = die_te_solve(c, e_in[i], e_tot[i], nrhs[i], opts, info ? info[i] : nullptr, s);
+    res[i].msg = die_host::last_error();
+    (void)hipStreamDestroy(s);
+  };
+  std::vector<std::thread> th;
+  th.reserve(nctx);
+  for (int i = 0; i < nctx; ++i) th.emplace_back(run, i);
+  for (auto& t : th) t.join();
+  for (int i = 0; i < nctx; ++i)
+    if (res[i].rc < 0) return fail(res[i].rc, "context " + std::to_string(i) + ": " + res[i].msg);
+  for (int i = 0; i < nctx; ++i)
+    if (res[i].rc != DIE_OK) return res[i].rc;
+  return DIE_OK;
 }
 
 int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void* stream) {

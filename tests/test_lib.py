@@ -53,3 +53,19 @@ def test_unet_create_validates_before_any_gpu_call():
     assert lib.die_te_unet_create(ctypes.byref(net), 2, 8, 16, 16, 0, 0, None) == _lib.DIE_E_INVALID
     assert not net.value
     assert lib.die_te_unet_forward(None, None, None, 1, None) == _lib.DIE_E_INVALID
+
+
+def test_solve_batch_validates_before_any_gpu_call():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    o = _lib.DieTeSolveOpts(30, 100, 1e-8, 0, 0, 0.0, 0)
+    one = (ctypes.c_int * 2)(1, 1)
+    dummy = (vp * 2)(vp(16), vp(32))  # never dereferenced: the argument checks come first
+    assert lib.die_te_solve_batch(None, 2, dummy, dummy, one, ctypes.byref(o), None, None) == _lib.DIE_E_INVALID
+    assert lib.die_te_solve_batch(dummy, 0, dummy, dummy, one, ctypes.byref(o), None, None) == _lib.DIE_E_INVALID
+    same = (vp * 2)(vp(16), vp(16))
+    assert lib.die_te_solve_batch(same, 2, dummy, dummy, one, ctypes.byref(o), None, None) == _lib.DIE_E_INVALID
+    assert b"twice" in lib.die_te_last_error()
+    nul = (vp * 2)(vp(16), None)
+    assert lib.die_te_solve_batch(nul, 2, dummy, dummy, one, ctypes.byref(o), None, None) == _lib.DIE_E_INVALID
+    assert b"null" in lib.die_te_last_error()
