@@ -92,6 +92,10 @@ typedef struct {
                         passes over the basis); 1 = CGS2 with the second projection of each
                         vector delayed to the next step (one block reduction and two passes
                         over the basis per step; equal in exact arithmetic) */
+  int graph;         /* 1: capture the launches of one restart cycle's inner iterations once
+                        into a HIP graph (on a stream the call creates) and replay it on
+                        `stream` every cycle (fewer launches; the same results bit for bit);
+                        0: launch them one by one.  Ignored while profiling is on. */
 } die_te_solve_opts;
 
 typedef struct {

@@ -402,6 +402,39 @@ int run_eigs(die_te_ctx* c, int obj, int r, double tol, int mk, int maxrst, unsi
 // ------------------------------------------------------------------ GMRES
 // T: precision of the cycle's products and vectors; TB: storage of the Krylov basis in the
 // one-reduction path (T, or binary16 for the compressed basis).
+// Optional HIP graph of one restart cycle's inner iterations, captured on a stream of its own
+// (the caller's may be the legacy default stream, which cannot be captured) and launched on
+// the solve's stream.
+struct CycleGraph {
+  hipStream_t cs = nullptr;
+  hipGraphExec_t exec = nullptr;
+  CycleGraph() = default;
+  CycleGraph(const CycleGraph&) = delete;
+  CycleGraph& operator=(const CycleGraph&) = delete;
+  ~CycleGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  // issue(stream) queues the launches to capture
+  template <class F> int capture(F&& issue) {
+    DIE_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    DIE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = issue(cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc < 0) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    DIE_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) exec = nullptr;
+    DIE_HIP(ei);
+    return DIE_OK;
+  }
+};
+
 template <class T, class TB = T>
 int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
                 die_te_solve_info* info, hipStream_t st) {
@@ -500,6 +533,8 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     for (int r = 0; r < nrhs; ++r) k += act[r] != 0;
     return k;
   };
+  CycleGraph gx;
+  const bool use_graph = o.graph != 0 && !c->prof_on;
   for (;;) {
     // ---- FP64 true residual res = b - A u
     c->prof_nlive = nlive();
@@ -570,75 +605,85 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     DIE_HIP(hipMemcpyAsync(live.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     int* dlive = live.as<int>();
     DIE_HIP((die::launch_scale<double, T>(s, n, dcgs ? vf : q, n, sc.as<double>(), 1, n, nrhs, dact, st)));
-    // ---- Arnoldi / GMRES iterations of this cycle
-    for (int j = 0; dcgs && j <= m; ++j) {
-      // one-reduction step j: product on v, one dots pass, scalar update, one pass writing
-      // q_j into the basis and the next v
-      c2<T>* v = vf;
-      c2<T>* w = j < m ? wf : nullptr;
-      if (w) {
-        const c2<T>* zin = v;
-        if (defl) {
-          DIE_TRY(apply_pinv<T>(c, v, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st,
-                                rpo));
-          zin = Zb.as<c2<T>>();
+    // ---- Arnoldi / GMRES iterations of this cycle (every launch argument is the same in every
+    // cycle: the per-rhs state, flags and counters live on the device)
+    auto iterate = [&](hipStream_t st) -> int {
+      for (int j = 0; dcgs && j <= m; ++j) {
+        // one-reduction step j: product on v, one dots pass, scalar update, one pass writing
+        // q_j into the basis and the next v
+        c2<T>* v = vf;
+        c2<T>* w = j < m ? wf : nullptr;
+        if (w) {
+          const c2<T>* zin = v;
+          if (defl) {
+            DIE_TRY(apply_pinv<T>(c, v, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st,
+                                  rpo));
+            zin = Zb.as<c2<T>>();
+          }
+          DIE_TRY(apply_M<T>(c, reg, zin, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
         }
-        DIE_TRY(apply_M<T>(c, reg, zin, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
+        // algorithmic bytes: j basis vectors in TB, v and w in T
+        const double nl = (double)live_count(c, nrhs) * n;
+        const double bb = nl * sizeof(c2<TB>), vb = nl * sizeof(c2<T>);
+        {
+          ProfScope prof(c, DIE_PROF_DOTS, st, bb * j + vb * (w ? 2 : 1));
+          DIE_HIP((die::launch_dots2<TB, T>(qb, vs, j, v, w, n, n, nrhs, part2.as<double2>(), Dd.as<double2>(), dstride,
+                                            dcnt, dlive, st)));
+        }
+        DIE_HIP(die::launch_dcgs_update(Dd.as<double2>(), dstride, j, m, nrhs, state.as<die::GmresState>(),
+                                        Hu.as<double2>(), Rm.as<double2>(), cs.as<double>(), sn.as<double2>(),
+                                        g.as<double2>(), cprev.as<double2>(), coef.as<double2>(), dlive, st));
+        if (j < m) {
+          ProfScope prof(c, DIE_PROF_AXPY, st, bb * (j + 1) + vb * 3);
+          DIE_HIP((die::launch_dcgs_axpy<TB, T>(qb, vs, j, vf, wf, n, n, nrhs, coef.as<double2>(), m + 1,
+                                                state.as<die::GmresState>(), dlive, st)));
+        }
       }
-      // algorithmic bytes: j basis vectors in TB, v and w in T
-      const double nl = (double)live_count(c, nrhs) * n;
-      const double bb = nl * sizeof(c2<TB>), vb = nl * sizeof(c2<T>);
-      {
-        ProfScope prof(c, DIE_PROF_DOTS, st, bb * j + vb * (w ? 2 : 1));
-        DIE_HIP((die::launch_dots2<TB, T>(qb, vs, j, v, w, n, n, nrhs, part2.as<double2>(), Dd.as<double2>(), dstride,
-                                          dcnt, dlive, st)));
+      for (int j = 0; !dcgs && j < m; ++j) {
+        const c2<T>* qj = q + (size_t)j * vs;
+        const c2<T>* z = qj;
+        if (defl) {
+          DIE_TRY(apply_pinv<T>(c, qj, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st, rpo));
+          z = Zb.as<c2<T>>();
+        }
+        c2<T>* w = q + (size_t)(j + 1) * vs;
+        DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
+        // CGS2 against Q[0..j], FP64 Givens update, normalisation
+        const int nq = j + 1;
+        // per live right-hand side: dots read nq basis vectors and w; the multi-axpys also write w
+        const double vb = (double)live_count(c, nrhs) * n * sizeof(c2<T>);
+        {
+          ProfScope prof(c, DIE_PROF_DOTS, st, vb * (nq + 1));
+          DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
+                                          h1.as<double2>(), dcnt, dlive, st)));
+        }
+        {
+          ProfScope prof(c, DIE_PROF_AXPY, st, vb * (nq + 2));
+          DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, 1, nq, h1.as<double2>(), (const c2<T>*)nullptr, w, n, n, nrhs,
+                                           dlive, st)));
+        }
+        {
+          ProfScope prof(c, DIE_PROF_DOTS, st, vb * (nq + 1));
+          DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
+                                          h2.as<double2>(), dcnt, dlive, st)));
+        }
+        {
+          ProfScope prof(c, DIE_PROF_AXPY, st, vb * (nq + 2));
+          DIE_HIP((die::launch_faxpy_givens<T, T>(q, vs, n, nq, h2.as<double2>(), h1.as<double2>(), w, n, n, nrhs,
+                                                  part.as<double2>(), dcnt, state.as<die::GmresState>(),
+                                                  Rm.as<double2>(), cs.as<double>(), sn.as<double2>(), g.as<double2>(),
+                                                  m, dlive, st)));
+        }
+        DIE_HIP((die::launch_scale<T, T>(w, n, w, n, &state.as<die::GmresState>()->invbeta,
+                                         (int)(sizeof(die::GmresState) / sizeof(double)), n, nrhs, dlive, st)));
       }
-      DIE_HIP(die::launch_dcgs_update(Dd.as<double2>(), dstride, j, m, nrhs, state.as<die::GmresState>(),
-                                      Hu.as<double2>(), Rm.as<double2>(), cs.as<double>(), sn.as<double2>(),
-                                      g.as<double2>(), cprev.as<double2>(), coef.as<double2>(), dlive, st));
-      if (j < m) {
-        ProfScope prof(c, DIE_PROF_AXPY, st, bb * (j + 1) + vb * 3);
-        DIE_HIP((die::launch_dcgs_axpy<TB, T>(qb, vs, j, vf, wf, n, n, nrhs, coef.as<double2>(), m + 1,
-                                              state.as<die::GmresState>(), dlive, st)));
-      }
-    }
-    for (int j = 0; !dcgs && j < m; ++j) {
-      const c2<T>* qj = q + (size_t)j * vs;
-      const c2<T>* z = qj;
-      if (defl) {
-        DIE_TRY(apply_pinv<T>(c, qj, Zb.as<c2<T>>(), nrhs, part.as<double2>(), hd.as<double2>(), dcnt, dlive, st, rpo));
-        z = Zb.as<c2<T>>();
-      }
-      c2<T>* w = q + (size_t)(j + 1) * vs;
-      DIE_TRY(apply_M<T>(c, reg, z, reg ? Tb.as<c2<T>>() : nullptr, w, nrhs, dlive, st, rpo));
-      // CGS2 against Q[0..j], FP64 Givens update, normalisation
-      const int nq = j + 1;
-      // per live right-hand side: dots read nq basis vectors and w; the multi-axpys also write w
-      const double vb = (double)live_count(c, nrhs) * n * sizeof(c2<T>);
-      {
-        ProfScope prof(c, DIE_PROF_DOTS, st, vb * (nq + 1));
-        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
-                                        h1.as<double2>(), dcnt, dlive, st)));
-      }
-      {
-        ProfScope prof(c, DIE_PROF_AXPY, st, vb * (nq + 2));
-        DIE_HIP((die::launch_faxpy<T, T>(q, vs, n, 1, nq, h1.as<double2>(), (const c2<T>*)nullptr, w, n, n, nrhs,
-                                         dlive, st)));
-      }
-      {
-        ProfScope prof(c, DIE_PROF_DOTS, st, vb * (nq + 1));
-        DIE_HIP((die::launch_fdot<T, T>(q, vs, n, 1, nq, w, n, n, nrhs, part.as<double2>(), -1.0, nullptr, 0,
-                                        h2.as<double2>(), dcnt, dlive, st)));
-      }
-      {
-        ProfScope prof(c, DIE_PROF_AXPY, st, vb * (nq + 2));
-        DIE_HIP((die::launch_faxpy_givens<T, T>(q, vs, n, nq, h2.as<double2>(), h1.as<double2>(), w, n, n, nrhs,
-                                                part.as<double2>(), dcnt, state.as<die::GmresState>(),
-                                                Rm.as<double2>(), cs.as<double>(), sn.as<double2>(), g.as<double2>(),
-                                                m, dlive, st)));
-      }
-      DIE_HIP((die::launch_scale<T, T>(w, n, w, n, &state.as<die::GmresState>()->invbeta,
-                                       (int)(sizeof(die::GmresState) / sizeof(double)), n, nrhs, dlive, st)));
+      return DIE_OK;
+    };
+    if (use_graph) {
+      if (!gx.exec) DIE_TRY(gx.capture(iterate));  // captured once, replayed every cycle
+      DIE_HIP(hipGraphLaunch(gx.exec, st));
+    } else {
+      DIE_TRY(iterate(st));
     }
     // ---- least squares y = R^-1 g, then u += P^-1 (Q y)
     DIE_HIP(die::launch_lsq(state.as<die::GmresState>(), Rm.as<double2>(), g.as<double2>(), y.as<double2>(), m, nrhs,
