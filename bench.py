@@ -344,7 +344,9 @@ def main():
                              f"per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call",
                    "iters_mean": round(float(iters.mean()), 1), "iters_max": int(iters.max()),
                    "products_mean": round(float(prods.mean()), 1),
-                   "rel_res_true_max": max(x["rel_res_true"] for x in last), "setup_s": round(setup_s, 3)},
+                   "rel_res_true_max": max(x["rel_res_true"] for x in last), "setup_s": round(setup_s, 3),
+                   "fft_variants": {"complex64": s.fft_plan(nsolve, torch.complex64),
+                                    "complex128": s.fft_plan(nsolve, torch.complex128)}},
         "roofline": roofline,
     }
 

@@ -73,6 +73,8 @@ typedef struct {
   int eigs_krylov;         /* Krylov dimension of the eigensolver; 0 -> max(2r + 8, 24) */
   int eigs_max_restarts;   /* 0 -> 300 */
   unsigned long long seed; /* start vector of the eigensolver */
+  int fft_variant;         /* 0: autotune the operator product's FFT passes (see
+                              die_te_fft_plan); 1 + v: use variant v (0..3) in every pass */
 } die_te_setup_opts;
 
 typedef struct {
@@ -179,6 +181,19 @@ int die_te_apply_deflation(die_te_ctx *ctx, const void *x, void *y, int nrhs, vo
  * leaves its P^-1 unchanged there.  Synchronises `stream`. */
 int die_te_deflation_info(die_te_ctx *ctx, int *r, void *ritz_values, void *V, void *C,
                           void *stream);
+
+/* The FFT pass variants the operator products of nrhs fields in precision `prec` use:
+ * variants[0..2] for the row transform, the column transform with the symbol multiply and
+ * the inverse row transform.  Variant v: bit 0 set takes the other register radix (8 <->
+ * 16), bit 1 set halves the tile (rows or columns per block); only transforms of length
+ * >= 128 have variants.  Unless the context forces a variant (fft_variant at setup), the
+ * library picks them by timing the variants on the context's grid the first time a
+ * product of that precision and batch-size class (1-2, 3-32, > 32 fields) runs, or here:
+ * the radix of each pass once per device, precision and grid shape for the whole process
+ * (it changes the rounding, so every context and batch shares it), the tile per batch-size
+ * class (results are equal bit for bit).  Tuning allocates scratch for min(nrhs, 64)
+ * fields and synchronises `stream`. */
+int die_te_fft_plan(die_te_ctx *ctx, int prec, int nrhs, int *variants, void *stream);
 
 /* Diagnostic: in-place unnormalised forward (inverse = 0) or backward
  * (inverse = 1, also unnormalised) 2-D FFT of `batch` complex arrays

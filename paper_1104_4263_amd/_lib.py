@@ -31,7 +31,8 @@ class DieTeGrid(ctypes.Structure):
 
 class DieTeSetupOpts(ctypes.Structure):
     _fields_ = [("regularize", ctypes.c_int), ("deflate_k", ctypes.c_int), ("eigs_tol", ctypes.c_double),
-                ("eigs_krylov", ctypes.c_int), ("eigs_max_restarts", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
+                ("eigs_krylov", ctypes.c_int), ("eigs_max_restarts", ctypes.c_int), ("seed", ctypes.c_ulonglong),
+                ("fft_variant", ctypes.c_int)]
 
 
 class DieTeSolveOpts(ctypes.Structure):
@@ -77,6 +78,7 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(DieTeSolveOpts),
                                        ctypes.POINTER(vp), vp]
     lib.die_te_apply_deflation.argtypes = [vp, vp, vp, i, vp]
+    lib.die_te_fft_plan.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_int), vp]
     lib.die_te_deflation_info.argtypes = [vp, ctypes.POINTER(ip), vp, vp, vp, vp]
     lib.die_te_fft2.argtypes = [vp, i, i, i, i, i, vp]
     lib.die_te_destroy.argtypes = [vp]

@@ -32,11 +32,12 @@ def _prec(t: torch.Tensor) -> int:
 
 def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0, py: int = 0,
                  regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
-                 eigs_max_restarts: int = 0, seed: int = 0) -> ctypes.c_void_p:
+                 eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1) -> ctypes.c_void_p:
+    """fft_variant: -1 autotunes the FFT passes, 0..3 forces that variant in every pass."""
     lib = load()
     g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
     o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
-                       int(eigs_max_restarts), int(seed))
+                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1)
     ctx = ctypes.c_void_p()
     check(lib.die_te_setup(ctypes.byref(ctx), ctypes.byref(g), _dev(eps_r, (torch.complex128,), "eps_r"),
                            ctypes.byref(o), _stream()))
@@ -45,11 +46,12 @@ def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float 
 
 def die_te_setup_multi(nx: int, ny: int, h: float, nobj: int, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0,
                        py: int = 0, regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4,
-                       eigs_krylov: int = 0, eigs_max_restarts: int = 0, seed: int = 0) -> ctypes.c_void_p:
+                       eigs_krylov: int = 0, eigs_max_restarts: int = 0, seed: int = 0,
+                       fft_variant: int = -1) -> ctypes.c_void_p:
     lib = load()
     g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
     o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
-                       int(eigs_max_restarts), int(seed))
+                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1)
     ctx = ctypes.c_void_p()
     check(lib.die_te_setup_multi(ctypes.byref(ctx), ctypes.byref(g), int(nobj),
                                  _dev(eps_r, (torch.complex128,), "eps_r"), ctypes.byref(o), _stream()))
@@ -99,6 +101,13 @@ def die_te_solve_batch(ctxs, e_ins, e_tots, nrhs, *, restart: int = 30, max_iter
     rc = load().die_te_solve_batch(c_arr, n, i_arr, o_arr, r_arr, ctypes.byref(o), f_arr, _stream())
     check(rc, allow_warning=True)
     return rc, [[x[k].as_dict() for k in range(int(r))] for x, r in zip(infos, nrhs)]
+
+
+def die_te_fft_plan(ctx, prec: int, nrhs: int) -> list[int]:
+    """The FFT pass variants (row, column + symbol, inverse row) of products of nrhs fields."""
+    v = (ctypes.c_int * 3)()
+    check(load().die_te_fft_plan(ctx, int(prec), int(nrhs), v, _stream()))
+    return [int(x) for x in v]
 
 
 def die_te_apply_deflation(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
@@ -164,7 +173,7 @@ class Solver:
 
     def __init__(self, nx: int, ny: int, h: float, eps_r, *, k_b: float = 2.0 * math.pi, px: int = 0, py: int = 0,
                  regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
-                 eigs_max_restarts: int = 0, seed: int = 0, device: str = "cuda"):
+                 eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1, device: str = "cuda"):
         eps = torch.as_tensor(eps_r, dtype=torch.complex128).to(device).contiguous()
         if tuple(eps.shape[-2:]) != (ny, nx) or eps.dim() not in (2, 3):
             raise ValueError(f"eps_r must have shape ({ny}, {nx}) or (nobj, {ny}, {nx})")
@@ -174,7 +183,7 @@ class Solver:
         self.device = device
         self.regularized = bool(regularize)
         kw = dict(k_b=k_b, px=px, py=py, regularize=regularize, deflate_k=deflate_k, eigs_tol=eigs_tol,
-                  eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts, seed=seed)
+                  eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts, seed=seed, fft_variant=fft_variant)
         if eps.dim() == 2:
             self.ctx = die_te_setup(nx, ny, h, eps, **kw)
         else:
@@ -216,6 +225,9 @@ class Solver:
         rc, infos = die_te_solve_batch([s.ctx for s in solvers], [e.contiguous() for e in e_ins], outs, nrhs,
                                        x0_given=x0s is not None, **kw)
         return [(u, inf) for u, inf in zip(outs, infos)], rc
+
+    def fft_plan(self, nrhs: int, dtype=torch.complex64) -> list[int]:
+        return die_te_fft_plan(self.ctx, DIE_C128 if dtype == torch.complex128 else DIE_C64, nrhs)
 
     def apply_deflation(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)

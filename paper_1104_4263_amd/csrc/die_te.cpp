@@ -14,7 +14,10 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -76,6 +79,9 @@ struct die_te_ctx {
   double prof_bytes[3] = {0, 0, 0};  // algorithmic bytes of the bracketed launches
   int prof_every = 1;
   int prof_nlive = -1;  // right-hand sides live in the current launches (-1: all of them)
+  // FFT pass variants of the products: forced (>= 0) or tuned per [FP64, FP32][batch class][pass]
+  int fft_force = -1;
+  int fftv[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}, {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};
   ~die_te_ctx() {
     for (auto& v : prof_ev)
       for (auto& pr : v) {
@@ -146,19 +152,131 @@ int ensure_work(die_te_ctx* c, size_t bytes, hipStream_t st) {
   return c->work.alloc(bytes);
 }
 
+// ------------------------------------------------------------------ FFT pass autotuner
+// The radix of each product pass is chosen once per (device, precision, grid shape) for the
+// whole process, because it changes the rounding and every context and batch size must agree;
+// the tile of each pass is chosen per batch-size class (it moves no arithmetic).  Both by
+// timing the variants of the pass on the grid with min(nrhs, 64) fields.
+struct TuneKey {
+  int dev, prec, lpx, lpy, nx, ny;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, prec, lpx, lpy, nx, ny) < std::tie(o.dev, o.prec, o.lpx, o.lpy, o.nx, o.ny);
+  }
+};
+struct TuneEntry {
+  int radix[3] = {-1, -1, -1};                                   // per pass: 0 default radix, 1 the other
+  int tile[3][3] = {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}};   // [batch class][pass]: 0 full, 1 half tile
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+int batch_class(int nrhs) { return nrhs <= 2 ? 0 : (nrhs <= 32 ? 1 : 2); }
+
+template <class T> const c2<T>* chi_of(const die_te_ctx* c, bool reg);
+template <class T> const c2<T>* sym_of(const die_te_ctx* c);
+
+// Launch pass `pass` (0 rows, 1 columns + symbol, 2 inverse rows) of a product on R fields.
+template <class T>
+hipError_t launch_pass(die_te_ctx* c, int pass, int v, const c2<T>* x, c2<T>* y, c2<T>* W, int R, const int* live,
+                       hipStream_t st, int rpo, const c2<T>* chi) {
+  if (pass == 0) return die::launch_rows_fwd<T, T>(c->lpx, false, x, chi, W, c->nx, c->ny, R, 2, 0, rpo, live, st, v);
+  if (pass == 1) return die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, R, live, st, v);
+  return die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, 2 * R, 2, live, st, v);
+}
+
+// The variants of the three passes for products of nrhs fields; tunes them first if needed
+// (synchronises st; never while st is being captured: the default variants are used then).
+template <class T>
+int fft_plan(die_te_ctx* c, int nrhs, hipStream_t st, const int** out) {
+  const int prec = std::is_same<T, double>::value ? 0 : 1, bc = batch_class(nrhs);
+  int* pv = c->fftv[prec][bc];
+  *out = pv;
+  if (pv[0] >= 0) return DIE_OK;
+  if (c->fft_force >= 0) {
+    pv[0] = pv[1] = pv[2] = c->fft_force;
+    return DIE_OK;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  DIE_HIP(hipStreamIsCapturing(st, &cap));
+  static const int kDefault[3] = {0, 0, 0};
+  if (cap != hipStreamCaptureStatusNone) {
+    *out = kDefault;
+    return DIE_OK;
+  }
+  const bool tuned_len[3] = {c->lpx >= die::kFftTunedMinLog, c->lpy >= die::kFftTunedMinLog,
+                             c->lpx >= die::kFftTunedMinLog};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  TuneEntry& te = g_tune[TuneKey{c->dev, prec, c->lpx, c->lpy, c->nx, c->ny}];
+  if (te.tile[bc][0] < 0) {
+    const int R = std::min(nrhs, 64);
+    const size_t vbytes = (size_t)R * c->nvec * sizeof(c2<T>);
+    DBuf xb, yb;
+    DIE_TRY(xb.alloc(vbytes));
+    DIE_TRY(yb.alloc(vbytes));
+    DIE_HIP(hipMemsetAsync(xb.p, 0, vbytes, st));
+    DIE_TRY(ensure_work(c, (size_t)R * 2 * c->px * c->ny * sizeof(c2<T>), st));
+    c2<T>* W = c->work.as<c2<T>>();
+    const c2<T>* chi = chi_of<T>(c, false);
+    hipEvent_t e0, e1;
+    DIE_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(DIE_E_HIP, "hipEventCreate failed");
+    }
+    struct Ev {
+      hipEvent_t a, b;
+      ~Ev() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } ev{e0, e1};
+    auto time_pass = [&](int pass, int v, float* ms) -> int {
+      for (int k = 0; k < 2; ++k)
+        DIE_HIP(launch_pass<T>(c, pass, v, xb.as<c2<T>>(), yb.as<c2<T>>(), W, R, nullptr, st, 0, chi));
+      DIE_HIP(hipEventRecord(ev.a, st));
+      for (int k = 0; k < 3; ++k)
+        DIE_HIP(launch_pass<T>(c, pass, v, xb.as<c2<T>>(), yb.as<c2<T>>(), W, R, nullptr, st, 0, chi));
+      DIE_HIP(hipEventRecord(ev.b, st));
+      DIE_HIP(hipEventSynchronize(ev.b));
+      DIE_HIP(hipEventElapsedTime(ms, ev.a, ev.b));
+      return DIE_OK;
+    };
+    for (int pass = 0; pass < 3; ++pass) {
+      if (!tuned_len[pass]) {
+        te.radix[pass] = 0;
+        te.tile[bc][pass] = 0;
+        continue;
+      }
+      if (te.radix[pass] < 0) {
+        float t0, t1;
+        DIE_TRY(time_pass(pass, 0, &t0));
+        DIE_TRY(time_pass(pass, 1, &t1));
+        te.radix[pass] = t1 < t0 ? 1 : 0;
+      }
+      float tf, th;
+      DIE_TRY(time_pass(pass, te.radix[pass], &tf));
+      DIE_TRY(time_pass(pass, te.radix[pass] | 2, &th));
+      te.tile[bc][pass] = th < tf ? 1 : 0;
+    }
+    DIE_HIP(hipStreamSynchronize(st));  // xb, yb are freed on return
+  }
+  for (int pass = 0; pass < 3; ++pass) pv[pass] = te.radix[pass] | (te.tile[bc][pass] << 1);
+  return DIE_OK;
+}
+
 // y = A(chi) x (reg = false) or A(chi') x (reg = true) for nrhs fields.
 // Right-hand side r uses object obj0 + r / rpo (rpo = 0: every right-hand side uses object obj0).
 template <class T>
 int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const int* live, hipStream_t st,
              int rpo, int obj0 = 0) {
+  const int* v = nullptr;
+  DIE_TRY(fft_plan<T>(c, nrhs, st, &v));
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * sizeof(c2<T>), st));
   c2<T>* W = c->work.as<c2<T>>();
   const int nchi = rpo > 0 ? (nrhs + rpo - 1) / rpo : 1;
   ProfScope prof(c, DIE_PROF_PRODUCT, st, product_bytes(c, live_count(c, nrhs), nchi, sizeof(c2<T>)));
   const c2<T>* chi = chi_of<T>(c, reg) + (size_t)obj0 * c->ncell;
-  DIE_HIP((die::launch_rows_fwd<T, T>(c->lpx, false, x, chi, W, c->nx, c->ny, nrhs, 2, 0, rpo, live, st)));
-  DIE_HIP((die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, nrhs, live, st)));
-  DIE_HIP((die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, 2 * nrhs, 2, live, st)));
+  for (int pass = 0; pass < 3; ++pass) DIE_HIP(launch_pass<T>(c, pass, v[pass], x, y, W, nrhs, live, st, rpo, chi));
   return DIE_OK;
 }
 
@@ -483,6 +601,11 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   DIE_TRY(cnt.alloc((size_t)nrhs * die::kCounterStride * sizeof(int)));
   DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nrhs * die::kCounterStride * sizeof(int), st));
   int* dcnt = cnt.as<int>();
+  {  // pick the FFT pass variants now, never inside a captured cycle
+    const int* pv = nullptr;
+    DIE_TRY(fft_plan<T>(c, nrhs, st, &pv));
+    DIE_TRY(fft_plan<double>(c, nrhs, st, &pv));
+  }
   DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * std::max(sizeof(c2<T>), sizeof(double2)), st));
   // one-reduction Arnoldi: raw dots, unrotated Hessenberg, first projections, axpy coefficients
   const int dstride = 2 * (m + 2);
@@ -770,6 +893,8 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
   die_te_setup_opts o{};
   if (opts) o = *opts;
   if (o.deflate_k < 0) return fail(DIE_E_INVALID, "deflate_k must be >= 0");
+  if (o.fft_variant < 0 || o.fft_variant > die::kFftVariants)
+    return fail(DIE_E_INVALID, "fft_variant must be 0 (autotune) or 1 + v with v in [0, 3]");
 
   auto* c = new (std::nothrow) die_te_ctx();
   if (!c) return fail(DIE_E_NOMEM, "host allocation failed");
@@ -785,6 +910,7 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
   c->nvec = 2 * c->ncell;
   c->nobj = nobj;
   c->regularize = o.regularize ? 1 : 0;
+  c->fft_force = o.fft_variant - 1;
   const size_t ncells = c->ncell * (size_t)nobj;
 
   // contrast (eq. ElectricContrast) and regularizer contrast (eq. InverseSymbol)
@@ -944,6 +1070,18 @@ int die_te_solve_batch(die_te_ctx* const* ctx, int nctx, const void* const* e_in
     if (res[i].rc < 0) return fail(res[i].rc, "context " + std::to_string(i) + ": " + res[i].msg);
   for (int i = 0; i < nctx; ++i)
     if (res[i].rc != DIE_OK) return res[i].rc;
+  return DIE_OK;
+}
+
+int die_te_fft_plan(die_te_ctx* c, int prec, int nrhs, int* variants, void* stream) {
+  die_host::last_error().clear();
+  DIE_TRY(check_ctx(c));
+  if (!variants || nrhs < 1) return fail(DIE_E_INVALID, "null variants or nrhs < 1");
+  if (prec != DIE_C128 && prec != DIE_C64) return fail(DIE_E_INVALID, "prec must be DIE_C128 or DIE_C64");
+  const int* v = nullptr;
+  if (prec == DIE_C128) DIE_TRY(fft_plan<double>(c, nrhs, (hipStream_t)stream, &v));
+  else DIE_TRY(fft_plan<float>(c, nrhs, (hipStream_t)stream, &v));
+  for (int p = 0; p < 3; ++p) variants[p] = v[p];
   return DIE_OK;
 }
 

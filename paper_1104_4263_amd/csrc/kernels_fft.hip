@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace die {
@@ -28,24 +29,32 @@ template <class T> __host__ __device__ constexpr int fft_loge(int logn) {
   return (sizeof(c2<T>) == 8 && logn % 3 != 0) ? 4 : 3;
 }
 constexpr int kLdsBudget = 76000;
-template <class T> __host__ __device__ constexpr int fft_e(int logn) {
-  return 1 << (fft_loge<T>(logn) < logn ? fft_loge<T>(logn) : logn);
+
+// Variants of the three product passes, chosen at run time by the library's autotuner:
+// bit 0 takes the other radix (8 <-> 16), bit 1 halves the tile (rows per block in the row
+// passes, columns per block in the column pass).  Transforms shorter than 2^kFftTunedMinLog
+// compile the default variant only.  A tile change moves no arithmetic (results are equal
+// bit for bit); a radix change rounds differently.
+template <class T> __host__ __device__ constexpr int fft_le(int logn, int v) {
+  const int d = fft_loge<T>(logn), le = (v & 1) ? 7 - d : d;
+  return le < logn ? le : logn;
 }
-template <class T> __host__ __device__ constexpr int rows_ty(int logn) {
+template <class T> __host__ __device__ constexpr int fft_e(int logn, int v = 0) { return 1 << fft_le<T>(logn, v); }
+template <class T> __host__ __device__ constexpr int rows_ty(int logn, int v = 0) {
   int n = 1 << logn, es = (int)sizeof(c2<T>), ty = 16;
-  while (ty > 1 && (ty * fft_row_stride(n, es) * es > kLdsBudget || ty * n / fft_e<T>(logn) > 1024)) ty >>= 1;
-  return ty;
+  while (ty > 1 && (ty * fft_row_stride(n, es) * es > kLdsBudget || ty * n / fft_e<T>(logn, v) > 1024)) ty >>= 1;
+  return (v & 2) && ty > 1 ? ty >> 1 : ty;
 }
-template <class T> __host__ __device__ constexpr int rows_threads(int logn) {
-  return rows_ty<T>(logn) * (1 << logn) / fft_e<T>(logn);
+template <class T> __host__ __device__ constexpr int rows_threads(int logn, int v = 0) {
+  return rows_ty<T>(logn, v) * (1 << logn) / fft_e<T>(logn, v);
 }
-template <class T> __host__ __device__ constexpr int cols_cx(int logn) {
+template <class T> __host__ __device__ constexpr int cols_cx(int logn, int v = 0) {
   int n = 1 << logn, es = (int)sizeof(c2<T>), cx = 16;
-  while (cx > 1 && (2 * cx * fft_row_stride(n, es) * es > kLdsBudget || cx * n / fft_e<T>(logn) > 1024)) cx >>= 1;
-  return cx;
+  while (cx > 1 && (2 * cx * fft_row_stride(n, es) * es > kLdsBudget || cx * n / fft_e<T>(logn, v) > 1024)) cx >>= 1;
+  return (v & 2) && cx > 1 ? cx >> 1 : cx;
 }
-template <class T> __host__ __device__ constexpr int cols_threads(int logn) {
-  return cols_cx<T>(logn) * (1 << logn) / fft_e<T>(logn);
+template <class T> __host__ __device__ constexpr int cols_threads(int logn, int v = 0) {
+  return cols_cx<T>(logn, v) * (1 << logn) / fft_e<T>(logn, v);
 }
 
 // ------------------------------------------------------------------ pass 1
@@ -53,13 +62,13 @@ template <class T> __host__ __device__ constexpr int cols_threads(int logn) {
 // Loads rows position-fast (coalesced), stores W[s][x][y] array-fast (TY-contiguous).
 // HALF: the rows hold at most N/2 values (nx <= N/2, the zero-padded product), so inputs in
 // the upper half are known zeros at compile time and the first stage folds them away.
-template <class T, class S, int LOGN, bool INV, bool HALF>
-__global__ void __launch_bounds__(rows_threads<T>(LOGN))
+template <class T, class S, int LOGN, bool INV, bool HALF, int V = 0>
+__global__ void __launch_bounds__(rows_threads<T>(LOGN, V))
 k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* __restrict__ W,
            const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr, int rb, int rpo,
            const int* __restrict__ live) {
-  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(LOGN), 1, false, kPosFast, kArrFast>;
-  constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN);
+  using F = RegFft<T, LOGN, rows_ty<T>(LOGN, V), fft_le<T>(LOGN, V), 1, false, kPosFast, kArrFast>;
+  constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN, V);
   __shared__ c2<T> lds[F::LDS_ELEMS];
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = L % ntiles, grp = L / ntiles;
@@ -110,13 +119,13 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* _
 // so the 2x2 symbol multiply runs in registers between the forward and the inverse
 // transform.  Logical blocks are ordered rhs-fastest: blocks sharing symbol columns run
 // on the same XCD at the same time.
-template <class T, int LOGN>
-__global__ void __launch_bounds__(cols_threads<T>(LOGN))
+template <class T, int LOGN, int V = 0>
+__global__ void __launch_bounds__(cols_threads<T>(LOGN, V))
 k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>* __restrict__ tw, int ncols,
               int nrows, int nrhs, const int* __restrict__ live) {
-  constexpr int CX = cols_cx<T>(LOGN);
-  using F = RegFft<T, LOGN, CX, fft_loge<T>(LOGN), 2, false, kPosFast, kPosFast>;
-  using G = RegFft<T, LOGN, CX, fft_loge<T>(LOGN), 2, true, kPosFast, kPosFast>;
+  constexpr int CX = cols_cx<T>(LOGN, V);
+  using F = RegFft<T, LOGN, CX, fft_le<T>(LOGN, V), 2, false, kPosFast, kPosFast>;
+  using G = RegFft<T, LOGN, CX, fft_le<T>(LOGN, V), 2, true, kPosFast, kPosFast>;
   static_assert(G::R0 == F::RL, "inverse must start with the forward's last radix");
   constexpr int N = F::N, E = F::E;
   __shared__ c2<T> lds[F::LDS_ELEMS];
@@ -178,7 +187,7 @@ template <class T, int LOGN, bool INV>
 __global__ void __launch_bounds__(cols_threads<T>(LOGN))
 k_cols_plain(c2<T>* __restrict__ W, const c2<T>* __restrict__ tw, int ncols, int ntiles) {
   constexpr int NB = cols_cx<T>(LOGN);
-  using F = RegFft<T, LOGN, NB, fft_loge<T>(LOGN), 1, false, kPosFast, kPosFast>;
+  using F = RegFft<T, LOGN, NB, fft_le<T>(LOGN, 0), 1, false, kPosFast, kPosFast>;
   constexpr int N = F::N, E = F::E;
   __shared__ c2<T> lds[F::LDS_ELEMS];
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -207,12 +216,12 @@ k_cols_plain(c2<T>* __restrict__ W, const c2<T>* __restrict__ tw, int ncols, int
 // ------------------------------------------------------------------ pass 3
 // Block: TY rows of one set.  Loads W[s][x][y] array-fast (TY-contiguous), stores
 // y = u - crop(IFFT) position-fast (coalesced).
-template <class T, class S, int LOGN>
-__global__ void __launch_bounds__(rows_threads<T>(LOGN))
+template <class T, class S, int LOGN, int V = 0>
+__global__ void __launch_bounds__(rows_threads<T>(LOGN, V))
 k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* __restrict__ y,
                const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int spr, const int* __restrict__ live) {
-  using F = RegFft<T, LOGN, rows_ty<T>(LOGN), fft_loge<T>(LOGN), 1, false, kArrFast, kPosFast>;
-  constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN);
+  using F = RegFft<T, LOGN, rows_ty<T>(LOGN, V), fft_le<T>(LOGN, V), 1, false, kArrFast, kPosFast>;
+  constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN, V);
   __shared__ c2<T> lds[F::LDS_ELEMS];
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = L % ntiles, s = L / ntiles, t = threadIdx.x;
@@ -335,28 +344,52 @@ template <> const float2* table_for<float>() {
 
 #define DIE_LOGN_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 
+namespace {
+// Calls f(std::integral_constant<int, V>) for the pass variant v (default only below the
+// tuned lengths).
+template <int L, class F> void for_variant(int v, F&& f) {
+  if constexpr (L < kFftTunedMinLog) {
+    (void)v;
+    f(std::integral_constant<int, 0>{});
+  } else {
+    switch (v & (kFftVariants - 1)) {
+      case 1: f(std::integral_constant<int, 1>{}); break;
+      case 2: f(std::integral_constant<int, 2>{}); break;
+      case 3: f(std::integral_constant<int, 3>{}); break;
+      default: f(std::integral_constant<int, 0>{}); break;
+    }
+  }
+}
+}  // namespace
+
 template <class T, class S>
 hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* chi, c2<T>* W, int nx, int nrows,
-                           int nrhs, int spr, int rb, int rpo, const int* live, hipStream_t st) {
+                           int nrhs, int spr, int rb, int rpo, const int* live, hipStream_t st, int v) {
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nrhs <= 0 || nrows <= 0) return hipSuccess;
+  const bool half = !inverse && 2 * nx <= (1 << logn);  // the zero-padded product: the tuned kernels
   switch (logn) {
 #define CASE(L)                                                                                         \
   case L: {                                                                                             \
-    const int ntiles = (nrows + rows_ty<T>(L) - 1) / rows_ty<T>(L);                                     \
-    if (rb <= 0) rb = std::max(1, std::min(nrhs, ntiles * nrhs / 2048));                                \
-    const int ngroups = (nrhs + rb - 1) / rb;                                                           \
-    dim3 grid((unsigned)(ntiles * ngroups));                                                            \
-    if (inverse)                                                                                        \
-      hipLaunchKernelGGL((k_rows_fwd<T, S, L, true, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
-                         nx, nrows, ntiles, nrhs, spr, rb, rpo, live);                                  \
-    else if (2 * nx <= (1 << L))                                                                        \
-      hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, true>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
-                         nx, nrows, ntiles, nrhs, spr, rb, rpo, live);                                  \
-    else                                                                                                \
-      hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, false>), grid, dim3(rows_threads<T>(L)), 0, st, x, chi, W, tw, \
-                         nx, nrows, ntiles, nrhs, spr, rb, rpo, live);                                  \
+    for_variant<L>(half ? v : 0, [&](auto vc) {                                                         \
+      constexpr int V = decltype(vc)::value;                                                            \
+      const int ntiles = (nrows + rows_ty<T>(L, V) - 1) / rows_ty<T>(L, V);                             \
+      const int rbv = rb > 0 ? rb : std::max(1, std::min(nrhs, ntiles * nrhs / 2048));                  \
+      dim3 grid((unsigned)(ntiles * ((nrhs + rbv - 1) / rbv)));                                         \
+      dim3 block(rows_threads<T>(L, V));                                                                \
+      if (half)                                                                                         \
+        hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, true, V>), grid, block, 0, st, x, chi, W, tw, nx, nrows, \
+                           ntiles, nrhs, spr, rbv, rpo, live);                                          \
+      else if constexpr (V == 0) {                                                                      \
+        if (inverse)                                                                                    \
+          hipLaunchKernelGGL((k_rows_fwd<T, S, L, true, false>), grid, block, 0, st, x, chi, W, tw, nx, nrows, \
+                             ntiles, nrhs, spr, rbv, rpo, live);                                        \
+        else                                                                                            \
+          hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, false>), grid, block, 0, st, x, chi, W, tw, nx, nrows, \
+                             ntiles, nrhs, spr, rbv, rpo, live);                                        \
+      }                                                                                                 \
+    });                                                                                                 \
     break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
@@ -369,7 +402,7 @@ hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* 
 
 template <class T>
 hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
-                              const int* live, hipStream_t st) {
+                              const int* live, hipStream_t st, int v) {
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nrhs <= 0) return hipSuccess;
@@ -377,9 +410,12 @@ hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, i
   switch (logn) {
 #define CASE(L)                                                                                         \
   case L: {                                                                                             \
-    dim3 grid((unsigned)(((ncols + cols_cx<T>(L) - 1) / cols_cx<T>(L)) * nrhs));                        \
-    hipLaunchKernelGGL((k_cols_symbol<T, L>), grid, dim3(cols_threads<T>(L)), 0, st, W, sym, tw, ncols, nrows, \
-                       nrhs, live);                                                                     \
+    for_variant<L>(v, [&](auto vc) {                                                                    \
+      constexpr int V = decltype(vc)::value;                                                            \
+      dim3 grid((unsigned)(((ncols + cols_cx<T>(L, V) - 1) / cols_cx<T>(L, V)) * nrhs));                \
+      hipLaunchKernelGGL((k_cols_symbol<T, L, V>), grid, dim3(cols_threads<T>(L, V)), 0, st, W, sym, tw, ncols, \
+                         nrows, nrhs, live);                                                            \
+    });                                                                                                 \
     break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
@@ -392,7 +428,7 @@ hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, i
 
 template <class T, class S>
 hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y, int nx, int nrows, int nsets,
-                               int spr, const int* live, hipStream_t st) {
+                               int spr, const int* live, hipStream_t st, int v) {
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nsets <= 0 || nrows <= 0) return hipSuccess;
@@ -400,10 +436,13 @@ hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* 
   switch (logn) {
 #define CASE(L)                                                                                         \
   case L: {                                                                                             \
-    const int ntiles = (nrows + rows_ty<T>(L) - 1) / rows_ty<T>(L);                                     \
-    dim3 grid((unsigned)(ntiles * nsets));                                                              \
-    hipLaunchKernelGGL((k_rows_inv_sub<T, S, L>), grid, dim3(rows_threads<T>(L)), 0, st, W, u, y, tw, nx, nrows, \
-                       ntiles, spr, live);                                                              \
+    for_variant<L>(v, [&](auto vc) {                                                                    \
+      constexpr int V = decltype(vc)::value;                                                            \
+      const int ntiles = (nrows + rows_ty<T>(L, V) - 1) / rows_ty<T>(L, V);                             \
+      dim3 grid((unsigned)(ntiles * nsets));                                                            \
+      hipLaunchKernelGGL((k_rows_inv_sub<T, S, L, V>), grid, dim3(rows_threads<T>(L, V)), 0, st, W, u, y, tw, nx, \
+                         nrows, ntiles, spr, live);                                                     \
+    });                                                                                                 \
     break;                                                                                              \
   }
     DIE_LOGN_CASES(CASE)
@@ -456,17 +495,17 @@ hipError_t launch_pack_symbol(const double2* W, double2* s64, float2* s32, int p
 
 // explicit instantiations
 template hipError_t launch_rows_fwd<double, double>(int, bool, const double2*, const double2*, double2*, int,
-                                                    int, int, int, int, int, const int*, hipStream_t);
+                                                    int, int, int, int, int, const int*, hipStream_t, int);
 template hipError_t launch_rows_fwd<float, float>(int, bool, const float2*, const float2*, float2*, int, int,
-                                                  int, int, int, int, const int*, hipStream_t);
+                                                  int, int, int, int, const int*, hipStream_t, int);
 template hipError_t launch_cols_symbol<double>(int, double2*, const double2*, int, int, int, const int*,
-                                               hipStream_t);
+                                               hipStream_t, int);
 template hipError_t launch_cols_symbol<float>(int, float2*, const float2*, int, int, int, const int*,
-                                              hipStream_t);
+                                              hipStream_t, int);
 template hipError_t launch_rows_inv_sub<double, double>(int, const double2*, const double2*, double2*, int,
-                                                        int, int, int, const int*, hipStream_t);
+                                                        int, int, int, const int*, hipStream_t, int);
 template hipError_t launch_rows_inv_sub<float, float>(int, const float2*, const float2*, float2*, int, int,
-                                                      int, int, const int*, hipStream_t);
+                                                      int, int, const int*, hipStream_t, int);
 template hipError_t launch_cols_plain<double>(int, bool, double2*, int, int, hipStream_t);
 template hipError_t launch_cols_plain<float>(int, bool, float2*, int, int, hipStream_t);
 template hipError_t launch_transpose<double>(const double2*, double2*, int, int, int, hipStream_t);

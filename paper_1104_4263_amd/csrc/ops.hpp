@@ -8,6 +8,12 @@ namespace die {
 // Twiddle tables exp(-2 pi i j / 4096) for the current device (created on first use).
 hipError_t fft_tables(const double2** tw64, const float2** tw32);
 
+// Variants of the three product passes (the `v` argument; see kernels_fft.hip): bit 0 the
+// other radix, bit 1 half the tile.  Only transforms of length >= 2^kFftTunedMinLog have
+// them (shorter ones, the inverse and the unpadded row transforms always use variant 0).
+constexpr int kFftVariants = 4;
+constexpr int kFftTunedMinLog = 7;
+
 // Pass 1.  For every set s = r * spr + c (r < nrhs right-hand sides, c < spr components)
 // and row y < nrows: W[s][x][y] = FFT_N( pad_N( chi[y][:] * x_in[s][y][:] ) )[x],
 // x < N = 2^logn (chi may be NULL).  x_in rows have nx <= N entries; W is transposed
@@ -17,20 +23,20 @@ hipError_t fft_tables(const double2** tw64, const float2** tw32);
 template <class T, class S>
 hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x_in, const c2<T>* chi, c2<T>* W,
                            int nx, int nrows, int nrhs, int spr, int rb, int rpo, const int* live,
-                           hipStream_t st);
+                           hipStream_t st, int v = 0);
 
 // Pass 2.  For every rhs r and column x < ncols of W[r][c][x][0:nrows] (c = 0, 1):
 // FFT_N over y (zero padded), 2x2 multiply by sym[x][ky][{11,12,22}], inverse FFT_N,
 // keep y < nrows; in place.
 template <class T>
 hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
-                              const int* live, hipStream_t st);
+                              const int* live, hipStream_t st, int v = 0);
 
 // Pass 3.  y_out[s][y][x] = u[s][y][x] - IFFT_N(W[s][:][y])[x] for x < nx.
 template <class T, class S>
 hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y_out, int nx,
                                int nrows, int nsets, int sets_per_rhs, const int* live,
-                               hipStream_t st);
+                               hipStream_t st, int v = 0);
 
 // Full-length FFT along the contiguous axis of W[nsets][ncols][N], in place.
 template <class T>
