@@ -98,6 +98,14 @@ typedef struct {
                         into a HIP graph (on a stream the call creates) and replay it on
                         `stream` every cycle (fewer launches; the same results bit for bit);
                         0: launch them one by one.  Ignored while profiling is on. */
+  int block;         /* 1: block GMRES(m): all right-hand sides of an object share one block
+                        Krylov space (its first block spans their residuals, rank-revealed by a
+                        pivoted Cholesky QR); CGS2 block orthogonalisation and CholQR2 of each
+                        new block on the matrix cores (complex GEMM in the basis precision), the
+                        block least squares once per cycle; every cycle restarts from the FP64
+                        true residual.  Needs mixed = 0 (FP64) or 1 (complex64 basis and
+                        products); orth and graph do not apply.  iters counts block steps;
+                        products_A per right-hand side is the object's share.  0: per-rhs GMRES */
 } die_te_solve_opts;
 
 typedef struct {

@@ -38,7 +38,7 @@ class DieTeSetupOpts(ctypes.Structure):
 class DieTeSolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("tol", ctypes.c_double),
                 ("mixed", ctypes.c_int), ("x0_given", ctypes.c_int), ("reg_margin", ctypes.c_double),
-                ("orth", ctypes.c_int), ("graph", ctypes.c_int)]
+                ("orth", ctypes.c_int), ("graph", ctypes.c_int), ("block", ctypes.c_int)]
 
 
 class DieTeSolveInfo(ctypes.Structure):

@@ -70,11 +70,11 @@ def die_te_regularize(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
 
 def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, restart: int = 30,
                  max_iters: int = 100_000, tol: float = 1e-8, mixed: int = 0, x0_given: bool = False,
-                 reg_margin: float = 0.0, orth: int = 0, graph: int = 0) -> tuple[int, list[dict]]:
+                 reg_margin: float = 0.0, orth: int = 0, graph: int = 0, block: int = 0) -> tuple[int, list[dict]]:
     """mixed: 0 FP64, 1 (or True) complex64 products and basis, 2 complex64 products with a
     binary16 basis (orth=1)."""
     o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
-                       float(reg_margin), int(orth), int(bool(graph)))
+                       float(reg_margin), int(orth), int(bool(graph)), int(bool(block)))
     info = (DieTeSolveInfo * nrhs)()
     rc = load().die_te_solve(ctx, _dev(e_in, (torch.complex128,), "e_in"), _dev(e_tot, (torch.complex128,), "e_tot"),
                              nrhs, ctypes.byref(o), info, _stream())
@@ -84,13 +84,13 @@ def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, res
 
 def die_te_solve_batch(ctxs, e_ins, e_tots, nrhs, *, restart: int = 30, max_iters: int = 100_000, tol: float = 1e-8,
                        mixed: int = 0, x0_given: bool = False, reg_margin: float = 0.0,
-                       orth: int = 0, graph: int = 0) -> tuple[int, list[list[dict]]]:
+                       orth: int = 0, graph: int = 0, block: int = 0) -> tuple[int, list[list[dict]]]:
     """Several contexts (grid sizes) in one call; returns (code, per-context info lists)."""
     n = len(ctxs)
     if not (len(e_ins) == len(e_tots) == len(nrhs) == n):
         raise ValueError("ctxs, e_ins, e_tots and nrhs must have the same length")
     o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
-                       float(reg_margin), int(orth), int(bool(graph)))
+                       float(reg_margin), int(orth), int(bool(graph)), int(bool(block)))
     vp = ctypes.c_void_p
     c_arr = (vp * n)(*[vp(c.value if isinstance(c, vp) else c) for c in ctxs])
     i_arr = (vp * n)(*[_dev(t, (torch.complex128,), "e_in") for t in e_ins])

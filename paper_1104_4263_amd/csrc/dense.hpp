@@ -196,6 +196,101 @@ inline Mat tri_eigvecs(const Mat& T) {
   return Y;
 }
 
+// Cholesky G = L L^H of a Hermitian matrix (lower triangle of G read); false when a pivot is
+// not above rel_tol times the largest diagonal entry (numerically rank deficient).
+inline bool cholesky(const Mat& G, Mat& L, double rel_tol) {
+  const int k = G.n;
+  L = Mat(k, k);
+  double dmax = 0.0;
+  for (int i = 0; i < k; ++i) dmax = std::max(dmax, G(i, i).real());
+  if (!(dmax > 0.0)) return false;
+  for (int j = 0; j < k; ++j) {
+    double d = G(j, j).real();
+    for (int q = 0; q < j; ++q) d -= std::norm(L(j, q));
+    if (!(d > rel_tol * dmax)) return false;
+    const double ljj = std::sqrt(d);
+    L(j, j) = ljj;
+    for (int i = j + 1; i < k; ++i) {
+      cd s = G(i, j);
+      for (int q = 0; q < j; ++q) s -= L(i, q) * std::conj(L(j, q));
+      L(i, j) = s / ljj;
+    }
+  }
+  return true;
+}
+
+// Pivoted Cholesky of a Hermitian positive semidefinite G: with rows of L in pivot order,
+// G(perm[i], perm[j]) = sum_q L(i, q) conj(L(j, q)) for the leading p pivots, L (k x k, lower
+// trapezoidal in its first p columns).  Stops when the largest remaining diagonal entry is
+// not above tau2; returns the rank p.
+inline int pivoted_cholesky(const Mat& G, double tau2, Mat& L, std::vector<int>& perm) {
+  const int k = G.n;
+  L = Mat(k, k);
+  perm.resize(k);
+  for (int i = 0; i < k; ++i) perm[i] = i;
+  std::vector<double> d(k);
+  for (int i = 0; i < k; ++i) d[i] = G(i, i).real();
+  int p = 0;
+  for (; p < k; ++p) {
+    int q = p;
+    for (int i = p + 1; i < k; ++i)
+      if (d[perm[i]] > d[perm[q]]) q = i;
+    if (!(d[perm[q]] > tau2)) break;
+    if (q != p) {
+      std::swap(perm[p], perm[q]);
+      for (int c = 0; c < p; ++c) std::swap(L(p, c), L(q, c));
+    }
+    const int jp = perm[p];
+    const double ljj = std::sqrt(d[jp]);
+    L(p, p) = ljj;
+    for (int i = p + 1; i < k; ++i) {
+      const int ji = perm[i];
+      cd s = G(ji, jp);
+      for (int c = 0; c < p; ++c) s -= L(i, c) * std::conj(L(p, c));
+      L(i, p) = s / ljj;
+      d[ji] -= std::norm(L(i, p));
+    }
+  }
+  return p;
+}
+
+// Inverse of the upper triangular R (non-zero diagonal).
+inline Mat upper_inverse(const Mat& R) {
+  const int k = R.n;
+  Mat X(k, k);
+  for (int j = 0; j < k; ++j) {
+    X(j, j) = 1.0 / R(j, j);
+    for (int i = j - 1; i >= 0; --i) {
+      cd s = 0.0;
+      for (int q = i + 1; q <= j; ++q) s += R(i, q) * X(q, j);
+      X(i, j) = -s / R(i, i);
+    }
+  }
+  return X;
+}
+
+// G = R^H R with R upper triangular, from the Cholesky factor of the unit-diagonal scaling
+// D G D (D = diag(G)^-1/2), so that the rank test rel_tol is relative to each column's own
+// norm; false when a column vanishes or the scaled matrix is numerically rank deficient.
+inline bool chol_upper_scaled(const Mat& G, double rel_tol, Mat& R) {
+  const int k = G.n;
+  std::vector<double> dinv(k);
+  for (int i = 0; i < k; ++i) {
+    const double d = G(i, i).real();
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    dinv[i] = 1.0 / std::sqrt(d);
+  }
+  Mat S(k, k);
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) S(i, j) = G(i, j) * dinv[i] * dinv[j];
+  Mat L;
+  if (!cholesky(S, L, rel_tol)) return false;
+  R = Mat(k, k);  // R = L^H D^-1
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= j; ++i) R(i, j) = std::conj(L(j, i)) / dinv[j];
+  return true;
+}
+
 // Inverse by LU with partial pivoting; false if singular.
 inline bool inverse(const Mat& A, Mat& Ainv) {
   const int n = A.n;

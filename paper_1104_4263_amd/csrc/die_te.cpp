@@ -21,6 +21,9 @@
 #include <thread>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "dense.hpp"
 #include "green.hpp"
 #include "host.hpp"
@@ -81,8 +84,10 @@ struct die_te_ctx {
   int prof_nlive = -1;  // right-hand sides live in the current launches (-1: all of them)
   // FFT pass variants of the products: forced (>= 0) or tuned per [FP64, FP32][batch class][pass]
   int fft_force = -1;
+  rocblas_handle blas = nullptr;  // block GMRES: GEMMs and the block least squares
   int fftv[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}, {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};
   ~die_te_ctx() {
+    if (blas) (void)rocblas_destroy_handle(blas);
     for (auto& v : prof_ev)
       for (auto& pr : v) {
         (void)hipEventDestroy(pr.first);
@@ -298,12 +303,17 @@ int apply_M(die_te_ctx* c, bool reg, const c2<T>* in, c2<T>* tmp, c2<T>* out, in
 // (rpo right-hand sides per object: each uses its object's V and C)
 template <class T>
 int apply_pinv(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, double2* part, double2* coef, int* counter,
-               const int* live, hipStream_t st, int rpo) {
+               const int* live, hipStream_t st, int rpo, int obj0 = 0) {
+  // right-hand side r uses object obj0 + r / rpo, which must exist
+  if (rpo < 1 || obj0 < 0 || obj0 + (nrhs - 1) / rpo >= c->nobj)
+    return fail(DIE_E_INVALID, "deflation: right-hand sides map past the last object");
   const size_t n = c->nvec;
   const size_t vstride = (size_t)c->r * n, cstride = (size_t)c->r * c->r;
-  DIE_HIP((die::launch_fdot<double, T>(c->V.as<double2>(), n, vstride, rpo, c->r, x, n, n, nrhs, part, 1.0,
-                                       c->Cdev.as<double2>(), cstride, coef, counter, live, st)));
-  DIE_HIP((die::launch_faxpy<double, T>(c->V.as<double2>(), n, vstride, rpo, c->r, coef, x, y, n, n, nrhs, live, st)));
+  const double2* V = c->V.as<double2>() + (size_t)obj0 * vstride;
+  const double2* C = c->Cdev.as<double2>() + (size_t)obj0 * cstride;
+  DIE_HIP((die::launch_fdot<double, T>(V, n, vstride, rpo, c->r, x, n, n, nrhs, part, 1.0, C, cstride, coef, counter,
+                                       live, st)));
+  DIE_HIP((die::launch_faxpy<double, T>(V, n, vstride, rpo, c->r, coef, x, y, n, n, nrhs, live, st)));
   return DIE_OK;
 }
 
@@ -861,6 +871,428 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   return rc;
 }
 
+// ------------------------------------------------------------------ block GMRES
+#define DIE_BLAS(expr)                                                                              \
+  do {                                                                                              \
+    rocblas_status _s = (expr);                                                                     \
+    if (_s != rocblas_status_success)                                                               \
+      return die_host::fail(DIE_E_HIP, std::string(#expr) + ": " + rocblas_status_to_string(_s));  \
+  } while (0)
+
+int blas_on(die_te_ctx* c, hipStream_t st, rocblas_handle* h) {
+  if (!c->blas) {
+    rocblas_handle nh = nullptr;
+    DIE_BLAS(rocblas_create_handle(&nh));
+    c->blas = nh;
+    DIE_BLAS(rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed));  // fixed-order sums
+  }
+  DIE_BLAS(rocblas_set_stream(c->blas, st));
+  *h = c->blas;
+  return DIE_OK;
+}
+
+// C = alpha op(A) op(B) + beta C, column-major complex in the precision of T (matrix cores).
+template <class T>
+rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, cd alpha,
+                    const c2<T>* A, int lda, const c2<T>* B, int ldb, cd beta, c2<T>* C, int ldc);
+template <>
+rocblas_status gemm<double>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+                            cd alpha, const double2* A, int lda, const double2* B, int ldb, cd beta, double2* C,
+                            int ldc) {
+  const rocblas_double_complex a(alpha.real(), alpha.imag()), b(beta.real(), beta.imag());
+  return rocblas_zgemm(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                       reinterpret_cast<const rocblas_double_complex*>(B), ldb, &b,
+                       reinterpret_cast<rocblas_double_complex*>(C), ldc);
+}
+template <>
+rocblas_status gemm<float>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+                           cd alpha, const float2* A, int lda, const float2* B, int ldb, cd beta, float2* C,
+                           int ldc) {
+  const rocblas_float_complex a((float)alpha.real(), (float)alpha.imag()), b((float)beta.real(), (float)beta.imag());
+  return rocblas_cgemm(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_float_complex*>(A), lda,
+                       reinterpret_cast<const rocblas_float_complex*>(B), ldb, &b,
+                       reinterpret_cast<rocblas_float_complex*>(C), ldc);
+}
+
+constexpr rocblas_operation kN = rocblas_operation_none, kH = rocblas_operation_conjugate_transpose;
+
+template <class T>
+rocblas_status gemm_batched(rocblas_handle h, int m, int n, int k, const c2<T>* A, int lda, rocblas_stride sa,
+                            const c2<T>* B, int ldb, rocblas_stride sb, c2<T>* C, int ldc, rocblas_stride sc, int batch);
+template <>
+rocblas_status gemm_batched<double>(rocblas_handle h, int m, int n, int k, const double2* A, int lda, rocblas_stride sa,
+                                    const double2* B, int ldb, rocblas_stride sb, double2* C, int ldc,
+                                    rocblas_stride sc, int batch) {
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  return rocblas_zgemm_strided_batched(h, kH, kN, m, n, k, &one, reinterpret_cast<const rocblas_double_complex*>(A),
+                                       lda, sa, reinterpret_cast<const rocblas_double_complex*>(B), ldb, sb, &zero,
+                                       reinterpret_cast<rocblas_double_complex*>(C), ldc, sc, batch);
+}
+template <>
+rocblas_status gemm_batched<float>(rocblas_handle h, int m, int n, int k, const float2* A, int lda, rocblas_stride sa,
+                                   const float2* B, int ldb, rocblas_stride sb, float2* C, int ldc, rocblas_stride sc,
+                                   int batch) {
+  const rocblas_float_complex one(1.0f, 0.0f), zero(0.0f, 0.0f);
+  return rocblas_cgemm_strided_batched(h, kH, kN, m, n, k, &one, reinterpret_cast<const rocblas_float_complex*>(A),
+                                       lda, sa, reinterpret_cast<const rocblas_float_complex*>(B), ldb, sb, &zero,
+                                       reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, batch);
+}
+template <class T>
+rocblas_status gemv(rocblas_handle h, int m, int n, const c2<T>* A, int lda, const c2<T>* x, c2<T>* y);
+template <>
+rocblas_status gemv<double>(rocblas_handle h, int m, int n, const double2* A, int lda, const double2* x, double2* y) {
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  return rocblas_zgemv(h, kN, m, n, &one, reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                       reinterpret_cast<const rocblas_double_complex*>(x), 1, &zero,
+                       reinterpret_cast<rocblas_double_complex*>(y), 1);
+}
+template <>
+rocblas_status gemv<float>(rocblas_handle h, int m, int n, const float2* A, int lda, const float2* x, float2* y) {
+  const rocblas_float_complex one(1.0f, 0.0f), zero(0.0f, 0.0f);
+  return rocblas_cgemv(h, kN, m, n, &one, reinterpret_cast<const rocblas_float_complex*>(A), lda,
+                       reinterpret_cast<const rocblas_float_complex*>(x), 1, &zero,
+                       reinterpret_cast<rocblas_float_complex*>(y), 1);
+}
+
+// Scratch of the long inner-dimension products: chunk partials and a vector of ones.
+struct LongGemm {
+  DBuf part, ones;
+  size_t cap = 0;  // complex values of the partial buffer
+  int nones = 0;
+};
+constexpr size_t kLongGemmPartial = (size_t)1 << 25;  // complex values
+
+// C (m x n, leading dimension m) = A^H B for A (K x m), B (K x n), K long (a vector length):
+// the K range is cut into equal chunks that a strided-batched GEMM multiplies in parallel
+// (a plain GEMM over K leaves the chip idle when m n is small), and one GEMV sums the chunk
+// products in a fixed order.
+template <class T>
+int gemm_hn_long(rocblas_handle h, LongGemm& lg, int m, int n, int K, const c2<T>* A, int lda, const c2<T>* B,
+                 int ldb, c2<T>* C, hipStream_t st) {
+  int nch = 1;
+  for (int c = 256; c >= 2; c /= 2)
+    if (K % c == 0 && K / c >= 256 && (size_t)m * n * c <= kLongGemmPartial) {
+      nch = c;
+      break;
+    }
+  if (nch == 1) {
+    DIE_BLAS(gemm<T>(h, kH, kN, m, n, K, 1.0, A, lda, B, ldb, 0.0, C, m));
+    return DIE_OK;
+  }
+  if (lg.cap < (size_t)m * n * nch) {
+    DIE_TRY(lg.part.alloc(kLongGemmPartial * sizeof(c2<T>)));
+    lg.cap = kLongGemmPartial;
+  }
+  if (lg.nones < nch) {
+    std::vector<c2<T>> o(256, die::mk<T>((T)1, (T)0));
+    DIE_TRY(lg.ones.alloc(256 * sizeof(c2<T>)));
+    DIE_HIP(hipMemcpyAsync(lg.ones.p, o.data(), 256 * sizeof(c2<T>), hipMemcpyHostToDevice, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    lg.nones = 256;
+  }
+  const int ck = K / nch;
+  c2<T>* part = lg.part.as<c2<T>>();
+  DIE_BLAS(gemm_batched<T>(h, m, n, ck, A, lda, ck, B, ldb, ck, part, m, (rocblas_stride)m * n, nch));
+  DIE_BLAS(gemv<T>(h, m * n, nch, part, m * n, lg.ones.as<c2<T>>(), C));
+  return DIE_OK;
+}
+
+// Host <-> device transfers of a small column-major matrix (rows x cols, leading dimension
+// = rows on the device) in the precision of T.
+template <class T> int download(const void* d, int rows, int cols, die::la::Mat& M, hipStream_t st) {
+  std::vector<c2<T>> h((size_t)rows * cols);
+  DIE_HIP(hipMemcpyAsync(h.data(), d, h.size() * sizeof(c2<T>), hipMemcpyDeviceToHost, st));
+  DIE_HIP(hipStreamSynchronize(st));
+  M = die::la::Mat(rows, cols);
+  for (size_t e = 0; e < h.size(); ++e) M.a[e] = cd((double)h[e].x, (double)h[e].y);
+  return DIE_OK;
+}
+template <class T> int upload(const die::la::Mat& M, void* d, hipStream_t st, std::vector<c2<T>>& stage) {
+  stage.resize(M.a.size());
+  for (size_t e = 0; e < M.a.size(); ++e) stage[e] = die::mk<T>((T)M.a[e].real(), (T)M.a[e].imag());
+  DIE_HIP(hipMemcpyAsync(d, stage.data(), stage.size() * sizeof(c2<T>), hipMemcpyHostToDevice, st));
+  DIE_HIP(hipStreamSynchronize(st));  // the staging vector is reused by the next upload
+  return DIE_OK;
+}
+
+// Restarted block GMRES(m) (Section 4's GMRES applied to all right-hand sides of an object
+// at once): per object, the active residuals (normalised) span the first block through a
+// rank-revealing (pivoted) Cholesky QR; block Arnoldi with CGS2 as GEMMs and CholQR2 for each
+// new block; the block least squares once per cycle (rocSOLVER); every cycle restarts from
+// the FP64 true residual, as in the per-rhs solver.  Objects are processed one after another.
+template <class T>
+int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
+                      die_te_solve_info* info, hipStream_t st) {
+  using die::la::Mat;
+  namespace la = die::la;
+  const size_t n = c->nvec;
+  const int m = o.restart;
+  const int nblk = die::blas_blocks(n);
+  const bool reg = c->regularize != 0;
+  const bool defl = c->r > 0;
+  const int rpo = nrhs / c->nobj;  // right-hand sides per object: the largest block
+  const double tol = o.tol > 0 ? o.tol : 1e-8;
+  const double chol_tol = std::is_same<T, float>::value ? 1e-6 : 1e-12;  // rank test of a new block
+  const double rank_tau2 = 1e-12;  // initial block: drop residual directions below 1e-6 (unit columns)
+  if ((size_t)n > (size_t)INT32_MAX || (size_t)(m + 1) * rpo > 65535)
+    return fail(DIE_E_INVALID, "block GMRES: vectors or blocks too large for the GEMM interface");
+  rocblas_handle bh;
+  DIE_TRY(blas_on(c, st, &bh));
+  const int ni = (int)n, ldh = (m + 1) * rpo;
+  const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
+  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, Hls, Bls, ones, idxd, infod, part, coef, cnt, scl;
+  DIE_TRY(Rs.alloc(dbytes));
+  if (reg) DIE_TRY(Sd.alloc(dbytes));
+  DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
+  DIE_TRY(nrm.alloc(nrhs * sizeof(double)));
+  DIE_TRY(active.alloc(nrhs * sizeof(int)));
+  DIE_TRY(Vb.alloc((size_t)(m + 1) * rpo * n * sizeof(c2<T>)));
+  DIE_TRY(Wt.alloc((size_t)rpo * n * sizeof(c2<T>)));
+  if (defl) DIE_TRY(Zb.alloc((size_t)rpo * n * sizeof(c2<T>)));
+  if (reg) DIE_TRY(Tm.alloc((size_t)rpo * n * sizeof(c2<T>)));
+  DIE_TRY(Ra.alloc((size_t)2 * rpo * n * sizeof(double2)));  // residual block, then its orthonormal basis
+  DIE_TRY(Tb.alloc((size_t)rpo * n * sizeof(c2<T>)));
+  DIE_TRY(sm.alloc((size_t)ldh * rpo * sizeof(double2)));
+  DIE_TRY(Hls.alloc((size_t)ldh * m * rpo * sizeof(double2)));
+  DIE_TRY(Bls.alloc((size_t)ldh * rpo * sizeof(double2)));
+  DIE_TRY(ones.alloc(sizeof(double)));
+  DIE_TRY(idxd.alloc(rpo * sizeof(int)));
+  DIE_TRY(infod.alloc(sizeof(int)));
+  DIE_TRY(scl.alloc(rpo * sizeof(double)));
+  if (defl) {
+    DIE_TRY(part.alloc((size_t)rpo * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
+                       sizeof(double2)));
+    DIE_TRY(coef.alloc((size_t)rpo * c->r * sizeof(double2)));
+    DIE_TRY(cnt.alloc((size_t)rpo * die::kCounterStride * sizeof(int)));
+    DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)rpo * die::kCounterStride * sizeof(int), st));
+  }
+  const double one = 1.0;
+  DIE_HIP(hipMemcpyAsync(ones.p, &one, sizeof(double), hipMemcpyHostToDevice, st));
+  {  // pick the FFT pass variants before any timing-sensitive work
+    const int* pv = nullptr;
+    DIE_TRY(fft_plan<T>(c, rpo, st, &pv));
+    DIE_TRY(fft_plan<double>(c, nrhs, st, &pv));
+  }
+  DIE_TRY(ensure_work(c, (size_t)std::max((size_t)nrhs * sizeof(double2), (size_t)rpo * sizeof(c2<T>)) * 2 * c->px *
+                             c->ny, st));
+  c2<T>* vb = Vb.as<c2<T>>();
+  LongGemm lg64, lgT;  // scratch of the long inner-dimension products (FP64 first block, basis precision)
+  std::vector<c2<T>> stage;
+  std::vector<double> bnorm(nrhs), rnorm(nrhs), snorm(nrhs), hn(nrhs), relres(nrhs, 1.0);
+  std::vector<int> act(nrhs, 1), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0),
+      brk(nrhs, 0);
+  if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
+  DIE_HIP((die::launch_norm2<double>(b, n, n, nrhs, partn.as<double>(), nullptr, st)));
+  DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), nullptr, st));
+  DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  DIE_HIP(hipStreamSynchronize(st));
+  for (int r = 0; r < nrhs; ++r) {
+    bnorm[r] = std::sqrt(hn[r]);
+    if (!std::isfinite(bnorm[r])) return fail(DIE_E_INVALID, "e_in contains non-finite values");
+  }
+  for (;;) {
+    // ---- FP64 true residual res = b - A u
+    DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    const int* dact = active.as<int>();
+    double2* res = Rs.as<double2>();
+    DIE_TRY(apply_op<double>(c, u, res, nrhs, false, dact, st, rpo));
+    DIE_HIP((die::launch_maxpy<double, double, double>(2, (const double2*)nullptr, 0, 0, 0, nullptr, nullptr, 0, b, n,
+                                                       1.0, res, n, -1.0, n, nrhs, nullptr, partn.as<double>(), dact,
+                                                       st)));
+    DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), dact, st));
+    DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    int nact = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!act[r]) continue;
+      pa[r] += 1;
+      rnorm[r] = std::sqrt(hn[r]);
+      relres[r] = bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0;
+      if (!std::isfinite(rnorm[r])) {
+        brk[r] = 1;
+        act[r] = 0;
+      } else if (relres[r] <= tol || bnorm[r] == 0.0) {
+        conv[r] = 1;
+        act[r] = 0;
+      } else if (iters[r] >= o.max_iters) {
+        act[r] = 0;
+      } else {
+        ++nact;
+      }
+    }
+    if (nact == 0) break;
+    DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    const double2* s = res;
+    if (reg) {
+      DIE_TRY(apply_op<double>(c, res, Sd.as<double2>(), nrhs, true, dact, st, rpo));
+      s = Sd.as<double2>();
+      for (int r = 0; r < nrhs; ++r) par[r] += act[r];
+    }
+    DIE_HIP((die::launch_norm2<double>(s, n, n, nrhs, partn.as<double>(), dact, st)));
+    DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), dact, st));
+    DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) snorm[r] = std::sqrt(hn[r]);
+    bool progress = false;  // some object took a block step this cycle
+    for (int ob = 0; ob < c->nobj; ++ob) {
+      std::vector<int> K;
+      for (int r = ob * rpo; r < (ob + 1) * rpo; ++r)
+        if (act[r] && snorm[r] > 0 && std::isfinite(snorm[r])) K.push_back(r);
+      const int k = (int)K.size();
+      if (k == 0) continue;
+      // ---- first block: normalised residuals, rank-revealing Cholesky QR (two passes, FP64)
+      double2* ra = Ra.as<double2>();
+      double2* v0 = ra + (size_t)rpo * n;
+      std::vector<double> inv(k);
+      for (int q = 0; q < k; ++q) {
+        DIE_HIP(hipMemcpyAsync(ra + (size_t)q * n, s + (size_t)K[q] * n, n * sizeof(double2), hipMemcpyDeviceToDevice,
+                               st));
+        inv[q] = 1.0 / snorm[K[q]];
+      }
+      DIE_HIP(hipMemcpyAsync(scl.p, inv.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+      DIE_HIP((die::launch_scale<double, double>(ra, n, ra, n, scl.as<double>(), 1, n, k, nullptr, st)));
+      DIE_TRY(gemm_hn_long<double>(bh, lg64, k, k, ni, ra, ni, ra, ni, sm.as<double2>(), st));
+      Mat G, L;
+      DIE_TRY(download<double>(sm.p, k, k, G, st));
+      std::vector<int> perm;
+      const int p = la::pivoted_cholesky(G, rank_tau2, L, perm);
+      if (p == 0) continue;
+      Mat R1(p, p);
+      for (int j = 0; j < p; ++j)
+        for (int i = 0; i <= j; ++i) R1(i, j) = std::conj(L(j, i));
+      const Mat R1i = la::upper_inverse(R1);
+      Mat Msel(k, p), S0(p, k);
+      for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) Msel(perm[i], j) = R1i(i, j);
+      for (int i = 0; i < k; ++i)
+        for (int q = 0; q < p; ++q) S0(q, perm[i]) = std::conj(L(i, q));
+      std::vector<double2> stage64;
+      DIE_TRY(upload<double>(Msel, sm.p, st, stage64));
+      DIE_BLAS(gemm<double>(bh, kN, kN, ni, p, k, 1.0, ra, ni, sm.as<double2>(), k, 0.0, v0, ni));
+      DIE_TRY(gemm_hn_long<double>(bh, lg64, p, p, ni, v0, ni, v0, ni, sm.as<double2>(), st));
+      Mat G2, R2;
+      DIE_TRY(download<double>(sm.p, p, p, G2, st));
+      if (!la::chol_upper_scaled(G2, 1e-14, R2)) continue;  // not expected after the pivoted selection
+      DIE_TRY(upload<double>(la::upper_inverse(R2), sm.p, st, stage64));
+      DIE_BLAS(gemm<double>(bh, kN, kN, ni, p, p, 1.0, v0, ni, sm.as<double2>(), p, 0.0, ra, ni));
+      {
+        Mat S(p, k);
+        for (int j = 0; j < k; ++j)
+          for (int i = 0; i < p; ++i) {
+            cd a = 0.0;
+            for (int q = i; q < p; ++q) a += R2(i, q) * S0(q, j);
+            S(i, j) = a;
+          }
+        S0 = S;
+      }
+      DIE_HIP((die::launch_scale<double, T>(ra, n, vb, n, ones.as<double>(), 0, n, p, nullptr, st)));
+      // ---- block Arnoldi: H ((m+1) p x m p), CGS2 as GEMMs, CholQR2 of every new block
+      Mat H((m + 1) * p, m * p);
+      int meff = m;
+      bool early = false;
+      for (int j = 0; j < m; ++j) {
+        c2<T>* Vj = vb + (size_t)j * p * n;
+        c2<T>* W = vb + (size_t)(j + 1) * p * n;
+        const c2<T>* z = Vj;
+        if (defl) {
+          // rpo = p: every field of the block uses object ob's V and C
+          DIE_TRY(apply_pinv<T>(c, Vj, Zb.as<c2<T>>(), p, part.as<double2>(), coef.as<double2>(), cnt.as<int>(), nullptr,
+                                st, p, ob));
+          z = Zb.as<c2<T>>();
+        }
+        DIE_TRY(apply_M<T>(c, reg, z, reg ? Tm.as<c2<T>>() : nullptr, W, p, nullptr, st, 0, ob));
+        const int nq = (j + 1) * p;
+        for (int rep = 0; rep < 2; ++rep) {
+          DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, sm.as<c2<T>>(), st));
+          DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, nq, -1.0, vb, ni, sm.as<c2<T>>(), nq, 1.0, W, ni));
+          Mat Hc;
+          DIE_TRY(download<T>(sm.p, nq, p, Hc, st));
+          for (int jj = 0; jj < p; ++jj)
+            for (int i = 0; i < nq; ++i) H(i, j * p + jj) += Hc(i, jj);
+        }
+        Mat Gw, Q1, Q2;
+        DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, W, ni, W, ni, sm.as<c2<T>>(), st));
+        DIE_TRY(download<T>(sm.p, p, p, Gw, st));
+        bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1);
+        if (ok) {
+          DIE_TRY(upload<T>(la::upper_inverse(Q1), sm.p, st, stage));
+          DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, p, 1.0, W, ni, sm.as<c2<T>>(), p, 0.0, Wt.as<c2<T>>(), ni));
+          DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, Wt.as<c2<T>>(), ni, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), st));
+          DIE_TRY(download<T>(sm.p, p, p, Gw, st));
+          ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
+        }
+        if (!ok) {  // the new block is numerically dependent: end the cycle here
+          meff = j + 1;
+          early = true;
+          break;
+        }
+        DIE_TRY(upload<T>(la::upper_inverse(Q2), sm.p, st, stage));
+        DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
+        for (int jj = 0; jj < p; ++jj)  // H(j+1, j) = Q2 Q1
+          for (int i = 0; i <= jj; ++i) {
+            cd a = 0.0;
+            for (int q = i; q <= jj; ++q) a += Q2(i, q) * Q1(q, jj);
+            H((j + 1) * p + i, j * p + jj) = a;
+          }
+      }
+      // ---- block least squares min || E1 S0 - H Y || on the GPU, then u += P^-1 V Y
+      const int mr = early ? meff * p : (meff + 1) * p, nc = meff * p;
+      {
+        Mat Hm(mr, nc), Bm(mr, k);
+        for (int j = 0; j < nc; ++j)
+          for (int i = 0; i < mr; ++i) Hm(i, j) = H(i, j);
+        for (int j = 0; j < k; ++j)
+          for (int i = 0; i < p; ++i) Bm(i, j) = S0(i, j);
+        DIE_TRY(upload<double>(Hm, Hls.p, st, stage64));
+        DIE_TRY(upload<double>(Bm, Bls.p, st, stage64));
+        DIE_BLAS(rocsolver_zgels(bh, kN, mr, nc, k, reinterpret_cast<rocblas_double_complex*>(Hls.p), mr,
+                                 reinterpret_cast<rocblas_double_complex*>(Bls.p), mr, infod.as<int>()));
+        int linfo = 0;
+        DIE_HIP(hipMemcpyAsync(&linfo, infod.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        Mat Y;
+        DIE_TRY(download<double>(Bls.p, mr, k, Y, st));
+        if (linfo != 0) return fail(DIE_E_BREAKDOWN, "block GMRES: rank-deficient block Hessenberg");
+        Mat Ys(nc, k);  // columns scaled back by the residual norms
+        for (int j = 0; j < k; ++j)
+          for (int i = 0; i < nc; ++i) Ys(i, j) = Y(i, j) * snorm[K[j]];
+        DIE_TRY(upload<T>(Ys, sm.p, st, stage));
+      }
+      c2<T>* tb = Tb.as<c2<T>>();
+      DIE_BLAS(gemm<T>(bh, kN, kN, ni, k, nc, 1.0, vb, ni, sm.as<c2<T>>(), nc, 0.0, tb, ni));
+      if (defl)
+        DIE_TRY(apply_pinv<T>(c, tb, tb, k, part.as<double2>(), coef.as<double2>(), cnt.as<int>(), nullptr, st, k, ob));
+      DIE_HIP(hipMemcpyAsync(idxd.p, K.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+      DIE_HIP(die::launch_add_cols<T>(tb, n, idxd.as<int>(), k, u, st));
+      DIE_HIP(hipStreamSynchronize(st));  // K and the staging vectors are reused by the next object
+      const int prods = (meff * p + k - 1) / k;
+      progress = true;
+      for (int q = 0; q < k; ++q) {
+        const int r = K[q];
+        iters[r] += meff;
+        cycles[r] += 1;
+        pa[r] += prods;
+        if (reg) par[r] += prods;
+      }
+    }
+    if (!progress) return fail(DIE_E_BREAKDOWN, "block GMRES: no residual block could be orthonormalised");
+  }
+  int rc = DIE_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    if (brk[r]) rc = std::min(rc, (int)DIE_E_BREAKDOWN);
+    else if (!conv[r] && rc == DIE_OK) rc = DIE_NOT_CONVERGED;
+    if (info) {
+      info[r].status = brk[r] ? DIE_E_BREAKDOWN : (conv[r] ? DIE_OK : DIE_NOT_CONVERGED);
+      info[r].iters = iters[r];
+      info[r].products_A = pa[r];
+      info[r].products_AR = par[r];
+      info[r].cycles = cycles[r];
+      info[r].rel_res_true = relres[r];
+    }
+  }
+  if (rc == DIE_E_BREAKDOWN) return fail(DIE_E_BREAKDOWN, "block GMRES met a non-finite value");
+  return rc;
+}
+
 int check_ctx(const die_te_ctx* c) {
   if (!c) return fail(DIE_E_INVALID, "null context");
   return DIE_OK;
@@ -1028,6 +1460,12 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   hipStream_t st = (hipStream_t)stream;
   if (o.mixed < 0 || o.mixed > 2) return fail(DIE_E_INVALID, "mixed must be 0, 1 or 2");
   if (o.mixed == 2 && o.orth != 1) return fail(DIE_E_INVALID, "mixed = 2 (binary16 basis) needs orth = 1");
+  if (o.block != 0 && o.block != 1) return fail(DIE_E_INVALID, "block must be 0 or 1");
+  if (o.block) {
+    if (o.mixed == 2) return fail(DIE_E_INVALID, "block GMRES needs mixed = 0 or 1");
+    if (o.mixed) return block_gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+    return block_gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+  }
   if (o.mixed == 2)
     return gmres_solve<float, _Float16>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
   if (o.mixed) return gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);

@@ -477,6 +477,33 @@ DIE_INST_SCALE(float, float)
 DIE_INST_SCALE(double, float)
 DIE_INST_SCALE(float, double)
 
+// u[idx[c]] += src[c] for c < k (vectors of n complex values; the sum in FP64).
+template <class S>
+__global__ void __launch_bounds__(NT)
+k_add_cols(const c2<S>* __restrict__ src, size_t n, const int* __restrict__ idx, double2* __restrict__ u) {
+  const int c = blockIdx.y;
+  const c2<S>* sc = src + (size_t)c * n;
+  double2* uc = u + (size_t)idx[c] * n;
+  for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < n; e += (size_t)gridDim.x * NT) {
+    const c2<S> a = sc[e];
+    double2 v = uc[e];
+    v.x += (double)a.x;
+    v.y += (double)a.y;
+    uc[e] = v;
+  }
+}
+
+template <class S>
+hipError_t launch_add_cols(const c2<S>* src, size_t n, const int* idx, int k, double2* u, hipStream_t st) {
+  if (k <= 0 || n == 0) return hipSuccess;
+  if (k > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)std::min<size_t>((n + NT - 1) / NT, 1024), (unsigned)k);
+  hipLaunchKernelGGL(k_add_cols<S>, grid, dim3(NT), 0, st, src, n, idx, u);
+  return hipGetLastError();
+}
+template hipError_t launch_add_cols<double>(const double2*, size_t, const int*, int, double2*, hipStream_t);
+template hipError_t launch_add_cols<float>(const float2*, size_t, const int*, int, double2*, hipStream_t);
+
 }  // namespace die
 
 // =====================================================================================

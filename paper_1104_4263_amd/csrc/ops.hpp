@@ -92,6 +92,10 @@ template <class SX, class SY>
 hipError_t launch_scale(const c2<SX>* X, size_t x_rs, c2<SY>* Y, size_t y_rs, const double* scale,
                         int sstride, size_t n, int nrhs, const int* live, hipStream_t st);
 
+// u[idx[c]] += src[c] for c < k <= 65535: src [k][n] in S, u [*][n] complex128 (block GMRES update).
+template <class S>
+hipError_t launch_add_cols(const c2<S>* src, size_t n, const int* idx, int k, double2* u, hipStream_t st);
+
 // ----------------------------------------------------------------- GMRES state
 struct GmresState {
   int j;         // iterations done in the current cycle

@@ -58,7 +58,7 @@ def test_unet_create_validates_before_any_gpu_call():
 def test_solve_batch_validates_before_any_gpu_call():
     lib = _lib.load()
     vp = ctypes.c_void_p
-    o = _lib.DieTeSolveOpts(30, 100, 1e-8, 0, 0, 0.0, 0, 0)
+    o = _lib.DieTeSolveOpts(30, 100, 1e-8, 0, 0, 0.0, 0, 0, 0)
     one = (ctypes.c_int * 2)(1, 1)
     dummy = (vp * 2)(vp(16), vp(32))  # never dereferenced: the argument checks come first
     assert lib.die_te_solve_batch(None, 2, dummy, dummy, one, ctypes.byref(o), None, None) == _lib.DIE_E_INVALID
