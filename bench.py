@@ -38,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {32: 157.3, 64: 78.6}  # dense matrix-core peaks, fp32 and fp64
 N_ANGLES = 64
 OBJ_SEEDS = (1004, 1005, 1006, 1007)
 RESTART = 30
@@ -235,6 +236,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--solver", default="block", choices=("block", "rhs"),
+                    help="block: block GMRES(30), one block Krylov space per object (default); rhs: per-rhs GMRES(30)")
+    ap.add_argument("--block-precision", type=int, default=32, choices=(32, 64),
+                    help="bits per real part of the block basis, GEMMs and products (32 with FP64 refinement, or 64)")
     ap.add_argument("--orth", type=int, default=1, choices=(0, 1),
                     help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
     ap.add_argument("--basis", type=int, default=16, choices=(16, 32),
@@ -257,7 +262,7 @@ def main():
     import torch
     from synth import workload, plane_wave, centred_grid, cylinder, random_field_object
     from paper_1104_4263_amd import Solver
-    from paper_1104_4263_amd._lib import DIE_PROF_PRODUCT, DIE_PROF_DOTS, DIE_PROF_AXPY
+    from paper_1104_4263_amd._lib import DIE_PROF_PRODUCT, DIE_PROF_DOTS, DIE_PROF_AXPY, DIE_PROF_GEMM
 
     torch.cuda.set_device(0)
     objs = [random_field_object(256, seed=sd) for sd in OBJ_SEEDS]
@@ -275,7 +280,12 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"setup of {nobj} objects on {g.nx}x{g.ny}: {setup_s:.3f} s")
 
-    def batch_solve():
+    block = args.solver == "block"
+
+    def batch_solve(use_block=block):
+        if use_block:
+            return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
+                           mixed=1 if args.block_precision == 32 else 0, block=1)
         return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=2 if args.basis == 16 else 1,
                        orth=args.orth)
 
@@ -304,44 +314,64 @@ def main():
 
     # live kernel timings from the library's event brackets over the timed region
     prof = {}
-    for kind, name in ((DIE_PROF_PRODUCT, "product"), (DIE_PROF_DOTS, "dots"), (DIE_PROF_AXPY, "axpy")):
+    for kind, name in ((DIE_PROF_PRODUCT, "product"), (DIE_PROF_DOTS, "dots"), (DIE_PROF_AXPY, "axpy"),
+                       (DIE_PROF_GEMM, "gemm")):
         cnt, seen, ms, nbytes = s.profile_read(kind)
-        prof[name] = dict(timed=cnt, seen=seen, ms=ms, bytes=nbytes)
+        if seen:
+            prof[name] = dict(timed=cnt, seen=seen, ms=ms, bytes=nbytes)
     est = {k: v["ms"] / max(v["timed"], 1) * v["seen"] for k, v in prof.items()}  # estimated total ms per kind
     dom = max(est, key=est.get)
     p = prof[dom]
     avg_ms = p["ms"] / max(p["timed"], 1)
-    bytes_per_launch = p["bytes"] / max(p["timed"], 1)
-    achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
-    # the kernel file and every header it includes (a traffic summary is only valid for this code)
-    src = source_hash(*(("kernels_fft.hip", "fft.hpp", "ops.hpp", "common.hpp") if dom == "product" else
-                        ("kernels_krylov.hip", "ops.hpp", "common.hpp")))
-    kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "arnoldi_dots_c64_256_batched",
-                  "axpy": "arnoldi_axpy_c64_256_batched"}[dom]
-    traffic = read_traffic(kernel_tag, src, bytes_per_launch)
-    traffic = None if traffic is None else int(traffic)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "avg_launch_us": round(1000.0 * avg_ms, 2),
-                "algorithmic_bytes_per_launch": int(bytes_per_launch), "kernel_source_sha256": src,
-                "per_kind": {k: {"launches": v["seen"], "timed": v["timed"],
-                                 "avg_us": round(1000.0 * v["ms"] / max(v["timed"], 1), 2),
-                                 "GBs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1),
-                                 "est_share_of_step": round(est[k] / (ms_per_step * args.steps), 3)}
-                             for k, v in prof.items()}}
+    work_per_launch = p["bytes"] / max(p["timed"], 1)
+    per_kind = {}
+    for k, v in prof.items():
+        rate = v["bytes"] / max(v["ms"], 1e-9) / 1e6  # GB/s, or GFLOP/s for the GEMM kind
+        per_kind[k] = {"launches": v["seen"], "timed": v["timed"], "avg_us": round(1000.0 * v["ms"] / max(v["timed"], 1), 2),
+                       ("TFLOPs" if k == "gemm" else "GBs"): round(rate / 1000.0, 2) if k == "gemm" else round(rate, 1),
+                       "est_share_of_step": round(est[k] / (ms_per_step * args.steps), 3)}
+    if dom == "gemm":
+        # complex GEMM on the matrix cores: flops against the dense MFMA peak of its precision
+        peak = MFMA_PEAK_TFLOPS[args.block_precision]
+        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": "gemm (block basis update W -= Q H)",
+                    "avg_launch_us": round(1000.0 * avg_ms, 2), "algorithmic_flops_per_launch": int(work_per_launch),
+                    "per_kind": per_kind}
+    else:
+        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+        # the kernel file and every header it includes (a traffic summary is only valid for this code)
+        src = source_hash(*(("kernels_fft.hip", "fft.hpp", "ops.hpp", "common.hpp") if dom == "product" else
+                            ("kernels_krylov.hip", "ops.hpp", "common.hpp")))
+        kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "arnoldi_dots_c64_256_batched",
+                      "axpy": "arnoldi_axpy_c64_256_batched"}[dom]
+        traffic = read_traffic(kernel_tag, src, work_per_launch)
+        traffic = None if traffic is None else int(traffic)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": dom, "avg_launch_us": round(1000.0 * avg_ms, 2),
+                    "algorithmic_bytes_per_launch": int(work_per_launch), "kernel_source_sha256": src,
+                    "per_kind": per_kind}
     log(f"roofline: {roofline}")
 
     out = {
         "metric": "TE solves/s to rel-res 1e-8 (plain vs mixed/batched/learned); matvec % HBM peak",
         "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": f"f32 products, {'f16' if args.basis == 16 else 'f32'} basis storage, f64 dots/Givens/refinement",
+        "dtype": ((f"c{64 if args.block_precision == 32 else 128} products and block GEMMs, f64 block least squares "
+                   "and refinement") if block else
+                  f"f32 products, {'f16' if args.basis == 16 else 'f32'} basis storage, f64 dots/Givens/refinement"),
         "data": "synthetic",
         "config": {"workload": f"random-field objects, 256x256 cells (h = lambda/48), {nobj} objects x "
                                f"{N_ANGLES} TE incidence angles = {nsolve} solves per step",
-                   "method": f"batched GMRES({RESTART}) on A, FP32 products, {args.basis}-bit basis storage, "
-                             f"{'one-reduction' if args.orth else 'two-pass'} CGS2, FP64 true-residual refinement "
-                             f"per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call",
+                   "method": ((f"block GMRES({RESTART}) on A, one block Krylov space per object (its {N_ANGLES} "
+                               f"angles), {'complex64' if args.block_precision == 32 else 'complex128'} products and "
+                               "CGS2/CholQR2 block GEMMs, FP64 block least squares and true-residual restart per "
+                               f"cycle, tol {TOL}, zero initial guess, all {nsolve} in one call") if block else
+                              (f"batched GMRES({RESTART}) on A, FP32 products, {args.basis}-bit basis storage, "
+                               f"{'one-reduction' if args.orth else 'two-pass'} CGS2, FP64 true-residual refinement "
+                               f"per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call")),
+                   "iters_counted_as": "block steps" if block else "GMRES iterations",
                    "iters_mean": round(float(iters.mean()), 1), "iters_max": int(iters.max()),
                    "products_mean": round(float(prods.mean()), 1),
                    "rel_res_true_max": max(x["rel_res_true"] for x in last), "setup_s": round(setup_s, 3),
@@ -349,6 +379,20 @@ def main():
                                     "complex128": s.fft_plan(nsolve, torch.complex128)}},
         "roofline": roofline,
     }
+
+    if block and not args.no_variants:
+        # the per-rhs batched solver on the same 256 solves, for comparison
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc2, inf2 = batch_solve(use_block=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter() - t0
+        ok2 = rc2 == 0 and all(x["rel_res_true"] <= TOL for x in inf2)
+        out["per_rhs_solver"] = {"value": round(nsolve / t2, 3) if ok2 else 0.0, "unit": "solves/s",
+                                 "method": f"per-rhs batched GMRES({RESTART}), one-reduction CGS2, binary16 basis",
+                                 "iters_mean": round(float(np.mean([x["iters"] for x in inf2])), 1),
+                                 "products_mean": round(float(np.mean([x["products_A"] for x in inf2])), 1)}
+        log(f"per-rhs solver: {out['per_rhs_solver']}")
 
     if not args.no_plain:
         # plain: FP64, one right-hand side per call, same method; angles 0, 16, 32, 48 of each object

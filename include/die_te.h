@@ -213,8 +213,9 @@ int die_te_fft2(void *data, int px, int py, int batch, int inverse, int prec, vo
 /* Diagnostic timing.  die_te_profile(ctx, s) with s >= 1 clears the counters and starts
  * bracketing, with hipEvents on the stream each launch is issued on, one in every s
  * launches of each kind: operator products (the three FFT passes of one application of
- * A or A_R: kind DIE_PROF_PRODUCT), Arnoldi dot-product kernels (DIE_PROF_DOTS) and
- * Arnoldi multi-axpy kernels (DIE_PROF_AXPY) issued through the context;
+ * A or A_R: kind DIE_PROF_PRODUCT), Arnoldi dot-product kernels (DIE_PROF_DOTS),
+ * Arnoldi multi-axpy kernels (DIE_PROF_AXPY) and the block solver's basis-update GEMMs
+ * W -= Q H (DIE_PROF_GEMM) issued through the context;
  * die_te_profile(ctx, 0) stops.
  * die_te_profile_read returns the number of bracketed launches of `kind`, the number of
  * launches of that kind issued while profiling was on (`seen`, may be NULL), the total
@@ -223,8 +224,9 @@ int die_te_fft2(void *data, int px, int py, int batch, int inverse, int prec, vo
  * writes of each launch's operands for the right-hand sides live when it was issued
  * (inside a solve: those active at the start of the GMRES cycle).  Products:
  * es (2RN + n_obj N + 8R ny px + 3 px py + 4RN) with es the bytes per complex value;
- * dots over j basis vectors: R (j + 1) 2N es; multi-axpys: R (j + 2) 2N es. */
-enum { DIE_PROF_PRODUCT = 0, DIE_PROF_DOTS = 1, DIE_PROF_AXPY = 2 };
+ * dots over j basis vectors: R (j + 1) 2N es; multi-axpys: R (j + 2) 2N es.  For
+ * DIE_PROF_GEMM the `bytes` output holds flops instead: 8 M N K per complex GEMM. */
+enum { DIE_PROF_PRODUCT = 0, DIE_PROF_DOTS = 1, DIE_PROF_AXPY = 2, DIE_PROF_GEMM = 3 };
 int die_te_profile(die_te_ctx *ctx, int enable);
 int die_te_profile_read(die_te_ctx *ctx, int kind, long long *launches, long long *seen, double *total_ms,
                         double *bytes);

@@ -22,6 +22,7 @@ DIE_C64 = 1
 DIE_PROF_PRODUCT = 0
 DIE_PROF_DOTS = 1
 DIE_PROF_AXPY = 2
+DIE_PROF_GEMM = 3
 
 
 class DieTeGrid(ctypes.Structure):

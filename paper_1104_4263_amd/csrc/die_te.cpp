@@ -76,10 +76,10 @@ struct die_te_ctx {
   int eigs_restarts = 0, eigs_converged = 0;
   // diagnostic timing: event pairs recorded around launches of each kind
   bool prof_on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[3];
-  size_t prof_used[3] = {0, 0, 0};
-  unsigned long long prof_seen[3] = {0, 0, 0};
-  double prof_bytes[3] = {0, 0, 0};  // algorithmic bytes of the bracketed launches
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[4];
+  size_t prof_used[4] = {0, 0, 0, 0};
+  unsigned long long prof_seen[4] = {0, 0, 0, 0};
+  double prof_bytes[4] = {0, 0, 0, 0};  // algorithmic bytes (flops for the GEMM kind) of the bracketed launches
   int prof_every = 1;
   int prof_nlive = -1;  // right-hand sides live in the current launches (-1: all of them)
   // FFT pass variants of the products: forced (>= 0) or tuned per [FP64, FP32][batch class][pass]
@@ -1204,7 +1204,10 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         const int nq = (j + 1) * p;
         for (int rep = 0; rep < 2; ++rep) {
           DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, sm.as<c2<T>>(), st));
-          DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, nq, -1.0, vb, ni, sm.as<c2<T>>(), nq, 1.0, W, ni));
+          {
+            ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq);
+            DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, nq, -1.0, vb, ni, sm.as<c2<T>>(), nq, 1.0, W, ni));
+          }
           Mat Hc;
           DIE_TRY(download<T>(sm.p, nq, p, Hc, st));
           for (int jj = 0; jj < p; ++jj)
@@ -1605,7 +1608,7 @@ int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long*
                         double* bytes) {
   die_host::last_error().clear();
   DIE_TRY(check_ctx(c));
-  if (kind < 0 || kind > 2 || !launches || !total_ms) return fail(DIE_E_INVALID, "bad profile kind or null output");
+  if (kind < 0 || kind > 3 || !launches || !total_ms) return fail(DIE_E_INVALID, "bad profile kind or null output");
   if (seen) *seen = (long long)c->prof_seen[kind];
   if (bytes) *bytes = c->prof_bytes[kind];
   double tot = 0.0;
