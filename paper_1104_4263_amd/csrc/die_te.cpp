@@ -1040,7 +1040,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(blas_on(c, st, &bh));
   const int ni = (int)n, ldh = (m + 1) * rpo;
   const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
-  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, Hls, Bls, ones, idxd, infod, part, coef, cnt, scl;
+  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, Hls, Bls, ones, idxd, infod, part, coef, cnt, scl, Uq, sq;
   DIE_TRY(Rs.alloc(dbytes));
   if (reg) DIE_TRY(Sd.alloc(dbytes));
   DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
@@ -1059,6 +1059,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(idxd.alloc(rpo * sizeof(int)));
   DIE_TRY(infod.alloc(sizeof(int)));
   DIE_TRY(scl.alloc(rpo * sizeof(double)));
+  DIE_TRY(Uq.alloc((size_t)die::kPanelMaxRows * die::kPanelMaxCols * sizeof(double2)));  // panel reflectors
+  DIE_TRY(sq.alloc(die::kPanelMaxCols * sizeof(double)));
   if (defl) {
     DIE_TRY(part.alloc((size_t)rpo * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
                        sizeof(double2)));
@@ -1248,13 +1250,27 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
           for (int i = 0; i < p; ++i) Bm(i, j) = S0(i, j);
         DIE_TRY(upload<double>(Hm, Hls.p, st, stage64));
         DIE_TRY(upload<double>(Bm, Bls.p, st, stage64));
-        DIE_BLAS(rocsolver_zgels(bh, kN, mr, nc, k, reinterpret_cast<rocblas_double_complex*>(Hls.p), mr,
-                                 reinterpret_cast<rocblas_double_complex*>(Bls.p), mr, infod.as<int>()));
         int linfo = 0;
-        DIE_HIP(hipMemcpyAsync(&linfo, infod.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        if (p <= die::kPanelMaxCols) {
+          // Householder QR panel by panel (H has at most p sub-diagonals), then R Y = Q^H B
+          DIE_HIP(die::launch_block_hessenberg_qr(Hls.as<double2>(), mr, mr, nc, p, Bls.as<double2>(), mr, k,
+                                                  Uq.as<double2>(), sq.as<double>(), st));
+          const rocblas_double_complex one(1.0, 0.0);
+          DIE_BLAS(rocblas_ztrsm(bh, rocblas_side_left, rocblas_fill_upper, kN, rocblas_diagonal_non_unit, nc, k, &one,
+                                 reinterpret_cast<const rocblas_double_complex*>(Hls.p), mr,
+                                 reinterpret_cast<rocblas_double_complex*>(Bls.p), mr));
+        } else {
+          DIE_BLAS(rocsolver_zgels(bh, kN, mr, nc, k, reinterpret_cast<rocblas_double_complex*>(Hls.p), mr,
+                                   reinterpret_cast<rocblas_double_complex*>(Bls.p), mr, infod.as<int>()));
+          DIE_HIP(hipMemcpyAsync(&linfo, infod.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        }
         Mat Y;
         DIE_TRY(download<double>(Bls.p, mr, k, Y, st));
-        if (linfo != 0) return fail(DIE_E_BREAKDOWN, "block GMRES: rank-deficient block Hessenberg");
+        bool finite = true;
+        for (int j = 0; j < k && finite; ++j)
+          for (int i = 0; i < nc; ++i)
+            if (!std::isfinite(Y(i, j).real()) || !std::isfinite(Y(i, j).imag())) finite = false;
+        if (linfo != 0 || !finite) return fail(DIE_E_BREAKDOWN, "block GMRES: rank-deficient block Hessenberg");
         Mat Ys(nc, k);  // columns scaled back by the residual norms
         for (int j = 0; j < k; ++j)
           for (int i = 0; i < nc; ++i) Ys(i, j) = Y(i, j) * snorm[K[j]];

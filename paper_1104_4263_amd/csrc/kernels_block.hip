@@ -1,0 +1,160 @@
+// Least squares of the block GMRES cycle on the GPU: min || B - H Y || for the block upper
+// Hessenberg H of block Arnoldi with block size p (at most p sub-diagonals), by Householder
+// QR one p-column panel at a time: the panel's rows span at most 2p (its own block row and
+// the triangular sub-diagonal block below it), so each panel is factored in LDS by one
+// workgroup, and its reflectors are then applied to the trailing columns and to B in
+// parallel, one wavefront per column.  A triangular solve with R finishes it (the caller).
+// Complex FP64 throughout; H is column-major with leading dimension ld.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ops.hpp"
+
+namespace die {
+namespace {
+
+constexpr int kPanelThreads = 256;
+
+__device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) {  // acc + conj(a) b
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+
+// Factor the panel H[r0 : r0 + rows, c0 : c0 + pc] (rows <= kPanelMaxRows, pc <= kPanelMaxCols)
+// in place: R on and above the diagonal; the reflectors u_q (q < pc; u_q[i] = 0 for i < q) go to
+// U (rows x pc, column-major, leading dimension kPanelMaxRows) with scales s[q] = 2 / (u_q^H u_q)
+// (0 for a zero column).  The reflector P_q = I - s_q u_q u_q^H maps column q to -e^{i arg a} |x| e_q.
+__global__ void __launch_bounds__(kPanelThreads)
+k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, double2* __restrict__ U,
+           double* __restrict__ s) {
+  __shared__ double2 A[kPanelMaxRows * kPanelMaxCols];  // column-major, leading dimension kPanelMaxRows
+  __shared__ double red[kPanelThreads / 64];
+  __shared__ double2 redc[kPanelMaxCols][kPanelThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int e = t; e < kPanelMaxRows * pc; e += kPanelThreads) {
+    const int i = e % kPanelMaxRows, j = e / kPanelMaxRows;
+    A[e] = i < rows ? H[(size_t)(c0 + j) * ld + r0 + i] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int q = 0; q < pc; ++q) {
+    double2* x = A + (size_t)q * kPanelMaxRows;
+    // |x[q:]|^2
+    double sq = 0.0;
+    for (int i = q + t; i < rows; i += kPanelThreads) sq = fma(x[i].x, x[i].x, fma(x[i].y, x[i].y, sq));
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if (lane == 0) red[w] = sq;
+    __syncthreads();
+    double nrm2 = 0.0;
+    for (int k = 0; k < kPanelThreads / 64; ++k) nrm2 += red[k];
+    const double nrm = sqrt(nrm2);
+    const double2 a = x[q];
+    const double aa = sqrt(a.x * a.x + a.y * a.y);
+    const double2 ph = aa > 0.0 ? make_double2(a.x / aa, a.y / aa) : make_double2(1.0, 0.0);
+    // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
+    const double uu = 2.0 * nrm * (nrm + aa);
+    const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
+    __syncthreads();  // everyone has read x[q] and red
+    if (t == 0) {
+      x[q] = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
+      s[q] = sc;
+    }
+    __syncthreads();
+    // apply P_q to columns q+1 .. pc-1: y -= sc u (u^H y); one wave per column, round robin
+    for (int j = q + 1 + w; j < pc; j += kPanelThreads / 64) {
+      double2* y = A + (size_t)j * kPanelMaxRows;
+      double2 d = make_double2(0.0, 0.0);
+      for (int i = q + lane; i < rows; i += 64) d = cfma_conj(x[i], y[i], d);
+      for (int off = 32; off > 0; off >>= 1) {
+        d.x += __shfl_xor(d.x, off);
+        d.y += __shfl_xor(d.y, off);
+      }
+      const double2 f = make_double2(sc * d.x, sc * d.y);
+      for (int i = q + lane; i < rows; i += 64) {
+        const double2 u = x[i];
+        y[i].x -= u.x * f.x - u.y * f.y;
+        y[i].y -= u.x * f.y + u.y * f.x;
+      }
+    }
+    __syncthreads();
+    // export u_q, and put R's diagonal entry -e^{i arg a} |x| in place (zeros below)
+    for (int i = t; i < rows; i += kPanelThreads) U[(size_t)q * kPanelMaxRows + i] = i >= q ? x[i] : make_double2(0.0, 0.0);
+    __syncthreads();
+    if (t == 0) x[q] = make_double2(-ph.x * nrm, -ph.y * nrm);
+    for (int i = q + 1 + t; i < rows; i += kPanelThreads) x[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+  }
+  (void)redc;
+  for (int e = t; e < kPanelMaxRows * pc; e += kPanelThreads) {
+    const int i = e % kPanelMaxRows, j = e / kPanelMaxRows;
+    if (i < rows) H[(size_t)(c0 + j) * ld + r0 + i] = A[e];
+  }
+}
+
+// Apply the panel's reflectors P_0, P_1, ..., P_{pc-1} (in that order) to rows r0 .. r0+rows of
+// the columns [cb, ce) of H and all k columns of B (leading dimension ldb): one wave per column.
+__global__ void __launch_bounds__(256)
+k_panel_apply(double2* __restrict__ H, int ld, double2* __restrict__ B, int ldb, int k, int r0, int rows, int pc,
+              int cb, int ce, const double2* __restrict__ U, const double* __restrict__ s) {
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nh = ce - cb;
+  if (col >= nh + k) return;
+  double2* y = col < nh ? H + (size_t)(cb + col) * ld + r0 : B + (size_t)(col - nh) * ldb + r0;
+  constexpr int R = kPanelMaxRows / 64;  // rows per lane
+  double2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = lane + 64 * r;
+    v[r] = i < rows ? y[i] : make_double2(0.0, 0.0);
+  }
+  for (int q = 0; q < pc; ++q) {
+    const double2* u = U + (size_t)q * kPanelMaxRows;
+    double2 uq[R];
+    double2 d = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + 64 * r;
+      uq[r] = i < rows ? u[i] : make_double2(0.0, 0.0);
+      d = cfma_conj(uq[r], v[r], d);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      d.x += __shfl_xor(d.x, off);
+      d.y += __shfl_xor(d.y, off);
+    }
+    const double sc = s[q];
+    const double2 f = make_double2(sc * d.x, sc * d.y);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r].x -= uq[r].x * f.x - uq[r].y * f.y;
+      v[r].y -= uq[r].x * f.y + uq[r].y * f.x;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = lane + 64 * r;
+    if (i < rows) y[i] = v[r];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p, double2* B, int ldb, int k,
+                                      double2* U, double* s, hipStream_t st) {
+  if (p < 1 || p > kPanelMaxCols || nc % p || mr > ld || mr < nc || k < 0) return hipErrorInvalidValue;
+  for (int c0 = 0; c0 < nc; c0 += p) {
+    const int rows = std::min(2 * p, mr - c0);
+    if (rows < p || rows > kPanelMaxRows) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_panel_qr, dim3(1), dim3(kPanelThreads), 0, st, H, ld, c0, c0, rows, p, U, s);
+    const int cb = c0 + p, ncols = (nc - cb) + k;
+    if (ncols > 0)
+      hipLaunchKernelGGL(k_panel_apply, dim3((ncols + 3) / 4), dim3(256), 0, st, H, ld, B, ldb, k, c0, rows, p, cb,
+                         nc, U, s);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace die

@@ -96,6 +96,15 @@ hipError_t launch_scale(const c2<SX>* X, size_t x_rs, c2<SY>* Y, size_t y_rs, co
 template <class S>
 hipError_t launch_add_cols(const c2<S>* src, size_t n, const int* idx, int k, double2* u, hipStream_t st);
 
+// QR of the block upper Hessenberg H (mr x nc, column-major, leading dimension ld, at most p
+// sub-diagonals, nc a multiple of p, p <= kPanelMaxCols) in place, p columns at a time, with the
+// same reflectors applied to B (mr x k, leading dimension ldb): on return R is in H[0:nc, 0:nc]
+// and Q^H B in B.  U (kPanelMaxRows x p complex) and s (p doubles) are scratch.  Complex FP64.
+constexpr int kPanelMaxCols = 64;
+constexpr int kPanelMaxRows = 2 * kPanelMaxCols;
+hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p, double2* B, int ldb, int k,
+                                      double2* U, double* s, hipStream_t st);
+
 // ----------------------------------------------------------------- GMRES state
 struct GmresState {
   int j;         // iterations done in the current cycle
