@@ -938,6 +938,69 @@ rocblas_status gemm_batched<float>(rocblas_handle h, int m, int n, int k, const 
                                        reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, batch);
 }
 template <class T>
+rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, cd alpha,
+                       const c2<T>* A, int lda, rocblas_stride sa, const c2<T>* B, int ldb, rocblas_stride sb, cd beta,
+                       c2<T>* C, int ldc, rocblas_stride sc, int batch);
+template <>
+rocblas_status gemm_sb<double>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+                               cd alpha, const double2* A, int lda, rocblas_stride sa, const double2* B, int ldb,
+                               rocblas_stride sb, cd beta, double2* C, int ldc, rocblas_stride sc, int batch) {
+  const rocblas_double_complex a(alpha.real(), alpha.imag()), b(beta.real(), beta.imag());
+  return rocblas_zgemm_strided_batched(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                                       sa, reinterpret_cast<const rocblas_double_complex*>(B), ldb, sb, &b,
+                                       reinterpret_cast<rocblas_double_complex*>(C), ldc, sc, batch);
+}
+template <>
+rocblas_status gemm_sb<float>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+                              cd alpha, const float2* A, int lda, rocblas_stride sa, const float2* B, int ldb,
+                              rocblas_stride sb, cd beta, float2* C, int ldc, rocblas_stride sc, int batch) {
+  const rocblas_float_complex a((float)alpha.real(), (float)alpha.imag()), b((float)beta.real(), (float)beta.imag());
+  return rocblas_cgemm_strided_batched(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_float_complex*>(A), lda,
+                                       sa, reinterpret_cast<const rocblas_float_complex*>(B), ldb, sb, &b,
+                                       reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, batch);
+}
+// C = A + B (m x n; leading dimensions lda, ldb, ldc)
+template <class T>
+rocblas_status geam_add(rocblas_handle h, int m, int n, const c2<T>* A, int lda, const c2<T>* B, int ldb, c2<T>* C,
+                        int ldc);
+template <>
+rocblas_status geam_add<double>(rocblas_handle h, int m, int n, const double2* A, int lda, const double2* B, int ldb,
+                                double2* C, int ldc) {
+  const rocblas_double_complex one(1.0, 0.0);
+  return rocblas_zgeam(h, kN, kN, m, n, &one, reinterpret_cast<const rocblas_double_complex*>(A), lda, &one,
+                       reinterpret_cast<const rocblas_double_complex*>(B), ldb,
+                       reinterpret_cast<rocblas_double_complex*>(C), ldc);
+}
+template <>
+rocblas_status geam_add<float>(rocblas_handle h, int m, int n, const float2* A, int lda, const float2* B, int ldb,
+                               float2* C, int ldc) {
+  const rocblas_float_complex one(1.0f, 0.0f);
+  return rocblas_cgeam(h, kN, kN, m, n, &one, reinterpret_cast<const rocblas_float_complex*>(A), lda, &one,
+                       reinterpret_cast<const rocblas_float_complex*>(B), ldb,
+                       reinterpret_cast<rocblas_float_complex*>(C), ldc);
+}
+
+// W (K x n, leading dimension ldw) -= Q (K x m, leading dimension ldq) H (m x n, leading
+// dimension ldh) with K long: a strided batch over row chunks of Q and W (the same H), which
+// gives the matrix cores a tile shape that fits the narrow n.
+template <class T>
+int gemm_update_long(rocblas_handle h, int K, int n, int m, const c2<T>* Q, int ldq, const c2<T>* H, int ldh, c2<T>* W,
+                     int ldw) {
+  int rc = K;
+  for (int c = 1024; c >= 256; c /= 2)
+    if (K % c == 0 && K / c >= 16) {
+      rc = c;
+      break;
+    }
+  if (rc == K) {
+    DIE_BLAS(gemm<T>(h, kN, kN, K, n, m, -1.0, Q, ldq, H, ldh, 1.0, W, ldw));
+    return DIE_OK;
+  }
+  DIE_BLAS(gemm_sb<T>(h, kN, kN, rc, n, m, -1.0, Q, ldq, rc, H, ldh, 0, 1.0, W, ldw, rc, K / rc));
+  return DIE_OK;
+}
+
+template <class T>
 rocblas_status gemv(rocblas_handle h, int m, int n, const c2<T>* A, int lda, const c2<T>* x, c2<T>* y);
 template <>
 rocblas_status gemv<double>(rocblas_handle h, int m, int n, const double2* A, int lda, const double2* x, double2* y) {
@@ -1040,7 +1103,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(blas_on(c, st, &bh));
   const int ni = (int)n, ldh = (m + 1) * rpo;
   const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
-  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, Hls, Bls, ones, idxd, infod, part, coef, cnt, scl, Uq, sq;
+  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, sm2, Ht, Hls, Bls, ones, idxd, infod, part, coef, cnt,
+      scl, Uq, sq;
   DIE_TRY(Rs.alloc(dbytes));
   if (reg) DIE_TRY(Sd.alloc(dbytes));
   DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
@@ -1053,6 +1117,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(Ra.alloc((size_t)2 * rpo * n * sizeof(double2)));  // residual block, then its orthonormal basis
   DIE_TRY(Tb.alloc((size_t)rpo * n * sizeof(c2<T>)));
   DIE_TRY(sm.alloc((size_t)ldh * rpo * sizeof(double2)));
+  DIE_TRY(sm2.alloc((size_t)ldh * rpo * sizeof(c2<T>)));
+  DIE_TRY(Ht.alloc((size_t)ldh * m * rpo * sizeof(c2<T>)));
   DIE_TRY(Hls.alloc((size_t)ldh * m * rpo * sizeof(double2)));
   DIE_TRY(Bls.alloc((size_t)ldh * rpo * sizeof(double2)));
   DIE_TRY(ones.alloc(sizeof(double)));
@@ -1188,8 +1254,11 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         S0 = S;
       }
       DIE_HIP((die::launch_scale<double, T>(ra, n, vb, n, ones.as<double>(), 0, n, p, nullptr, st)));
-      // ---- block Arnoldi: H ((m+1) p x m p), CGS2 as GEMMs, CholQR2 of every new block
-      Mat H((m + 1) * p, m * p);
+      // ---- block Arnoldi: H ((m+1) p x m p, on the device in the basis precision, leading
+      // dimension ldhp), CGS2 as GEMMs, CholQR2 of every new block
+      const int ldhp = (m + 1) * p;
+      c2<T>* Hd = Ht.as<c2<T>>();
+      DIE_HIP(hipMemsetAsync(Hd, 0, (size_t)ldhp * m * p * sizeof(c2<T>), st));
       int meff = m;
       bool early = false;
       for (int j = 0; j < m; ++j) {
@@ -1204,17 +1273,14 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         }
         DIE_TRY(apply_M<T>(c, reg, z, reg ? Tm.as<c2<T>>() : nullptr, W, p, nullptr, st, 0, ob));
         const int nq = (j + 1) * p;
+        c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the two projections (nq x p each)
         for (int rep = 0; rep < 2; ++rep) {
-          DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, sm.as<c2<T>>(), st));
-          {
-            ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq);
-            DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, nq, -1.0, vb, ni, sm.as<c2<T>>(), nq, 1.0, W, ni));
-          }
-          Mat Hc;
-          DIE_TRY(download<T>(sm.p, nq, p, Hc, st));
-          for (int jj = 0; jj < p; ++jj)
-            for (int i = 0; i < nq; ++i) H(i, j * p + jj) += Hc(i, jj);
+          DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, hc[rep], st));
+          ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq);
+          DIE_TRY(gemm_update_long<T>(bh, ni, p, nq, vb, ni, hc[rep], nq, W, ni));
         }
+        // column block j of H: the sum of the two projections
+        DIE_BLAS(geam_add<T>(bh, nq, p, hc[0], nq, hc[1], nq, Hd + (size_t)j * p * ldhp, ldhp));
         Mat Gw, Q1, Q2;
         DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, W, ni, W, ni, sm.as<c2<T>>(), st));
         DIE_TRY(download<T>(sm.p, p, p, Gw, st));
@@ -1233,22 +1299,26 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         }
         DIE_TRY(upload<T>(la::upper_inverse(Q2), sm.p, st, stage));
         DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
-        for (int jj = 0; jj < p; ++jj)  // H(j+1, j) = Q2 Q1
+        Mat Hs(p, p);  // H(j+1, j) = Q2 Q1
+        for (int jj = 0; jj < p; ++jj)
           for (int i = 0; i <= jj; ++i) {
             cd a = 0.0;
             for (int q = i; q <= jj; ++q) a += Q2(i, q) * Q1(q, jj);
-            H((j + 1) * p + i, j * p + jj) = a;
+            Hs(i, jj) = a;
           }
+        DIE_TRY(upload<T>(Hs, sm.p, st, stage));
+        DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp + (size_t)(j + 1) * p, ldhp * sizeof(c2<T>), sm.p,
+                                 p * sizeof(c2<T>), p * sizeof(c2<T>), p, hipMemcpyDeviceToDevice, st));
       }
       // ---- block least squares min || E1 S0 - H Y || on the GPU, then u += P^-1 V Y
       const int mr = early ? meff * p : (meff + 1) * p, nc = meff * p;
       {
-        Mat Hm(mr, nc), Bm(mr, k);
-        for (int j = 0; j < nc; ++j)
-          for (int i = 0; i < mr; ++i) Hm(i, j) = H(i, j);
+        Mat Bm(mr, k);
         for (int j = 0; j < k; ++j)
           for (int i = 0; i < p; ++i) Bm(i, j) = S0(i, j);
-        DIE_TRY(upload<double>(Hm, Hls.p, st, stage64));
+        // H (mr x nc) to FP64 with leading dimension mr: column j is "right-hand side" j of the scale kernel
+        DIE_HIP((die::launch_scale<T, double>(Hd, ldhp, Hls.as<double2>(), mr, ones.as<double>(), 0, mr, nc, nullptr,
+                                              st)));
         DIE_TRY(upload<double>(Bm, Bls.p, st, stage64));
         int linfo = 0;
         if (p <= die::kPanelMaxCols) {
