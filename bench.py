@@ -3,12 +3,13 @@
 Headline workload: the 256 x 256 size class of the batched random-field workload --
 four objects (seeds 1004..1007: Re eps = 1 + 9U, Im eps = 0.5 U2, correlation length
 lambda/2, masked to a random ellipse; h = lambda/48, so 5.33 wavelengths across) lit
-by 64 equispaced TE plane waves each: 256 solves.  A step solves all 256 in one call
-of the batched solver: FP32 (complex64) operator products inside restarted GMRES(30)
-with the one-reduction Arnoldi and the Krylov basis stored as complex binary16 (dots,
-Hessenberg and Givens in FP64; --basis 32 / --orth 0 select the complex64 basis and the
-two-pass CGS2), every cycle restarted from the FP64 true residual, tol 1e-8 on that
-residual, zero initial guess.  Inputs are resident in HBM before the timed region; the
+by 64 equispaced TE plane waves each: 256 solves.  A step solves all 256 in one call:
+block GMRES(30) with one block Krylov space per object (complex64 products, basis and
+block GEMMs on the matrix cores, FP64 block least squares; --block-precision 64 for
+complex128), every cycle restarted from the FP64 true residual, tol 1e-8 on that
+residual, zero initial guess.  --solver rhs times the per-rhs batched solver instead
+(one-reduction Arnoldi, complex binary16 basis; --basis 32 / --orth 0 select the
+complex64 basis and the two-pass CGS2); it is also reported beside the block run.  Inputs are resident in HBM before the timed region; the
 per-object setup (symbol) is done once, outside it.
 
 The configured deflation (k = 16 largest-magnitude eigenvalues) is not applied in the
