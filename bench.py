@@ -286,7 +286,7 @@ def main():
     def batch_solve(use_block=block):
         if use_block:
             return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
-                           mixed=1 if args.block_precision == 32 else 0, block=1)
+                           mixed=1 if args.block_precision == 32 else 0, block=1, orth=args.orth)
         return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=2 if args.basis == 16 else 1,
                        orth=args.orth)
 
@@ -367,8 +367,9 @@ def main():
                                f"{N_ANGLES} TE incidence angles = {nsolve} solves per step",
                    "method": ((f"block GMRES({RESTART}) on A, one block Krylov space per object (its {N_ANGLES} "
                                f"angles), {'complex64' if args.block_precision == 32 else 'complex128'} products and "
-                               "CGS2/CholQR2 block GEMMs, FP64 block least squares and true-residual restart per "
-                               f"cycle, tol {TOL}, zero initial guess, all {nsolve} in one call") if block else
+                               f"{'one-pass block CGS' if args.orth else 'block CGS2'} + CholQR2 GEMMs, FP64 block "
+                               f"least squares and true-residual restart per cycle, tol {TOL}, zero initial guess, "
+                               f"all {nsolve} in one call") if block else
                               (f"batched GMRES({RESTART}) on A, FP32 products, {args.basis}-bit basis storage, "
                                f"{'one-reduction' if args.orth else 'two-pass'} CGS2, FP64 true-residual refinement "
                                f"per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call")),

@@ -104,7 +104,9 @@ typedef struct {
                         new block on the matrix cores (complex GEMM in the basis precision), the
                         block least squares once per cycle; every cycle restarts from the FP64
                         true residual.  Needs mixed = 0 (FP64) or 1 (complex64 basis and
-                        products); orth and graph do not apply.  iters counts block steps;
+                        products).  orth = 0: two block Gram-Schmidt passes (CGS2); orth = 1:
+                        one pass, the CholQR2 of the new block restoring its own
+                        orthonormality.  graph does not apply.  iters counts block steps;
                         products_A per right-hand side is the object's share.  0: per-rhs GMRES */
 } die_te_solve_opts;
 

@@ -1097,6 +1097,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   const double tol = o.tol > 0 ? o.tol : 1e-8;
   const double chol_tol = std::is_same<T, float>::value ? 1e-6 : 1e-12;  // rank test of a new block
   const double rank_tau2 = 1e-12;  // initial block: drop residual directions below 1e-6 (unit columns)
+  const int npass = o.orth == 1 ? 1 : 2;  // block CGS passes against the previous blocks
   if ((size_t)n > (size_t)INT32_MAX || (size_t)(m + 1) * rpo > 65535)
     return fail(DIE_E_INVALID, "block GMRES: vectors or blocks too large for the GEMM interface");
   rocblas_handle bh;
@@ -1273,14 +1274,18 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         }
         DIE_TRY(apply_M<T>(c, reg, z, reg ? Tm.as<c2<T>>() : nullptr, W, p, nullptr, st, 0, ob));
         const int nq = (j + 1) * p;
-        c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the two projections (nq x p each)
-        for (int rep = 0; rep < 2; ++rep) {
+        c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the projections (nq x p each)
+        for (int rep = 0; rep < npass; ++rep) {
           DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, hc[rep], st));
           ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq);
           DIE_TRY(gemm_update_long<T>(bh, ni, p, nq, vb, ni, hc[rep], nq, W, ni));
         }
-        // column block j of H: the sum of the two projections
-        DIE_BLAS(geam_add<T>(bh, nq, p, hc[0], nq, hc[1], nq, Hd + (size_t)j * p * ldhp, ldhp));
+        // column block j of H: the sum of the projections
+        if (npass == 2)
+          DIE_BLAS(geam_add<T>(bh, nq, p, hc[0], nq, hc[1], nq, Hd + (size_t)j * p * ldhp, ldhp));
+        else
+          DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp, ldhp * sizeof(c2<T>), hc[0], nq * sizeof(c2<T>),
+                                   nq * sizeof(c2<T>), p, hipMemcpyDeviceToDevice, st));
         Mat Gw, Q1, Q2;
         DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, W, ni, W, ni, sm.as<c2<T>>(), st));
         DIE_TRY(download<T>(sm.p, p, p, Gw, st));

@@ -15,18 +15,19 @@ api = pytest.importorskip("paper_1104_4263_amd.api")
 from paper_1104_4263_amd._lib import DieTeError  # noqa: E402
 
 
+@pytest.mark.parametrize("orth", [0, 1])
 @pytest.mark.parametrize("eps_obj,reg,defl,mixed", [
     (4.0 + 0j, False, 0, 0), (4.0 + 0j, False, 0, 1), (-2.5 + 0.2j, True, 0, 0),
     (-2.5 + 0.2j, True, 8, 0), (16.0 + 0j, False, 6, 1), (-16 + 1.5j, True, 10, 1),
 ])
-def test_block_matches_lu(eps_obj, reg, defl, mixed):
-    say(f"block GMRES eps={eps_obj} reg={reg} defl={defl} mixed={mixed}")
+def test_block_matches_lu(eps_obj, reg, defl, mixed, orth):
+    say(f"block GMRES eps={eps_obj} reg={reg} defl={defl} mixed={mixed} orth={orth}")
     g = centred_grid(24, 1.0, ny=20)
     eps = cylinder(g, 0.35, eps_obj)
     b = np.stack([plane_wave(g, p) for p in (0.3, 1.2, 2.1, 4.0)])
     u_lu = op.solve_dense(g, eps, b)
     s = api.Solver.from_grid(g, eps, regularize=reg, deflate_k=defl, seed=3)
-    u, rc, info = s.solve(dev(b), restart=20, max_iters=4000, tol=1e-8, mixed=mixed, block=1)
+    u, rc, info = s.solve(dev(b), restart=20, max_iters=4000, tol=1e-8, mixed=mixed, block=1, orth=orth)
     assert rc == 0
     uh = host(u)
     for r in range(b.shape[0]):
@@ -44,7 +45,7 @@ def test_block_multi_object_agrees_with_per_rhs_solver():
     psis = [2 * np.pi * j / 8 for j in range(8)]
     b = np.concatenate([np.stack([plane_wave(g, p) for p in psis])] * 3)
     s = api.Solver.from_grid(g, eps)
-    ub, rcb, ib = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=1, block=1)
+    ub, rcb, ib = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=1, block=1, orth=1)
     up, rcp, ip = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=1)
     assert rcb == 0 and rcp == 0
     assert rel(host(ub), host(up)) < 1e-6
