@@ -980,12 +980,12 @@ rocblas_status geam_add<float>(rocblas_handle h, int m, int n, const float2* A, 
                        reinterpret_cast<rocblas_float_complex*>(C), ldc);
 }
 
-// W (K x n, leading dimension ldw) -= Q (K x m, leading dimension ldq) H (m x n, leading
-// dimension ldh) with K long: a strided batch over row chunks of Q and W (the same H), which
-// gives the matrix cores a tile shape that fits the narrow n.
+// W (K x n, leading dimension ldw) = alpha Q (K x m, leading dimension ldq) H (m x n, leading
+// dimension ldh) + beta W with K long: a strided batch over row chunks of Q and W (the same H),
+// which gives the matrix cores a tile shape that fits the narrow n.
 template <class T>
-int gemm_update_long(rocblas_handle h, int K, int n, int m, const c2<T>* Q, int ldq, const c2<T>* H, int ldh, c2<T>* W,
-                     int ldw) {
+int gemm_rows_long(rocblas_handle h, int K, int n, int m, cd alpha, const c2<T>* Q, int ldq, const c2<T>* H, int ldh,
+                   cd beta, c2<T>* W, int ldw) {
   int rc = K;
   for (int c = 1024; c >= 256; c /= 2)
     if (K % c == 0 && K / c >= 16) {
@@ -993,11 +993,16 @@ int gemm_update_long(rocblas_handle h, int K, int n, int m, const c2<T>* Q, int 
       break;
     }
   if (rc == K) {
-    DIE_BLAS(gemm<T>(h, kN, kN, K, n, m, -1.0, Q, ldq, H, ldh, 1.0, W, ldw));
+    DIE_BLAS(gemm<T>(h, kN, kN, K, n, m, alpha, Q, ldq, H, ldh, beta, W, ldw));
     return DIE_OK;
   }
-  DIE_BLAS(gemm_sb<T>(h, kN, kN, rc, n, m, -1.0, Q, ldq, rc, H, ldh, 0, 1.0, W, ldw, rc, K / rc));
+  DIE_BLAS(gemm_sb<T>(h, kN, kN, rc, n, m, alpha, Q, ldq, rc, H, ldh, 0, beta, W, ldw, rc, K / rc));
   return DIE_OK;
+}
+template <class T>
+int gemm_update_long(rocblas_handle h, int K, int n, int m, const c2<T>* Q, int ldq, const c2<T>* H, int ldh, c2<T>* W,
+                     int ldw) {
+  return gemm_rows_long<T>(h, K, n, m, -1.0, Q, ldq, H, ldh, 1.0, W, ldw);
 }
 
 template <class T>
@@ -1292,7 +1297,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1);
         if (ok) {
           DIE_TRY(upload<T>(la::upper_inverse(Q1), sm.p, st, stage));
-          DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, p, 1.0, W, ni, sm.as<c2<T>>(), p, 0.0, Wt.as<c2<T>>(), ni));
+          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, W, ni, sm.as<c2<T>>(), p, 0.0, Wt.as<c2<T>>(), ni));
           DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, Wt.as<c2<T>>(), ni, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), st));
           DIE_TRY(download<T>(sm.p, p, p, Gw, st));
           ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
@@ -1303,7 +1308,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
           break;
         }
         DIE_TRY(upload<T>(la::upper_inverse(Q2), sm.p, st, stage));
-        DIE_BLAS(gemm<T>(bh, kN, kN, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
+        DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
         Mat Hs(p, p);  // H(j+1, j) = Q2 Q1
         for (int jj = 0; jj < p; ++jj)
           for (int i = 0; i <= jj; ++i) {

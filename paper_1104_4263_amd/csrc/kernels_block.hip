@@ -14,7 +14,9 @@
 namespace die {
 namespace {
 
-constexpr int kPanelThreads = 256;
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelWaves = kPanelThreads / 64;
+static_assert(kPanelMaxRows <= kPanelThreads, "the column norm takes one element per thread");
 
 __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) {  // acc + conj(a) b
   acc.x = fma(a.x, b.x, acc.x);
@@ -28,12 +30,13 @@ __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) 
 // in place: R on and above the diagonal; the reflectors u_q (q < pc; u_q[i] = 0 for i < q) go to
 // U (rows x pc, column-major, leading dimension kPanelMaxRows) with scales s[q] = 2 / (u_q^H u_q)
 // (0 for a zero column).  The reflector P_q = I - s_q u_q u_q^H maps column q to -e^{i arg a} |x| e_q.
+// Per reflector: the column norm (all waves), then the update of the later columns (one wave per
+// column) while the reflector is exported; four barriers.
 __global__ void __launch_bounds__(kPanelThreads)
 k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, double2* __restrict__ U,
            double* __restrict__ s) {
   __shared__ double2 A[kPanelMaxRows * kPanelMaxCols];  // column-major, leading dimension kPanelMaxRows
-  __shared__ double red[kPanelThreads / 64];
-  __shared__ double2 redc[kPanelMaxCols][kPanelThreads / 64];
+  __shared__ double red[kPanelWaves];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int e = t; e < kPanelMaxRows * pc; e += kPanelThreads) {
     const int i = e % kPanelMaxRows, j = e / kPanelMaxRows;
@@ -42,14 +45,14 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
   __syncthreads();
   for (int q = 0; q < pc; ++q) {
     double2* x = A + (size_t)q * kPanelMaxRows;
-    // |x[q:]|^2
+    // |x[q:]|^2 (rows <= kPanelMaxRows <= kPanelThreads: one element per thread at most)
     double sq = 0.0;
-    for (int i = q + t; i < rows; i += kPanelThreads) sq = fma(x[i].x, x[i].x, fma(x[i].y, x[i].y, sq));
+    if (t >= q && t < rows) sq = fma(x[t].x, x[t].x, x[t].y * x[t].y);
     for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
     if (lane == 0) red[w] = sq;
-    __syncthreads();
+    __syncthreads();  // (1) partial norms in red
     double nrm2 = 0.0;
-    for (int k = 0; k < kPanelThreads / 64; ++k) nrm2 += red[k];
+    for (int k = 0; k < kPanelWaves; ++k) nrm2 += red[k];
     const double nrm = sqrt(nrm2);
     const double2 a = x[q];
     const double aa = sqrt(a.x * a.x + a.y * a.y);
@@ -57,14 +60,15 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
     // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
     const double uu = 2.0 * nrm * (nrm + aa);
     const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
-    __syncthreads();  // everyone has read x[q] and red
+    __syncthreads();  // (2) everyone has read x[q] and red
     if (t == 0) {
       x[q] = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
       s[q] = sc;
     }
-    __syncthreads();
-    // apply P_q to columns q+1 .. pc-1: y -= sc u (u^H y); one wave per column, round robin
-    for (int j = q + 1 + w; j < pc; j += kPanelThreads / 64) {
+    __syncthreads();  // (3) the reflector u = x[q:] is in place
+    if (t < rows) U[(size_t)q * kPanelMaxRows + t] = t >= q ? x[t] : make_double2(0.0, 0.0);
+    // apply P_q to columns q+1 .. pc-1: y -= sc u (u^H y); one wave per column
+    for (int j = q + 1 + w; j < pc; j += kPanelWaves) {
       double2* y = A + (size_t)j * kPanelMaxRows;
       double2 d = make_double2(0.0, 0.0);
       for (int i = q + lane; i < rows; i += 64) d = cfma_conj(x[i], y[i], d);
@@ -79,15 +83,12 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
         y[i].y -= u.x * f.y + u.y * f.x;
       }
     }
-    __syncthreads();
-    // export u_q, and put R's diagonal entry -e^{i arg a} |x| in place (zeros below)
-    for (int i = t; i < rows; i += kPanelThreads) U[(size_t)q * kPanelMaxRows + i] = i >= q ? x[i] : make_double2(0.0, 0.0);
-    __syncthreads();
+    __syncthreads();  // (4) every later column updated and u exported: column q becomes R's
+    // column q: -e^{i arg a} |x| on the diagonal, zeros below (read again only at the end)
     if (t == 0) x[q] = make_double2(-ph.x * nrm, -ph.y * nrm);
-    for (int i = q + 1 + t; i < rows; i += kPanelThreads) x[i] = make_double2(0.0, 0.0);
-    __syncthreads();
+    if (t > q && t < rows) x[t] = make_double2(0.0, 0.0);
   }
-  (void)redc;
+  __syncthreads();
   for (int e = t; e < kPanelMaxRows * pc; e += kPanelThreads) {
     const int i = e % kPanelMaxRows, j = e / kPanelMaxRows;
     if (i < rows) H[(size_t)(c0 + j) * ld + r0 + i] = A[e];
