@@ -193,19 +193,36 @@ def uneven_run(sizes, args):
         solvers.append(Solver.from_grid(gn, np.stack([e for _, e in objs])))
         b1 = np.stack([plane_wave(gn, 2.0 * math.pi * j / N_ANGLES) for j in range(N_ANGLES)])
         Bs.append(torch.from_numpy(np.concatenate([b1] * 4)).cuda())
-    kw = dict(restart=RESTART, tol=TOL, mixed=2 if args.basis == 16 else 1, orth=args.orth)
+    if args.solver == "block":
+        kw = dict(restart=RESTART, tol=TOL, mixed=1 if args.block_precision == 32 else 0, block=1, orth=args.orth)
+    else:
+        kw = dict(restart=RESTART, tol=TOL, mixed=2 if args.basis == 16 else 1, orth=args.orth)
     Solver.solve_batch(solvers, Bs, max_iters=RESTART, **kw)  # allocates every context's buffers
     torch.cuda.synchronize()
+    # solved in chunks of two restart cycles, each starting from the previous chunk's fields (the
+    # restart the next cycle would make anyway), so that every chunk reports its progress
+    X = [torch.zeros_like(b) for b in Bs]
+    iters = [np.zeros(b.shape[0], dtype=np.int64) for b in Bs]
     t0 = time.perf_counter()
-    res, rc = Solver.solve_batch(solvers, Bs, max_iters=MAX_ITERS, **kw)
+    rc, chunk = 1, 2 * RESTART
+    while rc != 0 and int(max(i.max() for i in iters)) < MAX_ITERS:
+        res, rc = Solver.solve_batch(solvers, Bs, x0s=X, max_iters=chunk, **kw)
+        X = [u for u, _ in res]
+        for c, (_, inf) in enumerate(res):
+            iters[c] += np.array([x["iters"] for x in inf])
+        worst = [max(x["rel_res_true"] for x in inf) for _, inf in res]
+        log(f"uneven: {time.perf_counter() - t0:.1f} s, worst rel-res per class "
+            f"{', '.join(f'{n}: {w:.1e}' for n, w in zip(sizes, worst))}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     nsol = sum(b.shape[0] for b in Bs)
     ok = rc == 0 and all(x["rel_res_true"] <= TOL for _, inf in res for x in inf)
-    per = {f"{n}x{n}": {"iters_mean": round(float(np.mean([x["iters"] for x in inf])), 1),
-                        "iters_max": int(max(x["iters"] for x in inf))} for n, (_, inf) in zip(sizes, res)}
+    per = {f"{n}x{n}": {"iters_mean": round(float(np.mean(it)), 1), "iters_max": int(it.max())}
+           for n, it in zip(sizes, iters)}
     out = {"workload": f"size classes {sizes} of the batched random-field workload, 4 objects x {N_ANGLES} "
-                       f"angles each, one die_te_solve_batch call", "solves": nsol, "s": round(dt, 3),
+                       f"angles each, die_te_solve_batch calls of two restart cycles each", "solver": args.solver,
+           "solves": nsol,
+           "s": round(dt, 3),
            "solves_per_s": round(nsol / dt, 3) if ok else 0.0, "classes": per}
     log(f"uneven: {out}")
     for sv in solvers:
