@@ -39,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {32: 157.3, 64: 78.6}  # dense matrix-core peaks, fp32 and fp64
+MFMA_PEAK_TFLOPS = {16: 2500.0, 32: 157.3, 64: 78.6}  # dense matrix-core peaks: fp16, fp32, fp64
 N_ANGLES = 64
 OBJ_SEEDS = (1004, 1005, 1006, 1007)
 RESTART = 30
@@ -194,7 +194,8 @@ def uneven_run(sizes, args):
         b1 = np.stack([plane_wave(gn, 2.0 * math.pi * j / N_ANGLES) for j in range(N_ANGLES)])
         Bs.append(torch.from_numpy(np.concatenate([b1] * 4)).cuda())
     if args.solver == "block":
-        kw = dict(restart=RESTART, tol=TOL, mixed=1 if args.block_precision == 32 else 0, block=1, orth=args.orth)
+        kw = dict(restart=RESTART, tol=TOL, mixed=1 if args.block_precision == 32 else 0,
+                  block=2 if args.block_gemm == 16 else 1, orth=args.orth)
     else:
         kw = dict(restart=RESTART, tol=TOL, mixed=2 if args.basis == 16 else 1, orth=args.orth)
     Solver.solve_batch(solvers, Bs, max_iters=RESTART, **kw)  # allocates every context's buffers
@@ -258,6 +259,9 @@ def main():
                     help="block: block GMRES(30), one block Krylov space per object (default); rhs: per-rhs GMRES(30)")
     ap.add_argument("--block-precision", type=int, default=32, choices=(32, 64),
                     help="bits per real part of the block basis, GEMMs and products (32 with FP64 refinement, or 64)")
+    ap.add_argument("--block-gemm", type=int, default=32, choices=(16, 32),
+                    help="block solver: 16 = block Gram-Schmidt GEMMs on binary16 planar copies of the basis "
+                         "(FP32 accumulation; needs --block-precision 32), 32 = complex GEMMs in the basis precision")
     ap.add_argument("--orth", type=int, default=1, choices=(0, 1),
                     help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
     ap.add_argument("--basis", type=int, default=16, choices=(16, 32),
@@ -271,6 +275,8 @@ def main():
                     help="also solve size classes of the batched workload on grids of different sizes in one "
                          "call (e.g. 128,256,512: 4 objects x 64 angles per class, seeds 1000 + object index)")
     args = ap.parse_args()
+    if args.block_gemm == 16 and args.block_precision != 32:
+        ap.error("--block-gemm 16 needs --block-precision 32")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
               "in DESIGN.md and is not part of this build", file=sys.stderr)
@@ -303,7 +309,8 @@ def main():
     def batch_solve(use_block=block):
         if use_block:
             return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
-                           mixed=1 if args.block_precision == 32 else 0, block=1, orth=args.orth)
+                           mixed=1 if args.block_precision == 32 else 0, block=2 if args.block_gemm == 16 else 1,
+                           orth=args.orth)
         return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=2 if args.basis == 16 else 1,
                        orth=args.orth)
 
@@ -350,11 +357,20 @@ def main():
                        "est_share_of_step": round(est[k] / (ms_per_step * args.steps), 3)}
     if dom == "gemm":
         # complex GEMM on the matrix cores: flops against the dense MFMA peak of its precision
-        peak = MFMA_PEAK_TFLOPS[args.block_precision]
+        peak = MFMA_PEAK_TFLOPS[16 if args.block_gemm == 16 else args.block_precision]
         achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e12
+        # HBM traffic: the operand bytes of the same launches times the measured HBM/algorithmic
+        # ratio of the update GEMM (valid only for the solver source the counters were taken on)
+        mem_per_launch = s.profile_mem(DIE_PROF_GEMM) / max(p["timed"], 1)
+        src = source_hash("die_te.cpp", "dense.hpp", "ops.hpp", "common.hpp")
+        tag = ("block_gemm_update_h16_256" if args.block_gemm == 16 else
+               f"block_gemm_update_c{64 if args.block_precision == 32 else 128}_256")
+        traffic = read_traffic(tag, src, mem_per_launch)
         roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": "gemm (block basis update W -= Q H)",
+                    "frac": round(achieved / peak, 4), "traffic": None if traffic is None else int(traffic),
+                    "kernel": "gemm (block basis update W -= Q H)",
                     "avg_launch_us": round(1000.0 * avg_ms, 2), "algorithmic_flops_per_launch": int(work_per_launch),
+                    "algorithmic_bytes_per_launch": int(mem_per_launch), "solver_source_sha256": src,
                     "per_kind": per_kind}
     else:
         achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
@@ -376,7 +392,9 @@ def main():
         "metric": "TE solves/s to rel-res 1e-8 (plain vs mixed/batched/learned); matvec % HBM peak",
         "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": ((f"c{64 if args.block_precision == 32 else 128} products and block GEMMs, f64 block least squares "
+        "dtype": (("c64 products, f16 block Gram-Schmidt GEMMs (f32 accumulation), c64 CholQR, f64 block least "
+                   "squares and refinement") if block and args.block_gemm == 16 else
+                  (f"c{64 if args.block_precision == 32 else 128} products and block GEMMs, f64 block least squares "
                    "and refinement") if block else
                   f"f32 products, {'f16' if args.basis == 16 else 'f32'} basis storage, f64 dots/Givens/refinement"),
         "data": "synthetic",
@@ -384,7 +402,9 @@ def main():
                                f"{N_ANGLES} TE incidence angles = {nsolve} solves per step",
                    "method": ((f"block GMRES({RESTART}) on A, one block Krylov space per object (its {N_ANGLES} "
                                f"angles), {'complex64' if args.block_precision == 32 else 'complex128'} products and "
-                               f"{'one-pass block CGS' if args.orth else 'block CGS2'} + CholQR2 GEMMs, FP64 block "
+                               f"{'one-pass block CGS' if args.orth else 'block CGS2'}"
+                               f"{' (binary16 planar GEMMs, FP32 accumulation)' if args.block_gemm == 16 else ''}"
+                               f" + CholQR2 GEMMs, FP64 block "
                                f"least squares and true-residual restart per cycle, tol {TOL}, zero initial guess, "
                                f"all {nsolve} in one call") if block else
                               (f"batched GMRES({RESTART}) on A, FP32 products, {args.basis}-bit basis storage, "

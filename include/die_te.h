@@ -107,7 +107,14 @@ typedef struct {
                         products).  orth = 0: two block Gram-Schmidt passes (CGS2); orth = 1:
                         one pass, the CholQR2 of the new block restoring its own
                         orthonormality.  graph does not apply.  iters counts block steps;
-                        products_A per right-hand side is the object's share.  0: per-rhs GMRES */
+                        products_A per right-hand side is the object's share.
+                        2: block GMRES as for 1 with mixed = 1 only, its block Gram-Schmidt
+                        products Q^H W and W -= Q H on the binary16 matrix cores: a binary16
+                        planar shadow of the basis (real and imaginary parts as separate real
+                        columns) and of W, FP32 accumulation and FP32 W, the projection
+                        coefficients rounded to binary16 (and kept so in H); CholQR2, products
+                        and least squares as for 1.  Needs an even vector length.
+                        0: per-rhs GMRES */
 } die_te_solve_opts;
 
 typedef struct {
@@ -227,11 +234,16 @@ int die_te_fft2(void *data, int px, int py, int batch, int inverse, int prec, vo
  * (inside a solve: those active at the start of the GMRES cycle).  Products:
  * es (2RN + n_obj N + 8R ny px + 3 px py + 4RN) with es the bytes per complex value;
  * dots over j basis vectors: R (j + 1) 2N es; multi-axpys: R (j + 2) 2N es.  For
- * DIE_PROF_GEMM the `bytes` output holds flops instead: 8 M N K per complex GEMM. */
+ * DIE_PROF_GEMM the `bytes` output holds flops instead: 8 M N K per complex GEMM.
+ * die_te_profile_mem returns in *mem_bytes the algorithmic HBM bytes of the bracketed
+ * launches of `kind` (the same figure as `bytes` for the first three kinds; for
+ * DIE_PROF_GEMM the operand bytes es (n nq + 2 n p + nq p) of each update W -= Q H with
+ * W of n x p and Q of n x nq).  DIE_E_INVALID for a bad kind or a NULL output. */
 enum { DIE_PROF_PRODUCT = 0, DIE_PROF_DOTS = 1, DIE_PROF_AXPY = 2, DIE_PROF_GEMM = 3 };
 int die_te_profile(die_te_ctx *ctx, int enable);
 int die_te_profile_read(die_te_ctx *ctx, int kind, long long *launches, long long *seen, double *total_ms,
                         double *bytes);
+int die_te_profile_mem(die_te_ctx *ctx, int kind, double *mem_bytes);
 
 /* Release everything the context owns. */
 int die_te_destroy(die_te_ctx *ctx);

@@ -20,6 +20,7 @@ from .api import (  # noqa: F401
     die_te_destroy,
     die_te_profile,
     die_te_profile_read,
+    die_te_profile_mem,
     die_te_last_error,
     UNet,
     die_te_unet_create,

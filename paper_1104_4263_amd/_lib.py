@@ -86,6 +86,7 @@ def load() -> ctypes.CDLL:
     lib.die_te_profile.argtypes = [vp, i]
     lib.die_te_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.die_te_profile_mem.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
     lib.die_te_last_error.argtypes = []
     lib.die_te_last_error.restype = ctypes.c_char_p
     fp, dp, ll, f, ull = (ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double), ctypes.c_longlong,

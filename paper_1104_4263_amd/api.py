@@ -74,7 +74,7 @@ def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, res
     """mixed: 0 FP64, 1 (or True) complex64 products and basis, 2 complex64 products with a
     binary16 basis (orth=1)."""
     o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
-                       float(reg_margin), int(orth), int(bool(graph)), int(bool(block)))
+                       float(reg_margin), int(orth), int(bool(graph)), int(block))
     info = (DieTeSolveInfo * nrhs)()
     rc = load().die_te_solve(ctx, _dev(e_in, (torch.complex128,), "e_in"), _dev(e_tot, (torch.complex128,), "e_tot"),
                              nrhs, ctypes.byref(o), info, _stream())
@@ -90,7 +90,7 @@ def die_te_solve_batch(ctxs, e_ins, e_tots, nrhs, *, restart: int = 30, max_iter
     if not (len(e_ins) == len(e_tots) == len(nrhs) == n):
         raise ValueError("ctxs, e_ins, e_tots and nrhs must have the same length")
     o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
-                       float(reg_margin), int(orth), int(bool(graph)), int(bool(block)))
+                       float(reg_margin), int(orth), int(bool(graph)), int(block))
     vp = ctypes.c_void_p
     c_arr = (vp * n)(*[vp(c.value if isinstance(c, vp) else c) for c in ctxs])
     i_arr = (vp * n)(*[_dev(t, (torch.complex128,), "e_in") for t in e_ins])
@@ -155,6 +155,14 @@ def die_te_profile_read(ctx, kind: int) -> tuple[int, int, float, float]:
     check(load().die_te_profile_read(ctx, int(kind), ctypes.byref(n), ctypes.byref(seen), ctypes.byref(ms),
                                      ctypes.byref(nb)))
     return int(n.value), int(seen.value), float(ms.value), float(nb.value)
+
+
+def die_te_profile_mem(ctx, kind: int) -> float:
+    """Total algorithmic HBM bytes of the bracketed launches of `kind` (operand bytes for the
+    GEMM kind, whose die_te_profile_read figure is flops)."""
+    nb = ctypes.c_double(0.0)
+    check(load().die_te_profile_mem(ctx, int(kind), ctypes.byref(nb)))
+    return float(nb.value)
 
 
 def die_te_destroy(ctx) -> None:
@@ -248,6 +256,9 @@ class Solver:
 
     def profile_read(self, kind: int) -> tuple[int, int, float, float]:
         return die_te_profile_read(self.ctx, kind)
+
+    def profile_mem(self, kind: int) -> float:
+        return die_te_profile_mem(self.ctx, kind)
 
     def close(self):
         if self.ctx:

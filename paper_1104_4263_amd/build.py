@@ -48,7 +48,7 @@ def build(verbose: bool = True) -> str:
             list(ex.map(lambda so: _compile(*so), zip(SOURCES, objs)))
         out_tmp = LIB + ".tmp"
         cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp] + objs + \
-            ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]
+            ["-L/opt/rocm/lib", "-lhipblaslt", "-lrocsolver", "-lrocblas", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"linking failed:\n{res.stdout}\n{res.stderr}")

@@ -9,18 +9,21 @@
 #include "die_te_learn.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
 #include <thread>
 #include <vector>
 
+#include <hipblaslt/hipblaslt.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -44,6 +47,29 @@ namespace {
 
 using die_host::DBuf;
 using die_host::fail;
+
+// hipBLASLt plans of the binary16 GEMMs of the block solver (binary16 inputs, FP32 output and
+// accumulation), one per shape, and the workspace they share.
+struct LtPlan {
+  hipblasLtMatmulDesc_t desc = nullptr;
+  hipblasLtMatrixLayout_t a = nullptr, b = nullptr, d = nullptr;
+  hipblasLtMatmulAlgo_t algo{};
+  size_t ws = 0;
+};
+struct LtCache {
+  hipblasLtHandle_t h = nullptr;
+  std::map<std::array<int64_t, 11>, LtPlan> plans;
+  DBuf ws;
+  ~LtCache() {
+    for (auto& kv : plans) {
+      if (kv.second.a) (void)hipblasLtMatrixLayoutDestroy(kv.second.a);
+      if (kv.second.b) (void)hipblasLtMatrixLayoutDestroy(kv.second.b);
+      if (kv.second.d) (void)hipblasLtMatrixLayoutDestroy(kv.second.d);
+      if (kv.second.desc) (void)hipblasLtMatmulDescDestroy(kv.second.desc);
+    }
+    if (h) (void)hipblasLtDestroy(h);
+  }
+};
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int v) {
@@ -80,11 +106,13 @@ struct die_te_ctx {
   size_t prof_used[4] = {0, 0, 0, 0};
   unsigned long long prof_seen[4] = {0, 0, 0, 0};
   double prof_bytes[4] = {0, 0, 0, 0};  // algorithmic bytes (flops for the GEMM kind) of the bracketed launches
+  double prof_mem[4] = {0, 0, 0, 0};    // algorithmic HBM bytes of the bracketed launches (every kind)
   int prof_every = 1;
   int prof_nlive = -1;  // right-hand sides live in the current launches (-1: all of them)
   // FFT pass variants of the products: forced (>= 0) or tuned per [FP64, FP32][batch class][pass]
   int fft_force = -1;
   rocblas_handle blas = nullptr;  // block GMRES: GEMMs and the block least squares
+  std::unique_ptr<LtCache> lt;    // block GMRES, binary16 planar GEMMs
   int fftv[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}, {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};
   ~die_te_ctx() {
     if (blas) (void)rocblas_destroy_handle(blas);
@@ -105,8 +133,9 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t end = nullptr;
   // bytes: the algorithmic HBM bytes of the bracketed launch (the compulsory reads and writes
-  // of its operands), credited to the kind only when the launch is bracketed.
-  ProfScope(die_te_ctx* cc, int k, hipStream_t s, double bytes) : c(cc), kind(k), st(s) {
+  // of its operands), credited to the kind only when the launch is bracketed; for a GEMM,
+  // bytes holds its flops and mem its operand bytes (mem < 0: mem = bytes).
+  ProfScope(die_te_ctx* cc, int k, hipStream_t s, double bytes, double mem = -1.0) : c(cc), kind(k), st(s) {
     if (!c->prof_on) return;
     if (c->prof_seen[kind]++ % c->prof_every) return;  // sample one launch in prof_every
     auto& v = c->prof_ev[kind];
@@ -121,6 +150,7 @@ struct ProfScope {
     end = v[u].second;
     ++u;
     c->prof_bytes[kind] += bytes;
+    c->prof_mem[kind] += mem < 0.0 ? bytes : mem;
   }
   ~ProfScope() {
     if (end) (void)hipEventRecord(end, st);
@@ -891,6 +921,87 @@ int blas_on(die_te_ctx* c, hipStream_t st, rocblas_handle* h) {
   return DIE_OK;
 }
 
+#define DIE_LT(expr)                                                                               \
+  do {                                                                                             \
+    hipblasStatus_t _s = (expr);                                                                   \
+    if (_s != HIPBLAS_STATUS_SUCCESS)                                                              \
+      return die_host::fail(DIE_E_HIP, std::string(#expr) + ": hipBLASLt status " + std::to_string((int)_s)); \
+  } while (0)
+
+// D_b = alpha op(A_b) B_b + beta D_b for b < batch (strides sa, sb, sd in elements), column-major:
+// A (binary16; m x k, or k x m read transposed when ta), B (binary16, k x n), D (FP32, m x n).
+// The plan of each shape is made once (hipBLASLt's first heuristic choice) and kept.
+int lt_gemm(die_te_ctx* c, bool ta, int m, int n, int k, float alpha, const _Float16* A, int64_t lda, int64_t sa,
+            const _Float16* B, int64_t ldb, int64_t sb, float beta, float* D, int64_t ldd, int64_t sd, int batch,
+            hipStream_t st) {
+  if (!c->lt) {
+    c->lt.reset(new LtCache());
+    DIE_LT(hipblasLtCreate(&c->lt->h));
+  }
+  LtCache& L = *c->lt;
+  const std::array<int64_t, 11> key = {ta ? 1 : 0, m, n, k, lda, sa, ldb, sb, ldd, sd, batch};
+  auto it = L.plans.find(key);
+  if (it == L.plans.end()) {
+    LtPlan pl;
+    auto mk_layout = [&](hipblasLtMatrixLayout_t* lay, hipDataType ty, int64_t r, int64_t cl, int64_t ld,
+                         int64_t stride) -> int {
+      DIE_LT(hipblasLtMatrixLayoutCreate(lay, ty, (uint64_t)r, (uint64_t)cl, ld));
+      if (batch > 1) {
+        const int32_t bc = batch;
+        DIE_LT(hipblasLtMatrixLayoutSetAttribute(*lay, HIPBLASLT_MATRIX_LAYOUT_BATCH_COUNT, &bc, sizeof(bc)));
+        DIE_LT(hipblasLtMatrixLayoutSetAttribute(*lay, HIPBLASLT_MATRIX_LAYOUT_STRIDED_BATCH_OFFSET, &stride,
+                                                 sizeof(stride)));
+      }
+      return DIE_OK;
+    };
+    int rc = [&]() -> int {
+      DIE_LT(hipblasLtMatmulDescCreate(&pl.desc, HIPBLAS_COMPUTE_32F, HIP_R_32F));
+      const int32_t opa = ta ? HIPBLAS_OP_T : HIPBLAS_OP_N, opb = HIPBLAS_OP_N;
+      DIE_LT(hipblasLtMatmulDescSetAttribute(pl.desc, HIPBLASLT_MATMUL_DESC_TRANSA, &opa, sizeof(opa)));
+      DIE_LT(hipblasLtMatmulDescSetAttribute(pl.desc, HIPBLASLT_MATMUL_DESC_TRANSB, &opb, sizeof(opb)));
+      DIE_TRY(mk_layout(&pl.a, HIP_R_16F, ta ? k : m, ta ? m : k, lda, sa));
+      DIE_TRY(mk_layout(&pl.b, HIP_R_16F, k, n, ldb, sb));
+      DIE_TRY(mk_layout(&pl.d, HIP_R_32F, m, n, ldd, sd));
+      hipblasLtMatmulPreference_t pref = nullptr;
+      DIE_LT(hipblasLtMatmulPreferenceCreate(&pref));
+      const uint64_t wmax = (uint64_t)64 << 20;
+      hipblasLtMatmulHeuristicResult_t res[4];
+      int got = 0;
+      hipblasStatus_t hs = hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES,
+                                                                 &wmax, sizeof(wmax));
+      if (hs == HIPBLAS_STATUS_SUCCESS)
+        hs = hipblasLtMatmulAlgoGetHeuristic(L.h, pl.desc, pl.a, pl.b, pl.d, pl.d, pref, 4, res, &got);
+      (void)hipblasLtMatmulPreferenceDestroy(pref);
+      DIE_LT(hs);
+      int pick = -1;
+      for (int i = 0; i < got && pick < 0; ++i)
+        if (res[i].state == HIPBLAS_STATUS_SUCCESS) pick = i;
+      if (pick < 0)
+        return fail(DIE_E_HIP, "hipBLASLt has no binary16 GEMM for shape m=" + std::to_string(m) +
+                                   " n=" + std::to_string(n) + " k=" + std::to_string(k));
+      pl.algo = res[pick].algo;
+      pl.ws = res[pick].workspaceSize;
+      return DIE_OK;
+    }();
+    if (rc != DIE_OK) {
+      if (pl.a) (void)hipblasLtMatrixLayoutDestroy(pl.a);
+      if (pl.b) (void)hipblasLtMatrixLayoutDestroy(pl.b);
+      if (pl.d) (void)hipblasLtMatrixLayoutDestroy(pl.d);
+      if (pl.desc) (void)hipblasLtMatmulDescDestroy(pl.desc);
+      return rc;
+    }
+    it = L.plans.emplace(key, pl).first;
+  }
+  const LtPlan& pl = it->second;
+  if (pl.ws > L.ws.bytes) {
+    DIE_HIP(hipStreamSynchronize(st));  // the old workspace may still be in use
+    DIE_TRY(L.ws.alloc(pl.ws));
+  }
+  DIE_LT(hipblasLtMatmul(L.h, pl.desc, &alpha, A, pl.a, B, pl.b, &beta, D, pl.d, D, pl.d, &pl.algo,
+                         pl.ws ? L.ws.p : nullptr, pl.ws, st));
+  return DIE_OK;
+}
+
 // C = alpha op(A) op(B) + beta C, column-major complex in the precision of T (matrix cores).
 template <class T>
 rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, cd alpha,
@@ -1083,6 +1194,59 @@ template <class T> int upload(const die::la::Mat& M, void* d, hipStream_t st, st
   return DIE_OK;
 }
 
+// ---- binary16 planar GEMMs of the block Arnoldi step (complex64 basis).  Qs holds every
+// p-column block of the basis planar in binary16 (n x 2p: real parts, then imaginary parts), so
+// that Q^H W and W -= Q H are real GEMMs on the binary16 matrix cores with FP32 accumulation.
+constexpr size_t kHalfProjPartial = (size_t)1 << 25;  // FP32 values of the projection's chunk products
+
+// Binary16 planar copy of the new basis block X (n x p complex64) into its place in Qs.
+template <class T>
+int half_shadow(const c2<T>* X, size_t n, int p, _Float16* Qsj, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    DIE_HIP(die::launch_planar_split(X, n, n, p, nullptr, Qsj, n, st));
+    return DIE_OK;
+  } else {
+    return fail(DIE_E_INVALID, "binary16 GEMMs need a complex64 basis");
+  }
+}
+
+// Chunks of the projection's inner dimension K = n: a power of two that keeps K / nch >= 512,
+// the chunk products within kHalfProjPartial and about 1024 output tiles in flight.
+int half_chunks(size_t K, int rows, int cols) {
+  const size_t tiles = (size_t)((rows + 255) / 256) * (size_t)((cols + 255) / 256);
+  for (int cnum = 256; cnum >= 2; cnum /= 2)
+    if (K % cnum == 0 && K / cnum >= 512 && (size_t)rows * cols * cnum <= kHalfProjPartial && tiles * cnum <= 1024)
+      return cnum;
+  return 1;
+}
+
+// One block classical Gram-Schmidt pass of W (n x p complex64) against the first nq basis
+// columns: H = Q^H W (nq x p, complex64 holding binary16-rounded values) and W -= Q H, both
+// as binary16 GEMMs on the planar copies (chunked over K for the projection, in fixed order).
+template <class T>
+int half_block_cgs(die_te_ctx* c, const _Float16* Qs, c2<T>* W, size_t n, int nq, int p, float* Ws, _Float16* Wh,
+                   float* Cpart, c2<T>* H, _Float16* Hb, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    const int M = 2 * nq, P2 = 2 * p;
+    DIE_HIP(die::launch_planar_split(W, n, n, p, Ws, Wh, n, st));
+    const int nch = half_chunks(n, M, P2);
+    const int64_t ck = (int64_t)(n / nch);
+    DIE_TRY(lt_gemm(c, true, M, P2, (int)ck, 1.0f, Qs, (int64_t)n, ck, Wh, (int64_t)n, ck, 0.0f, Cpart, M,
+                    (int64_t)M * P2, nch, st));
+    DIE_HIP(die::launch_planar_combine(Cpart, nch, nq, p, H, Hb, st));
+    {
+      // flops 8 n p nq; operands: Qs (n x 2nq binary16) and Hb read, Ws (n x 2p FP32) read and written
+      ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq,
+                     2.0 * n * M + 8.0 * n * P2 + 2.0 * M * P2);
+      DIE_TRY(lt_gemm(c, false, (int)n, P2, M, -1.0f, Qs, (int64_t)n, 0, Hb, M, 0, 1.0f, Ws, (int64_t)n, 0, 1, st));
+    }
+    DIE_HIP(die::launch_planar_merge(Ws, n, n, p, W, n, st));
+    return DIE_OK;
+  } else {
+    return fail(DIE_E_INVALID, "binary16 GEMMs need a complex64 basis");
+  }
+}
+
 // Restarted block GMRES(m) (Section 4's GMRES applied to all right-hand sides of an object
 // at once): per object, the active residuals (normalised) span the first block through a
 // rank-revealing (pivoted) Cholesky QR; block Arnoldi with CGS2 as GEMMs and CholQR2 for each
@@ -1131,6 +1295,18 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(idxd.alloc(rpo * sizeof(int)));
   DIE_TRY(infod.alloc(sizeof(int)));
   DIE_TRY(scl.alloc(rpo * sizeof(double)));
+  // binary16 planar GEMMs (complex64 only): the basis shadow Qs (block j planar, n x 2p), W planar
+  // in FP32 and binary16, the chunk products of the projection and the real update matrix Hb
+  const bool hgemm = std::is_same<T, float>::value && o.block == 2;
+  DBuf Qs, Wsb, Whb, Cpart, Hbh;
+  if (hgemm) {
+    if (n % 2) return fail(DIE_E_INVALID, "block = 2 needs an even vector length");
+    DIE_TRY(Qs.alloc((size_t)(m + 1) * 2 * rpo * n * sizeof(_Float16)));
+    DIE_TRY(Wsb.alloc((size_t)2 * rpo * n * sizeof(float)));
+    DIE_TRY(Whb.alloc((size_t)2 * rpo * n * sizeof(_Float16)));
+    DIE_TRY(Cpart.alloc(kHalfProjPartial * sizeof(float)));
+    DIE_TRY(Hbh.alloc((size_t)2 * m * rpo * 2 * rpo * sizeof(_Float16)));
+  }
   DIE_TRY(Uq.alloc((size_t)die::kPanelMaxRows * die::kPanelMaxCols * sizeof(double2)));  // panel reflectors
   DIE_TRY(sq.alloc(die::kPanelMaxCols * sizeof(double)));
   if (defl) {
@@ -1260,6 +1436,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         S0 = S;
       }
       DIE_HIP((die::launch_scale<double, T>(ra, n, vb, n, ones.as<double>(), 0, n, p, nullptr, st)));
+      if (hgemm) DIE_TRY(half_shadow<T>(vb, n, p, Qs.as<_Float16>(), st));
       // ---- block Arnoldi: H ((m+1) p x m p, on the device in the basis precision, leading
       // dimension ldhp), CGS2 as GEMMs, CholQR2 of every new block
       const int ldhp = (m + 1) * p;
@@ -1281,8 +1458,15 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         const int nq = (j + 1) * p;
         c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the projections (nq x p each)
         for (int rep = 0; rep < npass; ++rep) {
+          if (hgemm) {
+            DIE_TRY(half_block_cgs<T>(c, Qs.as<_Float16>(), W, n, nq, p, Wsb.as<float>(), Whb.as<_Float16>(),
+                                      Cpart.as<float>(), hc[rep], Hbh.as<_Float16>(), st));
+            continue;
+          }
           DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, hc[rep], st));
-          ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq);
+          // flops 8 n p nq; operands: Q (n x nq) read, W (n x p) read and written, H (nq x p) read
+          ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq,
+                         (double)sizeof(c2<T>) * ((double)n * (nq + 2.0 * p) + (double)nq * p));
           DIE_TRY(gemm_update_long<T>(bh, ni, p, nq, vb, ni, hc[rep], nq, W, ni));
         }
         // column block j of H: the sum of the projections
@@ -1309,6 +1493,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         }
         DIE_TRY(upload<T>(la::upper_inverse(Q2), sm.p, st, stage));
         DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
+        if (hgemm) DIE_TRY(half_shadow<T>(W, n, p, Qs.as<_Float16>() + (size_t)(j + 1) * 2 * p * n, st));
         Mat Hs(p, p);  // H(j+1, j) = Q2 Q1
         for (int jj = 0; jj < p; ++jj)
           for (int i = 0; i <= jj; ++i) {
@@ -1559,9 +1744,10 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   hipStream_t st = (hipStream_t)stream;
   if (o.mixed < 0 || o.mixed > 2) return fail(DIE_E_INVALID, "mixed must be 0, 1 or 2");
   if (o.mixed == 2 && o.orth != 1) return fail(DIE_E_INVALID, "mixed = 2 (binary16 basis) needs orth = 1");
-  if (o.block != 0 && o.block != 1) return fail(DIE_E_INVALID, "block must be 0 or 1");
+  if (o.block < 0 || o.block > 2) return fail(DIE_E_INVALID, "block must be 0, 1 or 2");
   if (o.block) {
     if (o.mixed == 2) return fail(DIE_E_INVALID, "block GMRES needs mixed = 0 or 1");
+    if (o.block == 2 && o.mixed != 1) return fail(DIE_E_INVALID, "block = 2 (binary16 GEMMs) needs mixed = 1");
     if (o.mixed) return block_gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
     return block_gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
   }
@@ -1696,6 +1882,7 @@ int die_te_profile(die_te_ctx* c, int enable) {
     for (size_t& u : c->prof_used) u = 0;
     for (auto& sn : c->prof_seen) sn = 0;
     for (double& b : c->prof_bytes) b = 0;
+    for (double& b : c->prof_mem) b = 0;
   }
   return DIE_OK;
 }
@@ -1718,6 +1905,14 @@ int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long*
   }
   *launches = (long long)u;
   *total_ms = tot;
+  return DIE_OK;
+}
+
+int die_te_profile_mem(die_te_ctx* c, int kind, double* mem_bytes) {
+  die_host::last_error().clear();
+  DIE_TRY(check_ctx(c));
+  if (kind < 0 || kind > 3 || !mem_bytes) return fail(DIE_E_INVALID, "bad profile kind or null output");
+  *mem_bytes = c->prof_mem[kind];
   return DIE_OK;
 }
 

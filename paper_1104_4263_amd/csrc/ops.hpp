@@ -105,6 +105,19 @@ constexpr int kPanelMaxRows = 2 * kPanelMaxCols;
 hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p, double2* B, int ldb, int k,
                                       double2* U, double* s, hipStream_t st);
 
+// Planar binary16 GEMM path of the block Arnoldi step (complex64 blocks, n even).
+// launch_planar_split: X (n x p complex, leading dimension ldx) to Xs (n x 2p FP32: real parts,
+// then imaginary parts; leading dimension ldo) and/or Xh (the same in binary16); either may be null.
+hipError_t launch_planar_split(const float2* X, size_t ldx, size_t n, int p, float* Xs, _Float16* Xh, size_t ldo,
+                               hipStream_t st);
+// launch_planar_merge: Xs (planar FP32, leading dimension lds) back to X (interleaved).
+hipError_t launch_planar_merge(const float* Xs, size_t lds, size_t n, int p, float2* X, size_t ldx, hipStream_t st);
+// launch_planar_combine: H (nq x p complex, leading dimension nq) = Q^H W from nch chunk products
+// C_b = Qs^T Ws (2nq x 2p FP32, leading dimension 2nq, stride 4 nq p), summed in chunk order and
+// rounded to binary16; Hb (2nq x 2p binary16, leading dimension 2nq) the real matrix with
+// Ws -= Qs Hb equal to W -= Q H.  Qs holds each p-column block of Q planar.
+hipError_t launch_planar_combine(const float* C, int nch, int nq, int p, float2* H, _Float16* Hb, hipStream_t st);
+
 // ----------------------------------------------------------------- GMRES state
 struct GmresState {
   int j;         // iterations done in the current cycle

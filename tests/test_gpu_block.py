@@ -1,6 +1,7 @@
-"""Block GMRES (solve option block=1): all right-hand sides of an object share one block
-Krylov space.  Solutions against dense LU and against the per-rhs solver, the regularized
-and deflated variants, a rank-deficient set of incident fields, and the product savings."""
+"""Block GMRES (solve option block=1, and block=2 with its Gram-Schmidt GEMMs in binary16):
+all right-hand sides of an object share one block Krylov space.  Solutions against dense LU
+and against the per-rhs solver, the regularized and deflated variants, a rank-deficient set
+of incident fields, and the product savings."""
 import numpy as np
 import pytest
 import torch
@@ -74,9 +75,58 @@ def test_block_rank_deficient_fields_and_warm_start():
     assert rc2 == 0 and all(x["iters"] == 0 for x in info2)
 
 
+@pytest.mark.parametrize("orth", [0, 1])
+@pytest.mark.parametrize("eps_obj,reg,defl", [
+    (4.0 + 0j, False, 0), (-2.5 + 0.2j, True, 8), (16.0 + 0j, False, 6), (-16 + 1.5j, True, 10),
+])
+def test_block_half_gemm_matches_lu(eps_obj, reg, defl, orth):
+    """block=2: the projections and updates on binary16 planar copies; the FP64 restarts still
+    take every right-hand side to the same true residual and LU solution as block=1."""
+    say(f"block GMRES binary16 GEMMs eps={eps_obj} reg={reg} defl={defl} orth={orth}")
+    g = centred_grid(24, 1.0, ny=20)
+    eps = cylinder(g, 0.35, eps_obj)
+    b = np.stack([plane_wave(g, p) for p in (0.3, 1.2, 2.1, 4.0)])
+    u_lu = op.solve_dense(g, eps, b)
+    s = api.Solver.from_grid(g, eps, regularize=reg, deflate_k=defl, seed=3)
+    u, rc, info = s.solve(dev(b), restart=20, max_iters=4000, tol=1e-8, mixed=1, block=2, orth=orth)
+    assert rc == 0
+    uh = host(u)
+    for r in range(b.shape[0]):
+        assert info[r]["rel_res_true"] <= 1e-8
+        assert op.relative_residual(g, eps, uh[r], b[r]) <= 1.02e-8
+        assert rel(uh[r], u_lu[r]) < 2e-5
+    say(f"  block steps {[x['iters'] for x in info]}, cycles {[x['cycles'] for x in info]}")
+
+
+@pytest.mark.parametrize("n_side,nobj,nang", [(32, 3, 8), (64, 2, 16)])
+def test_block_half_gemm_multi_object_agrees(n_side, nobj, nang):
+    """block=2 on random-field objects with the projection split into several K chunks
+    (vector lengths 2048 and 8192): same solutions as the per-rhs solver, to the tolerance."""
+    objs = [random_field_object(n_side, seed=7100 + i) for i in range(nobj)]
+    g = objs[0][0]
+    eps = np.stack([e for _, e in objs])
+    psis = [2 * np.pi * j / nang for j in range(nang)]
+    b = np.concatenate([np.stack([plane_wave(g, p) for p in psis])] * nobj)
+    s = api.Solver.from_grid(g, eps)
+    say(f"block=2 {n_side}^2 x {nobj} objects x {nang} angles")
+    ub, rcb, ib = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=1, block=2, orth=1)
+    up, rcp, ip = s.solve(dev(b), restart=30, max_iters=20000, tol=1e-8, mixed=1)
+    assert rcb == 0 and rcp == 0
+    uh = host(ub)
+    for r in range(b.shape[0]):
+        assert ib[r]["rel_res_true"] <= 1e-8
+        assert op.relative_residual(g, eps[r // nang], uh[r], b[r]) <= 1.02e-8
+    assert rel(uh, host(up)) < 1e-6
+    say(f"  block steps {sorted(set(x['iters'] for x in ib))}, cycles {sorted(set(x['cycles'] for x in ib))}")
+
+
 def test_block_option_validation():
     g = centred_grid(16, 1.0)
     s = api.Solver.from_grid(g, cylinder(g, 0.3, 4.0))
     b = dev(plane_wave(g, 0.0))
     with pytest.raises(DieTeError):
         s.solve(b, block=1, mixed=2, orth=1)
+    with pytest.raises(DieTeError):
+        s.solve(b, block=2, mixed=0)
+    with pytest.raises(DieTeError):
+        s.solve(b, block=3, mixed=1)
