@@ -1211,33 +1211,35 @@ int half_shadow(const c2<T>* X, size_t n, int p, _Float16* Qsj, hipStream_t st) 
 }
 
 // Chunks of the projection's inner dimension K = n: a power of two that keeps K / nch >= 512,
-// the chunk products within kHalfProjPartial and about 1024 output tiles in flight.
+// the chunk products within kHalfProjPartial and about 512 output tiles in flight.
 int half_chunks(size_t K, int rows, int cols) {
   const size_t tiles = (size_t)((rows + 255) / 256) * (size_t)((cols + 255) / 256);
   for (int cnum = 256; cnum >= 2; cnum /= 2)
-    if (K % cnum == 0 && K / cnum >= 512 && (size_t)rows * cols * cnum <= kHalfProjPartial && tiles * cnum <= 1024)
+    if (K % cnum == 0 && K / cnum >= 512 && (size_t)rows * cols * cnum <= kHalfProjPartial && tiles * cnum <= 512)
       return cnum;
   return 1;
 }
 
-// One block classical Gram-Schmidt pass of W (n x p complex64) against the first nq basis
-// columns: H = Q^H W (nq x p, complex64 holding binary16-rounded values) and W -= Q H, both
-// as binary16 GEMMs on the planar copies (chunked over K for the projection, in fixed order).
+// npass block classical Gram-Schmidt passes of W (n x p complex64) against the first nq basis
+// columns: per pass H_pass = Q^H W (nq x p, complex64 holding binary16-rounded values) and
+// W -= Q H_pass, both as binary16 GEMMs on the planar copies (the projection chunked over K, its
+// chunk products summed in fixed order).  W stays planar in FP32 between the passes; the
+// binary16 copy that the next projection reads is made from it.
 template <class T>
-int half_block_cgs(die_te_ctx* c, const _Float16* Qs, c2<T>* W, size_t n, int nq, int p, float* Ws, _Float16* Wh,
-                   float* Cpart, c2<T>* H, _Float16* Hb, hipStream_t st) {
+int half_block_cgs(die_te_ctx* c, const _Float16* Qs, c2<T>* W, size_t n, int nq, int p, int npass, float* Ws,
+                   _Float16* Wh, float* Cpart, c2<T>* const* H, _Float16* Hb, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
     const int M = 2 * nq, P2 = 2 * p;
     DIE_HIP(die::launch_planar_split(W, n, n, p, Ws, Wh, n, st));
     const int nch = half_chunks(n, M, P2);
     const int64_t ck = (int64_t)(n / nch);
-    DIE_TRY(lt_gemm(c, true, M, P2, (int)ck, 1.0f, Qs, (int64_t)n, ck, Wh, (int64_t)n, ck, 0.0f, Cpart, M,
-                    (int64_t)M * P2, nch, st));
-    DIE_HIP(die::launch_planar_combine(Cpart, nch, nq, p, H, Hb, st));
-    {
+    for (int pass = 0; pass < npass; ++pass) {
+      if (pass > 0) DIE_HIP(die::launch_planar_to_half(Ws, n, n, p, Wh, st));
+      DIE_TRY(lt_gemm(c, true, M, P2, (int)ck, 1.0f, Qs, (int64_t)n, ck, Wh, (int64_t)n, ck, 0.0f, Cpart, M,
+                      (int64_t)M * P2, nch, st));
+      DIE_HIP(die::launch_planar_combine(Cpart, nch, nq, p, H[pass], Hb, st));
       // flops 8 n p nq; operands: Qs (n x 2nq binary16) and Hb read, Ws (n x 2p FP32) read and written
-      ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq,
-                     2.0 * n * M + 8.0 * n * P2 + 2.0 * M * P2);
+      ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq, 2.0 * n * M + 8.0 * n * P2 + 2.0 * M * P2);
       DIE_TRY(lt_gemm(c, false, (int)n, P2, M, -1.0f, Qs, (int64_t)n, 0, Hb, M, 0, 1.0f, Ws, (int64_t)n, 0, 1, st));
     }
     DIE_HIP(die::launch_planar_merge(Ws, n, n, p, W, n, st));
@@ -1457,12 +1459,10 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_TRY(apply_M<T>(c, reg, z, reg ? Tm.as<c2<T>>() : nullptr, W, p, nullptr, st, 0, ob));
         const int nq = (j + 1) * p;
         c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the projections (nq x p each)
-        for (int rep = 0; rep < npass; ++rep) {
-          if (hgemm) {
-            DIE_TRY(half_block_cgs<T>(c, Qs.as<_Float16>(), W, n, nq, p, Wsb.as<float>(), Whb.as<_Float16>(),
-                                      Cpart.as<float>(), hc[rep], Hbh.as<_Float16>(), st));
-            continue;
-          }
+        if (hgemm)
+          DIE_TRY(half_block_cgs<T>(c, Qs.as<_Float16>(), W, n, nq, p, npass, Wsb.as<float>(), Whb.as<_Float16>(),
+                                    Cpart.as<float>(), hc, Hbh.as<_Float16>(), st));
+        for (int rep = 0; rep < npass && !hgemm; ++rep) {
           DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, hc[rep], st));
           // flops 8 n p nq; operands: Q (n x nq) read, W (n x p) read and written, H (nq x p) read
           ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq,
@@ -1542,7 +1542,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_TRY(upload<T>(Ys, sm.p, st, stage));
       }
       c2<T>* tb = Tb.as<c2<T>>();
-      DIE_BLAS(gemm<T>(bh, kN, kN, ni, k, nc, 1.0, vb, ni, sm.as<c2<T>>(), nc, 0.0, tb, ni));
+      DIE_TRY(gemm_rows_long<T>(bh, ni, k, nc, 1.0, vb, ni, sm.as<c2<T>>(), nc, 0.0, tb, ni));
       if (defl)
         DIE_TRY(apply_pinv<T>(c, tb, tb, k, part.as<double2>(), coef.as<double2>(), cnt.as<int>(), nullptr, st, k, ob));
       DIE_HIP(hipMemcpyAsync(idxd.p, K.data(), k * sizeof(int), hipMemcpyHostToDevice, st));

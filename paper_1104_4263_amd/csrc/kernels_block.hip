@@ -16,7 +16,9 @@ namespace {
 
 constexpr int kPanelThreads = 1024;
 constexpr int kPanelWaves = kPanelThreads / 64;
-static_assert(kPanelMaxRows <= kPanelThreads, "the column norm takes one element per thread");
+constexpr int kColsPerWave = kPanelMaxCols / kPanelWaves;
+constexpr int kRowsPerLane = kPanelMaxRows / 64;
+static_assert(kPanelMaxCols % kPanelWaves == 0 && kPanelMaxRows % 64 == 0, "panel tiling");
 
 __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) {  // acc + conj(a) b
   acc.x = fma(a.x, b.x, acc.x);
@@ -30,68 +32,110 @@ __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) 
 // in place: R on and above the diagonal; the reflectors u_q (q < pc; u_q[i] = 0 for i < q) go to
 // U (rows x pc, column-major, leading dimension kPanelMaxRows) with scales s[q] = 2 / (u_q^H u_q)
 // (0 for a zero column).  The reflector P_q = I - s_q u_q u_q^H maps column q to -e^{i arg a} |x| e_q.
-// Per reflector: the column norm (all waves), then the update of the later columns (one wave per
-// column) while the reflector is exported; four barriers.
+// The panel lives in registers: wave w holds columns w, w + 16, w + 32, w + 48 (two rows per
+// lane).  Per reflector the wave owning column q (which already carries P_0 .. P_{q-1}) forms
+// u_q and publishes it in one of two LDS slots; after one barrier every wave applies it to its
+// later columns.  The slots alternate, so a slot is rewritten only after the barrier that
+// follows every read of it.
 __global__ void __launch_bounds__(kPanelThreads)
 k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, double2* __restrict__ U,
            double* __restrict__ s) {
-  __shared__ double2 A[kPanelMaxRows * kPanelMaxCols];  // column-major, leading dimension kPanelMaxRows
-  __shared__ double red[kPanelWaves];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int e = t; e < kPanelMaxRows * pc; e += kPanelThreads) {
-    const int i = e % kPanelMaxRows, j = e / kPanelMaxRows;
-    A[e] = i < rows ? H[(size_t)(c0 + j) * ld + r0 + i] : make_double2(0.0, 0.0);
+  __shared__ double2 ub[2][kPanelMaxRows];
+  __shared__ double sb[2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double2 x[kColsPerWave][kRowsPerLane];
+#pragma unroll
+  for (int c = 0; c < kColsPerWave; ++c) {
+    const int j = w + kPanelWaves * c;
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) {
+      const int i = lane + 64 * r;
+      x[c][r] = (j < pc && i < rows) ? H[(size_t)(c0 + j) * ld + r0 + i] : make_double2(0.0, 0.0);
+    }
   }
-  __syncthreads();
   for (int q = 0; q < pc; ++q) {
-    double2* x = A + (size_t)q * kPanelMaxRows;
-    // |x[q:]|^2 (rows <= kPanelMaxRows <= kPanelThreads: one element per thread at most)
-    double sq = 0.0;
-    if (t >= q && t < rows) sq = fma(x[t].x, x[t].x, x[t].y * x[t].y);
-    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
-    if (lane == 0) red[w] = sq;
-    __syncthreads();  // (1) partial norms in red
-    double nrm2 = 0.0;
-    for (int k = 0; k < kPanelWaves; ++k) nrm2 += red[k];
-    const double nrm = sqrt(nrm2);
-    const double2 a = x[q];
-    const double aa = sqrt(a.x * a.x + a.y * a.y);
-    const double2 ph = aa > 0.0 ? make_double2(a.x / aa, a.y / aa) : make_double2(1.0, 0.0);
-    // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
-    const double uu = 2.0 * nrm * (nrm + aa);
-    const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
-    __syncthreads();  // (2) everyone has read x[q] and red
-    if (t == 0) {
-      x[q] = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
-      s[q] = sc;
-    }
-    __syncthreads();  // (3) the reflector u = x[q:] is in place
-    if (t < rows) U[(size_t)q * kPanelMaxRows + t] = t >= q ? x[t] : make_double2(0.0, 0.0);
-    // apply P_q to columns q+1 .. pc-1: y -= sc u (u^H y); one wave per column
-    for (int j = q + 1 + w; j < pc; j += kPanelWaves) {
-      double2* y = A + (size_t)j * kPanelMaxRows;
-      double2 d = make_double2(0.0, 0.0);
-      for (int i = q + lane; i < rows; i += 64) d = cfma_conj(x[i], y[i], d);
-      for (int off = 32; off > 0; off >>= 1) {
-        d.x += __shfl_xor(d.x, off);
-        d.y += __shfl_xor(d.y, off);
+    const int buf = q & 1;
+    if (w == q % kPanelWaves) {  // the owner of column q (wave-uniform)
+      const int cq = q / kPanelWaves;
+#pragma unroll
+      for (int c = 0; c < kColsPerWave; ++c) {
+        if (c != cq) continue;  // compile-time register indices only
+        double sq = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRowsPerLane; ++r) {
+          const int i = lane + 64 * r;
+          if (i >= q && i < rows) sq = fma(x[c][r].x, x[c][r].x, fma(x[c][r].y, x[c][r].y, sq));
+        }
+        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+        const double nrm = sqrt(sq);
+        double2 aq = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < kRowsPerLane; ++r)
+          if (q / 64 == r) aq = x[c][r];
+        const double2 a = make_double2(__shfl(aq.x, q & 63), __shfl(aq.y, q & 63));
+        const double aa = sqrt(a.x * a.x + a.y * a.y);
+        const double2 ph = aa > 0.0 ? make_double2(a.x / aa, a.y / aa) : make_double2(1.0, 0.0);
+        // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
+        const double uu = 2.0 * nrm * (nrm + aa);
+        const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
+#pragma unroll
+        for (int r = 0; r < kRowsPerLane; ++r) {
+          const int i = lane + 64 * r;
+          double2 u = make_double2(0.0, 0.0);
+          if (i == q) u = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
+          else if (i > q && i < rows) u = x[c][r];
+          ub[buf][i] = u;
+          if (i < rows) U[(size_t)q * kPanelMaxRows + i] = u;
+          // column q becomes R's: -e^{i arg a} |x| on the diagonal, zeros below
+          if (i == q) x[c][r] = make_double2(-ph.x * nrm, -ph.y * nrm);
+          else if (i > q) x[c][r] = make_double2(0.0, 0.0);
+        }
+        if (lane == 0) {
+          sb[buf] = sc;
+          s[q] = sc;
+        }
       }
-      const double2 f = make_double2(sc * d.x, sc * d.y);
-      for (int i = q + lane; i < rows; i += 64) {
-        const double2 u = x[i];
-        y[i].x -= u.x * f.x - u.y * f.y;
-        y[i].y -= u.x * f.y + u.y * f.x;
+    }
+    __syncthreads();
+    const double sc = sb[buf];
+    double2 u[kRowsPerLane];
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) u[r] = ub[buf][lane + 64 * r];
+    // apply P_q to this wave's columns j > q: y -= sc u (u^H y), the reductions interleaved
+    double2 d[kColsPerWave];
+#pragma unroll
+    for (int c = 0; c < kColsPerWave; ++c) {
+      d[c] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < kRowsPerLane; ++r) d[c] = cfma_conj(u[r], x[c][r], d[c]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+      for (int c = 0; c < kColsPerWave; ++c) {
+        d[c].x += __shfl_xor(d[c].x, off);
+        d[c].y += __shfl_xor(d[c].y, off);
       }
     }
-    __syncthreads();  // (4) every later column updated and u exported: column q becomes R's
-    // column q: -e^{i arg a} |x| on the diagonal, zeros below (read again only at the end)
-    if (t == 0) x[q] = make_double2(-ph.x * nrm, -ph.y * nrm);
-    if (t > q && t < rows) x[t] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < kColsPerWave; ++c) {
+      const int j = w + kPanelWaves * c;
+      if (j <= q || j >= pc) continue;
+      const double2 f = make_double2(sc * d[c].x, sc * d[c].y);
+#pragma unroll
+      for (int r = 0; r < kRowsPerLane; ++r) {
+        x[c][r].x -= u[r].x * f.x - u[r].y * f.y;
+        x[c][r].y -= u[r].x * f.y + u[r].y * f.x;
+      }
+    }
   }
-  __syncthreads();
-  for (int e = t; e < kPanelMaxRows * pc; e += kPanelThreads) {
-    const int i = e % kPanelMaxRows, j = e / kPanelMaxRows;
-    if (i < rows) H[(size_t)(c0 + j) * ld + r0 + i] = A[e];
+#pragma unroll
+  for (int c = 0; c < kColsPerWave; ++c) {
+    const int j = w + kPanelWaves * c;
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) {
+      const int i = lane + 64 * r;
+      if (j < pc && i < rows) H[(size_t)(c0 + j) * ld + r0 + i] = x[c][r];
+    }
   }
 }
 
@@ -178,6 +222,16 @@ __global__ void k_planar_merge(const float* __restrict__ Xs, size_t lds, size_t 
   *reinterpret_cast<float4*>(X + col * ldx + r) = make_float4(re.x, im.x, re.y, im.y);
 }
 
+// Binary16 copy of a planar FP32 block (n x 2p, both leading dimensions ld), two values a thread.
+__global__ void k_planar_to_half(const float* __restrict__ Xs, size_t ld, size_t n2, int p2, _Float16* __restrict__ Xh) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n2 * (size_t)p2) return;
+  const size_t col = e / n2, r = 2 * (e - col * n2);
+  const float2 v = *reinterpret_cast<const float2*>(Xs + col * ld + r);
+  Xh[col * ld + r] = (_Float16)v.x;
+  Xh[col * ld + r + 1] = (_Float16)v.y;
+}
+
 // One thread per entry (q, k) of the complex projection H = Q^H W (nq x p): sums the nch chunk
 // products C_b = Qs^T Ws (2nq x 2p each, leading dimension 2nq) in chunk order, then
 //   Re H = Qr^T Wr + Qi^T Wi,  Im H = Qr^T Wi - Qi^T Wr,
@@ -240,6 +294,14 @@ hipError_t launch_planar_merge(const float* Xs, size_t lds, size_t n, int p, flo
   const size_t tot = n / 2 * (size_t)p;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_planar_merge, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Xs, lds, n / 2, p, X, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_planar_to_half(const float* Xs, size_t ld, size_t n, int p, _Float16* Xh, hipStream_t st) {
+  if (n % 2 || p < 1 || ld < n || ld % 2) return hipErrorInvalidValue;
+  const size_t tot = n / 2 * (size_t)(2 * p);
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_planar_to_half, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Xs, ld, n / 2, 2 * p, Xh);
   return hipGetLastError();
 }
 

@@ -112,6 +112,9 @@ hipError_t launch_planar_split(const float2* X, size_t ldx, size_t n, int p, flo
                                hipStream_t st);
 // launch_planar_merge: Xs (planar FP32, leading dimension lds) back to X (interleaved).
 hipError_t launch_planar_merge(const float* Xs, size_t lds, size_t n, int p, float2* X, size_t ldx, hipStream_t st);
+// launch_planar_to_half: the binary16 copy of a planar FP32 block (n x 2p, leading dimension ld;
+// n and ld even).
+hipError_t launch_planar_to_half(const float* Xs, size_t ld, size_t n, int p, _Float16* Xh, hipStream_t st);
 // launch_planar_combine: H (nq x p complex, leading dimension nq) = Q^H W from nch chunk products
 // C_b = Qs^T Ws (2nq x 2p FP32, leading dimension 2nq, stride 4 nq p), summed in chunk order and
 // rounded to binary16; Hb (2nq x 2p binary16, leading dimension 2nq) the real matrix with

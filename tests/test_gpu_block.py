@@ -98,6 +98,18 @@ def test_block_half_gemm_matches_lu(eps_obj, reg, defl, orth):
     say(f"  block steps {[x['iters'] for x in info]}, cycles {[x['cycles'] for x in info]}")
 
 
+def test_block_half_gemm_odd_grid():
+    """block=2 on a 15 x 13 grid: a vector length (390) that is even but not a multiple of 4."""
+    g = centred_grid(15, 1.0, ny=13)
+    eps = cylinder(g, 0.3, 4.0 + 0.5j)
+    b = np.stack([plane_wave(g, p) for p in (0.1, 1.7, 3.3)])
+    u_lu = op.solve_dense(g, eps, b)
+    s = api.Solver.from_grid(g, eps)
+    u, rc, info = s.solve(dev(b), restart=12, max_iters=2000, tol=1e-8, mixed=1, block=2, orth=0)
+    assert rc == 0
+    assert rel(host(u), u_lu) < 2e-5
+
+
 @pytest.mark.parametrize("n_side,nobj,nang", [(32, 3, 8), (64, 2, 16)])
 def test_block_half_gemm_multi_object_agrees(n_side, nobj, nang):
     """block=2 on random-field objects with the projection split into several K chunks
