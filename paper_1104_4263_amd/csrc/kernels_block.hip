@@ -16,9 +16,28 @@ namespace {
 
 constexpr int kPanelThreads = 1024;
 constexpr int kPanelWaves = kPanelThreads / 64;
-constexpr int kColsPerWave = kPanelMaxCols / kPanelWaves;
-constexpr int kRowsPerLane = kPanelMaxRows / 64;
-static_assert(kPanelMaxCols % kPanelWaves == 0 && kPanelMaxRows % 64 == 0, "panel tiling");
+// A 16-lane row of a wave holds one column, 8 rows a lane (row i at lane i % 16, slot i / 16):
+// a column's inner product is 8 local multiply-adds and a 4-step DPP butterfly in the row.
+constexpr int kRowsPerLane = kPanelMaxRows / 16;
+static_assert(kPanelMaxCols == 4 * kPanelWaves && kPanelMaxRows % 16 == 0, "panel tiling");
+
+// DPP move of a double within each row of 16 lanes (CTRL: a DPP16 row or quad permutation).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffu), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Sum over the 16 lanes of each row, left in all of them: row mirror (i <-> 15 - i), half-row
+// mirror (i <-> 7 - i), then the quad permutations [2,3,0,1] and [1,0,3,2].
+__device__ __forceinline__ double sum16(double v) {
+  v += dpp_f64<0x140>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x4e>(v);
+  v += dpp_f64<0xb1>(v);
+  return v;
+}
 
 __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) {  // acc + conj(a) b
   acc.x = fma(a.x, b.x, acc.x);
@@ -32,65 +51,68 @@ __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) 
 // in place: R on and above the diagonal; the reflectors u_q (q < pc; u_q[i] = 0 for i < q) go to
 // U (rows x pc, column-major, leading dimension kPanelMaxRows) with scales s[q] = 2 / (u_q^H u_q)
 // (0 for a zero column).  The reflector P_q = I - s_q u_q u_q^H maps column q to -e^{i arg a} |x| e_q.
-// The panel lives in registers: wave w holds columns w, w + 16, w + 32, w + 48 (two rows per
-// lane).  Per reflector the wave owning column q (which already carries P_0 .. P_{q-1}) forms
-// u_q and publishes it in one of two LDS slots; after one barrier every wave applies it to its
-// later columns.  The slots alternate, so a slot is rewritten only after the barrier that
-// follows every read of it.
+// The panel lives in registers: column j in row j / 16 of wave j % 16.  Per reflector the row
+// holding column q (which already carries P_0 .. P_{q-1}) forms u_q and publishes it in one of
+// two LDS slots; after one barrier every row applies it to its column if that lies right of q.
+// The slots alternate, so a slot is rewritten only after the barrier that follows its reads.
 __global__ void __launch_bounds__(kPanelThreads)
 k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, double2* __restrict__ U,
            double* __restrict__ s) {
   __shared__ double2 ub[2][kPanelMaxRows];
   __shared__ double sb[2];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double2 x[kColsPerWave][kRowsPerLane];
+  const int g = lane >> 4, l16 = lane & 15;
+  const int j = w + kPanelWaves * g;  // this row's column
+  double2 x[kRowsPerLane];
 #pragma unroll
-  for (int c = 0; c < kColsPerWave; ++c) {
-    const int j = w + kPanelWaves * c;
-#pragma unroll
-    for (int r = 0; r < kRowsPerLane; ++r) {
-      const int i = lane + 64 * r;
-      x[c][r] = (j < pc && i < rows) ? H[(size_t)(c0 + j) * ld + r0 + i] : make_double2(0.0, 0.0);
-    }
+  for (int t = 0; t < kRowsPerLane; ++t) {
+    const int i = l16 + 16 * t;
+    x[t] = (j < pc && i < rows) ? H[(size_t)(c0 + j) * ld + r0 + i] : make_double2(0.0, 0.0);
   }
   for (int q = 0; q < pc; ++q) {
     const int buf = q & 1;
-    if (w == q % kPanelWaves) {  // the owner of column q (wave-uniform)
-      const int cq = q / kPanelWaves;
+    if (w == q % kPanelWaves) {  // the wave holding column q (wave-uniform); its row q / 16 writes
+      const bool own = g == q / kPanelWaves;
+      double sq = 0.0;
 #pragma unroll
-      for (int c = 0; c < kColsPerWave; ++c) {
-        if (c != cq) continue;  // compile-time register indices only
-        double sq = 0.0;
+      for (int t = 0; t < kRowsPerLane; ++t) {
+        const int i = l16 + 16 * t;
+        if (i >= q && i < rows) sq = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, sq));
+      }
+      const double nrm = sqrt(sum16(sq));  // the norm of this row's column below q
+      double2 aq = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int r = 0; r < kRowsPerLane; ++r) {
-          const int i = lane + 64 * r;
-          if (i >= q && i < rows) sq = fma(x[c][r].x, x[c][r].x, fma(x[c][r].y, x[c][r].y, sq));
-        }
-        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
-        const double nrm = sqrt(sq);
-        double2 aq = make_double2(0.0, 0.0);
+      for (int t = 0; t < kRowsPerLane; ++t)
+        if (q / 16 == t) aq = x[t];
+      const int src = (q / kPanelWaves) * 16 + (q & 15);  // the lane holding row q of column q
+      const unsigned long long ax = __builtin_bit_cast(unsigned long long, aq.x);
+      const unsigned long long ay = __builtin_bit_cast(unsigned long long, aq.y);
+      const double2 a = make_double2(
+          __builtin_bit_cast(double, ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(ax >> 32), src)
+                                      << 32) |
+                                         (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(ax & 0xffffffffu), src)),
+          __builtin_bit_cast(double, ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(ay >> 32), src)
+                                      << 32) |
+                                         (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(ay & 0xffffffffu), src)));
+      const double aa = sqrt(a.x * a.x + a.y * a.y);
+      const double2 ph = aa > 0.0 ? make_double2(a.x / aa, a.y / aa) : make_double2(1.0, 0.0);
+      // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
+      const double uu = 2.0 * nrm * (nrm + aa);
+      const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
+      if (own) {
 #pragma unroll
-        for (int r = 0; r < kRowsPerLane; ++r)
-          if (q / 64 == r) aq = x[c][r];
-        const double2 a = make_double2(__shfl(aq.x, q & 63), __shfl(aq.y, q & 63));
-        const double aa = sqrt(a.x * a.x + a.y * a.y);
-        const double2 ph = aa > 0.0 ? make_double2(a.x / aa, a.y / aa) : make_double2(1.0, 0.0);
-        // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
-        const double uu = 2.0 * nrm * (nrm + aa);
-        const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
-#pragma unroll
-        for (int r = 0; r < kRowsPerLane; ++r) {
-          const int i = lane + 64 * r;
+        for (int t = 0; t < kRowsPerLane; ++t) {
+          const int i = l16 + 16 * t;
           double2 u = make_double2(0.0, 0.0);
           if (i == q) u = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
-          else if (i > q && i < rows) u = x[c][r];
+          else if (i > q && i < rows) u = x[t];
           ub[buf][i] = u;
           if (i < rows) U[(size_t)q * kPanelMaxRows + i] = u;
           // column q becomes R's: -e^{i arg a} |x| on the diagonal, zeros below
-          if (i == q) x[c][r] = make_double2(-ph.x * nrm, -ph.y * nrm);
-          else if (i > q) x[c][r] = make_double2(0.0, 0.0);
+          if (i == q) x[t] = make_double2(-ph.x * nrm, -ph.y * nrm);
+          else if (i > q) x[t] = make_double2(0.0, 0.0);
         }
-        if (lane == 0) {
+        if (l16 == 0) {
           sb[buf] = sc;
           s[q] = sc;
         }
@@ -99,89 +121,72 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
     __syncthreads();
     const double sc = sb[buf];
     double2 u[kRowsPerLane];
+    double2 d = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int r = 0; r < kRowsPerLane; ++r) u[r] = ub[buf][lane + 64 * r];
-    // apply P_q to this wave's columns j > q: y -= sc u (u^H y), the reductions interleaved
-    double2 d[kColsPerWave];
-#pragma unroll
-    for (int c = 0; c < kColsPerWave; ++c) {
-      d[c] = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int r = 0; r < kRowsPerLane; ++r) d[c] = cfma_conj(u[r], x[c][r], d[c]);
+    for (int t = 0; t < kRowsPerLane; ++t) {
+      u[t] = ub[buf][l16 + 16 * t];
+      d = cfma_conj(u[t], x[t], d);
     }
-    for (int off = 32; off > 0; off >>= 1) {
+    d.x = sum16(d.x);
+    d.y = sum16(d.y);
+    if (j > q && j < pc) {  // y -= sc u (u^H y)
+      const double2 f = make_double2(sc * d.x, sc * d.y);
 #pragma unroll
-      for (int c = 0; c < kColsPerWave; ++c) {
-        d[c].x += __shfl_xor(d[c].x, off);
-        d[c].y += __shfl_xor(d[c].y, off);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < kColsPerWave; ++c) {
-      const int j = w + kPanelWaves * c;
-      if (j <= q || j >= pc) continue;
-      const double2 f = make_double2(sc * d[c].x, sc * d[c].y);
-#pragma unroll
-      for (int r = 0; r < kRowsPerLane; ++r) {
-        x[c][r].x -= u[r].x * f.x - u[r].y * f.y;
-        x[c][r].y -= u[r].x * f.y + u[r].y * f.x;
+      for (int t = 0; t < kRowsPerLane; ++t) {
+        x[t].x -= u[t].x * f.x - u[t].y * f.y;
+        x[t].y -= u[t].x * f.y + u[t].y * f.x;
       }
     }
   }
 #pragma unroll
-  for (int c = 0; c < kColsPerWave; ++c) {
-    const int j = w + kPanelWaves * c;
-#pragma unroll
-    for (int r = 0; r < kRowsPerLane; ++r) {
-      const int i = lane + 64 * r;
-      if (j < pc && i < rows) H[(size_t)(c0 + j) * ld + r0 + i] = x[c][r];
-    }
+  for (int t = 0; t < kRowsPerLane; ++t) {
+    const int i = l16 + 16 * t;
+    if (j < pc && i < rows) H[(size_t)(c0 + j) * ld + r0 + i] = x[t];
   }
 }
 
 // Apply the panel's reflectors P_0, P_1, ..., P_{pc-1} (in that order) to rows r0 .. r0+rows of
-// the columns [cb, ce) of H and all k columns of B (leading dimension ldb): one wave per column.
+// the columns [cb, ce) of H and all k columns of B (leading dimension ldb): one 16-lane row per
+// column, 16 columns a workgroup.
 __global__ void __launch_bounds__(256)
 k_panel_apply(double2* __restrict__ H, int ld, double2* __restrict__ B, int ldb, int k, int r0, int rows, int pc,
               int cb, int ce, const double2* __restrict__ U, const double* __restrict__ s) {
-  const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l16 = threadIdx.x & 15;
+  const int col = blockIdx.x * 16 + (threadIdx.x >> 4);
   const int nh = ce - cb;
-  if (col >= nh + k) return;
-  double2* y = col < nh ? H + (size_t)(cb + col) * ld + r0 : B + (size_t)(col - nh) * ldb + r0;
-  constexpr int R = kPanelMaxRows / 64;  // rows per lane
-  double2 v[R];
+  const bool live = col < nh + k;  // the whole row of 16 lanes agrees; rows past the end idle
+  double2* y = !live ? nullptr : col < nh ? H + (size_t)(cb + col) * ld + r0 : B + (size_t)(col - nh) * ldb + r0;
+  double2 v[kRowsPerLane];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = lane + 64 * r;
-    v[r] = i < rows ? y[i] : make_double2(0.0, 0.0);
+  for (int t = 0; t < kRowsPerLane; ++t) {
+    const int i = l16 + 16 * t;
+    v[t] = live && i < rows ? y[i] : make_double2(0.0, 0.0);
   }
   for (int q = 0; q < pc; ++q) {
     const double2* u = U + (size_t)q * kPanelMaxRows;
-    double2 uq[R];
+    double2 uq[kRowsPerLane];
     double2 d = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = lane + 64 * r;
-      uq[r] = i < rows ? u[i] : make_double2(0.0, 0.0);
-      d = cfma_conj(uq[r], v[r], d);
+    for (int t = 0; t < kRowsPerLane; ++t) {
+      const int i = l16 + 16 * t;
+      uq[t] = i < rows ? u[i] : make_double2(0.0, 0.0);
+      d = cfma_conj(uq[t], v[t], d);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      d.x += __shfl_xor(d.x, off);
-      d.y += __shfl_xor(d.y, off);
-    }
+    d.x = sum16(d.x);
+    d.y = sum16(d.y);
     const double sc = s[q];
     const double2 f = make_double2(sc * d.x, sc * d.y);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      v[r].x -= uq[r].x * f.x - uq[r].y * f.y;
-      v[r].y -= uq[r].x * f.y + uq[r].y * f.x;
+    for (int t = 0; t < kRowsPerLane; ++t) {
+      v[t].x -= uq[t].x * f.x - uq[t].y * f.y;
+      v[t].y -= uq[t].x * f.y + uq[t].y * f.x;
     }
   }
+  if (!live) return;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = lane + 64 * r;
-    if (i < rows) y[i] = v[r];
+  for (int t = 0; t < kRowsPerLane; ++t) {
+    const int i = l16 + 16 * t;
+    if (i < rows) y[i] = v[t];
   }
 }
 
@@ -273,7 +278,7 @@ hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p,
     hipLaunchKernelGGL(k_panel_qr, dim3(1), dim3(kPanelThreads), 0, st, H, ld, c0, c0, rows, p, U, s);
     const int cb = c0 + p, ncols = (nc - cb) + k;
     if (ncols > 0)
-      hipLaunchKernelGGL(k_panel_apply, dim3((ncols + 3) / 4), dim3(256), 0, st, H, ld, B, ldb, k, c0, rows, p, cb,
+      hipLaunchKernelGGL(k_panel_apply, dim3((ncols + 15) / 16), dim3(256), 0, st, H, ld, B, ldb, k, c0, rows, p, cb,
                          nc, U, s);
   }
   return hipGetLastError();
