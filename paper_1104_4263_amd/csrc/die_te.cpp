@@ -1249,6 +1249,33 @@ int half_block_cgs(die_te_ctx* c, const _Float16* Qs, c2<T>* W, size_t n, int nq
   }
 }
 
+// Page-locked host memory (hipHostMalloc), released with the owner.
+struct PinnedBuf {
+  void* p = nullptr;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  int alloc(size_t bytes) {
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(DIE_E_NOMEM, "hipHostMalloc failed");
+    }
+    return DIE_OK;
+  }
+};
+
+// Host -> device copy of a small matrix through a page-locked slot, without waiting: the caller
+// rewrites the slot only after a later synchronisation of the stream.
+template <class T> int upload_async(const die::la::Mat& M, void* d, c2<T>* slot, hipStream_t st) {
+  for (size_t e = 0; e < M.a.size(); ++e) slot[e] = die::mk<T>((T)M.a[e].real(), (T)M.a[e].imag());
+  DIE_HIP(hipMemcpyAsync(d, slot, M.a.size() * sizeof(c2<T>), hipMemcpyHostToDevice, st));
+  return DIE_OK;
+}
+
 // Restarted block GMRES(m) (Section 4's GMRES applied to all right-hand sides of an object
 // at once): per object, the active residuals (normalised) span the first block through a
 // rank-revealing (pivoted) Cholesky QR; block Arnoldi with CGS2 as GEMMs and CholQR2 for each
@@ -1311,6 +1338,11 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   }
   DIE_TRY(Uq.alloc((size_t)die::kPanelMaxRows * die::kPanelMaxCols * sizeof(double2)));  // panel reflectors
   DIE_TRY(sq.alloc(die::kPanelMaxCols * sizeof(double)));
+  // three page-locked slots for the per-step uploads (R1^-1, R2^-1, H(j+1, j)); each step's Gram
+  // downloads synchronise the stream before a slot is written again
+  PinnedBuf pin;
+  DIE_TRY(pin.alloc((size_t)3 * rpo * rpo * sizeof(c2<T>)));
+  c2<T>* slot[3] = {(c2<T>*)pin.p, (c2<T>*)pin.p + (size_t)rpo * rpo, (c2<T>*)pin.p + (size_t)2 * rpo * rpo};
   if (defl) {
     DIE_TRY(part.alloc((size_t)rpo * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
                        sizeof(double2)));
@@ -1480,7 +1512,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_TRY(download<T>(sm.p, p, p, Gw, st));
         bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1);
         if (ok) {
-          DIE_TRY(upload<T>(la::upper_inverse(Q1), sm.p, st, stage));
+          DIE_TRY(upload_async<T>(la::upper_inverse(Q1), sm.p, slot[0], st));
           DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, W, ni, sm.as<c2<T>>(), p, 0.0, Wt.as<c2<T>>(), ni));
           DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, Wt.as<c2<T>>(), ni, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), st));
           DIE_TRY(download<T>(sm.p, p, p, Gw, st));
@@ -1491,7 +1523,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
           early = true;
           break;
         }
-        DIE_TRY(upload<T>(la::upper_inverse(Q2), sm.p, st, stage));
+        DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
         DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
         if (hgemm) DIE_TRY(half_shadow<T>(W, n, p, Qs.as<_Float16>() + (size_t)(j + 1) * 2 * p * n, st));
         Mat Hs(p, p);  // H(j+1, j) = Q2 Q1
@@ -1501,9 +1533,10 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
             for (int q = i; q <= jj; ++q) a += Q2(i, q) * Q1(q, jj);
             Hs(i, jj) = a;
           }
-        DIE_TRY(upload<T>(Hs, sm.p, st, stage));
-        DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp + (size_t)(j + 1) * p, ldhp * sizeof(c2<T>), sm.p,
-                                 p * sizeof(c2<T>), p * sizeof(c2<T>), p, hipMemcpyDeviceToDevice, st));
+        // into H's block (j+1, j) straight from the page-locked slot
+        for (size_t e = 0; e < Hs.a.size(); ++e) slot[2][e] = die::mk<T>((T)Hs.a[e].real(), (T)Hs.a[e].imag());
+        DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp + (size_t)(j + 1) * p, ldhp * sizeof(c2<T>), slot[2],
+                                 p * sizeof(c2<T>), p * sizeof(c2<T>), p, hipMemcpyHostToDevice, st));
       }
       // ---- block least squares min || E1 S0 - H Y || on the GPU, then u += P^-1 V Y
       const int mr = early ? meff * p : (meff + 1) * p, nc = meff * p;

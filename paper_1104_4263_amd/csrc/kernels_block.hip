@@ -147,10 +147,18 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
 
 // Apply the panel's reflectors P_0, P_1, ..., P_{pc-1} (in that order) to rows r0 .. r0+rows of
 // the columns [cb, ce) of H and all k columns of B (leading dimension ldb): one 16-lane row per
-// column, 16 columns a workgroup.
+// column, 16 columns a workgroup.  The reflectors and their scales are first staged in LDS, so
+// the serial chain over q reads LDS rather than L2.
 __global__ void __launch_bounds__(256)
 k_panel_apply(double2* __restrict__ H, int ld, double2* __restrict__ B, int ldb, int k, int r0, int rows, int pc,
               int cb, int ce, const double2* __restrict__ U, const double* __restrict__ s) {
+  __shared__ double2 Us[kPanelMaxCols * kPanelMaxRows];
+  __shared__ double ss[kPanelMaxCols];
+  for (int e = threadIdx.x; e < pc * kPanelMaxRows; e += blockDim.x) {
+    const int i = e % kPanelMaxRows;
+    Us[e] = i < rows ? U[e] : make_double2(0.0, 0.0);
+  }
+  if (threadIdx.x < pc) ss[threadIdx.x] = s[threadIdx.x];
   const int l16 = threadIdx.x & 15;
   const int col = blockIdx.x * 16 + (threadIdx.x >> 4);
   const int nh = ce - cb;
@@ -162,19 +170,19 @@ k_panel_apply(double2* __restrict__ H, int ld, double2* __restrict__ B, int ldb,
     const int i = l16 + 16 * t;
     v[t] = live && i < rows ? y[i] : make_double2(0.0, 0.0);
   }
+  __syncthreads();
   for (int q = 0; q < pc; ++q) {
-    const double2* u = U + (size_t)q * kPanelMaxRows;
+    const double2* u = Us + q * kPanelMaxRows;
     double2 uq[kRowsPerLane];
     double2 d = make_double2(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < kRowsPerLane; ++t) {
-      const int i = l16 + 16 * t;
-      uq[t] = i < rows ? u[i] : make_double2(0.0, 0.0);
+      uq[t] = u[l16 + 16 * t];
       d = cfma_conj(uq[t], v[t], d);
     }
     d.x = sum16(d.x);
     d.y = sum16(d.y);
-    const double sc = s[q];
+    const double sc = ss[q];
     const double2 f = make_double2(sc * d.x, sc * d.y);
 #pragma unroll
     for (int t = 0; t < kRowsPerLane; ++t) {
