@@ -4,10 +4,12 @@ Headline workload: the 256 x 256 size class of the batched random-field workload
 four objects (seeds 1004..1007: Re eps = 1 + 9U, Im eps = 0.5 U2, correlation length
 lambda/2, masked to a random ellipse; h = lambda/48, so 5.33 wavelengths across) lit
 by 64 equispaced TE plane waves each: 256 solves.  A step solves all 256 in one call:
-block GMRES(30) with one block Krylov space per object (complex64 products, basis and
-block GEMMs on the matrix cores, FP64 block least squares; --block-precision 64 for
-complex128), every cycle restarted from the FP64 true residual, tol 1e-8 on that
-residual, zero initial guess.  --solver rhs times the per-rhs batched solver instead
+block GMRES(30) with one block Krylov space per object (complex64 products and basis;
+the two block Gram-Schmidt passes of each step as binary16 GEMMs on planar copies of the
+basis with FP32 accumulation, CholQR2 of each new block as complex64 GEMMs, FP64 block
+least squares; --block-gemm 32 keeps the Gram-Schmidt GEMMs in complex64 with one pass,
+--block-precision 64 runs everything in complex128), every cycle restarted from the FP64
+true residual, tol 1e-8 on that residual, zero initial guess.  --solver rhs times the per-rhs batched solver instead
 (one-reduction Arnoldi, complex binary16 basis; --basis 32 / --orth 0 select the
 complex64 basis and the two-pass CGS2); it is also reported beside the block run.  Inputs are resident in HBM before the timed region; the
 per-object setup (symbol) is done once, outside it.
@@ -195,7 +197,7 @@ def uneven_run(sizes, args):
         Bs.append(torch.from_numpy(np.concatenate([b1] * 4)).cuda())
     if args.solver == "block":
         kw = dict(restart=RESTART, tol=TOL, mixed=1 if args.block_precision == 32 else 0,
-                  block=2 if args.block_gemm == 16 else 1, orth=args.orth)
+                  block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
     else:
         kw = dict(restart=RESTART, tol=TOL, mixed=2 if args.basis == 16 else 1, orth=args.orth)
     Solver.solve_batch(solvers, Bs, max_iters=RESTART, **kw)  # allocates every context's buffers
@@ -259,9 +261,12 @@ def main():
                     help="block: block GMRES(30), one block Krylov space per object (default); rhs: per-rhs GMRES(30)")
     ap.add_argument("--block-precision", type=int, default=32, choices=(32, 64),
                     help="bits per real part of the block basis, GEMMs and products (32 with FP64 refinement, or 64)")
-    ap.add_argument("--block-gemm", type=int, default=32, choices=(16, 32),
+    ap.add_argument("--block-gemm", type=int, default=16, choices=(16, 32),
                     help="block solver: 16 = block Gram-Schmidt GEMMs on binary16 planar copies of the basis "
                          "(FP32 accumulation; needs --block-precision 32), 32 = complex GEMMs in the basis precision")
+    ap.add_argument("--block-orth", type=int, default=None, choices=(0, 1),
+                    help="block solver: 0 = two block Gram-Schmidt passes (default with --block-gemm 16), "
+                         "1 = one pass (default with --block-gemm 32); CholQR2 of each new block either way")
     ap.add_argument("--orth", type=int, default=1, choices=(0, 1),
                     help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
     ap.add_argument("--basis", type=int, default=16, choices=(16, 32),
@@ -275,8 +280,10 @@ def main():
                     help="also solve size classes of the batched workload on grids of different sizes in one "
                          "call (e.g. 128,256,512: 4 objects x 64 angles per class, seeds 1000 + object index)")
     args = ap.parse_args()
-    if args.block_gemm == 16 and args.block_precision != 32:
-        ap.error("--block-gemm 16 needs --block-precision 32")
+    if args.block_precision != 32:
+        args.block_gemm = 32  # binary16 GEMMs only over a complex64 basis
+    if args.block_orth is None:
+        args.block_orth = 0 if args.block_gemm == 16 else 1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
               "in DESIGN.md and is not part of this build", file=sys.stderr)
@@ -310,7 +317,7 @@ def main():
         if use_block:
             return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
                            mixed=1 if args.block_precision == 32 else 0, block=2 if args.block_gemm == 16 else 1,
-                           orth=args.orth)
+                           orth=args.block_orth)
         return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=2 if args.basis == 16 else 1,
                        orth=args.orth)
 
@@ -402,7 +409,7 @@ def main():
                                f"{N_ANGLES} TE incidence angles = {nsolve} solves per step",
                    "method": ((f"block GMRES({RESTART}) on A, one block Krylov space per object (its {N_ANGLES} "
                                f"angles), {'complex64' if args.block_precision == 32 else 'complex128'} products and "
-                               f"{'one-pass block CGS' if args.orth else 'block CGS2'}"
+                               f"{'one-pass block CGS' if args.block_orth else 'block CGS2'}"
                                f"{' (binary16 planar GEMMs, FP32 accumulation)' if args.block_gemm == 16 else ''}"
                                f" + CholQR2 GEMMs, FP64 block "
                                f"least squares and true-residual restart per cycle, tol {TOL}, zero initial guess, "
