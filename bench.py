@@ -3,7 +3,8 @@
 Headline workload: the 256 x 256 size class of the batched random-field workload --
 four objects (seeds 1004..1007: Re eps = 1 + 9U, Im eps = 0.5 U2, correlation length
 lambda/2, masked to a random ellipse; h = lambda/48, so 5.33 wavelengths across) lit
-by 64 equispaced TE plane waves each: 256 solves.  A step solves all 256 in one call:
+by 64 equispaced TE plane waves each: 256 solves.  A step solves all 256 in one
+die_te_solve_batch call over four single-object contexts (a host thread and a stream each):
 block GMRES(30) with one block Krylov space per object (complex64 products and basis;
 the two block Gram-Schmidt passes of each step as binary16 GEMMs on planar copies of the
 basis with FP32 accumulation, CholQR2 of each new block as complex64 GEMMs, FP64 block
@@ -305,19 +306,25 @@ def main():
     B = torch.from_numpy(np.concatenate([b1] * nobj)).cuda()  # [object][angle] order
     nsolve = nobj * N_ANGLES
 
+    block = args.solver == "block"
     t0 = time.perf_counter()
-    s = Solver.from_grid(g, eps)
+    s = Solver.from_grid(g, eps)  # one context holding the four objects (per-rhs solver, plain sample)
+    # block solver: one context per object, all solved in one die_te_solve_batch call (a host
+    # thread and a stream per context, so one object's host-side Cholesky factorisations and
+    # one-workgroup least squares overlap the other objects' GEMMs and products)
+    per_obj = [Solver.from_grid(g, eps[o]) for o in range(nobj)] if block else []
+    B_obj = [B[o * N_ANGLES:(o + 1) * N_ANGLES] for o in range(nobj)]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"setup of {nobj} objects on {g.nx}x{g.ny}: {setup_s:.3f} s")
-
-    block = args.solver == "block"
+    timed_ctx = per_obj if block else [s]
 
     def batch_solve(use_block=block):
         if use_block:
-            return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
-                           mixed=1 if args.block_precision == 32 else 0, block=2 if args.block_gemm == 16 else 1,
-                           orth=args.block_orth)
+            res, rc = Solver.solve_batch(per_obj, B_obj, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
+                                         mixed=1 if args.block_precision == 32 else 0,
+                                         block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
+            return None, rc, [x for _, inf in res for x in inf]
         return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=2 if args.basis == 16 else 1,
                        orth=args.orth)
 
@@ -325,7 +332,8 @@ def main():
         _, rc, info = batch_solve()
         log(f"warmup {i}: rc {rc}, max iters {max(x['iters'] for x in info)}")
     torch.cuda.synchronize()
-    s.profile(3)  # events around one launch in three of each kind (coprime with the per-iteration pattern)
+    for sv in timed_ctx:
+        sv.profile(3)  # events around one launch in three of each kind (coprime with the per-iteration pattern)
     infos = []
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -334,7 +342,8 @@ def main():
         log(f"step {i}: rc {rc}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    s.profile(0)
+    for sv in timed_ctx:
+        sv.profile(0)
     ms_per_step = 1000.0 * dt / args.steps
     last = infos[-1]
     converged = all(x["status"] == 0 and x["rel_res_true"] <= TOL for inf in infos for x in inf)
@@ -344,56 +353,85 @@ def main():
     log(f"timed {args.steps} batches of {nsolve} solves in {dt:.3f} s -> {value:.2f} solves/s; "
         f"iters per object mean {iters.mean(1).round(1)} max {iters.max(1)}")
 
+    def measure_roofline(ctxs, wall_ms):
+        """Roofline of the dominant kernel class from the contexts' HIP-event brackets (their
+        launches, times and algorithmic bytes summed) over a region of wall_ms."""
+        prof = {}
+        for kind, name in ((DIE_PROF_PRODUCT, "product"), (DIE_PROF_DOTS, "dots"), (DIE_PROF_AXPY, "axpy"),
+                           (DIE_PROF_GEMM, "gemm")):
+            cnt = seen = 0
+            ms = nbytes = 0.0
+            for sv in ctxs:  # summed over the contexts
+                c_, s_, m_, b_ = sv.profile_read(kind)
+                cnt, seen, ms, nbytes = cnt + c_, seen + s_, ms + m_, nbytes + b_
+            if seen:
+                prof[name] = dict(timed=cnt, seen=seen, ms=ms, bytes=nbytes)
+        est = {k: v["ms"] / max(v["timed"], 1) * v["seen"] for k, v in prof.items()}  # estimated total ms per kind
+        dom = max(est, key=est.get)
+        p = prof[dom]
+        avg_ms = p["ms"] / max(p["timed"], 1)
+        work_per_launch = p["bytes"] / max(p["timed"], 1)
+        per_kind = {}
+        for k, v in prof.items():
+            rate = v["bytes"] / max(v["ms"], 1e-9) / 1e6  # GB/s, or GFLOP/s for the GEMM kind
+            per_kind[k] = {"launches": v["seen"], "timed": v["timed"], "avg_us": round(1000.0 * v["ms"] / max(v["timed"], 1), 2),
+                           ("TFLOPs" if k == "gemm" else "GBs"): round(rate / 1000.0, 2) if k == "gemm" else round(rate, 1),
+                           "est_share_of_step": round(est[k] / wall_ms, 3)}
+        if dom == "gemm":
+            # complex GEMM on the matrix cores: flops against the dense MFMA peak of its precision
+            peak = MFMA_PEAK_TFLOPS[16 if args.block_gemm == 16 else args.block_precision]
+            achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e12
+            # HBM traffic: the operand bytes of the same launches times the measured HBM/algorithmic
+            # ratio of the update GEMM (valid only for the solver source the counters were taken on)
+            mem_per_launch = sum(sv.profile_mem(DIE_PROF_GEMM) for sv in ctxs) / max(p["timed"], 1)
+            src = source_hash("die_te.cpp", "dense.hpp", "ops.hpp", "common.hpp")
+            tag = ("block_gemm_update_h16_256" if args.block_gemm == 16 else
+                   f"block_gemm_update_c{64 if args.block_precision == 32 else 128}_256")
+            traffic = read_traffic(tag, src, mem_per_launch)
+            roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                        "frac": round(achieved / peak, 4), "traffic": None if traffic is None else int(traffic),
+                        "kernel": "gemm (block basis update W -= Q H)",
+                        "avg_launch_us": round(1000.0 * avg_ms, 2), "algorithmic_flops_per_launch": int(work_per_launch),
+                        "algorithmic_bytes_per_launch": int(mem_per_launch), "solver_source_sha256": src,
+                        "per_kind": per_kind}
+        else:
+            achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+            # the kernel file and every header it includes (a traffic summary is only valid for this code)
+            src = source_hash(*(("kernels_fft.hip", "fft.hpp", "ops.hpp", "common.hpp") if dom == "product" else
+                                ("kernels_krylov.hip", "ops.hpp", "common.hpp")))
+            kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "arnoldi_dots_c64_256_batched",
+                          "axpy": "arnoldi_axpy_c64_256_batched"}[dom]
+            traffic = read_traffic(kernel_tag, src, work_per_launch)
+            traffic = None if traffic is None else int(traffic)
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "kernel": dom, "avg_launch_us": round(1000.0 * avg_ms, 2),
+                        "algorithmic_bytes_per_launch": int(work_per_launch), "kernel_source_sha256": src,
+                        "per_kind": per_kind}
+
+        return roofline
+
     # live kernel timings from the library's event brackets over the timed region
-    prof = {}
-    for kind, name in ((DIE_PROF_PRODUCT, "product"), (DIE_PROF_DOTS, "dots"), (DIE_PROF_AXPY, "axpy"),
-                       (DIE_PROF_GEMM, "gemm")):
-        cnt, seen, ms, nbytes = s.profile_read(kind)
-        if seen:
-            prof[name] = dict(timed=cnt, seen=seen, ms=ms, bytes=nbytes)
-    est = {k: v["ms"] / max(v["timed"], 1) * v["seen"] for k, v in prof.items()}  # estimated total ms per kind
-    dom = max(est, key=est.get)
-    p = prof[dom]
-    avg_ms = p["ms"] / max(p["timed"], 1)
-    work_per_launch = p["bytes"] / max(p["timed"], 1)
-    per_kind = {}
-    for k, v in prof.items():
-        rate = v["bytes"] / max(v["ms"], 1e-9) / 1e6  # GB/s, or GFLOP/s for the GEMM kind
-        per_kind[k] = {"launches": v["seen"], "timed": v["timed"], "avg_us": round(1000.0 * v["ms"] / max(v["timed"], 1), 2),
-                       ("TFLOPs" if k == "gemm" else "GBs"): round(rate / 1000.0, 2) if k == "gemm" else round(rate, 1),
-                       "est_share_of_step": round(est[k] / (ms_per_step * args.steps), 3)}
-    if dom == "gemm":
-        # complex GEMM on the matrix cores: flops against the dense MFMA peak of its precision
-        peak = MFMA_PEAK_TFLOPS[16 if args.block_gemm == 16 else args.block_precision]
-        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e12
-        # HBM traffic: the operand bytes of the same launches times the measured HBM/algorithmic
-        # ratio of the update GEMM (valid only for the solver source the counters were taken on)
-        mem_per_launch = s.profile_mem(DIE_PROF_GEMM) / max(p["timed"], 1)
-        src = source_hash("die_te.cpp", "dense.hpp", "ops.hpp", "common.hpp")
-        tag = ("block_gemm_update_h16_256" if args.block_gemm == 16 else
-               f"block_gemm_update_c{64 if args.block_precision == 32 else 128}_256")
-        traffic = read_traffic(tag, src, mem_per_launch)
-        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": None if traffic is None else int(traffic),
-                    "kernel": "gemm (block basis update W -= Q H)",
-                    "avg_launch_us": round(1000.0 * avg_ms, 2), "algorithmic_flops_per_launch": int(work_per_launch),
-                    "algorithmic_bytes_per_launch": int(mem_per_launch), "solver_source_sha256": src,
-                    "per_kind": per_kind}
-    else:
-        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
-        # the kernel file and every header it includes (a traffic summary is only valid for this code)
-        src = source_hash(*(("kernels_fft.hip", "fft.hpp", "ops.hpp", "common.hpp") if dom == "product" else
-                            ("kernels_krylov.hip", "ops.hpp", "common.hpp")))
-        kernel_tag = {"product": "fft_product_c64_256_batched", "dots": "arnoldi_dots_c64_256_batched",
-                      "axpy": "arnoldi_axpy_c64_256_batched"}[dom]
-        traffic = read_traffic(kernel_tag, src, work_per_launch)
-        traffic = None if traffic is None else int(traffic)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": dom, "avg_launch_us": round(1000.0 * avg_ms, 2),
-                    "algorithmic_bytes_per_launch": int(work_per_launch), "kernel_source_sha256": src,
-                    "per_kind": per_kind}
+    roofline = measure_roofline(timed_ctx, ms_per_step * args.steps)
     log(f"roofline: {roofline}")
+    roofline_unc = None
+    if block:
+        # the contexts' kernels share the chip in the timed call, so the events there also hold
+        # other streams' work; one more (untimed) batch of the same block solver on the one
+        # four-object context, whose launches have the chip to themselves, gives each class alone
+        torch.cuda.synchronize()
+        s.profile(3)
+        t1 = time.perf_counter()
+        _, rc_u, inf_u = s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
+                                 mixed=1 if args.block_precision == 32 else 0,
+                                 block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
+        torch.cuda.synchronize()
+        wall_u = 1000.0 * (time.perf_counter() - t1)
+        s.profile(0)
+        roofline_unc = measure_roofline([s], wall_u)
+        roofline_unc["batch_ms"] = round(wall_u, 2)
+        roofline_unc["converged"] = bool(rc_u == 0 and all(x["rel_res_true"] <= TOL for x in inf_u))
+        log(f"roofline, one context, no concurrency: {roofline_unc}")
 
     out = {
         "metric": "TE solves/s to rel-res 1e-8 (plain vs mixed/batched/learned); matvec % HBM peak",
@@ -413,7 +451,8 @@ def main():
                                f"{' (binary16 planar GEMMs, FP32 accumulation)' if args.block_gemm == 16 else ''}"
                                f" + CholQR2 GEMMs, FP64 block "
                                f"least squares and true-residual restart per cycle, tol {TOL}, zero initial guess, "
-                               f"all {nsolve} in one call") if block else
+                               f"all {nsolve} in one die_te_solve_batch call over {nobj} single-object contexts "
+                               f"(a host thread and a stream each)") if block else
                               (f"batched GMRES({RESTART}) on A, FP32 products, {args.basis}-bit basis storage, "
                                f"{'one-reduction' if args.orth else 'two-pass'} CGS2, FP64 true-residual refinement "
                                f"per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call")),
@@ -421,10 +460,13 @@ def main():
                    "iters_mean": round(float(iters.mean()), 1), "iters_max": int(iters.max()),
                    "products_mean": round(float(prods.mean()), 1),
                    "rel_res_true_max": max(x["rel_res_true"] for x in last), "setup_s": round(setup_s, 3),
-                   "fft_variants": {"complex64": s.fft_plan(nsolve, torch.complex64),
-                                    "complex128": s.fft_plan(nsolve, torch.complex128)}},
+                   "fft_variants": {"complex64": timed_ctx[0].fft_plan(N_ANGLES if block else nsolve, torch.complex64),
+                                    "complex128": timed_ctx[0].fft_plan(N_ANGLES if block else nsolve,
+                                                                        torch.complex128)}},
         "roofline": roofline,
     }
+    if roofline_unc is not None:
+        out["roofline_uncontended"] = roofline_unc
 
     if block and not args.no_variants:
         # the per-rhs batched solver on the same 256 solves, for comparison

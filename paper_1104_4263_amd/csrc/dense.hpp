@@ -200,22 +200,32 @@ inline Mat tri_eigvecs(const Mat& T) {
 // not above rel_tol times the largest diagonal entry (numerically rank deficient).
 inline bool cholesky(const Mat& G, Mat& L, double rel_tol) {
   const int k = G.n;
-  L = Mat(k, k);
   double dmax = 0.0;
   for (int i = 0; i < k; ++i) dmax = std::max(dmax, G(i, i).real());
   if (!(dmax > 0.0)) return false;
+  // row-major working copy, so that every inner product below runs over contiguous memory;
+  // the complex multiply-adds are written out (finite values only)
+  std::vector<cd> Lr((size_t)k * k, cd(0.0, 0.0));
   for (int j = 0; j < k; ++j) {
+    const cd* lj = &Lr[(size_t)j * k];
     double d = G(j, j).real();
-    for (int q = 0; q < j; ++q) d -= std::norm(L(j, q));
+    for (int q = 0; q < j; ++q) d -= lj[q].real() * lj[q].real() + lj[q].imag() * lj[q].imag();
     if (!(d > rel_tol * dmax)) return false;
     const double ljj = std::sqrt(d);
-    L(j, j) = ljj;
+    Lr[(size_t)j * k + j] = ljj;
     for (int i = j + 1; i < k; ++i) {
-      cd s = G(i, j);
-      for (int q = 0; q < j; ++q) s -= L(i, q) * std::conj(L(j, q));
-      L(i, j) = s / ljj;
+      const cd* li = &Lr[(size_t)i * k];
+      double sr = G(i, j).real(), si = G(i, j).imag();
+      for (int q = 0; q < j; ++q) {  // s -= L(i, q) conj(L(j, q))
+        sr -= li[q].real() * lj[q].real() + li[q].imag() * lj[q].imag();
+        si -= li[q].imag() * lj[q].real() - li[q].real() * lj[q].imag();
+      }
+      Lr[(size_t)i * k + j] = cd(sr / ljj, si / ljj);
     }
   }
+  L = Mat(k, k);
+  for (int j = 0; j < k; ++j)
+    for (int i = j; i < k; ++i) L(i, j) = Lr[(size_t)i * k + j];
   return true;
 }
 
@@ -257,16 +267,53 @@ inline int pivoted_cholesky(const Mat& G, double tau2, Mat& L, std::vector<int>&
 // Inverse of the upper triangular R (non-zero diagonal).
 inline Mat upper_inverse(const Mat& R) {
   const int k = R.n;
+  // rows of R contiguous, columns of X contiguous: each entry is one contiguous inner product
+  std::vector<cd> Rr((size_t)k * k), rd(k);
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= j; ++i) Rr[(size_t)i * k + j] = R(i, j);
+  for (int i = 0; i < k; ++i) {
+    const cd r = R(i, i);
+    const double m = r.real() * r.real() + r.imag() * r.imag();
+    rd[i] = cd(r.real() / m, -r.imag() / m);  // 1 / R(i, i)
+  }
   Mat X(k, k);
   for (int j = 0; j < k; ++j) {
-    X(j, j) = 1.0 / R(j, j);
+    cd* xj = &X.a[(size_t)j * k];
+    xj[j] = rd[j];
     for (int i = j - 1; i >= 0; --i) {
-      cd s = 0.0;
-      for (int q = i + 1; q <= j; ++q) s += R(i, q) * X(q, j);
-      X(i, j) = -s / R(i, i);
+      const cd* ri = &Rr[(size_t)i * k];
+      double sr = 0.0, si = 0.0;
+      for (int q = i + 1; q <= j; ++q) {
+        sr += ri[q].real() * xj[q].real() - ri[q].imag() * xj[q].imag();
+        si += ri[q].real() * xj[q].imag() + ri[q].imag() * xj[q].real();
+      }
+      // X(i, j) = -s / R(i, i)
+      xj[i] = cd(-(sr * rd[i].real() - si * rd[i].imag()), -(sr * rd[i].imag() + si * rd[i].real()));
     }
   }
   return X;
+}
+
+// Product of two upper triangular matrices (k x k): C = A B, upper triangular.
+inline Mat upper_product(const Mat& A, const Mat& B) {
+  const int k = A.n;
+  std::vector<cd> Ar((size_t)k * k);
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= j; ++i) Ar[(size_t)i * k + j] = A(i, j);
+  Mat C(k, k);
+  for (int j = 0; j < k; ++j) {
+    const cd* bj = &B.a[(size_t)j * k];
+    for (int i = 0; i <= j; ++i) {
+      const cd* ai = &Ar[(size_t)i * k];
+      double sr = 0.0, si = 0.0;
+      for (int q = i; q <= j; ++q) {
+        sr += ai[q].real() * bj[q].real() - ai[q].imag() * bj[q].imag();
+        si += ai[q].real() * bj[q].imag() + ai[q].imag() * bj[q].real();
+      }
+      C(i, j) = cd(sr, si);
+    }
+  }
+  return C;
 }
 
 // G = R^H R with R upper triangular, from the Cholesky factor of the unit-diagonal scaling

@@ -107,6 +107,8 @@ struct die_te_ctx {
   unsigned long long prof_seen[4] = {0, 0, 0, 0};
   double prof_bytes[4] = {0, 0, 0, 0};  // algorithmic bytes (flops for the GEMM kind) of the bracketed launches
   double prof_mem[4] = {0, 0, 0, 0};    // algorithmic HBM bytes of the bracketed launches (every kind)
+  double prof_ms[4] = {0, 0, 0, 0};     // elapsed ms of the bracketed launches already read back
+  size_t prof_resolved[4] = {0, 0, 0, 0};  // event pairs read back so far
   int prof_every = 1;
   int prof_nlive = -1;  // right-hand sides live in the current launches (-1: all of them)
   // FFT pass variants of the products: forced (>= 0) or tuned per [FP64, FP32][batch class][pass]
@@ -158,6 +160,22 @@ struct ProfScope {
 };
 
 int live_count(const die_te_ctx* c, int nrhs) { return c->prof_nlive >= 0 ? std::min(c->prof_nlive, nrhs) : nrhs; }
+
+// Read back the elapsed time of every bracketed launch not read yet (waits for their events).
+// Called before a stream that the library created is destroyed, and by die_te_profile_read.
+int prof_resolve(die_te_ctx* c) {
+  for (int kind = 0; kind < 4; ++kind) {
+    for (size_t i = c->prof_resolved[kind]; i < c->prof_used[kind]; ++i) {
+      auto& pr = c->prof_ev[kind][i];
+      DIE_HIP(hipEventSynchronize(pr.second));
+      float ms = 0.0f;
+      DIE_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      c->prof_ms[kind] += ms;
+    }
+    c->prof_resolved[kind] = c->prof_used[kind];
+  }
+  return DIE_OK;
+}
 
 // Algorithmic bytes of one product on R live right-hand sides (the three passes):
 // pass 1 reads u (2RN) and chi, writes the row transforms (2R ny px);
@@ -1526,13 +1544,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
         DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
         if (hgemm) DIE_TRY(half_shadow<T>(W, n, p, Qs.as<_Float16>() + (size_t)(j + 1) * 2 * p * n, st));
-        Mat Hs(p, p);  // H(j+1, j) = Q2 Q1
-        for (int jj = 0; jj < p; ++jj)
-          for (int i = 0; i <= jj; ++i) {
-            cd a = 0.0;
-            for (int q = i; q <= jj; ++q) a += Q2(i, q) * Q1(q, jj);
-            Hs(i, jj) = a;
-          }
+        const Mat Hs = la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1
         // into H's block (j+1, j) straight from the page-locked slot
         for (size_t e = 0; e < Hs.a.size(); ++e) slot[2][e] = die::mk<T>((T)Hs.a[e].real(), (T)Hs.a[e].imag());
         DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp + (size_t)(j + 1) * p, ldhp * sizeof(c2<T>), slot[2],
@@ -1816,6 +1828,8 @@ int die_te_solve_batch(die_te_ctx* const* ctx, int nctx, const void* const* e_in
     }
     res[i].rc = die_te_solve(c, e_in[i], e_tot[i], nrhs[i], opts, info ? info[i] : nullptr, s);
     res[i].msg = die_host::last_error();
+    // timing brackets recorded on this stream are read back before it goes away
+    if (prof_resolve(c) != DIE_OK && res[i].rc >= 0) res[i] = {DIE_E_HIP, die_host::last_error()};
     (void)hipStreamDestroy(s);
   };
   std::vector<std::thread> th;
@@ -1916,6 +1930,8 @@ int die_te_profile(die_te_ctx* c, int enable) {
     for (auto& sn : c->prof_seen) sn = 0;
     for (double& b : c->prof_bytes) b = 0;
     for (double& b : c->prof_mem) b = 0;
+    for (double& b : c->prof_ms) b = 0;
+    for (size_t& r : c->prof_resolved) r = 0;
   }
   return DIE_OK;
 }
@@ -1927,17 +1943,9 @@ int die_te_profile_read(die_te_ctx* c, int kind, long long* launches, long long*
   if (kind < 0 || kind > 3 || !launches || !total_ms) return fail(DIE_E_INVALID, "bad profile kind or null output");
   if (seen) *seen = (long long)c->prof_seen[kind];
   if (bytes) *bytes = c->prof_bytes[kind];
-  double tot = 0.0;
-  const size_t u = c->prof_used[kind];
-  for (size_t i = 0; i < u; ++i) {
-    auto& pr = c->prof_ev[kind][i];
-    DIE_HIP(hipEventSynchronize(pr.second));
-    float ms = 0.0f;
-    DIE_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-    tot += ms;
-  }
-  *launches = (long long)u;
-  *total_ms = tot;
+  DIE_TRY(prof_resolve(c));
+  *launches = (long long)c->prof_used[kind];
+  *total_ms = c->prof_ms[kind];
   return DIE_OK;
 }
 

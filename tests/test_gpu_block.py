@@ -13,7 +13,7 @@ from synth import centred_grid, cylinder, plane_wave, random_field_object
 pytestmark = pytest.mark.gpu
 
 api = pytest.importorskip("paper_1104_4263_amd.api")
-from paper_1104_4263_amd._lib import DieTeError  # noqa: E402
+from paper_1104_4263_amd._lib import DIE_PROF_GEMM, DieTeError  # noqa: E402
 
 
 @pytest.mark.parametrize("orth", [0, 1])
@@ -130,6 +130,33 @@ def test_block_half_gemm_multi_object_agrees(n_side, nobj, nang):
         assert op.relative_residual(g, eps[r // nang], uh[r], b[r]) <= 1.02e-8
     assert rel(uh, host(up)) < 1e-6
     say(f"  block steps {sorted(set(x['iters'] for x in ib))}, cycles {sorted(set(x['cycles'] for x in ib))}")
+
+
+def test_block_contexts_in_one_batch_call_with_profiling():
+    """Two single-object contexts solved together by die_te_solve_batch (a thread and a stream
+    each) with block=2: the same fields as solving them one by one, and the HIP-event timing
+    recorded on the call's own streams can still be read after the call returns."""
+    objs = [random_field_object(32, seed=7200 + i) for i in range(2)]
+    g = objs[0][0]
+    b = np.stack([plane_wave(g, 2 * np.pi * j / 8) for j in range(8)])
+    kw = dict(restart=30, max_iters=20000, tol=1e-8, mixed=1, block=2, orth=0)
+    singles = [api.Solver.from_grid(g, e) for _, e in objs]
+    for sv in singles:
+        sv.profile(1)
+    res, rc = api.Solver.solve_batch(singles, [dev(b)] * 2, **kw)
+    assert rc == 0
+    for sv in singles:
+        n, seen, ms, flops = sv.profile_read(DIE_PROF_GEMM)
+        assert n > 0 and seen == n and ms > 0.0 and flops > 0.0
+        assert sv.profile_mem(DIE_PROF_GEMM) > 0.0
+        sv.profile(0)
+    for (u, info), sv, (_, e) in zip(res, singles, objs):
+        u1, rc1, _ = sv.solve(dev(b), **kw)
+        assert rc1 == 0
+        assert rel(host(u), host(u1)) < 1e-6
+        for r in range(b.shape[0]):
+            assert info[r]["rel_res_true"] <= 1e-8
+            assert op.relative_residual(g, e, host(u)[r], b[r]) <= 1.02e-8
 
 
 def test_block_option_validation():
