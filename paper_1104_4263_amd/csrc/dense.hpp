@@ -198,7 +198,7 @@ inline Mat tri_eigvecs(const Mat& T) {
 
 // Cholesky G = L L^H of a Hermitian matrix (lower triangle of G read); false when a pivot is
 // not above rel_tol times the largest diagonal entry (numerically rank deficient).
-inline bool cholesky(const Mat& G, Mat& L, double rel_tol) {
+inline bool cholesky(const Mat& G, Mat& L, double rel_tol, double* min_pivot = nullptr) {
   const int k = G.n;
   double dmax = 0.0;
   for (int i = 0; i < k; ++i) dmax = std::max(dmax, G(i, i).real());
@@ -206,11 +206,13 @@ inline bool cholesky(const Mat& G, Mat& L, double rel_tol) {
   // row-major working copy, so that every inner product below runs over contiguous memory;
   // the complex multiply-adds are written out (finite values only)
   std::vector<cd> Lr((size_t)k * k, cd(0.0, 0.0));
+  double dmin = 1.0;
   for (int j = 0; j < k; ++j) {
     const cd* lj = &Lr[(size_t)j * k];
     double d = G(j, j).real();
     for (int q = 0; q < j; ++q) d -= lj[q].real() * lj[q].real() + lj[q].imag() * lj[q].imag();
     if (!(d > rel_tol * dmax)) return false;
+    dmin = std::min(dmin, d / dmax);
     const double ljj = std::sqrt(d);
     Lr[(size_t)j * k + j] = ljj;
     for (int i = j + 1; i < k; ++i) {
@@ -226,6 +228,7 @@ inline bool cholesky(const Mat& G, Mat& L, double rel_tol) {
   L = Mat(k, k);
   for (int j = 0; j < k; ++j)
     for (int i = j; i < k; ++i) L(i, j) = Lr[(size_t)i * k + j];
+  if (min_pivot) *min_pivot = dmin;
   return true;
 }
 
@@ -319,7 +322,7 @@ inline Mat upper_product(const Mat& A, const Mat& B) {
 // G = R^H R with R upper triangular, from the Cholesky factor of the unit-diagonal scaling
 // D G D (D = diag(G)^-1/2), so that the rank test rel_tol is relative to each column's own
 // norm; false when a column vanishes or the scaled matrix is numerically rank deficient.
-inline bool chol_upper_scaled(const Mat& G, double rel_tol, Mat& R) {
+inline bool chol_upper_scaled(const Mat& G, double rel_tol, Mat& R, double* min_pivot = nullptr) {
   const int k = G.n;
   std::vector<double> dinv(k);
   for (int i = 0; i < k; ++i) {
@@ -331,7 +334,7 @@ inline bool chol_upper_scaled(const Mat& G, double rel_tol, Mat& R) {
   for (int j = 0; j < k; ++j)
     for (int i = 0; i < k; ++i) S(i, j) = G(i, j) * dinv[i] * dinv[j];
   Mat L;
-  if (!cholesky(S, L, rel_tol)) return false;
+  if (!cholesky(S, L, rel_tol, min_pivot)) return false;
   R = Mat(k, k);  // R = L^H D^-1
   for (int j = 0; j < k; ++j)
     for (int i = 0; i <= j; ++i) R(i, j) = std::conj(L(j, i)) / dinv[j];

@@ -1216,6 +1216,9 @@ template <class T> int upload(const die::la::Mat& M, void* d, hipStream_t st, st
 // p-column block of the basis planar in binary16 (n x 2p: real parts, then imaginary parts), so
 // that Q^H W and W -= Q H are real GEMMs on the binary16 matrix cores with FP32 accumulation.
 constexpr size_t kHalfProjPartial = (size_t)1 << 25;  // FP32 values of the projection's chunk products
+// CholQR of a new block: one pass when the smallest pivot of the unit-diagonal Gram's Cholesky is
+// at least this (the second pass of CholQR2 otherwise)
+constexpr double kCholQRSinglePivot = 0.05;
 
 // Binary16 planar copy of the new basis block X (n x p complex64) into its place in Qs.
 template <class T>
@@ -1528,23 +1531,33 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         Mat Gw, Q1, Q2;
         DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, W, ni, W, ni, sm.as<c2<T>>(), st));
         DIE_TRY(download<T>(sm.p, p, p, Gw, st));
-        bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1);
+        double piv1 = 0.0;
+        bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1, &piv1);
+        // a well-conditioned block (smallest scaled pivot >= kCholQRSinglePivot, condition <= ~4.5)
+        // is orthonormal to about cond^2 times the Gram's rounding after one CholQR pass
+        const bool single = ok && piv1 >= kCholQRSinglePivot;
         if (ok) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q1), sm.p, slot[0], st));
           DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, W, ni, sm.as<c2<T>>(), p, 0.0, Wt.as<c2<T>>(), ni));
-          DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, Wt.as<c2<T>>(), ni, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), st));
-          DIE_TRY(download<T>(sm.p, p, p, Gw, st));
-          ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
+          if (!single) {
+            DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, Wt.as<c2<T>>(), ni, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), st));
+            DIE_TRY(download<T>(sm.p, p, p, Gw, st));
+            ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
+          }
         }
         if (!ok) {  // the new block is numerically dependent: end the cycle here
           meff = j + 1;
           early = true;
           break;
         }
-        DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
-        DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
+        if (single) {
+          DIE_HIP(hipMemcpyAsync(W, Wt.p, (size_t)p * n * sizeof(c2<T>), hipMemcpyDeviceToDevice, st));
+        } else {
+          DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
+          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
+        }
         if (hgemm) DIE_TRY(half_shadow<T>(W, n, p, Qs.as<_Float16>() + (size_t)(j + 1) * 2 * p * n, st));
-        const Mat Hs = la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1
+        const Mat Hs = single ? Q1 : la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1 (Q2 = I: one pass)
         // into H's block (j+1, j) straight from the page-locked slot
         for (size_t e = 0; e < Hs.a.size(); ++e) slot[2][e] = die::mk<T>((T)Hs.a[e].real(), (T)Hs.a[e].imag());
         DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp + (size_t)(j + 1) * p, ldhp * sizeof(c2<T>), slot[2],
