@@ -353,9 +353,9 @@ def main():
     log(f"timed {args.steps} batches of {nsolve} solves in {dt:.3f} s -> {value:.2f} solves/s; "
         f"iters per object mean {iters.mean(1).round(1)} max {iters.max(1)}")
 
-    def measure_roofline(ctxs, wall_ms):
-        """Roofline of the dominant kernel class from the contexts' HIP-event brackets (their
-        launches, times and algorithmic bytes summed) over a region of wall_ms."""
+    def measure_roofline(ctxs, wall_ms, dom=None):
+        """Roofline of the dominant kernel class (or of class dom) from the contexts' HIP-event
+        brackets (their launches, times and algorithmic bytes summed) over a region of wall_ms."""
         prof = {}
         for kind, name in ((DIE_PROF_PRODUCT, "product"), (DIE_PROF_DOTS, "dots"), (DIE_PROF_AXPY, "axpy"),
                            (DIE_PROF_GEMM, "gemm")):
@@ -367,7 +367,8 @@ def main():
             if seen:
                 prof[name] = dict(timed=cnt, seen=seen, ms=ms, bytes=nbytes)
         est = {k: v["ms"] / max(v["timed"], 1) * v["seen"] for k, v in prof.items()}  # estimated total ms per kind
-        dom = max(est, key=est.get)
+        if dom is None or dom not in prof:
+            dom = max(est, key=est.get)
         p = prof[dom]
         avg_ms = p["ms"] / max(p["timed"], 1)
         work_per_launch = p["bytes"] / max(p["timed"], 1)
@@ -411,10 +412,8 @@ def main():
 
         return roofline
 
-    # live kernel timings from the library's event brackets over the timed region
-    roofline = measure_roofline(timed_ctx, ms_per_step * args.steps)
-    log(f"roofline: {roofline}")
     roofline_unc = None
+    dom_unc = None
     if block:
         # the contexts' kernels share the chip in the timed call, so the events there also hold
         # other streams' work; one more (untimed) batch of the same block solver on the one
@@ -431,7 +430,14 @@ def main():
         roofline_unc = measure_roofline([s], wall_u)
         roofline_unc["batch_ms"] = round(wall_u, 2)
         roofline_unc["converged"] = bool(rc_u == 0 and all(x["rel_res_true"] <= TOL for x in inf_u))
+        dom_unc = "gemm" if roofline_unc["bound"] == "mfma" else roofline_unc["kernel"]
         log(f"roofline, one context, no concurrency: {roofline_unc}")
+    # live kernel timings from the library's event brackets over the timed region (for the block
+    # solver: the class that dominates when it runs alone)
+    roofline = measure_roofline(timed_ctx, ms_per_step * args.steps, dom_unc)
+    if block:
+        roofline["contended"] = True  # brackets in the timed call overlap the other contexts' kernels
+    log(f"roofline: {roofline}")
 
     out = {
         "metric": "TE solves/s to rel-res 1e-8 (plain vs mixed/batched/learned); matvec % HBM peak",
