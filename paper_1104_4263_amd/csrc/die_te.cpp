@@ -1232,11 +1232,11 @@ int half_shadow(const c2<T>* X, size_t n, int p, _Float16* Qsj, hipStream_t st) 
 }
 
 // Chunks of the projection's inner dimension K = n: a power of two that keeps K / nch >= 512,
-// the chunk products within kHalfProjPartial and about 512 output tiles in flight.
+// the chunk products within kHalfProjPartial and about 256 output tiles in flight.
 int half_chunks(size_t K, int rows, int cols) {
   const size_t tiles = (size_t)((rows + 255) / 256) * (size_t)((cols + 255) / 256);
   for (int cnum = 256; cnum >= 2; cnum /= 2)
-    if (K % cnum == 0 && K / cnum >= 512 && (size_t)rows * cols * cnum <= kHalfProjPartial && tiles * cnum <= 512)
+    if (K % cnum == 0 && K / cnum >= 512 && (size_t)rows * cols * cnum <= kHalfProjPartial && tiles * cnum <= 256)
       return cnum;
   return 1;
 }
@@ -1245,10 +1245,10 @@ int half_chunks(size_t K, int rows, int cols) {
 // columns: per pass H_pass = Q^H W (nq x p, complex64 holding binary16-rounded values) and
 // W -= Q H_pass, both as binary16 GEMMs on the planar copies (the projection chunked over K, its
 // chunk products summed in fixed order).  W stays planar in FP32 between the passes; the
-// binary16 copy that the next projection reads is made from it.
+// binary16 copy that the next projection reads is made from it.  The result goes to Wout.
 template <class T>
-int half_block_cgs(die_te_ctx* c, const _Float16* Qs, c2<T>* W, size_t n, int nq, int p, int npass, float* Ws,
-                   _Float16* Wh, float* Cpart, c2<T>* const* H, _Float16* Hb, hipStream_t st) {
+int half_block_cgs(die_te_ctx* c, const _Float16* Qs, const c2<T>* W, c2<T>* Wout, size_t n, int nq, int p, int npass,
+                   float* Ws, _Float16* Wh, float* Cpart, c2<T>* const* H, _Float16* Hb, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
     const int M = 2 * nq, P2 = 2 * p;
     DIE_HIP(die::launch_planar_split(W, n, n, p, Ws, Wh, n, st));
@@ -1263,7 +1263,7 @@ int half_block_cgs(die_te_ctx* c, const _Float16* Qs, c2<T>* W, size_t n, int nq
       ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq, 2.0 * n * M + 8.0 * n * P2 + 2.0 * M * P2);
       DIE_TRY(lt_gemm(c, false, (int)n, P2, M, -1.0f, Qs, (int64_t)n, 0, Hb, M, 0, 1.0f, Ws, (int64_t)n, 0, 1, st));
     }
-    DIE_HIP(die::launch_planar_merge(Ws, n, n, p, W, n, st));
+    DIE_HIP(die::launch_planar_merge(Ws, n, n, p, Wout, n, st));
     return DIE_OK;
   } else {
     return fail(DIE_E_INVALID, "binary16 GEMMs need a complex64 basis");
@@ -1513,8 +1513,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         const int nq = (j + 1) * p;
         c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the projections (nq x p each)
         if (hgemm)
-          DIE_TRY(half_block_cgs<T>(c, Qs.as<_Float16>(), W, n, nq, p, npass, Wsb.as<float>(), Whb.as<_Float16>(),
-                                    Cpart.as<float>(), hc, Hbh.as<_Float16>(), st));
+          DIE_TRY(half_block_cgs<T>(c, Qs.as<_Float16>(), W, Wt.as<c2<T>>(), n, nq, p, npass, Wsb.as<float>(),
+                                    Whb.as<_Float16>(), Cpart.as<float>(), hc, Hbh.as<_Float16>(), st));
         for (int rep = 0; rep < npass && !hgemm; ++rep) {
           DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, hc[rep], st));
           // flops 8 n p nq; operands: Q (n x nq) read, W (n x p) read and written, H (nq x p) read
@@ -1528,8 +1528,12 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         else
           DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp, ldhp * sizeof(c2<T>), hc[0], nq * sizeof(c2<T>),
                                    nq * sizeof(c2<T>), p, hipMemcpyDeviceToDevice, st));
+        // CholQR of the orthogonalised block, which the binary16 passes leave in Wt and the complex
+        // ones in W: each factor application writes the other buffer, and the result ends in W
+        c2<T>* wa = hgemm ? Wt.as<c2<T>>() : W;
+        c2<T>* wb = hgemm ? W : Wt.as<c2<T>>();
         Mat Gw, Q1, Q2;
-        DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, W, ni, W, ni, sm.as<c2<T>>(), st));
+        DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, wa, ni, wa, ni, sm.as<c2<T>>(), st));
         DIE_TRY(download<T>(sm.p, p, p, Gw, st));
         double piv1 = 0.0;
         bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1, &piv1);
@@ -1538,9 +1542,9 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         const bool single = ok && piv1 >= kCholQRSinglePivot;
         if (ok) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q1), sm.p, slot[0], st));
-          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, W, ni, sm.as<c2<T>>(), p, 0.0, Wt.as<c2<T>>(), ni));
+          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, wa, ni, sm.as<c2<T>>(), p, 0.0, wb, ni));
           if (!single) {
-            DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, Wt.as<c2<T>>(), ni, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), st));
+            DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, wb, ni, wb, ni, sm.as<c2<T>>(), st));
             DIE_TRY(download<T>(sm.p, p, p, Gw, st));
             ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
           }
@@ -1550,12 +1554,14 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
           early = true;
           break;
         }
-        if (single) {
-          DIE_HIP(hipMemcpyAsync(W, Wt.p, (size_t)p * n * sizeof(c2<T>), hipMemcpyDeviceToDevice, st));
-        } else {
+        c2<T>* wres = wb;
+        if (!single) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
-          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, Wt.as<c2<T>>(), ni, sm.as<c2<T>>(), p, 0.0, W, ni));
+          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, wb, ni, sm.as<c2<T>>(), p, 0.0, wa, ni));
+          wres = wa;
         }
+        if (wres != W)
+          DIE_HIP(hipMemcpyAsync(W, wres, (size_t)p * n * sizeof(c2<T>), hipMemcpyDeviceToDevice, st));
         if (hgemm) DIE_TRY(half_shadow<T>(W, n, p, Qs.as<_Float16>() + (size_t)(j + 1) * 2 * p * n, st));
         const Mat Hs = single ? Q1 : la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1 (Q2 = I: one pass)
         // into H's block (j+1, j) straight from the page-locked slot
