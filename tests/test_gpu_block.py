@@ -98,6 +98,38 @@ def test_block_half_gemm_matches_lu(eps_obj, reg, defl, orth):
     say(f"  block steps {[x['iters'] for x in info]}, cycles {[x['cycles'] for x in info]}")
 
 
+@pytest.mark.parametrize("nang", [1, 3])
+def test_block_half_gemm_small_blocks(nang):
+    """block=2 with one and with three right-hand sides per object (blocks of width 1 and 3)."""
+    g = centred_grid(24, 1.0, ny=20)
+    eps = cylinder(g, 0.35, 4.0 + 0j)
+    b = np.stack([plane_wave(g, 0.4 + 1.9 * q) for q in range(nang)])
+    u_lu = op.solve_dense(g, eps, b)
+    s = api.Solver.from_grid(g, eps)
+    u, rc, info = s.solve(dev(b), restart=20, max_iters=4000, tol=1e-8, mixed=1, block=2, orth=0)
+    assert rc == 0
+    for r in range(nang):
+        assert info[r]["rel_res_true"] <= 1e-8
+        assert rel(host(u)[r], u_lu[r]) < 2e-5
+
+
+def test_block_half_gemm_rank_deficient_and_warm_start():
+    """block=2 on fields where three of four lie along one direction: the duplicates get the same
+    solution (and the doubled field twice it), and a start at the solution takes no block step."""
+    g = centred_grid(24, 1.0, ny=20)
+    eps = cylinder(g, 0.35, 4.0 + 0j)
+    b0 = plane_wave(g, 0.7)
+    b = np.stack([b0, plane_wave(g, 2.0), b0, 2.0 * b0])
+    s = api.Solver.from_grid(g, eps)
+    u, rc, info = s.solve(dev(b), restart=20, max_iters=4000, tol=1e-8, mixed=1, block=2, orth=0)
+    assert rc == 0
+    uh = host(u)
+    assert rel(uh[2], uh[0]) < 1e-12 and rel(uh[3], 2.0 * uh[0]) < 1e-12
+    assert rel(uh, op.solve_dense(g, eps, b)) < 2e-5
+    u2, rc2, info2 = s.solve(dev(b), x0=u, restart=20, max_iters=4000, tol=1e-8, mixed=1, block=2, orth=0)
+    assert rc2 == 0 and all(x["iters"] == 0 for x in info2)
+
+
 def test_block_half_gemm_odd_grid():
     """block=2 on a 15 x 13 grid: a vector length (390) that is even but not a multiple of 4."""
     g = centred_grid(15, 1.0, ny=13)
