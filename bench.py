@@ -268,6 +268,9 @@ def main():
     ap.add_argument("--block-orth", type=int, default=None, choices=(0, 1),
                     help="block solver: 0 = two block Gram-Schmidt passes (default with --block-gemm 16), "
                          "1 = one pass (default with --block-gemm 32); CholQR2 of each new block either way")
+    ap.add_argument("--contexts", default="per-object", choices=("per-object", "one"),
+                    help="block solver: per-object = one context per object, all in one die_te_solve_batch call "
+                         "(default); one = the single four-object context, objects one after another")
     ap.add_argument("--orth", type=int, default=1, choices=(0, 1),
                     help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
     ap.add_argument("--basis", type=int, default=16, choices=(16, 32),
@@ -312,14 +315,19 @@ def main():
     # block solver: one context per object, all solved in one die_te_solve_batch call (a host
     # thread and a stream per context, so one object's host-side Cholesky factorisations and
     # one-workgroup least squares overlap the other objects' GEMMs and products)
-    per_obj = [Solver.from_grid(g, eps[o]) for o in range(nobj)] if block else []
+    concurrent = block and args.contexts == "per-object"
+    per_obj = [Solver.from_grid(g, eps[o]) for o in range(nobj)] if concurrent else []
     B_obj = [B[o * N_ANGLES:(o + 1) * N_ANGLES] for o in range(nobj)]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"setup of {nobj} objects on {g.nx}x{g.ny}: {setup_s:.3f} s")
-    timed_ctx = per_obj if block else [s]
+    timed_ctx = per_obj if concurrent else [s]
 
     def batch_solve(use_block=block):
+        if use_block and not concurrent:
+            return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
+                           mixed=1 if args.block_precision == 32 else 0,
+                           block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
         if use_block:
             res, rc = Solver.solve_batch(per_obj, B_obj, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
                                          mixed=1 if args.block_precision == 32 else 0,
@@ -414,7 +422,7 @@ def main():
 
     roofline_unc = None
     dom_unc = None
-    if block:
+    if concurrent:
         # the contexts' kernels share the chip in the timed call, so the events there also hold
         # other streams' work; one more (untimed) batch of the same block solver on the one
         # four-object context, whose launches have the chip to themselves, gives each class alone
@@ -435,7 +443,7 @@ def main():
     # live kernel timings from the library's event brackets over the timed region (for the block
     # solver: the class that dominates when it runs alone)
     roofline = measure_roofline(timed_ctx, ms_per_step * args.steps, dom_unc)
-    if block:
+    if concurrent:
         roofline["contended"] = True  # brackets in the timed call overlap the other contexts' kernels
     log(f"roofline: {roofline}")
 
@@ -455,10 +463,11 @@ def main():
                                f"angles), {'complex64' if args.block_precision == 32 else 'complex128'} products and "
                                f"{'one-pass block CGS' if args.block_orth else 'block CGS2'}"
                                f"{' (binary16 planar GEMMs, FP32 accumulation)' if args.block_gemm == 16 else ''}"
-                               f" + CholQR2 GEMMs, FP64 block "
+                               f" + CholQR GEMMs (a second CholQR pass for ill-conditioned blocks), FP64 block "
                                f"least squares and true-residual restart per cycle, tol {TOL}, zero initial guess, "
-                               f"all {nsolve} in one die_te_solve_batch call over {nobj} single-object contexts "
-                               f"(a host thread and a stream each)") if block else
+                               + (f"all {nsolve} in one die_te_solve_batch call over {nobj} single-object contexts "
+                                  f"(a host thread and a stream each)" if concurrent else
+                                  f"all {nsolve} in one call of a {nobj}-object context")) if block else
                               (f"batched GMRES({RESTART}) on A, FP32 products, {args.basis}-bit basis storage, "
                                f"{'one-reduction' if args.orth else 'two-pass'} CGS2, FP64 true-residual refinement "
                                f"per cycle, tol {TOL}, zero initial guess, all {nsolve} in one call")),
@@ -466,8 +475,9 @@ def main():
                    "iters_mean": round(float(iters.mean()), 1), "iters_max": int(iters.max()),
                    "products_mean": round(float(prods.mean()), 1),
                    "rel_res_true_max": max(x["rel_res_true"] for x in last), "setup_s": round(setup_s, 3),
-                   "fft_variants": {"complex64": timed_ctx[0].fft_plan(N_ANGLES if block else nsolve, torch.complex64),
-                                    "complex128": timed_ctx[0].fft_plan(N_ANGLES if block else nsolve,
+                   "fft_variants": {"complex64": timed_ctx[0].fft_plan(N_ANGLES if concurrent else nsolve,
+                                                                       torch.complex64),
+                                    "complex128": timed_ctx[0].fft_plan(N_ANGLES if concurrent else nsolve,
                                                                         torch.complex128)}},
         "roofline": roofline,
     }
