@@ -397,12 +397,23 @@ def main():
             tag = ("block_gemm_update_h16_256" if args.block_gemm == 16 else
                    f"block_gemm_update_c{64 if args.block_precision == 32 else 128}_256")
             traffic = read_traffic(tag, src, mem_per_launch)
-            roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                        "frac": round(achieved / peak, 4), "traffic": None if traffic is None else int(traffic),
-                        "kernel": "gemm (block basis update W -= Q H)",
-                        "avg_launch_us": round(1000.0 * avg_ms, 2), "algorithmic_flops_per_launch": int(work_per_launch),
-                        "algorithmic_bytes_per_launch": int(mem_per_launch), "solver_source_sha256": src,
-                        "per_kind": per_kind}
+            # the bound follows the arithmetic intensity: below the ridge point (peak flops / peak HBM
+            # bytes) the GEMM is limited by HBM and is measured in algorithmic bytes per second
+            ai = work_per_launch / max(mem_per_launch, 1.0)
+            ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+            common = {"kernel": "gemm (block basis update W -= Q H)", "class": "gemm",
+                      "traffic": None if traffic is None else int(traffic),
+                      "avg_launch_us": round(1000.0 * avg_ms, 2), "algorithmic_flops_per_launch": int(work_per_launch),
+                      "algorithmic_bytes_per_launch": int(mem_per_launch), "flops_per_byte": round(ai, 1),
+                      "ridge_flops_per_byte": round(ridge, 1), "solver_source_sha256": src, "per_kind": per_kind}
+            if ai < ridge:
+                gbs = mem_per_launch / (avg_ms * 1e-3) / 1e9
+                roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(gbs / HBM_PEAK_GBS, 4), "tflops": round(achieved, 2),
+                            "mfma_peak_tflops": peak, **common}
+            else:
+                roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                            "frac": round(achieved / peak, 4), **common}
         else:
             achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
             # the kernel file and every header it includes (a traffic summary is only valid for this code)
@@ -413,7 +424,7 @@ def main():
             traffic = read_traffic(kernel_tag, src, work_per_launch)
             traffic = None if traffic is None else int(traffic)
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "class": dom,
                         "kernel": dom, "avg_launch_us": round(1000.0 * avg_ms, 2),
                         "algorithmic_bytes_per_launch": int(work_per_launch), "kernel_source_sha256": src,
                         "per_kind": per_kind}
@@ -438,7 +449,7 @@ def main():
         roofline_unc = measure_roofline([s], wall_u)
         roofline_unc["batch_ms"] = round(wall_u, 2)
         roofline_unc["converged"] = bool(rc_u == 0 and all(x["rel_res_true"] <= TOL for x in inf_u))
-        dom_unc = "gemm" if roofline_unc["bound"] == "mfma" else roofline_unc["kernel"]
+        dom_unc = roofline_unc["class"]
         log(f"roofline, one context, no concurrency: {roofline_unc}")
     # live kernel timings from the library's event brackets over the timed region (for the block
     # solver: the class that dominates when it runs alone)
