@@ -71,6 +71,9 @@ struct LtCache {
   }
 };
 
+// Work buffers of the block solver, kept in the context between calls (defined with the solver).
+struct BlockWork;
+
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int v) {
   int l = 0;
@@ -115,6 +118,7 @@ struct die_te_ctx {
   int fft_force = -1;
   rocblas_handle blas = nullptr;  // block GMRES: GEMMs and the block least squares
   std::unique_ptr<LtCache> lt;    // block GMRES, binary16 planar GEMMs
+  std::shared_ptr<BlockWork> bw;  // block GMRES work buffers, reused by later calls
   int fftv[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}, {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};
   ~die_te_ctx() {
     if (blas) (void)rocblas_destroy_handle(blas);
@@ -1273,20 +1277,33 @@ int half_block_cgs(die_te_ctx* c, const _Float16* Qs, const c2<T>* W, c2<T>* Wou
 // Page-locked host memory (hipHostMalloc), released with the owner.
 struct PinnedBuf {
   void* p = nullptr;
+  size_t cap = 0;
   PinnedBuf() = default;
   PinnedBuf(const PinnedBuf&) = delete;
   PinnedBuf& operator=(const PinnedBuf&) = delete;
   ~PinnedBuf() {
     if (p) (void)hipHostFree(p);
   }
-  int alloc(size_t bytes) {
+  int alloc(size_t bytes) {  // at least `bytes`, keeping a large enough earlier allocation
+    if (p && cap >= bytes) return DIE_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
     if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
       return fail(DIE_E_NOMEM, "hipHostMalloc failed");
     }
+    cap = bytes;
     return DIE_OK;
   }
+};
+
+struct BlockWork {
+  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, sm2, Ht, Hls, Bls, ones, idxd, infod, part, coef, cnt,
+      scl, Uq, sq, Qs, Wsb, Whb, Cpart, Hbh;
+  LongGemm lg64, lgT;  // scratch of the long inner-dimension products (FP64 first block, basis precision)
+  PinnedBuf pin;       // page-locked slots of the per-step uploads
 };
 
 // Host -> device copy of a small matrix through a page-locked slot, without waiting: the caller
@@ -1323,8 +1340,13 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(blas_on(c, st, &bh));
   const int ni = (int)n, ldh = (m + 1) * rpo;
   const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
-  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, sm2, Ht, Hls, Bls, ones, idxd, infod, part, coef, cnt,
-      scl, Uq, sq;
+  // work buffers live in the context, so repeated calls (restarted solves, batches) reuse them
+  if (!c->bw) c->bw = std::make_shared<BlockWork>();
+  BlockWork& bw = *c->bw;
+  DBuf &Rs = bw.Rs, &Sd = bw.Sd, &partn = bw.partn, &nrm = bw.nrm, &active = bw.active, &Vb = bw.Vb, &Wt = bw.Wt,
+       &Zb = bw.Zb, &Tm = bw.Tm, &Ra = bw.Ra, &Tb = bw.Tb, &sm = bw.sm, &sm2 = bw.sm2, &Ht = bw.Ht, &Hls = bw.Hls,
+       &Bls = bw.Bls, &ones = bw.ones, &idxd = bw.idxd, &infod = bw.infod, &part = bw.part, &coef = bw.coef,
+       &cnt = bw.cnt, &scl = bw.scl, &Uq = bw.Uq, &sq = bw.sq;
   DIE_TRY(Rs.alloc(dbytes));
   if (reg) DIE_TRY(Sd.alloc(dbytes));
   DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
@@ -1348,7 +1370,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   // binary16 planar GEMMs (complex64 only): the basis shadow Qs (block j planar, n x 2p), W planar
   // in FP32 and binary16, the chunk products of the projection and the real update matrix Hb
   const bool hgemm = std::is_same<T, float>::value && o.block == 2;
-  DBuf Qs, Wsb, Whb, Cpart, Hbh;
+  DBuf &Qs = bw.Qs, &Wsb = bw.Wsb, &Whb = bw.Whb, &Cpart = bw.Cpart, &Hbh = bw.Hbh;
   if (hgemm) {
     if (n % 2) return fail(DIE_E_INVALID, "block = 2 needs an even vector length");
     DIE_TRY(Qs.alloc((size_t)(m + 1) * 2 * rpo * n * sizeof(_Float16)));
@@ -1361,7 +1383,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(sq.alloc(die::kPanelMaxCols * sizeof(double)));
   // three page-locked slots for the per-step uploads (R1^-1, R2^-1, H(j+1, j)); each step's Gram
   // downloads synchronise the stream before a slot is written again
-  PinnedBuf pin;
+  PinnedBuf& pin = bw.pin;
   DIE_TRY(pin.alloc((size_t)3 * rpo * rpo * sizeof(c2<T>)));
   c2<T>* slot[3] = {(c2<T>*)pin.p, (c2<T>*)pin.p + (size_t)rpo * rpo, (c2<T>*)pin.p + (size_t)2 * rpo * rpo};
   if (defl) {
@@ -1381,7 +1403,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(ensure_work(c, (size_t)std::max((size_t)nrhs * sizeof(double2), (size_t)rpo * sizeof(c2<T>)) * 2 * c->px *
                              c->ny, st));
   c2<T>* vb = Vb.as<c2<T>>();
-  LongGemm lg64, lgT;  // scratch of the long inner-dimension products (FP64 first block, basis precision)
+  LongGemm &lg64 = bw.lg64, &lgT = bw.lgT;  // scratch of the long inner-dimension products
   std::vector<c2<T>> stage;
   std::vector<double> bnorm(nrhs), rnorm(nrhs), snorm(nrhs), hn(nrhs), relres(nrhs, 1.0);
   std::vector<int> act(nrhs, 1), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0),
