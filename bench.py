@@ -183,19 +183,28 @@ SIZE_CLASSES = (128, 256, 512, 1024)  # object o of the batched workload has siz
 
 def uneven_run(sizes, args):
     """Several size classes of the batched workload (4 objects x 64 angles each) solved in one
-    die_te_solve_batch call, one context per grid size."""
+    die_te_solve_batch call: one context per object with the block solver and --contexts
+    per-object, else one context per grid size."""
     import numpy as np
     import torch
     from synth import plane_wave, random_field_object
     from paper_1104_4263_amd import Solver
-    solvers, Bs = [], []
+    solvers, Bs, cls = [], [], []
+    per_object = args.solver == "block" and args.contexts == "per-object"
     for n in sizes:
         c = SIZE_CLASSES.index(n)
         objs = [random_field_object(n, seed=1000 + 4 * c + i) for i in range(4)]
         gn = objs[0][0]
-        solvers.append(Solver.from_grid(gn, np.stack([e for _, e in objs])))
-        b1 = np.stack([plane_wave(gn, 2.0 * math.pi * j / N_ANGLES) for j in range(N_ANGLES)])
-        Bs.append(torch.from_numpy(np.concatenate([b1] * 4)).cuda())
+        b1 = torch.from_numpy(np.stack([plane_wave(gn, 2.0 * math.pi * j / N_ANGLES) for j in range(N_ANGLES)])).cuda()
+        if per_object:
+            for _, e in objs:
+                solvers.append(Solver.from_grid(gn, e))
+                Bs.append(b1)
+                cls.append(n)
+        else:
+            solvers.append(Solver.from_grid(gn, np.stack([e for _, e in objs])))
+            Bs.append(torch.cat([b1] * 4))
+            cls.append(n)
     if args.solver == "block":
         kw = dict(restart=RESTART, tol=TOL, mixed=1 if args.block_precision == 32 else 0,
                   block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
@@ -214,17 +223,21 @@ def uneven_run(sizes, args):
         X = [u for u, _ in res]
         for c, (_, inf) in enumerate(res):
             iters[c] += np.array([x["iters"] for x in inf])
-        worst = [max(x["rel_res_true"] for x in inf) for _, inf in res]
+        worst = {n: max(max(x["rel_res_true"] for x in inf) for (_, inf), cn in zip(res, cls) if cn == n)
+                 for n in sizes}
         log(f"uneven: {time.perf_counter() - t0:.1f} s, worst rel-res per class "
-            f"{', '.join(f'{n}: {w:.1e}' for n, w in zip(sizes, worst))}")
+            f"{', '.join(f'{n}: {w:.1e}' for n, w in worst.items())}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     nsol = sum(b.shape[0] for b in Bs)
     ok = rc == 0 and all(x["rel_res_true"] <= TOL for _, inf in res for x in inf)
-    per = {f"{n}x{n}": {"iters_mean": round(float(np.mean(it)), 1), "iters_max": int(it.max())}
-           for n, it in zip(sizes, iters)}
+    per = {}
+    for n in sizes:
+        it = np.concatenate([i for i, cn in zip(iters, cls) if cn == n])
+        per[f"{n}x{n}"] = {"iters_mean": round(float(np.mean(it)), 1), "iters_max": int(it.max())}
     out = {"workload": f"size classes {sizes} of the batched random-field workload, 4 objects x {N_ANGLES} "
-                       f"angles each, die_te_solve_batch calls of two restart cycles each", "solver": args.solver,
+                       f"angles each, die_te_solve_batch calls of two restart cycles each over "
+                       f"{len(solvers)} contexts", "solver": args.solver,
            "solves": nsol,
            "s": round(dt, 3),
            "solves_per_s": round(nsol / dt, 3) if ok else 0.0, "classes": per}

@@ -1158,8 +1158,7 @@ rocblas_status gemv<float>(rocblas_handle h, int m, int n, const float2* A, int 
 // Scratch of the long inner-dimension products: chunk partials and a vector of ones.
 struct LongGemm {
   DBuf part, ones;
-  size_t cap = 0;  // complex values of the partial buffer
-  int nones = 0;
+  size_t ones_es = 0;  // bytes per complex value of the uploaded ones (the precision they were made for)
 };
 constexpr size_t kLongGemmPartial = (size_t)1 << 25;  // complex values
 
@@ -1180,16 +1179,14 @@ int gemm_hn_long(rocblas_handle h, LongGemm& lg, int m, int n, int K, const c2<T
     DIE_BLAS(gemm<T>(h, kH, kN, m, n, K, 1.0, A, lda, B, ldb, 0.0, C, m));
     return DIE_OK;
   }
-  if (lg.cap < (size_t)m * n * nch) {
-    DIE_TRY(lg.part.alloc(kLongGemmPartial * sizeof(c2<T>)));
-    lg.cap = kLongGemmPartial;
-  }
-  if (lg.nones < nch) {
+  // the scratch may have served the other precision before: sizes in bytes, ones re-made per type
+  DIE_TRY(lg.part.alloc(kLongGemmPartial * sizeof(c2<T>)));  // holds m n nch values (nch was chosen so)
+  if (lg.ones_es != sizeof(c2<T>)) {
     std::vector<c2<T>> o(256, die::mk<T>((T)1, (T)0));
     DIE_TRY(lg.ones.alloc(256 * sizeof(c2<T>)));
     DIE_HIP(hipMemcpyAsync(lg.ones.p, o.data(), 256 * sizeof(c2<T>), hipMemcpyHostToDevice, st));
     DIE_HIP(hipStreamSynchronize(st));
-    lg.nones = 256;
+    lg.ones_es = sizeof(c2<T>);
   }
   const int ck = K / nch;
   c2<T>* part = lg.part.as<c2<T>>();
@@ -1321,7 +1318,8 @@ template <class T> int upload_async(const die::la::Mat& M, void* d, c2<T>* slot,
 // the FP64 true residual, as in the per-rhs solver.  Objects are processed one after another.
 template <class T>
 int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
-                      die_te_solve_info* info, hipStream_t st) {
+                      die_te_solve_info* info, hipStream_t st, std::vector<char>* stalled = nullptr,
+                      const std::vector<char>* only = nullptr) {
   using die::la::Mat;
   namespace la = die::la;
   const size_t n = c->nvec;
@@ -1329,16 +1327,27 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   const int nblk = die::blas_blocks(n);
   const bool reg = c->regularize != 0;
   const bool defl = c->r > 0;
-  const int rpo = nrhs / c->nobj;  // right-hand sides per object: the largest block
+  const int rpo = nrhs / c->nobj;  // right-hand sides per object
+  // the widest block the buffers hold: rpo, or the most right-hand sides of one object in `only`
+  // (the only ones iterated when it is given)
+  int pw = rpo;
+  if (only) {
+    pw = 1;
+    for (int ob = 0; ob < c->nobj; ++ob) {
+      int cntv = 0;
+      for (int r = ob * rpo; r < (ob + 1) * rpo; ++r) cntv += (*only)[r] ? 1 : 0;
+      pw = std::max(pw, cntv);
+    }
+  }
   const double tol = o.tol > 0 ? o.tol : 1e-8;
   const double chol_tol = std::is_same<T, float>::value ? 1e-6 : 1e-12;  // rank test of a new block
   const double rank_tau2 = 1e-12;  // initial block: drop residual directions below 1e-6 (unit columns)
   const int npass = o.orth == 1 ? 1 : 2;  // block CGS passes against the previous blocks
-  if ((size_t)n > (size_t)INT32_MAX || (size_t)(m + 1) * rpo > 65535)
+  if ((size_t)n > (size_t)INT32_MAX || (size_t)(m + 1) * pw > 65535)
     return fail(DIE_E_INVALID, "block GMRES: vectors or blocks too large for the GEMM interface");
   rocblas_handle bh;
   DIE_TRY(blas_on(c, st, &bh));
-  const int ni = (int)n, ldh = (m + 1) * rpo;
+  const int ni = (int)n, ldh = (m + 1) * pw;
   const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
   // work buffers live in the context, so repeated calls (restarted solves, batches) reuse them
   if (!c->bw) c->bw = std::make_shared<BlockWork>();
@@ -1352,55 +1361,55 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
   DIE_TRY(nrm.alloc(nrhs * sizeof(double)));
   DIE_TRY(active.alloc(nrhs * sizeof(int)));
-  DIE_TRY(Vb.alloc((size_t)(m + 1) * rpo * n * sizeof(c2<T>)));
-  DIE_TRY(Wt.alloc((size_t)rpo * n * sizeof(c2<T>)));
-  if (defl) DIE_TRY(Zb.alloc((size_t)rpo * n * sizeof(c2<T>)));
-  if (reg) DIE_TRY(Tm.alloc((size_t)rpo * n * sizeof(c2<T>)));
-  DIE_TRY(Ra.alloc((size_t)2 * rpo * n * sizeof(double2)));  // residual block, then its orthonormal basis
-  DIE_TRY(Tb.alloc((size_t)rpo * n * sizeof(c2<T>)));
-  DIE_TRY(sm.alloc((size_t)ldh * rpo * sizeof(double2)));
-  DIE_TRY(sm2.alloc((size_t)ldh * rpo * sizeof(c2<T>)));
-  DIE_TRY(Ht.alloc((size_t)ldh * m * rpo * sizeof(c2<T>)));
-  DIE_TRY(Hls.alloc((size_t)ldh * m * rpo * sizeof(double2)));
-  DIE_TRY(Bls.alloc((size_t)ldh * rpo * sizeof(double2)));
+  DIE_TRY(Vb.alloc((size_t)(m + 1) * pw * n * sizeof(c2<T>)));
+  DIE_TRY(Wt.alloc((size_t)pw * n * sizeof(c2<T>)));
+  if (defl) DIE_TRY(Zb.alloc((size_t)pw * n * sizeof(c2<T>)));
+  if (reg) DIE_TRY(Tm.alloc((size_t)pw * n * sizeof(c2<T>)));
+  DIE_TRY(Ra.alloc((size_t)2 * pw * n * sizeof(double2)));  // residual block, then its orthonormal basis
+  DIE_TRY(Tb.alloc((size_t)pw * n * sizeof(c2<T>)));
+  DIE_TRY(sm.alloc((size_t)ldh * pw * sizeof(double2)));
+  DIE_TRY(sm2.alloc((size_t)ldh * pw * sizeof(c2<T>)));
+  DIE_TRY(Ht.alloc((size_t)ldh * m * pw * sizeof(c2<T>)));
+  DIE_TRY(Hls.alloc((size_t)ldh * m * pw * sizeof(double2)));
+  DIE_TRY(Bls.alloc((size_t)ldh * pw * sizeof(double2)));
   DIE_TRY(ones.alloc(sizeof(double)));
-  DIE_TRY(idxd.alloc(rpo * sizeof(int)));
+  DIE_TRY(idxd.alloc(pw * sizeof(int)));
   DIE_TRY(infod.alloc(sizeof(int)));
-  DIE_TRY(scl.alloc(rpo * sizeof(double)));
+  DIE_TRY(scl.alloc(pw * sizeof(double)));
   // binary16 planar GEMMs (complex64 only): the basis shadow Qs (block j planar, n x 2p), W planar
   // in FP32 and binary16, the chunk products of the projection and the real update matrix Hb
   const bool hgemm = std::is_same<T, float>::value && o.block == 2;
   DBuf &Qs = bw.Qs, &Wsb = bw.Wsb, &Whb = bw.Whb, &Cpart = bw.Cpart, &Hbh = bw.Hbh;
   if (hgemm) {
     if (n % 2) return fail(DIE_E_INVALID, "block = 2 needs an even vector length");
-    DIE_TRY(Qs.alloc((size_t)(m + 1) * 2 * rpo * n * sizeof(_Float16)));
-    DIE_TRY(Wsb.alloc((size_t)2 * rpo * n * sizeof(float)));
-    DIE_TRY(Whb.alloc((size_t)2 * rpo * n * sizeof(_Float16)));
+    DIE_TRY(Qs.alloc((size_t)(m + 1) * 2 * pw * n * sizeof(_Float16)));
+    DIE_TRY(Wsb.alloc((size_t)2 * pw * n * sizeof(float)));
+    DIE_TRY(Whb.alloc((size_t)2 * pw * n * sizeof(_Float16)));
     DIE_TRY(Cpart.alloc(kHalfProjPartial * sizeof(float)));
-    DIE_TRY(Hbh.alloc((size_t)2 * m * rpo * 2 * rpo * sizeof(_Float16)));
+    DIE_TRY(Hbh.alloc((size_t)2 * m * pw * 2 * pw * sizeof(_Float16)));
   }
   DIE_TRY(Uq.alloc((size_t)die::kPanelMaxRows * die::kPanelMaxCols * sizeof(double2)));  // panel reflectors
   DIE_TRY(sq.alloc(die::kPanelMaxCols * sizeof(double)));
   // three page-locked slots for the per-step uploads (R1^-1, R2^-1, H(j+1, j)); each step's Gram
   // downloads synchronise the stream before a slot is written again
   PinnedBuf& pin = bw.pin;
-  DIE_TRY(pin.alloc((size_t)3 * rpo * rpo * sizeof(c2<T>)));
-  c2<T>* slot[3] = {(c2<T>*)pin.p, (c2<T>*)pin.p + (size_t)rpo * rpo, (c2<T>*)pin.p + (size_t)2 * rpo * rpo};
+  DIE_TRY(pin.alloc((size_t)3 * pw * pw * sizeof(c2<T>)));
+  c2<T>* slot[3] = {(c2<T>*)pin.p, (c2<T>*)pin.p + (size_t)pw * pw, (c2<T>*)pin.p + (size_t)2 * pw * pw};
   if (defl) {
-    DIE_TRY(part.alloc((size_t)rpo * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
+    DIE_TRY(part.alloc((size_t)pw * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
                        sizeof(double2)));
-    DIE_TRY(coef.alloc((size_t)rpo * c->r * sizeof(double2)));
-    DIE_TRY(cnt.alloc((size_t)rpo * die::kCounterStride * sizeof(int)));
-    DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)rpo * die::kCounterStride * sizeof(int), st));
+    DIE_TRY(coef.alloc((size_t)pw * c->r * sizeof(double2)));
+    DIE_TRY(cnt.alloc((size_t)pw * die::kCounterStride * sizeof(int)));
+    DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)pw * die::kCounterStride * sizeof(int), st));
   }
   const double one = 1.0;
   DIE_HIP(hipMemcpyAsync(ones.p, &one, sizeof(double), hipMemcpyHostToDevice, st));
   {  // pick the FFT pass variants before any timing-sensitive work
     const int* pv = nullptr;
-    DIE_TRY(fft_plan<T>(c, rpo, st, &pv));
+    DIE_TRY(fft_plan<T>(c, pw, st, &pv));
     DIE_TRY(fft_plan<double>(c, nrhs, st, &pv));
   }
-  DIE_TRY(ensure_work(c, (size_t)std::max((size_t)nrhs * sizeof(double2), (size_t)rpo * sizeof(c2<T>)) * 2 * c->px *
+  DIE_TRY(ensure_work(c, (size_t)std::max((size_t)nrhs * sizeof(double2), (size_t)pw * sizeof(c2<T>)) * 2 * c->px *
                              c->ny, st));
   c2<T>* vb = Vb.as<c2<T>>();
   LongGemm &lg64 = bw.lg64, &lgT = bw.lgT;  // scratch of the long inner-dimension products
@@ -1408,6 +1417,9 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   std::vector<double> bnorm(nrhs), rnorm(nrhs), snorm(nrhs), hn(nrhs), relres(nrhs, 1.0);
   std::vector<int> act(nrhs, 1), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0),
       brk(nrhs, 0);
+  std::vector<char> full_cycle(c->nobj, 0);  // per object: its last cycle ran all m block steps
+  if (only)
+    for (int r = 0; r < nrhs; ++r) act[r] = (*only)[r] ? 1 : 0;
   if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
   DIE_HIP((die::launch_norm2<double>(b, n, n, nrhs, partn.as<double>(), nullptr, st)));
   DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), nullptr, st));
@@ -1434,6 +1446,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       if (!act[r]) continue;
       pa[r] += 1;
       rnorm[r] = std::sqrt(hn[r]);
+      const double before = relres[r];
       relres[r] = bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0;
       if (!std::isfinite(rnorm[r])) {
         brk[r] = 1;
@@ -1442,6 +1455,11 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         conv[r] = 1;
         act[r] = 0;
       } else if (iters[r] >= o.max_iters) {
+        act[r] = 0;
+      } else if (stalled && full_cycle[r / rpo] && relres[r] > 0.9 * before) {
+        // a full cycle took this residual down by less than 10%: the inner precision limits it
+        // (its condition times the FP32 rounding nears one); the caller finishes it in FP64
+        (*stalled)[r] = 1;
         act[r] = 0;
       } else {
         ++nact;
@@ -1469,7 +1487,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       if (k == 0) continue;
       // ---- first block: normalised residuals, rank-revealing Cholesky QR (two passes, FP64)
       double2* ra = Ra.as<double2>();
-      double2* v0 = ra + (size_t)rpo * n;
+      double2* v0 = ra + (size_t)pw * n;
       std::vector<double> inv(k);
       for (int q = 0; q < k; ++q) {
         DIE_HIP(hipMemcpyAsync(ra + (size_t)q * n, s + (size_t)K[q] * n, n * sizeof(double2), hipMemcpyDeviceToDevice,
@@ -1635,6 +1653,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       DIE_HIP(die::launch_add_cols<T>(tb, n, idxd.as<int>(), k, u, st));
       DIE_HIP(hipStreamSynchronize(st));  // K and the staging vectors are reused by the next object
       const int prods = (meff * p + k - 1) / k;
+      full_cycle[ob] = meff == m;
       progress = true;
       for (int q = 0; q < k; ++q) {
         const int r = K[q];
@@ -1834,8 +1853,47 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   if (o.block) {
     if (o.mixed == 2) return fail(DIE_E_INVALID, "block GMRES needs mixed = 0 or 1");
     if (o.block == 2 && o.mixed != 1) return fail(DIE_E_INVALID, "block = 2 (binary16 GEMMs) needs mixed = 1");
-    if (o.mixed) return block_gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
-    return block_gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+    if (!o.mixed) return block_gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+    // complex64 cycles with FP64 refinement; right-hand sides whose FP32 cycles stall (a full cycle
+    // gains less than 10%) are finished by FP64 block cycles from the fields reached, with buffers
+    // sized for them alone
+    std::vector<char> stalled(nrhs, 0);
+    std::vector<die_te_solve_info> i32(nrhs);
+    int rc = block_gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, i32.data(), st, &stalled);
+    int used = -1;
+    for (int r = 0; r < nrhs; ++r)
+      if (stalled[r]) used = std::max(used, i32[r].iters);
+    if (rc >= 0 && used >= 0) {
+      if (used < o.max_iters) {
+        die_te_solve_opts o64 = o;
+        o64.mixed = 0;
+        o64.block = 1;
+        o64.x0_given = 1;
+        o64.max_iters = o.max_iters - used;
+        std::vector<die_te_solve_info> i64(nrhs);
+        rc = block_gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o64, i64.data(), st,
+                                       nullptr, &stalled);
+        if (rc < 0) return rc;
+        for (int r = 0; r < nrhs; ++r) {
+          if (!stalled[r]) continue;
+          i32[r].status = i64[r].status;
+          i32[r].iters += i64[r].iters;
+          i32[r].products_A += i64[r].products_A;
+          i32[r].products_AR += i64[r].products_AR;
+          i32[r].cycles += i64[r].cycles;
+          i32[r].rel_res_true = i64[r].rel_res_true;
+        }
+      } else {
+        for (int r = 0; r < nrhs; ++r)
+          if (stalled[r]) i32[r].status = DIE_NOT_CONVERGED;
+      }
+      rc = DIE_OK;
+      for (int r = 0; r < nrhs; ++r)
+        if (i32[r].status != DIE_OK) rc = DIE_NOT_CONVERGED;
+    }
+    if (info)
+      for (int r = 0; r < nrhs; ++r) info[r] = i32[r];
+    return rc;
   }
   if (o.mixed == 2)
     return gmres_solve<float, _Float16>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);

@@ -191,6 +191,29 @@ def test_block_contexts_in_one_batch_call_with_profiling():
             assert op.relative_residual(g, e, host(u)[r], b[r]) <= 1.02e-8
 
 
+def test_block_context_reused_across_precisions():
+    """The block solver keeps its work buffers in the context: complex64, then complex128, then
+    complex64 solves on one context give the same fields as fresh contexts."""
+    g = centred_grid(32, 1.0, ny=28)
+    eps = cylinder(g, 0.35, 4.0 + 0.3j)
+    b = np.stack([plane_wave(g, p) for p in (0.2, 1.1, 2.6, 3.9, 5.0)])
+    s = api.Solver.from_grid(g, eps)
+    outs = []
+    for mixed, block in ((1, 2), (0, 1), (1, 1)):
+        u, rc, info = s.solve(dev(b), restart=15, max_iters=4000, tol=1e-8, mixed=mixed, block=block,
+                              orth=0 if block == 2 else 1)
+        assert rc == 0
+        fresh = api.Solver.from_grid(g, eps)
+        uf, rcf, _ = fresh.solve(dev(b), restart=15, max_iters=4000, tol=1e-8, mixed=mixed, block=block,
+                                 orth=0 if block == 2 else 1)
+        assert rcf == 0
+        assert rel(host(u), host(uf)) < 1e-6
+        for r in range(b.shape[0]):
+            assert op.relative_residual(g, eps, host(u)[r], b[r]) <= 1.02e-8
+        outs.append(host(u))
+    assert rel(outs[0], outs[1]) < 2e-6 and rel(outs[2], outs[1]) < 2e-6
+
+
 def test_block_option_validation():
     g = centred_grid(16, 1.0)
     s = api.Solver.from_grid(g, cylinder(g, 0.3, 4.0))
