@@ -112,8 +112,13 @@ typedef struct {
                         products Q^H W and W -= Q H on the binary16 matrix cores: a binary16
                         planar shadow of the basis (real and imaginary parts as separate real
                         columns) and of W, FP32 accumulation and FP32 W, the projection
-                        coefficients rounded to binary16 (and kept so in H); CholQR2, products
+                        coefficients rounded to binary16 (and kept so in H); CholQR, products
                         and least squares as for 1.  Needs an even vector length.
+                        With mixed = 1 (block 1 or 2), a right-hand side whose full complex64
+                        cycle reduces its FP64 true residual by less than 10% leaves the
+                        complex64 iteration, and the call finishes it with FP64 block cycles
+                        (its iters, products and cycles then count both phases).  The block
+                        solver keeps its work buffers in the context until die_te_destroy.
                         0: per-rhs GMRES */
 } die_te_solve_opts;
 
