@@ -184,7 +184,7 @@ SIZE_CLASSES = (128, 256, 512, 1024)  # object o of the batched workload has siz
 def uneven_run(sizes, args):
     """Several size classes of the batched workload (4 objects x 64 angles each) solved in one
     die_te_solve_batch call: one context per object with the block solver and --contexts
-    per-object, else one context per grid size."""
+    per-object (classes up to 512^2), else one context per grid size."""
     import numpy as np
     import torch
     from synth import plane_wave, random_field_object
@@ -196,7 +196,7 @@ def uneven_run(sizes, args):
         objs = [random_field_object(n, seed=1000 + 4 * c + i) for i in range(4)]
         gn = objs[0][0]
         b1 = torch.from_numpy(np.stack([plane_wave(gn, 2.0 * math.pi * j / N_ANGLES) for j in range(N_ANGLES)])).cuda()
-        if per_object:
+        if per_object and n <= 512:  # a 1024^2 object's block buffers (~57 GB) allow one context per class
             for _, e in objs:
                 solvers.append(Solver.from_grid(gn, e))
                 Bs.append(b1)
