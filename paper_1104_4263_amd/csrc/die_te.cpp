@@ -1301,7 +1301,12 @@ struct BlockWork {
       scl, Uq, sq, Qs, Wsb, Whb, Cpart, Hbh;
   LongGemm lg64, lgT;  // scratch of the long inner-dimension products (FP64 first block, basis precision)
   PinnedBuf pin;       // page-locked slots of the per-step uploads
+  DBuf Zall;                // per right-hand side: the correction V Y of its last cycle (FP64)
+  std::vector<char> zvalid;  // which columns of Zall hold one
 };
+// A narrowed block (at most this many right-hand sides of an object left) starts its cycle from
+// the residuals and the previous cycle's corrections of the same right-hand sides.
+constexpr int kAugmentMax = 16;
 
 // Host -> device copy of a small matrix through a page-locked slot, without waiting: the caller
 // rewrites the slot only after a later synchronisation of the stream.
@@ -1418,6 +1423,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   std::vector<int> act(nrhs, 1), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0),
       brk(nrhs, 0);
   std::vector<char> full_cycle(c->nobj, 0);  // per object: its last cycle ran all m block steps
+  DIE_TRY(bw.Zall.alloc((size_t)nrhs * n * sizeof(double2)));
+  if (bw.zvalid.size() != (size_t)nrhs) bw.zvalid.assign(nrhs, 0);
   if (only)
     for (int r = 0; r < nrhs; ++r) act[r] = (*only)[r] ? 1 : 0;
   if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
@@ -1496,9 +1503,27 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       }
       DIE_HIP(hipMemcpyAsync(scl.p, inv.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
       DIE_HIP((die::launch_scale<double, double>(ra, n, ra, n, scl.as<double>(), 1, n, k, nullptr, st)));
-      DIE_TRY(gemm_hn_long<double>(bh, lg64, k, k, ni, ra, ni, ra, ni, sm.as<double2>(), st));
+      // a narrowed block also takes its right-hand sides' previous corrections (a restart that keeps
+      // the last error approximation, against stagnation): extra columns of the first block that
+      // carry no right-hand side of their own
+      int kt = k;
+      if (k <= kAugmentMax)
+        for (int q = 0; q < k && kt < pw; ++q)
+          if (bw.zvalid[K[q]]) {
+            DIE_HIP(hipMemcpyAsync(ra + (size_t)kt * n, bw.Zall.as<double2>() + (size_t)K[q] * n,
+                                   n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+            ++kt;
+          }
+      DIE_TRY(gemm_hn_long<double>(bh, lg64, kt, kt, ni, ra, ni, ra, ni, sm.as<double2>(), st));
       Mat G, L;
-      DIE_TRY(download<double>(sm.p, k, k, G, st));
+      DIE_TRY(download<double>(sm.p, kt, kt, G, st));
+      std::vector<double> dz(kt, 1.0);  // the correction columns enter with unit norm
+      for (int i = k; i < kt; ++i) {
+        const double g = G(i, i).real();
+        dz[i] = (g > 0.0 && std::isfinite(g)) ? 1.0 / std::sqrt(g) : 0.0;
+      }
+      for (int j = 0; j < kt; ++j)
+        for (int i = 0; i < kt; ++i) G(i, j) *= dz[i] * dz[j];
       std::vector<int> perm;
       const int p = la::pivoted_cholesky(G, rank_tau2, L, perm);
       if (p == 0) continue;
@@ -1506,14 +1531,16 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       for (int j = 0; j < p; ++j)
         for (int i = 0; i <= j; ++i) R1(i, j) = std::conj(L(j, i));
       const Mat R1i = la::upper_inverse(R1);
-      Mat Msel(k, p), S0(p, k);
+      Mat Msel(kt, p), S0(p, k);
       for (int i = 0; i < p; ++i)
-        for (int j = 0; j < p; ++j) Msel(perm[i], j) = R1i(i, j);
-      for (int i = 0; i < k; ++i)
-        for (int q = 0; q < p; ++q) S0(q, perm[i]) = std::conj(L(i, q));
+        for (int j = 0; j < p; ++j) Msel(perm[i], j) = R1i(i, j) * dz[perm[i]];
+      // the k right-hand sides (columns 0 .. k-1, wherever the pivoting put them) in the p pivots
+      for (int i = 0; i < kt; ++i)
+        if (perm[i] < k)
+          for (int q = 0; q < p; ++q) S0(q, perm[i]) = std::conj(L(i, q));
       std::vector<double2> stage64;
       DIE_TRY(upload<double>(Msel, sm.p, st, stage64));
-      DIE_BLAS(gemm<double>(bh, kN, kN, ni, p, k, 1.0, ra, ni, sm.as<double2>(), k, 0.0, v0, ni));
+      DIE_BLAS(gemm<double>(bh, kN, kN, ni, p, kt, 1.0, ra, ni, sm.as<double2>(), kt, 0.0, v0, ni));
       DIE_TRY(gemm_hn_long<double>(bh, lg64, p, p, ni, v0, ni, v0, ni, sm.as<double2>(), st));
       Mat G2, R2;
       DIE_TRY(download<double>(sm.p, p, p, G2, st));
@@ -1647,6 +1674,12 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       }
       c2<T>* tb = Tb.as<c2<T>>();
       DIE_TRY(gemm_rows_long<T>(bh, ni, k, nc, 1.0, vb, ni, sm.as<c2<T>>(), nc, 0.0, tb, ni));
+      // keep each right-hand side's correction V Y (before the projector) for a later narrowed block
+      for (int q = 0; q < k; ++q) {
+        DIE_HIP((die::launch_scale<T, double>(tb + (size_t)q * n, n, bw.Zall.as<double2>() + (size_t)K[q] * n, n,
+                                              ones.as<double>(), 0, n, 1, nullptr, st)));
+        bw.zvalid[K[q]] = 1;
+      }
       if (defl)
         DIE_TRY(apply_pinv<T>(c, tb, tb, k, part.as<double2>(), coef.as<double2>(), cnt.as<int>(), nullptr, st, k, ob));
       DIE_HIP(hipMemcpyAsync(idxd.p, K.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
