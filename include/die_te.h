@@ -117,8 +117,11 @@ typedef struct {
                         With mixed = 1 (block 1 or 2), a right-hand side whose full complex64
                         cycle reduces its FP64 true residual by less than 10% leaves the
                         complex64 iteration, and the call finishes it with FP64 block cycles
-                        (its iters, products and cycles then count both phases).  The block
-                        solver keeps its work buffers in the context until die_te_destroy.
+                        (its iters, products and cycles then count both phases).  When at most
+                        16 right-hand sides of an object remain, a cycle's first block also
+                        holds their corrections from the previous cycle.  The block solver
+                        keeps its work buffers (and those corrections) in the context until
+                        die_te_destroy.
                         0: per-rhs GMRES */
 } die_te_solve_opts;
 
