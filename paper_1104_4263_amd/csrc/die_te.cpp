@@ -1424,7 +1424,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       brk(nrhs, 0);
   std::vector<char> full_cycle(c->nobj, 0);  // per object: its last cycle ran all m block steps
   DIE_TRY(bw.Zall.alloc((size_t)nrhs * n * sizeof(double2)));
-  if (bw.zvalid.size() != (size_t)nrhs) bw.zvalid.assign(nrhs, 0);
+  // corrections kept from an earlier call serve only its continuation (a call given x0)
+  if (bw.zvalid.size() != (size_t)nrhs || !o.x0_given) bw.zvalid.assign(nrhs, 0);
   if (only)
     for (int r = 0; r < nrhs; ++r) act[r] = (*only)[r] ? 1 : 0;
   if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
@@ -1458,6 +1459,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       if (!std::isfinite(rnorm[r])) {
         brk[r] = 1;
         act[r] = 0;
+        bw.zvalid[r] = 0;
       } else if (relres[r] <= tol || bnorm[r] == 0.0) {
         conv[r] = 1;
         act[r] = 0;
