@@ -302,8 +302,8 @@ def main():
     if args.block_orth is None:
         args.block_orth = 0 if args.block_gemm == 16 else 1
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
-              "in DESIGN.md and is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver has no path across GPUs",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
