@@ -1,6 +1,6 @@
 """Host dense algebra of the block solver (dense.hpp), compiled with g++ and checked against
-numpy: rank-revealing pivoted Cholesky of a Gram matrix, the scaled Cholesky QR factor, and
-the upper triangular inverse."""
+numpy: rank-revealing pivoted Cholesky of a Gram matrix, the scaled Cholesky QR factor with its
+smallest scaled pivot, the upper triangular inverse and the product of upper triangular matrices."""
 import os
 import shutil
 import subprocess
@@ -34,6 +34,11 @@ int main(int argc, char** argv) {
     Mat X = upper_inverse(R);
     for (int j = 0; j < k; ++j) for (int i = 0; i < k; ++i) std::printf("%.17g %.17g\n", R(i, j).real(), R(i, j).imag());
     for (int j = 0; j < k; ++j) for (int i = 0; i < k; ++i) std::printf("%.17g %.17g\n", X(i, j).real(), X(i, j).imag());
+    Mat R2; double mp = -1.0;
+    chol_upper_scaled(G, 1e-13, R2, &mp);
+    std::printf("%.17g\n", mp);
+    Mat P = upper_product(R, R);
+    for (int j = 0; j < k; ++j) for (int i = 0; i < k; ++i) std::printf("%.17g %.17g\n", P(i, j).real(), P(i, j).imag());
   }
   return 0;
 }
@@ -62,10 +67,14 @@ def run(exe, G, tau2):
     L = np.array(vals).reshape(k, k).T
     ok = out[2 + k * k] == "1"
     R = X = None
+    run.extra = None
     if ok:
         base = 3 + k * k
         R = np.array([complex(*map(float, ln.split())) for ln in out[base:base + k * k]]).reshape(k, k).T
         X = np.array([complex(*map(float, ln.split())) for ln in out[base + k * k:base + 2 * k * k]]).reshape(k, k).T
+        mp = float(out[base + 2 * k * k])
+        P = np.array([complex(*map(float, ln.split())) for ln in out[base + 2 * k * k + 1:base + 3 * k * k + 1]])
+        run.extra = (mp, P.reshape(k, k).T)
     return p, perm, L, ok, R, X
 
 
@@ -82,6 +91,14 @@ def test_full_rank_gram(driver):
     assert np.allclose(np.triu(R), R)
     assert np.allclose(R.conj().T @ R, G, rtol=0, atol=1e-12 * np.abs(G).max())
     assert np.allclose(X @ R, np.eye(6), atol=1e-10)
+    # smallest pivot of the unit-diagonal Gram's Cholesky, and the triangular product R R
+    mp, P = run.extra
+    d = 1.0 / np.sqrt(np.diag(G).real)
+    S = G * d[:, None] * d[None, :]
+    piv = np.diag(np.linalg.cholesky(S)).real ** 2
+    assert abs(mp - piv.min()) <= 1e-12
+    assert np.allclose(P, R @ R, rtol=0, atol=1e-12 * np.abs(R @ R).max())
+    assert np.allclose(np.tril(P, -1), 0)
 
 
 def test_rank_deficient_gram_selects_independent_columns(driver):
