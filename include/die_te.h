@@ -87,7 +87,9 @@ typedef struct {
                         and the deflation basis stay FP64); 2: as 1 with the Krylov basis
                         stored as complex binary16 (half the basis traffic; dots, Hessenberg
                         and Givens still FP64; needs orth = 1) */
-  int x0_given;      /* 1: e_tot holds the initial guess on entry; 0: start from zero */
+  int x0_given;      /* 1: e_tot holds the initial guess on entry; 0: start from zero.  A
+                        given guess whose FP64 residual ||b - A x0|| is non-finite or not
+                        below ||b|| is replaced by zero (plain GMRES is the fallback) */
   double reg_margin; /* regularized runs end a cycle when the regularized residual estimate
                         reaches reg_margin * (the target scaled to the cycle); 0 -> 0.1 */
   int orth;          /* Arnoldi orthogonalisation: 0 = CGS2 (two projections per step, four
@@ -144,11 +146,12 @@ typedef struct {
 int die_te_setup(die_te_ctx **ctx, const die_te_grid *grid, const void *eps_r,
                  const die_te_setup_opts *opts, void *stream);
 
-/* A context for nobj objects (1 <= nobj <= 65536) on one grid: the batched
- * many-object / many-incidence regime of the paper's learning experiments
- * (Section 6), where every object shares the grid, hence the symbol, and keeps
- * its own contrasts and, when deflate_k > 0, its own deflation data (one offline
- * eigensolve per object; Section 4, eq. DeflatingPrecondtioner).
+/* A context for nobj objects (1 <= nobj <= 65536) on one grid.  Each object is the
+ * collocation system of Section 4 (eq. A11 family) on its own; the paper solves one
+ * object and one incidence at a time, and solving many of them in the same launches
+ * is this library's batching, not the paper's.  Every object shares the grid, hence
+ * the symbol, and keeps its own contrasts and, when deflate_k > 0, its own deflation
+ * data (one offline eigensolve per object; Section 4, eq. DeflatingPrecondtioner).
  * eps_r: device, complex128 [nobj][ny][nx].  Every entry point that takes nrhs
  * then requires nrhs to be a multiple of nobj and maps right-hand side r to
  * object r / (nrhs / nobj): fields are grouped object by object.  die_te_setup is
@@ -176,7 +179,9 @@ int die_te_regularize(die_te_ctx *ctx, const void *x, void *y, int nrhs, int pre
  *        entry when opts->x0_given).
  * info:  host array of nrhs records (may be NULL).
  * Returns DIE_OK when every RHS converged, DIE_NOT_CONVERGED when some did not
- * (their best iterate is returned), < 0 on error.  Synchronises `stream`. */
+ * (each of those gets back the iterate with the lowest FP64 true residual met at the
+ * start of a cycle, and info reports that residual), < 0 on error (info records the
+ * solver did not reach read status < 0).  Synchronises `stream`. */
 int die_te_solve(die_te_ctx *ctx, const void *e_in, void *e_tot, int nrhs,
                  const die_te_solve_opts *opts, die_te_solve_info *info, void *stream);
 

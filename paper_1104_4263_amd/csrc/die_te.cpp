@@ -615,6 +615,26 @@ struct CycleGraph {
   }
 };
 
+// Copy the kept best iterate back into u for every right-hand side that ended without
+// convergence or breakdown at a true residual above its best one (synchronises st).
+int restore_best(double2* u, const double2* ubest, size_t n, int nrhs, const std::vector<int>& conv,
+                 const std::vector<int>& brk, const std::vector<double>& best, std::vector<double>& relres,
+                 std::vector<int>& bm, int* dmask, const double* one, hipStream_t st) {
+  int nb = 0;
+  for (int r = 0; r < nrhs; ++r) {
+    bm[r] = !conv[r] && !brk[r] && best[r] < relres[r];
+    if (bm[r]) {
+      relres[r] = best[r];
+      ++nb;
+    }
+  }
+  if (!nb) return DIE_OK;
+  DIE_HIP(hipMemcpyAsync(dmask, bm.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+  DIE_HIP((die::launch_scale<double, double>(ubest, n, u, n, one, 0, n, nrhs, dmask, st)));
+  DIE_HIP(hipStreamSynchronize(st));
+  return DIE_OK;
+}
+
 template <class T, class TB = T>
 int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
                 die_te_solve_info* info, hipStream_t st) {
@@ -690,6 +710,17 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   std::vector<int> act(nrhs, 1), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0),
       brk(nrhs, 0);
   std::vector<double> relres(nrhs, 1.0);
+  // best iterate so far per right-hand side (returned when the tolerance is not reached: the
+  // regularized cycles minimise ||A_R r||, so ||r|| need not decrease from cycle to cycle)
+  DBuf Ubest, bmask, oned;
+  DIE_TRY(Ubest.alloc(dbytes));
+  DIE_TRY(bmask.alloc((size_t)nrhs * sizeof(int)));
+  DIE_TRY(oned.alloc(sizeof(double)));
+  const double one = 1.0;
+  DIE_HIP(hipMemcpyAsync(oned.p, &one, sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<double> best(nrhs, std::numeric_limits<double>::infinity());
+  std::vector<int> bm(nrhs, 0);
+  bool first_check = true;
 
   if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
   DIE_HIP((die::launch_norm2<double>(b, n, n, nrhs, partn.as<double>(), nullptr, st)));
@@ -732,13 +763,17 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), dact, st));
     DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     DIE_HIP(hipStreamSynchronize(st));
-    int nact = 0;
+    int nact = 0, nfb = 0;
     for (int r = 0; r < nrhs; ++r) {
       if (!act[r]) continue;
       pa[r] += 1;
       rnorm[r] = std::sqrt(hn[r]);
       relres[r] = bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0;
-      if (!std::isfinite(rnorm[r])) {
+      if (first_check && o.x0_given && !(std::isfinite(rnorm[r]) && rnorm[r] < bnorm[r])) {
+        // a given guess that is non-finite or no better than zero is replaced by zero
+        DIE_HIP(hipMemsetAsync(u + (size_t)r * n, 0, n * sizeof(double2), st));
+        ++nfb;
+      } else if (!std::isfinite(rnorm[r])) {
         brk[r] = 1;
         act[r] = 0;
       } else if (relres[r] <= tol || bnorm[r] == 0.0) {
@@ -750,7 +785,25 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
         ++nact;
       }
     }
+    first_check = false;
+    if (nfb) continue;  // residuals of the zeroed guesses
     if (nact == 0) break;
+    // the iterate about to be corrected is kept when it is the best one so far
+    {
+      int nb = 0;
+      for (int r = 0; r < nrhs; ++r) {
+        bm[r] = act[r] && relres[r] < best[r];
+        if (bm[r]) {
+          best[r] = relres[r];
+          ++nb;
+        }
+      }
+      if (nb) {
+        DIE_HIP(hipMemcpyAsync(bmask.p, bm.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+        DIE_HIP((die::launch_scale<double, double>(u, n, Ubest.as<double2>(), n, oned.as<double>(), 0, n, nrhs,
+                                                   bmask.as<int>(), st)));
+      }
+    }
     DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     // ---- cycle right-hand side s = A_R res (or res), beta0, q0 = s / beta0
     const double2* s = res;
@@ -906,6 +959,9 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
       }
     }
   }
+  // right-hand sides that stopped short of the tolerance get their best iterate back
+  DIE_TRY(restore_best(u, Ubest.as<double2>(), n, nrhs, conv, brk, best, relres, bm, bmask.as<int>(),
+                       oned.as<double>(), st));
   int rc = DIE_OK;
   for (int r = 0; r < nrhs; ++r) {
     if (brk[r]) rc = std::min(rc, (int)DIE_E_BREAKDOWN);
@@ -1303,6 +1359,7 @@ struct BlockWork {
   PinnedBuf pin;       // page-locked slots of the per-step uploads
   DBuf Zall;                // per right-hand side: the correction V Y of its last cycle (FP64)
   std::vector<char> zvalid;  // which columns of Zall hold one
+  DBuf Ubest, bmask;         // best iterate so far per right-hand side, and the copy mask
 };
 // A narrowed block (at most this many right-hand sides of an object left) starts its cycle from
 // the residuals and the previous cycle's corrections of the same right-hand sides.
@@ -1426,6 +1483,24 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(bw.Zall.alloc((size_t)nrhs * n * sizeof(double2)));
   // corrections kept from an earlier call serve only its continuation (a call given x0)
   if (bw.zvalid.size() != (size_t)nrhs || !o.x0_given) bw.zvalid.assign(nrhs, 0);
+  // best iterate so far (returned when the tolerance is not reached)
+  DIE_TRY(bw.Ubest.alloc(dbytes));
+  DIE_TRY(bw.bmask.alloc((size_t)nrhs * sizeof(int)));
+  std::vector<double> best(nrhs, std::numeric_limits<double>::infinity());
+  std::vector<int> bm(nrhs, 0);
+  bool first_check = true;
+  // the records of every right-hand side as they stand (also before a breakdown return)
+  auto fill_info = [&]() {
+    if (!info) return;
+    for (int r = 0; r < nrhs; ++r) {
+      info[r].status = brk[r] ? DIE_E_BREAKDOWN : (conv[r] ? DIE_OK : DIE_NOT_CONVERGED);
+      info[r].iters = iters[r];
+      info[r].products_A = pa[r];
+      info[r].products_AR = par[r];
+      info[r].cycles = cycles[r];
+      info[r].rel_res_true = relres[r];
+    }
+  };
   if (only)
     for (int r = 0; r < nrhs; ++r) act[r] = (*only)[r] ? 1 : 0;
   if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
@@ -1449,14 +1524,20 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
     DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), dact, st));
     DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     DIE_HIP(hipStreamSynchronize(st));
-    int nact = 0;
+    int nact = 0, nfb = 0;
     for (int r = 0; r < nrhs; ++r) {
       if (!act[r]) continue;
       pa[r] += 1;
       rnorm[r] = std::sqrt(hn[r]);
       const double before = relres[r];
       relres[r] = bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0;
-      if (!std::isfinite(rnorm[r])) {
+      if (first_check && o.x0_given && !(std::isfinite(rnorm[r]) && rnorm[r] < bnorm[r])) {
+        // a given guess that is non-finite or no better than zero is replaced by zero
+        DIE_HIP(hipMemsetAsync(u + (size_t)r * n, 0, n * sizeof(double2), st));
+        bw.zvalid[r] = 0;
+        relres[r] = 1.0;
+        ++nfb;
+      } else if (!std::isfinite(rnorm[r])) {
         brk[r] = 1;
         act[r] = 0;
         bw.zvalid[r] = 0;
@@ -1474,6 +1555,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         ++nact;
       }
     }
+    first_check = false;
+    if (nfb) continue;  // residuals of the zeroed guesses
     if (nact == 0) break;
     DIE_HIP(hipMemcpyAsync(active.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     const double2* s = res;
@@ -1486,7 +1569,36 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
     DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), dact, st));
     DIE_HIP(hipMemcpyAsync(hn.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     DIE_HIP(hipStreamSynchronize(st));
-    for (int r = 0; r < nrhs; ++r) snorm[r] = std::sqrt(hn[r]);
+    nact = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      snorm[r] = std::sqrt(hn[r]);
+      if (!act[r]) continue;
+      if (!std::isfinite(snorm[r])) {
+        brk[r] = 1;
+        act[r] = 0;
+      } else if (!(snorm[r] > 0)) {
+        act[r] = 0;  // regularized residual vanished: nothing a cycle can do (as in the per-rhs solver)
+      } else {
+        ++nact;
+      }
+    }
+    if (nact == 0) break;
+    // the iterates about to be corrected are kept when they are the best ones so far
+    {
+      int nb = 0;
+      for (int r = 0; r < nrhs; ++r) {
+        bm[r] = act[r] && relres[r] < best[r];
+        if (bm[r]) {
+          best[r] = relres[r];
+          ++nb;
+        }
+      }
+      if (nb) {
+        DIE_HIP(hipMemcpyAsync(bw.bmask.p, bm.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+        DIE_HIP((die::launch_scale<double, double>(u, n, bw.Ubest.as<double2>(), n, ones.as<double>(), 0, n, nrhs,
+                                                   bw.bmask.as<int>(), st)));
+      }
+    }
     bool progress = false;  // some object took a block step this cycle
     for (int ob = 0; ob < c->nobj; ++ob) {
       std::vector<int> K;
@@ -1668,7 +1780,11 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         for (int j = 0; j < k && finite; ++j)
           for (int i = 0; i < nc; ++i)
             if (!std::isfinite(Y(i, j).real()) || !std::isfinite(Y(i, j).imag())) finite = false;
-        if (linfo != 0 || !finite) return fail(DIE_E_BREAKDOWN, "block GMRES: rank-deficient block Hessenberg");
+        if (linfo != 0 || !finite) {
+          for (int q = 0; q < k; ++q) brk[K[q]] = 1;
+          fill_info();
+          return fail(DIE_E_BREAKDOWN, "block GMRES: rank-deficient block Hessenberg");
+        }
         Mat Ys(nc, k);  // columns scaled back by the residual norms
         for (int j = 0; j < k; ++j)
           for (int i = 0; i < nc; ++i) Ys(i, j) = Y(i, j) * snorm[K[j]];
@@ -1698,21 +1814,22 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         if (reg) par[r] += prods;
       }
     }
-    if (!progress) return fail(DIE_E_BREAKDOWN, "block GMRES: no residual block could be orthonormalised");
+    if (!progress) {
+      for (int r = 0; r < nrhs; ++r)
+        if (act[r]) brk[r] = 1;
+      fill_info();
+      return fail(DIE_E_BREAKDOWN, "block GMRES: no residual block could be orthonormalised");
+    }
   }
+  // right-hand sides that stopped short of the tolerance get their best iterate back
+  DIE_TRY(restore_best(u, bw.Ubest.as<double2>(), n, nrhs, conv, brk, best, relres, bm, bw.bmask.as<int>(),
+                       ones.as<double>(), st));
   int rc = DIE_OK;
   for (int r = 0; r < nrhs; ++r) {
     if (brk[r]) rc = std::min(rc, (int)DIE_E_BREAKDOWN);
     else if (!conv[r] && rc == DIE_OK) rc = DIE_NOT_CONVERGED;
-    if (info) {
-      info[r].status = brk[r] ? DIE_E_BREAKDOWN : (conv[r] ? DIE_OK : DIE_NOT_CONVERGED);
-      info[r].iters = iters[r];
-      info[r].products_A = pa[r];
-      info[r].products_AR = par[r];
-      info[r].cycles = cycles[r];
-      info[r].rel_res_true = relres[r];
-    }
   }
+  fill_info();
   if (rc == DIE_E_BREAKDOWN) return fail(DIE_E_BREAKDOWN, "block GMRES met a non-finite value");
   return rc;
 }
@@ -1893,7 +2010,11 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
     // gains less than 10%) are finished by FP64 block cycles from the fields reached, with buffers
     // sized for them alone
     std::vector<char> stalled(nrhs, 0);
-    std::vector<die_te_solve_info> i32(nrhs);
+    // records the solver did not reach (an error return) read as errors, never as converged
+    die_te_solve_info unset{};
+    unset.status = DIE_E_HIP;
+    unset.rel_res_true = std::numeric_limits<double>::quiet_NaN();
+    std::vector<die_te_solve_info> i32(nrhs, unset);
     int rc = block_gmres_solve<float>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, i32.data(), st, &stalled);
     int used = -1;
     for (int r = 0; r < nrhs; ++r)
@@ -1905,10 +2026,9 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
         o64.block = 1;
         o64.x0_given = 1;
         o64.max_iters = o.max_iters - used;
-        std::vector<die_te_solve_info> i64(nrhs);
+        std::vector<die_te_solve_info> i64(nrhs, unset);
         rc = block_gmres_solve<double>(c, (const double2*)e_in, (double2*)e_tot, nrhs, o64, i64.data(), st,
                                        nullptr, &stalled);
-        if (rc < 0) return rc;
         for (int r = 0; r < nrhs; ++r) {
           if (!stalled[r]) continue;
           i32[r].status = i64[r].status;
@@ -1922,9 +2042,11 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
         for (int r = 0; r < nrhs; ++r)
           if (stalled[r]) i32[r].status = DIE_NOT_CONVERGED;
       }
-      rc = DIE_OK;
-      for (int r = 0; r < nrhs; ++r)
-        if (i32[r].status != DIE_OK) rc = DIE_NOT_CONVERGED;
+      if (rc >= 0) {
+        rc = DIE_OK;
+        for (int r = 0; r < nrhs; ++r)
+          if (i32[r].status != DIE_OK) rc = DIE_NOT_CONVERGED;
+      }
     }
     if (info)
       for (int r = 0; r < nrhs; ++r) info[r] = i32[r];

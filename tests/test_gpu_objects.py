@@ -1,7 +1,8 @@
-"""Contexts holding several objects on one grid (the many-object, many-incidence
-regime of the paper's learning experiments, Section 6): every product, projector
-and solve of a multi-object context must equal the same call on one-object
-contexts, and the products must equal the oracle's direct sum."""
+"""Contexts holding several objects on one grid (each object the collocation system
+of Section 4; solving many of them in the same launches is the library's batching,
+not the paper's): every product, projector and solve of a multi-object context must
+equal the same call on one-object contexts, and the products must equal the
+oracle's direct sum."""
 import numpy as np
 import pytest
 import torch
