@@ -164,6 +164,20 @@ int die_te_setup_multi(die_te_ctx **ctx, const die_te_grid *grid, int nobj, cons
  * x and y must not overlap.  Asynchronous on `stream`. */
 int die_te_matvec(die_te_ctx *ctx, const void *x, void *y, int nrhs, int prec, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): y = A x exactly as die_te_matvec, with
+ * the FFT intermediate (nrhs * 2 * px * ny complex values in the precision `prec`) held
+ * in a static per-device scratch array of 64 MiB instead of a buffer the context
+ * allocates; the call allocates nothing and never tunes the FFT passes (it uses the
+ * variants a die_te_matvec of the same batch-size class already uses, else the forced
+ * variant, else the radix tuned for the grid).  DIE_E_INVALID when the intermediate
+ * exceeds 64 MiB (e.g. 256 x 256 cells: at most 32 complex64 or 16 complex128 fields)
+ * or when the context's device is not current.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (different streams, or
+ * threads) race and give wrong results; serialise them.  Same arguments otherwise as
+ * die_te_matvec; asynchronous on `stream`. */
+int die_te_matvec_noalloc(die_te_ctx *ctx, const void *x, void *y, int nrhs, int prec, void *stream);
+
 /* y = A_R x = A(chi') x: the same operator with the regularizer contrast
  * chi' = 1/eps_r - 1 (Section 3, eq. InverseSymbol; Section 5).  Same arguments
  * and semantics as die_te_matvec. */

@@ -73,6 +73,7 @@ def load() -> ctypes.CDLL:
     lib.die_te_setup_multi.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(DieTeGrid), i, vp,
                                        ctypes.POINTER(DieTeSetupOpts), vp]
     lib.die_te_matvec.argtypes = [vp, vp, vp, i, i, vp]
+    lib.die_te_matvec_noalloc.argtypes = [vp, vp, vp, i, i, vp]
     lib.die_te_regularize.argtypes = [vp, vp, vp, i, i, vp]
     lib.die_te_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(DieTeSolveOpts), ctypes.POINTER(DieTeSolveInfo), vp]
     lib.die_te_solve_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp),

@@ -63,6 +63,11 @@ def die_te_matvec(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
                                _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))
 
 
+def die_te_matvec_noalloc(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
+    check(load().die_te_matvec_noalloc(ctx, _dev(x, (torch.complex128, torch.complex64), "x"),
+                                       _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))
+
+
 def die_te_regularize(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
     check(load().die_te_regularize(ctx, _dev(x, (torch.complex128, torch.complex64), "x"),
                                    _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))

@@ -31,6 +31,7 @@
 #include "green.hpp"
 #include "host.hpp"
 #include "ops.hpp"
+#include "scratch.hpp"
 #include "unet_internal.hpp"
 
 using die::c2;
@@ -1876,6 +1877,11 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
     return rc;
   };
   if (hipGetDevice(&c->dev) != hipSuccess) return guard(fail(DIE_E_HIP, "hipGetDevice failed"));
+  {  // device address of this device's static scratch (die_te_matvec_noalloc), once per device
+    const hipError_t es = die::scratch_init(c->dev);
+    if (es != hipSuccess)
+      return guard(fail(DIE_E_HIP, std::string("looking up the static scratch array failed: ") + hipGetErrorString(es)));
+  }
   c->nx = gr->nx; c->ny = gr->ny; c->px = px; c->py = py;
   c->lpx = ilog2(px); c->lpy = ilog2(py);
   c->h = gr->h; c->k = k;
@@ -1980,6 +1986,51 @@ static int product(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, vo
 
 int die_te_matvec(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream) {
   return product(c, x, y, nrhs, prec, stream, false);
+}
+
+int die_te_matvec_noalloc(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream) {
+  die_host::last_error().clear();
+  DIE_TRY(check_ctx(c));
+  if (!x || !y || nrhs < 1) return fail(DIE_E_INVALID, "null pointer or nrhs < 1");
+  if (x == y) return fail(DIE_E_INVALID, "x and y must not overlap");
+  if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
+  if (prec != DIE_C128 && prec != DIE_C64) return fail(DIE_E_INVALID, "prec must be DIE_C128 or DIE_C64");
+  const size_t es = prec == DIE_C128 ? sizeof(double2) : sizeof(float2);
+  const size_t need = (size_t)nrhs * 2 * c->px * c->ny * es;
+  if (need > die::kScratchBytes)
+    return fail(DIE_E_INVALID, "die_te_matvec_noalloc: nrhs * 2 * px * ny complex values (" + std::to_string(need) +
+                                   " bytes) exceed the static scratch of " + std::to_string(die::kScratchBytes) +
+                                   " bytes");
+  int cur = -1;
+  DIE_HIP(hipGetDevice(&cur));
+  if (cur != c->dev) return fail(DIE_E_INVALID, "the context's device must be the current device");
+  void* W = die::scratch_ptr(c->dev);
+  if (!W) return fail(DIE_E_HIP, "the static scratch of this device was not looked up at setup");
+  // pass variants without tuning (tuning allocates): those a product of this batch-size class
+  // already uses, else the forced variant, else the radix tuned for the grid with the full tile
+  const int pi = prec == DIE_C128 ? 0 : 1, bc = batch_class(nrhs);
+  int v[3] = {0, 0, 0};
+  if (c->fftv[pi][bc][0] >= 0) {
+    for (int p = 0; p < 3; ++p) v[p] = c->fftv[pi][bc][p];
+  } else if (c->fft_force >= 0) {
+    v[0] = v[1] = v[2] = c->fft_force;
+  } else {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune.find(TuneKey{c->dev, pi, c->lpx, c->lpy, c->nx, c->ny});
+    if (it != g_tune.end())
+      for (int p = 0; p < 3; ++p) v[p] = std::max(it->second.radix[p], 0);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int rpo = nrhs / c->nobj;
+  for (int pass = 0; pass < 3; ++pass) {
+    if (prec == DIE_C128)
+      DIE_HIP(launch_pass<double>(c, pass, v[pass], (const double2*)x, (double2*)y, (double2*)W, nrhs, nullptr, st,
+                                  rpo, chi_of<double>(c, false)));
+    else
+      DIE_HIP(launch_pass<float>(c, pass, v[pass], (const float2*)x, (float2*)y, (float2*)W, nrhs, nullptr, st, rpo,
+                                 chi_of<float>(c, false)));
+  }
+  return DIE_OK;
 }
 
 int die_te_regularize(die_te_ctx* c, const void* x, void* y, int nrhs, int prec, void* stream) {
