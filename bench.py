@@ -247,6 +247,87 @@ def uneven_run(sizes, args):
     return out
 
 
+# The paper's Table 2 (TE, tol 1e-8 on the solved system, fair memory: restart + r = 40): per
+# object (eps of the square) and system, the deflation size r, the restart and the iterations.
+PAPER_TABLE2 = {
+    "16": {"A": (0, 40, 15258), "A P^-1": (6, 34, 14002), "A_R A": (0, 40, 4030), "A_R A P^-1": (14, 26, 3626)},
+    "-16+1.5i": {"A": (0, 40, 1708), "A P^-1": (7, 33, 1659), "A_R A": (0, 40, 1021), "A_R A P^-1": (30, 10, 534)},
+    "16 with a 2.5+20i core": {"A": (0, 40, 11823), "A P^-1": (3, 37, 13156), "A_R A": (0, 40, 3032),
+                               "A_R A P^-1": (14, 26, 2911)},
+}
+
+
+def method_variants(cap_reg=24000, long_k=(20, 40)):
+    """The paper's four systems A, A P^-1, A_R A and A_R A P^-1 (per-rhs GMRES, FP64 and mixed
+    precision) on three workloads: the hard cylinder (256^2, eps = -2.5+0.2i, psi = 30 deg), its
+    half-size analog (128^2 over 2.2 lambda, radius 1 lambda, same eps and cell size) and the three
+    squares of the paper's Table 2 at 61^2 nodes with the table's r and restart.  Every solve is
+    accepted on the FP64 true residual; the paper's iteration counts are context only (its 3N system
+    and its regularized residual)."""
+    import numpy as np
+    import torch
+    from synth import workload, plane_wave, centred_grid, cylinder
+    from paper_1104_4263_amd import Solver
+
+    def run(g, e, b, reg, k, restart, cap, mixed, seed=1):
+        t0 = time.perf_counter()
+        sv = Solver.from_grid(g, e, regularize=reg, deflate_k=k, seed=seed)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, rc, inf = sv.solve(b, restart=restart, max_iters=cap, tol=TOL, mixed=mixed)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sv.close()
+        i = inf[0]
+        return {"converged": rc == 0, "iters": i["iters"], "products_A": i["products_A"],
+                "products_AR": i["products_AR"], "rel_res_true": i["rel_res_true"], "restart": restart, "k": k,
+                "setup_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 4)}
+
+    out = {}
+    systems = (("A", False, False), ("A P^-1", False, True), ("A_R A", True, False), ("A_R A P^-1", True, True))
+    # hard cylinder and its half-size analog: GMRES(30), k = 20
+    w = workload("cyl_hard")
+    cases = {"cylinder 256^2 (r = 2 lambda, eps = -2.5+0.2i, psi = 30 deg)": (w["grids"][0], w["eps"][0])}
+    gh = centred_grid(128, 2.2)
+    cases["cylinder 128^2 half-size analog (r = 1 lambda, same eps and h)"] = (gh, cylinder(gh, 1.0, -2.5 + 0.2j))
+    for cname, (gc, ec) in cases.items():
+        bc = torch.from_numpy(plane_wave(gc, math.pi / 6.0)).cuda()
+        res = {}
+        for name, reg, defl in systems:
+            for mixed in (False, True):
+                cap = cap_reg if reg else MAX_ITERS
+                key = name + (" mixed" if mixed else "")
+                res[key] = run(gc, ec, bc, reg, 20 if defl else 0, 30, cap, mixed)
+                log(f"{cname} {key}: {res[key]}")
+        out[cname] = res
+    # the hard cylinder's regularized systems with the larger deflation sizes
+    gc, ec = w["grids"][0], w["eps"][0]
+    bc = torch.from_numpy(plane_wave(gc, math.pi / 6.0)).cuda()
+    extra = {}
+    for k in long_k:
+        if k == 20:
+            continue
+        key = f"A_R A P^-1, k = {k}"
+        extra[key] = run(gc, ec, bc, True, k, 30, cap_reg, False)
+        log(f"cylinder 256^2 {key}: {extra[key]}")
+    out["cylinder 256^2 (r = 2 lambda, eps = -2.5+0.2i, psi = 30 deg)"].update(extra)
+    # the paper's squares (side lambda, 61^2 nodes), psi = 0, with Table 2's r and restart
+    ws = workload("paper_squares")
+    gs = ws["grids"][0]
+    bs = torch.from_numpy(plane_wave(gs, 0.0)).cuda()
+    for label, es in zip(PAPER_TABLE2, ws["eps"]):
+        res = {}
+        for name, reg, defl in systems:
+            r, restart, paper_it = PAPER_TABLE2[label][name]
+            for mixed in (False, True):
+                key = name + (" mixed" if mixed else "")
+                res[key] = run(gs, es, bs, reg, r, restart, MAX_ITERS if not reg else cap_reg, mixed)
+                res[key]["paper_iters"] = paper_it
+                log(f"square eps = {label} {key}: {res[key]}")
+        out[f"Table 2 square, eps = {label} (61^2 nodes)"] = res
+    return out
+
+
 def time_matvec(s, x, reps):
     """Average ms of one product call, timed with events on the stream the library launches on."""
     import torch
@@ -293,6 +374,8 @@ def main():
                          "solves, then time the batch from its guesses (several minutes)")
     ap.add_argument("--configured-deflation", action="store_true",
                     help="also run the batch with the configured k=16 deflation (about 40 s)")
+    ap.add_argument("--variants-only", action="store_true",
+                    help="only run the paper's four systems on the cylinders and Table 2's squares")
     ap.add_argument("--uneven", type=str, default="", metavar="SIZES",
                     help="also solve size classes of the batched workload on grids of different sizes in one "
                          "call (e.g. 128,256,512: 4 objects x 64 angles per class, seeds 1000 + object index)")
@@ -313,6 +396,9 @@ def main():
     from paper_1104_4263_amd._lib import DIE_PROF_PRODUCT, DIE_PROF_DOTS, DIE_PROF_AXPY, DIE_PROF_GEMM
 
     torch.cuda.set_device(0)
+    if args.variants_only:
+        print(json.dumps({"method_variants": method_variants()}), flush=True)
+        return
     objs = [random_field_object(256, seed=sd) for sd in OBJ_SEEDS]
     g = objs[0][0]
     eps = np.stack([e for _, e in objs])
@@ -586,28 +672,8 @@ def main():
         sd.close()
 
     if not args.no_variants:
-        # the hard cylinder (r = 2 lambda, eps = -2.5 + 0.2i, 256^2, psi = 30 deg), one solve per variant
-        w = workload("cyl_hard")
-        gc, ec = w["grids"][0], w["eps"][0]
-        bc = torch.from_numpy(plane_wave(gc, w["psi"][0])).cuda()
-        k = w["deflate_k"]
-        variants = {}
-        for name, reg, defl, mixed, cap in (("A", False, 0, False, 20000), ("A mixed", False, 0, True, 20000),
-                                            ("A P^-1", False, k, False, 20000),
-                                            ("A P^-1 mixed", False, k, True, 20000),
-                                            ("A_R A", True, 0, False, 3000), ("A_R A P^-1", True, k, False, 3000),
-                                            ("A_R A P^-1 mixed", True, k, True, 3000)):
-            sv = Solver.from_grid(gc, ec, regularize=reg, deflate_k=defl, seed=1)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, rc, inf = sv.solve(bc, restart=w["restart"], max_iters=cap, tol=TOL, mixed=mixed)
-            torch.cuda.synchronize()
-            tv = time.perf_counter() - t0
-            variants[name] = {"converged": rc == 0, "iters": inf[0]["iters"], "rel_res_true": inf[0]["rel_res_true"],
-                              "solve_s": round(tv, 4)}
-            log(f"cylinder variant {name}: {variants[name]}")
-            sv.close()
-        out["cylinder_variants"] = variants
+        # the paper's four systems on the hard cylinder, its 128^2 analog and Table 2's squares
+        out["method_variants"] = method_variants()
 
     if args.uneven:
         out["uneven"] = uneven_run([int(v) for v in args.uneven.split(",")], args)
