@@ -92,25 +92,96 @@ def read_traffic(kernel_tag, src_hash, algorithmic_bytes):
         return None
 
 
-def cpu_baseline(g, eps, products_per_solve):
-    """The FP64 oracle on the host: one O(N^2) direct-sum product of the same operator,
-    scaled by the operator applications one solve needs."""
-    import numpy as np
-    from oracle import operator as op
+def cpu_info():
+    """(BLAS threads, CPU model) of the host."""
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return int(threads), model
+
+
+def cpu_baseline(g, eps, n_angles):
+    """The FP64 oracle on the host cores, as it stands: direct-sum products (O(N^2)) at 64^2
+    and on the headline's 256^2 object, and the oracle's solver (dense assembly, LU factor,
+    per-angle triangular solves) at 64^2 and 32^2.  The oracle cannot solve the 256^2 headline
+    (its dense matrix would take 275 GB), so `value` is the 64^2 dense solve extrapolated to
+    256^2 (assembly O(N^2), factorisation O(N^3), each angle's solve O(N^2)) with the
+    factorisation shared by the object's n_angles angles, labelled as an extrapolation."""
+    import numpy as np
+    import scipy.linalg as sla
+    from oracle import operator as op
+    from synth import workload, plane_wave, centred_grid, cylinder
+    threads, model = cpu_info()
     rng = np.random.default_rng(0)
-    x = rng.standard_normal((2, g.ny, g.nx)) + 1j * rng.standard_normal((2, g.ny, g.nx))
-    chi = op.electric_contrast(eps)
-    t0 = time.perf_counter()
-    op.apply_operator(g, chi, x)
-    t = time.perf_counter() - t0
-    return {"value": 1.0 / (t * products_per_solve), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one direct-sum product of the {g.nx}x{g.ny} operator of object 0 ({t:.2f} s), scaled by "
-                      f"the mean {products_per_solve:.0f} operator applications per solve of the batched run"}
+    out = {}
+    # (1) direct-sum products
+    w = workload("cyl_small")
+    g64, e64 = w["grids"][0], w["eps"][0]
+    mv = {}
+    for name, gg, ee in (("64x64 (small cylinder)", g64, e64), (f"{g.nx}x{g.ny} (headline object 0)", g, eps)):
+        x = rng.standard_normal((2, gg.ny, gg.nx)) + 1j * rng.standard_normal((2, gg.ny, gg.nx))
+        chi = op.electric_contrast(ee)
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            op.apply_operator(gg, chi, x)
+            reps += 1
+            if time.perf_counter() - t0 > 1.0 or gg.nx > 64:
+                break
+        t = (time.perf_counter() - t0) / reps
+        mv[name] = {"s": round(t, 4), "matvecs_per_s": round(1.0 / t, 4)}
+        log(f"oracle direct-sum product {name}: {t:.3f} s")
+    out["oracle_matvecs"] = mv
+    # (2) dense solves: assembly, LU factor, per-angle solve
+    lu = {}
+    t64 = None
+    for n, gg, ee in ((64, g64, e64), (32, None, None)):
+        if gg is None:
+            gg = centred_grid(n, 0.6)
+            ee = cylinder(gg, 0.25, 4.0 + 0j)
+        t0 = time.perf_counter()
+        A = op.dense_operator(gg, op.electric_contrast(ee))
+        t1 = time.perf_counter()
+        f = sla.lu_factor(A, overwrite_a=True, check_finite=False)
+        t2 = time.perf_counter()
+        bs = np.stack([plane_wave(gg, 2.0 * math.pi * j / 8).ravel() for j in range(8)], axis=1)
+        sla.lu_solve(f, bs, check_finite=False)
+        t3 = time.perf_counter()
+        per_angle = (t3 - t2) / 8
+        lu[f"{n}x{n}"] = {"assemble_s": round(t1 - t0, 3), "factor_s": round(t2 - t1, 3),
+                          "solve_per_angle_s": round(per_angle, 5),
+                          "solves_per_s_one_angle": round(1.0 / (t3 - t0 - 7 * per_angle), 4),
+                          f"solves_per_s_{n_angles}_angles": round(n_angles / (t2 - t0 + n_angles * per_angle), 4)}
+        if n == 64:
+            t64 = (t1 - t0, t2 - t1, per_angle)
+        log(f"oracle dense solve {n}x{n}: {lu[f'{n}x{n}']}")
+        del A, f
+    out["oracle_dense_solves"] = lu
+    # (3) the 256^2 headline by extrapolation from 64^2
+    q = (g.nx * g.ny) / (64.0 * 64.0)
+    t_obj = t64[0] * q * q + t64[1] * q ** 3 + n_angles * t64[2] * q * q
+    value = n_angles / t_obj
+    total = sum(v["s"] for v in mv.values()) + sum(v["assemble_s"] + v["factor_s"] for v in lu.values())
+    out.update({"value": value, "unit": "solves/s", "cores": threads, "kind": "oracle",
+                "cpu_model": model, "blas_threads": threads,
+                "sample": (f"oracle dense LU solve at 64x64 (assembly {t64[0]:.1f} s, factor {t64[1]:.1f} s, "
+                           f"{t64[2] * 1e3:.1f} ms per angle) extrapolated to the {g.nx}x{g.ny} headline "
+                           f"(assembly x{q * q:.0f}, factor x{q ** 3:.0f}, per-angle solve x{q * q:.0f}; "
+                           f"{n_angles} angles per factorisation): an extrapolation, the 256^2 dense matrix "
+                           f"needs 275 GB; measured oracle figures beside it ({total:.1f} s of CPU work)"),
+                "extrapolated": True})
+    return out
 
 
 def learned_run(ntrain, g, eps, B, nsolve, value_batched, iters_batched):
@@ -328,6 +399,40 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
     return out
 
 
+PRODUCT_SRC = ("kernels_fft.hip", "fft.hpp", "ops.hpp", "common.hpp")  # the product kernels and their headers
+
+
+def product_roofline(n=1024, nrhs=64, reps=10):
+    """Roofline of the operator product (the three FFT pass kernels of one application of A)
+    on nrhs complex64 fields of an n x n grid (px = py = 2n), the size whose working set is far
+    beyond the 256 MB last-level cache: algorithmic bytes (22 R + 1) N s + 3 P s per launch of
+    the three passes, divided by their average duration from HIP events recorded on the stream
+    the library launches them on."""
+    import torch
+    from synth import centred_grid, cylinder
+    from paper_1104_4263_amd import Solver
+    gl = centred_grid(n, n / 48.0)
+    sl = Solver.from_grid(gl, cylinder(gl, n / 48.0 / 3.0, 4.0))
+    x = torch.randn(nrhs, 2, n, n, dtype=torch.complex64, device="cuda")
+    ms = time_matvec(sl, x, reps)
+    variants = sl.fft_plan(nrhs, torch.complex64)
+    sl.close()
+    del x
+    mb = product_model_bytes(n, n, 2 * n, 2 * n, nrhs, 8)
+    src = source_hash(*PRODUCT_SRC)
+    traffic = read_traffic(f"fft_product_c64_{n}x{nrhs}", src, mb)
+    gbs = mb / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else int(traffic),
+            "kernel": "operator product: die::k_rows_fwd + die::k_cols_symbol + die::k_rows_inv_sub",
+            "workload": f"{n}x{n} cells (px = py = {2 * n}), {nrhs} complex64 fields, one object",
+            "avg_launch_us": round(1000.0 * ms, 2), "algorithmic_bytes_per_launch": int(mb),
+            "bytes_model": "(22 R + 1) N s + 3 P s (pass 1: 2RN + N read, 4RN written; pass 2: 4RN + 3P read, "
+                           "4RN written; pass 3: 6RN read, 2RN written)",
+            "matvecs_per_s": round(nrhs / ms * 1e3, 1), "fft_variants": variants, "kernel_source_sha256": src,
+            "timing": f"HIP events on the launch stream around {reps} products after 2 warm-up products"}
+
+
 def time_matvec(s, x, reps):
     """Average ms of one product call, timed with events on the stream the library launches on."""
     import torch
@@ -351,7 +456,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--solver", default="block", choices=("block", "rhs"),
                     help="block: block GMRES(30), one block Krylov space per object (default); rhs: per-rhs GMRES(30)")
     ap.add_argument("--block-precision", type=int, default=32, choices=(32, 64),
@@ -374,6 +478,8 @@ def main():
                          "solves, then time the batch from its guesses (several minutes)")
     ap.add_argument("--configured-deflation", action="store_true",
                     help="also run the batch with the configured k=16 deflation (about 40 s)")
+    ap.add_argument("--product-only", action="store_true",
+                    help="only time the operator product at 1024^2 x 64 fields (for profiling)")
     ap.add_argument("--variants-only", action="store_true",
                     help="only run the paper's four systems on the cylinders and Table 2's squares")
     ap.add_argument("--uneven", type=str, default="", metavar="SIZES",
@@ -396,6 +502,18 @@ def main():
     from paper_1104_4263_amd._lib import DIE_PROF_PRODUCT, DIE_PROF_DOTS, DIE_PROF_AXPY, DIE_PROF_GEMM
 
     torch.cuda.set_device(0)
+    if args.product_only:
+        # the product kernels alone (for kernel traces and counters), then a 1 GiB copy whose
+        # counters calibrate FETCH_SIZE and WRITE_SIZE
+        r = product_roofline()
+        x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy of 1073741824 bytes done")
+        print(json.dumps({"roofline": r}), flush=True)
+        return
     if args.variants_only:
         print(json.dumps({"method_variants": method_variants()}), flush=True)
         return
@@ -589,10 +707,11 @@ def main():
                                                                        torch.complex64),
                                     "complex128": timed_ctx[0].fft_plan(N_ANGLES if concurrent else nsolve,
                                                                         torch.complex128)}},
-        "roofline": roofline,
+        "roofline": None,
+        "step_kernels": roofline,
     }
     if roofline_unc is not None:
-        out["roofline_uncontended"] = roofline_unc
+        out["step_kernels_uncontended"] = roofline_unc
 
     if block and not args.no_variants:
         # the per-rhs batched solver on the same 256 solves, for comparison
@@ -645,19 +764,10 @@ def main():
     log(f"batched-shape product: {out['matvec_batched']}")
     del x
 
-    if not args.no_large:
-        # the largest class of the batched workload: 1024^2 cells, 64 fields, complex64
-        gl = centred_grid(1024, 1024 / 48.0)
-        sl = Solver.from_grid(gl, cylinder(gl, 7.0, 4.0))
-        x = torch.randn(64, 2, 1024, 1024, dtype=torch.complex64, device="cuda")
-        mst = time_matvec(sl, x, 10)
-        mb = product_model_bytes(1024, 1024, 2048, 2048, 64, 8)
-        out["matvec_large"] = {"workload": "1024x1024 cells, 64 fields, complex64", "ms": round(mst, 3),
-                               "matvecs_per_s": round(64 / mst * 1e3, 1), "model_GBs": round(mb / mst / 1e6, 1),
-                               "frac_hbm": round(mb / mst / 1e6 / HBM_PEAK_GBS, 4)}
-        log(f"large product: {out['matvec_large']}")
-        del x
-        sl.close()
+    # the roofline of the product kernels at the largest class of the batched workload (1024^2
+    # cells, 64 fields, complex64), where each pass's working set is far beyond the last-level cache
+    out["roofline"] = product_roofline()
+    log(f"roofline (product at 1024^2 x 64): {out['roofline']}")
 
     if args.configured_deflation:
         sd = Solver.from_grid(g, eps, deflate_k=16, seed=1)
@@ -682,8 +792,8 @@ def main():
         out["learned"] = learned_run(args.learned, g, eps, B, nsolve, value, iters)
 
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle (one direct-sum product at 256^2) ...")
-        out["cpu_baseline"] = cpu_baseline(g, eps[0], float(prods.mean()))
+        log("timing the CPU oracle (direct-sum products, dense solves) ...")
+        out["cpu_baseline"] = cpu_baseline(g, eps[0], N_ANGLES)
         log(f"cpu baseline: {out['cpu_baseline']}")
     s.close()
     print(json.dumps(out), flush=True)
