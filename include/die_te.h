@@ -166,7 +166,8 @@ int die_te_matvec(die_te_ctx *ctx, const void *x, void *y, int nrhs, int prec, v
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): y = A x exactly as die_te_matvec, with
- * the FFT intermediate (nrhs * 2 * px * ny complex values in the precision `prec`) held
+ * the FFT intermediate (nrhs * 2 * px * ny4 complex values in the precision `prec`, ny4 = ny
+ * rounded up to a multiple of 4) held
  * in a static per-device scratch array of 64 MiB instead of a buffer the context
  * allocates; the call allocates nothing and never tunes the FFT passes (it uses the
  * variants a die_te_matvec of the same batch-size class already uses, else the forced

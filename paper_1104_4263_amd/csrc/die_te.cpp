@@ -204,6 +204,12 @@ template <class T> const c2<T>* sym_of(const die_te_ctx* c);
 template <> const double2* sym_of<double>(const die_te_ctx* c) { return c->sym64.as<double2>(); }
 template <> const float2* sym_of<float>(const die_te_ctx* c) { return c->sym32.as<float2>(); }
 
+// Bytes of the product's FFT intermediate for nrhs fields of es-byte complex values (the
+// tiled layout of the three passes: wtile_cols(px) x wtile_rows(ny) per component).
+size_t work_bytes(const die_te_ctx* c, size_t nrhs, size_t es) {
+  return nrhs * 2 * (size_t)die::wtile_cols(c->px) * die::wtile_rows(c->ny) * es;
+}
+
 int ensure_work(die_te_ctx* c, size_t bytes, hipStream_t st) {
   if (c->work.p && c->work.bytes >= bytes) return DIE_OK;
   if (c->work.p) DIE_HIP(hipStreamSynchronize(st));
@@ -272,7 +278,7 @@ int fft_plan(die_te_ctx* c, int nrhs, hipStream_t st, const int** out) {
     DIE_TRY(xb.alloc(vbytes));
     DIE_TRY(yb.alloc(vbytes));
     DIE_HIP(hipMemsetAsync(xb.p, 0, vbytes, st));
-    DIE_TRY(ensure_work(c, (size_t)R * 2 * c->px * c->ny * sizeof(c2<T>), st));
+    DIE_TRY(ensure_work(c, work_bytes(c, R, sizeof(c2<T>)), st));
     c2<T>* W = c->work.as<c2<T>>();
     const c2<T>* chi = chi_of<T>(c, false);
     hipEvent_t e0, e1;
@@ -329,7 +335,7 @@ int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const 
              int rpo, int obj0 = 0) {
   const int* v = nullptr;
   DIE_TRY(fft_plan<T>(c, nrhs, st, &v));
-  DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * sizeof(c2<T>), st));
+  DIE_TRY(ensure_work(c, work_bytes(c, nrhs, sizeof(c2<T>)), st));
   c2<T>* W = c->work.as<c2<T>>();
   const int nchi = rpo > 0 ? (nrhs + rpo - 1) / rpo : 1;
   ProfScope prof(c, DIE_PROF_PRODUCT, st, product_bytes(c, live_count(c, nrhs), nchi, sizeof(c2<T>)));
@@ -689,7 +695,7 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
     DIE_TRY(fft_plan<T>(c, nrhs, st, &pv));
     DIE_TRY(fft_plan<double>(c, nrhs, st, &pv));
   }
-  DIE_TRY(ensure_work(c, (size_t)nrhs * 2 * c->px * c->ny * std::max(sizeof(c2<T>), sizeof(double2)), st));
+  DIE_TRY(ensure_work(c, work_bytes(c, nrhs, std::max(sizeof(c2<T>), sizeof(double2))), st));
   // one-reduction Arnoldi: raw dots, unrotated Hessenberg, first projections, axpy coefficients
   const int dstride = 2 * (m + 2);
   DBuf Dd, Hu, cprev, coef, part2;
@@ -1472,8 +1478,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
     DIE_TRY(fft_plan<T>(c, pw, st, &pv));
     DIE_TRY(fft_plan<double>(c, nrhs, st, &pv));
   }
-  DIE_TRY(ensure_work(c, (size_t)std::max((size_t)nrhs * sizeof(double2), (size_t)pw * sizeof(c2<T>)) * 2 * c->px *
-                             c->ny, st));
+  DIE_TRY(ensure_work(c, std::max(work_bytes(c, nrhs, sizeof(double2)), work_bytes(c, pw, sizeof(c2<T>))), st));
   c2<T>* vb = Vb.as<c2<T>>();
   LongGemm &lg64 = bw.lg64, &lgT = bw.lgT;  // scratch of the long inner-dimension products
   std::vector<c2<T>> stage;
@@ -1996,7 +2001,7 @@ int die_te_matvec_noalloc(die_te_ctx* c, const void* x, void* y, int nrhs, int p
   if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
   if (prec != DIE_C128 && prec != DIE_C64) return fail(DIE_E_INVALID, "prec must be DIE_C128 or DIE_C64");
   const size_t es = prec == DIE_C128 ? sizeof(double2) : sizeof(float2);
-  const size_t need = (size_t)nrhs * 2 * c->px * c->ny * es;
+  const size_t need = work_bytes(c, nrhs, es);
   if (need > die::kScratchBytes)
     return fail(DIE_E_INVALID, "die_te_matvec_noalloc: nrhs * 2 * px * ny complex values (" + std::to_string(need) +
                                    " bytes) exceed the static scratch of " + std::to_string(die::kScratchBytes) +

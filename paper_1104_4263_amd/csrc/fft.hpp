@@ -150,7 +150,9 @@ __host__ __device__ constexpr int fft_row_stride(int n, int elem_bytes) {
   return n + (n >> fft_pad_shift(elem_bytes)) + 5;
 }
 
-template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int MAPR> struct RegFft {
+// MAP0: thread mapping of the first stage, MAPR of the stages after it, MAPL of the last stage
+// (when there is more than one).
+template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int MAPR, int MAPL = MAPR> struct RegFft {
   static constexpr int N = 1 << LOGN;
   static constexpr int LE = LOGE < LOGN ? LOGE : LOGN;
   static constexpr int E = 1 << LE;
@@ -164,7 +166,7 @@ template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int M
 
   static constexpr int lr(int s) { return (REM && (REV ? s == NS - 1 : s == 0)) ? REM : LE; }
   static constexpr int lp(int s) { return s == 0 ? 0 : lp(s - 1) + lr(s - 1); }
-  static constexpr int map(int s) { return s == 0 ? MAP0 : MAPR; }
+  static constexpr int map(int s) { return s == 0 ? MAP0 : (s == NS - 1 ? MAPL : MAPR); }
   static __device__ __forceinline__ int f(int j) { return j + (j >> PS); }
 
   // butterfly (array b, index i) of thread t, slot u, in stage S

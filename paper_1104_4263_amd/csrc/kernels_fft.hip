@@ -48,9 +48,14 @@ template <class T> __host__ __device__ constexpr int rows_ty(int logn, int v = 0
 template <class T> __host__ __device__ constexpr int rows_threads(int logn, int v = 0) {
   return rows_ty<T>(logn, v) * (1 << logn) / fft_e<T>(logn, v);
 }
+// Columns per block of the column passes.  The exchange buffer holds one field component at a
+// time; at least kWTile columns where it fits, so that a block reads and writes whole lines of
+// the tiled intermediate (kWTile columns x kWTile rows).
 template <class T> __host__ __device__ constexpr int cols_cx(int logn, int v = 0) {
   int n = 1 << logn, es = (int)sizeof(c2<T>), cx = 16;
   while (cx > 1 && (2 * cx * fft_row_stride(n, es) * es > kLdsBudget || cx * n / fft_e<T>(logn, v) > 1024)) cx >>= 1;
+  while (cx < kWTile && 2 * cx * fft_row_stride(n, es) * es <= kLdsBudget && 2 * cx * n / fft_e<T>(logn, v) <= 1024)
+    cx <<= 1;
   return (v & 2) && cx > 1 ? cx >> 1 : cx;
 }
 template <class T> __host__ __device__ constexpr int cols_threads(int logn, int v = 0) {
@@ -100,7 +105,9 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* _
           v[0][u * F::R0 + q] = a;
         }
       F::template run<INV>(v, lds, tw, t);
-      c2<T>* Ws = W + s * N * nrows;
+      // the product's intermediate is tiled (wtile_index); the plain transforms store W[s][x][y]
+      const int rows4 = wtile_rows(nrows);
+      c2<T>* Ws = W + s * (HALF ? (size_t)wtile_cols(N) * rows4 : (size_t)N * nrows);
 #pragma unroll
       for (int u = 0; u < E / F::RL; ++u)
 #pragma unroll
@@ -108,7 +115,8 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* _
           int b, pos;
           F::out_pos(t, u, q, b, pos);
           const int yy = y0 + b;
-          if (yy < nrows) Ws[(size_t)pos * nrows + yy] = v[0][u * F::RL + q];
+          if (yy < nrows)
+            Ws[HALF ? wtile_index(pos, yy, rows4) : (size_t)pos * nrows + yy] = v[0][u * F::RL + q];
         }
     }
   }
@@ -117,23 +125,31 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* _
 // ------------------------------------------------------------------ pass 2
 // Block: CX columns of one right-hand side, both components held by the same threads,
 // so the 2x2 symbol multiply runs in registers between the forward and the inverse
-// transform.  Logical blocks are ordered rhs-fastest: blocks sharing symbol columns run
-// on the same XCD at the same time.
+// transform.  Logical blocks sharing symbol columns run on the same XCD close together.
+// With more than one stage, the first stage loads and the last stage stores array-fast
+// (consecutive lanes on the CX columns of one row first), so that a wave moves whole lines of
+// the tiled intermediate; the symbol multiply between the transforms runs position-fast
+// (consecutive lanes on consecutive frequencies: contiguous symbol reads).
 template <class T, int LOGN, int V = 0>
 __global__ void __launch_bounds__(cols_threads<T>(LOGN, V))
 k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>* __restrict__ tw, int ncols,
               int nrows, int nrhs, const int* __restrict__ live) {
   constexpr int CX = cols_cx<T>(LOGN, V);
-  using F = RegFft<T, LOGN, CX, fft_le<T>(LOGN, V), 2, false, kPosFast, kPosFast>;
-  using G = RegFft<T, LOGN, CX, fft_le<T>(LOGN, V), 2, true, kPosFast, kPosFast>;
+  constexpr int LE = fft_le<T>(LOGN, V);
+  constexpr int MEDGE = LOGN > LE ? kArrFast : kPosFast;  // one stage only: position-fast throughout
+  using F = RegFft<T, LOGN, CX, LE, 2, false, MEDGE, kPosFast, kPosFast>;
+  using G = RegFft<T, LOGN, CX, LE, 2, true, kPosFast, kPosFast, MEDGE>;
   static_assert(G::R0 == F::RL, "inverse must start with the forward's last radix");
   constexpr int N = F::N, E = F::E;
   __shared__ c2<T> lds[F::LDS_ELEMS];
+  // logical order rhs-fastest: blocks sharing symbol columns run on the same XCD together
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int r = L % nrhs, x0 = (L / nrhs) * CX;
   int t = threadIdx.x;
   if (live && !live[r]) return;
-  c2<T>* Wr = W + (size_t)r * 2 * ncols * nrows;
+  const int rows4 = wtile_rows(nrows);
+  const size_t plane = (size_t)wtile_cols(ncols) * rows4;  // one component of the tiled intermediate
+  c2<T>* Wr = W + (size_t)r * 2 * plane;
   c2<T> v[2][E];
 #pragma unroll
   for (int u = 0; u < E / F::R0; ++u)
@@ -146,7 +162,7 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       const bool lower = q * (N / F::R0) < N / 2;
 #pragma unroll
       for (int c = 0; c < 2; ++c)
-        v[c][e] = (lower && xx < ncols && pos < nrows) ? Wr[((size_t)c * ncols + xx) * nrows + pos] : mk<T>(0, 0);
+        v[c][e] = (lower && xx < ncols && pos < nrows) ? Wr[c * plane + wtile_index(xx, pos, rows4)] : mk<T>(0, 0);
     }
   F::template run<false>(v, lds, tw, t);
   asm volatile("" : "+v"(t));  // per-phase address arithmetic (hoisting it costs VGPRs)
@@ -176,7 +192,7 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       const int xx = x0 + b, e = u * G::RL + q;
       if (q * (N / G::RL) < N / 2 && xx < ncols && pos < nrows) {  // only rows < nrows <= N/2 are kept
 #pragma unroll
-        for (int c = 0; c < 2; ++c) Wr[((size_t)c * ncols + xx) * nrows + pos] = v[c][e];
+        for (int c = 0; c < 2; ++c) Wr[c * plane + wtile_index(xx, pos, rows4)] = v[c][e];
       }
     }
 }
@@ -227,7 +243,8 @@ k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* 
   const int tile = L % ntiles, s = L / ntiles, t = threadIdx.x;
   if (live && !live[s / spr]) return;
   const int y0 = tile * TY;
-  const c2<T>* Ws = W + (size_t)s * N * nrows;
+  const int rows4 = wtile_rows(nrows);
+  const c2<T>* Ws = W + (size_t)s * wtile_cols(N) * rows4;
   c2<T> v[1][E];
 #pragma unroll
   for (int uu = 0; uu < E / F::R0; ++uu)
@@ -236,7 +253,7 @@ k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* 
       int b, pos;
       F::in_pos(t, uu, q, b, pos);
       const int yy = y0 + b;
-      v[0][uu * F::R0 + q] = yy < nrows ? Ws[(size_t)pos * nrows + yy] : mk<T>(0, 0);
+      v[0][uu * F::R0 + q] = yy < nrows ? Ws[wtile_index(pos, yy, rows4)] : mk<T>(0, 0);
     }
   F::template run<true>(v, lds, tw, t);
   const size_t so = (size_t)s * nrows * nx;

@@ -14,9 +14,25 @@ hipError_t fft_tables(const double2** tw64, const float2** tw32);
 constexpr int kFftVariants = 4;
 constexpr int kFftTunedMinLog = 7;
 
+// The product's FFT intermediate is tiled: one plane per (right-hand side, component) of
+// wtile_cols(px) x wtile_rows(ny) values in kWTile x kWTile tiles (one 128-byte line of
+// complex64), the tiles of one column strip (kWTile columns) contiguous:
+// element (x, y) at ((x / kWTile) rows4 / kWTile + y / kWTile) kWTile^2 + (x % kWTile) kWTile
+// + y % kWTile, rows4 = wtile_rows(ny).  The column pass (kWTile columns per block) reads and
+// writes one contiguous run per block; the row passes (kWTile rows per block or more) whole
+// lines, adjacent ones for adjacent row tiles.
+constexpr int kWTile = 4;
+__host__ __device__ constexpr int wtile_rows(int ny) { return (ny + kWTile - 1) / kWTile * kWTile; }
+__host__ __device__ constexpr int wtile_cols(int px) { return (px + kWTile - 1) / kWTile * kWTile; }
+__host__ __device__ constexpr size_t wtile_index(int x, int y, int rows4) {
+  return ((size_t)(x / kWTile) * (rows4 / kWTile) + y / kWTile) * (kWTile * kWTile) + (x % kWTile) * kWTile +
+         y % kWTile;
+}
+
 // Pass 1.  For every set s = r * spr + c (r < nrhs right-hand sides, c < spr components)
 // and row y < nrows: W[s][x][y] = FFT_N( pad_N( chi[y][:] * x_in[s][y][:] ) )[x],
-// x < N = 2^logn (chi may be NULL).  x_in rows have nx <= N entries; W is transposed
+// x < N = 2^logn (chi may be NULL).  x_in rows have nx <= N entries; W is the tiled
+// intermediate above for the zero-padded product (2 nx <= N, not inverse), else transposed
 // ([N][nrows]).  A block handles the spr sets of rb right-hand sides (rb = 0: automatic).
 // chi holds one [nrows][nx] plane per object; right-hand side r uses plane r / rpo
 // (rpo = 0: every right-hand side uses the first plane).
@@ -25,14 +41,14 @@ hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x_in, const c2<T
                            int nx, int nrows, int nrhs, int spr, int rb, int rpo, const int* live,
                            hipStream_t st, int v = 0);
 
-// Pass 2.  For every rhs r and column x < ncols of W[r][c][x][0:nrows] (c = 0, 1):
+// Pass 2.  For every rhs r and column x < ncols of the tiled W (components c = 0, 1):
 // FFT_N over y (zero padded), 2x2 multiply by sym[x][ky][{11,12,22}], inverse FFT_N,
 // keep y < nrows; in place.
 template <class T>
 hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
                               const int* live, hipStream_t st, int v = 0);
 
-// Pass 3.  y_out[s][y][x] = u[s][y][x] - IFFT_N(W[s][:][y])[x] for x < nx.
+// Pass 3.  y_out[s][y][x] = u[s][y][x] - IFFT_N(W[s][:][y])[x] for x < nx (W tiled).
 template <class T, class S>
 hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y_out, int nx,
                                int nrows, int nsets, int sets_per_rhs, const int* live,
