@@ -340,11 +340,17 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
     from synth import workload, plane_wave, centred_grid, cylinder
     from paper_1104_4263_amd import Solver
 
-    def run(g, e, b, reg, k, restart, cap, mixed, seed=1):
+    def run(g, e, b, reg, k, restart, cap, mixed, seed=1, memory=None):
+        """k = -1: automatic deflation size; memory: restart = memory - r (fair memory)."""
         t0 = time.perf_counter()
         sv = Solver.from_grid(g, e, regularize=reg, deflate_k=k, seed=seed)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if k == -1:
+            ritz, _, _ = sv.deflation_info()
+            k = int((ritz.abs() > 0).sum())
+            if memory is not None:
+                restart = max(memory - k, 5)
         _, rc, inf = sv.solve(b, restart=restart, max_iters=cap, tol=TOL, mixed=mixed)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -395,6 +401,11 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
                 res[key] = run(gs, es, bs, reg, r, restart, MAX_ITERS if not reg else cap_reg, mixed)
                 res[key]["paper_iters"] = paper_it
                 log(f"square eps = {label} {key}: {res[key]}")
+        # Section 5's automatic deflation size (radius rule) with the fair-memory restart 40 - r
+        res["A_R A P^-1, automatic r"] = run(gs, es, bs, True, -1, 0, cap_reg, False, memory=40)
+        res["A_R A P^-1, automatic r"]["deflation_radius"] = round(
+            __import__("paper_1104_4263_amd").die_te_deflation_radius(es, True), 4)
+        log(f"square eps = {label} automatic r: {res['A_R A P^-1, automatic r']}")
         out[f"Table 2 square, eps = {label} (61^2 nodes)"] = res
     return out
 

@@ -68,17 +68,24 @@ typedef struct {
   int deflate_k;           /* r >= 0: deflate the r largest-magnitude eigenvalues of the
                               solved operator (A_R A, or A) with the right preconditioner
                               P^-1 = I + V (T^-1 - I) V^*, T = V^* M V (Section 4,
-                              eq. DeflatingPrecondtioner); 0 = no deflation */
+                              eq. DeflatingPrecondtioner); 0 = no deflation;
+                              -1 = automatic (Section 5): every eigenvalue beyond the
+                              object's deflation radius (die_te_deflation_radius), r doubled
+                              from 16 until fewer than r of the r largest Ritz values lie
+                              beyond it, at most deflate_max; objects of one context may
+                              then deflate different counts (die_te_deflation_info) */
   double eigs_tol;         /* Ritz pair accepted when ||M v - theta v|| <= eigs_tol |theta|; 0 -> 1e-4 */
   int eigs_krylov;         /* Krylov dimension of the eigensolver; 0 -> max(2r + 8, 24) */
   int eigs_max_restarts;   /* 0 -> 300 */
   unsigned long long seed; /* start vector of the eigensolver */
   int fft_variant;         /* 0: autotune the operator product's FFT passes (see
                               die_te_fft_plan); 1 + v: use variant v (0..3) in every pass */
+  int deflate_max;         /* automatic deflation: largest r (0 -> 256; never above nx ny) */
 } die_te_setup_opts;
 
 typedef struct {
-  int restart;       /* GMRES restart length m (>= 1, <= 510) */
+  int restart;       /* GMRES restart length m (>= 1, <= 510; the block solver: <= 65534 with
+                        (m + 1) times the block width <= 65535) */
   int max_iters;     /* cap on the total number of inner GMRES iterations (>= 1) */
   double tol;        /* stop when ||b - A u||_2 <= tol ||b||_2, checked in FP64 on the
                         original (unregularized) operator; 0 -> 1e-8 */
@@ -272,6 +279,37 @@ int die_te_profile(die_te_ctx *ctx, int enable);
 int die_te_profile_read(die_te_ctx *ctx, int kind, long long *launches, long long *seen, double *total_ms,
                         double *bytes);
 int die_te_profile_mem(die_te_ctx *ctx, int kind, double *mem_bytes);
+
+/* Section 5's deflation radius R of an object: the dense segment [1, eps(x)] of the
+ * spectrum of A at every cell mapped through eq. EigenvaluesArA (regularized != 0, the
+ * solved operator A_R A) or taken as it is (regularized == 0, A), the largest magnitude over
+ * all cells: R = max_x max(1, |1 + (eps - 1)^2 / (4 eps)|) or max_x max(1, |eps|).
+ * eps_r: HOST complex128 [ncells].  DIE_E_SINGULAR if some eps_r is 0.  No GPU work. */
+int die_te_deflation_radius(const void *eps_r, long long ncells, int regularized, double *radius);
+
+/* The memory planner of Section 5 (its systematic application, steps 1-5) for the paper's
+ * 3N-unknown system with 16-byte complex values: a memory budget of mem_bytes, the ratio
+ * beta = r / (3N) of deflated eigenvalues, a grid of points_per_wavelength points per
+ * smallest medium wavelength, restart = x r and the largest real relative permittivity.
+ * The grid follows from M_A + M_prec = mem_bytes with M_A = 720 N and
+ * M_prec = 16 r^2 + 48 N r + 48 N restart; the unpreconditioned system gets restart + r
+ * (the same memory).  This library's TE solver keeps 2N unknowns, 2/3 of the vectors
+ * counted here.  No GPU work. */
+typedef struct {
+  double alpha;              /* points_per_wavelength * sqrt(eps_re_max) */
+  double n_max;              /* the largest affordable number of grid points */
+  double a_over_lambda_max;  /* the largest affordable object size (sqrt(n_max) - 1) / alpha */
+  long long nodes;           /* grid points per side of that object, floor(sqrt(n_max)) */
+  long long n;               /* nodes^2 */
+  long long unknowns;        /* 3 n */
+  int r;                     /* deflated eigenvalues, ceil(3 n beta) */
+  int restart;               /* restart of the preconditioned system, x r */
+  int restart_unpreconditioned; /* restart + r */
+  double mem_system;         /* M_A, bytes */
+  double mem_preconditioner; /* M_prec, bytes */
+} die_te_plan;
+int die_te_plan_memory(double mem_bytes, double beta, double points_per_wavelength, double x, double eps_re_max,
+                       die_te_plan *plan);
 
 /* Release everything the context owns. */
 int die_te_destroy(die_te_ctx *ctx);

@@ -18,6 +18,8 @@ Contents (each function cites the passage of Zouros & Budko it follows):
                     image, the essential-spectrum segment (eq. EssentialSpectrum),
                     dense-eigenvector deflation (Section 4, eq.
                     DeflatingPrecondtioner).
+* ``planning``   -- Section 5's deflation radius (the mapped segments [1, eps(x)]) and
+                    its memory planner with the fair-memory rule.
 * ``mie``        -- textbook Bessel/Hankel series of the TE (H-polarised) plane
                     wave on a homogeneous circular cylinder; the paper only names
                     it as its accuracy reference (Section 4, grid rule).

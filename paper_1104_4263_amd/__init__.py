@@ -12,12 +12,15 @@ from .api import (  # noqa: F401
     die_te_setup,
     die_te_setup_multi,
     die_te_matvec,
+    die_te_matvec_noalloc,
     die_te_regularize,
     die_te_solve,
     die_te_apply_deflation,
     die_te_deflation_info,
     die_te_fft2,
     die_te_destroy,
+    die_te_deflation_radius,
+    die_te_plan_memory,
     die_te_profile,
     die_te_profile_read,
     die_te_profile_mem,

@@ -33,7 +33,7 @@ class DieTeGrid(ctypes.Structure):
 class DieTeSetupOpts(ctypes.Structure):
     _fields_ = [("regularize", ctypes.c_int), ("deflate_k", ctypes.c_int), ("eigs_tol", ctypes.c_double),
                 ("eigs_krylov", ctypes.c_int), ("eigs_max_restarts", ctypes.c_int), ("seed", ctypes.c_ulonglong),
-                ("fft_variant", ctypes.c_int)]
+                ("fft_variant", ctypes.c_int), ("deflate_max", ctypes.c_int)]
 
 
 class DieTeSolveOpts(ctypes.Structure):
@@ -45,6 +45,16 @@ class DieTeSolveOpts(ctypes.Structure):
 class DieTeSolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("products_A", ctypes.c_int),
                 ("products_AR", ctypes.c_int), ("cycles", ctypes.c_int), ("rel_res_true", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class DieTePlan(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("n_max", ctypes.c_double), ("a_over_lambda_max", ctypes.c_double),
+                ("nodes", ctypes.c_longlong), ("n", ctypes.c_longlong), ("unknowns", ctypes.c_longlong),
+                ("r", ctypes.c_int), ("restart", ctypes.c_int), ("restart_unpreconditioned", ctypes.c_int),
+                ("mem_system", ctypes.c_double), ("mem_preconditioner", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -84,6 +94,8 @@ def load() -> ctypes.CDLL:
     lib.die_te_deflation_info.argtypes = [vp, ctypes.POINTER(ip), vp, vp, vp, vp]
     lib.die_te_fft2.argtypes = [vp, i, i, i, i, i, vp]
     lib.die_te_destroy.argtypes = [vp]
+    lib.die_te_deflation_radius.argtypes = [vp, ctypes.c_longlong, i, ctypes.POINTER(ctypes.c_double)]
+    lib.die_te_plan_memory.argtypes = [ctypes.c_double] * 5 + [ctypes.POINTER(DieTePlan)]
     lib.die_te_profile.argtypes = [vp, i]
     lib.die_te_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]

@@ -9,7 +9,8 @@ import math
 import torch
 
 from . import _lib
-from ._lib import (DIE_C128, DIE_C64, DieTeGrid, DieTeSetupOpts, DieTeSolveInfo, DieTeSolveOpts, check, load)
+from ._lib import (DIE_C128, DIE_C64, DieTeGrid, DieTePlan, DieTeSetupOpts, DieTeSolveInfo, DieTeSolveOpts, check,
+                   load)
 
 
 def _stream():
@@ -32,12 +33,14 @@ def _prec(t: torch.Tensor) -> int:
 
 def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0, py: int = 0,
                  regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
-                 eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1) -> ctypes.c_void_p:
-    """fft_variant: -1 autotunes the FFT passes, 0..3 forces that variant in every pass."""
+                 eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1,
+                 deflate_max: int = 0) -> ctypes.c_void_p:
+    """fft_variant: -1 autotunes the FFT passes, 0..3 forces that variant in every pass.
+    deflate_k = -1: automatic deflation size (at most deflate_max, 0 -> 256)."""
     lib = load()
     g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
     o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
-                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1)
+                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1, int(deflate_max))
     ctx = ctypes.c_void_p()
     check(lib.die_te_setup(ctypes.byref(ctx), ctypes.byref(g), _dev(eps_r, (torch.complex128,), "eps_r"),
                            ctypes.byref(o), _stream()))
@@ -47,11 +50,11 @@ def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float 
 def die_te_setup_multi(nx: int, ny: int, h: float, nobj: int, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0,
                        py: int = 0, regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4,
                        eigs_krylov: int = 0, eigs_max_restarts: int = 0, seed: int = 0,
-                       fft_variant: int = -1) -> ctypes.c_void_p:
+                       fft_variant: int = -1, deflate_max: int = 0) -> ctypes.c_void_p:
     lib = load()
     g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
     o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
-                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1)
+                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1, int(deflate_max))
     ctx = ctypes.c_void_p()
     check(lib.die_te_setup_multi(ctypes.byref(ctx), ctypes.byref(g), int(nobj),
                                  _dev(eps_r, (torch.complex128,), "eps_r"), ctypes.byref(o), _stream()))
@@ -170,6 +173,25 @@ def die_te_profile_mem(ctx, kind: int) -> float:
     return float(nb.value)
 
 
+def die_te_deflation_radius(eps_r, regularized: bool) -> float:
+    """Section 5's deflation radius of an object (eps_r: any array of complex values)."""
+    import numpy as np
+    e = np.ascontiguousarray(np.asarray(eps_r, dtype=np.complex128).ravel())
+    R = ctypes.c_double(0.0)
+    check(load().die_te_deflation_radius(ctypes.c_void_p(e.ctypes.data), int(e.size), int(bool(regularized)),
+                                         ctypes.byref(R)))
+    return float(R.value)
+
+
+def die_te_plan_memory(mem_bytes: float, beta: float, points_per_wavelength: float, x: float,
+                       eps_re_max: float) -> dict:
+    """Section 5's memory planner (the paper's 3N system)."""
+    p = DieTePlan()
+    check(load().die_te_plan_memory(float(mem_bytes), float(beta), float(points_per_wavelength), float(x),
+                                    float(eps_re_max), ctypes.byref(p)))
+    return p.as_dict()
+
+
 def die_te_destroy(ctx) -> None:
     if ctx:
         check(load().die_te_destroy(ctx))
@@ -186,7 +208,8 @@ class Solver:
 
     def __init__(self, nx: int, ny: int, h: float, eps_r, *, k_b: float = 2.0 * math.pi, px: int = 0, py: int = 0,
                  regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
-                 eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1, device: str = "cuda"):
+                 eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1, deflate_max: int = 0,
+                 device: str = "cuda"):
         eps = torch.as_tensor(eps_r, dtype=torch.complex128).to(device).contiguous()
         if tuple(eps.shape[-2:]) != (ny, nx) or eps.dim() not in (2, 3):
             raise ValueError(f"eps_r must have shape ({ny}, {nx}) or (nobj, {ny}, {nx})")
@@ -196,7 +219,8 @@ class Solver:
         self.device = device
         self.regularized = bool(regularize)
         kw = dict(k_b=k_b, px=px, py=py, regularize=regularize, deflate_k=deflate_k, eigs_tol=eigs_tol,
-                  eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts, seed=seed, fft_variant=fft_variant)
+                  eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts, seed=seed, fft_variant=fft_variant,
+                  deflate_max=deflate_max)
         if eps.dim() == 2:
             self.ctx = die_te_setup(nx, ny, h, eps, **kw)
         else:

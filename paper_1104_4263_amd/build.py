@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdie_te.so")
 SOURCES = ["kernels_fft.hip", "kernels_krylov.hip", "kernels_block.hip", "kernels_unet.hip", "scratch.hip", "die_te.cpp",
-           "unet.cpp"]
+           "unet.cpp", "plan.cpp"]
 ARCH = "gfx950"
 
 

@@ -103,6 +103,7 @@ struct die_te_ctx {
   DBuf V;     // [nobj][r][nvec] complex128, orthonormal per object
   DBuf Cdev;  // [nobj][r][r] row-major complex128, C = T^-1 - I
   std::vector<cd> Chost, ritz;  // [nobj][r][r], [nobj][r]
+  std::vector<double> radius;   // automatic deflation: each object's deflation radius
   int eigs_restarts = 0, eigs_converged = 0;
   // diagnostic timing: event pairs recorded around launches of each kind
   bool prof_on = false;
@@ -404,10 +405,13 @@ uint64_t splitmix(uint64_t& s) {
   return z ^ (z >> 31);
 }
 
-// Deflation data of object `obj` into the slots of c->V / c->Cdev / c->Chost / c->ritz (sized for
-// c->r vectors per object; an object whose Krylov space closes early fills fewer and the rest of
-// its slots stay zero, which leaves P^-1 unchanged).
-int run_eigs(die_te_ctx* c, int obj, int r, double tol, int mk, int maxrst, unsigned long long seed, hipStream_t st) {
+// Deflation data of the r largest-magnitude eigenpairs of object `obj`'s operator into slot
+// `slot` of c->V / c->Cdev / c->Chost / c->ritz (each slot sized for c->r >= r vectors; an
+// object whose Krylov space closes early, or that wants fewer than c->r, fills fewer and the
+// rest of its slot stays zero, which leaves P^-1 unchanged).
+int run_eigs(die_te_ctx* c, int obj, int slot, int r, double tol, int mk, int maxrst, unsigned long long seed,
+             hipStream_t st) {
+  const int ld = c->r;  // vectors per slot
   const size_t n = c->nvec;
   const bool reg = c->regularize != 0;
   const int nblk = die::blas_blocks(n);
@@ -543,7 +547,7 @@ int run_eigs(die_te_ctx* c, int obj, int r, double tol, int mk, int maxrst, unsi
   c->eigs_restarts = rst;
   const int rr = std::min(r, mk_eff);
   // deflation basis V = Q Z[:, :rr]
-  double2* Vo = c->V.as<double2>() + (size_t)obj * r * n;
+  double2* Vo = c->V.as<double2>() + (size_t)slot * ld * n;
   {
     std::vector<double2> zh((size_t)mk_eff * rr);
     for (int l = 0; l < rr; ++l)
@@ -570,17 +574,17 @@ int run_eigs(die_te_ctx* c, int obj, int r, double tol, int mk, int maxrst, unsi
   for (int l = 0; l < rr; ++l)
     for (int i = 0; i < rr; ++i) T(i, l) = cd(th[(size_t)l * rr + i].x, th[(size_t)l * rr + i].y);
   if (!die::la::inverse(T, Ti)) return fail(DIE_E_BREAKDOWN, "deflation: T = V^* M V is singular");
-  std::vector<double2> ch((size_t)r * r, make_double2(0.0, 0.0));
-  cd* Ch = c->Chost.data() + (size_t)obj * r * r;
+  std::vector<double2> ch((size_t)ld * ld, make_double2(0.0, 0.0));
+  cd* Ch = c->Chost.data() + (size_t)slot * ld * ld;
   for (int i = 0; i < rr; ++i)
     for (int l = 0; l < rr; ++l) {
       cd v = Ti(i, l) - (i == l ? 1.0 : 0.0);
-      Ch[(size_t)i * r + l] = v;
-      ch[(size_t)i * r + l] = make_double2(v.real(), v.imag());
+      Ch[(size_t)i * ld + l] = v;
+      ch[(size_t)i * ld + l] = make_double2(v.real(), v.imag());
     }
-  DIE_HIP(hipMemcpyAsync(c->Cdev.as<double2>() + (size_t)obj * r * r, ch.data(), ch.size() * sizeof(double2),
+  DIE_HIP(hipMemcpyAsync(c->Cdev.as<double2>() + (size_t)slot * ld * ld, ch.data(), ch.size() * sizeof(double2),
                          hipMemcpyHostToDevice, st));
-  for (int i = 0; i < rr; ++i) c->ritz[(size_t)obj * r + i] = S(i, i);
+  for (int i = 0; i < rr; ++i) c->ritz[(size_t)slot * ld + i] = S(i, i);
   DIE_HIP(hipStreamSynchronize(st));
   (void)converged;
   return DIE_OK;
@@ -1871,7 +1875,8 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
     return fail(DIE_E_INVALID, "px, py must be powers of two in [max(2, 2n-1), 4096]");
   die_te_setup_opts o{};
   if (opts) o = *opts;
-  if (o.deflate_k < 0) return fail(DIE_E_INVALID, "deflate_k must be >= 0");
+  if (o.deflate_k < -1) return fail(DIE_E_INVALID, "deflate_k must be >= -1");
+  if (o.deflate_max < 0) return fail(DIE_E_INVALID, "deflate_max must be >= 0");
   if (o.fft_variant < 0 || o.fft_variant > die::kFftVariants)
     return fail(DIE_E_INVALID, "fft_variant must be 0 (autotune) or 1 + v with v in [0, 3]");
 
@@ -1947,25 +1952,60 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
       return guard(fail(DIE_E_HIP, "symbol transform failed"));
   }
-  if (o.deflate_k > 0) {
-    if ((size_t)o.deflate_k >= c->nvec) return guard(fail(DIE_E_INVALID, "deflate_k must be < 2 nx ny"));
-    const int r = o.deflate_k;
-    if ((rc = c->V.alloc((size_t)nobj * r * c->nvec * sizeof(double2))) < 0 ||
-        (rc = c->Cdev.alloc((size_t)nobj * r * r * sizeof(double2))) < 0)
-      return guard(rc);
-    if (hipMemsetAsync(c->V.p, 0, (size_t)nobj * r * c->nvec * sizeof(double2), st) != hipSuccess ||
-        hipMemsetAsync(c->Cdev.p, 0, (size_t)nobj * r * r * sizeof(double2), st) != hipSuccess)
-      return guard(fail(DIE_E_HIP, "clearing the deflation data failed"));
-    c->Chost.assign((size_t)nobj * r * r, cd(0, 0));
-    c->ritz.assign((size_t)nobj * r, cd(0, 0));
+  // slots for nslot objects with r vectors each, cleared (zero vectors leave P^-1 unchanged)
+  auto alloc_deflation = [&](int nslot, int r) -> int {
+    int e;
+    if ((e = c->V.alloc((size_t)nslot * r * c->nvec * sizeof(double2))) < 0 ||
+        (e = c->Cdev.alloc((size_t)nslot * r * r * sizeof(double2))) < 0)
+      return e;
+    if (hipMemsetAsync(c->V.p, 0, (size_t)nslot * r * c->nvec * sizeof(double2), st) != hipSuccess ||
+        hipMemsetAsync(c->Cdev.p, 0, (size_t)nslot * r * r * sizeof(double2), st) != hipSuccess)
+      return fail(DIE_E_HIP, "clearing the deflation data failed");
+    c->Chost.assign((size_t)nslot * r * r, cd(0, 0));
+    c->ritz.assign((size_t)nslot * r, cd(0, 0));
     c->r = r;
-    int conv = r;
+    return DIE_OK;
+  };
+  std::vector<int> want(nobj, o.deflate_k);  // eigenpairs wanted per object
+  if (o.deflate_k == -1) {
+    // automatic size (Section 5): the deflation radius R of each object from its contrast, then
+    // r doubled from 16 until fewer than r of the r largest Ritz values lie beyond R
+    const int rcap = (int)std::min<size_t>(o.deflate_max > 0 ? (size_t)o.deflate_max : 256, c->nvec / 2);
+    if (rcap < 1) return guard(fail(DIE_E_INVALID, "automatic deflation needs 2 nx ny >= 2"));
+    c->radius.assign(nobj, 1.0);
     for (int ob = 0; ob < nobj; ++ob) {
-      rc = run_eigs(c, ob, r, o.eigs_tol, o.eigs_krylov, o.eigs_max_restarts, o.seed, st);
+      const double R = die_host::deflation_radius(eps.data() + (size_t)ob * c->ncell, c->ncell, c->regularize != 0);
+      c->radius[ob] = R;
+      for (int rt = std::min(16, rcap);; rt = std::min(2 * rt, rcap)) {
+        if ((rc = alloc_deflation(1, rt)) < 0) return guard(rc);
+        rc = run_eigs(c, ob, 0, rt, o.eigs_tol, o.eigs_krylov, o.eigs_max_restarts, o.seed, st);
+        if (rc < 0) return guard(rc);
+        int beyond = 0;
+        for (int i = 0; i < rt; ++i) beyond += std::abs(c->ritz[i]) > R ? 1 : 0;
+        want[ob] = beyond;
+        if (beyond < rt || rt >= rcap) break;
+      }
+    }
+  } else if (o.deflate_k > 0 && (size_t)o.deflate_k >= c->nvec) {
+    return guard(fail(DIE_E_INVALID, "deflate_k must be < 2 nx ny"));
+  }
+  const int rdef = *std::max_element(want.begin(), want.end());
+  c->r = 0;
+  if (rdef > 0) {
+    if ((rc = alloc_deflation(nobj, rdef)) < 0) return guard(rc);
+    int conv = rdef;
+    for (int ob = 0; ob < nobj; ++ob) {
+      if (want[ob] <= 0) continue;
+      rc = run_eigs(c, ob, ob, want[ob], o.eigs_tol, o.eigs_krylov, o.eigs_max_restarts, o.seed, st);
       if (rc < 0) return guard(rc);
       conv = std::min(conv, c->eigs_converged);
     }
     c->eigs_converged = conv;
+  } else {
+    c->V.release();
+    c->Cdev.release();
+    c->Chost.clear();
+    c->ritz.clear();
   }
   *out = c;
   return DIE_OK;
@@ -2050,7 +2090,8 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   if (e_in == e_tot) return fail(DIE_E_INVALID, "e_in and e_tot must not overlap");
   if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
   die_te_solve_opts o = *opts;
-  if (o.restart < 1 || o.restart > 510) return fail(DIE_E_INVALID, "restart must be in [1, 510]");
+  if (o.restart < 1 || o.restart > (o.block ? 65534 : 510))
+    return fail(DIE_E_INVALID, "restart must be in [1, 510] (block solver: [1, 65534])");
   if (o.orth != 0 && o.orth != 1) return fail(DIE_E_INVALID, "orth must be 0 (CGS2) or 1 (one-reduction CGS2)");
   if (o.max_iters < 1) return fail(DIE_E_INVALID, "max_iters must be >= 1");
   if (o.tol < 0 || !std::isfinite(o.tol)) return fail(DIE_E_INVALID, "tol must be >= 0");

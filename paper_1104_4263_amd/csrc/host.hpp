@@ -61,6 +61,10 @@ struct DBuf {
   template <class X> X* as() const { return static_cast<X*>(p); }
 };
 
+// Section 5's deflation radius of eps_r[0 .. ncells) (complex128), with (regularized) or
+// without the regularizer (plan.cpp).
+double deflation_radius(const double2* eps, size_t ncells, bool regularized);
+
 }  // namespace die_host
 
 #define DIE_HIP(expr)                                                                                  \

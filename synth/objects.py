@@ -175,9 +175,11 @@ def inclusion_object(n: int = 2048, side: float = 25.6, seed: int = 5000, n_incl
     return g, out
 
 
-def sinusoid_object(n: int, side: float) -> tuple[Grid, np.ndarray]:
-    """The paper's continuously varying object: eps = 10 + 5 sin(4 pi x/a) sin(4 pi y/a)."""
+def sinusoid_object(n: int, side: float, a: float | None = None) -> tuple[Grid, np.ndarray]:
+    """The paper's continuously varying object: eps = 10 + 5 sin(4 pi x/a) sin(4 pi y/a), with
+    a the object's side (default: the grid's side)."""
     g = centred_grid(n, side)
     X, Y = cell_centres(g)
-    eps = 10.0 + 5.0 * np.sin(4.0 * math.pi * X / side) * np.sin(4.0 * math.pi * Y / side)
+    a = side if a is None else a
+    eps = 10.0 + 5.0 * np.sin(4.0 * math.pi * X / a) * np.sin(4.0 * math.pi * Y / a)
     return g, eps.astype(np.complex128)

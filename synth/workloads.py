@@ -67,7 +67,8 @@ def _paper_squares(nodes=61):
 
 
 def _paper_sinusoid(nodes=233, side=4.0):
-    g, e = sinusoid_object(nodes, side * nodes / (nodes - 1))
+    # nodes spanning the object: cell centres from -a/2 to a/2 with a = side
+    g, e = sinusoid_object(nodes, side * nodes / (nodes - 1), a=side)
     return dict(name="paper_sinusoid", grids=[g], eps=[e], psi=[0.0], restart=1440,
                 regularize=True, deflate_k=180)
 
