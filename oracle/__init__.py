@@ -18,6 +18,10 @@ Contents (each function cites the passage of Zouros & Budko it follows):
                     image, the essential-spectrum segment (eq. EssentialSpectrum),
                     dense-eigenvector deflation (Section 4, eq.
                     DeflatingPrecondtioner).
+* ``systems``    -- the TM operator (Section 2 eq. MatrixSolutionTM, Section 4's [A33]
+                    formulas with chi_e) and the full three-component TE system
+                    (E1, E2, H3) with magnetic contrast (Section 4 eq. lin_system; the
+                    coupling blocks from Section 3's compact kernels K13..K33).
 * ``planning``   -- Section 5's deflation radius (the mapped segments [1, eps(x)]) and
                     its memory planner with the fair-memory rule.
 * ``mie``        -- textbook Bessel/Hankel series of the TE (H-polarised) plane
