@@ -60,15 +60,20 @@ inline void hessenberg(Mat& A, Mat& Z) {
   const int n = A.n;
   std::vector<cd> v(n);
   for (int k = 0; k + 2 < n + 0 && k < n - 2; ++k) {
+    // the column is scaled by its largest entry before any squaring: entries as small as the
+    // ones a Krylov-Schur restart leaves for converged directions (1e-200 and below) would
+    // otherwise underflow in |x|^2 and overflow in 2 / |v|^2
+    double scale = 0.0;
+    for (int i = k + 1; i < n; ++i) scale = std::max(scale, std::abs(A(i, k)));
+    if (scale == 0.0) continue;
     double alpha2 = 0.0;
-    for (int i = k + 1; i < n; ++i) alpha2 += std::norm(A(i, k));
-    const double anorm = std::sqrt(alpha2);
-    if (anorm == 0.0) continue;
+    for (int i = k + 1; i < n; ++i) alpha2 += std::norm(A(i, k) / scale);
+    const double anorm = std::sqrt(alpha2);  // |x| / scale
     const cd x0 = A(k + 1, k);
     const cd ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cd(1.0, 0.0);
-    // v = x + ph * |x| e1, H = I - 2 v v^H / (v^H v)
+    // v = x / scale + ph |x / scale| e1, H = I - 2 v v^H / (v^H v) (independent of the scale)
     for (int i = 0; i < n; ++i) v[i] = 0.0;
-    for (int i = k + 1; i < n; ++i) v[i] = A(i, k);
+    for (int i = k + 1; i < n; ++i) v[i] = A(i, k) / scale;
     v[k + 1] += ph * anorm;
     double vn = 0.0;
     for (int i = k + 1; i < n; ++i) vn += std::norm(v[i]);
@@ -187,6 +192,11 @@ inline Mat tri_eigvecs(const Mat& T) {
       cd d = T(i, i) - lam;
       if (std::abs(d) < small) d = small;
       Y(i, k) = -s / d;
+      // through a cluster of close eigenvalues the entries grow by |T(i, j) / d| per step: the
+      // partial vector is rescaled before it can overflow (the normalisation below removes it)
+      const double a = std::abs(Y(i, k));
+      if (a > 1e100)
+        for (int j = i; j <= k; ++j) Y(j, k) /= a;
     }
     double nrm = 0.0;
     for (int i = 0; i <= k; ++i) nrm += std::norm(Y(i, k));
