@@ -320,6 +320,12 @@ def uneven_run(sizes, args):
 
 # The paper's Table 2 (TE, tol 1e-8 on the solved system, fair memory: restart + r = 40): per
 # object (eps of the square) and system, the deflation size r, the restart and the iterations.
+# The paper's Table 1 (TM, fair memory): per square, the deflation size r, the restart and the iterations.
+PAPER_TABLE1 = {
+    "16": {"A": (0, 40, 7311), "A P^-1": (28, 12, 4230)},
+    "-16+1.5i": {"A": (0, 40, 27), "A P^-1": (28, 12, 14)},
+    "16 with a 2.5+20i core": {"A": (0, 40, 1000), "A P^-1": (28, 12, 749)},
+}
 PAPER_TABLE2 = {
     "16": {"A": (0, 40, 15258), "A P^-1": (6, 34, 14002), "A_R A": (0, 40, 4030), "A_R A P^-1": (14, 26, 3626)},
     "-16+1.5i": {"A": (0, 40, 1708), "A P^-1": (7, 33, 1659), "A_R A": (0, 40, 1021), "A_R A P^-1": (30, 10, 534)},
@@ -337,13 +343,14 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
     and its regularized residual)."""
     import numpy as np
     import torch
-    from synth import workload, plane_wave, centred_grid, cylinder
+    from synth import workload, plane_wave, plane_wave_te3, plane_wave_tm, centred_grid, cylinder
     from paper_1104_4263_amd import Solver
 
-    def run(g, e, b, reg, k, restart, cap, mixed, seed=1, memory=None):
-        """k = -1: automatic deflation size; memory: restart = memory - r (fair memory)."""
+    def run(g, e, b, reg, k, restart, cap, mixed, seed=1, memory=None, **kw):
+        """k = -1: automatic deflation size; memory: restart = memory - r (fair memory); kw: the
+        system (polarization, magnetic)."""
         t0 = time.perf_counter()
-        sv = Solver.from_grid(g, e, regularize=reg, deflate_k=k, seed=seed)
+        sv = Solver.from_grid(g, e, regularize=reg, deflate_k=k, seed=seed, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if k == -1:
@@ -407,6 +414,29 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
             __import__("paper_1104_4263_amd").die_te_deflation_radius(es, True), 4)
         log(f"square eps = {label} automatic r: {res['A_R A P^-1, automatic r']}")
         out[f"Table 2 square, eps = {label} (61^2 nodes)"] = res
+    # Table 2 on the paper's own 3N system (E1, E2, H3; no magnetic contrast): counts comparable to the table
+    b3 = torch.from_numpy(plane_wave_te3(gs, 0.0)).cuda()
+    for label, es in zip(PAPER_TABLE2, ws["eps"]):
+        res = {}
+        for name, reg, defl in systems:
+            r, restart, paper_it = PAPER_TABLE2[label][name]
+            res[name] = run(gs, es, b3, reg, r, restart, cap_reg if reg else MAX_ITERS, False, magnetic=True)
+            res[name]["paper_iters"] = paper_it
+            log(f"3N square eps = {label} {name}: {res[name]}")
+        out[f"Table 2 square, eps = {label}, the 3N (E1, E2, H3) system"] = res
+    # Table 1: the TM squares, unpreconditioned against deflated (r = 28, restart 12), and the
+    # automatic size (every eigenvalue outside the unit circle) with the fair-memory restart
+    btm = torch.from_numpy(plane_wave_tm(gs, 0.0)).cuda()
+    for label, es in zip(PAPER_TABLE1, ws["eps"]):
+        res = {}
+        for name, defl in (("A", False), ("A P^-1", True)):
+            r, restart, paper_it = PAPER_TABLE1[label][name]
+            res[name] = run(gs, es, btm, False, r, restart, MAX_ITERS, False, polarization="tm")
+            res[name]["paper_iters"] = paper_it
+            log(f"TM square eps = {label} {name}: {res[name]}")
+        res["A P^-1, automatic r"] = run(gs, es, btm, False, -1, 0, MAX_ITERS, False, memory=40, polarization="tm")
+        log(f"TM square eps = {label} automatic r: {res['A P^-1, automatic r']}")
+        out[f"Table 1 square (TM), eps = {label} (61^2 nodes)"] = res
     return out
 
 

@@ -18,9 +18,11 @@
  * Conventions shared by every entry point
  *   - Complex numbers are interleaved (re, im): complex128 = 2 doubles,
  *     complex64 = 2 floats (the layout of PyTorch complex tensors).
- *   - Field arrays are laid out [nrhs][2][ny][nx] (component 0 = E1 = E_x),
- *     x fastest.  Cell (ix, iy) is centred at (x0 + (ix + 1/2) h, y0 + (iy + 1/2) h);
- *     only h enters the operator (it is translation invariant).
+ *   - Field arrays are laid out [nrhs][ncomp][ny][nx], x fastest: ncomp = 2 for the TE
+ *     E-block (component 0 = E1 = E_x, 1 = E2), 1 for TM (E3), 3 for the full TE system
+ *     (E1, E2, H3) of die_te_setup_opts.magnetic; "2 nx ny" below reads ncomp nx ny.
+ *     Cell (ix, iy) is centred at (x0 + (ix + 1/2) h, y0 + (iy + 1/2) h); only h enters
+ *     the operator (it is translation invariant).
  *   - Units: lambda_b = 1 unless k_b says otherwise.
  *   - Pointers named "device" must point to GPU memory of the current device;
  *     the caller owns them and keeps them alive for the duration of the call
@@ -81,6 +83,20 @@ typedef struct {
   int fft_variant;         /* 0: autotune the operator product's FFT passes (see
                               die_te_fft_plan); 1 + v: use variant v (0..3) in every pass */
   int deflate_max;         /* automatic deflation: largest r (0 -> 256; never above nx ny) */
+  int polarization;        /* 0: TE (the default); 1: TM, the scalar operator of Section 2
+                              eq. MatrixSolutionTM with chi_m = 0: E3_in = E3 - k^2 g * (chi E3),
+                              collocated with the [A33] formulas of Section 4 (chi_e in place of
+                              chi_m); fields have one component; no regularizer; automatic
+                              deflation deflates outside the unit circle (Section 4, TM table) */
+  int magnetic;            /* TE only.  1: the full system of Section 4 eq. lin_system on
+                              u = (E1, E2, H3) with magnetic contrast chi_m = mu_r - 1: fields have
+                              three components; the coupling blocks follow the compact kernels
+                              K13, K23, K31, K32 of Section 3 (eps_b = mu_b = 1), A33 the [A33]
+                              formulas; the regularizer, when on, uses chi' = 1/eps_r - 1 and
+                              chi_m' = 1/mu_r - 1.  0: the E-block only (two components) */
+  const void *mu_r;        /* magnetic = 1: device, complex128 [nobj][ny][nx] relative
+                              permeability (copied at setup); NULL: mu_r = 1 (H3 is then computed
+                              with the field, from E) */
 } die_te_setup_opts;
 
 typedef struct {

@@ -33,7 +33,8 @@ class DieTeGrid(ctypes.Structure):
 class DieTeSetupOpts(ctypes.Structure):
     _fields_ = [("regularize", ctypes.c_int), ("deflate_k", ctypes.c_int), ("eigs_tol", ctypes.c_double),
                 ("eigs_krylov", ctypes.c_int), ("eigs_max_restarts", ctypes.c_int), ("seed", ctypes.c_ulonglong),
-                ("fft_variant", ctypes.c_int), ("deflate_max", ctypes.c_int)]
+                ("fft_variant", ctypes.c_int), ("deflate_max", ctypes.c_int), ("polarization", ctypes.c_int),
+                ("magnetic", ctypes.c_int), ("mu_r", ctypes.c_void_p)]
 
 
 class DieTeSolveOpts(ctypes.Structure):

@@ -31,16 +31,27 @@ def _prec(t: torch.Tensor) -> int:
     return DIE_C128 if t.dtype == torch.complex128 else DIE_C64
 
 
+def _setup_opts(regularize, deflate_k, eigs_tol, eigs_krylov, eigs_max_restarts, seed, fft_variant, deflate_max,
+                polarization, magnetic, mu_r):
+    mu = None if mu_r is None else _dev(mu_r, (torch.complex128,), "mu_r")
+    return DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
+                          int(eigs_max_restarts), int(seed), int(fft_variant) + 1, int(deflate_max),
+                          1 if polarization in (1, "tm", "TM") else 0, int(bool(magnetic)), mu)
+
+
 def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0, py: int = 0,
                  regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
                  eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1,
-                 deflate_max: int = 0) -> ctypes.c_void_p:
+                 deflate_max: int = 0, polarization=0, magnetic: bool = False,
+                 mu_r: torch.Tensor | None = None) -> ctypes.c_void_p:
     """fft_variant: -1 autotunes the FFT passes, 0..3 forces that variant in every pass.
-    deflate_k = -1: automatic deflation size (at most deflate_max, 0 -> 256)."""
+    deflate_k = -1: automatic deflation size (at most deflate_max, 0 -> 256).
+    polarization "tm" (or 1): the scalar TM operator; magnetic: the (E1, E2, H3) TE system
+    with relative permeability mu_r (device complex128, same shape as eps_r; None = 1)."""
     lib = load()
     g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
-    o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
-                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1, int(deflate_max))
+    o = _setup_opts(regularize, deflate_k, eigs_tol, eigs_krylov, eigs_max_restarts, seed, fft_variant, deflate_max,
+                    polarization, magnetic, mu_r)
     ctx = ctypes.c_void_p()
     check(lib.die_te_setup(ctypes.byref(ctx), ctypes.byref(g), _dev(eps_r, (torch.complex128,), "eps_r"),
                            ctypes.byref(o), _stream()))
@@ -50,11 +61,12 @@ def die_te_setup(nx: int, ny: int, h: float, eps_r: torch.Tensor, *, k_b: float 
 def die_te_setup_multi(nx: int, ny: int, h: float, nobj: int, eps_r: torch.Tensor, *, k_b: float = 0.0, px: int = 0,
                        py: int = 0, regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4,
                        eigs_krylov: int = 0, eigs_max_restarts: int = 0, seed: int = 0,
-                       fft_variant: int = -1, deflate_max: int = 0) -> ctypes.c_void_p:
+                       fft_variant: int = -1, deflate_max: int = 0, polarization=0, magnetic: bool = False,
+                       mu_r: torch.Tensor | None = None) -> ctypes.c_void_p:
     lib = load()
     g = DieTeGrid(nx, ny, float(h), float(k_b), px, py)
-    o = DieTeSetupOpts(int(bool(regularize)), int(deflate_k), float(eigs_tol), int(eigs_krylov),
-                       int(eigs_max_restarts), int(seed), int(fft_variant) + 1, int(deflate_max))
+    o = _setup_opts(regularize, deflate_k, eigs_tol, eigs_krylov, eigs_max_restarts, seed, fft_variant, deflate_max,
+                    polarization, magnetic, mu_r)
     ctx = ctypes.c_void_p()
     check(lib.die_te_setup_multi(ctypes.byref(ctx), ctypes.byref(g), int(nobj),
                                  _dev(eps_r, (torch.complex128,), "eps_r"), ctypes.byref(o), _stream()))
@@ -209,18 +221,22 @@ class Solver:
     def __init__(self, nx: int, ny: int, h: float, eps_r, *, k_b: float = 2.0 * math.pi, px: int = 0, py: int = 0,
                  regularize: bool = False, deflate_k: int = 0, eigs_tol: float = 1e-4, eigs_krylov: int = 0,
                  eigs_max_restarts: int = 0, seed: int = 0, fft_variant: int = -1, deflate_max: int = 0,
-                 device: str = "cuda"):
+                 polarization=0, magnetic: bool = False, mu_r=None, device: str = "cuda"):
         eps = torch.as_tensor(eps_r, dtype=torch.complex128).to(device).contiguous()
+        mu = None if mu_r is None else torch.as_tensor(mu_r, dtype=torch.complex128).to(device).contiguous()
+        if mu is not None and mu.shape != eps.shape:
+            raise ValueError("mu_r must have the shape of eps_r")
         if tuple(eps.shape[-2:]) != (ny, nx) or eps.dim() not in (2, 3):
             raise ValueError(f"eps_r must have shape ({ny}, {nx}) or (nobj, {ny}, {nx})")
         self.nobj = 1 if eps.dim() == 2 else int(eps.shape[0])
         self.nx, self.ny, self.h, self.k_b = nx, ny, h, k_b
-        self.nvec = 2 * nx * ny
+        self.ncomp = 1 if polarization in (1, "tm", "TM") else (3 if magnetic else 2)
+        self.nvec = self.ncomp * nx * ny
         self.device = device
         self.regularized = bool(regularize)
         kw = dict(k_b=k_b, px=px, py=py, regularize=regularize, deflate_k=deflate_k, eigs_tol=eigs_tol,
                   eigs_krylov=eigs_krylov, eigs_max_restarts=eigs_max_restarts, seed=seed, fft_variant=fft_variant,
-                  deflate_max=deflate_max)
+                  deflate_max=deflate_max, polarization=polarization, magnetic=magnetic, mu_r=mu)
         if eps.dim() == 2:
             self.ctx = die_te_setup(nx, ny, h, eps, **kw)
         else:
@@ -231,8 +247,8 @@ class Solver:
         return cls(grid.nx, grid.ny, grid.h, eps_r, k_b=grid.k, **kw)
 
     def _shape(self, x: torch.Tensor) -> int:
-        if x.shape[-3:] != (2, self.ny, self.nx):
-            raise ValueError(f"fields must be [..., 2, {self.ny}, {self.nx}]")
+        if x.shape[-3:] != (self.ncomp, self.ny, self.nx):
+            raise ValueError(f"fields must be [..., {self.ncomp}, {self.ny}, {self.nx}]")
         return 1 if x.dim() == 3 else int(x.shape[0])
 
     def matvec(self, x: torch.Tensor) -> torch.Tensor:

@@ -95,7 +95,9 @@ struct die_te_ctx {
   double h = 0, k = 0;
   size_t ncell = 0, nvec = 0;
   int nobj = 1;  // objects sharing this grid (and therefore the symbol)
+  int ncomp = 2;  // field components: 2 = TE (E1, E2), 1 = TM (E3), 3 = TE with H3 (E1, E2, H3)
   DBuf chi64, chir64, chi32, chir32, sym64, sym32;
+  DBuf chim64, chimr64, chim32, chimr32;  // ncomp 3: magnetic contrast chi_m and its regularizer
   DBuf work;  // FFT intermediate [nrhs][2][px][ny]
   int regularize = 0;
   // deflation
@@ -189,8 +191,9 @@ int prof_resolve(die_te_ctx* c) {
 // pass 3 reads those and u, writes y (2RN).
 double product_bytes(const die_te_ctx* c, int R, int nchi, size_t es) {
   const double N = (double)c->ncell, rows = (double)c->ny * c->px, P = (double)c->px * c->py;
-  return es * (2.0 * R * N + nchi * N + 2.0 * R * rows + 2.0 * R * rows + 3.0 * P + 2.0 * R * rows +
-               2.0 * R * rows + 2.0 * R * N + 2.0 * R * N);
+  const double nc = c->ncomp, nplanes = die::sym_planes(c->ncomp), ncontrast = c->ncomp == 3 ? 2.0 : 1.0;
+  return es * (nc * R * N + ncontrast * nchi * N + nc * R * rows + nc * R * rows + nplanes * P + nc * R * rows +
+               nc * R * rows + nc * R * N + nc * R * N);
 }
 
 // ------------------------------------------------------------------ operator products
@@ -201,6 +204,16 @@ template <> const double2* chi_of<double>(const die_te_ctx* c, bool reg) {
 template <> const float2* chi_of<float>(const die_te_ctx* c, bool reg) {
   return reg ? c->chir32.as<float2>() : c->chi32.as<float2>();
 }
+// The contrast of components from the third on (chi_m of the full TE system), null otherwise.
+template <class T> const c2<T>* chi2_of(const die_te_ctx* c, bool reg);
+template <> const double2* chi2_of<double>(const die_te_ctx* c, bool reg) {
+  if (c->ncomp != 3) return nullptr;
+  return reg ? c->chimr64.as<double2>() : c->chim64.as<double2>();
+}
+template <> const float2* chi2_of<float>(const die_te_ctx* c, bool reg) {
+  if (c->ncomp != 3) return nullptr;
+  return reg ? c->chimr32.as<float2>() : c->chim32.as<float2>();
+}
 template <class T> const c2<T>* sym_of(const die_te_ctx* c);
 template <> const double2* sym_of<double>(const die_te_ctx* c) { return c->sym64.as<double2>(); }
 template <> const float2* sym_of<float>(const die_te_ctx* c) { return c->sym32.as<float2>(); }
@@ -208,7 +221,7 @@ template <> const float2* sym_of<float>(const die_te_ctx* c) { return c->sym32.a
 // Bytes of the product's FFT intermediate for nrhs fields of es-byte complex values (the
 // tiled layout of the three passes: wtile_cols(px) x wtile_rows(ny) per component).
 size_t work_bytes(const die_te_ctx* c, size_t nrhs, size_t es) {
-  return nrhs * 2 * (size_t)die::wtile_cols(c->px) * die::wtile_rows(c->ny) * es;
+  return nrhs * (size_t)c->ncomp * die::wtile_cols(c->px) * die::wtile_rows(c->ny) * es;
 }
 
 int ensure_work(die_te_ctx* c, size_t bytes, hipStream_t st) {
@@ -223,9 +236,9 @@ int ensure_work(die_te_ctx* c, size_t bytes, hipStream_t st) {
 // the tile of each pass is chosen per batch-size class (it moves no arithmetic).  Both by
 // timing the variants of the pass on the grid with min(nrhs, 64) fields.
 struct TuneKey {
-  int dev, prec, lpx, lpy, nx, ny;
+  int dev, prec, lpx, lpy, nx, ny, ncomp;
   bool operator<(const TuneKey& o) const {
-    return std::tie(dev, prec, lpx, lpy, nx, ny) < std::tie(o.dev, o.prec, o.lpx, o.lpy, o.nx, o.ny);
+    return std::tie(dev, prec, lpx, lpy, nx, ny, ncomp) < std::tie(o.dev, o.prec, o.lpx, o.lpy, o.nx, o.ny, o.ncomp);
   }
 };
 struct TuneEntry {
@@ -243,10 +256,12 @@ template <class T> const c2<T>* sym_of(const die_te_ctx* c);
 // Launch pass `pass` (0 rows, 1 columns + symbol, 2 inverse rows) of a product on R fields.
 template <class T>
 hipError_t launch_pass(die_te_ctx* c, int pass, int v, const c2<T>* x, c2<T>* y, c2<T>* W, int R, const int* live,
-                       hipStream_t st, int rpo, const c2<T>* chi) {
-  if (pass == 0) return die::launch_rows_fwd<T, T>(c->lpx, false, x, chi, W, c->nx, c->ny, R, 2, 0, rpo, live, st, v);
-  if (pass == 1) return die::launch_cols_symbol<T>(c->lpy, W, sym_of<T>(c), c->px, c->ny, R, live, st, v);
-  return die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, 2 * R, 2, live, st, v);
+                       hipStream_t st, int rpo, const c2<T>* chi, const c2<T>* chi2) {
+  const int nc = c->ncomp;
+  if (pass == 0)
+    return die::launch_rows_fwd<T, T>(c->lpx, false, x, chi, chi2, W, c->nx, c->ny, R, nc, 0, rpo, live, st, v);
+  if (pass == 1) return die::launch_cols_symbol<T>(c->lpy, nc, W, sym_of<T>(c), c->px, c->ny, R, live, st, v);
+  return die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, nc * R, nc, live, st, v);
 }
 
 // The variants of the three passes for products of nrhs fields; tunes them first if needed
@@ -271,7 +286,7 @@ int fft_plan(die_te_ctx* c, int nrhs, hipStream_t st, const int** out) {
   const bool tuned_len[3] = {c->lpx >= die::kFftTunedMinLog, c->lpy >= die::kFftTunedMinLog,
                              c->lpx >= die::kFftTunedMinLog};
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  TuneEntry& te = g_tune[TuneKey{c->dev, prec, c->lpx, c->lpy, c->nx, c->ny}];
+  TuneEntry& te = g_tune[TuneKey{c->dev, prec, c->lpx, c->lpy, c->nx, c->ny, c->ncomp}];
   if (te.tile[bc][0] < 0) {
     const int R = std::min(nrhs, 64);
     const size_t vbytes = (size_t)R * c->nvec * sizeof(c2<T>);
@@ -282,6 +297,7 @@ int fft_plan(die_te_ctx* c, int nrhs, hipStream_t st, const int** out) {
     DIE_TRY(ensure_work(c, work_bytes(c, R, sizeof(c2<T>)), st));
     c2<T>* W = c->work.as<c2<T>>();
     const c2<T>* chi = chi_of<T>(c, false);
+    const c2<T>* chi2 = chi2_of<T>(c, false);
     hipEvent_t e0, e1;
     DIE_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -297,10 +313,10 @@ int fft_plan(die_te_ctx* c, int nrhs, hipStream_t st, const int** out) {
     } ev{e0, e1};
     auto time_pass = [&](int pass, int v, float* ms) -> int {
       for (int k = 0; k < 2; ++k)
-        DIE_HIP(launch_pass<T>(c, pass, v, xb.as<c2<T>>(), yb.as<c2<T>>(), W, R, nullptr, st, 0, chi));
+        DIE_HIP(launch_pass<T>(c, pass, v, xb.as<c2<T>>(), yb.as<c2<T>>(), W, R, nullptr, st, 0, chi, chi2));
       DIE_HIP(hipEventRecord(ev.a, st));
       for (int k = 0; k < 3; ++k)
-        DIE_HIP(launch_pass<T>(c, pass, v, xb.as<c2<T>>(), yb.as<c2<T>>(), W, R, nullptr, st, 0, chi));
+        DIE_HIP(launch_pass<T>(c, pass, v, xb.as<c2<T>>(), yb.as<c2<T>>(), W, R, nullptr, st, 0, chi, chi2));
       DIE_HIP(hipEventRecord(ev.b, st));
       DIE_HIP(hipEventSynchronize(ev.b));
       DIE_HIP(hipEventElapsedTime(ms, ev.a, ev.b));
@@ -341,7 +357,10 @@ int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const 
   const int nchi = rpo > 0 ? (nrhs + rpo - 1) / rpo : 1;
   ProfScope prof(c, DIE_PROF_PRODUCT, st, product_bytes(c, live_count(c, nrhs), nchi, sizeof(c2<T>)));
   const c2<T>* chi = chi_of<T>(c, reg) + (size_t)obj0 * c->ncell;
-  for (int pass = 0; pass < 3; ++pass) DIE_HIP(launch_pass<T>(c, pass, v[pass], x, y, W, nrhs, live, st, rpo, chi));
+  const c2<T>* chi2 = chi2_of<T>(c, reg);
+  if (chi2) chi2 += (size_t)obj0 * c->ncell;
+  for (int pass = 0; pass < 3; ++pass)
+    DIE_HIP(launch_pass<T>(c, pass, v[pass], x, y, W, nrhs, live, st, rpo, chi, chi2));
   return DIE_OK;
 }
 
@@ -1879,6 +1898,13 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
   if (o.deflate_max < 0) return fail(DIE_E_INVALID, "deflate_max must be >= 0");
   if (o.fft_variant < 0 || o.fft_variant > die::kFftVariants)
     return fail(DIE_E_INVALID, "fft_variant must be 0 (autotune) or 1 + v with v in [0, 3]");
+  if (o.polarization != 0 && o.polarization != 1) return fail(DIE_E_INVALID, "polarization must be 0 (TE) or 1 (TM)");
+  if (o.magnetic != 0 && o.magnetic != 1) return fail(DIE_E_INVALID, "magnetic must be 0 or 1");
+  if (o.polarization == 1 && (o.magnetic || o.mu_r))
+    return fail(DIE_E_INVALID, "the TM operator has no magnetic contrast option (E3 only)");
+  if (o.mu_r && !o.magnetic) return fail(DIE_E_INVALID, "mu_r needs magnetic = 1 (the E1, E2, H3 system)");
+  if (o.polarization == 1 && o.regularize)
+    return fail(DIE_E_INVALID, "the TM operator is identity plus compact: no regularizer (regularize must be 0)");
 
   auto* c = new (std::nothrow) die_te_ctx();
   if (!c) return fail(DIE_E_NOMEM, "host allocation failed");
@@ -1896,7 +1922,8 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
   c->lpx = ilog2(px); c->lpy = ilog2(py);
   c->h = gr->h; c->k = k;
   c->ncell = (size_t)gr->nx * gr->ny;
-  c->nvec = 2 * c->ncell;
+  c->ncomp = o.polarization == 1 ? 1 : (o.magnetic ? 3 : 2);
+  c->nvec = (size_t)c->ncomp * c->ncell;
   c->nobj = nobj;
   c->regularize = o.regularize ? 1 : 0;
   c->fft_force = o.fft_variant - 1;
@@ -1931,24 +1958,57 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
       hipMemcpyAsync(c->chi32.p, chi32.data(), ncells * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c->chir32.p, chir32.data(), ncells * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess)
     return guard(fail(DIE_E_HIP, "uploading the contrast failed"));
+  if (c->ncomp == 3) {
+    // magnetic contrast chi_m = mu_r - 1 (eq. ElectricContrast's magnetic counterpart) and the
+    // regularizer's chi_m' = 1/mu_r - 1; mu_r == NULL: no magnetic contrast (H3 then follows E)
+    std::vector<double2> mu(ncells, make_double2(1.0, 0.0));
+    if (o.mu_r && (hipMemcpyAsync(mu.data(), o.mu_r, ncells * sizeof(double2), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                   hipStreamSynchronize(st) != hipSuccess))
+      return guard(fail(DIE_E_HIP, "reading mu_r failed (is it a device pointer?)"));
+    std::vector<double2> cm(ncells), cmr(ncells);
+    std::vector<float2> cm32(ncells), cmr32(ncells);
+    for (size_t e = 0; e < ncells; ++e) {
+      const cd mv(mu[e].x, mu[e].y);
+      if (!std::isfinite(mv.real()) || !std::isfinite(mv.imag()))
+        return guard(fail(DIE_E_INVALID, "mu_r contains non-finite values"));
+      if (mv == cd(0.0, 0.0))
+        return guard(fail(DIE_E_SINGULAR, "mu_r == 0 at cell " + std::to_string(e % c->ncell)));
+      const cd x = mv - 1.0, xr = 1.0 / mv - 1.0;
+      cm[e] = make_double2(x.real(), x.imag());
+      cmr[e] = make_double2(xr.real(), xr.imag());
+      cm32[e] = make_float2((float)x.real(), (float)x.imag());
+      cmr32[e] = make_float2((float)xr.real(), (float)xr.imag());
+    }
+    if ((rc = c->chim64.alloc(ncells * sizeof(double2))) < 0 || (rc = c->chimr64.alloc(ncells * sizeof(double2))) < 0 ||
+        (rc = c->chim32.alloc(ncells * sizeof(float2))) < 0 || (rc = c->chimr32.alloc(ncells * sizeof(float2))) < 0)
+      return guard(rc);
+    if (hipMemcpyAsync(c->chim64.p, cm.data(), ncells * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c->chimr64.p, cmr.data(), ncells * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c->chim32.p, cm32.data(), ncells * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c->chimr32.p, cmr32.data(), ncells * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return guard(fail(DIE_E_HIP, "uploading the magnetic contrast failed"));
+  }
 
   // Green tensor, circulant embedding, symbol = FFT2 / (px py) on the GPU
   {
     std::vector<cd> planes;
-    die::green::embed(c->nx, c->ny, px, py, c->h, c->k, planes);
+    const int npl = die::sym_planes(c->ncomp);
+    die::green::embed(c->nx, c->ny, px, py, c->h, c->k, c->ncomp, planes);
     const size_t plane = (size_t)px * py;
     DBuf E, W;
-    if ((rc = E.alloc(3 * plane * sizeof(double2))) < 0 || (rc = W.alloc(3 * plane * sizeof(double2))) < 0)
+    if ((rc = E.alloc(npl * plane * sizeof(double2))) < 0 || (rc = W.alloc(npl * plane * sizeof(double2))) < 0)
       return guard(rc);
-    if (hipMemcpyAsync(E.p, planes.data(), 3 * plane * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess)
+    if (hipMemcpyAsync(E.p, planes.data(), npl * plane * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess)
       return guard(fail(DIE_E_HIP, "uploading the Green tensor failed"));
-    if ((rc = c->sym64.alloc(3 * plane * sizeof(double2))) < 0 || (rc = c->sym32.alloc(3 * plane * sizeof(float2))) < 0)
+    if ((rc = c->sym64.alloc(npl * plane * sizeof(double2))) < 0 ||
+        (rc = c->sym32.alloc(npl * plane * sizeof(float2))) < 0)
       return guard(rc);
-    hipError_t e1 = die::launch_rows_fwd<double, double>(c->lpx, false, E.as<double2>(), nullptr, W.as<double2>(), px,
-                                                         py, 3, 1, 0, 0, nullptr, st);
-    hipError_t e2 = die::launch_cols_plain<double>(c->lpy, false, W.as<double2>(), px, 3, st);
+    hipError_t e1 = die::launch_rows_fwd<double, double>(c->lpx, false, E.as<double2>(), nullptr, nullptr,
+                                                         W.as<double2>(), px, py, npl, 1, 0, 0, nullptr, st);
+    hipError_t e2 = die::launch_cols_plain<double>(c->lpy, false, W.as<double2>(), px, npl, st);
     hipError_t e3 = die::launch_pack_symbol(W.as<double2>(), c->sym64.as<double2>(), c->sym32.as<float2>(), px, py,
-                                            1.0 / ((double)px * (double)py), st);
+                                            npl, 1.0 / ((double)px * (double)py), st);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
       return guard(fail(DIE_E_HIP, "symbol transform failed"));
   }
@@ -1974,7 +2034,10 @@ int die_te_setup_multi(die_te_ctx** out, const die_te_grid* gr, int nobj, const 
     if (rcap < 1) return guard(fail(DIE_E_INVALID, "automatic deflation needs 2 nx ny >= 2"));
     c->radius.assign(nobj, 1.0);
     for (int ob = 0; ob < nobj; ++ob) {
-      const double R = die_host::deflation_radius(eps.data() + (size_t)ob * c->ncell, c->ncell, c->regularize != 0);
+      // TM: no dense segments; the paper deflates every eigenvalue outside the unit circle
+      const double R = c->ncomp == 1 ? 1.0
+                                     : die_host::deflation_radius(eps.data() + (size_t)ob * c->ncell, c->ncell,
+                                                                  c->regularize != 0);
       c->radius[ob] = R;
       for (int rt = std::min(16, rcap);; rt = std::min(2 * rt, rcap)) {
         if ((rc = alloc_deflation(1, rt)) < 0) return guard(rc);
@@ -2043,7 +2106,7 @@ int die_te_matvec_noalloc(die_te_ctx* c, const void* x, void* y, int nrhs, int p
   const size_t es = prec == DIE_C128 ? sizeof(double2) : sizeof(float2);
   const size_t need = work_bytes(c, nrhs, es);
   if (need > die::kScratchBytes)
-    return fail(DIE_E_INVALID, "die_te_matvec_noalloc: nrhs * 2 * px * ny complex values (" + std::to_string(need) +
+    return fail(DIE_E_INVALID, "die_te_matvec_noalloc: the FFT intermediate (" + std::to_string(need) +
                                    " bytes) exceed the static scratch of " + std::to_string(die::kScratchBytes) +
                                    " bytes");
   int cur = -1;
@@ -2061,7 +2124,7 @@ int die_te_matvec_noalloc(die_te_ctx* c, const void* x, void* y, int nrhs, int p
     v[0] = v[1] = v[2] = c->fft_force;
   } else {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    const auto it = g_tune.find(TuneKey{c->dev, pi, c->lpx, c->lpy, c->nx, c->ny});
+    const auto it = g_tune.find(TuneKey{c->dev, pi, c->lpx, c->lpy, c->nx, c->ny, c->ncomp});
     if (it != g_tune.end())
       for (int p = 0; p < 3; ++p) v[p] = std::max(it->second.radix[p], 0);
   }
@@ -2070,10 +2133,10 @@ int die_te_matvec_noalloc(die_te_ctx* c, const void* x, void* y, int nrhs, int p
   for (int pass = 0; pass < 3; ++pass) {
     if (prec == DIE_C128)
       DIE_HIP(launch_pass<double>(c, pass, v[pass], (const double2*)x, (double2*)y, (double2*)W, nrhs, nullptr, st,
-                                  rpo, chi_of<double>(c, false)));
+                                  rpo, chi_of<double>(c, false), chi2_of<double>(c, false)));
     else
       DIE_HIP(launch_pass<float>(c, pass, v[pass], (const float2*)x, (float2*)y, (float2*)W, nrhs, nullptr, st, rpo,
-                                 chi_of<float>(c, false)));
+                                 chi_of<float>(c, false), chi2_of<float>(c, false)));
   }
   return DIE_OK;
 }
@@ -2256,13 +2319,13 @@ int die_te_fft2(void* data, int px, int py, int batch, int inverse, int prec, vo
   DBuf W;
   if (prec == DIE_C128) {
     DIE_TRY(W.alloc(batch * plane * sizeof(double2)));
-    DIE_HIP((die::launch_rows_fwd<double, double>(ilog2(px), inv, (const double2*)data, nullptr, W.as<double2>(), px,
+    DIE_HIP((die::launch_rows_fwd<double, double>(ilog2(px), inv, (const double2*)data, nullptr, nullptr, W.as<double2>(), px,
                                                   py, batch, 1, 0, 0, nullptr, st)));
     DIE_HIP(die::launch_cols_plain<double>(ilog2(py), inv, W.as<double2>(), px, batch, st));
     DIE_HIP(die::launch_transpose<double>(W.as<double2>(), (double2*)data, px, py, batch, st));
   } else if (prec == DIE_C64) {
     DIE_TRY(W.alloc(batch * plane * sizeof(float2)));
-    DIE_HIP((die::launch_rows_fwd<float, float>(ilog2(px), inv, (const float2*)data, nullptr, W.as<float2>(), px, py,
+    DIE_HIP((die::launch_rows_fwd<float, float>(ilog2(px), inv, (const float2*)data, nullptr, nullptr, W.as<float2>(), px, py,
                                                 batch, 1, 0, 0, nullptr, st)));
     DIE_HIP(die::launch_cols_plain<float>(ilog2(py), inv, W.as<float2>(), px, batch, st));
     DIE_HIP(die::launch_transpose<float>(W.as<float2>(), (float2*)data, px, py, batch, st));
@@ -2316,6 +2379,7 @@ int die_te_warm_start(die_te_ctx* c, die_te_unet* net, const void* e_in, void* x
   if (!net || !e_in || !x0 || nrhs < 1) return fail(DIE_E_INVALID, "null argument or nrhs < 1");
   if (nrhs % c->nobj) return fail(DIE_E_INVALID, "nrhs must be a multiple of the number of objects");
   if (e_in == x0) return fail(DIE_E_INVALID, "e_in and x0 must not overlap");
+  if (c->ncomp != 2) return fail(DIE_E_INVALID, "the warm-start network serves the TE (E1, E2) system only");
   return die_host::unet_guess(net, c->chi64.as<double2>(), nrhs / c->nobj, (const double2*)e_in, (double2*)x0, nrhs,
                               c->ny, c->nx, (hipStream_t)stream);
 }

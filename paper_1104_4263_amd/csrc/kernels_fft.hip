@@ -69,9 +69,9 @@ template <class T> __host__ __device__ constexpr int cols_threads(int logn, int 
 // the upper half are known zeros at compile time and the first stage folds them away.
 template <class T, class S, int LOGN, bool INV, bool HALF, int V = 0>
 __global__ void __launch_bounds__(rows_threads<T>(LOGN, V))
-k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* __restrict__ W,
-           const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr, int rb, int rpo,
-           const int* __restrict__ live) {
+k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, const c2<T>* __restrict__ chi20,
+           c2<T>* __restrict__ W, const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int nrhs, int spr,
+           int rb, int rpo, const int* __restrict__ live) {
   using F = RegFft<T, LOGN, rows_ty<T>(LOGN, V), fft_le<T>(LOGN, V), 1, false, kPosFast, kArrFast>;
   constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN, V);
   __shared__ c2<T> lds[F::LDS_ELEMS];
@@ -82,8 +82,10 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* _
   for (int r = grp * rb; r < r1; ++r) {
     if (live && !live[r]) continue;
     // right-hand side r belongs to object r / rpo (rpo = 0: a single object)
-    const c2<T>* chi = chi0 ? chi0 + (rpo > 0 ? (size_t)(r / rpo) * nrows * nx : 0) : nullptr;
+    const size_t oo = rpo > 0 ? (size_t)(r / rpo) * nrows * nx : 0;
     for (int c = 0; c < spr; ++c) {
+      // components from the third on (H3 of the full TE system) take the second contrast
+      const c2<T>* chi = (c >= 2 && chi20) ? chi20 + oo : (chi0 ? chi0 + oo : nullptr);
       const size_t s = (size_t)r * spr + c;
       const c2<S>* xs = x + s * nrows * nx;
       // keep per-element address arithmetic inside the loop (hoisting it costs ~100 VGPRs)
@@ -130,15 +132,19 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, c2<T>* _
 // (consecutive lanes on the CX columns of one row first), so that a wave moves whole lines of
 // the tiled intermediate; the symbol multiply between the transforms runs position-fast
 // (consecutive lanes on consecutive frequencies: contiguous symbol reads).
-template <class T, int LOGN, int V = 0>
+// NC field components per right-hand side (1: TM, 2: TE, 3: TE with H3); the symbol holds
+// sym_planes(NC) values per frequency, the upper triangle of the symmetric NC x NC matrix
+// (11 | 11, 12, 22 | 11, 12, 22, 13, 23, 33).
+template <class T, int LOGN, int V = 0, int NC = 2>
 __global__ void __launch_bounds__(cols_threads<T>(LOGN, V))
 k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>* __restrict__ tw, int ncols,
               int nrows, int nrhs, const int* __restrict__ live) {
+  constexpr int NPL = sym_planes(NC);
   constexpr int CX = cols_cx<T>(LOGN, V);
   constexpr int LE = fft_le<T>(LOGN, V);
   constexpr int MEDGE = LOGN > LE ? kArrFast : kPosFast;  // one stage only: position-fast throughout
-  using F = RegFft<T, LOGN, CX, LE, 2, false, MEDGE, kPosFast, kPosFast>;
-  using G = RegFft<T, LOGN, CX, LE, 2, true, kPosFast, kPosFast, MEDGE>;
+  using F = RegFft<T, LOGN, CX, LE, NC, false, MEDGE, kPosFast, kPosFast>;
+  using G = RegFft<T, LOGN, CX, LE, NC, true, kPosFast, kPosFast, MEDGE>;
   static_assert(G::R0 == F::RL, "inverse must start with the forward's last radix");
   constexpr int N = F::N, E = F::E;
   __shared__ c2<T> lds[F::LDS_ELEMS];
@@ -149,8 +155,8 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
   if (live && !live[r]) return;
   const int rows4 = wtile_rows(nrows);
   const size_t plane = (size_t)wtile_cols(ncols) * rows4;  // one component of the tiled intermediate
-  c2<T>* Wr = W + (size_t)r * 2 * plane;
-  c2<T> v[2][E];
+  c2<T>* Wr = W + (size_t)r * NC * plane;
+  c2<T> v[NC][E];
 #pragma unroll
   for (int u = 0; u < E / F::R0; ++u)
 #pragma unroll
@@ -161,7 +167,7 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       // nrows <= N/2 (zero padding to at least 2 nrows - 1): the upper half is known zero
       const bool lower = q * (N / F::R0) < N / 2;
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < NC; ++c)
         v[c][e] = (lower && xx < ncols && pos < nrows) ? Wr[c * plane + wtile_index(xx, pos, rows4)] : mk<T>(0, 0);
     }
   F::template run<false>(v, lds, tw, t);
@@ -174,11 +180,21 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       F::out_pos(t, u, q, b, pos);
       const int xx = x0 + b, e = u * F::RL + q;
       if (xx < ncols) {
-        const c2<T>* sp = sym + ((size_t)xx * N + pos) * 3;
-        const c2<T> s11 = sp[0], s12 = sp[1], s22 = sp[2];
-        const c2<T> a = v[0][e], bb = v[1][e];
-        v[0][e] = cadd<T>(cmul<T>(s11, a), cmul<T>(s12, bb));
-        v[1][e] = cadd<T>(cmul<T>(s12, a), cmul<T>(s22, bb));
+        const c2<T>* sp = sym + ((size_t)xx * N + pos) * NPL;
+        if constexpr (NC == 1) {
+          v[0][e] = cmul<T>(sp[0], v[0][e]);
+        } else if constexpr (NC == 2) {
+          const c2<T> s11 = sp[0], s12 = sp[1], s22 = sp[2];
+          const c2<T> a = v[0][e], bb = v[1][e];
+          v[0][e] = cadd<T>(cmul<T>(s11, a), cmul<T>(s12, bb));
+          v[1][e] = cadd<T>(cmul<T>(s12, a), cmul<T>(s22, bb));
+        } else {
+          const c2<T> s11 = sp[0], s12 = sp[1], s22 = sp[2], s13 = sp[3], s23 = sp[4], s33 = sp[5];
+          const c2<T> a = v[0][e], bb = v[1][e], cc = v[2][e];
+          v[0][e] = cadd<T>(cadd<T>(cmul<T>(s11, a), cmul<T>(s12, bb)), cmul<T>(s13, cc));
+          v[1][e] = cadd<T>(cadd<T>(cmul<T>(s12, a), cmul<T>(s22, bb)), cmul<T>(s23, cc));
+          v[2][e] = cadd<T>(cadd<T>(cmul<T>(s13, a), cmul<T>(s23, bb)), cmul<T>(s33, cc));
+        }
       }
     }
   G::template run<true>(v, lds, tw, t);
@@ -192,7 +208,7 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       const int xx = x0 + b, e = u * G::RL + q;
       if (q * (N / G::RL) < N / 2 && xx < ncols && pos < nrows) {  // only rows < nrows <= N/2 are kept
 #pragma unroll
-        for (int c = 0; c < 2; ++c) Wr[c * plane + wtile_index(xx, pos, rows4)] = v[c][e];
+        for (int c = 0; c < NC; ++c) Wr[c * plane + wtile_index(xx, pos, rows4)] = v[c][e];
       }
     }
 }
@@ -293,15 +309,15 @@ __global__ void __launch_bounds__(256) k_transpose(const c2<T>* __restrict__ in,
 }
 
 __global__ void __launch_bounds__(256) k_pack_symbol(const double2* __restrict__ W, double2* __restrict__ s64,
-                                                     float2* __restrict__ s32, size_t plane, double scale) {
+                                                     float2* __restrict__ s32, size_t plane, int npl, double scale) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= plane) return;
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < npl; ++a) {
     double2 v = W[a * plane + e];
     v.x *= scale;
     v.y *= scale;
-    s64[e * 3 + a] = v;
-    s32[e * 3 + a] = make_float2((float)v.x, (float)v.y);
+    s64[e * npl + a] = v;
+    s32[e * npl + a] = make_float2((float)v.x, (float)v.y);
   }
 }
 
@@ -380,8 +396,9 @@ template <int L, class F> void for_variant(int v, F&& f) {
 }  // namespace
 
 template <class T, class S>
-hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* chi, c2<T>* W, int nx, int nrows,
-                           int nrhs, int spr, int rb, int rpo, const int* live, hipStream_t st, int v) {
+hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* chi, const c2<T>* chi2, c2<T>* W,
+                           int nx, int nrows, int nrhs, int spr, int rb, int rpo, const int* live, hipStream_t st,
+                           int v) {
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nrhs <= 0 || nrows <= 0) return hipSuccess;
@@ -396,14 +413,14 @@ hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* 
       dim3 grid((unsigned)(ntiles * ((nrhs + rbv - 1) / rbv)));                                         \
       dim3 block(rows_threads<T>(L, V));                                                                \
       if (half)                                                                                         \
-        hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, true, V>), grid, block, 0, st, x, chi, W, tw, nx, nrows, \
+        hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, true, V>), grid, block, 0, st, x, chi, chi2, W, tw, nx, nrows, \
                            ntiles, nrhs, spr, rbv, rpo, live);                                          \
       else if constexpr (V == 0) {                                                                      \
         if (inverse)                                                                                    \
-          hipLaunchKernelGGL((k_rows_fwd<T, S, L, true, false>), grid, block, 0, st, x, chi, W, tw, nx, nrows, \
+          hipLaunchKernelGGL((k_rows_fwd<T, S, L, true, false>), grid, block, 0, st, x, chi, chi2, W, tw, nx, nrows, \
                              ntiles, nrhs, spr, rbv, rpo, live);                                        \
         else                                                                                            \
-          hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, false>), grid, block, 0, st, x, chi, W, tw, nx, nrows, \
+          hipLaunchKernelGGL((k_rows_fwd<T, S, L, false, false>), grid, block, 0, st, x, chi, chi2, W, tw, nx, nrows, \
                              ntiles, nrhs, spr, rbv, rpo, live);                                        \
       }                                                                                                 \
     });                                                                                                 \
@@ -418,8 +435,9 @@ hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x, const c2<T>* 
 }
 
 template <class T>
-hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
+hipError_t launch_cols_symbol(int logn, int ncomp, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
                               const int* live, hipStream_t st, int v) {
+  if (ncomp < 1 || ncomp > 3) return hipErrorInvalidValue;
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nrhs <= 0) return hipSuccess;
@@ -430,8 +448,15 @@ hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, i
     for_variant<L>(v, [&](auto vc) {                                                                    \
       constexpr int V = decltype(vc)::value;                                                            \
       dim3 grid((unsigned)(((ncols + cols_cx<T>(L, V) - 1) / cols_cx<T>(L, V)) * nrhs));                \
-      hipLaunchKernelGGL((k_cols_symbol<T, L, V>), grid, dim3(cols_threads<T>(L, V)), 0, st, W, sym, tw, ncols, \
-                         nrows, nrhs, live);                                                            \
+      if (ncomp == 1)                                                                                   \
+        hipLaunchKernelGGL((k_cols_symbol<T, L, V, 1>), grid, dim3(cols_threads<T>(L, V)), 0, st, W, sym, tw, \
+                           ncols, nrows, nrhs, live);                                                   \
+      else if (ncomp == 2)                                                                              \
+        hipLaunchKernelGGL((k_cols_symbol<T, L, V, 2>), grid, dim3(cols_threads<T>(L, V)), 0, st, W, sym, tw, \
+                           ncols, nrows, nrhs, live);                                                   \
+      else                                                                                              \
+        hipLaunchKernelGGL((k_cols_symbol<T, L, V, 3>), grid, dim3(cols_threads<T>(L, V)), 0, st, W, sym, tw, \
+                           ncols, nrows, nrhs, live);                                                   \
     });                                                                                                 \
     break;                                                                                              \
   }
@@ -502,22 +527,23 @@ hipError_t launch_transpose(const c2<T>* in, c2<T>* out, int rows, int cols, int
   return hipGetLastError();
 }
 
-hipError_t launch_pack_symbol(const double2* W, double2* s64, float2* s32, int px, int py, double scale,
+hipError_t launch_pack_symbol(const double2* W, double2* s64, float2* s32, int px, int py, int npl, double scale,
                               hipStream_t st) {
   const size_t plane = (size_t)px * py;
   hipLaunchKernelGGL(k_pack_symbol, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, W, s64, s32,
-                     plane, scale);
+                     plane, npl, scale);
   return hipGetLastError();
 }
 
 // explicit instantiations
-template hipError_t launch_rows_fwd<double, double>(int, bool, const double2*, const double2*, double2*, int,
-                                                    int, int, int, int, int, const int*, hipStream_t, int);
-template hipError_t launch_rows_fwd<float, float>(int, bool, const float2*, const float2*, float2*, int, int,
-                                                  int, int, int, int, const int*, hipStream_t, int);
-template hipError_t launch_cols_symbol<double>(int, double2*, const double2*, int, int, int, const int*,
+template hipError_t launch_rows_fwd<double, double>(int, bool, const double2*, const double2*, const double2*,
+                                                    double2*, int, int, int, int, int, int, const int*, hipStream_t,
+                                                    int);
+template hipError_t launch_rows_fwd<float, float>(int, bool, const float2*, const float2*, const float2*, float2*,
+                                                  int, int, int, int, int, int, const int*, hipStream_t, int);
+template hipError_t launch_cols_symbol<double>(int, int, double2*, const double2*, int, int, int, const int*,
                                                hipStream_t, int);
-template hipError_t launch_cols_symbol<float>(int, float2*, const float2*, int, int, int, const int*,
+template hipError_t launch_cols_symbol<float>(int, int, float2*, const float2*, int, int, int, const int*,
                                               hipStream_t, int);
 template hipError_t launch_rows_inv_sub<double, double>(int, const double2*, const double2*, double2*, int,
                                                         int, int, int, const int*, hipStream_t, int);

@@ -36,16 +36,22 @@ __host__ __device__ constexpr size_t wtile_index(int x, int y, int rows4) {
 // ([N][nrows]).  A block handles the spr sets of rb right-hand sides (rb = 0: automatic).
 // chi holds one [nrows][nx] plane per object; right-hand side r uses plane r / rpo
 // (rpo = 0: every right-hand side uses the first plane).
+// chi2 (may be NULL): the contrast of components c >= 2 (H3 of the full TE system, chi_m),
+// laid out as chi.
 template <class T, class S>
-hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x_in, const c2<T>* chi, c2<T>* W,
+hipError_t launch_rows_fwd(int logn, bool inverse, const c2<S>* x_in, const c2<T>* chi, const c2<T>* chi2, c2<T>* W,
                            int nx, int nrows, int nrhs, int spr, int rb, int rpo, const int* live,
                            hipStream_t st, int v = 0);
 
-// Pass 2.  For every rhs r and column x < ncols of the tiled W (components c = 0, 1):
-// FFT_N over y (zero padded), 2x2 multiply by sym[x][ky][{11,12,22}], inverse FFT_N,
-// keep y < nrows; in place.
+// Symbol values per frequency for ncomp field components: the upper triangle of the symmetric
+// ncomp x ncomp Green-tensor symbol (1: TM; 3: T11, T12, T22; 6: T11, T12, T22, T13, T23, T33).
+__host__ __device__ constexpr int sym_planes(int ncomp) { return ncomp == 1 ? 1 : (ncomp == 2 ? 3 : 6); }
+
+// Pass 2.  For every rhs r and column x < ncols of the tiled W (components c < ncomp):
+// FFT_N over y (zero padded), multiply by the symmetric symbol sym[x][ky][sym_planes(ncomp)],
+// inverse FFT_N, keep y < nrows; in place.
 template <class T>
-hipError_t launch_cols_symbol(int logn, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
+hipError_t launch_cols_symbol(int logn, int ncomp, c2<T>* W, const c2<T>* sym, int ncols, int nrows, int nrhs,
                               const int* live, hipStream_t st, int v = 0);
 
 // Pass 3.  y_out[s][y][x] = u[s][y][x] - IFFT_N(W[s][:][y])[x] for x < nx (W tiled).
@@ -62,8 +68,8 @@ hipError_t launch_cols_plain(int logn, bool inverse, c2<T>* W, int ncols, int ns
 template <class T>
 hipError_t launch_transpose(const c2<T>* in, c2<T>* out, int rows, int cols, int nb, hipStream_t st);
 
-// sym64[(x * py + ky) * 3 + a] = scale * W[a][x][ky]; sym32 the rounded copy.
-hipError_t launch_pack_symbol(const double2* W, double2* sym64, float2* sym32, int px, int py,
+// sym64[(x * py + ky) * npl + a] = scale * W[a][x][ky]; sym32 the rounded copy.
+hipError_t launch_pack_symbol(const double2* W, double2* sym64, float2* sym32, int px, int py, int npl,
                               double scale, hipStream_t st);
 
 // ------------------------------------------------------------- Krylov BLAS-1

@@ -15,6 +15,8 @@ from .objects import (  # noqa: F401
     layered_square,
     ellipse_mask,
     plane_wave,
+    plane_wave_te3,
+    plane_wave_tm,
     gaussian_random_field,
     random_field_object,
     inclusion_object,

@@ -100,6 +100,22 @@ def plane_wave(g: Grid, psi: float, k: float | None = None) -> np.ndarray:
     return np.stack([-math.sin(psi) * phase, math.cos(psi) * phase]).astype(np.complex128)
 
 
+def plane_wave_te3(g: Grid, psi: float, k: float | None = None) -> np.ndarray:
+    """The TE plane wave with its out-of-plane magnetic field: [E1, E2, H3] ([3, ny, nx])."""
+    E = plane_wave(g, psi, k)
+    k = g.k if k is None else k
+    X, Y = cell_centres(g)
+    H3 = np.exp(1j * k * (X * math.cos(psi) + Y * math.sin(psi)))
+    return np.concatenate([E, H3[None]]).astype(np.complex128)
+
+
+def plane_wave_tm(g: Grid, psi: float, k: float | None = None) -> np.ndarray:
+    """Electric field E3 of a unit TM plane wave travelling at angle ``psi`` ([1, ny, nx])."""
+    k = g.k if k is None else k
+    X, Y = cell_centres(g)
+    return np.exp(1j * k * (X * math.cos(psi) + Y * math.sin(psi)))[None].astype(np.complex128)
+
+
 def gaussian_random_field(n: int, h: float, ell: float, seed: int) -> np.ndarray:
     """Unit-variance, zero-mean periodic Gaussian random field on an n x n grid.
 
