@@ -17,8 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdie_te.so")
-SOURCES = ["kernels_fft.hip", "kernels_krylov.hip", "kernels_block.hip", "kernels_unet.hip", "scratch.hip", "die_te.cpp",
-           "unet.cpp", "plan.cpp"]
+SOURCES = ["kernels_fft.hip", "kernels_krylov.hip", "kernels_block.hip", "kernels_gemm.hip", "kernels_unet.hip",
+           "scratch.hip", "die_te.cpp", "unet.cpp", "plan.cpp"]
 ARCH = "gfx950"
 
 
@@ -49,7 +49,7 @@ def build(verbose: bool = True) -> str:
             list(ex.map(lambda so: _compile(*so), zip(SOURCES, objs)))
         out_tmp = LIB + ".tmp"
         cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp] + objs + \
-            ["-L/opt/rocm/lib", "-lhipblaslt", "-lrocsolver", "-lrocblas", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]
+            ["-lpthread"]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"linking failed:\n{res.stdout}\n{res.stderr}")

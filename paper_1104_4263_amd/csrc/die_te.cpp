@@ -23,9 +23,6 @@
 #include <thread>
 #include <vector>
 
-#include <hipblaslt/hipblaslt.h>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include "dense.hpp"
 #include "green.hpp"
@@ -48,29 +45,6 @@ namespace {
 
 using die_host::DBuf;
 using die_host::fail;
-
-// hipBLASLt plans of the binary16 GEMMs of the block solver (binary16 inputs, FP32 output and
-// accumulation), one per shape, and the workspace they share.
-struct LtPlan {
-  hipblasLtMatmulDesc_t desc = nullptr;
-  hipblasLtMatrixLayout_t a = nullptr, b = nullptr, d = nullptr;
-  hipblasLtMatmulAlgo_t algo{};
-  size_t ws = 0;
-};
-struct LtCache {
-  hipblasLtHandle_t h = nullptr;
-  std::map<std::array<int64_t, 11>, LtPlan> plans;
-  DBuf ws;
-  ~LtCache() {
-    for (auto& kv : plans) {
-      if (kv.second.a) (void)hipblasLtMatrixLayoutDestroy(kv.second.a);
-      if (kv.second.b) (void)hipblasLtMatrixLayoutDestroy(kv.second.b);
-      if (kv.second.d) (void)hipblasLtMatrixLayoutDestroy(kv.second.d);
-      if (kv.second.desc) (void)hipblasLtMatmulDescDestroy(kv.second.desc);
-    }
-    if (h) (void)hipblasLtDestroy(h);
-  }
-};
 
 // Work buffers of the block solver, kept in the context between calls (defined with the solver).
 struct BlockWork;
@@ -120,12 +94,9 @@ struct die_te_ctx {
   int prof_nlive = -1;  // right-hand sides live in the current launches (-1: all of them)
   // FFT pass variants of the products: forced (>= 0) or tuned per [FP64, FP32][batch class][pass]
   int fft_force = -1;
-  rocblas_handle blas = nullptr;  // block GMRES: GEMMs and the block least squares
-  std::unique_ptr<LtCache> lt;    // block GMRES, binary16 planar GEMMs
   std::shared_ptr<BlockWork> bw;  // block GMRES work buffers, reused by later calls
   int fftv[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}, {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};
   ~die_te_ctx() {
-    if (blas) (void)rocblas_destroy_handle(blas);
     for (auto& v : prof_ev)
       for (auto& pr : v) {
         (void)hipEventDestroy(pr.first);
@@ -1010,276 +981,10 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
 }
 
 // ------------------------------------------------------------------ block GMRES
-#define DIE_BLAS(expr)                                                                              \
-  do {                                                                                              \
-    rocblas_status _s = (expr);                                                                     \
-    if (_s != rocblas_status_success)                                                               \
-      return die_host::fail(DIE_E_HIP, std::string(#expr) + ": " + rocblas_status_to_string(_s));  \
-  } while (0)
-
-int blas_on(die_te_ctx* c, hipStream_t st, rocblas_handle* h) {
-  if (!c->blas) {
-    rocblas_handle nh = nullptr;
-    DIE_BLAS(rocblas_create_handle(&nh));
-    c->blas = nh;
-    DIE_BLAS(rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed));  // fixed-order sums
-  }
-  DIE_BLAS(rocblas_set_stream(c->blas, st));
-  *h = c->blas;
-  return DIE_OK;
-}
-
-#define DIE_LT(expr)                                                                               \
-  do {                                                                                             \
-    hipblasStatus_t _s = (expr);                                                                   \
-    if (_s != HIPBLAS_STATUS_SUCCESS)                                                              \
-      return die_host::fail(DIE_E_HIP, std::string(#expr) + ": hipBLASLt status " + std::to_string((int)_s)); \
-  } while (0)
-
-// D_b = alpha op(A_b) B_b + beta D_b for b < batch (strides sa, sb, sd in elements), column-major:
-// A (binary16; m x k, or k x m read transposed when ta), B (binary16, k x n), D (FP32, m x n).
-// The plan of each shape is made once (hipBLASLt's first heuristic choice) and kept.
-int lt_gemm(die_te_ctx* c, bool ta, int m, int n, int k, float alpha, const _Float16* A, int64_t lda, int64_t sa,
-            const _Float16* B, int64_t ldb, int64_t sb, float beta, float* D, int64_t ldd, int64_t sd, int batch,
-            hipStream_t st) {
-  if (!c->lt) {
-    c->lt.reset(new LtCache());
-    DIE_LT(hipblasLtCreate(&c->lt->h));
-  }
-  LtCache& L = *c->lt;
-  const std::array<int64_t, 11> key = {ta ? 1 : 0, m, n, k, lda, sa, ldb, sb, ldd, sd, batch};
-  auto it = L.plans.find(key);
-  if (it == L.plans.end()) {
-    LtPlan pl;
-    auto mk_layout = [&](hipblasLtMatrixLayout_t* lay, hipDataType ty, int64_t r, int64_t cl, int64_t ld,
-                         int64_t stride) -> int {
-      DIE_LT(hipblasLtMatrixLayoutCreate(lay, ty, (uint64_t)r, (uint64_t)cl, ld));
-      if (batch > 1) {
-        const int32_t bc = batch;
-        DIE_LT(hipblasLtMatrixLayoutSetAttribute(*lay, HIPBLASLT_MATRIX_LAYOUT_BATCH_COUNT, &bc, sizeof(bc)));
-        DIE_LT(hipblasLtMatrixLayoutSetAttribute(*lay, HIPBLASLT_MATRIX_LAYOUT_STRIDED_BATCH_OFFSET, &stride,
-                                                 sizeof(stride)));
-      }
-      return DIE_OK;
-    };
-    int rc = [&]() -> int {
-      DIE_LT(hipblasLtMatmulDescCreate(&pl.desc, HIPBLAS_COMPUTE_32F, HIP_R_32F));
-      const int32_t opa = ta ? HIPBLAS_OP_T : HIPBLAS_OP_N, opb = HIPBLAS_OP_N;
-      DIE_LT(hipblasLtMatmulDescSetAttribute(pl.desc, HIPBLASLT_MATMUL_DESC_TRANSA, &opa, sizeof(opa)));
-      DIE_LT(hipblasLtMatmulDescSetAttribute(pl.desc, HIPBLASLT_MATMUL_DESC_TRANSB, &opb, sizeof(opb)));
-      DIE_TRY(mk_layout(&pl.a, HIP_R_16F, ta ? k : m, ta ? m : k, lda, sa));
-      DIE_TRY(mk_layout(&pl.b, HIP_R_16F, k, n, ldb, sb));
-      DIE_TRY(mk_layout(&pl.d, HIP_R_32F, m, n, ldd, sd));
-      hipblasLtMatmulPreference_t pref = nullptr;
-      DIE_LT(hipblasLtMatmulPreferenceCreate(&pref));
-      const uint64_t wmax = (uint64_t)64 << 20;
-      hipblasLtMatmulHeuristicResult_t res[4];
-      int got = 0;
-      hipblasStatus_t hs = hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES,
-                                                                 &wmax, sizeof(wmax));
-      if (hs == HIPBLAS_STATUS_SUCCESS)
-        hs = hipblasLtMatmulAlgoGetHeuristic(L.h, pl.desc, pl.a, pl.b, pl.d, pl.d, pref, 4, res, &got);
-      (void)hipblasLtMatmulPreferenceDestroy(pref);
-      DIE_LT(hs);
-      int pick = -1;
-      for (int i = 0; i < got && pick < 0; ++i)
-        if (res[i].state == HIPBLAS_STATUS_SUCCESS) pick = i;
-      if (pick < 0)
-        return fail(DIE_E_HIP, "hipBLASLt has no binary16 GEMM for shape m=" + std::to_string(m) +
-                                   " n=" + std::to_string(n) + " k=" + std::to_string(k));
-      pl.algo = res[pick].algo;
-      pl.ws = res[pick].workspaceSize;
-      return DIE_OK;
-    }();
-    if (rc != DIE_OK) {
-      if (pl.a) (void)hipblasLtMatrixLayoutDestroy(pl.a);
-      if (pl.b) (void)hipblasLtMatrixLayoutDestroy(pl.b);
-      if (pl.d) (void)hipblasLtMatrixLayoutDestroy(pl.d);
-      if (pl.desc) (void)hipblasLtMatmulDescDestroy(pl.desc);
-      return rc;
-    }
-    it = L.plans.emplace(key, pl).first;
-  }
-  const LtPlan& pl = it->second;
-  if (pl.ws > L.ws.bytes) {
-    DIE_HIP(hipStreamSynchronize(st));  // the old workspace may still be in use
-    DIE_TRY(L.ws.alloc(pl.ws));
-  }
-  DIE_LT(hipblasLtMatmul(L.h, pl.desc, &alpha, A, pl.a, B, pl.b, &beta, D, pl.d, D, pl.d, &pl.algo,
-                         pl.ws ? L.ws.p : nullptr, pl.ws, st));
-  return DIE_OK;
-}
-
-// C = alpha op(A) op(B) + beta C, column-major complex in the precision of T (matrix cores).
-template <class T>
-rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, cd alpha,
-                    const c2<T>* A, int lda, const c2<T>* B, int ldb, cd beta, c2<T>* C, int ldc);
-template <>
-rocblas_status gemm<double>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                            cd alpha, const double2* A, int lda, const double2* B, int ldb, cd beta, double2* C,
-                            int ldc) {
-  const rocblas_double_complex a(alpha.real(), alpha.imag()), b(beta.real(), beta.imag());
-  return rocblas_zgemm(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                       reinterpret_cast<const rocblas_double_complex*>(B), ldb, &b,
-                       reinterpret_cast<rocblas_double_complex*>(C), ldc);
-}
-template <>
-rocblas_status gemm<float>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                           cd alpha, const float2* A, int lda, const float2* B, int ldb, cd beta, float2* C,
-                           int ldc) {
-  const rocblas_float_complex a((float)alpha.real(), (float)alpha.imag()), b((float)beta.real(), (float)beta.imag());
-  return rocblas_cgemm(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_float_complex*>(A), lda,
-                       reinterpret_cast<const rocblas_float_complex*>(B), ldb, &b,
-                       reinterpret_cast<rocblas_float_complex*>(C), ldc);
-}
-
-constexpr rocblas_operation kN = rocblas_operation_none, kH = rocblas_operation_conjugate_transpose;
-
-template <class T>
-rocblas_status gemm_batched(rocblas_handle h, int m, int n, int k, const c2<T>* A, int lda, rocblas_stride sa,
-                            const c2<T>* B, int ldb, rocblas_stride sb, c2<T>* C, int ldc, rocblas_stride sc, int batch);
-template <>
-rocblas_status gemm_batched<double>(rocblas_handle h, int m, int n, int k, const double2* A, int lda, rocblas_stride sa,
-                                    const double2* B, int ldb, rocblas_stride sb, double2* C, int ldc,
-                                    rocblas_stride sc, int batch) {
-  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  return rocblas_zgemm_strided_batched(h, kH, kN, m, n, k, &one, reinterpret_cast<const rocblas_double_complex*>(A),
-                                       lda, sa, reinterpret_cast<const rocblas_double_complex*>(B), ldb, sb, &zero,
-                                       reinterpret_cast<rocblas_double_complex*>(C), ldc, sc, batch);
-}
-template <>
-rocblas_status gemm_batched<float>(rocblas_handle h, int m, int n, int k, const float2* A, int lda, rocblas_stride sa,
-                                   const float2* B, int ldb, rocblas_stride sb, float2* C, int ldc, rocblas_stride sc,
-                                   int batch) {
-  const rocblas_float_complex one(1.0f, 0.0f), zero(0.0f, 0.0f);
-  return rocblas_cgemm_strided_batched(h, kH, kN, m, n, k, &one, reinterpret_cast<const rocblas_float_complex*>(A),
-                                       lda, sa, reinterpret_cast<const rocblas_float_complex*>(B), ldb, sb, &zero,
-                                       reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, batch);
-}
-template <class T>
-rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, cd alpha,
-                       const c2<T>* A, int lda, rocblas_stride sa, const c2<T>* B, int ldb, rocblas_stride sb, cd beta,
-                       c2<T>* C, int ldc, rocblas_stride sc, int batch);
-template <>
-rocblas_status gemm_sb<double>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                               cd alpha, const double2* A, int lda, rocblas_stride sa, const double2* B, int ldb,
-                               rocblas_stride sb, cd beta, double2* C, int ldc, rocblas_stride sc, int batch) {
-  const rocblas_double_complex a(alpha.real(), alpha.imag()), b(beta.real(), beta.imag());
-  return rocblas_zgemm_strided_batched(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                                       sa, reinterpret_cast<const rocblas_double_complex*>(B), ldb, sb, &b,
-                                       reinterpret_cast<rocblas_double_complex*>(C), ldc, sc, batch);
-}
-template <>
-rocblas_status gemm_sb<float>(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                              cd alpha, const float2* A, int lda, rocblas_stride sa, const float2* B, int ldb,
-                              rocblas_stride sb, cd beta, float2* C, int ldc, rocblas_stride sc, int batch) {
-  const rocblas_float_complex a((float)alpha.real(), (float)alpha.imag()), b((float)beta.real(), (float)beta.imag());
-  return rocblas_cgemm_strided_batched(h, ta, tb, m, n, k, &a, reinterpret_cast<const rocblas_float_complex*>(A), lda,
-                                       sa, reinterpret_cast<const rocblas_float_complex*>(B), ldb, sb, &b,
-                                       reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, batch);
-}
-// C = A + B (m x n; leading dimensions lda, ldb, ldc)
-template <class T>
-rocblas_status geam_add(rocblas_handle h, int m, int n, const c2<T>* A, int lda, const c2<T>* B, int ldb, c2<T>* C,
-                        int ldc);
-template <>
-rocblas_status geam_add<double>(rocblas_handle h, int m, int n, const double2* A, int lda, const double2* B, int ldb,
-                                double2* C, int ldc) {
-  const rocblas_double_complex one(1.0, 0.0);
-  return rocblas_zgeam(h, kN, kN, m, n, &one, reinterpret_cast<const rocblas_double_complex*>(A), lda, &one,
-                       reinterpret_cast<const rocblas_double_complex*>(B), ldb,
-                       reinterpret_cast<rocblas_double_complex*>(C), ldc);
-}
-template <>
-rocblas_status geam_add<float>(rocblas_handle h, int m, int n, const float2* A, int lda, const float2* B, int ldb,
-                               float2* C, int ldc) {
-  const rocblas_float_complex one(1.0f, 0.0f);
-  return rocblas_cgeam(h, kN, kN, m, n, &one, reinterpret_cast<const rocblas_float_complex*>(A), lda, &one,
-                       reinterpret_cast<const rocblas_float_complex*>(B), ldb,
-                       reinterpret_cast<rocblas_float_complex*>(C), ldc);
-}
-
-// W (K x n, leading dimension ldw) = alpha Q (K x m, leading dimension ldq) H (m x n, leading
-// dimension ldh) + beta W with K long: a strided batch over row chunks of Q and W (the same H),
-// which gives the matrix cores a tile shape that fits the narrow n.
-template <class T>
-int gemm_rows_long(rocblas_handle h, int K, int n, int m, cd alpha, const c2<T>* Q, int ldq, const c2<T>* H, int ldh,
-                   cd beta, c2<T>* W, int ldw) {
-  int rc = K;
-  for (int c = 1024; c >= 256; c /= 2)
-    if (K % c == 0 && K / c >= 16) {
-      rc = c;
-      break;
-    }
-  if (rc == K) {
-    DIE_BLAS(gemm<T>(h, kN, kN, K, n, m, alpha, Q, ldq, H, ldh, beta, W, ldw));
-    return DIE_OK;
-  }
-  DIE_BLAS(gemm_sb<T>(h, kN, kN, rc, n, m, alpha, Q, ldq, rc, H, ldh, 0, beta, W, ldw, rc, K / rc));
-  return DIE_OK;
-}
-template <class T>
-int gemm_update_long(rocblas_handle h, int K, int n, int m, const c2<T>* Q, int ldq, const c2<T>* H, int ldh, c2<T>* W,
-                     int ldw) {
-  return gemm_rows_long<T>(h, K, n, m, -1.0, Q, ldq, H, ldh, 1.0, W, ldw);
-}
-
-template <class T>
-rocblas_status gemv(rocblas_handle h, int m, int n, const c2<T>* A, int lda, const c2<T>* x, c2<T>* y);
-template <>
-rocblas_status gemv<double>(rocblas_handle h, int m, int n, const double2* A, int lda, const double2* x, double2* y) {
-  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  return rocblas_zgemv(h, kN, m, n, &one, reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                       reinterpret_cast<const rocblas_double_complex*>(x), 1, &zero,
-                       reinterpret_cast<rocblas_double_complex*>(y), 1);
-}
-template <>
-rocblas_status gemv<float>(rocblas_handle h, int m, int n, const float2* A, int lda, const float2* x, float2* y) {
-  const rocblas_float_complex one(1.0f, 0.0f), zero(0.0f, 0.0f);
-  return rocblas_cgemv(h, kN, m, n, &one, reinterpret_cast<const rocblas_float_complex*>(A), lda,
-                       reinterpret_cast<const rocblas_float_complex*>(x), 1, &zero,
-                       reinterpret_cast<rocblas_float_complex*>(y), 1);
-}
-
-// Scratch of the long inner-dimension products: chunk partials and a vector of ones.
-struct LongGemm {
-  DBuf part, ones;
-  size_t ones_es = 0;  // bytes per complex value of the uploaded ones (the precision they were made for)
-};
-constexpr size_t kLongGemmPartial = (size_t)1 << 25;  // complex values
-
-// C (m x n, leading dimension m) = A^H B for A (K x m), B (K x n), K long (a vector length):
-// the K range is cut into equal chunks that a strided-batched GEMM multiplies in parallel
-// (a plain GEMM over K leaves the chip idle when m n is small), and one GEMV sums the chunk
-// products in a fixed order.
-template <class T>
-int gemm_hn_long(rocblas_handle h, LongGemm& lg, int m, int n, int K, const c2<T>* A, int lda, const c2<T>* B,
-                 int ldb, c2<T>* C, hipStream_t st) {
-  int nch = 1;
-  for (int c = 256; c >= 2; c /= 2)
-    if (K % c == 0 && K / c >= 256 && (size_t)m * n * c <= kLongGemmPartial) {
-      nch = c;
-      break;
-    }
-  if (nch == 1) {
-    DIE_BLAS(gemm<T>(h, kH, kN, m, n, K, 1.0, A, lda, B, ldb, 0.0, C, m));
-    return DIE_OK;
-  }
-  // the scratch may have served the other precision before: sizes in bytes, ones re-made per type
-  DIE_TRY(lg.part.alloc(kLongGemmPartial * sizeof(c2<T>)));  // holds m n nch values (nch was chosen so)
-  if (lg.ones_es != sizeof(c2<T>)) {
-    std::vector<c2<T>> o(256, die::mk<T>((T)1, (T)0));
-    DIE_TRY(lg.ones.alloc(256 * sizeof(c2<T>)));
-    DIE_HIP(hipMemcpyAsync(lg.ones.p, o.data(), 256 * sizeof(c2<T>), hipMemcpyHostToDevice, st));
-    DIE_HIP(hipStreamSynchronize(st));
-    lg.ones_es = sizeof(c2<T>);
-  }
-  const int ck = K / nch;
-  c2<T>* part = lg.part.as<c2<T>>();
-  DIE_BLAS(gemm_batched<T>(h, m, n, ck, A, lda, ck, B, ldb, ck, part, m, (rocblas_stride)m * n, nch));
-  DIE_BLAS(gemv<T>(h, m * n, nch, part, m * n, lg.ones.as<c2<T>>(), C));
-  return DIE_OK;
-}
+// Scratch of the block products: the projection's chunk products (accumulation type) and the
+// Gram matrices' chunk partials (complex FP64).
+constexpr size_t kTsqPartial = (size_t)1 << 25;
+constexpr size_t kGramPartial = (size_t)1 << 20;
 
 // Host <-> device transfers of a small column-major matrix (rows x cols, leading dimension
 // = rows on the device) in the precision of T.
@@ -1299,63 +1004,9 @@ template <class T> int upload(const die::la::Mat& M, void* d, hipStream_t st, st
   return DIE_OK;
 }
 
-// ---- binary16 planar GEMMs of the block Arnoldi step (complex64 basis).  Qs holds every
-// p-column block of the basis planar in binary16 (n x 2p: real parts, then imaginary parts), so
-// that Q^H W and W -= Q H are real GEMMs on the binary16 matrix cores with FP32 accumulation.
-constexpr size_t kHalfProjPartial = (size_t)1 << 25;  // FP32 values of the projection's chunk products
 // CholQR of a new block: one pass when the smallest pivot of the unit-diagonal Gram's Cholesky is
 // at least this (the second pass of CholQR2 otherwise)
 constexpr double kCholQRSinglePivot = 0.05;
-
-// Binary16 planar copy of the new basis block X (n x p complex64) into its place in Qs.
-template <class T>
-int half_shadow(const c2<T>* X, size_t n, int p, _Float16* Qsj, hipStream_t st) {
-  if constexpr (std::is_same<T, float>::value) {
-    DIE_HIP(die::launch_planar_split(X, n, n, p, nullptr, Qsj, n, st));
-    return DIE_OK;
-  } else {
-    return fail(DIE_E_INVALID, "binary16 GEMMs need a complex64 basis");
-  }
-}
-
-// Chunks of the projection's inner dimension K = n: a power of two that keeps K / nch >= 512,
-// the chunk products within kHalfProjPartial and about 256 output tiles in flight.
-int half_chunks(size_t K, int rows, int cols) {
-  const size_t tiles = (size_t)((rows + 255) / 256) * (size_t)((cols + 255) / 256);
-  for (int cnum = 256; cnum >= 2; cnum /= 2)
-    if (K % cnum == 0 && K / cnum >= 512 && (size_t)rows * cols * cnum <= kHalfProjPartial && tiles * cnum <= 256)
-      return cnum;
-  return 1;
-}
-
-// npass block classical Gram-Schmidt passes of W (n x p complex64) against the first nq basis
-// columns: per pass H_pass = Q^H W (nq x p, complex64 holding binary16-rounded values) and
-// W -= Q H_pass, both as binary16 GEMMs on the planar copies (the projection chunked over K, its
-// chunk products summed in fixed order).  W stays planar in FP32 between the passes; the
-// binary16 copy that the next projection reads is made from it.  The result goes to Wout.
-template <class T>
-int half_block_cgs(die_te_ctx* c, const _Float16* Qs, const c2<T>* W, c2<T>* Wout, size_t n, int nq, int p, int npass,
-                   float* Ws, _Float16* Wh, float* Cpart, c2<T>* const* H, _Float16* Hb, hipStream_t st) {
-  if constexpr (std::is_same<T, float>::value) {
-    const int M = 2 * nq, P2 = 2 * p;
-    DIE_HIP(die::launch_planar_split(W, n, n, p, Ws, Wh, n, st));
-    const int nch = half_chunks(n, M, P2);
-    const int64_t ck = (int64_t)(n / nch);
-    for (int pass = 0; pass < npass; ++pass) {
-      if (pass > 0) DIE_HIP(die::launch_planar_to_half(Ws, n, n, p, Wh, st));
-      DIE_TRY(lt_gemm(c, true, M, P2, (int)ck, 1.0f, Qs, (int64_t)n, ck, Wh, (int64_t)n, ck, 0.0f, Cpart, M,
-                      (int64_t)M * P2, nch, st));
-      DIE_HIP(die::launch_planar_combine(Cpart, nch, nq, p, H[pass], Hb, st));
-      // flops 8 n p nq; operands: Qs (n x 2nq binary16) and Hb read, Ws (n x 2p FP32) read and written
-      ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq, 2.0 * n * M + 8.0 * n * P2 + 2.0 * M * P2);
-      DIE_TRY(lt_gemm(c, false, (int)n, P2, M, -1.0f, Qs, (int64_t)n, 0, Hb, M, 0, 1.0f, Ws, (int64_t)n, 0, 1, st));
-    }
-    DIE_HIP(die::launch_planar_merge(Ws, n, n, p, Wout, n, st));
-    return DIE_OK;
-  } else {
-    return fail(DIE_E_INVALID, "binary16 GEMMs need a complex64 basis");
-  }
-}
 
 // Page-locked host memory (hipHostMalloc), released with the owner.
 struct PinnedBuf {
@@ -1383,14 +1034,88 @@ struct PinnedBuf {
 };
 
 struct BlockWork {
-  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, sm2, Ht, Hls, Bls, ones, idxd, infod, part, coef, cnt,
-      scl, Uq, sq, Qs, Wsb, Whb, Cpart, Hbh;
-  LongGemm lg64, lgT;  // scratch of the long inner-dimension products (FP64 first block, basis precision)
-  PinnedBuf pin;       // page-locked slots of the per-step uploads
-  DBuf Zall;                // per right-hand side: the correction V Y of its last cycle (FP64)
+  DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, sm2, Ht, Hls, Bls, ones, idxd, part, coef, cnt, scl, Uq,
+      sq;
+  // the planar Gram-Schmidt on the matrix cores: the basis shadows (T1, T2), the block being
+  // orthogonalised (planar in the basis precision) and its T1 copy, the projection's chunk
+  // products and their two-stage sums, the real update matrix, the FP64 planar copy of the first
+  // block and the Gram result
+  DBuf Q1, Q2, Wacc, W1, Cpart, Csum, Hbm, P64, Gd;
+  PinnedBuf pin;             // page-locked slots of the per-step uploads
+  DBuf Zall;                 // per right-hand side: the correction V Y of its last cycle (FP64)
   std::vector<char> zvalid;  // which columns of Zall hold one
   DBuf Ubest, bmask;         // best iterate so far per right-hand side, and the copy mask
 };
+
+// Buffers of the planar Gram-Schmidt for element type E (basis precision T): nrow padded rows,
+// column capacity ccap of the basis shadows, block width at most pw.
+template <class T, class E>
+int planar_alloc(BlockWork& bw, size_t nrow, size_t ccap, int pw) {
+  using A = typename die::GemmTile<E>::Acc;
+  static_assert(std::is_same<A, T>::value, "the planar block is held in the basis precision");
+  const size_t cols = die::gemm_pad((size_t)2 * pw);
+  DIE_TRY(bw.Q1.alloc(nrow * ccap * sizeof(E)));
+  DIE_TRY(bw.Q2.alloc(nrow * ccap * sizeof(E)));
+  DIE_TRY(bw.Wacc.alloc(nrow * cols * sizeof(A)));
+  DIE_TRY(bw.W1.alloc(nrow * cols * sizeof(E)));
+  DIE_TRY(bw.Cpart.alloc(kTsqPartial * sizeof(A)));
+  DIE_TRY(bw.Csum.alloc(die::kTsqScratch * sizeof(double)));
+  DIE_TRY(bw.Hbm.alloc(ccap * 2 * pw * sizeof(E)));
+  DIE_TRY(bw.P64.alloc(nrow * cols * sizeof(double)));
+  DIE_TRY(bw.Gd.alloc((size_t)die::kPanelMaxCols * die::kPanelMaxCols * sizeof(double2)));
+  return DIE_OK;
+}
+
+// Block j (n x p) of the basis into columns [2 p j, 2 p (j + 1)) of both shadows.
+template <class T, class E>
+int planar_shadow(BlockWork& bw, const c2<T>* X, size_t n, int p, int j, size_t nrow, size_t ccap, hipStream_t st) {
+  using A = typename die::GemmTile<E>::Acc;
+  DIE_HIP((die::launch_tsq_split<T, A, E>(X, n, n, p, 2 * p * j, nrow, ccap, nullptr, 0, bw.Q1.as<E>(), bw.Q2.as<E>(),
+                                          st)));
+  return DIE_OK;
+}
+
+// npass block classical Gram-Schmidt passes of W (n x p) against the first nq basis columns on
+// the matrix cores: per pass H_pass = Q^H W (nq x p, rounded to E) and W -= Q H_pass as real
+// products of the planar shadows.  W is split into the planar Wacc (basis precision) and stays
+// there, its T1 copy remade for each projection; the caller merges it back.
+template <class T, class E>
+int planar_block_cgs(die_te_ctx* c, BlockWork& bw, const c2<T>* W, size_t n, int nq, int p, int npass, size_t nrow,
+                     size_t ccap, c2<T>* const* H, hipStream_t st) {
+  using A = typename die::GemmTile<E>::Acc;
+  A* Ws = bw.Wacc.as<A>();
+  E* W1 = bw.W1.as<E>();
+  const int M = 2 * nq, P2 = 2 * p, ldhb = (int)die::gemm_pad((size_t)M);
+  DIE_HIP((die::launch_tsq_split<T, A, E>(W, n, n, p, 0, nrow, ccap, Ws, nrow, W1, nullptr, st)));
+  for (int pass = 0; pass < npass; ++pass) {
+    if (pass > 0) DIE_HIP((die::launch_tsq_to_t1<A, E>(Ws, nrow, nrow, P2, W1, st)));
+    int nch = 0;
+    DIE_HIP((die::launch_tsq_proj<E>(bw.Q1.as<E>(), M, W1, P2, nrow, bw.Cpart.as<A>(), kTsqPartial, &nch, st)));
+    DIE_HIP((die::launch_tsq_combine<A, E, T>(bw.Cpart.as<A>(), nch, nq, p, H[pass], bw.Hbm.as<E>(), ldhb,
+                                              bw.Csum.as<double>(), die::kTsqScratch, st)));
+    // flops 8 n p nq; operands: Q (n x 2nq) and Hb read, Ws (n x 2p) read and written
+    ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq,
+                   (double)sizeof(E) * ((double)n * M + (double)M * P2) + 2.0 * sizeof(A) * (double)n * P2);
+    DIE_HIP((die::launch_tsq_update<E>(bw.Q2.as<E>(), M, ccap, nrow, bw.Hbm.as<E>(), ldhb, P2, Ws, nrow, st)));
+  }
+  return DIE_OK;
+}
+
+// G = X^H X (p x p <= 64 x 64) of the complex block held planar in Xs (nrow rows), downloaded to
+// the host (FP64 sums of products in A).
+template <class A>
+int gram_planar(BlockWork& bw, const A* Xs, size_t nrow, int p, die::la::Mat& G, hipStream_t st) {
+  DIE_HIP(die::launch_gram_planar<A>(Xs, nrow, p, bw.Cpart.as<A>(), kTsqPartial,
+                                     bw.Csum.as<double>(), die::kTsqScratch, bw.Gd.as<double2>(), st));
+  return download<double>(bw.Gd.p, p, p, G, st);
+}
+// The same for a complex block X (n x p, leading dimension n): split into planar Xs first.
+template <class T>
+int gram_complex(BlockWork& bw, const c2<T>* X, size_t n, size_t nrow, int p, T* Xs, die::la::Mat& G, hipStream_t st) {
+  DIE_HIP((die::launch_tsq_split<T, T, T>(X, n, n, p, 0, nrow, 32, Xs, nrow, nullptr, nullptr, st)));
+  return gram_planar<T>(bw, Xs, nrow, p, G, st);
+}
+
 // A narrowed block (at most this many right-hand sides of an object left) starts its cycle from
 // the residuals and the previous cycle's corrections of the same right-hand sides.
 constexpr int kAugmentMax = 16;
@@ -1404,10 +1129,12 @@ template <class T> int upload_async(const die::la::Mat& M, void* d, c2<T>* slot,
 }
 
 // Restarted block GMRES(m) (Section 4's GMRES applied to all right-hand sides of an object
-// at once): per object, the active residuals (normalised) span the first block through a
-// rank-revealing (pivoted) Cholesky QR; block Arnoldi with CGS2 as GEMMs and CholQR2 for each
-// new block; the block least squares once per cycle (rocSOLVER); every cycle restarts from
-// the FP64 true residual, as in the per-rhs solver.  Objects are processed one after another.
+// at once): per object (in groups of at most kPanelMaxCols right-hand sides), the active
+// residuals (normalised) span the first block through a rank-revealing (pivoted) Cholesky QR;
+// block Arnoldi with CGS2 on the matrix cores and CholQR2 for each new block; the block least
+// squares once per cycle on the GPU (panel Householder QR and a triangular solve); every cycle
+// restarts from the FP64 true residual, as in the per-rhs solver.  Objects are processed one
+// after another.
 template <class T>
 int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
                       die_te_solve_info* info, hipStream_t st, std::vector<char>* stalled = nullptr,
@@ -1421,7 +1148,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   const bool defl = c->r > 0;
   const int rpo = nrhs / c->nobj;  // right-hand sides per object
   // the widest block the buffers hold: rpo, or the most right-hand sides of one object in `only`
-  // (the only ones iterated when it is given)
+  // (the only ones iterated when it is given), at most kPanelMaxCols (wider sets run in groups)
   int pw = rpo;
   if (only) {
     pw = 1;
@@ -1431,23 +1158,25 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       pw = std::max(pw, cntv);
     }
   }
+  pw = std::min(pw, die::kPanelMaxCols);
   const double tol = o.tol > 0 ? o.tol : 1e-8;
   const double chol_tol = std::is_same<T, float>::value ? 1e-6 : 1e-12;  // rank test of a new block
   const double rank_tau2 = 1e-12;  // initial block: drop residual directions below 1e-6 (unit columns)
   const int npass = o.orth == 1 ? 1 : 2;  // block CGS passes against the previous blocks
   if ((size_t)n > (size_t)INT32_MAX || (size_t)(m + 1) * pw > 65535)
-    return fail(DIE_E_INVALID, "block GMRES: vectors or blocks too large for the GEMM interface");
-  rocblas_handle bh;
-  DIE_TRY(blas_on(c, st, &bh));
-  const int ni = (int)n, ldh = (m + 1) * pw;
+    return fail(DIE_E_INVALID, "block GMRES: vectors or blocks too large");
+  if ((size_t)m * pw > (size_t)die::kTrsmMaxRows)
+    return fail(DIE_E_INVALID, "block GMRES: restart times block width exceeds the device least squares (" +
+                                   std::to_string(die::kTrsmMaxRows) + ")");
+  const int ldh = (m + 1) * pw;
   const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
   // work buffers live in the context, so repeated calls (restarted solves, batches) reuse them
   if (!c->bw) c->bw = std::make_shared<BlockWork>();
   BlockWork& bw = *c->bw;
   DBuf &Rs = bw.Rs, &Sd = bw.Sd, &partn = bw.partn, &nrm = bw.nrm, &active = bw.active, &Vb = bw.Vb, &Wt = bw.Wt,
        &Zb = bw.Zb, &Tm = bw.Tm, &Ra = bw.Ra, &Tb = bw.Tb, &sm = bw.sm, &sm2 = bw.sm2, &Ht = bw.Ht, &Hls = bw.Hls,
-       &Bls = bw.Bls, &ones = bw.ones, &idxd = bw.idxd, &infod = bw.infod, &part = bw.part, &coef = bw.coef,
-       &cnt = bw.cnt, &scl = bw.scl, &Uq = bw.Uq, &sq = bw.sq;
+       &Bls = bw.Bls, &ones = bw.ones, &idxd = bw.idxd, &part = bw.part, &coef = bw.coef, &cnt = bw.cnt,
+       &scl = bw.scl, &Uq = bw.Uq, &sq = bw.sq;
   DIE_TRY(Rs.alloc(dbytes));
   if (reg) DIE_TRY(Sd.alloc(dbytes));
   DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
@@ -1466,20 +1195,24 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   DIE_TRY(Bls.alloc((size_t)ldh * pw * sizeof(double2)));
   DIE_TRY(ones.alloc(sizeof(double)));
   DIE_TRY(idxd.alloc(pw * sizeof(int)));
-  DIE_TRY(infod.alloc(sizeof(int)));
   DIE_TRY(scl.alloc(pw * sizeof(double)));
-  // binary16 planar GEMMs (complex64 only): the basis shadow Qs (block j planar, n x 2p), W planar
-  // in FP32 and binary16, the chunk products of the projection and the real update matrix Hb
+  // the planar Gram-Schmidt: binary16 shadows with block = 2 (complex64 only), else the basis
+  // precision
   const bool hgemm = std::is_same<T, float>::value && o.block == 2;
-  DBuf &Qs = bw.Qs, &Wsb = bw.Wsb, &Whb = bw.Whb, &Cpart = bw.Cpart, &Hbh = bw.Hbh;
-  if (hgemm) {
-    if (n % 2) return fail(DIE_E_INVALID, "block = 2 needs an even vector length");
-    DIE_TRY(Qs.alloc((size_t)(m + 1) * 2 * pw * n * sizeof(_Float16)));
-    DIE_TRY(Wsb.alloc((size_t)2 * pw * n * sizeof(float)));
-    DIE_TRY(Whb.alloc((size_t)2 * pw * n * sizeof(_Float16)));
-    DIE_TRY(Cpart.alloc(kHalfProjPartial * sizeof(float)));
-    DIE_TRY(Hbh.alloc((size_t)2 * m * pw * 2 * pw * sizeof(_Float16)));
+  const size_t nrow = die::gemm_pad(n), ccap = die::gemm_pad((size_t)2 * (m + 1) * pw);
+  if constexpr (std::is_same<T, float>::value) {
+    if (hgemm)
+      DIE_TRY((planar_alloc<T, _Float16>(bw, nrow, ccap, pw)));
+    else
+      DIE_TRY((planar_alloc<T, T>(bw, nrow, ccap, pw)));
+  } else {
+    DIE_TRY((planar_alloc<T, T>(bw, nrow, ccap, pw)));
   }
+  auto shadow = [&](const c2<T>* X, int p, int j) -> int {
+    if constexpr (std::is_same<T, float>::value)
+      if (hgemm) return planar_shadow<T, _Float16>(bw, X, n, p, j, nrow, ccap, st);
+    return planar_shadow<T, T>(bw, X, n, p, j, nrow, ccap, st);
+  };
   DIE_TRY(Uq.alloc((size_t)die::kPanelMaxRows * die::kPanelMaxCols * sizeof(double2)));  // panel reflectors
   DIE_TRY(sq.alloc(die::kPanelMaxCols * sizeof(double)));
   // three page-locked slots for the per-step uploads (R1^-1, R2^-1, H(j+1, j)); each step's Gram
@@ -1503,7 +1236,6 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   }
   DIE_TRY(ensure_work(c, std::max(work_bytes(c, nrhs, sizeof(double2)), work_bytes(c, pw, sizeof(c2<T>))), st));
   c2<T>* vb = Vb.as<c2<T>>();
-  LongGemm &lg64 = bw.lg64, &lgT = bw.lgT;  // scratch of the long inner-dimension products
   std::vector<c2<T>> stage;
   std::vector<double> bnorm(nrhs), rnorm(nrhs), snorm(nrhs), hn(nrhs), relres(nrhs, 1.0);
   std::vector<int> act(nrhs, 1), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0), cycles(nrhs, 0), conv(nrhs, 0),
@@ -1629,12 +1361,19 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       }
     }
     bool progress = false;  // some object took a block step this cycle
+    // the work units of this cycle: per object, its active right-hand sides in groups of at most pw
+    std::vector<std::pair<int, std::vector<int>>> groups;
     for (int ob = 0; ob < c->nobj; ++ob) {
-      std::vector<int> K;
+      std::vector<int> Kall;
       for (int r = ob * rpo; r < (ob + 1) * rpo; ++r)
-        if (act[r] && snorm[r] > 0 && std::isfinite(snorm[r])) K.push_back(r);
+        if (act[r] && snorm[r] > 0 && std::isfinite(snorm[r])) Kall.push_back(r);
+      for (size_t g0 = 0; g0 < Kall.size(); g0 += (size_t)pw)
+        groups.emplace_back(ob, std::vector<int>(Kall.begin() + g0, Kall.begin() + std::min(Kall.size(), g0 + pw)));
+    }
+    for (const auto& grp : groups) {
+      const int ob = grp.first;
+      const std::vector<int>& K = grp.second;
       const int k = (int)K.size();
-      if (k == 0) continue;
       // ---- first block: normalised residuals, rank-revealing Cholesky QR (two passes, FP64)
       double2* ra = Ra.as<double2>();
       double2* v0 = ra + (size_t)pw * n;
@@ -1657,9 +1396,9 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
                                    n * sizeof(double2), hipMemcpyDeviceToDevice, st));
             ++kt;
           }
-      DIE_TRY(gemm_hn_long<double>(bh, lg64, kt, kt, ni, ra, ni, ra, ni, sm.as<double2>(), st));
       Mat G, L;
-      DIE_TRY(download<double>(sm.p, kt, kt, G, st));
+      double* p64 = bw.P64.as<double>();
+      DIE_TRY(gram_complex<double>(bw, ra, n, nrow, kt, p64, G, st));
       std::vector<double> dz(kt, 1.0);  // the correction columns enter with unit norm
       for (int i = k; i < kt; ++i) {
         const double g = G(i, i).real();
@@ -1683,13 +1422,12 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
           for (int q = 0; q < p; ++q) S0(q, perm[i]) = std::conj(L(i, q));
       std::vector<double2> stage64;
       DIE_TRY(upload<double>(Msel, sm.p, st, stage64));
-      DIE_BLAS(gemm<double>(bh, kN, kN, ni, p, kt, 1.0, ra, ni, sm.as<double2>(), kt, 0.0, v0, ni));
-      DIE_TRY(gemm_hn_long<double>(bh, lg64, p, p, ni, v0, ni, v0, ni, sm.as<double2>(), st));
+      DIE_HIP(die::launch_cplx_rmul<double>(ra, n, kt, sm.as<double2>(), kt, p, n, v0, n, st));
       Mat G2, R2;
-      DIE_TRY(download<double>(sm.p, p, p, G2, st));
+      DIE_TRY(gram_complex<double>(bw, v0, n, nrow, p, p64, G2, st));
       if (!la::chol_upper_scaled(G2, 1e-14, R2)) continue;  // not expected after the pivoted selection
       DIE_TRY(upload<double>(la::upper_inverse(R2), sm.p, st, stage64));
-      DIE_BLAS(gemm<double>(bh, kN, kN, ni, p, p, 1.0, v0, ni, sm.as<double2>(), p, 0.0, ra, ni));
+      DIE_HIP(die::launch_cplx_rmul<double>(v0, n, p, sm.as<double2>(), p, p, n, ra, n, st));
       {
         Mat S(p, k);
         for (int j = 0; j < k; ++j)
@@ -1701,9 +1439,9 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         S0 = S;
       }
       DIE_HIP((die::launch_scale<double, T>(ra, n, vb, n, ones.as<double>(), 0, n, p, nullptr, st)));
-      if (hgemm) DIE_TRY(half_shadow<T>(vb, n, p, Qs.as<_Float16>(), st));
+      DIE_TRY(shadow(vb, p, 0));
       // ---- block Arnoldi: H ((m+1) p x m p, on the device in the basis precision, leading
-      // dimension ldhp), CGS2 as GEMMs, CholQR2 of every new block
+      // dimension ldhp), CGS2 on the matrix cores, CholQR2 of every new block
       const int ldhp = (m + 1) * p;
       c2<T>* Hd = Ht.as<c2<T>>();
       DIE_HIP(hipMemsetAsync(Hd, 0, (size_t)ldhp * m * p * sizeof(c2<T>), st));
@@ -1722,29 +1460,29 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_TRY(apply_M<T>(c, reg, z, reg ? Tm.as<c2<T>>() : nullptr, W, p, nullptr, st, 0, ob));
         const int nq = (j + 1) * p;
         c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the projections (nq x p each)
-        if (hgemm)
-          DIE_TRY(half_block_cgs<T>(c, Qs.as<_Float16>(), W, Wt.as<c2<T>>(), n, nq, p, npass, Wsb.as<float>(),
-                                    Whb.as<_Float16>(), Cpart.as<float>(), hc, Hbh.as<_Float16>(), st));
-        for (int rep = 0; rep < npass && !hgemm; ++rep) {
-          DIE_TRY(gemm_hn_long<T>(bh, lgT, nq, p, ni, vb, ni, W, ni, hc[rep], st));
-          // flops 8 n p nq; operands: Q (n x nq) read, W (n x p) read and written, H (nq x p) read
-          ProfScope prof(c, DIE_PROF_GEMM, st, 8.0 * (double)n * p * nq,
-                         (double)sizeof(c2<T>) * ((double)n * (nq + 2.0 * p) + (double)nq * p));
-          DIE_TRY(gemm_update_long<T>(bh, ni, p, nq, vb, ni, hc[rep], nq, W, ni));
+        if constexpr (std::is_same<T, float>::value) {
+          if (hgemm)
+            DIE_TRY((planar_block_cgs<T, _Float16>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st)));
+          else
+            DIE_TRY((planar_block_cgs<T, T>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st)));
+        } else {
+          DIE_TRY((planar_block_cgs<T, T>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st)));
         }
         // column block j of H: the sum of the projections
         if (npass == 2)
-          DIE_BLAS(geam_add<T>(bh, nq, p, hc[0], nq, hc[1], nq, Hd + (size_t)j * p * ldhp, ldhp));
+          DIE_HIP(die::launch_cadd2<T>(hc[0], nq, hc[1], nq, nq, p, Hd + (size_t)j * p * ldhp, ldhp, st));
         else
           DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp, ldhp * sizeof(c2<T>), hc[0], nq * sizeof(c2<T>),
                                    nq * sizeof(c2<T>), p, hipMemcpyDeviceToDevice, st));
-        // CholQR of the orthogonalised block, which the binary16 passes leave in Wt and the complex
-        // ones in W: each factor application writes the other buffer, and the result ends in W
-        c2<T>* wa = hgemm ? Wt.as<c2<T>>() : W;
-        c2<T>* wb = hgemm ? W : Wt.as<c2<T>>();
+        // CholQR of the orthogonalised block (planar in Wacc): the first Gram from the planar
+        // copy, then W back to complex; each factor application writes the other buffer, and
+        // the result ends in W
+        c2<T>* wa = W;
+        c2<T>* wb = Wt.as<c2<T>>();
+        T* ws = bw.Wacc.as<T>();
         Mat Gw, Q1, Q2;
-        DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, wa, ni, wa, ni, sm.as<c2<T>>(), st));
-        DIE_TRY(download<T>(sm.p, p, p, Gw, st));
+        DIE_TRY(gram_planar<T>(bw, ws, nrow, p, Gw, st));
+        DIE_HIP((die::launch_tsq_merge<T, T>(ws, nrow, n, p, W, n, st)));
         double piv1 = 0.0;
         bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1, &piv1);
         // a well-conditioned block (smallest scaled pivot >= kCholQRSinglePivot, condition <= ~4.5)
@@ -1752,10 +1490,9 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         const bool single = ok && piv1 >= kCholQRSinglePivot;
         if (ok) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q1), sm.p, slot[0], st));
-          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, wa, ni, sm.as<c2<T>>(), p, 0.0, wb, ni));
+          DIE_HIP(die::launch_cplx_rmul<T>(wa, n, p, sm.as<c2<T>>(), p, p, n, wb, n, st));
           if (!single) {
-            DIE_TRY(gemm_hn_long<T>(bh, lgT, p, p, ni, wb, ni, wb, ni, sm.as<c2<T>>(), st));
-            DIE_TRY(download<T>(sm.p, p, p, Gw, st));
+            DIE_TRY(gram_complex<T>(bw, wb, n, nrow, p, ws, Gw, st));
             ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
           }
         }
@@ -1767,12 +1504,12 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         c2<T>* wres = wb;
         if (!single) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
-          DIE_TRY(gemm_rows_long<T>(bh, ni, p, p, 1.0, wb, ni, sm.as<c2<T>>(), p, 0.0, wa, ni));
+          DIE_HIP(die::launch_cplx_rmul<T>(wb, n, p, sm.as<c2<T>>(), p, p, n, wa, n, st));
           wres = wa;
         }
         if (wres != W)
           DIE_HIP(hipMemcpyAsync(W, wres, (size_t)p * n * sizeof(c2<T>), hipMemcpyDeviceToDevice, st));
-        if (hgemm) DIE_TRY(half_shadow<T>(W, n, p, Qs.as<_Float16>() + (size_t)(j + 1) * 2 * p * n, st));
+        DIE_TRY(shadow(W, p, j + 1));
         const Mat Hs = single ? Q1 : la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1 (Q2 = I: one pass)
         // into H's block (j+1, j) straight from the page-locked slot
         for (size_t e = 0; e < Hs.a.size(); ++e) slot[2][e] = die::mk<T>((T)Hs.a[e].real(), (T)Hs.a[e].imag());
@@ -1789,27 +1526,17 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_HIP((die::launch_scale<T, double>(Hd, ldhp, Hls.as<double2>(), mr, ones.as<double>(), 0, mr, nc, nullptr,
                                               st)));
         DIE_TRY(upload<double>(Bm, Bls.p, st, stage64));
-        int linfo = 0;
-        if (p <= die::kPanelMaxCols) {
-          // Householder QR panel by panel (H has at most p sub-diagonals), then R Y = Q^H B
-          DIE_HIP(die::launch_block_hessenberg_qr(Hls.as<double2>(), mr, mr, nc, p, Bls.as<double2>(), mr, k,
-                                                  Uq.as<double2>(), sq.as<double>(), st));
-          const rocblas_double_complex one(1.0, 0.0);
-          DIE_BLAS(rocblas_ztrsm(bh, rocblas_side_left, rocblas_fill_upper, kN, rocblas_diagonal_non_unit, nc, k, &one,
-                                 reinterpret_cast<const rocblas_double_complex*>(Hls.p), mr,
-                                 reinterpret_cast<rocblas_double_complex*>(Bls.p), mr));
-        } else {
-          DIE_BLAS(rocsolver_zgels(bh, kN, mr, nc, k, reinterpret_cast<rocblas_double_complex*>(Hls.p), mr,
-                                   reinterpret_cast<rocblas_double_complex*>(Bls.p), mr, infod.as<int>()));
-          DIE_HIP(hipMemcpyAsync(&linfo, infod.p, sizeof(int), hipMemcpyDeviceToHost, st));
-        }
+        // Householder QR panel by panel (H has at most p sub-diagonals), then R Y = Q^H B
+        DIE_HIP(die::launch_block_hessenberg_qr(Hls.as<double2>(), mr, mr, nc, p, Bls.as<double2>(), mr, k,
+                                                Uq.as<double2>(), sq.as<double>(), st));
+        DIE_HIP(die::launch_trsm_upper(Hls.as<double2>(), mr, nc, Bls.as<double2>(), mr, k, st));
         Mat Y;
         DIE_TRY(download<double>(Bls.p, mr, k, Y, st));
         bool finite = true;
         for (int j = 0; j < k && finite; ++j)
           for (int i = 0; i < nc; ++i)
             if (!std::isfinite(Y(i, j).real()) || !std::isfinite(Y(i, j).imag())) finite = false;
-        if (linfo != 0 || !finite) {
+        if (!finite) {
           for (int q = 0; q < k; ++q) brk[K[q]] = 1;
           fill_info();
           return fail(DIE_E_BREAKDOWN, "block GMRES: rank-deficient block Hessenberg");
@@ -1820,7 +1547,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_TRY(upload<T>(Ys, sm.p, st, stage));
       }
       c2<T>* tb = Tb.as<c2<T>>();
-      DIE_TRY(gemm_rows_long<T>(bh, ni, k, nc, 1.0, vb, ni, sm.as<c2<T>>(), nc, 0.0, tb, ni));
+      DIE_HIP(die::launch_cplx_rmul<T>(vb, n, nc, sm.as<c2<T>>(), nc, k, n, tb, n, st));
       // keep each right-hand side's correction V Y (before the projector) for a later narrowed block
       for (int q = 0; q < k; ++q) {
         DIE_HIP((die::launch_scale<T, double>(tb + (size_t)q * n, n, bw.Zall.as<double2>() + (size_t)K[q] * n, n,

@@ -198,83 +198,6 @@ k_panel_apply(double2* __restrict__ H, int ld, double2* __restrict__ B, int ldb,
   }
 }
 
-// ---- binary16 planar GEMM path of the block Arnoldi step.  A complex block X (n x p,
-// interleaved) is held planar as n x 2p real columns: the p real parts, then the p imaginary
-// parts.  In that layout the block projection Q^H W and the update W -= Q H are each one real
-// GEMM with the same flop count as the complex one (see launch_planar_combine).
-
-// One thread per pair of consecutive rows of one column: X (interleaved, leading dimension ldx)
-// to Xs (FP32 planar, leading dimension ldo) and/or Xh (binary16 planar); n even.
-__global__ void k_planar_split(const float2* __restrict__ X, size_t ldx, size_t n2, int p, float* __restrict__ Xs,
-                               _Float16* __restrict__ Xh, size_t ldo) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n2 * (size_t)p) return;
-  const size_t col = e / n2, r = 2 * (e - col * n2);
-  const float4 v = *reinterpret_cast<const float4*>(X + col * ldx + r);
-  const size_t ore = col * ldo + r, oim = (p + col) * ldo + r;
-  if (Xs) {
-    *reinterpret_cast<float2*>(Xs + ore) = make_float2(v.x, v.z);
-    *reinterpret_cast<float2*>(Xs + oim) = make_float2(v.y, v.w);
-  }
-  if (Xh) {
-    Xh[ore] = (_Float16)v.x;
-    Xh[ore + 1] = (_Float16)v.z;
-    Xh[oim] = (_Float16)v.y;
-    Xh[oim + 1] = (_Float16)v.w;
-  }
-}
-
-// The inverse of the FP32 split: Xs (planar, leading dimension lds) to X (interleaved).
-__global__ void k_planar_merge(const float* __restrict__ Xs, size_t lds, size_t n2, int p, float2* __restrict__ X,
-                               size_t ldx) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n2 * (size_t)p) return;
-  const size_t col = e / n2, r = 2 * (e - col * n2);
-  const float2 re = *reinterpret_cast<const float2*>(Xs + col * lds + r);
-  const float2 im = *reinterpret_cast<const float2*>(Xs + (p + col) * lds + r);
-  *reinterpret_cast<float4*>(X + col * ldx + r) = make_float4(re.x, im.x, re.y, im.y);
-}
-
-// Binary16 copy of a planar FP32 block (n x 2p, both leading dimensions ld), two values a thread.
-__global__ void k_planar_to_half(const float* __restrict__ Xs, size_t ld, size_t n2, int p2, _Float16* __restrict__ Xh) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n2 * (size_t)p2) return;
-  const size_t col = e / n2, r = 2 * (e - col * n2);
-  const float2 v = *reinterpret_cast<const float2*>(Xs + col * ld + r);
-  Xh[col * ld + r] = (_Float16)v.x;
-  Xh[col * ld + r + 1] = (_Float16)v.y;
-}
-
-// One thread per entry (q, k) of the complex projection H = Q^H W (nq x p): sums the nch chunk
-// products C_b = Qs^T Ws (2nq x 2p each, leading dimension 2nq) in chunk order, then
-//   Re H = Qr^T Wr + Qi^T Wi,  Im H = Qr^T Wi - Qi^T Wr,
-// rounds H to binary16 and writes it twice: H (complex FP32 of the rounded values) and the real
-// update matrix Hb (2nq x 2p binary16) with which Ws -= Qs Hb is W -= Q H:
-//   Hb[re row, k] = Re H, Hb[re row, p + k] = Im H, Hb[im row, k] = -Im H, Hb[im row, p + k] = Re H.
-// Row q = j p + c of Q (block j, column c) is real row 2 p j + c and imaginary row 2 p j + p + c of Qs.
-__global__ void k_planar_combine(const float* __restrict__ C, int nch, size_t cstride, int nq, int p,
-                                 float2* __restrict__ H, _Float16* __restrict__ Hb) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nq * p) return;
-  const int k = e / nq, q = e - k * nq;
-  const int j = q / p, cc = q - j * p;
-  const int M = 2 * nq, rre = 2 * p * j + cc, rim = rre + p;
-  double rr = 0.0, ii = 0.0, ri = 0.0, ir = 0.0;
-  for (int b = 0; b < nch; ++b) {
-    const float* Cb = C + (size_t)b * cstride;
-    rr += Cb[(size_t)k * M + rre];
-    ii += Cb[(size_t)(p + k) * M + rim];
-    ri += Cb[(size_t)(p + k) * M + rre];
-    ir += Cb[(size_t)k * M + rim];
-  }
-  const _Float16 hr = (_Float16)(rr + ii), hi = (_Float16)(ri - ir);
-  H[(size_t)k * nq + q] = make_float2((float)hr, (float)hi);
-  Hb[(size_t)k * M + rre] = hr;
-  Hb[(size_t)(p + k) * M + rre] = hi;
-  Hb[(size_t)k * M + rim] = -hi;
-  Hb[(size_t)(p + k) * M + rim] = hr;
-}
-
 }  // namespace
 
 hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p, double2* B, int ldb, int k,
@@ -289,40 +212,6 @@ hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p,
       hipLaunchKernelGGL(k_panel_apply, dim3((ncols + 15) / 16), dim3(256), 0, st, H, ld, B, ldb, k, c0, rows, p, cb,
                          nc, U, s);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_planar_split(const float2* X, size_t ldx, size_t n, int p, float* Xs, _Float16* Xh, size_t ldo,
-                               hipStream_t st) {
-  if (n % 2 || p < 1 || ldx < n || ldo < n) return hipErrorInvalidValue;
-  const size_t tot = n / 2 * (size_t)p;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_planar_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X, ldx, n / 2, p, Xs, Xh,
-                     ldo);
-  return hipGetLastError();
-}
-
-hipError_t launch_planar_merge(const float* Xs, size_t lds, size_t n, int p, float2* X, size_t ldx, hipStream_t st) {
-  if (n % 2 || p < 1 || ldx < n || lds < n) return hipErrorInvalidValue;
-  const size_t tot = n / 2 * (size_t)p;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_planar_merge, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Xs, lds, n / 2, p, X, ldx);
-  return hipGetLastError();
-}
-
-hipError_t launch_planar_to_half(const float* Xs, size_t ld, size_t n, int p, _Float16* Xh, hipStream_t st) {
-  if (n % 2 || p < 1 || ld < n || ld % 2) return hipErrorInvalidValue;
-  const size_t tot = n / 2 * (size_t)(2 * p);
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_planar_to_half, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Xs, ld, n / 2, 2 * p, Xh);
-  return hipGetLastError();
-}
-
-hipError_t launch_planar_combine(const float* C, int nch, int nq, int p, float2* H, _Float16* Hb, hipStream_t st) {
-  if (nch < 1 || p < 1 || nq < p || nq % p) return hipErrorInvalidValue;
-  const int tot = nq * p;
-  hipLaunchKernelGGL(k_planar_combine, dim3((tot + 255) / 256), dim3(256), 0, st, C, nch, (size_t)2 * nq * 2 * p, nq,
-                     p, H, Hb);
   return hipGetLastError();
 }
 

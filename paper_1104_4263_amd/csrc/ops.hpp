@@ -127,21 +127,79 @@ constexpr int kPanelMaxRows = 2 * kPanelMaxCols;
 hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p, double2* B, int ldb, int k,
                                       double2* U, double* s, hipStream_t st);
 
-// Planar binary16 GEMM path of the block Arnoldi step (complex64 blocks, n even).
-// launch_planar_split: X (n x p complex, leading dimension ldx) to Xs (n x 2p FP32: real parts,
-// then imaginary parts; leading dimension ldo) and/or Xh (the same in binary16); either may be null.
-hipError_t launch_planar_split(const float2* X, size_t ldx, size_t n, int p, float* Xs, _Float16* Xh, size_t ldo,
-                               hipStream_t st);
-// launch_planar_merge: Xs (planar FP32, leading dimension lds) back to X (interleaved).
-hipError_t launch_planar_merge(const float* Xs, size_t lds, size_t n, int p, float2* X, size_t ldx, hipStream_t st);
-// launch_planar_to_half: the binary16 copy of a planar FP32 block (n x 2p, leading dimension ld;
-// n and ld even).
-hipError_t launch_planar_to_half(const float* Xs, size_t ld, size_t n, int p, _Float16* Xh, hipStream_t st);
-// launch_planar_combine: H (nq x p complex, leading dimension nq) = Q^H W from nch chunk products
-// C_b = Qs^T Ws (2nq x 2p FP32, leading dimension 2nq, stride 4 nq p), summed in chunk order and
-// rounded to binary16; Hb (2nq x 2p binary16, leading dimension 2nq) the real matrix with
-// Ws -= Qs Hb equal to W -= Q H.  Qs holds each p-column block of Q planar.
-hipError_t launch_planar_combine(const float* C, int nch, int nq, int p, float2* H, _Float16* Hb, hipStream_t st);
+// Block Gram-Schmidt products on the matrix cores (kernels_gemm.hip).  Element types E:
+// binary16, FP32, FP64; R rows per MFMA tile, KV values per 16-byte lane load, KS = (64 / R) KV
+// reduction values per tile, Acc the accumulation type.  Tiled layouts of an nrow-row matrix
+// (nrow and the column capacity ccap multiples of 32; a T1 buffer holds the columns rounded up
+// to a multiple of 32, a T2 buffer ccap):
+//   T1 (the projection's operands): element (n, c) at t1(n, c, nrow);
+//   T2 (the update's basis operand): element (n, c) at t2(n, c, ccap).
+template <class E> struct GemmTileBase;
+template <> struct GemmTileBase<_Float16> { static constexpr int R = 32, KV = 8; using Acc = float; };
+template <> struct GemmTileBase<float> { static constexpr int R = 32, KV = 4; using Acc = float; };
+template <> struct GemmTileBase<double> { static constexpr int R = 16, KV = 2; using Acc = double; };
+template <class E> struct GemmTile : GemmTileBase<E> {
+  using Base = GemmTileBase<E>;
+  static constexpr int R = Base::R, KV = Base::KV, KS = (64 / Base::R) * Base::KV, TILE = 64 * Base::KV;
+  __host__ __device__ static constexpr size_t t1(size_t n, size_t c, size_t nrow) {
+    return ((c / R) * (nrow / KS) + n / KS) * TILE + ((c % R) + R * ((n % KS) / KV)) * KV + n % KV;
+  }
+  __host__ __device__ static constexpr size_t t2(size_t n, size_t c, size_t ccap) {
+    return ((n / R) * (ccap / KS) + c / KS) * TILE + ((n % R) + R * ((c % KS) / KV)) * KV + c % KV;
+  }
+};
+__host__ __device__ constexpr size_t gemm_pad(size_t x) { return (x + 31) / 32 * 32; }
+
+// Columns [c0, c0 + 2p) of the planar form of X (n x p complex, leading dimension ldx; rows n ..
+// nrow - 1 zero): into Ws (planar, leading dimension ldw), A1 (T1) and A2 (T2, capacity ccap);
+// any of the three may be null (Ws takes the columns 0 .. 2p - 1).
+template <class T, class A, class E>
+hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0, size_t nrow, size_t ccap, A* Ws,
+                            size_t ldw, E* A1, E* A2, hipStream_t st);
+// B1 (T1, columns 0 .. nb - 1) from the planar Ws (nrow rows, leading dimension ldw).
+template <class A, class E>
+hipError_t launch_tsq_to_t1(const A* Ws, size_t ldw, size_t nrow, int nb, E* B1, hipStream_t st);
+// X (n x p complex) from the planar Ws.
+template <class A, class T>
+hipError_t launch_tsq_merge(const A* Ws, size_t ldw, size_t n, int p, c2<T>* X, size_t ldx, hipStream_t st);
+// part[h][b ma + a] = sum over the rows of chunk h of A(n, a) B(n, b) (A: ma columns, B: nb <= 128
+// columns, both T1 with nrow rows); the chunk count (at most part_cap / (ma nb)) goes to *nch.
+template <class E>
+hipError_t launch_tsq_proj(const E* A1, int ma, const E* B1, int nb, size_t nrow, typename GemmTile<E>::Acc* part,
+                           size_t part_cap, int* nch, hipStream_t st);
+// H (nq x p complex, leading dimension nq) = Q^H W from the nch chunk products of the planar
+// projection (2nq x 2p each), summed in chunk order (more than 16 in two stages through scratch,
+// at most scratch_cap doubles), rounded to E; Hb (2nq x 2p in E, leading dimension ldhb) the
+// real matrix with which Ws -= Qs Hb is W -= Q H.
+constexpr size_t kTsqScratch = (size_t)1 << 22;  // doubles of the two-stage sums that always suffice
+template <class A, class E, class T>
+hipError_t launch_tsq_combine(const A* part, int nch, int nq, int p, c2<T>* H, E* Hb, int ldhb, double* scratch,
+                              size_t scratch_cap, hipStream_t st);
+// Ws (nrow rows, nb <= 128 columns, leading dimension ldw) -= Q Hb over the mc columns of Q
+// (T2, capacity ccap) and rows of Hb (leading dimension ldhb, a multiple of KV).
+template <class E>
+hipError_t launch_tsq_update(const E* A2, int mc, size_t ccap, size_t nrow, const E* Hb, int ldhb, int nb,
+                             typename GemmTile<E>::Acc* Ws, size_t ldw, hipStream_t st);
+// G (p x p, leading dimension p, FP64) = X^H X for the complex block X held planar in Xs (n x 2p,
+// rows contiguous, leading dimension nrow, rows past the data zero; the buffer holds 2p rounded
+// up to 32 columns), p <= 64: on the matrix cores in A (FP32 or FP64) with the chunk products in
+// part (at most part_cap values), summed in FP64 (through scratch as for launch_tsq_combine).
+template <class A>
+hipError_t launch_gram_planar(const A* Xs, size_t nrow, int p, A* part, size_t part_cap, double* scratch,
+                              size_t scratch_cap, double2* G, hipStream_t st);
+// Y (n x q) = X (n x s) S (s x q, leading dimension lds), complex in T on the matrix cores, q <= 64;
+// X and Y distinct.
+template <class T>
+hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
+                            size_t ldy, hipStream_t st);
+// R Y = B in place in B (nc x k, leading dimension ldb) for the upper triangular R (leading
+// dimension ldr), nc <= kTrsmMaxRows.
+constexpr int kTrsmMaxRows = 4096;
+hipError_t launch_trsm_upper(const double2* R, int ldr, int nc, double2* B, int ldb, int k, hipStream_t st);
+// C = A + B (rows x cols).
+template <class T>
+hipError_t launch_cadd2(const c2<T>* A, int lda, const c2<T>* B, int ldb, int rows, int cols, c2<T>* C, int ldc,
+                        hipStream_t st);
 
 // ----------------------------------------------------------------- GMRES state
 struct GmresState {
