@@ -94,39 +94,42 @@ template <> struct Mf1<double> {
 
 // ---- layout conversions
 
-// One thread per KV consecutive rows of one planar column c < 2p of the complex block X (rows
-// n .. nrow - 1 are zero): the planar copy Ws (accumulation type A, leading dimension ldw) and
-// column c0 + c of the T1 copy A1; either may be null.
-template <class T, class A, class E>
-__global__ void k_split(const c2<T>* __restrict__ X, size_t ldx, size_t n, int p, int c0, size_t nrow,
-                        A* __restrict__ Ws, size_t ldw, E* __restrict__ A1) {
-  constexpr int KV = GemmTile<E>::KV;
-  const size_t chunks = nrow / KV;
+// The planar copy Ws (accumulation type A, leading dimension ldw, rows n .. nrow - 1 zero) of the
+// complex block X (n x p): one thread per row and column, the two parts to columns q and p + q.
+template <class T, class A>
+__global__ void k_split_planar(const c2<T>* __restrict__ X, size_t ldx, size_t n, int p, size_t nrow,
+                               A* __restrict__ Ws, size_t ldw) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= chunks * 2 * (size_t)p) return;
-  const int c = (int)(e / chunks);
-  const size_t n0 = (e - (size_t)c * chunks) * KV;
+  if (e >= nrow * (size_t)p) return;
+  const size_t q = e / nrow, r = e - q * nrow;
+  c2<T> z = mk<T>((T)0, (T)0);
+  if (r < n) z = X[q * ldx + r];
+  Ws[q * ldw + r] = (A)z.x;
+  Ws[(p + q) * ldw + r] = (A)z.y;
+}
+
+// Columns [c0, c0 + 2p) of the T1 copy A1 (nrow rows, rows past n zero) of the planar X: one
+// thread per planar column and group of KV rows, consecutive threads on consecutive columns (so
+// that the 16-byte writes of a tile are contiguous).
+template <class T, class E>
+__global__ void k_split_t1(const c2<T>* __restrict__ X, size_t ldx, size_t n, int p, int c0, size_t nrow,
+                           E* __restrict__ A1) {
+  using V = typename Mf<E>::V;
+  constexpr int KV = GemmTile<E>::KV;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nrow / KV * 2 * (size_t)p) return;
+  const int c = (int)(e % (2 * (size_t)p));
+  const size_t n0 = e / (2 * (size_t)p) * KV;
   const bool im = c >= p;
   const c2<T>* xc = X + (size_t)(im ? c - p : c) * ldx;
-  T v[KV];
+  V v{};
 #pragma unroll
-  for (int i = 0; i < KV; ++i) {
-    const size_t r = n0 + i;
-    v[i] = (T)0;
-    if (r < n) {
-      const c2<T> z = xc[r];
-      v[i] = im ? z.y : z.x;
+  for (int i = 0; i < KV; ++i)
+    if (n0 + i < n) {
+      const c2<T> z = xc[n0 + i];
+      v[i] = (E)(im ? z.y : z.x);
     }
-  }
-  if (Ws) {
-#pragma unroll
-    for (int i = 0; i < KV; ++i) Ws[(size_t)c * ldw + n0 + i] = (A)v[i];
-  }
-  if (A1) {
-    E* d = A1 + GemmTile<E>::t1(n0, (size_t)(c0 + c), nrow);
-#pragma unroll
-    for (int i = 0; i < KV; ++i) d[i] = (E)v[i];
-  }
+  *reinterpret_cast<V*>(A1 + GemmTile<E>::t1(n0, (size_t)(c0 + c), nrow)) = v;
 }
 
 // Columns [c0, c0 + 2p) of the T2 copy A2 (capacity ccap) of the planar X: one thread per row
@@ -565,35 +568,46 @@ k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restr
 }
 
 // ---- R Y = B for the upper triangular R (nc x nc, leading dimension ldr), in place in B
-// (nc x k, leading dimension ldb): one block per column of B, the column in LDS.  Blocks of 32
-// rows from the bottom: the block's 32 x 32 triangle is staged in LDS, the first wave solves it
-// (lane t holds row t, the solved value moves by a lane broadcast), then every thread
-// subtracts the block's contribution from its rows above it.  Three barriers per block of rows.
-__global__ void __launch_bounds__(256)
-k_trsm_upper(const double2* __restrict__ R, int ldr, int nc, double2* __restrict__ B, int ldb) {
-  extern __shared__ double2 bsh[];
-  __shared__ double2 ysh[32];
-  __shared__ double2 dsh[32][33];  // the diagonal block, [column][row]
-  double2* bc = B + (size_t)blockIdx.x * ldb;
-  for (int i = threadIdx.x; i < nc; i += 256) bsh[i] = bc[i];
-  __syncthreads();
-  for (int ie = nc; ie > 0; ie -= 32) {
-    const int ib = ie > 32 ? ie - 32 : 0, nb = ie - ib;
-    for (int e = threadIdx.x; e < nb * nb; e += 256) {
+// (nc x k, leading dimension ldb): one block of 1024 threads per KC columns of B, the columns
+// in LDS.  Blocks of 64 rows from the bottom: the block's 64 x 64 triangle is staged in LDS
+// with the reciprocals of its diagonal, wave c solves it for column c (lane t holds row t, the
+// solved value moves by a lane broadcast), then every thread subtracts the block's contribution
+// from its rows above it for all KC columns (one read of R serves KC columns).  Three barriers
+// per block of rows.
+template <int KC>
+__global__ void __launch_bounds__(1024)
+k_trsm_upper(const double2* __restrict__ R, int ldr, int nc, double2* __restrict__ B, int ldb, int k) {
+  extern __shared__ double2 bsh[];  // [KC][nc]
+  __shared__ double2 ysh[KC][64];
+  __shared__ double2 dsh[64][65];  // the diagonal block, [column][row]
+  __shared__ double2 rinv[64];     // 1 / its diagonal
+  const int c0 = blockIdx.x * KC, kc = k - c0 < KC ? k - c0 : KC;
+  for (int e = threadIdx.x; e < kc * nc; e += 1024) {
+    const int j = e / nc, i = e - j * nc;
+    bsh[j * nc + i] = B[(size_t)(c0 + j) * ldb + i];
+  }
+  const int wave = threadIdx.x >> 6, t = threadIdx.x & 63;
+  for (int ie = nc; ie > 0; ie -= 64) {
+    const int ib = ie > 64 ? ie - 64 : 0, nb = ie - ib;
+    __syncthreads();  // the previous block's updates (and the initial loads) are done
+    for (int e = threadIdx.x; e < nb * nb; e += 1024) {
       const int jc = e / nb, ir = e - jc * nb;
-      dsh[jc][ir] = R[(size_t)(ib + jc) * ldr + ib + ir];
+      const double2 v = R[(size_t)(ib + jc) * ldr + ib + ir];
+      dsh[jc][ir] = v;
+      if (jc == ir) {
+        const double dd = v.x * v.x + v.y * v.y;
+        rinv[ir] = make_double2(v.x / dd, -v.y / dd);
+      }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-      const int t = threadIdx.x;
-      double2 bt = t < nb ? bsh[ib + t] : make_double2(0.0, 0.0);
+    if (wave < kc) {
+      double2 bt = t < nb ? bsh[wave * nc + ib + t] : make_double2(0.0, 0.0);
       double2 yt = make_double2(0.0, 0.0);
       for (int i = nb - 1; i >= 0; --i) {
         // lane i holds the final right-hand side of row ib + i
         const double br = __shfl(bt.x, i), bi = __shfl(bt.y, i);
-        const double2 d = dsh[i][i];
-        const double dd = d.x * d.x + d.y * d.y;
-        const double yr = (br * d.x + bi * d.y) / dd, yi = (bi * d.x - br * d.y) / dd;
+        const double2 d = rinv[i];
+        const double yr = br * d.x - bi * d.y, yi = br * d.y + bi * d.x;
         if (t == i) yt = make_double2(yr, yi);
         if (t < i) {
           const double2 rt = dsh[i][t];
@@ -602,22 +616,29 @@ k_trsm_upper(const double2* __restrict__ R, int ldr, int nc, double2* __restrict
         }
       }
       if (t < nb) {
-        ysh[t] = yt;
-        bc[ib + t] = yt;
+        ysh[wave][t] = yt;
+        B[(size_t)(c0 + wave) * ldb + ib + t] = yt;
       }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < ib; t += 256) {
-      double2 a = bsh[t];
-#pragma unroll 8
+    for (int row = threadIdx.x; row < ib; row += 1024) {
+      double2 a[KC];
+#pragma unroll
+      for (int j = 0; j < KC; ++j) a[j] = j < kc ? bsh[j * nc + row] : make_double2(0.0, 0.0);
+#pragma unroll 16
       for (int i = 0; i < nb; ++i) {
-        const double2 rt = R[(size_t)(ib + i) * ldr + t], y = ysh[i];
-        a.x -= rt.x * y.x - rt.y * y.y;
-        a.y -= rt.x * y.y + rt.y * y.x;
+        const double2 rt = R[(size_t)(ib + i) * ldr + row];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+          const double2 y = ysh[j][i];
+          a[j].x -= rt.x * y.x - rt.y * y.y;
+          a[j].y -= rt.x * y.y + rt.y * y.x;
+        }
       }
-      bsh[t] = a;
+#pragma unroll
+      for (int j = 0; j < KC; ++j)
+        if (j < kc) bsh[j * nc + row] = a[j];
     }
-    __syncthreads();
   }
 }
 
@@ -638,13 +659,20 @@ inline unsigned blocks_for(size_t work, unsigned per = 256) { return (unsigned)(
 template <class T, class A, class E>
 hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0, size_t nrow, size_t ccap, A* Ws,
                             size_t ldw, E* A1, E* A2, hipStream_t st) {
-  if (p < 1 || n > nrow || nrow % 32 || ccap % 32 || (Ws && ldw < nrow) || (A2 && (size_t)c0 + 2 * p > ccap))
+  if (p < 1 || n > nrow || nrow % 32 || ccap % 32 || (Ws && ldw < nrow) || (A2 && (size_t)c0 + 2 * p > ccap) ||
+      (Ws && A1 && c0 != 0))
     return hipErrorInvalidValue;
   constexpr int KV = GemmTile<E>::KV;
-  if (Ws || A1) {
-    const size_t work = nrow / KV * 2 * (size_t)p;
-    hipLaunchKernelGGL((k_split<T, A, E>), dim3(blocks_for(work)), dim3(256), 0, st, X, ldx, n, p, c0, nrow, Ws, ldw,
-                       A1);
+  if (Ws)
+    hipLaunchKernelGGL((k_split_planar<T, A>), dim3(blocks_for(nrow * (size_t)p)), dim3(256), 0, st, X, ldx, n, p,
+                       nrow, Ws, ldw);
+  if (A1) {
+    if (Ws)  // the T1 copy from the planar one (contiguous reads and writes)
+      hipLaunchKernelGGL((k_planar_to_t1<A, E>), dim3(blocks_for(nrow / KV * 2 * (size_t)p)), dim3(256), 0, st, Ws,
+                         ldw, nrow, 2 * p, A1);
+    else
+      hipLaunchKernelGGL((k_split_t1<T, E>), dim3(blocks_for(nrow / KV * 2 * (size_t)p)), dim3(256), 0, st, X, ldx, n,
+                         p, c0, nrow, A1);
   }
   if (A2) {
     const size_t groups = (size_t)((c0 + 2 * p + KV - 1) / KV - c0 / KV);
@@ -891,10 +919,29 @@ hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, i
   return hipGetLastError();
 }
 
+namespace {
+template <int KC>
+hipError_t trsm_kc(const double2* R, int ldr, int nc, double2* B, int ldb, int k, hipStream_t st) {
+  // the columns' rows in LDS: at most 64 KiB beside the kernel's own 68 KiB
+  static bool attr_set[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (!attr_set[dev]) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trsm_upper<KC>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    if (e != hipSuccess) return e;
+    attr_set[dev] = true;
+  }
+  hipLaunchKernelGGL((k_trsm_upper<KC>), dim3((unsigned)((k + KC - 1) / KC)), dim3(1024),
+                     (size_t)KC * nc * sizeof(double2), st, R, ldr, nc, B, ldb, k);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_trsm_upper(const double2* R, int ldr, int nc, double2* B, int ldb, int k, hipStream_t st) {
   if (nc < 1 || nc > kTrsmMaxRows || ldr < nc || ldb < nc || k < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trsm_upper, dim3(k), dim3(256), (size_t)nc * sizeof(double2), st, R, ldr, nc, B, ldb);
-  return hipGetLastError();
+  // two columns a block where their rows fit in 64 KiB of LDS, else one
+  return nc <= kTrsmMaxRows / 2 ? trsm_kc<2>(R, ldr, nc, B, ldb, k, st) : trsm_kc<1>(R, ldr, nc, B, ldb, k, st);
 }
 
 template <class T>

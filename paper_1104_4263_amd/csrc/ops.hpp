@@ -152,7 +152,7 @@ __host__ __device__ constexpr size_t gemm_pad(size_t x) { return (x + 31) / 32 *
 
 // Columns [c0, c0 + 2p) of the planar form of X (n x p complex, leading dimension ldx; rows n ..
 // nrow - 1 zero): into Ws (planar, leading dimension ldw), A1 (T1) and A2 (T2, capacity ccap);
-// any of the three may be null (Ws takes the columns 0 .. 2p - 1).
+// any of the three may be null (Ws takes the columns 0 .. 2p - 1; with Ws and A1 both given, c0 = 0).
 template <class T, class A, class E>
 hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0, size_t nrow, size_t ccap, A* Ws,
                             size_t ldw, E* A1, E* A2, hipStream_t st);
