@@ -126,8 +126,10 @@ typedef struct {
   int block;         /* 1: block GMRES(m): all right-hand sides of an object share one block
                         Krylov space (its first block spans their residuals, rank-revealed by a
                         pivoted Cholesky QR); CGS2 block orthogonalisation and CholQR2 of each
-                        new block on the matrix cores (complex GEMM in the basis precision), the
-                        block least squares once per cycle; every cycle restarts from the FP64
+                        new block on the matrix cores (real products of planar copies of the
+                        basis in the basis precision), the block least squares once per cycle
+                        on the GPU; an object's right-hand sides run in groups of at most 64;
+                        every cycle restarts from the FP64
                         true residual.  Needs mixed = 0 (FP64) or 1 (complex64 basis and
                         products).  orth = 0: two block Gram-Schmidt passes (CGS2); orth = 1:
                         one pass, the CholQR2 of the new block restoring its own
@@ -138,7 +140,7 @@ typedef struct {
                         planar shadow of the basis (real and imaginary parts as separate real
                         columns) and of W, FP32 accumulation and FP32 W, the projection
                         coefficients rounded to binary16 (and kept so in H); CholQR, products
-                        and least squares as for 1.  Needs an even vector length.
+                        and least squares as for 1.
                         With mixed = 1 (block 1 or 2), a right-hand side whose full complex64
                         cycle reduces its FP64 true residual by less than 10% leaves the
                         complex64 iteration, and the call finishes it with FP64 block cycles
@@ -148,6 +150,15 @@ typedef struct {
                         keeps its work buffers (and those corrections) in the context until
                         die_te_destroy.
                         0: per-rhs GMRES */
+  int method;        /* 0: restarted GMRES (everything above).  1: Bi-CGSTAB; 2: restarted GCR(m) with
+                        m = restart kept directions (the Conclusions of the paper name both as
+                        alternatives on the same preconditioned system): per right-hand side, in
+                        FP64 (needs block = mixed = 0; orth and graph do not apply), on
+                        M P^-1 v = A_R r exactly as GMRES; a right-hand side whose recurrence
+                        residual reaches the tolerance scaled to the solved system, breaks down or
+                        stagnates has its FP64 true residual checked and, if that is not below the
+                        tolerance, restarts from it.  iters counts applications of M (two per
+                        Bi-CGSTAB step); cycles counts true-residual checks */
 } die_te_solve_opts;
 
 typedef struct {
@@ -235,6 +246,21 @@ int die_te_solve(die_te_ctx *ctx, const void *e_in, void *e_tot, int nrhs,
 int die_te_solve_batch(die_te_ctx *const *ctx, int nctx, const void *const *e_in, void *const *e_tot,
                        const int *nrhs, const die_te_solve_opts *opts, die_te_solve_info *const *info,
                        void *stream);
+
+/* The dense matrix of one of the context's operators for object obj (the spectral analysis of
+ * Sections 4 and 5, Figs. 2 and 3): which = 0 A, 1 A_R, 2 A_R A, 3 the operator GMRES solves
+ * (M P^-1: M = A_R A when the context is regularized, else A; P^-1 the deflation preconditioner
+ * when it has one).  Column j is the operator applied to the unit vector e_j in FP64 (batches
+ * of identity columns through the FFT products).  out: device, complex128, nvec x nvec
+ * column-major (nvec = ncomp nx ny), owned by the caller.  Synchronises `stream`. */
+int die_te_operator_dense(die_te_ctx *ctx, int which, int obj, void *out, void *stream);
+
+/* All eigenvalues of that matrix (same which and obj), for nvec <= 4096 (DIE_E_INVALID above):
+ * the dense matrix is formed on the GPU as above and reduced on the host (Householder
+ * Hessenberg reduction and shifted QR, O(nvec^3)).  eig: host, nvec complex128 values (order of
+ * the Schur form's diagonal).  DIE_E_BREAKDOWN if the QR iteration does not converge.
+ * Synchronises `stream`. */
+int die_te_spectrum(die_te_ctx *ctx, int which, int obj, void *eig, void *stream);
 
 /* P^-1 x = x + V ((T^-1 - I) (V^* x)) for nrhs complex128 vectors of length 2 nx ny
  * (Section 4, eq. DeflatingPrecondtioner).  x, y: device; may alias.

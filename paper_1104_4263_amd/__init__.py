@@ -17,6 +17,8 @@ from .api import (  # noqa: F401
     die_te_solve,
     die_te_apply_deflation,
     die_te_deflation_info,
+    die_te_operator_dense,
+    die_te_spectrum,
     die_te_fft2,
     die_te_destroy,
     die_te_deflation_radius,

@@ -40,7 +40,7 @@ class DieTeSetupOpts(ctypes.Structure):
 class DieTeSolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("tol", ctypes.c_double),
                 ("mixed", ctypes.c_int), ("x0_given", ctypes.c_int), ("reg_margin", ctypes.c_double),
-                ("orth", ctypes.c_int), ("graph", ctypes.c_int), ("block", ctypes.c_int)]
+                ("orth", ctypes.c_int), ("graph", ctypes.c_int), ("block", ctypes.c_int), ("method", ctypes.c_int)]
 
 
 class DieTeSolveInfo(ctypes.Structure):
@@ -91,6 +91,8 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(DieTeSolveOpts),
                                        ctypes.POINTER(vp), vp]
     lib.die_te_apply_deflation.argtypes = [vp, vp, vp, i, vp]
+    lib.die_te_operator_dense.argtypes = [vp, i, i, vp, vp]
+    lib.die_te_spectrum.argtypes = [vp, i, i, vp, vp]
     lib.die_te_fft_plan.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_int), vp]
     lib.die_te_deflation_info.argtypes = [vp, ctypes.POINTER(ip), vp, vp, vp, vp]
     lib.die_te_fft2.argtypes = [vp, i, i, i, i, i, vp]

@@ -6,6 +6,7 @@ from __future__ import annotations
 import ctypes
 import math
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -88,13 +89,26 @@ def die_te_regularize(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
                                    _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))
 
 
+METHODS = {"gmres": 0, "bicgstab": 1, "gcr": 2}
+
+
+def _method(method) -> int:
+    if isinstance(method, str):
+        if method not in METHODS:
+            raise ValueError(f"method must be one of {sorted(METHODS)}")
+        return METHODS[method]
+    return int(method)
+
+
 def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, restart: int = 30,
                  max_iters: int = 100_000, tol: float = 1e-8, mixed: int = 0, x0_given: bool = False,
-                 reg_margin: float = 0.0, orth: int = 0, graph: int = 0, block: int = 0) -> tuple[int, list[dict]]:
+                 reg_margin: float = 0.0, orth: int = 0, graph: int = 0, block: int = 0,
+                 method="gmres") -> tuple[int, list[dict]]:
     """mixed: 0 FP64, 1 (or True) complex64 products and basis, 2 complex64 products with a
-    binary16 basis (orth=1)."""
+    binary16 basis (orth=1).  method: "gmres", "bicgstab" or "gcr" (restart = GCR's kept
+    directions)."""
     o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
-                       float(reg_margin), int(orth), int(bool(graph)), int(block))
+                       float(reg_margin), int(orth), int(bool(graph)), int(block), _method(method))
     info = (DieTeSolveInfo * nrhs)()
     rc = load().die_te_solve(ctx, _dev(e_in, (torch.complex128,), "e_in"), _dev(e_tot, (torch.complex128,), "e_tot"),
                              nrhs, ctypes.byref(o), info, _stream())
@@ -104,13 +118,13 @@ def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, res
 
 def die_te_solve_batch(ctxs, e_ins, e_tots, nrhs, *, restart: int = 30, max_iters: int = 100_000, tol: float = 1e-8,
                        mixed: int = 0, x0_given: bool = False, reg_margin: float = 0.0,
-                       orth: int = 0, graph: int = 0, block: int = 0) -> tuple[int, list[list[dict]]]:
+                       orth: int = 0, graph: int = 0, block: int = 0, method="gmres") -> tuple[int, list[list[dict]]]:
     """Several contexts (grid sizes) in one call; returns (code, per-context info lists)."""
     n = len(ctxs)
     if not (len(e_ins) == len(e_tots) == len(nrhs) == n):
         raise ValueError("ctxs, e_ins, e_tots and nrhs must have the same length")
     o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
-                       float(reg_margin), int(orth), int(bool(graph)), int(block))
+                       float(reg_margin), int(orth), int(bool(graph)), int(block), _method(method))
     vp = ctypes.c_void_p
     c_arr = (vp * n)(*[vp(c.value if isinstance(c, vp) else c) for c in ctxs])
     i_arr = (vp * n)(*[_dev(t, (torch.complex128,), "e_in") for t in e_ins])
@@ -128,6 +142,29 @@ def die_te_fft_plan(ctx, prec: int, nrhs: int) -> list[int]:
     v = (ctypes.c_int * 3)()
     check(load().die_te_fft_plan(ctx, int(prec), int(nrhs), v, _stream()))
     return [int(x) for x in v]
+
+
+OPERATORS = {"A": 0, "AR": 1, "ARA": 2, "solved": 3}
+
+
+def _which(which) -> int:
+    if isinstance(which, str):
+        if which not in OPERATORS:
+            raise ValueError(f"which must be one of {sorted(OPERATORS)}")
+        return OPERATORS[which]
+    return int(which)
+
+
+def die_te_operator_dense(ctx, which, obj: int, out: torch.Tensor) -> None:
+    """out: device complex128 (nvec, nvec); filled column-major (its transpose, row-major)."""
+    check(load().die_te_operator_dense(ctx, _which(which), int(obj), _dev(out, (torch.complex128,), "out"),
+                                       _stream()))
+
+
+def die_te_spectrum(ctx, which, obj: int, nvec: int) -> np.ndarray:
+    eig = np.zeros(nvec, dtype=np.complex128)
+    check(load().die_te_spectrum(ctx, _which(which), int(obj), ctypes.c_void_p(eig.ctypes.data), _stream()))
+    return eig
 
 
 def die_te_apply_deflation(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
@@ -281,6 +318,16 @@ class Solver:
 
     def fft_plan(self, nrhs: int, dtype=torch.complex64) -> list[int]:
         return die_te_fft_plan(self.ctx, DIE_C128 if dtype == torch.complex128 else DIE_C64, nrhs)
+
+    def dense_operator(self, which="A", obj: int = 0) -> torch.Tensor:
+        """The dense nvec x nvec matrix of an operator ("A", "AR", "ARA" or "solved") for one object."""
+        out = torch.empty((self.nvec, self.nvec), dtype=torch.complex128, device=self.device)
+        die_te_operator_dense(self.ctx, which, obj, out)
+        return out.t()  # the library writes column-major
+
+    def spectrum(self, which="A", obj: int = 0) -> np.ndarray:
+        """All eigenvalues of that matrix (nvec <= 4096)."""
+        return die_te_spectrum(self.ctx, which, obj, self.nvec)
 
     def apply_deflation(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)

@@ -60,6 +60,8 @@ int auto_pad(int n) {
   while (p < 2 * n - 1) p <<= 1;
   return p;
 }
+// Largest order of the dense eigenvalue problem die_te_spectrum solves on the host.
+constexpr int kSpectrumMaxOrder = 4096;
 
 }  // namespace
 
@@ -980,6 +982,414 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
   return rc;
 }
 
+// ------------------------------------------------------------ other Krylov solvers
+// Per right-hand side dots out[r] = (X_r, Y_r) = sum conj(X_r) Y_r (FP64, fixed order), on the device.
+int rhs_dots(const double2* X, const double2* Y, size_t n, int nrhs, double2* part, double2* out, const int* live,
+             hipStream_t st) {
+  DIE_HIP((die::launch_mdot<double, double>(X, 0, n, 1, nullptr, Y, n, n, nrhs, part, live, st)));
+  DIE_HIP(die::launch_reduce(part, 1, die::blas_blocks(n), nrhs, 1.0, nullptr, out, live, st));
+  return DIE_OK;
+}
+template <class V> int fetch(const DBuf& d, std::vector<V>& h, hipStream_t st) {
+  DIE_HIP(hipMemcpyAsync(h.data(), d.p, h.size() * sizeof(V), hipMemcpyDeviceToHost, st));
+  DIE_HIP(hipStreamSynchronize(st));
+  return DIE_OK;
+}
+template <class V> int put(DBuf& d, const std::vector<V>& h, hipStream_t st) {
+  DIE_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, st));
+  DIE_HIP(hipStreamSynchronize(st));  // the host vector may change before the copy would run
+  return DIE_OK;
+}
+
+// Bi-CGSTAB (method 1, van der Vorst's stabilised bi-conjugate gradients) and restarted GCR(m)
+// (method 2, generalized conjugate residuals, restart = m) on the system GMRES solves,
+// M P^-1 v = A_R r with M = A_R A (regularized) or A and u += P^-1 v, in FP64: the Conclusions
+// of the paper note that any short-memory Krylov solver applies to this preconditioned system and
+// name these.  Every right-hand side runs its own recurrence in the shared launches; the
+// recurrence scalars are formed on the host.  A right-hand side whose recurrence residual reaches
+// its target (the tolerance scaled to the solved system, as for GMRES cycles), breaks down or
+// stagnates has its FP64 true residual b - A u evaluated; below the tolerance it has converged,
+// else its recurrence restarts from that residual.  iters counts applications of M.
+int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_te_solve_opts& o,
+              die_te_solve_info* info, hipStream_t st) {
+  using cdv = std::complex<double>;
+  const size_t n = c->nvec;
+  const int m = o.restart;  // GCR: directions kept before a restart
+  const bool gcr = o.method == 2;
+  const int nblk = die::blas_blocks(n);
+  const bool reg = c->regularize != 0;
+  const bool defl = c->r > 0;
+  const int rpo = nrhs / c->nobj;
+  const double tol = o.tol > 0 ? o.tol : 1e-8;
+  const double margin = reg ? (o.reg_margin > 0 ? o.reg_margin : 0.1) : 1.0;
+  const size_t dbytes = (size_t)nrhs * n * sizeof(double2);
+  DBuf Rr, Rh, Pv, Vv, Sv, Tv, Ph, Sh, Tmp, Res, Pd, Qd, part, partn, nrm, dv, cf, livb, pcnt, pcoef, ppart, scl;
+  DBuf Ubest, bmask, one;  // the best iterate so far per right-hand side (returned when not converged)
+  DIE_TRY(Ubest.alloc(dbytes));
+  DIE_TRY(bmask.alloc((size_t)nrhs * sizeof(int)));
+  DIE_TRY(one.alloc(sizeof(double)));
+  {
+    const double v1 = 1.0;
+    DIE_HIP(hipMemcpyAsync(one.p, &v1, sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  DIE_TRY(Rr.alloc(dbytes));
+  DIE_TRY(Tmp.alloc(dbytes));
+  DIE_TRY(Res.alloc(dbytes));
+  if (gcr) {
+    DIE_TRY(Pd.alloc((size_t)m * dbytes));
+    DIE_TRY(Qd.alloc((size_t)m * dbytes));
+  } else {
+    DIE_TRY(Rh.alloc(dbytes));
+    DIE_TRY(Pv.alloc(dbytes));
+    DIE_TRY(Vv.alloc(dbytes));
+    DIE_TRY(Sv.alloc(dbytes));
+    DIE_TRY(Tv.alloc(dbytes));
+    if (defl) {
+      DIE_TRY(Ph.alloc(dbytes));
+      DIE_TRY(Sh.alloc(dbytes));
+    }
+  }
+  const int nvd = gcr ? m : 1;
+  DIE_TRY(part.alloc((size_t)nrhs * nvd * nblk * sizeof(double2)));
+  DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
+  DIE_TRY(nrm.alloc((size_t)nrhs * sizeof(double)));
+  DIE_TRY(dv.alloc((size_t)nrhs * 2 * nvd * sizeof(double2)));
+  DIE_TRY(cf.alloc((size_t)nrhs * 3 * sizeof(double2)));
+  DIE_TRY(livb.alloc((size_t)nrhs * sizeof(int)));
+  DIE_TRY(scl.alloc((size_t)nrhs * sizeof(double)));
+  if (defl) {
+    DIE_TRY(ppart.alloc((size_t)nrhs * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
+                        sizeof(double2)));
+    DIE_TRY(pcoef.alloc((size_t)nrhs * c->r * sizeof(double2)));
+    DIE_TRY(pcnt.alloc((size_t)nrhs * die::kCounterStride * sizeof(int)));
+    DIE_HIP(hipMemsetAsync(pcnt.p, 0, (size_t)nrhs * die::kCounterStride * sizeof(int), st));
+  }
+  {
+    const int* pv = nullptr;
+    DIE_TRY(fft_plan<double>(c, nrhs, st, &pv));
+  }
+  DIE_TRY(ensure_work(c, work_bytes(c, nrhs, sizeof(double2)), st));
+  const int* live = livb.as<int>();
+  double2* R = Rr.as<double2>();
+  double2* TMP = Tmp.as<double2>();
+  // z = P^-1 x (or x itself), y = M z
+  auto pinv = [&](const double2* x, double2* z) -> int {
+    return apply_pinv<double>(c, x, z, nrhs, ppart.as<double2>(), pcoef.as<double2>(), pcnt.as<int>(), live, st, rpo);
+  };
+  auto opM = [&](const double2* z, double2* y) -> int {
+    return apply_M<double>(c, reg, z, reg ? TMP : nullptr, y, nrhs, live, st, rpo);
+  };
+  auto norms = [&](const double2* x, std::vector<double>& out) -> int {
+    DIE_HIP((die::launch_norm2<double>(x, n, n, nrhs, partn.as<double>(), live, st)));
+    DIE_HIP(die::launch_reduce_norm(partn.as<double>(), nblk, nrhs, nrm.as<double>(), live, st));
+    std::vector<double> h(nrhs);
+    DIE_TRY(fetch(nrm, h, st));
+    for (int r = 0; r < nrhs; ++r) out[r] = std::sqrt(h[r]);
+    return DIE_OK;
+  };
+  auto dotsv = [&](const double2* X, const double2* Y, std::vector<cdv>& out) -> int {
+    DIE_TRY(rhs_dots(X, Y, n, nrhs, part.as<double2>(), dv.as<double2>(), live, st));
+    std::vector<double2> h(nrhs);
+    DIE_HIP(hipMemcpyAsync(h.data(), dv.p, nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
+    DIE_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) out[r] = cdv(h[r].x, h[r].y);
+    return DIE_OK;
+  };
+  std::vector<int> act(nrhs, 1), lv(nrhs, 0), conv(nrhs, 0), brk(nrhs, 0), iters(nrhs, 0), pa(nrhs, 0), par(nrhs, 0),
+      cyc(nrhs, 0), kslot(nrhs, 0), check(nrhs, 1);
+  std::vector<double> bnorm(nrhs), relres(nrhs, 1.0), target(nrhs, 0.0), rn(nrhs), best(nrhs, 1e300);
+  std::vector<cdv> rho(nrhs, 1.0), alpha(nrhs, 1.0), omega(nrhs, 1.0), d1(nrhs), d2(nrhs);
+  auto set_live = [&](const std::vector<int>& mask) -> int {
+    lv = mask;
+    return put(livb, lv, st);
+  };
+  if (!o.x0_given) DIE_HIP(hipMemsetAsync(u, 0, dbytes, st));
+  DIE_TRY(set_live(std::vector<int>(nrhs, 1)));
+  DIE_TRY(norms(b, bnorm));
+  for (int r = 0; r < nrhs; ++r)
+    if (!std::isfinite(bnorm[r])) return fail(DIE_E_INVALID, "e_in contains non-finite values");
+  bool first = true;
+  for (;;) {
+    // ---- FP64 true residuals of the right-hand sides due a check; restart their recurrences
+    std::vector<int> chk(nrhs, 0);
+    int nchk = 0;
+    for (int r = 0; r < nrhs; ++r)
+      if (act[r] && check[r]) {
+        chk[r] = 1;
+        ++nchk;
+      }
+    if (nchk) {
+      DIE_TRY(set_live(chk));
+      DIE_TRY(apply_op<double>(c, u, Res.as<double2>(), nrhs, false, live, st, rpo));
+      DIE_HIP((die::launch_maxpy<double, double, double>(0, (const double2*)nullptr, 0, 0, 0, nullptr, nullptr, 0, b, n,
+                                                         1.0, Res.as<double2>(), n, -1.0, n, nrhs, nullptr, nullptr,
+                                                         live, st)));
+      std::vector<double> tr(nrhs);
+      DIE_TRY(norms(Res.as<double2>(), tr));
+      std::vector<int> imp(nrhs, 0);  // iterates better than the best so far
+      int nimp = 0;
+      int nfb = 0;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!chk[r]) continue;
+        pa[r] += 1;
+        ++cyc[r];
+        const double rel = bnorm[r] > 0 ? tr[r] / bnorm[r] : 0.0;
+        if (first && o.x0_given && !(std::isfinite(tr[r]) && tr[r] < bnorm[r])) {
+          // a given guess that is non-finite or no better than zero is replaced by zero
+          DIE_HIP(hipMemsetAsync(u + (size_t)r * n, 0, n * sizeof(double2), st));
+          ++nfb;
+          continue;
+        }
+        relres[r] = rel;
+        if (std::isfinite(rel) && rel < best[r]) {
+          best[r] = rel;
+          imp[r] = 1;
+          ++nimp;
+        }
+        if (!std::isfinite(tr[r])) {
+          brk[r] = 1;
+          act[r] = 0;
+        } else if (rel <= tol || bnorm[r] == 0.0) {
+          conv[r] = 1;
+          act[r] = 0;
+        } else if (iters[r] >= o.max_iters) {
+          act[r] = 0;
+        }
+        if (!act[r]) chk[r] = 0;
+      }
+      first = false;
+      if (nfb) continue;  // residuals of the zeroed guesses
+      if (nimp) {
+        DIE_TRY(put(bmask, imp, st));
+        DIE_HIP((die::launch_scale<double, double>(u, n, Ubest.as<double2>(), n, one.as<double>(), 0, n, nrhs,
+                                                   bmask.as<int>(), st)));
+      }
+      int nre = 0;
+      for (int r = 0; r < nrhs; ++r) nre += chk[r];
+      if (nre) {
+        // the recurrence restarts: R = A_R res (or res), and the method's own state
+        DIE_TRY(set_live(chk));
+        if (reg) {
+          DIE_TRY(apply_op<double>(c, Res.as<double2>(), R, nrhs, true, live, st, rpo));
+        } else {
+          DIE_HIP(hipMemcpyAsync(R, Res.as<double2>(), dbytes, hipMemcpyDeviceToDevice, st));
+        }
+        std::vector<double> sn(nrhs);
+        DIE_TRY(norms(R, sn));
+        for (int r = 0; r < nrhs; ++r) {
+          if (!chk[r]) continue;
+          if (reg) par[r] += 1;
+          const double tres = relres[r] * bnorm[r];
+          target[r] = tres > 0 ? margin * tol * bnorm[r] * sn[r] / tres : 0.0;
+          rn[r] = sn[r];
+          check[r] = 0;
+          kslot[r] = 0;
+          rho[r] = alpha[r] = omega[r] = 1.0;
+          if (!(sn[r] > 0) || !std::isfinite(sn[r])) {  // the regularized residual vanished
+            act[r] = 0;
+          }
+        }
+        if (!gcr) {  // r^ = R, p = v = 0
+          DIE_HIP(hipMemcpyAsync(Rh.p, R, dbytes, hipMemcpyDeviceToDevice, st));
+          std::vector<double2> z3((size_t)nrhs * 3, make_double2(0.0, 0.0));
+          DIE_TRY(put(cf, z3, st));
+          DIE_HIP(die::launch_comb3(Pv.as<double2>(), nullptr, nullptr, nullptr, cf.as<double2>(), n, nrhs, live, st));
+          DIE_HIP(die::launch_comb3(Vv.as<double2>(), nullptr, nullptr, nullptr, cf.as<double2>(), n, nrhs, live, st));
+        }
+      }
+    }
+    // ---- one step of every right-hand side still iterating
+    std::vector<int> run(nrhs, 0);
+    int nrun = 0;
+    for (int r = 0; r < nrhs; ++r)
+      if (act[r] && !check[r]) {
+        run[r] = 1;
+        ++nrun;
+      }
+    if (nrun == 0) {
+      bool any = false;
+      for (int r = 0; r < nrhs; ++r) any = any || (act[r] && check[r]);
+      if (!any) break;
+      continue;
+    }
+    DIE_TRY(set_live(run));
+    const double tiny = 1e-300;
+    if (!gcr) {
+      // rho1 = (r^, r); p = r + beta (p - omega v)
+      DIE_TRY(dotsv(Rh.as<double2>(), R, d1));
+      std::vector<double2> co((size_t)nrhs * 3, make_double2(0.0, 0.0));
+      for (int r = 0; r < nrhs; ++r) {
+        if (!run[r]) continue;
+        const cdv beta = (d1[r] / rho[r]) * (alpha[r] / omega[r]);
+        if (std::abs(d1[r]) <= tiny || !std::isfinite(std::abs(beta))) {
+          check[r] = 1;  // breakdown: restart from the true residual
+          continue;
+        }
+        rho[r] = d1[r];
+        co[3 * r] = make_double2(1.0, 0.0);
+        co[3 * r + 1] = make_double2(beta.real(), beta.imag());
+        const cdv bo = -beta * omega[r];
+        co[3 * r + 2] = make_double2(bo.real(), bo.imag());
+      }
+      for (int r = 0; r < nrhs; ++r) run[r] = run[r] && !check[r];
+      DIE_TRY(set_live(run));
+      DIE_TRY(put(cf, co, st));
+      DIE_HIP(die::launch_comb3(Pv.as<double2>(), R, Pv.as<double2>(), Vv.as<double2>(), cf.as<double2>(), n, nrhs,
+                                live, st));
+      const double2* ph = Pv.as<double2>();
+      if (defl) {
+        DIE_TRY(pinv(Pv.as<double2>(), Ph.as<double2>()));
+        ph = Ph.as<double2>();
+      }
+      DIE_TRY(opM(ph, Vv.as<double2>()));
+      // alpha = rho1 / (r^, v); s = r - alpha v
+      DIE_TRY(dotsv(Rh.as<double2>(), Vv.as<double2>(), d2));
+      for (int r = 0; r < nrhs; ++r) {
+        if (!run[r]) continue;
+        iters[r] += 1;
+        pa[r] += 1;
+        if (reg) par[r] += 1;
+        if (std::abs(d2[r]) <= tiny) {
+          check[r] = 1;
+          co[3 * r] = co[3 * r + 1] = co[3 * r + 2] = make_double2(0.0, 0.0);
+          continue;
+        }
+        alpha[r] = rho[r] / d2[r];
+        co[3 * r] = make_double2(1.0, 0.0);
+        co[3 * r + 1] = make_double2(-alpha[r].real(), -alpha[r].imag());
+        co[3 * r + 2] = make_double2(0.0, 0.0);
+      }
+      for (int r = 0; r < nrhs; ++r) run[r] = run[r] && !check[r];
+      DIE_TRY(set_live(run));
+      DIE_TRY(put(cf, co, st));
+      DIE_HIP(die::launch_comb3(Sv.as<double2>(), R, Vv.as<double2>(), nullptr, cf.as<double2>(), n, nrhs, live, st));
+      const double2* sh = Sv.as<double2>();
+      if (defl) {
+        DIE_TRY(pinv(Sv.as<double2>(), Sh.as<double2>()));
+        sh = Sh.as<double2>();
+      }
+      DIE_TRY(opM(sh, Tv.as<double2>()));
+      // omega = (t, s) / (t, t); u += alpha p^ + omega s^; r = s - omega t
+      DIE_TRY(dotsv(Tv.as<double2>(), Sv.as<double2>(), d1));
+      DIE_TRY(dotsv(Tv.as<double2>(), Tv.as<double2>(), d2));
+      std::vector<double2> cu((size_t)nrhs * 3, make_double2(0.0, 0.0));
+      for (int r = 0; r < nrhs; ++r) {
+        if (!run[r]) continue;
+        iters[r] += 1;
+        pa[r] += 1;
+        if (reg) par[r] += 1;
+        omega[r] = d2[r].real() > 0 ? d1[r] / d2[r] : cdv(0.0);
+        cu[3 * r] = make_double2(1.0, 0.0);
+        cu[3 * r + 1] = make_double2(alpha[r].real(), alpha[r].imag());
+        cu[3 * r + 2] = make_double2(omega[r].real(), omega[r].imag());
+        co[3 * r] = make_double2(1.0, 0.0);
+        co[3 * r + 1] = make_double2(-omega[r].real(), -omega[r].imag());
+        co[3 * r + 2] = make_double2(0.0, 0.0);
+      }
+      DIE_TRY(put(cf, cu, st));
+      DIE_HIP(die::launch_comb3(u, u, ph, sh, cf.as<double2>(), n, nrhs, live, st));
+      DIE_TRY(put(cf, co, st));
+      DIE_HIP(die::launch_comb3(R, Sv.as<double2>(), Tv.as<double2>(), nullptr, cf.as<double2>(), n, nrhs, live, st));
+      for (int r = 0; r < nrhs; ++r)
+        if (run[r] && std::abs(omega[r]) <= tiny) check[r] = 1;  // stagnation: restart
+    } else {
+      // z = P^-1 r into slot k, q = M z; CGS2 of q against the slots before it (z alike);
+      // q, z scaled to ||q|| = 1; alpha = (q, r); u += alpha z; r -= alpha q
+      // every right-hand side of one call uses the same slot index: slots advance together
+      int k = -1;
+      for (int r = 0; r < nrhs; ++r)
+        if (run[r]) k = std::max(k, kslot[r]);
+      for (int r = 0; r < nrhs; ++r)
+        if (run[r] && kslot[r] != k) {  // right-hand sides that restarted at another slot wait
+          run[r] = 0;
+        }
+      DIE_TRY(set_live(run));
+      const size_t vs = (size_t)nrhs * n;
+      double2* zk = Pd.as<double2>() + (size_t)k * vs;
+      double2* qk = Qd.as<double2>() + (size_t)k * vs;
+      if (defl) {
+        DIE_TRY(pinv(R, zk));
+      } else {
+        DIE_HIP(hipMemcpyAsync(zk, R, dbytes, hipMemcpyDeviceToDevice, st));
+      }
+      DIE_TRY(opM(zk, qk));
+      for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        DIE_HIP((die::launch_mdot<double, double>(Qd.as<double2>(), vs, n, k, nullptr, qk, n, n, nrhs,
+                                                  part.as<double2>(), live, st)));
+        DIE_HIP(die::launch_reduce(part.as<double2>(), k, nblk, nrhs, -1.0, nullptr, dv.as<double2>(), live, st));
+        DIE_HIP((die::launch_maxpy<double, double, double>(0, Qd.as<double2>(), vs, n, k, nullptr, dv.as<double2>(), k,
+                                                           nullptr, n, 0.0, qk, n, 1.0, n, nrhs, nullptr, nullptr,
+                                                           live, st)));
+        DIE_HIP((die::launch_maxpy<double, double, double>(0, Pd.as<double2>(), vs, n, k, nullptr, dv.as<double2>(), k,
+                                                           nullptr, n, 0.0, zk, n, 1.0, n, nrhs, nullptr, nullptr,
+                                                           live, st)));
+      }
+      std::vector<double> qn(nrhs);
+      DIE_TRY(norms(qk, qn));
+      std::vector<double> inv(nrhs, 0.0);
+      for (int r = 0; r < nrhs; ++r) {
+        if (!run[r]) continue;
+        iters[r] += 1;
+        pa[r] += 1;
+        if (reg) par[r] += 1;
+        if (!(qn[r] > tiny) || !std::isfinite(qn[r])) {
+          check[r] = 1;  // the new direction lies in the span of the kept ones
+          continue;
+        }
+        inv[r] = 1.0 / qn[r];
+      }
+      for (int r = 0; r < nrhs; ++r) run[r] = run[r] && !check[r];
+      DIE_TRY(set_live(run));
+      DIE_TRY(put(scl, inv, st));
+      DIE_HIP((die::launch_scale<double, double>(qk, n, qk, n, scl.as<double>(), 1, n, nrhs, live, st)));
+      DIE_HIP((die::launch_scale<double, double>(zk, n, zk, n, scl.as<double>(), 1, n, nrhs, live, st)));
+      DIE_TRY(dotsv(qk, R, d1));
+      std::vector<double2> cu((size_t)nrhs * 3, make_double2(0.0, 0.0)), co((size_t)nrhs * 3, make_double2(0.0, 0.0));
+      for (int r = 0; r < nrhs; ++r) {
+        if (!run[r]) continue;
+        cu[3 * r] = make_double2(1.0, 0.0);
+        cu[3 * r + 1] = make_double2(d1[r].real(), d1[r].imag());
+        co[3 * r] = make_double2(1.0, 0.0);
+        co[3 * r + 1] = make_double2(-d1[r].real(), -d1[r].imag());
+        kslot[r] = (kslot[r] + 1) % m;
+      }
+      DIE_TRY(put(cf, cu, st));
+      DIE_HIP(die::launch_comb3(u, u, zk, nullptr, cf.as<double2>(), n, nrhs, live, st));
+      DIE_TRY(put(cf, co, st));
+      DIE_HIP(die::launch_comb3(R, R, qk, nullptr, cf.as<double2>(), n, nrhs, live, st));
+    }
+    // the recurrence residuals: a right-hand side at its target, or out of iterations, is checked
+    std::vector<double> rr(nrhs);
+    DIE_TRY(norms(R, rr));
+    for (int r = 0; r < nrhs; ++r) {
+      if (!run[r]) continue;
+      rn[r] = rr[r];
+      if (!std::isfinite(rr[r]) || rr[r] <= target[r] || iters[r] >= o.max_iters) check[r] = 1;
+    }
+  }
+  // right-hand sides that stopped short of the tolerance get their best checked iterate back
+  {
+    std::vector<int> bm(nrhs, 0);
+    DIE_TRY(restore_best(u, Ubest.as<double2>(), n, nrhs, conv, brk, best, relres, bm, bmask.as<int>(),
+                         one.as<double>(), st));
+  }
+  int rc = DIE_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    if (brk[r]) rc = std::min(rc, (int)DIE_E_BREAKDOWN);
+    else if (!conv[r] && rc == DIE_OK) rc = DIE_NOT_CONVERGED;
+    if (info) {
+      info[r].status = brk[r] ? DIE_E_BREAKDOWN : (conv[r] ? DIE_OK : DIE_NOT_CONVERGED);
+      info[r].iters = iters[r];
+      info[r].products_A = pa[r];
+      info[r].products_AR = par[r];
+      info[r].cycles = cyc[r];
+      info[r].rel_res_true = relres[r];
+    }
+  }
+  if (rc == DIE_E_BREAKDOWN) return fail(DIE_E_BREAKDOWN, "Krylov solver met a non-finite value");
+  return rc;
+}
+
 // ------------------------------------------------------------------ block GMRES
 // Scratch of the block products: the projection's chunk products (accumulation type) and the
 // Gram matrices' chunk partials (complex FP64).
@@ -1889,6 +2299,11 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   if (o.mixed < 0 || o.mixed > 2) return fail(DIE_E_INVALID, "mixed must be 0, 1 or 2");
   if (o.mixed == 2 && o.orth != 1) return fail(DIE_E_INVALID, "mixed = 2 (binary16 basis) needs orth = 1");
   if (o.block < 0 || o.block > 2) return fail(DIE_E_INVALID, "block must be 0, 1 or 2");
+  if (o.method < 0 || o.method > 2) return fail(DIE_E_INVALID, "method must be 0 (GMRES), 1 (Bi-CGSTAB) or 2 (GCR)");
+  if (o.method) {
+    if (o.block || o.mixed) return fail(DIE_E_INVALID, "Bi-CGSTAB and GCR run per right-hand side in FP64 (block = mixed = 0)");
+    return alt_solve(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
+  }
   if (o.block) {
     if (o.mixed == 2) return fail(DIE_E_INVALID, "block GMRES needs mixed = 0 or 1");
     if (o.block == 2 && o.mixed != 1) return fail(DIE_E_INVALID, "block = 2 (binary16 GEMMs) needs mixed = 1");
@@ -2016,6 +2431,81 @@ int die_te_apply_deflation(die_te_ctx* c, const void* x, void* y, int nrhs, void
   DIE_TRY(apply_pinv<double>(c, (const double2*)x, (double2*)y, nrhs, part.as<double2>(), coef.as<double2>(),
                              cnt.as<int>(), nullptr, st, nrhs / c->nobj));
   DIE_HIP(hipStreamSynchronize(st));  // part/coef are freed on return
+  return DIE_OK;
+}
+
+int die_te_operator_dense(die_te_ctx* c, int which, int obj, void* out, void* stream) {
+  die_host::last_error().clear();
+  DIE_TRY(check_ctx(c));
+  if (!out) return fail(DIE_E_INVALID, "null out");
+  if (which < 0 || which > 3) return fail(DIE_E_INVALID, "which must be 0 (A), 1 (A_R), 2 (A_R A) or 3 (M P^-1)");
+  if (obj < 0 || obj >= c->nobj) return fail(DIE_E_INVALID, "obj out of range");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = c->nvec;
+  // columns in batches: the identity columns e_j, then the operator on them (object obj)
+  const int nb = (int)std::min<size_t>(n, 256);
+  const int nblk = die::blas_blocks(n);
+  DBuf X, T1, T2, part, coef, cnt;
+  DIE_TRY(X.alloc((size_t)nb * n * sizeof(double2)));
+  DIE_TRY(T1.alloc((size_t)nb * n * sizeof(double2)));
+  if (which == 3 && c->r > 0) {
+    DIE_TRY(T2.alloc((size_t)nb * n * sizeof(double2)));
+    DIE_TRY(part.alloc((size_t)nb * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) * sizeof(double2)));
+    DIE_TRY(coef.alloc((size_t)nb * c->r * sizeof(double2)));
+    DIE_TRY(cnt.alloc((size_t)nb * die::kCounterStride * sizeof(int)));
+    DIE_HIP(hipMemsetAsync(cnt.p, 0, (size_t)nb * die::kCounterStride * sizeof(int), st));
+  }
+  const bool reg = c->regularize != 0;
+  for (size_t c0 = 0; c0 < n; c0 += (size_t)nb) {
+    const int k = (int)std::min<size_t>((size_t)nb, n - c0);
+    double2* y = (double2*)out + c0 * n;
+    double2* x = X.as<double2>();
+    DIE_HIP(die::launch_unit_cols(x, n, c0, k, st));
+    switch (which) {
+      case 0:
+        DIE_TRY(apply_op<double>(c, x, y, k, false, nullptr, st, k, obj));
+        break;
+      case 1:
+        DIE_TRY(apply_op<double>(c, x, y, k, true, nullptr, st, k, obj));
+        break;
+      case 2:
+        DIE_TRY(apply_M<double>(c, true, x, T1.as<double2>(), y, k, nullptr, st, k, obj));
+        break;
+      default: {
+        const double2* z = x;
+        if (c->r > 0) {
+          DIE_TRY(apply_pinv<double>(c, x, T2.as<double2>(), k, part.as<double2>(), coef.as<double2>(), cnt.as<int>(),
+                                     nullptr, st, k, obj));
+          z = T2.as<double2>();
+        }
+        DIE_TRY(apply_M<double>(c, reg, z, T1.as<double2>(), y, k, nullptr, st, k, obj));
+      }
+    }
+  }
+  DIE_HIP(hipStreamSynchronize(st));  // the batch buffers are freed on return
+  return DIE_OK;
+}
+
+int die_te_spectrum(die_te_ctx* c, int which, int obj, void* eig, void* stream) {
+  die_host::last_error().clear();
+  DIE_TRY(check_ctx(c));
+  if (!eig) return fail(DIE_E_INVALID, "null eig");
+  const size_t n = c->nvec;
+  if (n > (size_t)kSpectrumMaxOrder)
+    return fail(DIE_E_INVALID, "the dense eigenvalue problem is limited to " + std::to_string(kSpectrumMaxOrder) +
+                                   " unknowns (the host QR iteration is O(n^3))");
+  hipStream_t st = (hipStream_t)stream;
+  DBuf D;
+  DIE_TRY(D.alloc(n * n * sizeof(double2)));
+  DIE_TRY(die_te_operator_dense(c, which, obj, D.p, stream));
+  die::la::Mat A((int)n, (int)n);
+  DIE_HIP(hipMemcpyAsync(A.a.data(), D.p, n * n * sizeof(double2), hipMemcpyDeviceToHost, st));
+  DIE_HIP(hipStreamSynchronize(st));
+  die::la::Mat Z0;  // no Schur vectors: eigenvalues only
+  die::la::hessenberg(A, Z0);
+  if (!die::la::schur(A, Z0)) return fail(DIE_E_BREAKDOWN, "spectrum: QR iteration did not converge");
+  cd* e = (cd*)eig;
+  for (size_t i = 0; i < n; ++i) e[i] = A((int)i, (int)i);
   return DIE_OK;
 }
 

@@ -1433,4 +1433,48 @@ DIE_INST_FAXPY(float, float)
 template hipError_t launch_faxpy<double, float>(const double2*, size_t, size_t, int, int, const double2*,
                                                 const float2*, float2*, size_t, size_t, int, const int*, hipStream_t);
 
+
+// ---- helpers of the alternative Krylov solvers and of the dense operator
+
+// X[j][e] = 1 if e == col0 + j else 0 (complex128), j < ncols, e < n.
+__global__ void k_unit_cols(double2* __restrict__ X, size_t n, size_t col0, int ncols) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (e >= n || j >= ncols) return;
+  X[(size_t)j * n + e] = make_double2(e == col0 + (size_t)j ? 1.0 : 0.0, 0.0);
+}
+
+// Y_r = c[r][0] X0_r + c[r][1] X1_r + c[r][2] X2_r for live right-hand sides (an input may be null,
+// or alias Y: each element is read before it is written by the same thread).
+__global__ void k_comb3(double2* __restrict__ Y, const double2* X0, const double2* X1, const double2* X2,
+                        const double2* __restrict__ coef, size_t n, const int* __restrict__ live) {
+  const int r = blockIdx.y;
+  if (live && !live[r]) return;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const size_t o = (size_t)r * n + e;
+  double2 acc = make_double2(0.0, 0.0);
+  const double2* cr = coef + (size_t)r * 3;
+  if (X0) acc = cadd<double>(acc, cmul<double>(cr[0], X0[o]));
+  if (X1) acc = cadd<double>(acc, cmul<double>(cr[1], X1[o]));
+  if (X2) acc = cadd<double>(acc, cmul<double>(cr[2], X2[o]));
+  Y[o] = acc;
+}
+
+hipError_t launch_unit_cols(double2* X, size_t n, size_t col0, int ncols, hipStream_t st) {
+  if (ncols < 1 || ncols > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_unit_cols, dim3((unsigned)((n + 255) / 256), (unsigned)ncols), dim3(256), 0, st, X, n, col0,
+                     ncols);
+  return hipGetLastError();
+}
+
+hipError_t launch_comb3(double2* Y, const double2* X0, const double2* X1, const double2* X2, const double2* coef,
+                        size_t n, int nrhs, const int* live, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  if (nrhs > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_comb3, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, Y, X0, X1, X2, coef,
+                     n, live);
+  return hipGetLastError();
+}
+
 }  // namespace die

@@ -201,6 +201,14 @@ template <class T>
 hipError_t launch_cadd2(const c2<T>* A, int lda, const c2<T>* B, int ldb, int rows, int cols, c2<T>* C, int ldc,
                         hipStream_t st);
 
+// Identity columns X[j][e] = (e == col0 + j), j < ncols, complex128 vectors of length n.
+hipError_t launch_unit_cols(double2* X, size_t n, size_t col0, int ncols, hipStream_t st);
+// Y_r = c[r][0] X0_r + c[r][1] X1_r + c[r][2] X2_r, complex128 vectors of length n per right-hand
+// side (coefficients [nrhs][3]); an input may be null (skipped) or alias Y; only live[r] != 0
+// (live may be null).
+hipError_t launch_comb3(double2* Y, const double2* X0, const double2* X1, const double2* X2, const double2* coef,
+                        size_t n, int nrhs, const int* live, hipStream_t st);
+
 // ----------------------------------------------------------------- GMRES state
 struct GmresState {
   int j;         // iterations done in the current cycle
