@@ -151,8 +151,9 @@ typedef struct {
                         die_te_destroy.
                         0: per-rhs GMRES */
   int method;        /* 0: restarted GMRES (everything above).  1: Bi-CGSTAB; 2: restarted GCR(m) with
-                        m = restart kept directions (the Conclusions of the paper name both as
-                        alternatives on the same preconditioned system): per right-hand side, in
+                        m = restart kept directions; 3: IDR(s) with s = restart <= 64 (a random
+                        orthonormal shadow space from a fixed seed) (the Conclusions of the paper
+                        name these as alternatives on the same preconditioned system): per right-hand side, in
                         FP64 (needs block = mixed = 0; orth and graph do not apply), on
                         M P^-1 v = A_R r exactly as GMRES; a right-hand side whose recurrence
                         residual reaches the tolerance scaled to the solved system, breaks down or

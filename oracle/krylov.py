@@ -138,3 +138,72 @@ def gmres_residuals(M, b, steps: int) -> np.ndarray:
         y, *_ = np.linalg.lstsq(H[: j + 2, : j + 1], e1, rcond=None)
         out.append(np.linalg.norm(e1 - H[: j + 2, : j + 1] @ y))
     return np.array(out)
+
+
+def idrs(M, b, s=4, x0=None, tol=1e-10, maxiter=1000, prec=None, shadow=None, seed=0):
+    """Right-preconditioned IDR(s) (induced dimension reduction: P. Sonneveld, M. B. van Gijzen,
+    "IDR(s): a family of simple and fast algorithms for solving large nonsymmetric systems of
+    linear equations", SIAM J. Sci. Comput. 31 (2008), their prototype algorithm) on
+    M (P^-1 v) = b, x = P^-1 v.
+
+    s minimal-residual steps fill the difference matrices dR = -M dU (s columns each); then every
+    group of s + 1 steps builds the next residual in the intersection of the previous space with
+    the orthogonal complement of the shadow space span(shadow) (n x s; random orthonormal columns
+    from ``seed`` when None): c solves (shadow^H dR) c = shadow^H r, v = r - dR c, and the first
+    step of the group takes a new minimal-residual parameter omega on v.  The oldest difference
+    column is replaced by the new one at every step.  Returns (x, residual norms after every
+    step, applications of M)."""
+    A = _op(M)
+    P = prec if prec is not None else (lambda x: x)
+    n = b.shape[0]
+    if shadow is None:
+        rng = np.random.default_rng(seed)
+        shadow, _ = np.linalg.qr(rng.standard_normal((n, s)) + 1j * rng.standard_normal((n, s)))
+    S = np.asarray(shadow, dtype=np.complex128)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
+    r = b - A(x)
+    nb = np.linalg.norm(b)
+    hist = [np.linalg.norm(r)]
+    apps = 0
+    dR = np.zeros((n, s), dtype=np.complex128)
+    dU = np.zeros((n, s), dtype=np.complex128)
+    for k in range(s):  # the first s steps: minimal residual along the preconditioned residual
+        z = P(r)
+        v = A(z)
+        apps += 1
+        om = np.vdot(v, r) / np.vdot(v, v)
+        dU[:, k] = om * z
+        dR[:, k] = -om * v
+        x = x + dU[:, k]
+        r = r + dR[:, k]
+        hist.append(np.linalg.norm(r))
+    Mm = S.conj().T @ dR
+    m = S.conj().T @ r
+    oldest = 0
+    om = 1.0
+    while apps < maxiter and hist[-1] > tol * nb:
+        for k in range(s + 1):
+            c = np.linalg.solve(Mm, m)
+            q = -dR @ c
+            v = r + q
+            z = P(v)
+            if k == 0:
+                t = A(z)
+                apps += 1
+                om = np.vdot(t, v) / np.vdot(t, t)
+                dR[:, oldest] = q - om * t
+                dU[:, oldest] = -dU @ c + om * z
+            else:
+                dU[:, oldest] = -dU @ c + om * z
+                dR[:, oldest] = -A(dU[:, oldest])
+                apps += 1
+            r = r + dR[:, oldest]
+            x = x + dU[:, oldest]
+            dm = S.conj().T @ dR[:, oldest]
+            Mm[:, oldest] = dm
+            m = m + dm
+            oldest = (oldest + 1) % s
+            hist.append(np.linalg.norm(r))
+            if hist[-1] <= tol * nb or apps >= maxiter:
+                break
+    return x, np.array(hist), apps

@@ -89,7 +89,7 @@ def die_te_regularize(ctx, x: torch.Tensor, y: torch.Tensor, nrhs: int) -> None:
                                    _dev(y, (x.dtype,), "y"), nrhs, _prec(x), _stream()))
 
 
-METHODS = {"gmres": 0, "bicgstab": 1, "gcr": 2}
+METHODS = {"gmres": 0, "bicgstab": 1, "gcr": 2, "idrs": 3}
 
 
 def _method(method) -> int:
@@ -105,8 +105,8 @@ def die_te_solve(ctx, e_in: torch.Tensor, e_tot: torch.Tensor, nrhs: int, *, res
                  reg_margin: float = 0.0, orth: int = 0, graph: int = 0, block: int = 0,
                  method="gmres") -> tuple[int, list[dict]]:
     """mixed: 0 FP64, 1 (or True) complex64 products and basis, 2 complex64 products with a
-    binary16 basis (orth=1).  method: "gmres", "bicgstab" or "gcr" (restart = GCR's kept
-    directions)."""
+    binary16 basis (orth=1).  method: "gmres", "bicgstab", "gcr" (restart = GCR's kept
+    directions) or "idrs" (restart = s)."""
     o = DieTeSolveOpts(int(restart), int(max_iters), float(tol), int(mixed), int(bool(x0_given)),
                        float(reg_margin), int(orth), int(bool(graph)), int(block), _method(method))
     info = (DieTeSolveInfo * nrhs)()

@@ -1001,8 +1001,10 @@ template <class V> int put(DBuf& d, const std::vector<V>& h, hipStream_t st) {
   return DIE_OK;
 }
 
-// Bi-CGSTAB (method 1, van der Vorst's stabilised bi-conjugate gradients) and restarted GCR(m)
-// (method 2, generalized conjugate residuals, restart = m) on the system GMRES solves,
+// Bi-CGSTAB (method 1, van der Vorst's stabilised bi-conjugate gradients), restarted GCR(m)
+// (method 2, generalized conjugate residuals, restart = m) and IDR(s) (method 3, Sonneveld and van
+// Gijzen's induced dimension reduction, s = restart, a random orthonormal shadow space of s
+// vectors drawn from a fixed seed) on the system GMRES solves,
 // M P^-1 v = A_R r with M = A_R A (regularized) or A and u += P^-1 v, in FP64: the Conclusions
 // of the paper note that any short-memory Krylov solver applies to this preconditioned system and
 // name these.  Every right-hand side runs its own recurrence in the shared launches; the
@@ -1014,8 +1016,8 @@ int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_t
               die_te_solve_info* info, hipStream_t st) {
   using cdv = std::complex<double>;
   const size_t n = c->nvec;
-  const int m = o.restart;  // GCR: directions kept before a restart
-  const bool gcr = o.method == 2;
+  const int m = o.restart;  // GCR: directions kept before a restart; IDR: the shadow dimension s
+  const bool gcr = o.method == 2, idr = o.method == 3;
   const int nblk = die::blas_blocks(n);
   const bool reg = c->regularize != 0;
   const bool defl = c->r > 0;
@@ -1035,10 +1037,49 @@ int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_t
   DIE_TRY(Rr.alloc(dbytes));
   DIE_TRY(Tmp.alloc(dbytes));
   DIE_TRY(Res.alloc(dbytes));
-  if (gcr) {
+  DBuf Sd, VVd, Zd, Wd;  // IDR: shadow space (s x n, shared), v, P^-1 v, a temporary
+  if (gcr || idr) {  // GCR: directions and images; IDR: dU and dR (s columns per right-hand side)
     DIE_TRY(Pd.alloc((size_t)m * dbytes));
     DIE_TRY(Qd.alloc((size_t)m * dbytes));
-  } else {
+  }
+  if (idr) {
+    DIE_TRY(Sd.alloc((size_t)m * n * sizeof(double2)));
+    DIE_TRY(VVd.alloc(dbytes));
+    DIE_TRY(Zd.alloc(dbytes));
+    DIE_TRY(Wd.alloc(dbytes));
+    DIE_TRY(Tv.alloc(dbytes));
+    // the shadow space: s vectors of normal deviates (SplitMix64 and Box-Muller, seed fixed), made
+    // orthonormal by modified Gram-Schmidt on the host
+    std::vector<cd> Sh((size_t)m * n);
+    unsigned long long state = 0x1D5A11CEULL;
+    auto next = [&]() {
+      unsigned long long z = (state += 0x9E3779B97F4A7C15ULL);
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+      z ^= z >> 31;
+      return ((double)(z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    for (auto& v : Sh) {
+      const double u1 = next(), u2 = next(), rr = std::sqrt(-2.0 * std::log(u1));
+      v = cd(rr * std::cos(2.0 * M_PI * u2), rr * std::sin(2.0 * M_PI * u2));
+    }
+    for (int i = 0; i < m; ++i) {
+      cd* vi = Sh.data() + (size_t)i * n;
+      for (int j = 0; j < i; ++j) {
+        const cd* vj = Sh.data() + (size_t)j * n;
+        cd h = 0.0;
+        for (size_t e = 0; e < n; ++e) h += std::conj(vj[e]) * vi[e];
+        for (size_t e = 0; e < n; ++e) vi[e] -= h * vj[e];
+      }
+      double nv = 0.0;
+      for (size_t e = 0; e < n; ++e) nv += std::norm(vi[e]);
+      nv = std::sqrt(nv);
+      for (size_t e = 0; e < n; ++e) vi[e] /= nv;
+    }
+    DIE_HIP(hipMemcpyAsync(Sd.p, Sh.data(), Sh.size() * sizeof(cd), hipMemcpyHostToDevice, st));
+    DIE_HIP(hipStreamSynchronize(st));
+  }
+  if (!gcr && !idr) {
     DIE_TRY(Rh.alloc(dbytes));
     DIE_TRY(Pv.alloc(dbytes));
     DIE_TRY(Vv.alloc(dbytes));
@@ -1049,7 +1090,7 @@ int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_t
       DIE_TRY(Sh.alloc(dbytes));
     }
   }
-  const int nvd = gcr ? m : 1;
+  const int nvd = (gcr || idr) ? m : 1;
   DIE_TRY(part.alloc((size_t)nrhs * nvd * nblk * sizeof(double2)));
   DIE_TRY(partn.alloc((size_t)nrhs * nblk * sizeof(double)));
   DIE_TRY(nrm.alloc((size_t)nrhs * sizeof(double)));
@@ -1099,6 +1140,10 @@ int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_t
       cyc(nrhs, 0), kslot(nrhs, 0), check(nrhs, 1);
   std::vector<double> bnorm(nrhs), relres(nrhs, 1.0), target(nrhs, 0.0), rn(nrhs), best(nrhs, 1e300);
   std::vector<cdv> rho(nrhs, 1.0), alpha(nrhs, 1.0), omega(nrhs, 1.0), d1(nrhs), d2(nrhs);
+  // IDR: per right-hand side the phase (0 .. s-1 the first minimal-residual steps, s + k step k of
+  // a group of s + 1), the oldest difference column, S^H dR (s x s, column-major) and S^H r
+  std::vector<int> phase(nrhs, 0), oldest(nrhs, 0);
+  std::vector<cdv> SdR(idr ? (size_t)nrhs * m * m : 0), Sr(idr ? (size_t)nrhs * m : 0);
   auto set_live = [&](const std::vector<int>& mask) -> int {
     lv = mask;
     return put(livb, lv, st);
@@ -1184,12 +1229,14 @@ int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_t
           rn[r] = sn[r];
           check[r] = 0;
           kslot[r] = 0;
+          phase[r] = 0;
+          oldest[r] = 0;
           rho[r] = alpha[r] = omega[r] = 1.0;
           if (!(sn[r] > 0) || !std::isfinite(sn[r])) {  // the regularized residual vanished
             act[r] = 0;
           }
         }
-        if (!gcr) {  // r^ = R, p = v = 0
+        if (!gcr && !idr) {  // r^ = R, p = v = 0
           DIE_HIP(hipMemcpyAsync(Rh.p, R, dbytes, hipMemcpyDeviceToDevice, st));
           std::vector<double2> z3((size_t)nrhs * 3, make_double2(0.0, 0.0));
           DIE_TRY(put(cf, z3, st));
@@ -1214,7 +1261,207 @@ int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_t
     }
     DIE_TRY(set_live(run));
     const double tiny = 1e-300;
-    if (!gcr) {
+    if (idr) {
+      // the right-hand sides in the lowest phase take one step; the others wait for them
+      int ph = INT32_MAX;
+      for (int r = 0; r < nrhs; ++r)
+        if (run[r]) ph = std::min(ph, phase[r]);
+      for (int r = 0; r < nrhs; ++r) run[r] = run[r] && phase[r] == ph;
+      DIE_TRY(set_live(run));
+      const size_t vs = (size_t)nrhs * n;
+      double2* dU = Pd.as<double2>();
+      double2* dR = Qd.as<double2>();
+      double2* Vp = VVd.as<double2>();
+      double2* Zp = Zd.as<double2>();
+      double2* Wp = Wd.as<double2>();
+      double2* Tp = Tv.as<double2>();
+      const double2* Sp = Sd.as<double2>();
+      std::vector<double2> co((size_t)nrhs * 3, make_double2(0.0, 0.0)), cu((size_t)nrhs * 3, make_double2(0.0, 0.0));
+      auto c3 = [](cdv a) { return make_double2(a.real(), a.imag()); };
+      // dm = S^H x into column `col` of S^H dR (and, with add_r, into S^H r)
+      auto shadow_dots = [&](const double2* x, bool is_dr, const std::vector<int>& col) -> int {
+        DIE_HIP((die::launch_mdot<double, double>(Sp, n, 0, m, nullptr, x, n, n, nrhs, part.as<double2>(), live, st)));
+        DIE_HIP(die::launch_reduce(part.as<double2>(), m, nblk, nrhs, 1.0, nullptr, dv.as<double2>(), live, st));
+        std::vector<double2> h((size_t)nrhs * m);
+        DIE_HIP(hipMemcpyAsync(h.data(), dv.p, h.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+        DIE_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < nrhs; ++r) {
+          if (!run[r]) continue;
+          for (int i = 0; i < m; ++i) {
+            const cdv d(h[(size_t)r * m + i].x, h[(size_t)r * m + i].y);
+            if (is_dr) {
+              SdR[((size_t)r * m + col[r]) * m + i] = d;
+              Sr[(size_t)r * m + i] += d;  // r was updated by this dR
+            } else {
+              Sr[(size_t)r * m + i] = d;
+            }
+          }
+        }
+        return DIE_OK;
+      };
+      if (ph < m) {
+        // minimal-residual step ph: z = P^-1 r, v = M z, omega = (v, r) / (v, v),
+        // dU_ph = omega z, dR_ph = -omega v, u += dU_ph, r += dR_ph
+        const double2* z = R;
+        if (defl) {
+          DIE_TRY(pinv(R, Zp));
+          z = Zp;
+        }
+        DIE_TRY(opM(z, Vp));
+        DIE_TRY(dotsv(Vp, R, d1));
+        DIE_TRY(dotsv(Vp, Vp, d2));
+        for (int r = 0; r < nrhs; ++r) {
+          if (!run[r]) continue;
+          iters[r] += 1;
+          pa[r] += 1;
+          if (reg) par[r] += 1;
+          if (!(d2[r].real() > tiny)) {
+            check[r] = 1;
+            continue;
+          }
+          omega[r] = d1[r] / d2[r];
+          co[3 * r] = c3(omega[r]);
+          cu[3 * r] = c3(-omega[r]);
+        }
+        for (int r = 0; r < nrhs; ++r) run[r] = run[r] && !check[r];
+        DIE_TRY(set_live(run));
+        double2* dUk = dU + (size_t)ph * vs;
+        double2* dRk = dR + (size_t)ph * vs;
+        DIE_TRY(put(cf, co, st));
+        DIE_HIP(die::launch_comb3(dUk, z, nullptr, nullptr, cf.as<double2>(), n, nrhs, live, st));
+        DIE_TRY(put(cf, cu, st));
+        DIE_HIP(die::launch_comb3(dRk, Vp, nullptr, nullptr, cf.as<double2>(), n, nrhs, live, st));
+        std::vector<double2> one3((size_t)nrhs * 3, make_double2(1.0, 0.0));
+        DIE_TRY(put(cf, one3, st));
+        DIE_HIP(die::launch_comb3(u, u, dUk, nullptr, cf.as<double2>(), n, nrhs, live, st));
+        DIE_HIP(die::launch_comb3(R, R, dRk, nullptr, cf.as<double2>(), n, nrhs, live, st));
+        std::vector<int> col(nrhs, ph);
+        // the column of S^H dR; S^H r itself once the s steps are done
+        DIE_HIP((die::launch_mdot<double, double>(Sp, n, 0, m, nullptr, dRk, n, n, nrhs, part.as<double2>(), live,
+                                                  st)));
+        DIE_HIP(die::launch_reduce(part.as<double2>(), m, nblk, nrhs, 1.0, nullptr, dv.as<double2>(), live, st));
+        {
+          std::vector<double2> h((size_t)nrhs * m);
+          DIE_HIP(hipMemcpyAsync(h.data(), dv.p, h.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+          DIE_HIP(hipStreamSynchronize(st));
+          for (int r = 0; r < nrhs; ++r)
+            if (run[r])
+              for (int i = 0; i < m; ++i)
+                SdR[((size_t)r * m + ph) * m + i] = cdv(h[(size_t)r * m + i].x, h[(size_t)r * m + i].y);
+        }
+        if (ph == m - 1) DIE_TRY(shadow_dots(R, false, col));
+        for (int r = 0; r < nrhs; ++r)
+          if (run[r]) phase[r] = ph + 1;
+      } else {
+        const int k = ph - m;  // step k of the group
+        // c = (S^H dR)^-1 S^H r per right-hand side (host, s x s)
+        std::vector<double2> negc((size_t)nrhs * m, make_double2(0.0, 0.0));
+        for (int r = 0; r < nrhs; ++r) {
+          if (!run[r]) continue;
+          die::la::Mat Mm(m, m), Mi;
+          for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) Mm(i, j) = SdR[((size_t)r * m + j) * m + i];
+          if (!die::la::inverse(Mm, Mi)) {
+            check[r] = 1;
+            continue;
+          }
+          for (int i = 0; i < m; ++i) {
+            cdv ci = 0.0;
+            for (int j = 0; j < m; ++j) ci += Mi(i, j) * Sr[(size_t)r * m + j];
+            if (!std::isfinite(ci.real()) || !std::isfinite(ci.imag())) {
+              check[r] = 1;
+              break;
+            }
+            negc[(size_t)r * m + i] = c3(-ci);
+          }
+        }
+        for (int r = 0; r < nrhs; ++r) run[r] = run[r] && !check[r];
+        DIE_TRY(set_live(run));
+        DIE_TRY(put(dv, negc, st));
+        // v = r - dR c; z = P^-1 v; W = -dU c
+        DIE_HIP((die::launch_maxpy<double, double, double>(0, dR, vs, n, m, nullptr, dv.as<double2>(), m, R, n, 1.0,
+                                                           Vp, n, 0.0, n, nrhs, nullptr, nullptr, live, st)));
+        const double2* z = Vp;
+        if (defl) {
+          DIE_TRY(pinv(Vp, Zp));
+          z = Zp;
+        }
+        DIE_HIP((die::launch_maxpy<double, double, double>(0, dU, vs, n, m, nullptr, dv.as<double2>(), m, nullptr, n,
+                                                           0.0, Wp, n, 0.0, n, nrhs, nullptr, nullptr, live, st)));
+        std::vector<int> col(nrhs, 0);
+        for (int r = 0; r < nrhs; ++r) col[r] = oldest[r];
+        // the oldest column of every running right-hand side (they share the phase, not always
+        // the column): written through per-right-hand-side masks, one column index at a time
+        for (int oc = 0; oc < m; ++oc) {
+          std::vector<int> sel(nrhs, 0);
+          int ns = 0;
+          for (int r = 0; r < nrhs; ++r)
+            if (run[r] && oldest[r] == oc) {
+              sel[r] = 1;
+              ++ns;
+            }
+          if (!ns) continue;
+          DIE_TRY(set_live(sel));
+          double2* dUo = dU + (size_t)oc * vs;
+          double2* dRo = dR + (size_t)oc * vs;
+          if (k == 0) {
+            // t = M z, omega = (t, v) / (t, t); dR_o = (v - r) - omega t; dU_o = W + omega z
+            DIE_TRY(opM(z, Tp));
+            DIE_TRY(dotsv(Tp, Vp, d1));
+            DIE_TRY(dotsv(Tp, Tp, d2));
+            for (int r = 0; r < nrhs; ++r) {
+              if (!sel[r]) continue;
+              iters[r] += 1;
+              pa[r] += 1;
+              if (reg) par[r] += 1;
+              omega[r] = d2[r].real() > tiny ? d1[r] / d2[r] : cdv(0.0);
+              co[3 * r] = make_double2(1.0, 0.0);
+              co[3 * r + 1] = make_double2(-1.0, 0.0);
+              co[3 * r + 2] = c3(-omega[r]);
+              cu[3 * r] = make_double2(1.0, 0.0);
+              cu[3 * r + 1] = c3(omega[r]);
+              cu[3 * r + 2] = make_double2(0.0, 0.0);
+            }
+            DIE_TRY(put(cf, co, st));
+            DIE_HIP(die::launch_comb3(dRo, Vp, R, Tp, cf.as<double2>(), n, nrhs, live, st));
+            DIE_TRY(put(cf, cu, st));
+            DIE_HIP(die::launch_comb3(dUo, Wp, z, nullptr, cf.as<double2>(), n, nrhs, live, st));
+          } else {
+            // dU_o = W + omega z; dR_o = -M dU_o
+            for (int r = 0; r < nrhs; ++r) {
+              if (!sel[r]) continue;
+              iters[r] += 1;
+              pa[r] += 1;
+              if (reg) par[r] += 1;
+              cu[3 * r] = make_double2(1.0, 0.0);
+              cu[3 * r + 1] = c3(omega[r]);
+              cu[3 * r + 2] = make_double2(0.0, 0.0);
+              co[3 * r] = make_double2(-1.0, 0.0);
+            }
+            DIE_TRY(put(cf, cu, st));
+            DIE_HIP(die::launch_comb3(dUo, Wp, z, nullptr, cf.as<double2>(), n, nrhs, live, st));
+            DIE_TRY(opM(dUo, Tp));
+            DIE_TRY(put(cf, co, st));
+            DIE_HIP(die::launch_comb3(dRo, Tp, nullptr, nullptr, cf.as<double2>(), n, nrhs, live, st));
+          }
+          // u += dU_o; r += dR_o; the column of S^H dR and S^H r
+          std::vector<double2> one3((size_t)nrhs * 3, make_double2(1.0, 0.0));
+          DIE_TRY(put(cf, one3, st));
+          DIE_HIP(die::launch_comb3(u, u, dUo, nullptr, cf.as<double2>(), n, nrhs, live, st));
+          DIE_HIP(die::launch_comb3(R, R, dRo, nullptr, cf.as<double2>(), n, nrhs, live, st));
+          std::vector<int> runs = run;
+          run = sel;
+          DIE_TRY(shadow_dots(dRo, true, col));
+          run = runs;
+        }
+        DIE_TRY(set_live(run));
+        for (int r = 0; r < nrhs; ++r) {
+          if (!run[r]) continue;
+          oldest[r] = (oldest[r] + 1) % m;
+          phase[r] = m + (k + 1) % (m + 1);
+        }
+      }
+    } else if (!gcr) {
       // rho1 = (r^, r); p = r + beta (p - omega v)
       DIE_TRY(dotsv(Rh.as<double2>(), R, d1));
       std::vector<double2> co((size_t)nrhs * 3, make_double2(0.0, 0.0));
@@ -2299,9 +2546,12 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
   if (o.mixed < 0 || o.mixed > 2) return fail(DIE_E_INVALID, "mixed must be 0, 1 or 2");
   if (o.mixed == 2 && o.orth != 1) return fail(DIE_E_INVALID, "mixed = 2 (binary16 basis) needs orth = 1");
   if (o.block < 0 || o.block > 2) return fail(DIE_E_INVALID, "block must be 0, 1 or 2");
-  if (o.method < 0 || o.method > 2) return fail(DIE_E_INVALID, "method must be 0 (GMRES), 1 (Bi-CGSTAB) or 2 (GCR)");
+  if (o.method < 0 || o.method > 3)
+    return fail(DIE_E_INVALID, "method must be 0 (GMRES), 1 (Bi-CGSTAB), 2 (GCR) or 3 (IDR(s))");
   if (o.method) {
-    if (o.block || o.mixed) return fail(DIE_E_INVALID, "Bi-CGSTAB and GCR run per right-hand side in FP64 (block = mixed = 0)");
+    if (o.block || o.mixed)
+      return fail(DIE_E_INVALID, "Bi-CGSTAB, GCR and IDR(s) run per right-hand side in FP64 (block = mixed = 0)");
+    if (o.method == 3 && o.restart > 64) return fail(DIE_E_INVALID, "IDR(s): s = restart must be <= 64");
     return alt_solve(c, (const double2*)e_in, (double2*)e_tot, nrhs, o, info, st);
   }
   if (o.block) {

@@ -1,8 +1,9 @@
-"""Pins of the oracle's Bi-CGSTAB and GCR (oracle/krylov.py), which the GPU solvers are checked
-against: SciPy's Bi-CGSTAB (the same algorithm) produces the same iterates; finite termination
-on a matrix with few distinct eigenvalues; GCR with every direction kept has full GMRES's
-minimal residuals; restarted GCR never increases the residual; right preconditioning solves the
-original system."""
+"""Pins of the oracle's Bi-CGSTAB, GCR and IDR(s) (oracle/krylov.py), which the GPU solvers are
+checked against: SciPy's Bi-CGSTAB (the same algorithm) produces the same iterates; finite
+termination on a matrix with few distinct eigenvalues; GCR with every direction kept has full
+GMRES's minimal residuals; restarted GCR never increases the residual; IDR(s) terminates within
+n + n/s operator applications (the IDR theorem); right preconditioning solves the original
+system."""
 import numpy as np
 import pytest
 
@@ -59,4 +60,27 @@ def test_right_preconditioning_solves_the_original_system(solver):
     rng = np.random.default_rng(5)
     Pinv = np.eye(60) + 0.1 * (rng.standard_normal((60, 60)) + 1j * rng.standard_normal((60, 60))) / np.sqrt(60)
     x, _, _ = getattr(krylov, solver)(A, b, tol=1e-12, maxiter=400, prec=lambda v: Pinv @ v)
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("s", [2, 3, 4, 6])
+def test_idrs_terminates_within_n_plus_n_over_s(s):
+    # the IDR theorem (Sonneveld and van Gijzen): the residual spaces shrink by s dimensions every
+    # s + 1 steps, so in exact arithmetic IDR(s) reaches the zero residual within n + n / s
+    # applications of the operator; on a well-conditioned matrix rounding does not delay it
+    rng = np.random.default_rng(12 * 10 + s)
+    n = 12
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 6.0 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, hist, apps = krylov.idrs(A, b, s=s, tol=0.0, maxiter=n + n // s)
+    assert apps == n + n // s
+    assert hist[-1] <= 1e-9 * np.linalg.norm(b) and np.linalg.norm(A @ x - b) <= 1e-9 * np.linalg.norm(b)
+    assert hist[n // 2] > 1e-6 * np.linalg.norm(b)  # and not by accident much earlier
+
+
+def test_idrs_converges_with_a_right_preconditioner():
+    A, b = _matrix(seed=7, shift=3.0)
+    rng = np.random.default_rng(8)
+    Pinv = np.eye(60) + 0.1 * (rng.standard_normal((60, 60)) + 1j * rng.standard_normal((60, 60))) / np.sqrt(60)
+    x, hist, apps = krylov.idrs(A, b, s=4, tol=1e-12, maxiter=400, prec=lambda v: Pinv @ v)
     assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
