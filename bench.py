@@ -346,9 +346,9 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
     from synth import workload, plane_wave, plane_wave_te3, plane_wave_tm, centred_grid, cylinder
     from paper_1104_4263_amd import Solver
 
-    def run(g, e, b, reg, k, restart, cap, mixed, seed=1, memory=None, **kw):
-        """k = -1: automatic deflation size; memory: restart = memory - r (fair memory); kw: the
-        system (polarization, magnetic)."""
+    def run(g, e, b, reg, k, restart, cap, mixed, seed=1, memory=None, method="gmres", **kw):
+        """k = -1: automatic deflation size; memory: restart = memory - r (fair memory); method:
+        the Krylov solver; kw: the system (polarization, magnetic)."""
         t0 = time.perf_counter()
         sv = Solver.from_grid(g, e, regularize=reg, deflate_k=k, seed=seed, **kw)
         torch.cuda.synchronize()
@@ -358,7 +358,7 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
             k = int((ritz.abs() > 0).sum())
             if memory is not None:
                 restart = max(memory - k, 5)
-        _, rc, inf = sv.solve(b, restart=restart, max_iters=cap, tol=TOL, mixed=mixed)
+        _, rc, inf = sv.solve(b, restart=restart, max_iters=cap, tol=TOL, mixed=mixed, method=method)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         sv.close()
@@ -437,6 +437,70 @@ def method_variants(cap_reg=24000, long_k=(20, 40)):
         res["A P^-1, automatic r"] = run(gs, es, btm, False, -1, 0, MAX_ITERS, False, memory=40, polarization="tm")
         log(f"TM square eps = {label} automatic r: {res['A P^-1, automatic r']}")
         out[f"Table 1 square (TM), eps = {label} (61^2 nodes)"] = res
+    # the Conclusions' alternatives to restarted GMRES on the regularized, deflated system (Table 2's
+    # r; GMRES and GCR with the table's restart, Bi-CGSTAB, IDR(4)); iters count applications of M
+    for label, es in zip(PAPER_TABLE2, ws["eps"]):
+        r, restart, _ = PAPER_TABLE2[label]["A_R A P^-1"]
+        res = {}
+        for meth, rs in (("gmres", restart), ("bicgstab", restart), ("gcr", restart), ("idrs", 4)):
+            res[meth] = run(gs, es, bs, True, r, rs, cap_reg, False, method=meth)
+            log(f"square eps = {label} A_R A P^-1 {meth}: {res[meth]}")
+        out[f"Krylov solvers on A_R A P^-1, Table 2 square eps = {label}"] = res
+    out["spectra (Figs. 2 and 3), Table 2 squares at 21^2 nodes"] = spectra_summary()
+    return out
+
+
+def spectra_summary(nodes=21):
+    """Eigenvalues of A (TE and TM) and of A_R A (TE) for the three squares of Table 2 on a coarse
+    grid, summarised as the paper reads its Figs. 2 and 3: the share of eigenvalues on the far
+    three quarters of the dense segments [1, eps] (for A_R A their images under eq.
+    EigenvaluesArA; a TM spectrum only accumulates at 1), the largest magnitude and the number
+    beyond Section 5's deflation radius."""
+    import numpy as np
+    from synth import workload
+    from paper_1104_4263_amd import Solver, die_te_deflation_radius
+    ws = workload("paper_squares", nodes=nodes)
+    g = ws["grids"][0]
+    out = {}
+
+    def near(lam, segs, tol):
+        """share of lam within tol of the polyline segs, beyond its first quarter (by length)"""
+        lens = np.array([abs(b - a) for a, b in segs])
+        start = np.concatenate([[0.0], np.cumsum(lens)[:-1]])
+        total = max(float(lens.sum()), 1e-300)
+        hit = np.zeros(lam.shape, dtype=bool)
+        for (a, b), s0, ln in zip(segs, start, lens):
+            t = np.clip(((lam - a) * np.conj(b - a)).real / max(ln ** 2, 1e-300), 0.0, 1.0)
+            hit |= (np.abs(lam - (a + t * (b - a))) <= tol) & ((s0 + t * ln) >= 0.25 * total)
+        return float(np.mean(hit))
+
+    for label, es in zip(PAPER_TABLE2, ws["eps"]):
+        vals = np.unique(np.round(es[es != 1.0], 12))
+        res = {}
+        for pol, reg, which in (("te", False, "A"), ("te", True, "ARA"), ("tm", False, "A")):
+            t0 = time.perf_counter()
+            sv = Solver.from_grid(g, es, regularize=reg, polarization=pol)
+            lam = sv.spectrum(which)
+            sv.close()
+            segs = []
+            for e in vals:
+                if which == "ARA":  # the image of [1, e] under lam -> (1 + (1 - lam) / e) lam, as a polyline
+                    t = np.linspace(0.0, 1.0, 65)
+                    pts = 1.0 + t * (e - 1.0)
+                    pts = (1.0 + (1.0 - pts) / e) * pts
+                    segs += list(zip(pts[:-1], pts[1:]))
+                else:
+                    segs.append((1.0 + 0j, complex(e)))
+            scale = max(1.0, max(abs(e - 1.0) for e in vals))
+            radius = die_te_deflation_radius(es, reg) if pol == "te" else 1.0
+            key = f"{'TE' if pol == 'te' else 'TM'} {which}"
+            res[key] = {"unknowns": int(lam.size), "max_abs": round(float(np.abs(lam).max()), 4),
+                        "share_on_segments": round(near(lam, segs, 0.02 * scale), 4),
+                        "deflation_radius": round(float(radius), 4),
+                        "beyond_radius": int(np.sum(np.abs(lam) > radius * (1 + 1e-9))),
+                        "seconds": round(time.perf_counter() - t0, 2)}
+            log(f"spectrum square eps = {label} {key}: {res[key]}")
+        out[f"eps = {label}"] = res
     return out
 
 
