@@ -169,6 +169,9 @@ typedef struct {
   int products_AR;     /* applications of A_R */
   int cycles;          /* GMRES cycles = FP64 residual refinements */
   double rel_res_true; /* final ||b - A u|| / ||b|| evaluated in FP64 */
+  int finish_iters;    /* of iters, those run by the FP64 block cycles that finish a right-hand side
+                          whose complex64 block cycles stalled (block = 2 or block = 1 with
+                          mixed = 1); 0 otherwise */
 } die_te_solve_info;
 
 /* Build a context for one object: copies eps_r, evaluates the Green tensor on all

@@ -45,7 +45,8 @@ class DieTeSolveOpts(ctypes.Structure):
 
 class DieTeSolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("products_A", ctypes.c_int),
-                ("products_AR", ctypes.c_int), ("cycles", ctypes.c_int), ("rel_res_true", ctypes.c_double)]
+                ("products_AR", ctypes.c_int), ("cycles", ctypes.c_int), ("rel_res_true", ctypes.c_double),
+                ("finish_iters", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

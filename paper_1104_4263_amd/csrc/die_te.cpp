@@ -976,6 +976,7 @@ int gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die
       info[r].products_AR = par[r];
       info[r].cycles = cycles[r];
       info[r].rel_res_true = relres[r];
+      info[r].finish_iters = 0;
     }
   }
   if (rc == DIE_E_BREAKDOWN) return fail(DIE_E_BREAKDOWN, "GMRES met a non-finite value");
@@ -1631,6 +1632,7 @@ int alt_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, const die_t
       info[r].products_AR = par[r];
       info[r].cycles = cyc[r];
       info[r].rel_res_true = relres[r];
+      info[r].finish_iters = 0;
     }
   }
   if (rc == DIE_E_BREAKDOWN) return fail(DIE_E_BREAKDOWN, "Krylov solver met a non-finite value");
@@ -1917,6 +1919,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
       info[r].products_AR = par[r];
       info[r].cycles = cycles[r];
       info[r].rel_res_true = relres[r];
+      info[r].finish_iters = 0;
     }
   };
   if (only)
@@ -2589,6 +2592,7 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
           i32[r].products_AR += i64[r].products_AR;
           i32[r].cycles += i64[r].cycles;
           i32[r].rel_res_true = i64[r].rel_res_true;
+          i32[r].finish_iters = i64[r].iters;
         }
       } else {
         for (int r = 0; r < nrhs; ++r)

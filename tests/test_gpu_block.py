@@ -224,3 +224,29 @@ def test_block_option_validation():
         s.solve(b, block=2, mixed=0)
     with pytest.raises(DieTeError):
         s.solve(b, block=3, mixed=1)
+
+
+@pytest.mark.parametrize("block", [1, 2])
+def test_mixed_block_fp64_finish_of_stalled_rhs(block):
+    """Restarted GMRES(6) on an eps = 9 cylinder: an early cycle gains under 10% (restart
+    stagnation, in any precision), so the complex64 block cycles hand the right-hand side to the
+    FP64 finish, which converges (about 1200 steps, as the FP64 solvers alone); the result
+    matches dense LU."""
+    say(f"FP64 finish of a stalled complex64 block solve, block={block}")
+    g = centred_grid(24, 1.0, ny=20)
+    eps = cylinder(g, 0.35, 9.0 + 0j)
+    b = plane_wave(g, 0.3)[None]
+    u_lu = op.solve_dense(g, eps, b)
+    s = api.Solver.from_grid(g, eps)
+    u, rc, info = s.solve(dev(b), restart=6, max_iters=6000, tol=1e-8, mixed=1, block=block,
+                          orth=0 if block == 2 else 1)
+    say(f"  iters {info[0]['iters']}, FP64 finish {info[0]['finish_iters']}, cycles {info[0]['cycles']}")
+    assert rc == 0 and info[0]["status"] == 0
+    assert 0 < info[0]["finish_iters"] < info[0]["iters"]
+    assert info[0]["rel_res_true"] <= 1e-8
+    assert op.relative_residual(g, eps, host(u)[0], b[0]) <= 1.02e-8
+    assert rel(host(u)[0], u_lu[0]) < 2e-5
+    # a solve that converges without stalling reports no FP64 finish
+    _, rc2, info2 = s.solve(dev(b), restart=30, max_iters=6000, tol=1e-8, mixed=1, block=block,
+                            orth=0 if block == 2 else 1)
+    assert rc2 == 0 and info2[0]["finish_iters"] == 0

@@ -69,3 +69,33 @@ def test_solve_batch_validates_before_any_gpu_call():
     nul = (vp * 2)(vp(16), None)
     assert lib.die_te_solve_batch(nul, 2, dummy, dummy, one, ctypes.byref(o), None, None) == _lib.DIE_E_INVALID
     assert b"null" in lib.die_te_last_error()
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's mirrors of the header's structs have the C layout (size and every field
+    offset), measured by a C program compiled against include/die_te.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("die_te_grid", _lib.DieTeGrid), ("die_te_setup_opts", _lib.DieTeSetupOpts),
+             ("die_te_solve_opts", _lib.DieTeSolveOpts), ("die_te_solve_info", _lib.DieTeSolveInfo),
+             ("die_te_plan", _lib.DieTePlan)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "die_te.h"', 'int main(void) {']
+    for cname, py in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
