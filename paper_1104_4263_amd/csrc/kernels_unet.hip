@@ -162,6 +162,138 @@ k_conv_wgrad(const bf16raw* __restrict__ dZ, int ldz, const bf16raw* __restrict_
   }
 }
 
+// Weight and bias gradients with the pixel chunks staged in LDS (W % 32 == 0).
+// Block: 64 output channels (two 32-row tiles) x 32 input channels x every tap over one split of
+// the pixels, one wave per tap.  Each chunk of 32 consecutive pixels (one image row) is stored
+// transposed: dZ as [co][pixel] and, for each tap, the input shifted by that tap as [ci][pixel],
+// so that each MFMA operand (8 consecutive pixels of one channel) is one 16-byte LDS read.  The
+// next chunk's global loads are in flight while the current one is multiplied.  Blocks of the
+// first input-channel tile also sum dZ over the pixels (the bias gradient).
+constexpr int kWgPx = 32;         // pixels per chunk
+constexpr int kWgLd = kWgPx + 8;  // LDS row stride in bf16 (80 bytes: the 16-byte reads of 8 rows hit distinct banks)
+
+template <int NTAPS>
+__global__ void __launch_bounds__(64 * NTAPS)
+k_conv_wgrad_lds(const bf16raw* __restrict__ dZ, int ldz, const bf16raw* __restrict__ X, int H, int W, int cin,
+                 int cout, long M, long pps, float* __restrict__ part, float* __restrict__ bpart) {
+  constexpr int NTH = 64 * NTAPS;
+  constexpr int NR = NTAPS == 9 ? 3 : 1;       // input rows per chunk (dy = -1, 0, 1)
+  constexpr int NQ = NTAPS == 9 ? 34 : 32;     // input pixels per row (dx halo)
+  constexpr int QOFF = NTAPS == 9 ? 1 : 0;
+  constexpr int ZITEMS = 64 / 8 * kWgPx;       // 16-byte loads of the dZ chunk
+  constexpr int XITEMS = NR * NQ * 4;          // 16-byte loads of the input rows (4 groups of 8 channels)
+  constexpr int IZ = (ZITEMS + NTH - 1) / NTH, IX = (XITEMS + NTH - 1) / NTH;
+  __shared__ __attribute__((aligned(16))) bf16raw sZ[2][64 * kWgLd];
+  __shared__ __attribute__((aligned(16))) bf16raw sX[2][NTAPS * 32 * kWgLd];
+  __shared__ float sB[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, r32 = lane & 31;
+  const int c0 = blockIdx.x * 32, co0 = blockIdx.y * 64;
+  const long pbeg = (long)blockIdx.z * pps, pend = min(M, pbeg + pps);
+  const bool do_bias = bpart != nullptr && blockIdx.x == 0;
+  const long HW = (long)H * W;
+
+  u32x4 rz[IZ], rx[IX];
+  auto load = [&](long p0) {
+    const long bimg = p0 / HW;
+    const int y = (int)((p0 / W) % H), x0 = (int)(p0 % W);
+#pragma unroll
+    for (int k = 0; k < IZ; ++k) {
+      const int i = tid + k * NTH;
+      const int px = i & (kWgPx - 1), co = co0 + 8 * (i / kWgPx);
+      rz[k] = u32x4{0u, 0u, 0u, 0u};
+      if (i < ZITEMS && co < cout) rz[k] = *reinterpret_cast<const u32x4*>(dZ + (size_t)(p0 + px) * ldz + co);
+    }
+#pragma unroll
+    for (int k = 0; k < IX; ++k) {
+      const int i = tid + k * NTH;
+      const int grp = i & 3, rest = i >> 2, qi = rest % NQ, r = rest / NQ;
+      const int yy = y + r - (NR == 3 ? 1 : 0), xx = x0 + qi - QOFF, ci = c0 + 8 * grp;
+      rx[k] = u32x4{0u, 0u, 0u, 0u};
+      if (i < XITEMS && yy >= 0 && yy < H && xx >= 0 && xx < W && ci < cin)
+        rx[k] = *reinterpret_cast<const u32x4*>(X + ((size_t)bimg * HW + (size_t)yy * W + xx) * cin + ci);
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < IZ; ++k) {
+      const int i = tid + k * NTH;
+      if (i >= ZITEMS) continue;
+      const int px = i & (kWgPx - 1), row = 8 * (i / kWgPx);
+      const uint32_t w4[4] = {rz[k].x, rz[k].y, rz[k].z, rz[k].w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sZ[buf][(row + e) * kWgLd + px] = (bf16raw)(w4[e >> 1] >> (16 * (e & 1)));
+    }
+#pragma unroll
+    for (int k = 0; k < IX; ++k) {
+      const int i = tid + k * NTH;
+      if (i >= XITEMS) continue;
+      const int grp = i & 3, rest = i >> 2, qi = rest % NQ, r = rest / NQ, q = qi - QOFF;
+      const uint32_t w4[4] = {rx[k].x, rx[k].y, rx[k].z, rx[k].w};
+#pragma unroll
+      for (int dx = -QOFF; dx <= QOFF; ++dx) {
+        const int j = q - dx;  // position of input pixel q in the copy shifted by dx
+        if (j < 0 || j >= kWgPx) continue;
+        const int t = NTAPS == 9 ? r * 3 + dx + 1 : 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          sX[buf][(t * 32 + 8 * grp + e) * kWgLd + j] = (bf16raw)(w4[e >> 1] >> (16 * (e & 1)));
+      }
+    }
+  };
+
+  floatx16 acc0, acc1;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = 0.f;
+  float bsum = 0.f;
+  if (pbeg < pend) {
+    load(pbeg);
+    put(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (long p0 = pbeg; p0 < pend; p0 += kWgPx, buf ^= 1) {
+    const bool more = p0 + kWgPx < pend;
+    if (more) load(p0 + kWgPx);
+#pragma unroll
+    for (int s = 0; s < kWgPx / 16; ++s) {
+      const int k0 = 16 * s + 8 * g;
+      const u32x4 a0 = *reinterpret_cast<const u32x4*>(&sZ[buf][r32 * kWgLd + k0]);
+      const u32x4 a1 = *reinterpret_cast<const u32x4*>(&sZ[buf][(32 + r32) * kWgLd + k0]);
+      const u32x4 bv = *reinterpret_cast<const u32x4*>(&sX[buf][(wave * 32 + r32) * kWgLd + k0]);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a0), as_bf16x8(bv), acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a1), as_bf16x8(bv), acc1, 0, 0, 0);
+    }
+    if (do_bias) {
+      // row tid % 64, pixels 8 (tid / 64) .. + 7 (threads beyond 256 idle; 64-thread blocks loop)
+      for (int qq = tid >> 6; qq < 4; qq += NTH / 64) {
+        const u32x4 v = *reinterpret_cast<const u32x4*>(&sZ[buf][(tid & 63) * kWgLd + 8 * qq]);
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum += bf2f((bf16raw)(w4[e >> 1] >> (16 * (e & 1))));
+      }
+    }
+    if (more) put(buf ^ 1);
+    __syncthreads();
+  }
+  const int N = NTAPS * cin, col = c0 + r32;
+  if (col < cin) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = co0 + (i / 4) * 8 + g * 4 + (i % 4);
+      if (row < cout) part[((size_t)blockIdx.z * cout + row) * N + wave * cin + col] = acc0[i];
+      if (row + 32 < cout) part[((size_t)blockIdx.z * cout + row + 32) * N + wave * cin + col] = acc1[i];
+    }
+  }
+  if (do_bias) {
+    if (tid < 256) sB[tid >> 6][tid & 63] = bsum;
+    if (NTH == 64)
+      for (int qq = 1; qq < 4; ++qq) sB[qq][tid] = 0.f;
+    __syncthreads();
+    if (tid < 64 && co0 + tid < cout)
+      bpart[(size_t)blockIdx.z * cout + co0 + tid] = (sB[0][tid] + sB[1][tid]) + (sB[2][tid] + sB[3][tid]);
+  }
+}
+
 __global__ void __launch_bounds__(NT)
 k_bias_grad(const bf16raw* __restrict__ dZ, int ldz, long npix, int cout, long pps, float* __restrict__ part) {
   const long pbeg = (long)blockIdx.x * pps, pend = std::min(npix, pbeg + pps);
@@ -172,12 +304,23 @@ k_bias_grad(const bf16raw* __restrict__ dZ, int ldz, long npix, int cout, long p
   }
 }
 
+// Block: 32 consecutive outputs x 8 groups of splits (group q sums splits q, q + 8, ... in
+// order), then the 8 group sums in order.
+constexpr int kRedJ = 32, kRedG = NT / kRedJ;
 __global__ void __launch_bounds__(NT)
 k_reduce_splits(const float* __restrict__ part, int nsplit, size_t count, float* __restrict__ out) {
-  for (size_t j = (size_t)blockIdx.x * NT + threadIdx.x; j < count; j += (size_t)gridDim.x * NT) {
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * count + j];
-    out[j] = s;
+  __shared__ float red[kRedG][kRedJ];
+  const int jj = threadIdx.x % kRedJ, q = threadIdx.x / kRedJ;
+  const size_t j = (size_t)blockIdx.x * kRedJ + jj;
+  float s = 0.f;
+  if (j < count)
+    for (int k = q; k < nsplit; k += kRedG) s += part[(size_t)k * count + j];
+  red[q][jj] = s;
+  __syncthreads();
+  if (q == 0 && j < count) {
+    float t = red[0][jj];
+    for (int k = 1; k < kRedG; ++k) t += red[k][jj];
+    out[j] = t;
   }
 }
 
@@ -222,19 +365,22 @@ k_pool_grad_add(const float* __restrict__ dY, float* __restrict__ dX, int B, int
   }
 }
 
+// Eight channels (16 bytes) per thread; cl and cs are multiples of 8.
 __global__ void __launch_bounds__(NT)
 k_upcat(const bf16raw* __restrict__ low, const bf16raw* __restrict__ skip, bf16raw* __restrict__ cat, int B, int H,
         int W, int cl, int cs) {
-  const int C = cl + cs;
-  const size_t count = (size_t)B * H * W * C;
+  const int C8 = (cl + cs) / 8, cl8 = cl / 8;
+  const size_t count = (size_t)B * H * W * C8;
   for (size_t j = (size_t)blockIdx.x * NT + threadIdx.x; j < count; j += (size_t)gridDim.x * NT) {
-    const int c = (int)(j % C);
-    const size_t pix = j / C;
+    const int c8 = (int)(j % C8);
+    const size_t pix = j / C8;
     const int x = (int)(pix % W);
     size_t q = pix / W;
     const int y = (int)(q % H);
     const size_t b = q / H;
-    cat[j] = c < cl ? low[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * cl + c] : skip[pix * cs + (c - cl)];
+    const bf16raw* src = c8 < cl8 ? low + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * cl + 8 * c8
+                                  : skip + pix * cs + 8 * (c8 - cl8);
+    reinterpret_cast<u32x4*>(cat)[j] = *reinterpret_cast<const u32x4*>(src);
   }
 }
 
@@ -418,11 +564,42 @@ static void wgrad_shape(long M, int cout, int N, long* pps, int* nsplit) {
   *nsplit = (int)((M + *pps - 1) / *pps);
 }
 
+// Splits of the LDS-staged gradient kernel: about 1024 blocks, at most 256 splits and at most
+// kWgLdsPartFloats partial values (one split per 32-pixel chunk at most).
+constexpr long kWgLdsPartFloats = 8l << 20;
+static long wgrad_lds_splits(int cout, int taps, int cin) {
+  const long tiles = (long)((cin + 31) / 32) * ((cout + 63) / 64);
+  long s = std::max<long>(1, 1024 / tiles);
+  s = std::min<long>(s, 256);
+  return std::max<long>(1, std::min<long>(s, kWgLdsPartFloats / ((long)cout * taps * cin)));
+}
+
 size_t conv_wgrad_max_floats(int cout, int taps, int cin) {
   const int N = taps * cin;
   const long tiles = (long)((cout + 31) / 32) * ((N + 31) / 32);
   const long ns = std::max<long>(1, kWgradBlocks / std::max<long>(tiles, 1));
-  return (size_t)ns * cout * N;
+  return (size_t)std::max(ns, wgrad_lds_splits(cout, taps, cin)) * cout * N;
+}
+
+bool conv_wgrad_bias_fused(int W, int ldz, int cout) { return W % kWgPx == 0 && ldz % 8 == 0 && ldz >= cout; }
+
+hipError_t launch_conv_wgrad_bias(const bf16raw* dZ, int ldz, const bf16raw* X, int B, int H, int W, int cin,
+                                  int taps, int cout, float* part, float* bpart, int* nsplit, hipStream_t st) {
+  if (!conv_wgrad_bias_fused(W, ldz, cout) || (taps != 1 && taps != 9) || cin < 8 || cin % 8 || cout < 1 || B < 1 ||
+      H < 1)
+    return hipErrorInvalidValue;
+  const long M = (long)B * H * W;
+  const long chunks = M / kWgPx;
+  const long s = std::min(wgrad_lds_splits(cout, taps, cin), chunks);
+  const long pps = (chunks + s - 1) / s * kWgPx;
+  *nsplit = (int)((M + pps - 1) / pps);
+  dim3 grid((unsigned)((cin + 31) / 32), (unsigned)((cout + 63) / 64), (unsigned)*nsplit);
+  if (taps == 9)
+    hipLaunchKernelGGL(k_conv_wgrad_lds<9>, grid, dim3(64 * 9), 0, st, dZ, ldz, X, H, W, cin, cout, M, pps, part,
+                       bpart);
+  else
+    hipLaunchKernelGGL(k_conv_wgrad_lds<1>, grid, dim3(64), 0, st, dZ, ldz, X, H, W, cin, cout, M, pps, part, bpart);
+  return hipGetLastError();
 }
 
 hipError_t launch_conv_wgrad(const bf16raw* dZ, int ldz, const bf16raw* X, int B, int H, int W, int cin, int taps,
@@ -444,7 +621,9 @@ hipError_t launch_bias_grad(const bf16raw* dZ, int ldz, long npix, int cout, flo
 }
 
 hipError_t launch_reduce_splits(const float* part, int nsplit, size_t count, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_splits, dim3(blocks_for(count, NT)), dim3(NT), 0, st, part, nsplit, count, out);
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((count + kRedJ - 1) / kRedJ)), dim3(NT), 0, st, part, nsplit,
+                     count, out);
   return hipGetLastError();
 }
 
@@ -469,8 +648,8 @@ hipError_t launch_pool_grad_add(const float* dY, float* dX, int B, int H, int W,
 
 hipError_t launch_upcat(const bf16raw* low, const bf16raw* skip, bf16raw* cat, int B, int H, int W, int cl, int cs,
                         hipStream_t st) {
-  if (H % 2 || W % 2) return hipErrorInvalidValue;
-  const size_t count = (size_t)B * H * W * (cl + cs);
+  if (H % 2 || W % 2 || cl % 8 || cs % 8) return hipErrorInvalidValue;
+  const size_t count = (size_t)B * H * W * ((cl + cs) / 8);
   hipLaunchKernelGGL(k_upcat, dim3(blocks_for(count, NT * 4)), dim3(NT), 0, st, low, skip, cat, B, H, W, cl, cs);
   return hipGetLastError();
 }

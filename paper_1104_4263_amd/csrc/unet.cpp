@@ -113,12 +113,19 @@ int layer_backward(die_te_unet* n, const Layer& ly, const bf16raw* dz, int ldz, 
                    float* gx, ConvOut mode, hipStream_t st) {
   int ns = 0;
   float* g = n->grad.as<float>();
-  DIE_HIP(launch_conv_wgrad(dz, ldz, X, B, H, W, ly.cin, ly.taps, ly.cout, n->wpart.as<float>(), &ns, st));
-  DIE_HIP(launch_reduce_splits(n->wpart.as<float>(), ns, (size_t)ly.cout * ly.taps * ly.cin, g + ly.woff, st));
-  const long npix = (long)B * H * W;
-  const int nsb = (int)std::min<long>(256, std::max<long>(1, npix / 256));
-  DIE_HIP(launch_bias_grad(dz, ldz, npix, ly.cout, n->bpart.as<float>(), nsb, st));
-  DIE_HIP(launch_reduce_splits(n->bpart.as<float>(), nsb, (size_t)ly.cout, g + ly.boff, st));
+  if (conv_wgrad_bias_fused(W, ldz, ly.cout)) {
+    DIE_HIP(launch_conv_wgrad_bias(dz, ldz, X, B, H, W, ly.cin, ly.taps, ly.cout, n->wpart.as<float>(),
+                                   n->bpart.as<float>(), &ns, st));
+    DIE_HIP(launch_reduce_splits(n->wpart.as<float>(), ns, (size_t)ly.cout * ly.taps * ly.cin, g + ly.woff, st));
+    DIE_HIP(launch_reduce_splits(n->bpart.as<float>(), ns, (size_t)ly.cout, g + ly.boff, st));
+  } else {
+    DIE_HIP(launch_conv_wgrad(dz, ldz, X, B, H, W, ly.cin, ly.taps, ly.cout, n->wpart.as<float>(), &ns, st));
+    DIE_HIP(launch_reduce_splits(n->wpart.as<float>(), ns, (size_t)ly.cout * ly.taps * ly.cin, g + ly.woff, st));
+    const long npix = (long)B * H * W;
+    const int nsb = (int)std::min<long>(256, std::max<long>(1, npix / 256));
+    DIE_HIP(launch_bias_grad(dz, ldz, npix, ly.cout, n->bpart.as<float>(), nsb, st));
+    DIE_HIP(launch_reduce_splits(n->bpart.as<float>(), nsb, (size_t)ly.cout, g + ly.boff, st));
+  }
   if (gx)
     DIE_HIP(launch_conv(dz, B, H, W, ldz, ly.taps, true, ly.wbd.as<bf16raw>(), nullptr, false, gx, ly.cin, mode, st));
   return DIE_OK;

@@ -29,6 +29,12 @@ size_t conv_wgrad_max_floats(int cout, int taps, int cin);
 // dZ rows have ldz >= cout entries.
 hipError_t launch_conv_wgrad(const bf16raw* dZ, int ldz, const bf16raw* X, int B, int H, int W, int cin, int taps,
                              int cout, float* part, int* nsplit, hipStream_t st);
+// The same partials and the bias gradient partials bpart[s][co] = sum over the pixels of split
+// s of dZ[p][co] in one kernel that stages 32-pixel chunks in LDS; needs W % 32 == 0 and
+// ldz % 8 == 0 (conv_wgrad_bias_fused).  bpart holds at least 256 cout floats.
+bool conv_wgrad_bias_fused(int W, int ldz, int cout);
+hipError_t launch_conv_wgrad_bias(const bf16raw* dZ, int ldz, const bf16raw* X, int B, int H, int W, int cin,
+                                  int taps, int cout, float* part, float* bpart, int* nsplit, hipStream_t st);
 // Bias gradient partials: part[s][co] = sum over the pixels of split s of dZ[p][co].
 hipError_t launch_bias_grad(const bf16raw* dZ, int ldz, long npix, int cout, float* part, int nsplit, hipStream_t st);
 // out[j] = sum_s part[s][j] for j < count (fixed order).
