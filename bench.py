@@ -24,7 +24,8 @@ plain baseline both solve the undeflated system A.
 Reported next to it: the plain solver (FP64 products and basis, one right-hand side per
 call, the same GMRES(30) and orthogonalisation, a sample of 16 of the 256 solves), the product throughput at the batched shape and at
 the 1024^2 class (64 fields), the hard-cylinder variants (regularizer, deflation,
-mixed precision) and the FP64 oracle on the host.
+mixed precision), the learned warm start (the stored configured network's guesses, its
+inference inside the timed region, then the same batched solve) and the FP64 oracle on the host.
 
 One JSON line on stdout; progress on stderr.
 """
@@ -184,69 +185,60 @@ def cpu_baseline(g, eps, n_angles):
     return out
 
 
-def learned_run(ntrain, g, eps, B, nsolve, value_batched, iters_batched):
-    """Learned warm start on the headline batch: train the configured U-Net on ntrain solves
-    of fresh random-field objects (one random angle each, solved by the batched solver), then
-    time network guesses + the batched solve from them."""
+def learned_leg(solve, ctxs, Bs, steps, nsolve, value_zero, iters_zero, plain_value):
+    """The configured warm-start network (stored parameters, trained on 20 032 block-solver solves
+    of objects the headline never uses) guessing the headline batch: network inference and the
+    same batched solve from its guesses, timed together over `steps` batches after one warm-up."""
     import numpy as np
     import torch
-    from synth import plane_wave, random_field_object
-    from paper_1104_4263_amd import Solver, UNet
-    rng = np.random.default_rng(100_000)
-    X, T = [], []
-    t0 = time.perf_counter()
-    for c0 in range(0, ntrain, 256):
-        objs = [random_field_object(256, seed=100_000 + i) for i in range(c0, min(ntrain, c0 + 256))]
-        ps = 2 * math.pi * rng.random(len(objs))
-        e = np.stack([o[1] for o in objs])
-        b = torch.from_numpy(np.stack([plane_wave(g, p) for p in ps])).cuda()
-        sv = Solver.from_grid(g, e)
-        u, rc, _ = sv.solve(b, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=True)
-        X.append(UNet.pack_inputs(torch.from_numpy(e).cuda(), b))
-        T.append(UNet.pack_targets(u, b))
-        sv.close()
-        log(f"learned: generated {c0 + len(objs)} / {ntrain} training solves")
-    torch.cuda.synchronize()
-    gen_s = time.perf_counter() - t0
-    X, T = torch.cat(X), torch.cat(T)
-    bsz, epochs = 16, 12
-    net = UNet(4, 32, 256, 256, max_batch=bsz, seed=1)
-    order = np.arange(ntrain)
-    t0 = time.perf_counter()
-    losses = []
-    steps = 0
-    for ep in range(epochs):
-        rng.shuffle(order)
-        for k in range(0, ntrain - bsz + 1, bsz):
-            idx = torch.from_numpy(order[k:k + bsz]).cuda()
-            losses.append(net.train_step(X[idx], T[idx], 5e-4))
-            steps += 1
-        log(f"learned: epoch {ep} loss {np.mean(losses[-(ntrain // bsz):]):.4f}")
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    flops_step = 3 * 21.3e9 * bsz  # forward + two backward GEMMs per layer, 21.3 GFLOP per sample forward
-    # the headline batch from the network's guesses, network inference inside the timed region
-    s = Solver.from_grid(g, eps)
+    from paper_1104_4263_amd import warm_start
+    try:
+        net = warm_start.load_network(max_batch=64)
+    except (FileNotFoundError, ValueError) as e:
+        return {"skipped": str(e)}
+    with open(warm_start.RECORD_PATH) as f:
+        rec = json.load(f)
+
+    def guess_and_solve():
+        x0s = [net.warm_start(c, b) for c, b in zip(ctxs, Bs)]
+        return x0s, solve(x0s)
+
+    guess_and_solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x0 = net.warm_start(s, B)
+    for _ in range(steps):
+        x0s, (us, rc, info) = guess_and_solve()
     torch.cuda.synchronize()
-    inf_s = time.perf_counter() - t0
-    _, rc, info = s.solve(B, x0=x0, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=True)
+    dt = (time.perf_counter() - t0) / steps
+    # inference alone
+    t1 = time.perf_counter()
+    for c, b in zip(ctxs, Bs):
+        net.warm_start(c, b)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    it = np.array([x["iters"] for x in info])
+    inf_s = time.perf_counter() - t1
     ok = rc == 0 and all(x["rel_res_true"] <= TOL for x in info)
-    res = {"value": round(nsolve / dt, 3) if ok else 0.0, "unit": "solves/s", "train_solves": ntrain,
-           "generate_s": round(gen_s, 1), "train_s": round(train_s, 1), "epochs": epochs, "batch": bsz,
-           "train_loss_first_last": [round(losses[0], 4), round(float(np.mean(losses[-(ntrain // bsz):])), 4)],
-           "train_TFLOPs": round(flops_step * steps / train_s / 1e12, 2), "inference_s": round(inf_s, 3),
-           "iters_mean": round(float(it.mean()), 1), "iters_mean_zero_guess": round(float(iters_batched.mean()), 1),
-           "vs_batched": round((nsolve / dt) / value_batched, 3) if ok and value_batched > 0 else None}
-    log(f"learned: {res}")
-    s.close()
+    it = np.array([x["iters"] for x in info])
+    e_net, e_inc = [], []
+    for x0, u, b in zip(x0s, us, Bs):
+        for r in range(b.shape[0]):
+            nu = torch.linalg.vector_norm(u[r]).item()
+            e_net.append(torch.linalg.vector_norm(x0[r] - u[r]).item() / nu)
+            e_inc.append(torch.linalg.vector_norm(b[r] - u[r]).item() / nu)
+    v = nsolve / dt if ok else 0.0
     net.close()
-    return res
+    return {"value": round(v, 3), "unit": "solves/s", "ms_per_step": round(1000.0 * dt, 2),
+            "method": "the headline's batched solver started from the network's guesses (network inference inside "
+                      "the timed region)",
+            "network": rec["network"], "training": {**rec["data"], **{k: rec["training"][k] for k in
+                                                                      ("epochs", "steps", "train_s", "TFLOPs")}},
+            "inference_s": round(inf_s, 4), "iters_mean": round(float(it.mean()), 1), "iters_max": int(it.max()),
+            "iters_mean_zero_guess": round(float(iters_zero.mean()), 1),
+            "iters_max_zero_guess": int(iters_zero.max()),
+            "guess_rel_err_median": round(float(np.median(e_net)), 4),
+            "incident_rel_err_median": round(float(np.median(e_inc)), 4),
+            "rel_res_true_max": max(x["rel_res_true"] for x in info),
+            "vs_zero_guess": round(v / value_zero, 3) if value_zero > 0 else None,
+            "vs_plain": round(v / plain_value, 2) if plain_value else None}
 
 
 SIZE_CLASSES = (128, 256, 512, 1024)  # object o of the batched workload has size class o // 4, seed 1000 + o
@@ -578,9 +570,8 @@ def main():
                     help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
     ap.add_argument("--basis", type=int, default=16, choices=(16, 32),
                     help="bits per real part of the stored Krylov basis in the batched run (16 needs --orth 1)")
-    ap.add_argument("--learned", type=int, default=0, metavar="NTRAIN",
-                    help="train the warm-start U-Net (4 levels, 32 channels) on NTRAIN method-generated 256^2 "
-                         "solves, then time the batch from its guesses (several minutes)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm-start leg (the stored network's guesses + the batched solve)")
     ap.add_argument("--configured-deflation", action="store_true",
                     help="also run the batch with the configured k=16 deflation (about 40 s)")
     ap.add_argument("--product-only", action="store_true",
@@ -645,18 +636,23 @@ def main():
     log(f"setup of {nobj} objects on {g.nx}x{g.ny}: {setup_s:.3f} s")
     timed_ctx = per_obj if concurrent else [s]
 
-    def batch_solve(use_block=block):
+    def batch_solve(use_block=block, x0s=None):
+        """The headline batch (x0s: one initial guess per timed context, else zero); returns the
+        solutions per timed context (None for the per-object contexts unless guesses are given),
+        the code and the records."""
         if use_block and not concurrent:
-            return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
-                           mixed=1 if args.block_precision == 32 else 0,
-                           block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
+            u, rc, inf = s.solve(B, x0=None if x0s is None else x0s[0], restart=RESTART, max_iters=MAX_ITERS,
+                                 tol=TOL, mixed=1 if args.block_precision == 32 else 0,
+                                 block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
+            return [u], rc, inf
         if use_block:
-            res, rc = Solver.solve_batch(per_obj, B_obj, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
+            res, rc = Solver.solve_batch(per_obj, B_obj, x0s=x0s, restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
                                          mixed=1 if args.block_precision == 32 else 0,
                                          block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
-            return None, rc, [x for _, inf in res for x in inf]
-        return s.solve(B, restart=RESTART, max_iters=MAX_ITERS, tol=TOL, mixed=2 if args.basis == 16 else 1,
-                       orth=args.orth)
+            return ([u for u, _ in res] if x0s is not None else None), rc, [x for _, inf in res for x in inf]
+        u, rc, inf = s.solve(B, x0=None if x0s is None else x0s[0], restart=RESTART, max_iters=MAX_ITERS, tol=TOL,
+                             mixed=2 if args.basis == 16 else 1, orth=args.orth)
+        return [u], rc, inf
 
     for i in range(args.warmup):
         _, rc, info = batch_solve()
@@ -893,8 +889,11 @@ def main():
     if args.uneven:
         out["uneven"] = uneven_run([int(v) for v in args.uneven.split(",")], args)
 
-    if args.learned > 0:
-        out["learned"] = learned_run(args.learned, g, eps, B, nsolve, value, iters)
+    if not args.no_learned:
+        out["learned"] = learned_leg(lambda x0s: batch_solve(x0s=x0s), timed_ctx, B_obj if concurrent else [B],
+                                     args.steps, nsolve, value, iters,
+                                     out["plain"]["value"] if "plain" in out else None)
+        log(f"learned: {out['learned']}")
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (direct-sum products, dense solves) ...")
