@@ -32,6 +32,15 @@ template <class T> __device__ __forceinline__ c2<T> cmulc(c2<T> a, c2<T> b) {
 template <class T> __device__ __forceinline__ c2<T> mul_mi(c2<T> a) { return mk<T>(a.y, -a.x); }
 template <class T> __device__ __forceinline__ c2<T> mul_pi(c2<T> a) { return mk<T>(-a.y, a.x); }
 
+// Block barrier that the compiler may not move LDS accesses across: without the memory clobber,
+// LDS reads issued before __syncthreads() have been sunk below it (into the next loop
+// iteration's exchange), racing with other waves' writes after the barrier.
+__device__ __forceinline__ void lds_sync() {
+  asm volatile("" ::: "memory");
+  __syncthreads();
+  asm volatile("" ::: "memory");
+}
+
 // Widening / narrowing loads and stores between storage precision S and compute precision T.
 template <class T, class S> __device__ __forceinline__ c2<T> ld(const c2<S>* p) {
   c2<S> v = *p; return mk<T>((T)v.x, (T)v.y);

@@ -119,16 +119,26 @@ template <class T, int LR, bool INV> __device__ __forceinline__ void dftR(c2<T>*
   else dft16<T, INV>(v);
 }
 
-// Multiply v[q] (q = 1 .. R-1) by w^q, w = tw[base] (^* for INV), forming the powers
-// from the table entries w, w^2, w^4, w^8 with at most three products each.
+// The table entries w, w^2, w^4, w^8 (as far as R needs them) of w = tw[base].
+template <class T, int LR>
+__device__ __forceinline__ void twiddle_load(c2<T>* p4, const c2<T>* __restrict__ tw, int base) {
+  constexpr int R = 1 << LR;
+  p4[0] = tw[base];
+  if constexpr (R > 2) p4[1] = tw[(2 * base) & (kTw - 1)];
+  if constexpr (R > 4) p4[2] = tw[(4 * base) & (kTw - 1)];
+  if constexpr (R > 8) p4[3] = tw[(8 * base) & (kTw - 1)];
+}
+
+// Multiply v[q] (q = 1 .. R-1) by w^q (^* for INV), forming the powers from w, w^2, w^4, w^8
+// (twiddle_load) with at most three products each.
 template <class T, int LR, bool INV>
-__device__ __forceinline__ void twiddle(c2<T>* v, const c2<T>* __restrict__ tw, int base) {
+__device__ __forceinline__ void twiddle(c2<T>* v, const c2<T>* p4) {
   constexpr int R = 1 << LR;
   c2<T> p[R];
-  p[1] = tw[base];
-  if constexpr (R > 2) p[2] = tw[(2 * base) & (kTw - 1)];
-  if constexpr (R > 4) p[4] = tw[(4 * base) & (kTw - 1)];
-  if constexpr (R > 8) p[8] = tw[(8 * base) & (kTw - 1)];
+  p[1] = p4[0];
+  if constexpr (R > 2) p[2] = p4[1];
+  if constexpr (R > 4) p[4] = p4[2];
+  if constexpr (R > 8) p[8] = p4[3];
 #pragma unroll
   for (int q = 3; q < R; ++q) {
     if (q == 4 || q == 8) continue;
@@ -167,7 +177,7 @@ template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int M
   static constexpr int lr(int s) { return (REM && (REV ? s == NS - 1 : s == 0)) ? REM : LE; }
   static constexpr int lp(int s) { return s == 0 ? 0 : lp(s - 1) + lr(s - 1); }
   static constexpr int map(int s) { return s == 0 ? MAP0 : (s == NS - 1 ? MAPL : MAPR); }
-  static __device__ __forceinline__ int f(int j) { return j + (j >> PS); }
+  static __host__ __device__ constexpr int f(int j) { return j + (j >> PS); }
 
   // butterfly (array b, index i) of thread t, slot u, in stage S
   template <int S> static __device__ __forceinline__ void bi(int t, int u, int& b, int& i) {
@@ -195,25 +205,43 @@ template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int M
     pos = i + q * (N / RL);
   }
 
-  // Stage S on registers, then (except after the last stage) the exchange into the layout of
-  // stage S+1 through LDS.  The NP arrays held in lock step go through one LDS buffer in
-  // turn, so the buffer is NP times smaller than all the data (more blocks per CU).
+  // Twiddle base values of the butterflies a thread owns in stage S (none in stage 0).
+  template <int S> struct Tw {
+    c2<T> p[(E >> lr(S)) > 0 ? (E >> lr(S)) : 1][4];
+  };
+  template <int S> static __device__ __forceinline__ void load_tw(Tw<S>& w, const c2<T>* __restrict__ tw, int t) {
+    constexpr int LR = lr(S), LP = lp(S), P = 1 << LP, NU = E >> LR;
+    if constexpr (LP > 0) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        int b, i;
+        bi<S>(t, u, b, i);
+        twiddle_load<T, LR>(w.p[u], tw, (i & (P - 1)) << (kLogTw - LP - LR));
+      }
+    }
+  }
+
+  // Stage S on registers (its twiddle bases in w), then (except after the last stage) the
+  // exchange into the layout of stage S+1 through LDS.  The table loads of stage S+1 are issued
+  // before the exchange, whose barriers hide their latency.  The NP arrays held in lock step go
+  // through one LDS buffer in turn, so the buffer is NP times smaller than all the data (more
+  // blocks per CU).
   template <int S, bool INV>
-  static __device__ __forceinline__ void stage(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t) {
+  static __device__ __forceinline__ void stage(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t,
+                                               const Tw<S>& w) {
     constexpr int LR = lr(S), R = 1 << LR, LP = lp(S), P = 1 << LP, NU = E / R;
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      int b, i;
-      bi<S>(t, u, b, i);
-      const int k = i & (P - 1);
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        if constexpr (LP > 0) twiddle<T, LR, INV>(&v[p][u * R], tw, k << (kLogTw - LP - LR));
+        if constexpr (LP > 0) twiddle<T, LR, INV>(&v[p][u * R], w.p[u]);
         dftR<T, LR, INV>(&v[p][u * R]);
       }
     }
     if constexpr (S < NS - 1) {
       constexpr int LR1 = lr(S + 1), R1 = 1 << LR1, NR1 = N >> LR1, NU1 = E / R1;
+      Tw<S + 1> w1;
+      load_tw<S + 1>(w1, tw, t);
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
 #pragma unroll
@@ -222,33 +250,34 @@ template <class T, int LOGN, int NB, int LOGE, int NP, bool REV, int MAP0, int M
           bi<S>(t, u, b, i);
           const int k = i & (P - 1);
           const int j = ((i - k) << LR) + k;
+          // f(j + q P) = f(j) + f(q P): j mod 2^PS plus q P mod 2^PS never carries past 2^PS
+          // (j = multiple of P R plus k < P), so each element is a constant offset from f(j)
+          c2<T>* wr = lds + b * LDB + f(j);
 #pragma unroll
-          for (int q = 0; q < R; ++q) lds[b * LDB + f(j + q * P)] = v[p][u * R + q];
+          for (int q = 0; q < R; ++q) wr[f(q * P)] = v[p][u * R + q];
         }
-        __syncthreads();
+        lds_sync();
 #pragma unroll
         for (int u = 0; u < NU1; ++u) {
           int b, i;
           bi<S + 1>(t, u, b, i);
+          // the same for i + q NR1 (i < NR1, both powers of two)
+          const c2<T>* r = lds + b * LDB + f(i);
 #pragma unroll
-          for (int q = 0; q < R1; ++q) v[p][u * R1 + q] = lds[b * LDB + f(i + q * NR1)];
+          for (int q = 0; q < R1; ++q) v[p][u * R1 + q] = r[f(q * NR1)];
         }
-        __syncthreads();
+        lds_sync();
       }
+      stage<S + 1, INV>(v, lds, tw, t, w1);
     }
-  }
-
-  template <int S, bool INV>
-  static __device__ __forceinline__ void stages(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t) {
-    stage<S, INV>(v, lds, tw, t);
-    if constexpr (S + 1 < NS) stages<S + 1, INV>(v, lds, tw, t);
   }
 
   // v holds the stage-0 inputs; on return it holds the outputs (see out_pos).
   // LDS may be reused by the caller right after the call returns.
   template <bool INV>
   static __device__ __forceinline__ void run(c2<T> (&v)[NP][E], c2<T>* lds, const c2<T>* __restrict__ tw, int t) {
-    stages<0, INV>(v, lds, tw, t);
+    Tw<0> w0;
+    stage<0, INV>(v, lds, tw, t, w0);
   }
 };
 

@@ -118,7 +118,7 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
         }
       }
     }
-    __syncthreads();
+    lds_sync();
     const double sc = sb[buf];
     double2 u[kRowsPerLane];
     double2 d = make_double2(0.0, 0.0);
@@ -170,7 +170,7 @@ k_panel_apply(double2* __restrict__ H, int ld, double2* __restrict__ B, int ldb,
     const int i = l16 + 16 * t;
     v[t] = live && i < rows ? y[i] : make_double2(0.0, 0.0);
   }
-  __syncthreads();
+  lds_sync();
   for (int q = 0; q < pc; ++q) {
     const double2* u = Us + q * kPanelMaxRows;
     double2 uq[kRowsPerLane];

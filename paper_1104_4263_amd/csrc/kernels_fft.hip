@@ -75,8 +75,11 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, const c2
   using F = RegFft<T, LOGN, rows_ty<T>(LOGN, V), fft_le<T>(LOGN, V), 1, false, kPosFast, kArrFast>;
   constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN, V);
   __shared__ c2<T> lds[F::LDS_ELEMS];
+  // logical order group-fastest: the blocks of one row tile run on one XCD close together, so the
+  // contrast rows they all multiply by are read from HBM about once
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = L % ntiles, grp = L / ntiles;
+  const int ngrp = gridDim.x / ntiles;
+  const int tile = L / ngrp, grp = L % ngrp;
   const int y0 = tile * TY;
   const int r1 = min(nrhs, (grp + 1) * rb);
   for (int r = grp * rb; r < r1; ++r) {
@@ -100,9 +103,14 @@ k_rows_fwd(const c2<S>* __restrict__ x, const c2<T>* __restrict__ chi0, const c2
           F::in_pos(t, u, q, b, pos);
           const int yy = y0 + b;
           c2<T> a = mk<T>(0, 0);
-          if ((!HALF || q * (N / F::R0) < N / 2) && pos < nx && yy < nrows) {
-            a = ld<T, S>(xs + (size_t)yy * nx + pos);
-            if (chi) a = cmul<T>(a, chi[(size_t)yy * nx + pos]);
+          if (!HALF || q * (N / F::R0) < N / 2) {
+            // unconditional loads at a clamped address, zero by selection: no branch per element,
+            // so the loads of all elements are in flight together
+            const bool ok = pos < nx && yy < nrows;
+            const size_t o = (size_t)min(yy, nrows - 1) * nx + min(pos, nx - 1);
+            a = ld<T, S>(xs + o);
+            if (chi) a = cmul<T>(a, chi[o]);
+            if (!ok) a = mk<T>(0, 0);
           }
           v[0][u * F::R0 + q] = a;
         }
@@ -166,9 +174,16 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       const int xx = x0 + b, e = u * F::R0 + q;
       // nrows <= N/2 (zero padding to at least 2 nrows - 1): the upper half is known zero
       const bool lower = q * (N / F::R0) < N / 2;
+      const bool ok = xx < ncols && pos < nrows;
+      const size_t o = wtile_index(min(xx, ncols - 1), min(pos, nrows - 1), rows4);  // clamped: no branch
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        v[c][e] = (lower && xx < ncols && pos < nrows) ? Wr[c * plane + wtile_index(xx, pos, rows4)] : mk<T>(0, 0);
+      for (int c = 0; c < NC; ++c) {
+        v[c][e] = mk<T>(0, 0);
+        if (lower) {
+          const c2<T> a = Wr[c * plane + o];
+          if (ok) v[c][e] = a;
+        }
+      }
     }
   F::template run<false>(v, lds, tw, t);
   asm volatile("" : "+v"(t));  // per-phase address arithmetic (hoisting it costs VGPRs)
@@ -179,8 +194,10 @@ k_cols_symbol(c2<T>* __restrict__ W, const c2<T>* __restrict__ sym, const c2<T>*
       int b, pos;
       F::out_pos(t, u, q, b, pos);
       const int xx = x0 + b, e = u * F::RL + q;
-      if (xx < ncols) {
-        const c2<T>* sp = sym + ((size_t)xx * N + pos) * NPL;
+      {
+        // columns past ncols (a partial last block) multiply a clamped column's symbol; their
+        // results are never stored
+        const c2<T>* sp = sym + ((size_t)min(xx, ncols - 1) * N + pos) * NPL;
         if constexpr (NC == 1) {
           v[0][e] = cmul<T>(sp[0], v[0][e]);
         } else if constexpr (NC == 2) {
@@ -269,7 +286,8 @@ k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* 
       int b, pos;
       F::in_pos(t, uu, q, b, pos);
       const int yy = y0 + b;
-      v[0][uu * F::R0 + q] = yy < nrows ? Ws[wtile_index(pos, yy, rows4)] : mk<T>(0, 0);
+      const c2<T> a = Ws[wtile_index(pos, min(yy, nrows - 1), rows4)];  // clamped: no branch
+      v[0][uu * F::R0 + q] = yy < nrows ? a : mk<T>(0, 0);
     }
   F::template run<true>(v, lds, tw, t);
   const size_t so = (size_t)s * nrows * nx;
@@ -280,9 +298,10 @@ k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* 
       int b, pos;
       F::out_pos(t, uu, q, b, pos);
       const int yy = y0 + b;
-      if (q * (N / F::RL) < N / 2 && pos < nx && yy < nrows) {  // only columns < nx <= N/2 are kept
-        const size_t o = so + (size_t)yy * nx + pos;
-        st<S, T>(y + o, csub<T>(ld<T, S>(u + o), v[0][uu * F::RL + q]));
+      if (q * (N / F::RL) < N / 2) {  // only columns < nx <= N/2 are kept
+        const size_t o = so + (size_t)min(yy, nrows - 1) * nx + min(pos, nx - 1);
+        const c2<T> d = csub<T>(ld<T, S>(u + o), v[0][uu * F::RL + q]);  // unconditional (clamped) load
+        if (pos < nx && yy < nrows) st<S, T>(y + o, d);
       }
     }
 }
@@ -301,7 +320,7 @@ __global__ void __launch_bounds__(256) k_transpose(const c2<T>* __restrict__ in,
     const int rr = r0 + k, cc = c0 + tx;
     if (rr < rows && cc < cols) tile[k][tx] = ib[(size_t)rr * cols + cc];
   }
-  __syncthreads();
+  lds_sync();
   for (int k = ty; k < 32; k += 8) {
     const int cc = c0 + k, rr = r0 + tx;
     if (rr < rows && cc < cols) ob[(size_t)cc * rows + rr] = tile[tx][k];

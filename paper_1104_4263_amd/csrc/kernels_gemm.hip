@@ -252,7 +252,7 @@ k_tsq_proj(const E* __restrict__ A1, int ma, const E* __restrict__ B1, int nb, s
 #pragma unroll
     for (int i = 0; i < BPT; ++i) *reinterpret_cast<V*>(&bsh[0][(threadIdx.x + 256 * i) * KV]) = bst[i];
   }
-  __syncthreads();
+  lds_sync();
   for (int g = 0; g < ng; ++g) {
     const int cur = g & 1;
     const bool more = g + 1 < ng;
@@ -287,7 +287,7 @@ k_tsq_proj(const E* __restrict__ A1, int ma, const E* __restrict__ B1, int nb, s
 #pragma unroll
       for (int f = 0; f < GK; ++f) a[f] = an[f];
     }
-    __syncthreads();
+    lds_sync();
   }
   if (ta >= mt) return;
   typename Tl::Acc* out = part + (size_t)h * ma * nb;
@@ -433,7 +433,7 @@ k_tsq_update(const E* __restrict__ A2, int mc, size_t ccap, size_t nrow, const E
     q_load(0, q);
     stage_store(0, 0, x);
   }
-  __syncthreads();
+  lds_sync();
   const E* pa = &sh[0][0] + (lane % R) * CKP + (lane / R) * KV;
   for (int k = 0; k < nchunk; ++k) {
     const int cur = k & 1;
@@ -470,7 +470,7 @@ k_tsq_update(const E* __restrict__ A2, int mc, size_t ccap, size_t nrow, const E
 #pragma unroll
       for (int s = 0; s < NS; ++s) q[s] = qn[s];
     }
-    __syncthreads();
+    lds_sync();
   }
   if (!live) return;
   const size_t nn = stripe * R + M::col(lane);
@@ -523,7 +523,7 @@ k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restr
       const int c = c0 + u * G + kg;  // past s: a finite value of X against zero rows of S
       xv[u] = X[(size_t)(c < s ? c : s - 1) * ldx + rowc];
     }
-    __syncthreads();  // the previous chunk's LDS reads are done
+    lds_sync();  // the previous chunk's LDS reads are done
     {
       constexpr int PER = SC * NT * R / 256;  // staged values per thread
       c2<T> v[PER];
@@ -540,7 +540,7 @@ k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restr
         si[i * QP + j] = in ? v[k].y : (T)0;
       }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       if (u * G >= cn) break;
@@ -589,7 +589,7 @@ k_trsm_upper(const double2* __restrict__ R, int ldr, int nc, double2* __restrict
   const int wave = threadIdx.x >> 6, t = threadIdx.x & 63;
   for (int ie = nc; ie > 0; ie -= 64) {
     const int ib = ie > 64 ? ie - 64 : 0, nb = ie - ib;
-    __syncthreads();  // the previous block's updates (and the initial loads) are done
+    lds_sync();  // the previous block's updates (and the initial loads) are done
     for (int e = threadIdx.x; e < nb * nb; e += 1024) {
       const int jc = e / nb, ir = e - jc * nb;
       const double2 v = R[(size_t)(ib + jc) * ldr + ib + ir];
@@ -599,7 +599,7 @@ k_trsm_upper(const double2* __restrict__ R, int ldr, int nc, double2* __restrict
         rinv[ir] = make_double2(v.x / dd, -v.y / dd);
       }
     }
-    __syncthreads();
+    lds_sync();
     if (wave < kc) {
       double2 bt = t < nb ? bsh[wave * nc + ib + t] : make_double2(0.0, 0.0);
       double2 yt = make_double2(0.0, 0.0);
@@ -620,7 +620,7 @@ k_trsm_upper(const double2* __restrict__ R, int ldr, int nc, double2* __restrict
         B[(size_t)(c0 + wave) * ldb + ib + t] = yt;
       }
     }
-    __syncthreads();
+    lds_sync();
     for (int row = threadIdx.x; row < ib; row += 1024) {
       double2 a[KC];
 #pragma unroll

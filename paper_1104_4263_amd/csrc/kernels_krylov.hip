@@ -29,13 +29,13 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2* red) {
   v.y = wave_sum(v.y);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
+  lds_sync();
   double2 s = make_double2(0.0, 0.0);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NW; ++k) { s.x += red[k].x; s.y += red[k].y; }
   }
-  __syncthreads();
+  lds_sync();
   return s;
 }
 
@@ -43,13 +43,13 @@ __device__ __forceinline__ double block_sum1(double v, double* red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
+  lds_sync();
   double s = 0.0;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NW; ++k) s += red[k];
   }
-  __syncthreads();
+  lds_sync();
   return s;
 }
 
@@ -135,7 +135,7 @@ k_reduce(const double2* __restrict__ part, int nv, int nblk, double sign, const 
     sy = wave_sum(sy);
     if (lane == 0) tmp[i] = make_double2(sign * sx, sign * sy);
   }
-  __syncthreads();
+  lds_sync();
   for (int i = threadIdx.x; i < nv; i += NT) {
     double2 v;
     if (C) {
@@ -594,7 +594,7 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
     else dots_group<SA, false>(Ar, a_vs, i0, gn, base, n, b, v);
 #pragma unroll
     for (int q = 0; q < 2 * kDotG; ++q) red[q][t] = v[q];
-    __syncthreads();
+    lds_sync();
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < NT / 32; ++k) s += red[rv][k * 32 + rl];
@@ -604,16 +604,16 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
       double* dst = reinterpret_cast<double*>(part + ((size_t)r * nv + i0 + (rv >> 1)) * nchunk + blockIdx.x);
       __hip_atomic_store(dst + (rv & 1), s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
+    lds_sync();
   }
   // the partials were stored by lanes of every wave: each wave waits for its own stores
   // before the block's completion is counted
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+  lds_sync();
   int* cnt = counter + (size_t)r * kCounterStride;
   if (!WALK) {  // first level: the chunks of this vector group
     if (t == 0) s_last = arrive_last(cnt + 1 + blockIdx.y, nchunk);
-    __syncthreads();
+    lds_sync();
     if (!s_last) return;
     if (t == 0) {
       cnt[1 + blockIdx.y] = 0;
@@ -622,7 +622,7 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
   } else if (t == 0) {
     s_last = arrive_last(cnt, nchunk);
   }
-  __syncthreads();
+  lds_sync();
   if (!s_last) return;
   // last block of rhs r: sum each vector's chunk partials in a fixed order
   for (int g = w; g < nv; g += NW) {
@@ -643,7 +643,7 @@ k_dots(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
   }
   if (t == 0) cnt[0] = 0;
   if (!C) return;
-  __syncthreads();
+  lds_sync();
   for (int ii = t; ii < nv; ii += NT) {
     double2 v = make_double2(0.0, 0.0);
     for (int l = 0; l < nv; ++l) {
@@ -715,7 +715,7 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
       const double v = wave_sum(s2[k]);
       if (lane == 0) red1[k][w] = v;
     }
-    __syncthreads();
+    lds_sync();
     if (t < EPT) {  // wave 0 only: its vmcnt wait below orders these stores before the count
       double v = 0.0;
 #pragma unroll
@@ -728,7 +728,7 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
     const int grp = blockIdx.x / kBlocksPerGroup, ngrp = (nblk + kBlocksPerGroup - 1) / kBlocksPerGroup;
     const int gblocks = min(kBlocksPerGroup, nblk - grp * kBlocksPerGroup);
     if (t == 0) s_last = arrive_last(cnt + 1 + grp, gblocks);
-    __syncthreads();
+    lds_sync();
     if (!s_last) return;
     double2* gpart = part + (size_t)gridDim.y * npart;  // group sums after the partials
     const int gsize = gblocks * EPT;
@@ -743,7 +743,7 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
         s_last = arrive_last(cnt, ngrp);
       }
     }
-    __syncthreads();
+    lds_sync();
     if (!s_last) return;
     __shared__ double2 col[kFusedMaxNv + 1];
     __shared__ double s_beta;
@@ -758,7 +758,7 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
         cnt[0] = 0;
       }
     }
-    __syncthreads();
+    lds_sync();
     if (S.done) return;
     const int j = S.j, ld = m + 1;
     double2* R = Rm + (size_t)r * ld * m;
@@ -769,7 +769,7 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
       const double2 a = h1[(size_t)r * nv + i], b = coef[(size_t)r * nv + i];
       col[i] = make_double2(-(a.x + b.x), -(a.y + b.y));
     }
-    __syncthreads();
+    lds_sync();
     if (t == 0) {
       // apply the previous rotations to the new column, then the new rotation
       const double beta = s_beta;
@@ -813,7 +813,7 @@ k_axpy(const c2<SA>* __restrict__ A, size_t a_vs, size_t a_rs, int a_rpo, int nv
       }
       state[r] = Sn;
     }
-    __syncthreads();
+    lds_sync();
     for (int i = t; i <= j; i += NT) R[i + (size_t)j * ld] = col[i];
   }
 }
@@ -831,7 +831,7 @@ k_lsq(const GmresState* __restrict__ state, const double2* __restrict__ Rm, cons
   double2* yr = y + (size_t)r * m;
   __shared__ double2 rhs[kFusedMaxNv];
   for (int i = lane; i < jj; i += 64) rhs[i] = g[(size_t)r * ld + i];
-  __syncthreads();
+  lds_sync();
   for (int i = jj - 1; i >= 0; --i) {
     const double2 d = R[i + (size_t)i * ld];
     const double dd = d.x * d.x + d.y * d.y;
@@ -844,7 +844,7 @@ k_lsq(const GmresState* __restrict__ state, const double2* __restrict__ Rm, cons
       rhs[l].x -= p.x;
       rhs[l].y -= p.y;
     }
-    __syncthreads();
+    lds_sync();
   }
 }
 
@@ -971,7 +971,7 @@ k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restr
   auto reduce_store = [&](const double (&v)[8], int i0, int gn) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) red[q][t] = v[q];
-    __syncthreads();
+    lds_sync();
     double sum = 0.0;
 #pragma unroll
     for (int k = 0; k < NT / 32; ++k) sum += red[rv][k * 32 + rl];
@@ -983,7 +983,7 @@ k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restr
           reinterpret_cast<double*>(part + (((size_t)r * nA + i0 + gv) * 2 + tg) * nchunk + blockIdx.x);
       __hip_atomic_store(dst + comp, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
+    lds_sync();
   };
   // basis vectors Q_i, i < nq
   for (int i0 = ifirst; i0 < min(iend, nq); i0 += kDots2G) {
@@ -1011,11 +1011,11 @@ k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restr
     reduce_store(v, nq, 1);
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+  lds_sync();
   int* cnt = counter + (size_t)r * kCounterStride;
   if (!WALK) {
     if (t == 0) s_last = arrive_last(cnt + 1 + blockIdx.y, nchunk);
-    __syncthreads();
+    lds_sync();
     if (!s_last) return;
     if (t == 0) {
       cnt[1 + blockIdx.y] = 0;
@@ -1024,7 +1024,7 @@ k_dots2(const c2<SQ>* __restrict__ Q, size_t q_vs, int nq, const c2<SV>* __restr
   } else if (t == 0) {
     s_last = arrive_last(cnt, nchunk);
   }
-  __syncthreads();
+  lds_sync();
   if (!s_last) return;
   for (int g = w; g < 2 * nA; g += NW) {
     const double2* p = part + ((size_t)r * nA * 2 + g) * nchunk;
@@ -1090,7 +1090,7 @@ k_dcgs_update(const double2* __restrict__ D, int dstride, int j, int m, GmresSta
     s_stop = stop;
     state[r] = S;
   }
-  __syncthreads();
+  lds_sync();
   const double nu = s_nu;
   if (j >= 1 && !s_stop) {
     // column j-1 of H: c_{j-1} + s, subdiagonal nu
@@ -1103,7 +1103,7 @@ k_dcgs_update(const double2* __restrict__ D, int dstride, int j, int m, GmresSta
       col[j] = make_double2(nu, 0.0);
       Hr[j + (size_t)(j - 1) * ld] = col[j];
     }
-    __syncthreads();
+    lds_sync();
     if (lane == 0) {
       GmresState S = state[r];
       const int jc = j - 1;  // the column being rotated
@@ -1145,10 +1145,10 @@ k_dcgs_update(const double2* __restrict__ D, int dstride, int j, int m, GmresSta
       if (!fin || resid <= S.target || j >= m || !(nu > 0.0)) s_stop = 1;
       state[r] = S;
     }
-    __syncthreads();
+    lds_sync();
     for (int i = lane; i <= j - 1; i += 64) Rm[(size_t)r * ld * m + i + (size_t)(j - 1) * ld] = col[i];
   }
-  __syncthreads();
+  lds_sync();
   if (s_stop || j >= m) {
     if (lane == 0) {
       GmresState S = state[r];
@@ -1177,7 +1177,7 @@ k_dcgs_update(const double2* __restrict__ D, int dstride, int j, int m, GmresSta
   }
   sz.x = wave_sum(sz.x);
   sz.y = wave_sum(sz.y);
-  __syncthreads();
+  lds_sync();
   const double inu = 1.0 / nu;
   for (int i = lane; i <= j; i += 64) {
     double2 h;

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "common.hpp"
 #include "unet_ops.hpp"
 
 namespace die {
@@ -249,7 +250,7 @@ k_conv_wgrad_lds(const bf16raw* __restrict__ dZ, int ldz, const bf16raw* __restr
     load(pbeg);
     put(0);
   }
-  __syncthreads();
+  lds_sync();
   int buf = 0;
   for (long p0 = pbeg; p0 < pend; p0 += kWgPx, buf ^= 1) {
     const bool more = p0 + kWgPx < pend;
@@ -273,7 +274,7 @@ k_conv_wgrad_lds(const bf16raw* __restrict__ dZ, int ldz, const bf16raw* __restr
       }
     }
     if (more) put(buf ^ 1);
-    __syncthreads();
+    lds_sync();
   }
   const int N = NTAPS * cin, col = c0 + r32;
   if (col < cin) {
@@ -288,7 +289,7 @@ k_conv_wgrad_lds(const bf16raw* __restrict__ dZ, int ldz, const bf16raw* __restr
     if (tid < 256) sB[tid >> 6][tid & 63] = bsum;
     if (NTH == 64)
       for (int qq = 1; qq < 4; ++qq) sB[qq][tid] = 0.f;
-    __syncthreads();
+    lds_sync();
     if (tid < 64 && co0 + tid < cout)
       bpart[(size_t)blockIdx.z * cout + co0 + tid] = (sB[0][tid] + sB[1][tid]) + (sB[2][tid] + sB[3][tid]);
   }
@@ -316,7 +317,7 @@ k_reduce_splits(const float* __restrict__ part, int nsplit, size_t count, float*
   if (j < count)
     for (int k = q; k < nsplit; k += kRedG) s += part[(size_t)k * count + j];
   red[q][jj] = s;
-  __syncthreads();
+  lds_sync();
   if (q == 0 && j < count) {
     float t = red[0][jj];
     for (int k = 1; k < kRedG; ++k) t += red[k][jj];
@@ -431,10 +432,10 @@ k_mse(const float* __restrict__ out, const float* __restrict__ t, size_t count, 
     }
   }
   red[threadIdx.x] = s;
-  __syncthreads();
+  lds_sync();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+    lds_sync();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
@@ -444,10 +445,10 @@ __global__ void __launch_bounds__(NT) k_sum_doubles(const double* __restrict__ p
   double s = 0.0;
   for (int j = threadIdx.x; j < n; j += NT) s += part[j];
   red[threadIdx.x] = s;
-  __syncthreads();
+  lds_sync();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+    lds_sync();
   }
   if (threadIdx.x == 0) out[0] = red[0];
 }
