@@ -15,17 +15,19 @@ true residual, tol 1e-8 on that residual, zero initial guess.  --solver rhs time
 complex64 basis and the two-pass CGS2); it is also reported beside the block run.  Inputs are resident in HBM before the timed region; the
 per-object setup (symbol) is done once, outside it.
 
-The configured deflation (k = 16 largest-magnitude eigenvalues) is not applied in the
-headline: on these objects GMRES(30) on A P^-1 stagnates near 3e-2 for many angles (an
-independent scipy GMRES(30) with ARPACK eigenvectors stagnates at the same value), so
-deflation is measured as a variant (--configured-deflation) and the headline and the
-plain baseline both solve the undeflated system A.
+The configured deflation (k = 16 largest-magnitude eigenvalues per object) is not applied in
+the headline: on these objects GMRES(30) on A P^-1 stagnates near 3e-2 for many angles (an
+independent scipy GMRES(30) with ARPACK eigenvectors stagnates at the same value), so the
+headline and the plain baseline both solve the undeflated system A, and the same batch with
+k = 16 is reported beside them (configured_deflation_k16).
 
 Reported next to it: the plain solver (FP64 products and basis, one right-hand side per
 call, the same GMRES(30) and orthogonalisation, a sample of 16 of the 256 solves), the product throughput at the batched shape and at
 the 1024^2 class (64 fields), the hard-cylinder variants (regularizer, deflation,
 mixed precision), the learned warm start (the stored configured network's guesses, its
-inference inside the timed region, then the same batched solve) and the FP64 oracle on the host.
+inference inside the timed region, then the same batched solve), the uneven configuration (16
+objects in four size classes 128^2 .. 1024^2, 64 angles each, 1024 solves in one call per
+restart-cycle chunk, within a wall-clock budget) and the FP64 oracle on the host.
 
 One JSON line on stdout; progress on stderr.
 """
@@ -244,35 +246,42 @@ def learned_leg(solve, ctxs, Bs, steps, nsolve, value_zero, iters_zero, plain_va
 SIZE_CLASSES = (128, 256, 512, 1024)  # object o of the batched workload has size class o // 4, seed 1000 + o
 
 
-def uneven_run(sizes, args):
+def uneven_run(sizes, args, deflate_k=0, budget_s=None):
     """Several size classes of the batched workload (4 objects x 64 angles each) solved in one
     die_te_solve_batch call: one context per object with the block solver and --contexts
-    per-object (classes up to 512^2), else one context per grid size."""
+    per-object (classes up to 256^2), else one context per grid size.  deflate_k: the deflation
+    size of every object (eigensolver setup timed apart); budget_s: stop after the chunk that
+    passes this many seconds and report the state reached."""
     import numpy as np
     import torch
     from synth import plane_wave, random_field_object
     from paper_1104_4263_amd import Solver
     solvers, Bs, cls = [], [], []
     per_object = args.solver == "block" and args.contexts == "per-object"
+    t_setup = time.perf_counter()
     for n in sizes:
         c = SIZE_CLASSES.index(n)
         objs = [random_field_object(n, seed=1000 + 4 * c + i) for i in range(4)]
         gn = objs[0][0]
         b1 = torch.from_numpy(np.stack([plane_wave(gn, 2.0 * math.pi * j / N_ANGLES) for j in range(N_ANGLES)])).cuda()
-        if per_object and n <= 512:  # a 1024^2 object's block buffers (~57 GB) allow one context per class
+        dk = dict(deflate_k=deflate_k, seed=1) if deflate_k else {}
+        if per_object and n <= 256:  # larger classes: one context per class (block buffers of one object at a time)
             for _, e in objs:
-                solvers.append(Solver.from_grid(gn, e))
+                solvers.append(Solver.from_grid(gn, e, **dk))
                 Bs.append(b1)
                 cls.append(n)
         else:
-            solvers.append(Solver.from_grid(gn, np.stack([e for _, e in objs])))
+            solvers.append(Solver.from_grid(gn, np.stack([e for _, e in objs]), **dk))
             Bs.append(torch.cat([b1] * 4))
             cls.append(n)
+        log(f"uneven: class {n} set up ({time.perf_counter() - t_setup:.1f} s)")
     if args.solver == "block":
         kw = dict(restart=RESTART, tol=TOL, mixed=1 if args.block_precision == 32 else 0,
                   block=2 if args.block_gemm == 16 else 1, orth=args.block_orth)
     else:
         kw = dict(restart=RESTART, tol=TOL, mixed=2 if args.basis == 16 else 1, orth=args.orth)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
     Solver.solve_batch(solvers, Bs, max_iters=RESTART, **kw)  # allocates every context's buffers
     torch.cuda.synchronize()
     # solved in chunks of two restart cycles, each starting from the previous chunk's fields (the
@@ -281,8 +290,12 @@ def uneven_run(sizes, args):
     iters = [np.zeros(b.shape[0], dtype=np.int64) for b in Bs]
     t0 = time.perf_counter()
     rc, chunk = 1, 2 * RESTART
+    stopped = False
     while rc != 0 and int(max(i.max() for i in iters)) < MAX_ITERS:
-        res, rc = Solver.solve_batch(solvers, Bs, x0s=X, max_iters=chunk, **kw)
+        if budget_s is not None and time.perf_counter() - t0 > budget_s:
+            stopped = True
+            break
+        res, rc = Solver.solve_batch(solvers, Bs, x0s=X, inplace=True, max_iters=chunk, **kw)
         X = [u for u, _ in res]
         for c, (_, inf) in enumerate(res):
             iters[c] += np.array([x["iters"] for x in inf])
@@ -297,12 +310,15 @@ def uneven_run(sizes, args):
     per = {}
     for n in sizes:
         it = np.concatenate([i for i, cn in zip(iters, cls) if cn == n])
-        per[f"{n}x{n}"] = {"iters_mean": round(float(np.mean(it)), 1), "iters_max": int(it.max())}
+        rr = [x["rel_res_true"] for (_, inf), cn in zip(res, cls) if cn == n for x in inf]
+        per[f"{n}x{n}"] = {"iters_mean": round(float(np.mean(it)), 1), "iters_max": int(it.max()),
+                           "converged": int(sum(r <= TOL for r in rr)), "of": len(rr),
+                           "worst_rel_res": max(rr)}
     out = {"workload": f"size classes {sizes} of the batched random-field workload, 4 objects x {N_ANGLES} "
                        f"angles each, die_te_solve_batch calls of two restart cycles each over "
-                       f"{len(solvers)} contexts", "solver": args.solver,
-           "solves": nsol,
-           "s": round(dt, 3),
+                       f"{len(solvers)} contexts", "solver": args.solver, "deflate_k": deflate_k,
+           "setup_s": round(setup_s, 1), "solves": nsol,
+           "s": round(dt, 3), "finished": ok, "stopped_at_budget_s": budget_s if stopped else None,
            "solves_per_s": round(nsol / dt, 3) if ok else 0.0, "classes": per}
     log(f"uneven: {out}")
     for sv in solvers:
@@ -570,17 +586,20 @@ def main():
                     help="Arnoldi orthogonalisation: 1 = one-reduction CGS2 (default), 0 = two-pass CGS2")
     ap.add_argument("--basis", type=int, default=16, choices=(16, 32),
                     help="bits per real part of the stored Krylov basis in the batched run (16 needs --orth 1)")
+    ap.add_argument("--uneven-deflate", type=int, default=0, metavar="K",
+                    help="--uneven: deflate the K largest-magnitude eigenvalues of every object")
+    ap.add_argument("--uneven-budget", type=float, default=420.0, metavar="SECONDS",
+                    help="--uneven: stop after the chunk that passes this many seconds of solving (0: no limit)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (the stored network's guesses + the batched solve)")
-    ap.add_argument("--configured-deflation", action="store_true",
-                    help="also run the batch with the configured k=16 deflation (about 40 s)")
+    ap.add_argument("--no-configured-deflation", action="store_true",
+                    help="skip the headline batch with the configured k = 16 deflation per object")
     ap.add_argument("--product-only", action="store_true",
                     help="only time the operator product at 1024^2 x 64 fields (for profiling)")
     ap.add_argument("--variants-only", action="store_true",
                     help="only run the paper's four systems on the cylinders and Table 2's squares")
-    ap.add_argument("--uneven", type=str, default="", metavar="SIZES",
-                    help="also solve size classes of the batched workload on grids of different sizes in one "
-                         "call (e.g. 128,256,512: 4 objects x 64 angles per class, seeds 1000 + object index)")
+    ap.add_argument("--uneven", type=str, default="128,256,512,1024", metavar="SIZES",
+                    help="size classes of the uneven batched configuration solved in one call ('' skips it)")
     args = ap.parse_args()
     if args.block_precision != 32:
         args.block_gemm = 32  # binary16 GEMMs only over a complex64 basis
@@ -870,30 +889,47 @@ def main():
     out["roofline"] = product_roofline()
     log(f"roofline (product at 1024^2 x 64): {out['roofline']}")
 
-    if args.configured_deflation:
-        sd = Solver.from_grid(g, eps, deflate_k=16, seed=1)
-        torch.cuda.synchronize()
+    if not args.no_configured_deflation:
+        # the batched configuration's deflation (k = 16 per object) on the headline batch, with the
+        # headline's block solver (capped), beside the undeflated headline
         t0 = time.perf_counter()
-        _, rc, inf = sd.solve(B, restart=RESTART, max_iters=8000, tol=TOL, mixed=True)
+        sds = [Solver.from_grid(g, eps[o], deflate_k=16, seed=1) for o in range(nobj)]
         torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res_d, rc_d = Solver.solve_batch(sds, B_obj, restart=RESTART, max_iters=1500, tol=TOL, mixed=1, block=2,
+                                         orth=args.block_orth)
+        torch.cuda.synchronize()
+        inf = [x for _, i in res_d for x in i]
+        it_d = np.array([x["iters"] for x in inf])
         out["configured_deflation_k16"] = {
-            "converged": int(sum(x["status"] == 0 for x in inf)), "of": nsolve, "max_iters": 8000,
-            "worst_rel_res": max(x["rel_res_true"] for x in inf), "s": round(time.perf_counter() - t0, 2)}
+            "method": "the headline's block solver on A P^-1, k = 16 per object, capped at 1500 block steps",
+            "converged": int(sum(x["status"] == 0 for x in inf)), "of": nsolve,
+            "iters_mean": round(float(it_d.mean()), 1), "iters_max": int(it_d.max()),
+            "iters_mean_undeflated": round(float(iters.mean()), 1),
+            "worst_rel_res": max(x["rel_res_true"] for x in inf), "setup_s": round(t1 - t0, 2),
+            "s": round(time.perf_counter() - t1, 2)}
         log(f"configured deflation: {out['configured_deflation_k16']}")
-        sd.close()
+        for sv in sds:
+            sv.close()
 
     if not args.no_variants:
         # the paper's four systems on the hard cylinder, its 128^2 analog and Table 2's squares
         out["method_variants"] = method_variants()
-
-    if args.uneven:
-        out["uneven"] = uneven_run([int(v) for v in args.uneven.split(",")], args)
 
     if not args.no_learned:
         out["learned"] = learned_leg(lambda x0s: batch_solve(x0s=x0s), timed_ctx, B_obj if concurrent else [B],
                                      args.steps, nsolve, value, iters,
                                      out["plain"]["value"] if "plain" in out else None)
         log(f"learned: {out['learned']}")
+
+    if args.uneven:
+        # the headline's contexts hold block buffers the 1024^2 class needs
+        for sv in per_obj:
+            sv.close()
+        s.close()
+        torch.cuda.empty_cache()
+        out["uneven"] = uneven_run([int(v) for v in args.uneven.split(",")], args, deflate_k=args.uneven_deflate,
+                                   budget_s=args.uneven_budget or None)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (direct-sum products, dense solves) ...")

@@ -305,12 +305,15 @@ class Solver:
         return out, rc, info
 
     @staticmethod
-    def solve_batch(solvers, e_ins, x0s=None, **kw):
-        """Solvers on different grids in one call: returns [(u, info)] per solver and the code."""
+    def solve_batch(solvers, e_ins, x0s=None, inplace=False, **kw):
+        """Solvers on different grids in one call: returns [(u, info)] per solver and the code.
+        inplace: the solutions overwrite the (contiguous) initial guesses x0s instead of copies."""
         nrhs = [s._shape(e) for s, e in zip(solvers, e_ins)]
         if x0s is not None and any(x0 is None for x0 in x0s):
             raise ValueError("x0s must give an initial guess for every solver (or be None)")
-        outs = [(x0.clone().contiguous() if x0 is not None else torch.empty_like(e))
+        if inplace and (x0s is None or any(not x0.is_contiguous() for x0 in x0s)):
+            raise ValueError("inplace needs contiguous initial guesses")
+        outs = [(x0 if inplace else x0.clone().contiguous()) if x0 is not None else torch.empty_like(e)
                 for e, x0 in zip(e_ins, x0s or [None] * len(e_ins))]
         rc, infos = die_te_solve_batch([s.ctx for s in solvers], [e.contiguous() for e in e_ins], outs, nrhs,
                                        x0_given=x0s is not None, **kw)

@@ -310,7 +310,9 @@ int fft_plan(die_te_ctx* c, int nrhs, hipStream_t st, const int** out) {
       float tf, th;
       DIE_TRY(time_pass(pass, te.radix[pass], &tf));
       DIE_TRY(time_pass(pass, te.radix[pass] | 2, &th));
-      te.tile[bc][pass] = th < tf ? 1 : 0;
+      // the half tile reads each 128-byte line of the tiled intermediate in two blocks: taken only
+      // when clearly faster (its extra traffic costs the other streams' kernels)
+      te.tile[bc][pass] = th < 0.97f * tf ? 1 : 0;
     }
     DIE_HIP(hipStreamSynchronize(st));  // xb, yb are freed on return
   }
@@ -1706,6 +1708,13 @@ struct BlockWork {
   DBuf Ubest, bmask;         // best iterate so far per right-hand side, and the copy mask
 };
 
+// Frees the buffers that scale with the basis (kept: the per-right-hand-side corrections and best
+// iterates); the next block solve allocates them again at the size it needs.
+void release_block_basis(BlockWork& bw) {
+  for (DBuf* b : {&bw.Vb, &bw.Wt, &bw.Zb, &bw.Tm, &bw.Tb, &bw.Ra, &bw.Q1, &bw.Q2, &bw.Wacc, &bw.W1, &bw.P64})
+    b->release();
+}
+
 // Buffers of the planar Gram-Schmidt for element type E (basis precision T): nrow padded rows,
 // column capacity ccap of the basis shadows, block width at most pw.
 template <class T, class E>
@@ -2576,6 +2585,10 @@ int die_te_solve(die_te_ctx* c, const void* e_in, void* e_tot, int nrhs, const d
       if (stalled[r]) used = std::max(used, i32[r].iters);
     if (rc >= 0 && used >= 0) {
       if (used < o.max_iters) {
+        // the complex64 basis and its shadows make room for the FP64 ones (the corrections kept
+        // for augmented restarts and the best iterates stay)
+        DIE_HIP(hipStreamSynchronize(st));
+        if (c->bw) release_block_basis(*c->bw);
         die_te_solve_opts o64 = o;
         o64.mixed = 0;
         o64.block = 1;
