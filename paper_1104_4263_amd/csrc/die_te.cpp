@@ -2146,17 +2146,19 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         // CholQR of the orthogonalised block (planar in Wacc): the first Gram from the planar
         // copy, then W back to complex; each factor application writes the other buffer, and
         // the result ends in W
-        c2<T>* wa = W;
-        c2<T>* wb = Wt.as<c2<T>>();
         T* ws = bw.Wacc.as<T>();
         Mat Gw, Q1, Q2;
         DIE_TRY(gram_planar<T>(bw, ws, nrow, p, Gw, st));
-        DIE_HIP((die::launch_tsq_merge<T, T>(ws, nrow, n, p, W, n, st)));
         double piv1 = 0.0;
         bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1, &piv1);
         // a well-conditioned block (smallest scaled pivot >= kCholQRSinglePivot, condition <= ~4.5)
         // is orthonormal to about cond^2 times the Gram's rounding after one CholQR pass
         const bool single = ok && piv1 >= kCholQRSinglePivot;
+        // the planar block back to complex where the factor applications leave the result in W
+        // (one pass: merged into Wt, applied into W; two passes: W -> Wt -> W), so no copy follows
+        c2<T>* wa = single ? Wt.as<c2<T>>() : W;
+        c2<T>* wb = single ? W : Wt.as<c2<T>>();
+        DIE_HIP((die::launch_tsq_merge<T, T>(ws, nrow, n, p, wa, n, st)));
         if (ok) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q1), sm.p, slot[0], st));
           DIE_HIP(die::launch_cplx_rmul<T>(wa, n, p, sm.as<c2<T>>(), p, p, n, wb, n, st));
@@ -2170,14 +2172,10 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
           early = true;
           break;
         }
-        c2<T>* wres = wb;
         if (!single) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
           DIE_HIP(die::launch_cplx_rmul<T>(wb, n, p, sm.as<c2<T>>(), p, p, n, wa, n, st));
-          wres = wa;
         }
-        if (wres != W)
-          DIE_HIP(hipMemcpyAsync(W, wres, (size_t)p * n * sizeof(c2<T>), hipMemcpyDeviceToDevice, st));
         DIE_TRY(shadow(W, p, j + 1));
         const Mat Hs = single ? Q1 : la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1 (Q2 = I: one pass)
         // into H's block (j+1, j) straight from the page-locked slot

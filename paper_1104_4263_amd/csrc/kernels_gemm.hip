@@ -494,8 +494,8 @@ k_tsq_update(const E* __restrict__ A2, int mc, size_t ccap, size_t nrow, const E
 // ---- Y (n x q) = X (n x s) S (s x q), complex, on the matrix cores in T: per tile of R rows
 // of Y, D^T = S^T X^T as four real products (Re Y = Sr Xr - Si Xi, Im Y = Si Xr + Sr Xi,
 // transposed).  S is staged through LDS 64 rows at a time as real and imaginary planes [c][j]
-// (zero past s and q); each lane reads one complex value of X per MFMA step, and a chunk's
-// values are in flight while the chunk of S is staged.  X and Y are distinct.
+// (zero past s and q); each lane reads one complex value of X per MFMA step (the loop is
+// unrolled four steps deep, so that their loads are in flight together).  X and Y are distinct.
 template <class T, int NT>
 __global__ void __launch_bounds__(256)
 k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restrict__ S, int lds, int q, size_t n,
@@ -517,12 +517,6 @@ k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restr
   }
   for (int c0 = 0; c0 < s; c0 += SC) {
     const int cn = s - c0 < SC ? s - c0 : SC;
-    c2<T> xv[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int c = c0 + u * G + kg;  // past s: a finite value of X against zero rows of S
-      xv[u] = X[(size_t)(c < s ? c : s - 1) * ldx + rowc];
-    }
     lds_sync();  // the previous chunk's LDS reads are done
     {
       constexpr int PER = SC * NT * R / 256;  // staged values per thread
@@ -541,18 +535,35 @@ k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restr
       }
     }
     lds_sync();
+    // partly unrolled: fully unrolled, the compiler hoisted every LDS read of the chunk's S into
+    // registers (one wave per SIMD)
+    // groups of four MFMA steps without early exit (steps past cn multiply zero rows of S by a
+    // clamped, finite X): the four loads of a group are in flight together
+    const int nu = (cn + G - 1) / G;
+    for (int u0 = 0; u0 < nu; u0 += 4) {
+      c2<T> xv[4];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      if (u * G >= cn) break;
-      const T xr = xv[u].x, xi = xv[u].y;
-      const int ci = u * G + kg;
+      for (int k = 0; k < 4; ++k) {
+        const int ci = (u0 + k) * G + kg, c = c0 + ci;
+        xv[k] = X[(size_t)(c < s ? c : s - 1) * ldx + rowc];
+      }
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const T ar = sr[ci * QP + t * R + (lane % R)], ai = si[ci * QP + t * R + (lane % R)];
-        accr[t] = M::mma(ar, xr, accr[t]);
-        accr[t] = M::mma(ai, -xi, accr[t]);
-        acci[t] = M::mma(ai, xr, acci[t]);
-        acci[t] = M::mma(ar, xi, acci[t]);
+      for (int k = 0; k < 4; ++k) {
+        const int ci = (u0 + k) * G + kg;
+        const int cs = ci < SC ? ci : SC - 1;  // rows of the staged chunk past cn are zero
+        const T xr = xv[k].x, xi = xv[k].y;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const T ar = sr[cs * QP + t * R + (lane % R)], ai = si[cs * QP + t * R + (lane % R)];
+          accr[t] = M::mma(ar, xr, accr[t]);
+          acci[t] = M::mma(ai, xr, acci[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const T ar = sr[cs * QP + t * R + (lane % R)], ai = si[cs * QP + t * R + (lane % R)];
+          accr[t] = M::mma(ai, -xi, accr[t]);
+          acci[t] = M::mma(ar, xi, acci[t]);
+        }
       }
     }
   }
