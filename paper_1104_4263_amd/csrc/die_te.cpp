@@ -1746,7 +1746,8 @@ int planar_shadow(BlockWork& bw, const c2<T>* X, size_t n, int p, int j, size_t 
 // npass block classical Gram-Schmidt passes of W (n x p) against the first nq basis columns on
 // the matrix cores: per pass H_pass = Q^H W (nq x p, rounded to E) and W -= Q H_pass as real
 // products of the planar shadows.  W is split into the planar Wacc (basis precision) and stays
-// there, its T1 copy remade for each projection; the caller merges it back.
+// there, its T1 copy remade for each projection; the caller's CholQR factor application reads it
+// planar and writes the complex block.
 template <class T, class E>
 int planar_block_cgs(die_te_ctx* c, BlockWork& bw, const c2<T>* W, size_t n, int nq, int p, int npass, size_t nrow,
                      size_t ccap, c2<T>* const* H, hipStream_t st) {
@@ -2144,8 +2145,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
           DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp, ldhp * sizeof(c2<T>), hc[0], nq * sizeof(c2<T>),
                                    nq * sizeof(c2<T>), p, hipMemcpyDeviceToDevice, st));
         // CholQR of the orthogonalised block (planar in Wacc): the first Gram from the planar
-        // copy, then W back to complex; each factor application writes the other buffer, and
-        // the result ends in W
+        // copy; the result ends in W
         T* ws = bw.Wacc.as<T>();
         Mat Gw, Q1, Q2;
         DIE_TRY(gram_planar<T>(bw, ws, nrow, p, Gw, st));
@@ -2154,14 +2154,12 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         // a well-conditioned block (smallest scaled pivot >= kCholQRSinglePivot, condition <= ~4.5)
         // is orthonormal to about cond^2 times the Gram's rounding after one CholQR pass
         const bool single = ok && piv1 >= kCholQRSinglePivot;
-        // the planar block back to complex where the factor applications leave the result in W
-        // (one pass: merged into Wt, applied into W; two passes: W -> Wt -> W), so no copy follows
-        c2<T>* wa = single ? Wt.as<c2<T>>() : W;
+        // the first factor application reads the planar block and writes complex (one pass: into
+        // W; two passes: into Wt, whose Gram gives the second factor, applied from Wt into W)
         c2<T>* wb = single ? W : Wt.as<c2<T>>();
-        DIE_HIP((die::launch_tsq_merge<T, T>(ws, nrow, n, p, wa, n, st)));
         if (ok) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q1), sm.p, slot[0], st));
-          DIE_HIP(die::launch_cplx_rmul<T>(wa, n, p, sm.as<c2<T>>(), p, p, n, wb, n, st));
+          DIE_HIP(die::launch_cplx_rmul_planar<T>(ws, nrow, p, sm.as<c2<T>>(), p, p, n, wb, n, st));
           if (!single) {
             DIE_TRY(gram_complex<T>(bw, wb, n, nrow, p, ws, Gw, st));
             ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
@@ -2174,7 +2172,7 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         }
         if (!single) {
           DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
-          DIE_HIP(die::launch_cplx_rmul<T>(wb, n, p, sm.as<c2<T>>(), p, p, n, wa, n, st));
+          DIE_HIP(die::launch_cplx_rmul<T>(wb, n, p, sm.as<c2<T>>(), p, p, n, W, n, st));
         }
         DIE_TRY(shadow(W, p, j + 1));
         const Mat Hs = single ? Q1 : la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1 (Q2 = I: one pass)

@@ -186,16 +186,6 @@ __global__ void k_planar_to_t1(const A* __restrict__ Ws, size_t ldw, size_t nrow
   for (int i = 0; i < KV; ++i) d[i] = (E)s[i];
 }
 
-// X (n x p complex, leading dimension ldx) from the planar Ws.
-template <class A, class T>
-__global__ void k_planar_merge(const A* __restrict__ Ws, size_t ldw, size_t n, int p, c2<T>* __restrict__ X,
-                               size_t ldx) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * (size_t)p) return;
-  const size_t q = e / n, r = e - q * n;
-  X[q * ldx + r] = mk<T>((T)Ws[q * ldw + r], (T)Ws[(p + q) * ldw + r]);
-}
-
 // ---- projection: part[h][b ma + a] = sum over the rows n of chunk h of A(n, a) B(n, b)
 // for a < ma, b < nb.  A and B in T1 with nrow rows, or (NF) planar with the rows contiguous
 // (leading dimension nrow, rows past the data zero; a buffer of whole 32-column tiles).
@@ -496,9 +486,10 @@ k_tsq_update(const E* __restrict__ A2, int mc, size_t ccap, size_t nrow, const E
 // transposed).  S is staged through LDS 64 rows at a time as real and imaginary planes [c][j]
 // (zero past s and q); each lane reads one complex value of X per MFMA step (the loop is
 // unrolled four steps deep, so that their loads are in flight together).  X and Y are distinct.
-template <class T, int NT>
+// PLANAR: X is held planar in T (column c's real parts at c ldx, its imaginary parts at (s + c) ldx).
+template <class T, int NT, bool PLANAR = false>
 __global__ void __launch_bounds__(256)
-k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restrict__ S, int lds, int q, size_t n,
+k_cplx_rmul(const void* __restrict__ Xv, size_t ldx, int s, const c2<T>* __restrict__ S, int lds, int q, size_t n,
             c2<T>* __restrict__ Y, size_t ldy) {
   using M = Mf1<T>;
   constexpr int R = M::R, G = 64 / R, SC = 64, QP = NT * R + 1, NU = SC / G;
@@ -545,7 +536,13 @@ k_cplx_rmul(const c2<T>* __restrict__ X, size_t ldx, int s, const c2<T>* __restr
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int ci = (u0 + k) * G + kg, c = c0 + ci;
-        xv[k] = X[(size_t)(c < s ? c : s - 1) * ldx + rowc];
+        const size_t cc = (size_t)(c < s ? c : s - 1);
+        if constexpr (PLANAR) {
+          const T* Xs = static_cast<const T*>(Xv);
+          xv[k] = mk<T>(Xs[cc * ldx + rowc], Xs[(s + cc) * ldx + rowc]);
+        } else {
+          xv[k] = static_cast<const c2<T>*>(Xv)[cc * ldx + rowc];
+        }
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -698,14 +695,6 @@ hipError_t launch_tsq_to_t1(const A* Ws, size_t ldw, size_t nrow, int nb, E* B1,
   if (nb < 1 || nrow % 32 || ldw < nrow) return hipErrorInvalidValue;
   const size_t work = nrow / GemmTile<E>::KV * (size_t)nb;
   hipLaunchKernelGGL((k_planar_to_t1<A, E>), dim3(blocks_for(work)), dim3(256), 0, st, Ws, ldw, nrow, nb, B1);
-  return hipGetLastError();
-}
-
-template <class A, class T>
-hipError_t launch_tsq_merge(const A* Ws, size_t ldw, size_t n, int p, c2<T>* X, size_t ldx, hipStream_t st) {
-  if (p < 1 || ldw < n || ldx < n) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_planar_merge<A, T>), dim3(blocks_for(n * (size_t)p)), dim3(256), 0, st, Ws, ldw, n, p, X,
-                     ldx);
   return hipGetLastError();
 }
 
@@ -900,27 +889,32 @@ hipError_t launch_gram_planar(const A* Xs, size_t nrow, int p, A* part, size_t p
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
-                            size_t ldy, hipStream_t st) {
-  if (s < 1 || q < 1 || q > 64 || lds < s || ldx < n || ldy < n || (const void*)X == (const void*)Y)
+namespace {
+template <class T, bool PLANAR>
+hipError_t cplx_rmul(const void* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y, size_t ldy,
+                     hipStream_t st) {
+  if (s < 1 || q < 1 || q > 64 || lds < s || (!PLANAR && ldx < n) || ldy < n || X == (const void*)Y)
     return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   constexpr int R = Mf1<T>::R;
   const int nt = (q + R - 1) / R;
   const unsigned grid = (unsigned)((n + 4 * R - 1) / (4 * R));
   switch (nt) {
-    case 1: hipLaunchKernelGGL((k_cplx_rmul<T, 1>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy); break;
-    case 2: hipLaunchKernelGGL((k_cplx_rmul<T, 2>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy); break;
+    case 1:
+      hipLaunchKernelGGL((k_cplx_rmul<T, 1, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_cplx_rmul<T, 2, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+      break;
     case 3:
       if constexpr (R == 16) {
-        hipLaunchKernelGGL((k_cplx_rmul<T, 3>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+        hipLaunchKernelGGL((k_cplx_rmul<T, 3, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
         break;
       }
       return hipErrorInvalidValue;
     case 4:
       if constexpr (R == 16) {
-        hipLaunchKernelGGL((k_cplx_rmul<T, 4>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+        hipLaunchKernelGGL((k_cplx_rmul<T, 4, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
         break;
       }
       return hipErrorInvalidValue;
@@ -928,6 +922,20 @@ hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, i
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+}  // namespace
+
+template <class T>
+hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
+                            size_t ldy, hipStream_t st) {
+  return cplx_rmul<T, false>(X, ldx, s, S, lds, q, n, Y, ldy, st);
+}
+
+template <class T>
+hipError_t launch_cplx_rmul_planar(const T* Xs, size_t ldw, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
+                                   size_t ldy, hipStream_t st) {
+  if (ldw < n) return hipErrorInvalidValue;
+  return cplx_rmul<T, true>(Xs, ldw, s, S, lds, q, n, Y, ldy, st);
 }
 
 namespace {
@@ -965,8 +973,9 @@ hipError_t launch_cadd2(const c2<T>* A, int lda, const c2<T>* B, int ldb, int ro
 }
 
 #define DIE_INST_T(T)                                                                                              \
-  template hipError_t launch_tsq_merge<T, T>(const T*, size_t, size_t, int, c2<T>*, size_t, hipStream_t);          \
   template hipError_t launch_gram_planar<T>(const T*, size_t, int, T*, size_t, double*, size_t, double2*, hipStream_t); \
+  template hipError_t launch_cplx_rmul_planar<T>(const T*, size_t, int, const c2<T>*, int, int, size_t, c2<T>*,      \
+                                                  size_t, hipStream_t);                                              \
   template hipError_t launch_cplx_rmul<T>(const c2<T>*, size_t, int, const c2<T>*, int, int, size_t, c2<T>*, size_t, \
                                           hipStream_t);                                                             \
   template hipError_t launch_cadd2<T>(const c2<T>*, int, const c2<T>*, int, int, int, c2<T>*, int, hipStream_t);

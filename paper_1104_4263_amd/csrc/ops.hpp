@@ -159,9 +159,6 @@ hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0,
 // B1 (T1, columns 0 .. nb - 1) from the planar Ws (nrow rows, leading dimension ldw).
 template <class A, class E>
 hipError_t launch_tsq_to_t1(const A* Ws, size_t ldw, size_t nrow, int nb, E* B1, hipStream_t st);
-// X (n x p complex) from the planar Ws.
-template <class A, class T>
-hipError_t launch_tsq_merge(const A* Ws, size_t ldw, size_t n, int p, c2<T>* X, size_t ldx, hipStream_t st);
 // part[h][b ma + a] = sum over the rows of chunk h of A(n, a) B(n, b) (A: ma columns, B: nb <= 128
 // columns, both T1 with nrow rows); the chunk count (at most part_cap / (ma nb)) goes to *nch.
 template <class E>
@@ -192,6 +189,11 @@ hipError_t launch_gram_planar(const A* Xs, size_t nrow, int p, A* part, size_t p
 template <class T>
 hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
                             size_t ldy, hipStream_t st);
+// The same with X held planar in T (Xs: column c's real parts at c ldw, its imaginary parts at
+// (s + c) ldw, ldw >= n).
+template <class T>
+hipError_t launch_cplx_rmul_planar(const T* Xs, size_t ldw, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
+                                   size_t ldy, hipStream_t st);
 // R Y = B in place in B (nc x k, leading dimension ldb) for the upper triangular R (leading
 // dimension ldr), nc <= kTrsmMaxRows.
 constexpr int kTrsmMaxRows = 4096;
