@@ -171,6 +171,50 @@ __global__ void k_split_t2(const c2<T>* __restrict__ X, size_t ldx, size_t n, in
   }
 }
 
+// Both shadows at once (KV x KV planar sub-squares, p % KV == 0 and c0 % KV == 0): one thread per
+// group of KV rows and KV complex columns reads their KV x KV values once (KV consecutive rows of
+// each column, consecutive threads on consecutive row groups) and writes the 2 KV vectors of their
+// real and imaginary columns into A1 (KV rows each) and the 2 KV vectors of their rows into A2
+// (KV columns each).
+template <class T, class E>
+__global__ void __launch_bounds__(256) k_split_t12(const c2<T>* __restrict__ X, size_t ldx, size_t n, int p, int c0, size_t nrow,
+                            size_t ccap, E* __restrict__ A1, E* __restrict__ A2) {
+  using V = typename Mf<E>::V;
+  constexpr int KV = GemmTile<E>::KV;
+  const size_t groups = nrow / KV;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= groups * (size_t)(p / KV)) return;
+  const int cg = (int)(e / groups);
+  const size_t n0 = (e - (size_t)cg * groups) * KV;
+  V re[KV], im[KV];  // re[i][r]: column cg KV + i, row n0 + r
+#pragma unroll
+  for (int i = 0; i < KV; ++i) {
+    const c2<T>* xc = X + (size_t)(cg * KV + i) * ldx + n0;
+#pragma unroll
+    for (int r = 0; r < KV; ++r) {
+      const c2<T> z = n0 + r < n ? xc[r] : mk<T>((T)0, (T)0);
+      re[i][r] = (E)z.x;
+      im[i][r] = (E)z.y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KV; ++i) {
+    *reinterpret_cast<V*>(A1 + GemmTile<E>::t1(n0, (size_t)(c0 + cg * KV + i), nrow)) = re[i];
+    *reinterpret_cast<V*>(A1 + GemmTile<E>::t1(n0, (size_t)(c0 + p + cg * KV + i), nrow)) = im[i];
+  }
+#pragma unroll
+  for (int r = 0; r < KV; ++r) {
+    V vr, vi;
+#pragma unroll
+    for (int i = 0; i < KV; ++i) {
+      vr[i] = re[i][r];
+      vi[i] = im[i][r];
+    }
+    *reinterpret_cast<V*>(A2 + GemmTile<E>::t2(n0 + r, (size_t)(c0 + cg * KV), ccap)) = vr;
+    *reinterpret_cast<V*>(A2 + GemmTile<E>::t2(n0 + r, (size_t)(c0 + p + cg * KV), ccap)) = vi;
+  }
+}
+
 // T1 copy (columns 0 .. nb - 1) of the planar block Ws (nrow rows, leading dimension ldw).
 template <class A, class E>
 __global__ void k_planar_to_t1(const A* __restrict__ Ws, size_t ldw, size_t nrow, int nb, E* __restrict__ B1) {
@@ -671,6 +715,11 @@ hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0,
       (Ws && A1 && c0 != 0))
     return hipErrorInvalidValue;
   constexpr int KV = GemmTile<E>::KV;
+  if (!Ws && A1 && A2 && p % KV == 0 && c0 % KV == 0) {  // both shadows from one read of X
+    hipLaunchKernelGGL((k_split_t12<T, E>), dim3(blocks_for(nrow / KV * (size_t)(p / KV))), dim3(256), 0, st, X, ldx,
+                       n, p, c0, nrow, ccap, A1, A2);
+    return hipGetLastError();
+  }
   if (Ws)
     hipLaunchKernelGGL((k_split_planar<T, A>), dim3(blocks_for(nrow * (size_t)p)), dim3(256), 0, st, X, ldx, n, p,
                        nrow, Ws, ldw);
