@@ -227,14 +227,17 @@ template <class T> const c2<T>* chi_of(const die_te_ctx* c, bool reg);
 template <class T> const c2<T>* sym_of(const die_te_ctx* c);
 
 // Launch pass `pass` (0 rows, 1 columns + symbol, 2 inverse rows) of a product on R fields.
+// planar: pass 3 writes y planar (real parts of right-hand side r at planar[r ldp], imaginary parts at
+// planar[(R + r) ldp]) instead of into y.
 template <class T>
 hipError_t launch_pass(die_te_ctx* c, int pass, int v, const c2<T>* x, c2<T>* y, c2<T>* W, int R, const int* live,
-                       hipStream_t st, int rpo, const c2<T>* chi, const c2<T>* chi2) {
+                       hipStream_t st, int rpo, const c2<T>* chi, const c2<T>* chi2, T* planar = nullptr,
+                       size_t ldp = 0) {
   const int nc = c->ncomp;
   if (pass == 0)
     return die::launch_rows_fwd<T, T>(c->lpx, false, x, chi, chi2, W, c->nx, c->ny, R, nc, 0, rpo, live, st, v);
   if (pass == 1) return die::launch_cols_symbol<T>(c->lpy, nc, W, sym_of<T>(c), c->px, c->ny, R, live, st, v);
-  return die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, nc * R, nc, live, st, v);
+  return die::launch_rows_inv_sub<T, T>(c->lpx, W, x, y, c->nx, c->ny, nc * R, nc, live, st, v, planar, ldp, R);
 }
 
 // The variants of the three passes for products of nrhs fields; tunes them first if needed
@@ -324,7 +327,7 @@ int fft_plan(die_te_ctx* c, int nrhs, hipStream_t st, const int** out) {
 // Right-hand side r uses object obj0 + r / rpo (rpo = 0: every right-hand side uses object obj0).
 template <class T>
 int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const int* live, hipStream_t st,
-             int rpo, int obj0 = 0) {
+             int rpo, int obj0 = 0, T* planar = nullptr, size_t ldp = 0) {
   const int* v = nullptr;
   DIE_TRY(fft_plan<T>(c, nrhs, st, &v));
   DIE_TRY(ensure_work(c, work_bytes(c, nrhs, sizeof(c2<T>)), st));
@@ -335,19 +338,20 @@ int apply_op(die_te_ctx* c, const c2<T>* x, c2<T>* y, int nrhs, bool reg, const 
   const c2<T>* chi2 = chi2_of<T>(c, reg);
   if (chi2) chi2 += (size_t)obj0 * c->ncell;
   for (int pass = 0; pass < 3; ++pass)
-    DIE_HIP(launch_pass<T>(c, pass, v[pass], x, y, W, nrhs, live, st, rpo, chi, chi2));
+    DIE_HIP(launch_pass<T>(c, pass, v[pass], x, y, W, nrhs, live, st, rpo, chi, chi2, planar, ldp));
   return DIE_OK;
 }
 
 // Solved operator M = A_R A (regularized) or A: out = M in, tmp is a scratch field set.
 template <class T>
+// (planar: out is written planar instead, as launch_pass describes)
 int apply_M(die_te_ctx* c, bool reg, const c2<T>* in, c2<T>* tmp, c2<T>* out, int nrhs, const int* live,
-            hipStream_t st, int rpo, int obj0 = 0) {
+            hipStream_t st, int rpo, int obj0 = 0, T* planar = nullptr, size_t ldp = 0) {
   if (reg) {
     DIE_TRY(apply_op<T>(c, in, tmp, nrhs, false, live, st, rpo, obj0));
-    DIE_TRY(apply_op<T>(c, tmp, out, nrhs, true, live, st, rpo, obj0));
+    DIE_TRY(apply_op<T>(c, tmp, out, nrhs, true, live, st, rpo, obj0, planar, ldp));
   } else {
-    DIE_TRY(apply_op<T>(c, in, out, nrhs, false, live, st, rpo, obj0));
+    DIE_TRY(apply_op<T>(c, in, out, nrhs, false, live, st, rpo, obj0, planar, ldp));
   }
   return DIE_OK;
 }
@@ -1745,17 +1749,20 @@ int planar_shadow(BlockWork& bw, const c2<T>* X, size_t n, int p, int j, size_t 
 
 // npass block classical Gram-Schmidt passes of W (n x p) against the first nq basis columns on
 // the matrix cores: per pass H_pass = Q^H W (nq x p, rounded to E) and W -= Q H_pass as real
-// products of the planar shadows.  W is split into the planar Wacc (basis precision) and stays
-// there, its T1 copy remade for each projection; the caller's CholQR factor application reads it
-// planar and writes the complex block.
+// products of the planar shadows.  W is split into the planar Wacc (basis precision; planar_in:
+// the product wrote it there) and stays there, its T1 copy remade for each projection; the caller's
+// CholQR factor application reads it planar and writes the complex block.
 template <class T, class E>
 int planar_block_cgs(die_te_ctx* c, BlockWork& bw, const c2<T>* W, size_t n, int nq, int p, int npass, size_t nrow,
-                     size_t ccap, c2<T>* const* H, hipStream_t st) {
+                     size_t ccap, c2<T>* const* H, hipStream_t st, bool planar_in = false) {
   using A = typename die::GemmTile<E>::Acc;
   A* Ws = bw.Wacc.as<A>();
   E* W1 = bw.W1.as<E>();
   const int M = 2 * nq, P2 = 2 * p, ldhb = (int)die::gemm_pad((size_t)M);
-  DIE_HIP((die::launch_tsq_split<T, A, E>(W, n, n, p, 0, nrow, ccap, Ws, nrow, W1, nullptr, st)));
+  if (planar_in)  // the product wrote W planar into Wacc already
+    DIE_HIP((die::launch_tsq_to_t1<A, E>(Ws, nrow, nrow, P2, W1, st)));
+  else
+    DIE_HIP((die::launch_tsq_split<T, A, E>(W, n, n, p, 0, nrow, ccap, Ws, nrow, W1, nullptr, st)));
   for (int pass = 0; pass < npass; ++pass) {
     if (pass > 0) DIE_HIP((die::launch_tsq_to_t1<A, E>(Ws, nrow, nrow, P2, W1, st)));
     int nch = 0;
@@ -1877,6 +1884,8 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   } else {
     DIE_TRY((planar_alloc<T, T>(bw, nrow, ccap, pw)));
   }
+  // rows n .. nrow - 1 of the planar block stay zero (the products write rows below n only)
+  if (nrow > n) DIE_HIP(hipMemsetAsync(bw.Wacc.p, 0, bw.Wacc.bytes, st));
   auto shadow = [&](const c2<T>* X, int p, int j) -> int {
     if constexpr (std::is_same<T, float>::value)
       if (hgemm) return planar_shadow<T, _Float16>(bw, X, n, p, j, nrow, ccap, st);
@@ -2127,16 +2136,19 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
                                 st, p, ob));
           z = Zb.as<c2<T>>();
         }
-        DIE_TRY(apply_M<T>(c, reg, z, reg ? Tm.as<c2<T>>() : nullptr, W, p, nullptr, st, 0, ob));
+        // the product of the new block goes planar into Wacc (its complex form is made only after
+        // the Gram-Schmidt passes and CholQR, by the factor application into W)
+        DIE_TRY(apply_M<T>(c, reg, z, reg ? Tm.as<c2<T>>() : nullptr, W, p, nullptr, st, 0, ob, bw.Wacc.as<T>(),
+                           nrow));
         const int nq = (j + 1) * p;
         c2<T>* hc[2] = {sm.as<c2<T>>(), sm2.as<c2<T>>()};  // the projections (nq x p each)
         if constexpr (std::is_same<T, float>::value) {
           if (hgemm)
-            DIE_TRY((planar_block_cgs<T, _Float16>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st)));
+            DIE_TRY((planar_block_cgs<T, _Float16>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st, true)));
           else
-            DIE_TRY((planar_block_cgs<T, T>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st)));
+            DIE_TRY((planar_block_cgs<T, T>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st, true)));
         } else {
-          DIE_TRY((planar_block_cgs<T, T>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st)));
+          DIE_TRY((planar_block_cgs<T, T>(c, bw, W, n, nq, p, npass, nrow, ccap, hc, st, true)));
         }
         // column block j of H: the sum of the projections
         if (npass == 2)

@@ -268,7 +268,8 @@ k_cols_plain(c2<T>* __restrict__ W, const c2<T>* __restrict__ tw, int ncols, int
 template <class T, class S, int LOGN, int V = 0>
 __global__ void __launch_bounds__(rows_threads<T>(LOGN, V))
 k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* __restrict__ y,
-               const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int spr, const int* __restrict__ live) {
+               const c2<T>* __restrict__ tw, int nx, int nrows, int ntiles, int spr, const int* __restrict__ live,
+               S* __restrict__ planar, size_t ldp, int pw) {
   using F = RegFft<T, LOGN, rows_ty<T>(LOGN, V), fft_le<T>(LOGN, V), 1, false, kArrFast, kPosFast>;
   constexpr int N = F::N, E = F::E, TY = rows_ty<T>(LOGN, V);
   __shared__ c2<T> lds[F::LDS_ELEMS];
@@ -301,7 +302,15 @@ k_rows_inv_sub(const c2<T>* __restrict__ W, const c2<S>* __restrict__ u, c2<S>* 
       if (q * (N / F::RL) < N / 2) {  // only columns < nx <= N/2 are kept
         const size_t o = so + (size_t)min(yy, nrows - 1) * nx + min(pos, nx - 1);
         const c2<T> d = csub<T>(ld<T, S>(u + o), v[0][uu * F::RL + q]);  // unconditional (clamped) load
-        if (pos < nx && yy < nrows) st<S, T>(y + o, d);
+        if (pos < nx && yy < nrows) {
+          if (planar) {  // uniform: right-hand side s / spr, component s % spr
+            const size_t i = (size_t)(s % spr) * nrows * nx + (size_t)yy * nx + pos, r = (size_t)(s / spr);
+            planar[r * ldp + i] = (S)d.x;
+            planar[((size_t)pw + r) * ldp + i] = (S)d.y;
+          } else {
+            st<S, T>(y + o, d);
+          }
+        }
       }
     }
 }
@@ -489,7 +498,8 @@ hipError_t launch_cols_symbol(int logn, int ncomp, c2<T>* W, const c2<T>* sym, i
 
 template <class T, class S>
 hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y, int nx, int nrows, int nsets,
-                               int spr, const int* live, hipStream_t st, int v) {
+                               int spr, const int* live, hipStream_t st, int v, S* planar, size_t ldp, int pw) {
+  if (planar && (ldp < (size_t)spr * nrows * nx || pw < nsets / spr)) return hipErrorInvalidValue;
   const c2<T>* tw = table_for<T>();
   if (!tw) return hipErrorNotInitialized;
   if (nsets <= 0 || nrows <= 0) return hipSuccess;
@@ -502,7 +512,7 @@ hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* 
       const int ntiles = (nrows + rows_ty<T>(L, V) - 1) / rows_ty<T>(L, V);                             \
       dim3 grid((unsigned)(ntiles * nsets));                                                            \
       hipLaunchKernelGGL((k_rows_inv_sub<T, S, L, V>), grid, dim3(rows_threads<T>(L, V)), 0, st, W, u, y, tw, nx, \
-                         nrows, ntiles, spr, live);                                                     \
+                         nrows, ntiles, spr, live, planar, ldp, pw);                                    \
     });                                                                                                 \
     break;                                                                                              \
   }
@@ -565,9 +575,10 @@ template hipError_t launch_cols_symbol<double>(int, int, double2*, const double2
 template hipError_t launch_cols_symbol<float>(int, int, float2*, const float2*, int, int, int, const int*,
                                               hipStream_t, int);
 template hipError_t launch_rows_inv_sub<double, double>(int, const double2*, const double2*, double2*, int,
-                                                        int, int, int, const int*, hipStream_t, int);
+                                                        int, int, int, const int*, hipStream_t, int, double*, size_t,
+                                                        int);
 template hipError_t launch_rows_inv_sub<float, float>(int, const float2*, const float2*, float2*, int, int,
-                                                      int, int, const int*, hipStream_t, int);
+                                                      int, int, const int*, hipStream_t, int, float*, size_t, int);
 template hipError_t launch_cols_plain<double>(int, bool, double2*, int, int, hipStream_t);
 template hipError_t launch_cols_plain<float>(int, bool, float2*, int, int, hipStream_t);
 template hipError_t launch_transpose<double>(const double2*, double2*, int, int, int, hipStream_t);

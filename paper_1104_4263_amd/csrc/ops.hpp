@@ -55,10 +55,13 @@ hipError_t launch_cols_symbol(int logn, int ncomp, c2<T>* W, const c2<T>* sym, i
                               const int* live, hipStream_t st, int v = 0);
 
 // Pass 3.  y_out[s][y][x] = u[s][y][x] - IFFT_N(W[s][:][y])[x] for x < nx (W tiled).
+// With planar (a real array in S), y is written planar instead: right-hand side r's element i
+// (i = component nrows nx + y nx + x) to planar[r ldp + i] (real) and planar[(pw + r) ldp + i]
+// (imaginary), y_out unused.
 template <class T, class S>
 hipError_t launch_rows_inv_sub(int logn, const c2<T>* W, const c2<S>* u, c2<S>* y_out, int nx,
                                int nrows, int nsets, int sets_per_rhs, const int* live,
-                               hipStream_t st, int v = 0);
+                               hipStream_t st, int v = 0, S* planar = nullptr, size_t ldp = 0, int pw = 0);
 
 // Full-length FFT along the contiguous axis of W[nsets][ncols][N], in place.
 template <class T>
