@@ -111,6 +111,110 @@ k_conv(const bf16raw* __restrict__ X, int B, int H, int W, int cin, int taps, co
   }
 }
 
+// 3x3 convolutions with their operands staged in LDS (W % 32 == 0, cin % 16 == 0, cout a multiple
+// of 32 NCO).  Block: 4 image rows x 32 pixels x 32 NCO output channels, wave w on row w.  For each
+// chunk of 16 input channels the input patch (6 rows x 34 pixels with the halo, zero outside the
+// image) and the weights of the chunk (9 taps x 32 NCO channels x 16) are staged once; every tap's
+// A operand is then a 16-byte LDS read of the patch shifted by that tap (so each staged input
+// value serves nine MFMAs of the wave and the rows above and below), and each B operand is shared
+// by the four waves.  The next chunk's global loads are in flight while the current one is
+// multiplied.
+constexpr int kCvRows = 4, kCvPx = 32, kCvCi = 16;
+constexpr int kCvPr = kCvRows + 2, kCvPq = kCvPx + 2;  // patch rows and pixels with the halo
+
+template <bool FLIP, bool RELU, int OUT, int NCO>
+__global__ void __launch_bounds__(NT)
+k_conv_lds(const bf16raw* __restrict__ X, int H, int W, int cin, const bf16raw* __restrict__ Wm,
+           const float* __restrict__ bias, void* __restrict__ out, int cout) {
+  constexpr int NB = 32 * NCO;
+  constexpr int AITEMS = kCvPr * kCvPq * 2;   // 16-byte loads of the patch (two per pixel)
+  constexpr int BITEMS = 9 * NB * 2;          // 16-byte loads of the chunk's weights
+  constexpr int IA = (AITEMS + NT - 1) / NT, IB = (BITEMS + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) bf16raw sA[kCvPr * kCvPq * kCvCi];
+  __shared__ __attribute__((aligned(16))) bf16raw sB[9 * NB * kCvCi];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, r32 = lane & 31;
+  const int tiles_x = W / kCvPx, tiles_y = (H + kCvRows - 1) / kCvRows;
+  const int tx = blockIdx.x % tiles_x, rest = blockIdx.x / tiles_x;
+  const int ty = rest % tiles_y, b = rest / tiles_y;
+  const int x0 = tx * kCvPx, y0 = ty * kCvRows, n0 = blockIdx.y * NB;
+  const int K = 9 * cin;
+  u32x4 ra[IA], rb[IB];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < IA; ++k) {
+      const int i = tid + k * NT;
+      const int half = i & 1, pq = (i >> 1) % kCvPq, pr = (i >> 1) / kCvPq;
+      const int yy = y0 - 1 + pr, xx = x0 - 1 + pq;
+      ra[k] = u32x4{0u, 0u, 0u, 0u};
+      if (i < AITEMS && yy >= 0 && yy < H && xx >= 0 && xx < W)
+        ra[k] = *reinterpret_cast<const u32x4*>(X + (((size_t)b * H + yy) * W + xx) * cin + c0 + 8 * half);
+    }
+#pragma unroll
+    for (int k = 0; k < IB; ++k) {
+      const int i = tid + k * NT;
+      const int half = i & 1, nn = (i >> 1) % NB, t = (i >> 1) / NB;
+      rb[k] = u32x4{0u, 0u, 0u, 0u};
+      if (i < BITEMS) rb[k] = *reinterpret_cast<const u32x4*>(Wm + (size_t)(n0 + nn) * K + t * cin + c0 + 8 * half);
+    }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int k = 0; k < IA; ++k) {
+      const int i = tid + k * NT;
+      if (i < AITEMS) *reinterpret_cast<u32x4*>(&sA[(i >> 1) * kCvCi + 8 * (i & 1)]) = ra[k];
+    }
+#pragma unroll
+    for (int k = 0; k < IB; ++k) {
+      const int i = tid + k * NT;
+      if (i < BITEMS) *reinterpret_cast<u32x4*>(&sB[(i >> 1) * kCvCi + 8 * (i & 1)]) = rb[k];
+    }
+  };
+  floatx16 acc[NCO];
+#pragma unroll
+  for (int c = 0; c < NCO; ++c)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[c][i] = 0.f;
+  load(0);
+  for (int c0 = 0; c0 < cin; c0 += kCvCi) {
+    lds_sync();  // the previous chunk's LDS reads are done
+    put();
+    lds_sync();
+    if (c0 + kCvCi < cin) load(c0 + kCvCi);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      int dy = t / 3 - 1, dx = t % 3 - 1;
+      if (FLIP) {
+        dy = -dy;
+        dx = -dx;
+      }
+      const u32x4 av = *reinterpret_cast<const u32x4*>(
+          &sA[((wave + 1 + dy) * kCvPq + r32 + 1 + dx) * kCvCi + 8 * g]);
+#pragma unroll
+      for (int c = 0; c < NCO; ++c) {
+        const u32x4 bv = *reinterpret_cast<const u32x4*>(&sB[(t * NB + 32 * c + r32) * kCvCi + 8 * g]);
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv), acc[c], 0, 0, 0);
+      }
+    }
+  }
+  const int y = y0 + wave;
+  if (y >= H) return;
+#pragma unroll
+  for (int c = 0; c < NCO; ++c) {
+    const int n = n0 + 32 * c + r32;
+    const float bn = bias ? bias[n] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int px = x0 + (i / 4) * 8 + g * 4 + (i % 4);
+      float v = acc[c][i] + bn;
+      if (RELU) v = fmaxf(v, 0.f);
+      const size_t o = (((size_t)b * H + y) * W + px) * cout + n;
+      if (OUT == kOutBf16) static_cast<bf16raw*>(out)[o] = f2bf(v);
+      else if (OUT == kOutF32) static_cast<float*>(out)[o] = v;
+      else static_cast<float*>(out)[o] += v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ weight gradient
 // Tile: rows co0..co0+31 (A = dZ^T), columns n0..n0+31 of (t, ci) (B = shifted X), one
 // split of the pixels per blockIdx.z, 8 consecutive pixels of one image row per lane
@@ -540,6 +644,23 @@ k_unpack_guess(const double2* __restrict__ e_in, const float* __restrict__ y, do
 hipError_t launch_conv(const bf16raw* X, int B, int H, int W, int cin, int taps, bool flip, const bf16raw* Wm,
                        const float* bias, bool relu, void* out, int cout, ConvOut mode, hipStream_t st) {
   if (cin % 8 || (taps != 1 && taps != 9) || B < 1 || H < 1 || W < 1 || cout < 1) return hipErrorInvalidValue;
+  if (taps == 9 && W % kCvPx == 0 && cin % kCvCi == 0 && cout % 32 == 0) {
+    const int nco = cout % 64 == 0 ? 2 : 1;
+    const long tiles = (long)B * ((H + kCvRows - 1) / kCvRows) * (W / kCvPx);
+    dim3 g((unsigned)tiles, (unsigned)(cout / (32 * nco)));
+#define DIE_CONV_LDS(F, R, O)                                                                                  \
+  do {                                                                                                         \
+    if (nco == 2) hipLaunchKernelGGL((k_conv_lds<F, R, O, 2>), g, dim3(NT), 0, st, X, H, W, cin, Wm, bias, out, cout); \
+    else hipLaunchKernelGGL((k_conv_lds<F, R, O, 1>), g, dim3(NT), 0, st, X, H, W, cin, Wm, bias, out, cout);    \
+  } while (0)
+    if (!flip && relu && mode == kOutBf16) DIE_CONV_LDS(false, true, kOutBf16);
+    else if (!flip && !relu && mode == kOutF32) DIE_CONV_LDS(false, false, kOutF32);
+    else if (flip && !relu && mode == kOutF32) DIE_CONV_LDS(true, false, kOutF32);
+    else if (flip && !relu && mode == kOutF32Add) DIE_CONV_LDS(true, false, kOutF32Add);
+    else return hipErrorInvalidValue;
+#undef DIE_CONV_LDS
+    return hipGetLastError();
+  }
   const long M = (long)B * H * W;
   dim3 grid((unsigned)((M + 127) / 128), (unsigned)((cout + 31) / 32));
 #define DIE_CONV(F, R, O) \

@@ -18,6 +18,9 @@ api = pytest.importorskip("paper_1104_4263_amd.api")
 from paper_1104_4263_amd._lib import DieTeError  # noqa: E402
 
 CONFIGS = [(1, 8, 8, 8, 2), (2, 8, 16, 16, 2), (3, 16, 32, 32, 1), (2, 16, 16, 48, 3)]
+# base 32 on 64 x 64: every 3x3 layer but the first and its adjoints take the LDS-staged convolution
+# (widths multiples of 32, both output-tile widths)
+LDS_CONV = (2, 32, 64, 64, 1)
 
 
 def rand_inputs(rng, B, H, W):
@@ -28,7 +31,7 @@ def params_of(net):
     return net.get_params().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("levels,base,H,W,B", CONFIGS)
+@pytest.mark.parametrize("levels,base,H,W,B", CONFIGS + [LDS_CONV])
 def test_forward_matches_oracle(levels, base, H, W, B):
     say(f"unet forward L={levels} C={base} {H}x{W} B={B}")
     rng = np.random.default_rng(levels * 100 + base)
@@ -45,7 +48,7 @@ def test_forward_matches_oracle(levels, base, H, W, B):
 
 # the last two shapes have W % 32 == 0 at every level: all their weight and bias gradients come
 # from the LDS-staged gradient kernel (the first three mix both gradient kernels)
-@pytest.mark.parametrize("levels,base,H,W,B", CONFIGS[:3] + [(2, 8, 64, 64, 1), (1, 16, 32, 64, 2)])
+@pytest.mark.parametrize("levels,base,H,W,B", CONFIGS[:3] + [(2, 8, 64, 64, 1), (1, 16, 32, 64, 2), LDS_CONV])
 def test_gradient_matches_oracle(levels, base, H, W, B):
     say(f"unet gradient L={levels} C={base} {H}x{W} B={B}")
     rng = np.random.default_rng(7 + levels)
