@@ -1698,15 +1698,41 @@ struct PinnedBuf {
   }
 };
 
+// Events recorded once per block step (created on first use, reused by later cycles and calls).
+struct EventRing {
+  std::vector<hipEvent_t> ev;
+  EventRing() = default;
+  EventRing(const EventRing&) = delete;
+  EventRing& operator=(const EventRing&) = delete;
+  ~EventRing() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  int ensure(int n) {
+    while ((int)ev.size() < n) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DIE_E_HIP, "hipEventCreateWithFlags failed");
+      }
+      ev.push_back(e);
+    }
+    return DIE_OK;
+  }
+};
+
 struct BlockWork {
   DBuf Rs, Sd, partn, nrm, active, Vb, Wt, Zb, Tm, Ra, Tb, sm, sm2, Ht, Hls, Bls, ones, idxd, part, coef, cnt, scl, Uq,
       sq;
+  // the device CholQR of each block step: the first factor (FP64), the steps' flags (device and a
+  // page-locked copy the host reads one step later) and the steps' events
+  DBuf Rf, Fl;
+  PinnedBuf pflag;
+  EventRing ev;
   // the planar Gram-Schmidt on the matrix cores: the basis shadows (T1, T2), the block being
   // orthogonalised (planar in the basis precision) and its T1 copy, the projection's chunk
   // products and their two-stage sums, the real update matrix, the FP64 planar copy of the first
   // block and the Gram result
   DBuf Q1, Q2, Wacc, W1, Cpart, Csum, Hbm, P64, Gd;
-  PinnedBuf pin;             // page-locked slots of the per-step uploads
   DBuf Zall;                 // per right-hand side: the correction V Y of its last cycle (FP64)
   std::vector<char> zvalid;  // which columns of Zall hold one
   DBuf Ubest, bmask;         // best iterate so far per right-hand side, and the copy mask
@@ -1780,9 +1806,14 @@ int planar_block_cgs(die_te_ctx* c, BlockWork& bw, const c2<T>* W, size_t n, int
 // G = X^H X (p x p <= 64 x 64) of the complex block held planar in Xs (nrow rows), downloaded to
 // the host (FP64 sums of products in A).
 template <class A>
+int gram_planar_dev(BlockWork& bw, const A* Xs, size_t nrow, int p, hipStream_t st, const int* gate = nullptr) {
+  DIE_HIP(die::launch_gram_planar<A>(Xs, nrow, p, bw.Cpart.as<A>(), kTsqPartial, bw.Csum.as<double>(),
+                                     die::kTsqScratch, bw.Gd.as<double2>(), st, gate));
+  return DIE_OK;
+}
+template <class A>
 int gram_planar(BlockWork& bw, const A* Xs, size_t nrow, int p, die::la::Mat& G, hipStream_t st) {
-  DIE_HIP(die::launch_gram_planar<A>(Xs, nrow, p, bw.Cpart.as<A>(), kTsqPartial,
-                                     bw.Csum.as<double>(), die::kTsqScratch, bw.Gd.as<double2>(), st));
+  DIE_TRY(gram_planar_dev<A>(bw, Xs, nrow, p, st));
   return download<double>(bw.Gd.p, p, p, G, st);
 }
 // The same for a complex block X (n x p, leading dimension n): split into planar Xs first.
@@ -1795,14 +1826,6 @@ int gram_complex(BlockWork& bw, const c2<T>* X, size_t n, size_t nrow, int p, T*
 // A narrowed block (at most this many right-hand sides of an object left) starts its cycle from
 // the residuals and the previous cycle's corrections of the same right-hand sides.
 constexpr int kAugmentMax = 16;
-
-// Host -> device copy of a small matrix through a page-locked slot, without waiting: the caller
-// rewrites the slot only after a later synchronisation of the stream.
-template <class T> int upload_async(const die::la::Mat& M, void* d, c2<T>* slot, hipStream_t st) {
-  for (size_t e = 0; e < M.a.size(); ++e) slot[e] = die::mk<T>((T)M.a[e].real(), (T)M.a[e].imag());
-  DIE_HIP(hipMemcpyAsync(d, slot, M.a.size() * sizeof(c2<T>), hipMemcpyHostToDevice, st));
-  return DIE_OK;
-}
 
 // Restarted block GMRES(m) (Section 4's GMRES applied to all right-hand sides of an object
 // at once): per object (in groups of at most kPanelMaxCols right-hand sides), the active
@@ -1893,11 +1916,12 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
   };
   DIE_TRY(Uq.alloc((size_t)die::kPanelMaxRows * die::kPanelMaxCols * sizeof(double2)));  // panel reflectors
   DIE_TRY(sq.alloc(die::kPanelMaxCols * sizeof(double)));
-  // three page-locked slots for the per-step uploads (R1^-1, R2^-1, H(j+1, j)); each step's Gram
-  // downloads synchronise the stream before a slot is written again
-  PinnedBuf& pin = bw.pin;
-  DIE_TRY(pin.alloc((size_t)3 * pw * pw * sizeof(c2<T>)));
-  c2<T>* slot[3] = {(c2<T>*)pin.p, (c2<T>*)pin.p + (size_t)pw * pw, (c2<T>*)pin.p + (size_t)2 * pw * pw};
+  // the device CholQR of the block steps: first factor, per-step flags and events
+  DIE_TRY(bw.Rf.alloc((size_t)die::kCholQRMax * die::kCholQRMax * sizeof(double2)));
+  DIE_TRY(bw.Fl.alloc((size_t)8 * m * sizeof(int)));
+  DIE_TRY(bw.pflag.alloc((size_t)8 * m * sizeof(int)));
+  DIE_TRY(bw.ev.ensure(m));
+  const int* pflag = (const int*)bw.pflag.p;
   if (defl) {
     DIE_TRY(part.alloc((size_t)pw * std::max((size_t)c->r * nblk, die::gmres_part_elems(n, c->r)) *
                        sizeof(double2)));
@@ -2156,42 +2180,45 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         else
           DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp, ldhp * sizeof(c2<T>), hc[0], nq * sizeof(c2<T>),
                                    nq * sizeof(c2<T>), p, hipMemcpyDeviceToDevice, st));
-        // CholQR of the orthogonalised block (planar in Wacc): the first Gram from the planar
-        // copy; the result ends in W
+        // CholQR of the orthogonalised block (planar in Wacc) without a host round trip: its Gram,
+        // the factor and its inverse by one workgroup, the factor application into W (one pass) or
+        // Wt (two passes: the second Gram, factor and application then run, gated on the device),
+        // and H(j + 1, j) (= R1, or R2 R1) straight into H.  The host reads the step's flags one
+        // step later, when the next step is already queued behind it.
         T* ws = bw.Wacc.as<T>();
-        Mat Gw, Q1, Q2;
-        DIE_TRY(gram_planar<T>(bw, ws, nrow, p, Gw, st));
-        double piv1 = 0.0;
-        bool ok = la::chol_upper_scaled(Gw, chol_tol, Q1, &piv1);
-        // a well-conditioned block (smallest scaled pivot >= kCholQRSinglePivot, condition <= ~4.5)
-        // is orthonormal to about cond^2 times the Gram's rounding after one CholQR pass
-        const bool single = ok && piv1 >= kCholQRSinglePivot;
-        // the first factor application reads the planar block and writes complex (one pass: into
-        // W; two passes: into Wt, whose Gram gives the second factor, applied from Wt into W)
-        c2<T>* wb = single ? W : Wt.as<c2<T>>();
-        if (ok) {
-          DIE_TRY(upload_async<T>(la::upper_inverse(Q1), sm.p, slot[0], st));
-          DIE_HIP(die::launch_cplx_rmul_planar<T>(ws, nrow, p, sm.as<c2<T>>(), p, p, n, wb, n, st));
-          if (!single) {
-            DIE_TRY(gram_complex<T>(bw, wb, n, nrow, p, ws, Gw, st));
-            ok = la::chol_upper_scaled(Gw, chol_tol, Q2);
+        int* fl = bw.Fl.as<int>() + (size_t)8 * j;
+        double2* r1 = bw.Rf.as<double2>();
+        c2<T>* wt = Wt.as<c2<T>>();
+        c2<T>* hblk = Hd + (size_t)j * p * ldhp + (size_t)(j + 1) * p;
+        DIE_TRY(gram_planar_dev<T>(bw, ws, nrow, p, st));
+        DIE_HIP(die::launch_cholqr_factor<T>(bw.Gd.as<double2>(), p, chol_tol, kCholQRSinglePivot, 1, r1, sm.as<c2<T>>(),
+                                             fl, hblk, ldhp, st));
+        DIE_HIP(die::launch_cplx_rmul_planar<T>(ws, nrow, p, sm.as<c2<T>>(), p, p, n, W, n, st, fl, wt));
+        DIE_HIP((die::launch_tsq_split<T, T, T>(wt, n, n, p, 0, nrow, 32, ws, nrow, nullptr, nullptr, st, fl + 2)));
+        DIE_TRY(gram_planar_dev<T>(bw, ws, nrow, p, st, fl + 2));
+        DIE_HIP(die::launch_cholqr_factor<T>(bw.Gd.as<double2>(), p, chol_tol, kCholQRSinglePivot, 2, r1,
+                                             sm2.as<c2<T>>(), fl, hblk, ldhp, st));
+        DIE_HIP(die::launch_cplx_rmul<T>(wt, n, p, sm2.as<c2<T>>(), p, p, n, W, n, st, fl + 4, W));
+        DIE_HIP(hipMemcpyAsync((int*)bw.pflag.p + (size_t)8 * j, fl, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+        DIE_HIP(hipEventRecord(bw.ev.ev[j], st));
+        DIE_TRY(shadow(W, p, j + 1));
+        // the previous step's block: a numerically dependent one ends the cycle before it (this
+        // step's work, already queued, is then never used)
+        if (j > 0) {
+          DIE_HIP(hipEventSynchronize(bw.ev.ev[j - 1]));
+          if (!pflag[8 * (j - 1) + 3]) {
+            meff = j;
+            early = true;
+            break;
           }
         }
-        if (!ok) {  // the new block is numerically dependent: end the cycle here
-          meff = j + 1;
+      }
+      if (!early) {
+        DIE_HIP(hipEventSynchronize(bw.ev.ev[m - 1]));
+        if (!pflag[8 * (m - 1) + 3]) {
+          meff = m;
           early = true;
-          break;
         }
-        if (!single) {
-          DIE_TRY(upload_async<T>(la::upper_inverse(Q2), sm.p, slot[1], st));
-          DIE_HIP(die::launch_cplx_rmul<T>(wb, n, p, sm.as<c2<T>>(), p, p, n, W, n, st));
-        }
-        DIE_TRY(shadow(W, p, j + 1));
-        const Mat Hs = single ? Q1 : la::upper_product(Q2, Q1);  // H(j+1, j) = Q2 Q1 (Q2 = I: one pass)
-        // into H's block (j+1, j) straight from the page-locked slot
-        for (size_t e = 0; e < Hs.a.size(); ++e) slot[2][e] = die::mk<T>((T)Hs.a[e].real(), (T)Hs.a[e].imag());
-        DIE_HIP(hipMemcpy2DAsync(Hd + (size_t)j * p * ldhp + (size_t)(j + 1) * p, ldhp * sizeof(c2<T>), slot[2],
-                                 p * sizeof(c2<T>), p * sizeof(c2<T>), p, hipMemcpyHostToDevice, st));
       }
       // ---- block least squares min || E1 S0 - H Y || on the GPU, then u += P^-1 V Y
       const int mr = early ? meff * p : (meff + 1) * p, nc = meff * p;

@@ -52,14 +52,16 @@ __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) 
 // U (rows x pc, column-major, leading dimension kPanelMaxRows) with scales s[q] = 2 / (u_q^H u_q)
 // (0 for a zero column).  The reflector P_q = I - s_q u_q u_q^H maps column q to -e^{i arg a} |x| e_q.
 // The panel lives in registers: column j in row j / 16 of wave j % 16.  Per reflector the row
-// holding column q (which already carries P_0 .. P_{q-1}) forms u_q and publishes it in one of
-// two LDS slots; after one barrier every row applies it to its column if that lies right of q.
-// The slots alternate, so a slot is rewritten only after the barrier that follows its reads.
+// holding column q (which already carries P_0 .. P_{q-1}) forms u_q and publishes it in its own
+// LDS slot; after one barrier every row applies it to its column if that lies right of q.  U and s
+// are written once, after the last reflector.
 __global__ void __launch_bounds__(kPanelThreads)
 k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, double2* __restrict__ U,
            double* __restrict__ s) {
-  __shared__ double2 ub[2][kPanelMaxRows];
-  __shared__ double sb[2];
+  // every reflector stays in LDS until the end: global stores inside the loop would make each
+  // reflector's barrier wait for them
+  __shared__ double2 ush[kPanelMaxCols][kPanelMaxRows];
+  __shared__ double ssh[kPanelMaxCols];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int j = w + kPanelWaves * g;  // this row's column
@@ -70,7 +72,6 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
     x[t] = (j < pc && i < rows) ? H[(size_t)(c0 + j) * ld + r0 + i] : make_double2(0.0, 0.0);
   }
   for (int q = 0; q < pc; ++q) {
-    const int buf = q & 1;
     if (w == q % kPanelWaves) {  // the wave holding column q (wave-uniform); its row q / 16 writes
       const bool own = g == q / kPanelWaves;
       double sq = 0.0;
@@ -106,25 +107,21 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
           double2 u = make_double2(0.0, 0.0);
           if (i == q) u = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
           else if (i > q && i < rows) u = x[t];
-          ub[buf][i] = u;
-          if (i < rows) U[(size_t)q * kPanelMaxRows + i] = u;
+          ush[q][i] = u;
           // column q becomes R's: -e^{i arg a} |x| on the diagonal, zeros below
           if (i == q) x[t] = make_double2(-ph.x * nrm, -ph.y * nrm);
           else if (i > q) x[t] = make_double2(0.0, 0.0);
         }
-        if (l16 == 0) {
-          sb[buf] = sc;
-          s[q] = sc;
-        }
+        if (l16 == 0) ssh[q] = sc;
       }
     }
     lds_sync();
-    const double sc = sb[buf];
+    const double sc = ssh[q];
     double2 u[kRowsPerLane];
     double2 d = make_double2(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < kRowsPerLane; ++t) {
-      u[t] = ub[buf][l16 + 16 * t];
+      u[t] = ush[q][l16 + 16 * t];
       d = cfma_conj(u[t], x[t], d);
     }
     d.x = sum16(d.x);
@@ -143,6 +140,12 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
     const int i = l16 + 16 * t;
     if (j < pc && i < rows) H[(size_t)(c0 + j) * ld + r0 + i] = x[t];
   }
+  // the reflectors (rows < rows) and their scales, for the application to the later columns
+  for (int e = threadIdx.x; e < pc * kPanelMaxRows; e += kPanelThreads) {
+    const int q = e / kPanelMaxRows, i = e - q * kPanelMaxRows;
+    if (i < rows) U[e] = ush[q][i];
+  }
+  if (threadIdx.x < pc) s[threadIdx.x] = ssh[threadIdx.x];
 }
 
 // Apply the panel's reflectors P_0, P_1, ..., P_{pc-1} (in that order) to rows r0 .. r0+rows of
@@ -198,6 +201,175 @@ k_panel_apply(double2* __restrict__ H, int ld, double2* __restrict__ B, int ldb,
   }
 }
 
+
+// ------------------------------------------------------------------ CholQR factor
+// One workgroup of 1024 threads (16 row groups x 64 columns).  The Gram G is scaled to unit
+// diagonal, S = D G D with D = diag(G)^-1/2, and eliminated column by column with one barrier per
+// column: step j subtracts l_ij conj(S(c, j)) from S(i, c) (j < c <= i, l_ij = S(i, j) / d_j) and
+// applies the same row operations to the identity, which leaves Mi = L~^-1 for S = L~ diag(d) L~^H.
+// With L = L~ diag(d)^1/2 the factor of G = R^H R is R = L^H D^-1, R(i, c) = conj(S(c, i)) / sqrt(d_i)
+// / D_c (i < c), sqrt(d_c) / D_c (i = c), and R^-1 = D L^-H, R^-1(i, c) = D_i conj(Mi(c, i)) / sqrt(d_c).
+constexpr int kCholLd = kCholQRMax + 1;  // LDS row stride (double2)
+
+template <class T>
+__device__ __forceinline__ void put_c(c2<T>* p, double2 v) {
+  *p = mk<T>((T)v.x, (T)v.y);
+}
+
+template <class T>
+__global__ void __launch_bounds__(1024)
+k_cholqr_factor(const double2* __restrict__ G, int p, double rel_tol, double single_piv, int pass,
+                double2* __restrict__ R1, c2<T>* __restrict__ Rinv, int* __restrict__ flags, c2<T>* __restrict__ Hb,
+                int ldh) {
+  __shared__ double2 S[kCholQRMax * kCholLd];
+  __shared__ double2 Mi[kCholQRMax * kCholLd];
+  __shared__ double dinv[kCholQRMax], sdiag[kCholQRMax], dp[kCholQRMax], sqd[kCholQRMax], gd[kCholQRMax];
+  const int tid = threadIdx.x, c = tid & 63, rg = tid >> 6;
+  if (pass == 2 && !flags[2]) {  // one pass sufficed (or the first failed): H = R1
+    for (int e = tid; e < p * p; e += blockDim.x) {
+      const int i = e % p, cc = e / p;
+      put_c<T>(Hb + (size_t)cc * ldh + i, i <= cc ? R1[e] : make_double2(0.0, 0.0));
+    }
+    if (tid == 0) {
+      flags[3] = flags[0];
+      flags[4] = 0;
+    }
+    return;
+  }
+  if (tid < p) {
+    const double d = G[(size_t)tid * p + tid].x;
+    const bool ok = d > 0.0 && isfinite(d);
+    dinv[tid] = ok ? 1.0 / sqrt(d) : 0.0;
+    sdiag[tid] = ok ? d * dinv[tid] * dinv[tid] : 0.0;
+  }
+  lds_sync();
+  bool fail = false;
+  double dmax = 0.0;
+  for (int i = 0; i < p; ++i) {  // every thread takes the same decision
+    if (dinv[i] == 0.0) fail = true;
+    dmax = fmax(dmax, sdiag[i]);
+  }
+  if (!fail) {
+    for (int i = rg; i < p; i += 16)
+      if (c <= i) {
+        const double2 g = G[(size_t)c * p + i];
+        const double sc = dinv[i] * dinv[c];
+        S[i * kCholLd + c] = make_double2(g.x * sc, g.y * sc);
+        Mi[i * kCholLd + c] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+      }
+    lds_sync();
+    for (int j = 0; j < p; ++j) {
+      const double d = S[j * kCholLd + j].x;
+      if (!(d > rel_tol * dmax)) {  // uniform: every thread reads the same pivot
+        fail = true;
+        break;
+      }
+      if (tid == 0) dp[j] = d;
+      const double rd = 1.0 / d;
+      // this thread's rows j + 1 + rg + 16 r (at most four): every LDS read of the step is issued
+      // before its writes, so that their latencies overlap
+      const bool upd = c > j;  // S(i, c) -= l conj(S(c, j)); otherwise Mi(i, c) -= l Mi(j, c)
+      const double2 o = upd ? (c < p ? S[c * kCholLd + j] : make_double2(0.0, 0.0)) : Mi[j * kCholLd + c];
+      double2 li[4], v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = j + 1 + rg + 16 * r;
+        const bool live = i < p && (!upd || c <= i);
+        const int ii = live ? i : j;  // a row that exists (not written)
+        const double2 sij = S[ii * kCholLd + j];
+        li[r] = make_double2(sij.x * rd, sij.y * rd);
+        v[r] = upd ? S[ii * kCholLd + (live ? c : j)] : Mi[ii * kCholLd + c];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = j + 1 + rg + 16 * r;
+        if (i >= p || (upd && c > i)) continue;
+        const double2 l = li[r];
+        if (upd) {
+          v[r].x -= l.x * o.x + l.y * o.y;
+          v[r].y -= l.y * o.x - l.x * o.y;
+          S[i * kCholLd + c] = v[r];
+        } else {
+          v[r].x -= l.x * o.x - l.y * o.y;
+          v[r].y -= l.x * o.y + l.y * o.x;
+          Mi[i * kCholLd + c] = v[r];
+        }
+      }
+      lds_sync();
+    }
+  }
+  if (fail) {
+    if (tid == 0) {
+      if (pass == 1) {
+        flags[0] = 0;
+        flags[1] = 0;
+        flags[2] = 0;
+        flags[5] = 1;
+      } else {
+        flags[3] = 0;
+        flags[4] = 0;
+      }
+    }
+    return;
+  }
+  if (tid < p) {
+    sqd[tid] = sqrt(dp[tid]);
+    gd[tid] = 1.0 / dinv[tid];
+  }
+  lds_sync();
+  if (c < p)
+    for (int i = rg; i < p; i += 16) {
+      double2 ri = make_double2(0.0, 0.0);
+      if (i <= c) {
+        const double2 m = Mi[c * kCholLd + i];
+        const double f = dinv[i] / sqd[c];
+        ri = make_double2(m.x * f, -m.y * f);
+      }
+      put_c<T>(Rinv + (size_t)c * p + i, ri);
+      if (pass == 1) {
+        double2 r = make_double2(0.0, 0.0);
+        if (i < c) {
+          const double2 sv = S[c * kCholLd + i];
+          const double f = gd[c] / sqd[i];
+          r = make_double2(sv.x * f, -sv.y * f);
+        } else if (i == c) {
+          r = make_double2(sqd[c] * gd[c], 0.0);
+        }
+        R1[(size_t)c * p + i] = r;
+      } else {  // H(i, c) = sum over i <= q <= c of R2(i, q) R1(q, c)
+        double hx = 0.0, hy = 0.0;
+        for (int q = i; q <= c; ++q) {
+          double2 r2;
+          if (q == i) {
+            r2 = make_double2(sqd[i] * gd[i], 0.0);
+          } else {
+            const double2 sv = S[q * kCholLd + i];
+            const double f = gd[q] / sqd[i];
+            r2 = make_double2(sv.x * f, -sv.y * f);
+          }
+          const double2 r1 = R1[(size_t)c * p + q];
+          hx += r2.x * r1.x - r2.y * r1.y;
+          hy += r2.x * r1.y + r2.y * r1.x;
+        }
+        put_c<T>(Hb + (size_t)c * ldh + i, make_double2(hx, hy));
+      }
+    }
+  if (tid == 0) {
+    if (pass == 1) {
+      double dmin = 1.0;
+      for (int j = 0; j < p; ++j) dmin = fmin(dmin, dp[j] / dmax);
+      const int single = dmin >= single_piv;
+      flags[0] = 1;
+      flags[1] = single;
+      flags[2] = !single;
+      flags[5] = 1;
+    } else {
+      flags[3] = 1;
+      flags[4] = 1;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p, double2* B, int ldb, int k,
@@ -214,5 +386,20 @@ hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p,
   }
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_cholqr_factor(const double2* G, int p, double rel_tol, double single_piv, int pass, double2* R1,
+                                c2<T>* Rinv, int* flags, c2<T>* Hb, int ldh, hipStream_t st) {
+  if (p < 1 || p > kCholQRMax || (pass != 1 && pass != 2) || (pass == 2 && (!Hb || ldh < p)) || !G || !R1 || !Rinv ||
+      !flags)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(1), dim3(1024), 0, st, G, p, rel_tol, single_piv, pass, R1, Rinv, flags,
+                     Hb, ldh);
+  return hipGetLastError();
+}
+template hipError_t launch_cholqr_factor<float>(const double2*, int, double, double, int, double2*, c2<float>*, int*,
+                                                c2<float>*, int, hipStream_t);
+template hipError_t launch_cholqr_factor<double>(const double2*, int, double, double, int, double2*, c2<double>*,
+                                                 int*, c2<double>*, int, hipStream_t);
 
 }  // namespace die

@@ -98,9 +98,9 @@ template <> struct Mf1<double> {
 // complex block X (n x p): one thread per row and column, the two parts to columns q and p + q.
 template <class T, class A>
 __global__ void k_split_planar(const c2<T>* __restrict__ X, size_t ldx, size_t n, int p, size_t nrow,
-                               A* __restrict__ Ws, size_t ldw) {
+                               A* __restrict__ Ws, size_t ldw, const int* __restrict__ gate) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nrow * (size_t)p) return;
+  if ((gate && !*gate) || e >= nrow * (size_t)p) return;
   const size_t q = e / nrow, r = e - q * nrow;
   c2<T> z = mk<T>((T)0, (T)0);
   if (r < n) z = X[q * ldx + r];
@@ -243,7 +243,8 @@ template <class E> constexpr int proj_group() { return sizeof(E) == 8 ? 4 : 8; }
 template <class E, int NT, bool NF>
 __global__ void __launch_bounds__(256)
 k_tsq_proj(const E* __restrict__ A1, int ma, const E* __restrict__ B1, int nb, size_t nrow, int kc, int gy,
-           typename GemmTile<E>::Acc* __restrict__ part) {
+           typename GemmTile<E>::Acc* __restrict__ part, const int* __restrict__ gate) {
+  if (gate && !*gate) return;  // the whole block: before any barrier
   using M = Mf<E>;
   using Tl = GemmTile<E>;
   using V = typename M::V;
@@ -372,9 +373,10 @@ __global__ void k_tsq_combine(const P* __restrict__ C, int nch, int nq, int p, c
 // The Gram matrix G = X^H X (p x p, FP64, leading dimension p) from the chunk products of the
 // planar X (2p x 2p each, leading dimension 2p), summed in chunk order.
 template <class P>
-__global__ void k_gram_combine(const P* __restrict__ C, int nch, int p, double2* __restrict__ G) {
+__global__ void k_gram_combine(const P* __restrict__ C, int nch, int p, double2* __restrict__ G,
+                               const int* __restrict__ gate) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= p * p) return;
+  if ((gate && !*gate) || e >= p * p) return;
   const int b = e / p, a = e - b * p, P2 = 2 * p;
   double rr = 0.0, ii = 0.0, ri = 0.0, ir = 0.0;
   for (int h = 0; h < nch; ++h) {
@@ -390,9 +392,10 @@ __global__ void k_gram_combine(const P* __restrict__ C, int nch, int p, double2*
 // First stage of the sum over many chunk products: out[g][e] = the FP64 sum of the products of
 // chunks g cpg .. (g + 1) cpg - 1, in chunk order, for the L entries e of one product.
 template <class A>
-__global__ void k_chunk_sum(const A* __restrict__ part, int nch, size_t L, int cpg, double* __restrict__ out) {
+__global__ void k_chunk_sum(const A* __restrict__ part, int nch, size_t L, int cpg, double* __restrict__ out,
+                            const int* __restrict__ gate) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= L) return;
+  if ((gate && !*gate) || e >= L) return;
   const int h0 = blockIdx.y * cpg, h1 = h0 + cpg < nch ? h0 + cpg : nch;
   double acc = 0.0;
 #pragma unroll 8
@@ -534,9 +537,13 @@ k_tsq_update(const E* __restrict__ A2, int mc, size_t ccap, size_t nrow, const E
 template <class T, int NT, bool PLANAR = false>
 __global__ void __launch_bounds__(256)
 k_cplx_rmul(const void* __restrict__ Xv, size_t ldx, int s, const c2<T>* __restrict__ S, int lds, int q, size_t n,
-            c2<T>* __restrict__ Y, size_t ldy) {
+            c2<T>* __restrict__ Y, size_t ldy, const int* __restrict__ ctl, c2<T>* __restrict__ Yalt) {
+  if (ctl) {  // device control: ctl[0] == 0 skips the launch, ctl[1] == 0 writes Yalt instead of Y
+    if (!ctl[0]) return;
+    if (!ctl[1]) Y = Yalt;
+  }
   using M = Mf1<T>;
-  constexpr int R = M::R, G = 64 / R, SC = 64, QP = NT * R + 1, NU = SC / G;
+  constexpr int R = M::R, G = 64 / R, SC = 64, QP = NT * R + 1;
   __shared__ T sr[SC * QP], si[SC * QP];
   const int lane = threadIdx.x & 63;
   const size_t stripe = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -710,9 +717,9 @@ inline unsigned blocks_for(size_t work, unsigned per = 256) { return (unsigned)(
 
 template <class T, class A, class E>
 hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0, size_t nrow, size_t ccap, A* Ws,
-                            size_t ldw, E* A1, E* A2, hipStream_t st) {
+                            size_t ldw, E* A1, E* A2, hipStream_t st, const int* gate) {
   if (p < 1 || n > nrow || nrow % 32 || ccap % 32 || (Ws && ldw < nrow) || (A2 && (size_t)c0 + 2 * p > ccap) ||
-      (Ws && A1 && c0 != 0))
+      (Ws && A1 && c0 != 0) || (gate && (!Ws || A1 || A2)))  // a gate only for the planar copy alone
     return hipErrorInvalidValue;
   constexpr int KV = GemmTile<E>::KV;
   if (!Ws && A1 && A2 && p % KV == 0 && c0 % KV == 0) {  // both shadows from one read of X
@@ -722,7 +729,7 @@ hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0,
   }
   if (Ws)
     hipLaunchKernelGGL((k_split_planar<T, A>), dim3(blocks_for(nrow * (size_t)p)), dim3(256), 0, st, X, ldx, n, p,
-                       nrow, Ws, ldw);
+                       nrow, Ws, ldw, gate);
   if (A1) {
     if (Ws)  // the T1 copy from the planar one (contiguous reads and writes)
       hipLaunchKernelGGL((k_planar_to_t1<A, E>), dim3(blocks_for(nrow / KV * 2 * (size_t)p)), dim3(256), 0, st, Ws,
@@ -750,8 +757,9 @@ hipError_t launch_tsq_to_t1(const A* Ws, size_t ldw, size_t nrow, int nb, E* B1,
 namespace {
 template <class E, int NT, bool NF>
 void launch_proj_kernel(unsigned nblocks, const E* A1, int ma, const E* B1, int nb, size_t nrow, int kc, int gy,
-                        typename GemmTile<E>::Acc* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_tsq_proj<E, NT, NF>), dim3(nblocks), dim3(256), 0, st, A1, ma, B1, nb, nrow, kc, gy, part);
+                        typename GemmTile<E>::Acc* part, hipStream_t st, const int* gate) {
+  hipLaunchKernelGGL((k_tsq_proj<E, NT, NF>), dim3(nblocks), dim3(256), 0, st, A1, ma, B1, nb, nrow, kc, gy, part,
+                     gate);
 }
 // Blocks of the projection kernel that the device holds at once (its compute units times the
 // kernel's occupancy), per device and kernel.
@@ -791,20 +799,20 @@ int proj_slots_nt(int nt) {
 }
 template <class E, bool NF>
 hipError_t proj_nt(int nt, unsigned nblocks, const E* A1, int ma, const E* B1, int nb, size_t nrow, int kc, int gy,
-                   typename GemmTile<E>::Acc* part, hipStream_t st) {
+                   typename GemmTile<E>::Acc* part, hipStream_t st, const int* gate) {
   constexpr int NTMAX = 128 / GemmTile<E>::R;
   switch (nt) {
-    case 1: launch_proj_kernel<E, 1, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
-    case 2: launch_proj_kernel<E, 2, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
-    case 3: launch_proj_kernel<E, 3, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
-    case 4: launch_proj_kernel<E, 4, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
+    case 1: launch_proj_kernel<E, 1, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
+    case 2: launch_proj_kernel<E, 2, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
+    case 3: launch_proj_kernel<E, 3, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
+    case 4: launch_proj_kernel<E, 4, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
     default:
       if constexpr (NTMAX > 4) {
         switch (nt) {
-          case 5: launch_proj_kernel<E, 5, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
-          case 6: launch_proj_kernel<E, 6, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
-          case 7: launch_proj_kernel<E, 7, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
-          case 8: launch_proj_kernel<E, 8, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st); break;
+          case 5: launch_proj_kernel<E, 5, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
+          case 6: launch_proj_kernel<E, 6, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
+          case 7: launch_proj_kernel<E, 7, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
+          case 8: launch_proj_kernel<E, 8, NF>(nblocks, A1, ma, B1, nb, nrow, kc, gy, part, st, gate); break;
           default: return hipErrorInvalidValue;
         }
       } else {
@@ -816,7 +824,7 @@ hipError_t proj_nt(int nt, unsigned nblocks, const E* A1, int ma, const E* B1, i
 // part = the chunk products of A^T B (see k_tsq_proj); the chunk count to *nch_out
 template <class E, bool NF>
 hipError_t proj_any(const E* A1, int ma, const E* B1, int nb, size_t nrow, typename GemmTile<E>::Acc* part,
-                    size_t part_cap, int* nch_out, hipStream_t st) {
+                    size_t part_cap, int* nch_out, hipStream_t st, const int* gate = nullptr) {
   using Tl = GemmTile<E>;
   if (ma < 1 || nb < 1 || nb > 128 || nrow % 32 || nrow == 0) return hipErrorInvalidValue;
   const int mt = (ma + Tl::R - 1) / Tl::R, nt = (nb + Tl::R - 1) / Tl::R;
@@ -838,17 +846,18 @@ hipError_t proj_any(const E* A1, int ma, const E* B1, int nb, size_t nrow, typen
   const size_t kc = (tpc + nch - 1) / nch;
   *nch_out = (int)nch;
   const unsigned nblocks = (unsigned)(nch * gy);
-  return proj_nt<E, NF>(nt, nblocks, A1, ma, B1, nb, nrow, (int)kc, gy, part, st);
+  return proj_nt<E, NF>(nt, nblocks, A1, ma, B1, nb, nrow, (int)kc, gy, part, st, gate);
 }
 // Sums groups of 16 chunk products when there are more than 16 (FP64, into scratch); returns the
 // products the final combine reads and their count.
 template <class A>
 hipError_t chunk_groups(const A* part, int nch, size_t L, double* scratch, size_t scratch_cap, const double** out,
-                        int* nout, hipStream_t st) {
+                        int* nout, hipStream_t st, const int* gate = nullptr) {
   constexpr int kCpg = 16;
   const int g = (nch + kCpg - 1) / kCpg;
   if ((size_t)g * L > scratch_cap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_chunk_sum<A>), dim3(blocks_for(L), (unsigned)g), dim3(256), 0, st, part, nch, L, kCpg, scratch);
+  hipLaunchKernelGGL((k_chunk_sum<A>), dim3(blocks_for(L), (unsigned)g), dim3(256), 0, st, part, nch, L, kCpg, scratch,
+                     gate);
   *out = scratch;
   *nout = g;
   return hipGetLastError();
@@ -858,7 +867,7 @@ hipError_t chunk_groups(const A* part, int nch, size_t L, double* scratch, size_
 template <class E>
 hipError_t launch_tsq_proj(const E* A1, int ma, const E* B1, int nb, size_t nrow, typename GemmTile<E>::Acc* part,
                            size_t part_cap, int* nch_out, hipStream_t st) {
-  return proj_any<E, false>(A1, ma, B1, nb, nrow, part, part_cap, nch_out, st);
+  return proj_any<E, false>(A1, ma, B1, nb, nrow, part, part_cap, nch_out, st, nullptr);
 }
 
 template <class A, class E, class T>
@@ -920,20 +929,20 @@ hipError_t launch_tsq_update(const E* A2, int mc, size_t ccap, size_t nrow, cons
 
 template <class A>
 hipError_t launch_gram_planar(const A* Xs, size_t nrow, int p, A* part, size_t part_cap, double* scratch,
-                              size_t scratch_cap, double2* G, hipStream_t st) {
+                              size_t scratch_cap, double2* G, hipStream_t st, const int* gate) {
   if (p < 1 || p > 64) return hipErrorInvalidValue;
   int nch = 0;
-  hipError_t e = proj_any<A, true>(Xs, 2 * p, Xs, 2 * p, nrow, part, part_cap, &nch, st);
+  hipError_t e = proj_any<A, true>(Xs, 2 * p, Xs, 2 * p, nrow, part, part_cap, &nch, st, gate);
   if (e != hipSuccess) return e;
   const unsigned nb = blocks_for((size_t)p * p);
   if (nch > 16) {
     const double* g;
     int ng;
-    e = chunk_groups<A>(part, nch, (size_t)4 * p * p, scratch, scratch_cap, &g, &ng, st);
+    e = chunk_groups<A>(part, nch, (size_t)4 * p * p, scratch, scratch_cap, &g, &ng, st, gate);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_gram_combine<double>), dim3(nb), dim3(256), 0, st, g, ng, p, G);
+    hipLaunchKernelGGL((k_gram_combine<double>), dim3(nb), dim3(256), 0, st, g, ng, p, G, gate);
   } else {
-    hipLaunchKernelGGL((k_gram_combine<A>), dim3(nb), dim3(256), 0, st, part, nch, p, G);
+    hipLaunchKernelGGL((k_gram_combine<A>), dim3(nb), dim3(256), 0, st, part, nch, p, G, gate);
   }
   return hipGetLastError();
 }
@@ -941,8 +950,9 @@ hipError_t launch_gram_planar(const A* Xs, size_t nrow, int p, A* part, size_t p
 namespace {
 template <class T, bool PLANAR>
 hipError_t cplx_rmul(const void* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y, size_t ldy,
-                     hipStream_t st) {
-  if (s < 1 || q < 1 || q > 64 || lds < s || (!PLANAR && ldx < n) || ldy < n || X == (const void*)Y)
+                     hipStream_t st, const int* ctl, c2<T>* Yalt) {
+  if (s < 1 || q < 1 || q > 64 || lds < s || (!PLANAR && ldx < n) || ldy < n || X == (const void*)Y ||
+      (ctl && (!Yalt || X == (const void*)Yalt)))
     return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   constexpr int R = Mf1<T>::R;
@@ -950,20 +960,24 @@ hipError_t cplx_rmul(const void* X, size_t ldx, int s, const c2<T>* S, int lds, 
   const unsigned grid = (unsigned)((n + 4 * R - 1) / (4 * R));
   switch (nt) {
     case 1:
-      hipLaunchKernelGGL((k_cplx_rmul<T, 1, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+      hipLaunchKernelGGL((k_cplx_rmul<T, 1, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy,
+                         ctl, Yalt);
       break;
     case 2:
-      hipLaunchKernelGGL((k_cplx_rmul<T, 2, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+      hipLaunchKernelGGL((k_cplx_rmul<T, 2, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy,
+                         ctl, Yalt);
       break;
     case 3:
       if constexpr (R == 16) {
-        hipLaunchKernelGGL((k_cplx_rmul<T, 3, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+        hipLaunchKernelGGL((k_cplx_rmul<T, 3, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy,
+                         ctl, Yalt);
         break;
       }
       return hipErrorInvalidValue;
     case 4:
       if constexpr (R == 16) {
-        hipLaunchKernelGGL((k_cplx_rmul<T, 4, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy);
+        hipLaunchKernelGGL((k_cplx_rmul<T, 4, PLANAR>), dim3(grid), dim3(256), 0, st, X, ldx, s, S, lds, q, n, Y, ldy,
+                         ctl, Yalt);
         break;
       }
       return hipErrorInvalidValue;
@@ -976,15 +990,15 @@ hipError_t cplx_rmul(const void* X, size_t ldx, int s, const c2<T>* S, int lds, 
 
 template <class T>
 hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
-                            size_t ldy, hipStream_t st) {
-  return cplx_rmul<T, false>(X, ldx, s, S, lds, q, n, Y, ldy, st);
+                            size_t ldy, hipStream_t st, const int* ctl, c2<T>* Yalt) {
+  return cplx_rmul<T, false>(X, ldx, s, S, lds, q, n, Y, ldy, st, ctl, Yalt);
 }
 
 template <class T>
 hipError_t launch_cplx_rmul_planar(const T* Xs, size_t ldw, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
-                                   size_t ldy, hipStream_t st) {
+                                   size_t ldy, hipStream_t st, const int* ctl, c2<T>* Yalt) {
   if (ldw < n) return hipErrorInvalidValue;
-  return cplx_rmul<T, true>(Xs, ldw, s, S, lds, q, n, Y, ldy, st);
+  return cplx_rmul<T, true>(Xs, ldw, s, S, lds, q, n, Y, ldy, st, ctl, Yalt);
 }
 
 namespace {
@@ -1022,11 +1036,12 @@ hipError_t launch_cadd2(const c2<T>* A, int lda, const c2<T>* B, int ldb, int ro
 }
 
 #define DIE_INST_T(T)                                                                                              \
-  template hipError_t launch_gram_planar<T>(const T*, size_t, int, T*, size_t, double*, size_t, double2*, hipStream_t); \
+  template hipError_t launch_gram_planar<T>(const T*, size_t, int, T*, size_t, double*, size_t, double2*, hipStream_t, \
+                                            const int*);                                                             \
   template hipError_t launch_cplx_rmul_planar<T>(const T*, size_t, int, const c2<T>*, int, int, size_t, c2<T>*,      \
-                                                  size_t, hipStream_t);                                              \
+                                                  size_t, hipStream_t, const int*, c2<T>*);                          \
   template hipError_t launch_cplx_rmul<T>(const c2<T>*, size_t, int, const c2<T>*, int, int, size_t, c2<T>*, size_t, \
-                                          hipStream_t);                                                             \
+                                          hipStream_t, const int*, c2<T>*);                                         \
   template hipError_t launch_cadd2<T>(const c2<T>*, int, const c2<T>*, int, int, int, c2<T>*, int, hipStream_t);
 DIE_INST_T(float)
 DIE_INST_T(double)
@@ -1035,7 +1050,7 @@ DIE_INST_T(double)
 #define DIE_INST_E(T, E)                                                                                            \
   template hipError_t launch_tsq_split<T, typename GemmTile<E>::Acc, E>(const c2<T>*, size_t, size_t, int, int, size_t, \
                                                                         size_t, typename GemmTile<E>::Acc*, size_t, E*, \
-                                                                        E*, hipStream_t);                            \
+                                                                        E*, hipStream_t, const int*);                \
   template hipError_t launch_tsq_to_t1<typename GemmTile<E>::Acc, E>(const typename GemmTile<E>::Acc*, size_t, size_t, \
                                                                      int, E*, hipStream_t);                          \
   template hipError_t launch_tsq_proj<E>(const E*, int, const E*, int, size_t, typename GemmTile<E>::Acc*, size_t,    \

@@ -156,9 +156,10 @@ __host__ __device__ constexpr size_t gemm_pad(size_t x) { return (x + 31) / 32 *
 // Columns [c0, c0 + 2p) of the planar form of X (n x p complex, leading dimension ldx; rows n ..
 // nrow - 1 zero): into Ws (planar, leading dimension ldw), A1 (T1) and A2 (T2, capacity ccap);
 // any of the three may be null (Ws takes the columns 0 .. 2p - 1; with Ws and A1 both given, c0 = 0).
+// gate (device int, only with Ws alone): the launch does nothing while *gate == 0.
 template <class T, class A, class E>
 hipError_t launch_tsq_split(const c2<T>* X, size_t ldx, size_t n, int p, int c0, size_t nrow, size_t ccap, A* Ws,
-                            size_t ldw, E* A1, E* A2, hipStream_t st);
+                            size_t ldw, E* A1, E* A2, hipStream_t st, const int* gate = nullptr);
 // B1 (T1, columns 0 .. nb - 1) from the planar Ws (nrow rows, leading dimension ldw).
 template <class A, class E>
 hipError_t launch_tsq_to_t1(const A* Ws, size_t ldw, size_t nrow, int nb, E* B1, hipStream_t st);
@@ -184,19 +185,34 @@ hipError_t launch_tsq_update(const E* A2, int mc, size_t ccap, size_t nrow, cons
 // rows contiguous, leading dimension nrow, rows past the data zero; the buffer holds 2p rounded
 // up to 32 columns), p <= 64: on the matrix cores in A (FP32 or FP64) with the chunk products in
 // part (at most part_cap values), summed in FP64 (through scratch as for launch_tsq_combine).
+// gate (device int): every launch does nothing while *gate == 0.
 template <class A>
 hipError_t launch_gram_planar(const A* Xs, size_t nrow, int p, A* part, size_t part_cap, double* scratch,
-                              size_t scratch_cap, double2* G, hipStream_t st);
+                              size_t scratch_cap, double2* G, hipStream_t st, const int* gate = nullptr);
 // Y (n x q) = X (n x s) S (s x q, leading dimension lds), complex in T on the matrix cores, q <= 64;
-// X and Y distinct.
+// X and Y distinct.  ctl (device ints, with Yalt): nothing happens while ctl[0] == 0, and the result
+// goes to Yalt (distinct from X, same leading dimension) while ctl[1] == 0.
 template <class T>
 hipError_t launch_cplx_rmul(const c2<T>* X, size_t ldx, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
-                            size_t ldy, hipStream_t st);
+                            size_t ldy, hipStream_t st, const int* ctl = nullptr, c2<T>* Yalt = nullptr);
 // The same with X held planar in T (Xs: column c's real parts at c ldw, its imaginary parts at
 // (s + c) ldw, ldw >= n).
 template <class T>
 hipError_t launch_cplx_rmul_planar(const T* Xs, size_t ldw, int s, const c2<T>* S, int lds, int q, size_t n, c2<T>* Y,
-                                   size_t ldy, hipStream_t st);
+                                   size_t ldy, hipStream_t st, const int* ctl = nullptr, c2<T>* Yalt = nullptr);
+// CholQR factor of a block from its Gram matrix G (p x p, FP64, leading dimension p), p <= 64, by
+// one workgroup (no host round trip).  flags (device ints; every path writes each flag it owns):
+// [0] pass 1 succeeded, [1] one pass suffices (smallest pivot of the unit-diagonal Gram's
+// Cholesky >= single_piv), [2] a second pass is to run, [3] the block is orthonormalised,
+// [4] the second factor is to be applied, [5] 1.  pass 1: R1 (FP64, p x p, zero below the
+// diagonal) and R1^-1 (into Rinv, in T) from G; flags 0-2 and 5.  pass 2: while flags[2], R2^-1
+// into Rinv from the second Gram and H = R2 R1, otherwise H = R1; H into Hb (leading dimension
+// ldh, in T, zero below the diagonal); flags 3-4.  A pivot <= rel_tol x the largest diagonal entry
+// fails the pass (the block is numerically rank deficient).
+constexpr int kCholQRMax = 64;
+template <class T>
+hipError_t launch_cholqr_factor(const double2* G, int p, double rel_tol, double single_piv, int pass, double2* R1,
+                                c2<T>* Rinv, int* flags, c2<T>* Hb, int ldh, hipStream_t st);
 // R Y = B in place in B (nc x k, leading dimension ldb) for the upper triangular R (leading
 // dimension ldr), nc <= kTrsmMaxRows.
 constexpr int kTrsmMaxRows = 4096;
