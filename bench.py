@@ -730,7 +730,7 @@ def main():
             # HBM traffic: the operand bytes of the same launches times the measured HBM/algorithmic
             # ratio of the update GEMM (valid only for the solver source the counters were taken on)
             mem_per_launch = sum(sv.profile_mem(DIE_PROF_GEMM) for sv in ctxs) / max(p["timed"], 1)
-            src = source_hash("die_te.cpp", "dense.hpp", "ops.hpp", "common.hpp")
+            src = source_hash("die_te.cpp", "dense.hpp", "ops.hpp", "common.hpp", "kernels_gemm.hip")
             tag = ("block_gemm_update_h16_256" if args.block_gemm == 16 else
                    f"block_gemm_update_c{64 if args.block_precision == 32 else 128}_256")
             traffic = read_traffic(tag, src, mem_per_launch)
