@@ -2199,6 +2199,10 @@ int block_gmres_solve(die_te_ctx* c, const double2* b, double2* u, int nrhs, con
         DIE_HIP(die::launch_cholqr_factor<T>(bw.Gd.as<double2>(), p, chol_tol, kCholQRSinglePivot, 2, r1,
                                              sm2.as<c2<T>>(), fl, hblk, ldhp, st));
         DIE_HIP(die::launch_cplx_rmul<T>(wt, n, p, sm2.as<c2<T>>(), p, p, n, W, n, st, fl + 4, W));
+        // a block that could not be orthonormalised is cleared: the next step, queued before the
+        // host sees the flag, then works on zeros (an unwritten block could hold non-finite values,
+        // and 0 x NaN in its updates would reach the zero padding rows of the planar buffers)
+        DIE_HIP(die::launch_zero_unless<T>(W, n, n, p, fl + 3, st));
         DIE_HIP(hipMemcpyAsync((int*)bw.pflag.p + (size_t)8 * j, fl, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
         DIE_HIP(hipEventRecord(bw.ev.ev[j], st));
         DIE_TRY(shadow(W, p, j + 1));

@@ -370,6 +370,19 @@ k_cholqr_factor(const double2* __restrict__ G, int p, double rel_tol, double sin
   }
 }
 
+// Y = 0 unless *flag (a grid-stride loop over the n x p block; every block returns at once while
+// the flag is set).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_zero_unless(c2<T>* __restrict__ Y, size_t ldy, size_t n, int p, const int* __restrict__ flag) {
+  if (*flag) return;
+  const size_t total = n * (size_t)p;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t c = e / n, r = e - c * n;
+    Y[c * ldy + r] = mk<T>((T)0, (T)0);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_block_hessenberg_qr(double2* H, int ld, int mr, int nc, int p, double2* B, int ldb, int k,
@@ -401,5 +414,17 @@ template hipError_t launch_cholqr_factor<float>(const double2*, int, double, dou
                                                 c2<float>*, int, hipStream_t);
 template hipError_t launch_cholqr_factor<double>(const double2*, int, double, double, int, double2*, c2<double>*,
                                                  int*, c2<double>*, int, hipStream_t);
+
+template <class T>
+hipError_t launch_zero_unless(c2<T>* Y, size_t ldy, size_t n, int p, const int* flag, hipStream_t st) {
+  if (!Y || !flag || p < 1 || ldy < n) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  const size_t total = n * (size_t)p;
+  const unsigned grid = (unsigned)std::min<size_t>((total + 255) / 256, 1024);
+  hipLaunchKernelGGL((k_zero_unless<T>), dim3(grid), dim3(256), 0, st, Y, ldy, n, p, flag);
+  return hipGetLastError();
+}
+template hipError_t launch_zero_unless<float>(c2<float>*, size_t, size_t, int, const int*, hipStream_t);
+template hipError_t launch_zero_unless<double>(c2<double>*, size_t, size_t, int, const int*, hipStream_t);
 
 }  // namespace die

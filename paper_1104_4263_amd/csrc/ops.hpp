@@ -213,6 +213,10 @@ constexpr int kCholQRMax = 64;
 template <class T>
 hipError_t launch_cholqr_factor(const double2* G, int p, double rel_tol, double single_piv, int pass, double2* R1,
                                 c2<T>* Rinv, int* flags, c2<T>* Hb, int ldh, hipStream_t st);
+// Y (n x p complex, leading dimension ldy) = 0 unless *flag (device int): a block the device CholQR
+// could not orthonormalise is cleared, so that work queued behind it reads zeros.
+template <class T>
+hipError_t launch_zero_unless(c2<T>* Y, size_t ldy, size_t n, int p, const int* flag, hipStream_t st);
 // R Y = B in place in B (nc x k, leading dimension ldb) for the upper triangular R (leading
 // dimension ldr), nc <= kTrsmMaxRows.
 constexpr int kTrsmMaxRows = 4096;

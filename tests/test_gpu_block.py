@@ -98,6 +98,28 @@ def test_block_half_gemm_matches_lu(eps_obj, reg, defl, orth):
     say(f"  block steps {[x['iters'] for x in info]}, cycles {[x['cycles'] for x in info]}")
 
 
+@pytest.mark.parametrize("block,mixed", [(1, 0), (1, 1), (2, 1)])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (5, 4)])
+def test_block_krylov_space_filled_within_a_cycle(block, mixed, nx, ny):
+    """18 and 40 unknowns, four right-hand sides, GMRES(10): the block Krylov space fills the
+    whole space after a few block steps, so a new block is numerically dependent and the cycle
+    ends before it (the device CholQR factor's rank test, which the host reads one step later,
+    after the next step is already queued); the solutions still match dense LU."""
+    g = centred_grid(nx, 1.0, ny=ny)
+    eps = cylinder(g, 0.35, 4.0 + 0j)
+    b = np.stack([plane_wave(g, 0.3 + 1.1 * q) for q in range(4)])
+    u_lu = op.solve_dense(g, eps, b)
+    s = api.Solver.from_grid(g, eps)
+    u, rc, info = s.solve(dev(b), restart=10, max_iters=2000, tol=1e-8, mixed=mixed, block=block, orth=0)
+    say(f"  {nx}x{ny} block={block} mixed={mixed}: block steps {[x['iters'] for x in info]}")
+    assert rc == 0
+    uh = host(u)
+    for r in range(b.shape[0]):
+        assert info[r]["rel_res_true"] <= 1e-8
+        assert op.relative_residual(g, eps, uh[r], b[r]) <= 1.02e-8
+        assert rel(uh[r], u_lu[r]) < 2e-5
+
+
 @pytest.mark.parametrize("nang", [1, 3])
 def test_block_half_gemm_small_blocks(nang):
     """block=2 with one and with three right-hand sides per object (blocks of width 1 and 3)."""
