@@ -120,6 +120,26 @@ def test_block_krylov_space_filled_within_a_cycle(block, mixed, nx, ny):
         assert rel(uh[r], u_lu[r]) < 2e-5
 
 
+@pytest.mark.parametrize("block", [1, 2])
+def test_block_more_than_64_rhs_per_object(block):
+    """70 incidence angles on one object: the block solver runs them in two groups (64 and 6
+    right-hand sides) that reuse the same per-step flags, events and buffers one after another."""
+    g = centred_grid(16, 1.0)
+    eps = cylinder(g, 0.35, 4.0 + 0j)
+    b = np.stack([plane_wave(g, 2.0 * np.pi * q / 70) for q in range(70)])
+    u_lu = op.solve_dense(g, eps, b)
+    s = api.Solver.from_grid(g, eps)
+    u, rc, info = s.solve(dev(b), restart=20, max_iters=4000, tol=1e-8, mixed=1, block=block, orth=0)
+    say(f"  block={block}: block steps {sorted({x['iters'] for x in info})}")
+    assert rc == 0
+    uh = host(u)
+    for r in range(b.shape[0]):
+        assert info[r]["rel_res_true"] <= 1e-8
+        assert rel(uh[r], u_lu[r]) < 2e-5
+    for r in (0, 37, 64, 69):
+        assert op.relative_residual(g, eps, uh[r], b[r]) <= 1.02e-8
+
+
 @pytest.mark.parametrize("nang", [1, 3])
 def test_block_half_gemm_small_blocks(nang):
     """block=2 with one and with three right-hand sides per object (blocks of width 1 and 3)."""
