@@ -53,8 +53,9 @@ __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) 
 // (0 for a zero column).  The reflector P_q = I - s_q u_q u_q^H maps column q to -e^{i arg a} |x| e_q.
 // The panel lives in registers: column j in row j / 16 of wave j % 16.  Per reflector the row
 // holding column q (which already carries P_0 .. P_{q-1}) forms u_q and publishes it in its own
-// LDS slot; after one barrier every row applies it to its column if that lies right of q.  U and s
-// are written once, after the last reflector.
+// LDS slot; after one barrier every row applies it to its column if that lies right of q.  The
+// wave holding column q + 1 forms u_{q+1} right after applying u_q, in the same interval, at raised
+// issue priority.  U and s are written once, after the last reflector.
 __global__ void __launch_bounds__(kPanelThreads)
 k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, double2* __restrict__ U,
            double* __restrict__ s) {
@@ -71,51 +72,58 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
     const int i = l16 + 16 * t;
     x[t] = (j < pc && i < rows) ? H[(size_t)(c0 + j) * ld + r0 + i] : make_double2(0.0, 0.0);
   }
-  for (int q = 0; q < pc; ++q) {
-    if (w == q % kPanelWaves) {  // the wave holding column q (wave-uniform); its row q / 16 writes
-      const bool own = g == q / kPanelWaves;
-      double sq = 0.0;
+  // the wave holding column q forms u_q (wave-uniform call; its row q / 16 writes it to LDS) and
+  // turns column q into R's
+  auto form = [&](int q) {
+    const bool own = g == q / kPanelWaves;
+    double sq = 0.0;
+#pragma unroll
+    for (int t = 0; t < kRowsPerLane; ++t) {
+      const int i = l16 + 16 * t;
+      if (i >= q && i < rows) sq = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, sq));
+    }
+    const double nrm = sqrt(sum16(sq));  // the norm of this row's column below q
+    double2 aq = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < kRowsPerLane; ++t)
+      if (q / 16 == t) aq = x[t];
+    const int src = (q / kPanelWaves) * 16 + (q & 15);  // the lane holding row q of column q
+    const unsigned long long ax = __builtin_bit_cast(unsigned long long, aq.x);
+    const unsigned long long ay = __builtin_bit_cast(unsigned long long, aq.y);
+    const double2 a = make_double2(
+        __builtin_bit_cast(double, ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(ax >> 32), src)
+                                    << 32) |
+                                       (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(ax & 0xffffffffu), src)),
+        __builtin_bit_cast(double, ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(ay >> 32), src)
+                                    << 32) |
+                                       (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(ay & 0xffffffffu), src)));
+    const double aa = sqrt(a.x * a.x + a.y * a.y);
+    const double2 ph = aa > 0.0 ? make_double2(a.x / aa, a.y / aa) : make_double2(1.0, 0.0);
+    // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
+    const double uu = 2.0 * nrm * (nrm + aa);
+    const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
+    if (own) {
 #pragma unroll
       for (int t = 0; t < kRowsPerLane; ++t) {
         const int i = l16 + 16 * t;
-        if (i >= q && i < rows) sq = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, sq));
+        double2 u = make_double2(0.0, 0.0);
+        if (i == q) u = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
+        else if (i > q && i < rows) u = x[t];
+        ush[q][i] = u;
+        // column q becomes R's: -e^{i arg a} |x| on the diagonal, zeros below
+        if (i == q) x[t] = make_double2(-ph.x * nrm, -ph.y * nrm);
+        else if (i > q) x[t] = make_double2(0.0, 0.0);
       }
-      const double nrm = sqrt(sum16(sq));  // the norm of this row's column below q
-      double2 aq = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int t = 0; t < kRowsPerLane; ++t)
-        if (q / 16 == t) aq = x[t];
-      const int src = (q / kPanelWaves) * 16 + (q & 15);  // the lane holding row q of column q
-      const unsigned long long ax = __builtin_bit_cast(unsigned long long, aq.x);
-      const unsigned long long ay = __builtin_bit_cast(unsigned long long, aq.y);
-      const double2 a = make_double2(
-          __builtin_bit_cast(double, ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(ax >> 32), src)
-                                      << 32) |
-                                         (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(ax & 0xffffffffu), src)),
-          __builtin_bit_cast(double, ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(ay >> 32), src)
-                                      << 32) |
-                                         (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(ay & 0xffffffffu), src)));
-      const double aa = sqrt(a.x * a.x + a.y * a.y);
-      const double2 ph = aa > 0.0 ? make_double2(a.x / aa, a.y / aa) : make_double2(1.0, 0.0);
-      // u = x[q:] + e^{i arg a} |x| e_q;  u^H u = 2 |x| (|x| + |a|)
-      const double uu = 2.0 * nrm * (nrm + aa);
-      const double sc = uu > 0.0 ? 2.0 / uu : 0.0;
-      if (own) {
-#pragma unroll
-        for (int t = 0; t < kRowsPerLane; ++t) {
-          const int i = l16 + 16 * t;
-          double2 u = make_double2(0.0, 0.0);
-          if (i == q) u = make_double2(a.x + ph.x * nrm, a.y + ph.y * nrm);
-          else if (i > q && i < rows) u = x[t];
-          ush[q][i] = u;
-          // column q becomes R's: -e^{i arg a} |x| on the diagonal, zeros below
-          if (i == q) x[t] = make_double2(-ph.x * nrm, -ph.y * nrm);
-          else if (i > q) x[t] = make_double2(0.0, 0.0);
-        }
-        if (l16 == 0) ssh[q] = sc;
-      }
+      if (l16 == 0) ssh[q] = sc;
     }
-    lds_sync();
+  };
+  if (w == 0) form(0);
+  lds_sync();
+  for (int q = 0; q < pc; ++q) {
+    // the wave that forms u_{q+1} applies u_q first at raised issue priority, so that forming
+    // u_{q+1} (norm, square roots, divisions: a serial chain) overlaps the other waves' updates
+    const bool next = q + 1 < pc && w == (q + 1) % kPanelWaves;
+    if (next) __builtin_amdgcn_s_setprio(3);
     const double sc = ssh[q];
     double2 u[kRowsPerLane];
     double2 d = make_double2(0.0, 0.0);
@@ -134,6 +142,11 @@ k_panel_qr(double2* __restrict__ H, int ld, int r0, int c0, int rows, int pc, do
         x[t].y -= u[t].x * f.y + u[t].y * f.x;
       }
     }
+    if (next) {
+      form(q + 1);
+      __builtin_amdgcn_s_setprio(0);
+    }
+    lds_sync();
   }
 #pragma unroll
   for (int t = 0; t < kRowsPerLane; ++t) {
