@@ -7,8 +7,8 @@ by 64 equispaced TE plane waves each: 256 solves.  A step solves all 256 in one
 die_te_solve_batch call over four single-object contexts (a host thread and a stream each):
 block GMRES(30) with one block Krylov space per object (complex64 products and basis;
 the two block Gram-Schmidt passes of each step as binary16 GEMMs on planar copies of the
-basis with FP32 accumulation, CholQR2 of each new block as complex64 GEMMs, FP64 block
-least squares; --block-gemm 32 keeps the Gram-Schmidt GEMMs in complex64 with one pass,
+basis with FP32 accumulation, CholQR of each new block (its Gram on the matrix cores, the
+factor on the device, a second pass only for ill-conditioned blocks), FP64 block least squares; --block-gemm 32 keeps the Gram-Schmidt GEMMs in complex64 with one pass,
 --block-precision 64 runs everything in complex128), every cycle restarted from the FP64
 true residual, tol 1e-8 on that residual, zero initial guess.  --solver rhs times the per-rhs batched solver instead
 (one-reduction Arnoldi, complex binary16 basis; --basis 32 / --orth 0 select the
@@ -16,8 +16,9 @@ complex64 basis and the two-pass CGS2); it is also reported beside the block run
 per-object setup (symbol) is done once, outside it.
 
 The configured deflation (k = 16 largest-magnitude eigenvalues per object) is not applied in
-the headline: on these objects GMRES(30) on A P^-1 stagnates near 3e-2 for many angles (an
-independent scipy GMRES(30) with ARPACK eigenvectors stagnates at the same value), so the
+the headline: with the block solver it converges every solve but takes more block steps (and its
+eigensolver setup), and with one-vector GMRES(30) on A P^-1 many angles stagnate near 3e-2 (an
+independent scipy GMRES(30) with ARPACK eigenvectors stagnates at the same value).  So the
 headline and the plain baseline both solve the undeflated system A, and the same batch with
 k = 16 is reported beside them (configured_deflation_k16).
 
