@@ -589,7 +589,7 @@ def main():
                     help="bits per real part of the stored Krylov basis in the batched run (16 needs --orth 1)")
     ap.add_argument("--uneven-deflate", type=int, default=0, metavar="K",
                     help="--uneven: deflate the K largest-magnitude eigenvalues of every object")
-    ap.add_argument("--uneven-budget", type=float, default=420.0, metavar="SECONDS",
+    ap.add_argument("--uneven-budget", type=float, default=360.0, metavar="SECONDS",
                     help="--uneven: stop after the chunk that passes this many seconds of solving (0: no limit)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (the stored network's guesses + the batched solve)")
